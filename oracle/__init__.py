@@ -1,0 +1,420 @@
+"""CPU oracle of the GI-1.0 indirect-lighting pass -- TEST INFRASTRUCTURE ONLY.
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import this package.
+It wraps ``gi_oracle.c`` (plain C, built in FP32 parity mode and FP64 reference mode) through
+ctypes, and ``learned.py`` (float64 numpy) for the learned radiance-cache surrogate.
+It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBS = {}
+
+U32P = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+I32P = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+U64P = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+F32P = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+F64P = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+NCELL = 64
+STAT_NAMES = ["rays", "hits", "inserts", "overflow", "nonfinite", "wraps", "shadow", "occluded",
+              "evict", "live", "relaxed", "noprobe", "bounce"]
+
+
+class OrcConfig(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("rays_per_probe", C.c_uint32),
+                ("table_log2", C.c_uint32), ("bounces", C.c_uint32), ("leak_bit", C.c_uint32),
+                ("max_life", C.c_uint32), ("n_cap", C.c_uint32), ("seed", C.c_uint32),
+                ("frac_bits", C.c_uint32), ("pad0", C.c_uint32), ("pad1", C.c_uint32),
+                ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
+                ("t_sky", C.c_float), ("sky", C.c_float * 4)]
+
+
+class OrcFrame(C.Structure):
+    _fields_ = [("index", C.c_uint32), ("fov_y", C.c_float), ("tan_half", C.c_float),
+                ("pad", C.c_float), ("pos", C.c_float * 4), ("fwd", C.c_float * 4),
+                ("right", C.c_float * 4), ("up", C.c_float * 4)]
+
+
+def default_config(**kw) -> dict:
+    cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
+               max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
+               eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0))
+    cfg.update(kw)
+    return cfg
+
+
+def _lib(f64: bool):
+    key = "64" if f64 else "32"
+    if key in _LIBS:
+        return _LIBS[key]
+    path = os.path.join(HERE, f"liboracle{key}.so")
+    if not os.path.exists(path):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(path)
+    p = f"orc{key}_"
+    R = F64P if f64 else F32P
+    vp = C.c_void_p
+
+    def fn(name, res, *args):
+        f = getattr(lib, p + name)
+        f.restype = res
+        f.argtypes = list(args)
+        return f
+    fn("pcg", C.c_uint32, C.c_uint32)
+    fn("xxh32", C.c_uint32, C.c_uint32)
+    fn("rng", C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32)
+    fn("sincos2pi", None, R, C.c_uint32, R, R)
+    fn("halton_jitter", None, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32))
+    fn("scene_create", vp, F32P, C.c_uint32, U32P, C.c_uint32, U32P, F32P, C.c_uint32, C.c_uint32,
+       C.c_int)
+    fn("scene_set_dynamic", C.c_int, vp, F32P, U32P, C.c_uint32)
+    fn("scene_destroy", None, vp)
+    fn("scene_emitters", None, vp, C.POINTER(C.c_uint32), U32P, U32P, C.POINTER(C.c_double))
+    fn("scene_normals", None, vp, R)
+    fn("trace_closest", None, vp, R, R, C.c_uint32, C.c_double if f64 else C.c_float, U32P, R)
+    fn("trace_any", None, vp, R, R, C.c_uint32, R, U32P)
+    fn("pick_emitter", C.c_uint32, vp, C.c_uint32)
+    fn("render_gbuffer", None, vp, C.POINTER(OrcFrame), C.c_uint32, C.c_uint32, R, R, R, U32P)
+    fn("cell_moments", None, F64P)
+    fn("cosine_dirs", None, R, R, R, C.c_uint32, R, U32P)
+    fn("keys", None, C.POINTER(OrcConfig), R, R, R, C.c_uint32, U64P, U32P, U32P)
+    fn("create", vp, C.POINTER(OrcConfig), vp)
+    fn("destroy", None, vp)
+    fn("distance_scale", C.c_float, C.c_float, C.c_uint32, C.c_uint32)
+    fn("spawn", None, vp, C.POINTER(OrcFrame), R, R, U32P)
+    fn("trace", None, vp, C.POINTER(OrcFrame))
+    fn("update", None, vp, C.POINTER(OrcFrame))
+    fn("interpolate", None, vp, C.POINTER(OrcFrame), R, R, U32P, R)
+    fn("query", None, vp, R, R, C.c_uint32, R)
+    fn("dims", None, vp, U32P)
+    fn("export_probes", None, vp, U32P, R, R, R, R)
+    fn("export_rays", None, vp, I32P, R, U32P, U32P, U64P, R)
+    fn("export_table", C.c_uint32, vp, U64P, U64P, U32P, R, U32P, U32P, C.c_uint32)
+    fn("poke_cell", C.c_int, vp, C.c_uint64, U32P, R, C.c_uint32, C.c_uint32, C.c_uint32)
+    fn("cache_update_only", None, vp)
+    fn("stats", None, vp, U64P)
+    fn("find_probe", C.c_uint32, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32)
+    fn("sh_eval", None, R, R, C.c_uint32, R)
+    fn("sh_project_atlas", None, vp, R, R, C.c_uint32, R)
+    fn("nee_samples", None, vp, C.POINTER(OrcFrame), R, R, U32P, C.c_uint32, R)
+    _LIBS[key] = (lib, p)
+    return _LIBS[key]
+
+
+def _call(f64, name, *args):
+    lib, p = _lib(f64)
+    return getattr(lib, p + name)(*args)
+
+
+# ---------------------------------------------------------------------------------------
+# small functions
+# ---------------------------------------------------------------------------------------
+
+def pcg(v: int) -> int:
+    return _call(False, "pcg", v)
+
+
+def xxh32(v: int) -> int:
+    return _call(False, "xxh32", v)
+
+
+def rng(seed, frame, gid, dim) -> int:
+    return _call(False, "rng", seed, frame, gid, dim)
+
+
+def sincos2pi(u, f64=False):
+    dt = np.float64 if f64 else np.float32
+    u = np.ascontiguousarray(u, dt)
+    c = np.empty_like(u)
+    s = np.empty_like(u)
+    _call(f64, "sincos2pi", u, u.size, c, s)
+    return c, s
+
+
+def halton_jitter(frame: int):
+    jx, jy = C.c_uint32(), C.c_uint32()
+    _call(False, "halton_jitter", frame, C.byref(jx), C.byref(jy))
+    return jx.value, jy.value
+
+
+def cell_moments() -> np.ndarray:
+    out = np.zeros((64, 10), np.float64)
+    _call(False, "cell_moments", out)
+    return out
+
+
+def distance_scale(fov_y: float, W: int, H: int) -> float:
+    return _call(False, "distance_scale", fov_y, W, H)
+
+
+def cosine_dirs(n, u0, u1, f64=False):
+    dt = np.float64 if f64 else np.float32
+    n = np.ascontiguousarray(n, dt)
+    u0 = np.ascontiguousarray(u0, dt)
+    u1 = np.ascontiguousarray(u1, dt)
+    d = np.zeros((len(u0), 3), dt)
+    cell = np.zeros(len(u0), np.uint32)
+    _call(f64, "cosine_dirs", n, u0, u1, len(u0), d, cell)
+    return d, cell
+
+
+def keys(cfg: dict, y, n, t, f64=False):
+    dt = np.float64 if f64 else np.float32
+    y = np.ascontiguousarray(y, dt)
+    n = np.ascontiguousarray(n, dt)
+    t = np.ascontiguousarray(t, dt)
+    cnt = len(t)
+    key = np.zeros(cnt, np.uint64)
+    b = np.zeros(cnt, np.uint32)
+    fp = np.zeros(cnt, np.uint32)
+    c = make_config(cfg)
+    _call(f64, "keys", C.byref(c), y, n, t, cnt, key, b, fp)
+    return key, b, fp
+
+
+def sh_eval(coef, n, f64=False):
+    dt = np.float64 if f64 else np.float32
+    coef = np.ascontiguousarray(coef, dt).reshape(-1, 27)
+    n = np.ascontiguousarray(n, dt).reshape(-1, 3)
+    E = np.zeros((len(n), 3), dt)
+    _call(f64, "sh_eval", coef, n, len(n), E)
+    return E
+
+
+def make_config(cfg: dict) -> OrcConfig:
+    c = OrcConfig()
+    for k, v in cfg.items():
+        if k == "sky":
+            for i in range(3):
+                c.sky[i] = float(v[i])
+        elif hasattr(c, k):
+            setattr(c, k, v)
+    return c
+
+
+def make_frame(fr) -> OrcFrame:
+    f = OrcFrame()
+    f.index = fr.index
+    f.fov_y = fr.fov_y
+    f.tan_half = fr.tan_half
+    for name in ("pos", "fwd", "right", "up"):
+        v = getattr(fr, name)
+        arr = getattr(f, name)
+        for i in range(3):
+            arr[i] = float(v[i])
+    return f
+
+
+# ---------------------------------------------------------------------------------------
+# scene and frame state
+# ---------------------------------------------------------------------------------------
+
+class OracleScene:
+    def __init__(self, scene, f64=False, use_bvh=None, nd_cap=64):
+        self.f64 = f64
+        self.dt = np.float64 if f64 else np.float32
+        if use_bvh is None:
+            use_bvh = scene.n_tris > 2048
+        self.src = scene
+        self.h = _call(f64, "scene_create", np.ascontiguousarray(scene.verts, np.float32),
+                       len(scene.verts), np.ascontiguousarray(scene.idx, np.uint32), scene.n_tris,
+                       np.ascontiguousarray(scene.tri_mat, np.uint32),
+                       np.ascontiguousarray(scene.materials, np.float32), len(scene.materials),
+                       nd_cap, int(use_bvh))
+        self.nt = scene.n_tris
+        self.nd = 0
+
+    def set_dynamic(self, tv, mats):
+        tv = np.ascontiguousarray(tv, np.float32).reshape(-1, 9)
+        mats = np.ascontiguousarray(mats, np.uint32)
+        if _call(self.f64, "scene_set_dynamic", self.h, tv, mats, len(mats)) != 0:
+            raise ValueError("too many dynamic triangles")
+        self.nd = len(mats)
+
+    def set_frame_dynamic(self, frame_index: int):
+        if self.src.dynamic is not None:
+            tv, m = self.src.dynamic(frame_index)
+            self.set_dynamic(tv, m)
+
+    def emitters(self):
+        ne = C.c_uint32()
+        n = self.nt + 64
+        etri = np.zeros(n, np.uint32)
+        ethr = np.zeros(n, np.uint32)
+        area = C.c_double()
+        _call(self.f64, "scene_emitters", self.h, C.byref(ne), etri, ethr, C.byref(area))
+        return etri[:ne.value].copy(), ethr[:ne.value].copy(), area.value
+
+    def normals(self):
+        out = np.zeros((self.nt + self.nd, 3), self.dt)
+        _call(self.f64, "scene_normals", self.h, out)
+        return out
+
+    def closest(self, o, d, tmax=3.0e38):
+        o = np.ascontiguousarray(o, self.dt)
+        d = np.ascontiguousarray(d, self.dt)
+        n = len(o)
+        tri = np.zeros(n, np.uint32)
+        t = np.zeros(n, self.dt)
+        _call(self.f64, "trace_closest", self.h, o, d, n, tmax, tri, t)
+        return tri, t
+
+    def any(self, o, d, tmax):
+        o = np.ascontiguousarray(o, self.dt)
+        d = np.ascontiguousarray(d, self.dt)
+        tm = np.ascontiguousarray(np.broadcast_to(tmax, (len(o),)), self.dt)
+        hit = np.zeros(len(o), np.uint32)
+        _call(self.f64, "trace_any", self.h, o, d, len(o), tm, hit)
+        return hit
+
+    def pick_emitter(self, r: int) -> int:
+        return _call(self.f64, "pick_emitter", self.h, r)
+
+    def gbuffer(self, frame, W, H):
+        pos = np.zeros((H, W, 4), self.dt)
+        nrm = np.zeros((H, W, 4), self.dt)
+        alb = np.zeros((H, W, 4), self.dt)
+        prim = np.zeros((H, W), np.uint32)
+        f = make_frame(frame)
+        _call(self.f64, "render_gbuffer", self.h, C.byref(f), W, H, pos, nrm, alb, prim)
+        return pos, nrm, alb, prim
+
+    def __del__(self):
+        try:
+            _call(self.f64, "scene_destroy", self.h)
+        except Exception:
+            pass
+
+
+class OracleFrameState:
+    """World cache, probes and rays of one context; methods follow the frame order."""
+
+    def __init__(self, scene: OracleScene, cfg: dict):
+        self.scene = scene
+        self.f64 = scene.f64
+        self.dt = scene.dt
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        self.h = _call(self.f64, "create", C.byref(self._c), scene.h)
+        d = np.zeros(9, np.uint32)
+        _call(self.f64, "dims", self.h, d)
+        self.P, self.R, self.N, self.TW, self.TH, self.nmip, self.mask_total = (int(x) for x in d[:7])
+
+    def dims(self):
+        d = np.zeros(9, np.uint32)
+        _call(self.f64, "dims", self.h, d)
+        return d
+
+    def spawn(self, frame, gpos, gnrm, gprim):
+        self._f = make_frame(frame)
+        self._g = (np.ascontiguousarray(gpos, self.dt), np.ascontiguousarray(gnrm, self.dt),
+                   np.ascontiguousarray(gprim, np.uint32))
+        _call(self.f64, "spawn", self.h, C.byref(self._f), *self._g)
+
+    def trace(self, frame):
+        f = make_frame(frame)
+        _call(self.f64, "trace", self.h, C.byref(f))
+
+    def update(self, frame):
+        f = make_frame(frame)
+        _call(self.f64, "update", self.h, C.byref(f))
+
+    def interpolate(self, frame, gpos, gnrm, gprim):
+        H, W = gprim.shape
+        out = np.zeros((H, W, 4), self.dt)
+        f = make_frame(frame)
+        _call(self.f64, "interpolate", self.h, C.byref(f), np.ascontiguousarray(gpos, self.dt),
+              np.ascontiguousarray(gnrm, self.dt), np.ascontiguousarray(gprim, np.uint32), out)
+        return out
+
+    def frame(self, frame, gbuf):
+        """spawn -> trace -> update (+gather, SH) -> interpolate for one frame"""
+        pos, nrm, _alb, prim = gbuf
+        self.spawn(frame, pos, nrm, prim)
+        self.trace(frame)
+        self.update(frame)
+        return self.interpolate(frame, pos, nrm, prim)
+
+    def query(self, pos, nrm):
+        pos = np.ascontiguousarray(pos, self.dt)
+        nrm = np.ascontiguousarray(nrm, self.dt)
+        out = np.zeros((len(pos), 4), self.dt)
+        _call(self.f64, "query", self.h, pos, nrm, len(pos), out)
+        return out
+
+    def probes(self):
+        mask = np.zeros(self.mask_total, np.uint32)
+        ppos = np.zeros((self.P, 4), self.dt)
+        pnrm = np.zeros((self.P, 4), self.dt)
+        atlas = np.zeros((self.P, NCELL, 4), self.dt)
+        sh = np.zeros((self.P, 27), self.dt)
+        _call(self.f64, "export_probes", self.h, mask, ppos, pnrm, atlas, sh)
+        return dict(mask=mask, pos=ppos, nrm=pnrm, atlas=atlas, sh=sh)
+
+    def rays(self):
+        n = self.P * self.R
+        slot = np.zeros(n, np.int32)
+        t = np.zeros(n, self.dt)
+        tri = np.zeros(n, np.uint32)
+        cell = np.zeros(n, np.uint32)
+        key = np.zeros(n, np.uint64)
+        sample = np.zeros((n, 3), self.dt)
+        _call(self.f64, "export_rays", self.h, slot, t, tri, cell, key, sample)
+        return dict(slot=slot, t=t, tri=tri, cell=cell, key=key, sample=sample)
+
+    def table(self):
+        cap = self.N
+        ident = np.zeros(cap, np.uint64)
+        key = np.zeros(cap, np.uint64)
+        acc = np.zeros((cap, 4), np.uint32)
+        L = np.zeros((cap, 3), self.dt)
+        nh = np.zeros(cap, np.uint32)
+        life = np.zeros(cap, np.uint32)
+        n = _call(self.f64, "export_table", self.h, ident, key, acc, L, nh, life, cap)
+        order = np.argsort(ident[:n], kind="stable")
+        return dict(id=ident[:n][order], key=key[:n][order], acc=acc[:n][order], L=L[:n][order],
+                    nhist=nh[:n][order], life=life[:n][order])
+
+    def poke_cell(self, key, acc4, L3, nhist, life, accessed):
+        return _call(self.f64, "poke_cell", self.h, key, np.ascontiguousarray(acc4, np.uint32),
+                     np.ascontiguousarray(L3, self.dt), nhist, life, accessed)
+
+    def cache_update_only(self):
+        _call(self.f64, "cache_update_only", self.h)
+
+    def stats(self):
+        out = np.zeros(16, np.uint64)
+        _call(self.f64, "stats", self.h, out)
+        return {k: int(out[i]) for i, k in enumerate(STAT_NAMES)}
+
+    def find_probe(self, px, py, ox, oy):
+        return _call(self.f64, "find_probe", self.h, px, py, ox, oy)
+
+    def nee(self, frame, y, ny, ids):
+        """E/pi estimates (one light sample and one shadow ray each) at a point"""
+        ids = np.ascontiguousarray(ids, np.uint32)
+        out = np.zeros((len(ids), 3), self.dt)
+        f = make_frame(frame)
+        _call(self.f64, "nee_samples", self.h, C.byref(f), np.ascontiguousarray(y, self.dt),
+              np.ascontiguousarray(ny, self.dt), ids, len(ids), out)
+        return out
+
+    def sh_project(self, atlas, nrm):
+        atlas = np.ascontiguousarray(atlas, self.dt).reshape(-1, NCELL, 4)
+        nrm = np.ascontiguousarray(nrm, self.dt).reshape(-1, 3)
+        out = np.zeros((len(nrm), 27), self.dt)
+        _call(self.f64, "sh_project_atlas", self.h, atlas, nrm, len(nrm), out)
+        return out
+
+    def __del__(self):
+        try:
+            _call(self.f64, "destroy", self.h)
+        except Exception:
+            pass

@@ -1,0 +1,1648 @@
+/*
+ * CPU oracle for the GI-1.0 per-frame indirect-lighting pass (two-level radiance caching).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call this file;
+ * only tests, the smoke check and the CPU baseline of the benchmark do.  It shares no code
+ * with the HIP library: every definition here is written out again, plainly, from the
+ * method's description.
+ *
+ * The file is compiled twice:
+ *   - FP32 parity mode (default): the same float32 operation order as the GPU path, so that
+ *     every float-derived integer (hit index, hit distance bits, cell key, hemisphere cell,
+ *     fixed-point sums) is reproduced bit for bit.  Build with -ffp-contract=off.
+ *   - FP64 reference mode (-DORC_F64): the same algorithm in double precision and without
+ *     fixed-point quantisation of the cache samples; used for closed forms and converged
+ *     references.
+ *
+ * Section references are to the GI-1.0 paper (Boisse et al., 2022):
+ *   Section 2.1.1 temporal upscale / spawning, 2.1.3 ray tracing of probes, 2.1.4 radiance
+ *   blending and backup, 2.1.5 probe masking (Algorithm 4), 2.1.7 adaptive cell size
+ *   (Algorithm 6), 2.2.1 spatial-hash world cache, 2.2.2 light-leak bit, 2.2.3 temporal
+ *   accumulation into cells, 2.2.4 radiance feedback, 2.3.1 light sampling with one shadow
+ *   ray, 2.4.1 per-pixel interpolation, 2.4.2 spherical harmonics.
+ * Definitions that the paper leaves open are marked READING and listed in the design notes.
+ *
+ * parity unpinned: none of the functions below lacks a pin; see tests/test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORC_F64
+typedef double real;
+#define ORC(n) orc64_##n
+#define RC(x) (x)
+#define RSQRT(x) sqrt(x)
+#define RFLOOR(x) floor(x)
+#define RABS(x) fabs(x)
+#else
+typedef float real;
+#define ORC(n) orc32_##n
+#define RC(x) (x##f)
+#define RSQRT(x) sqrtf(x)
+#define RFLOOR(x) floorf(x)
+#define RABS(x) fabsf(x)
+#endif
+
+#define MISS 0xFFFFFFFFu
+#define SENTINEL 0xFFFFFFFFu
+#define BUCKET 32u
+#define NCELL 64
+
+static real rmax(real a, real b) { return a > b ? a : b; }
+static real rmin(real a, real b) { return a < b ? a : b; }
+
+/* ---------------------------------------------------------------------------------------
+ * Integer hashes (the two hash functions of the world cache, Section 2.2.1, and the
+ * counter-based random numbers).  READING: the paper names only the survey of GPU hash
+ * functions by Jarzynski and Olano (2020); we take its PCG-based hash for bucket selection
+ * and random numbers, and the 32-bit xxHash finaliser for fingerprints.
+ * ------------------------------------------------------------------------------------- */
+static uint32_t pcg_hash(uint32_t v)
+{
+    uint32_t state = v * 747796405u + 2891336453u;
+    uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+static uint32_t xxh32_hash(uint32_t v)
+{
+    /* XXH32 of the 4 little-endian bytes of v with seed 0: short-input path, then the
+     * avalanche finaliser, with the published primes */
+    uint32_t h = 374761393u + 4u;
+    h += v * 3266489917u;
+    h = ((h << 17) | (h >> 15)) * 668265263u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    h *= 3266489917u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* random 32-bit word for (seed, frame, stream id, dimension): nested PCG hashing */
+static uint32_t rng_u32(uint32_t seed, uint32_t frame, uint32_t id, uint32_t dim)
+{
+    return pcg_hash(dim + pcg_hash(id + pcg_hash(frame + pcg_hash(seed))));
+}
+
+/* top 24 bits of the word as a float in [0,1); exact in float32 */
+static real rng_unit(uint32_t h)
+{
+    return (real)(h >> 8) * RC(5.9604644775390625e-08);
+}
+
+uint32_t ORC(pcg)(uint32_t v) { return pcg_hash(v); }
+uint32_t ORC(xxh32)(uint32_t v) { return xxh32_hash(v); }
+uint32_t ORC(rng)(uint32_t s, uint32_t f, uint32_t id, uint32_t k) { return rng_u32(s, f, id, k); }
+
+/* number of repeated outputs of a hash over inputs [0, n) (test of injectivity); which = 0
+ * for the PCG hash, 1 for XXH32 */
+uint64_t ORC(hash_collisions)(uint32_t which, uint64_t n)
+{
+    uint64_t *bits = (uint64_t *)calloc((size_t)1 << 26, sizeof(uint64_t));
+    uint64_t rep = 0;
+    if (!bits) return ~(uint64_t)0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t h = which ? xxh32_hash((uint32_t)i) : pcg_hash((uint32_t)i);
+        uint64_t m = (uint64_t)1 << (h & 63u);
+        if (bits[h >> 6] & m) ++rep;
+        bits[h >> 6] |= m;
+    }
+    free(bits);
+    return rep;
+}
+
+/* ---------------------------------------------------------------------------------------
+ * sin/cos of 2*pi*u for u in [0,1) without a library transcendental, so that both sides
+ * produce identical bits.  Exact octant reduction (8u is exact), then Taylor polynomials
+ * with coefficients 1/n! on [0, pi/4].  In FP64 mode the library functions are used.
+ * ------------------------------------------------------------------------------------- */
+static void sincos_2pi(real u, real *c_out, real *s_out)
+{
+#ifdef ORC_F64
+    *c_out = cos(6.283185307179586 * u);
+    *s_out = sin(6.283185307179586 * u);
+#else
+    float v = u * 8.0f;
+    int k = (int)v;
+    float fr = v - (float)k;
+    float g = (k & 1) ? (1.0f - fr) : fr;
+    float x = g * 0.785398163397448310f;
+    float x2 = x * x;
+    float s = x * (1.0f + x2 * (-0.166666666666666667f + x2 * (0.00833333333333333333f +
+              x2 * (-0.000198412698412698413f + x2 * 2.75573192239858907e-06f))));
+    float c = 1.0f + x2 * (-0.5f + x2 * (0.0416666666666666667f + x2 * (-0.00138888888888888889f +
+              x2 * (2.48015873015873016e-05f + x2 * -2.75573192239858907e-07f))));
+    float co, si;
+    switch (k & 7) {
+    case 0: co = c; si = s; break;
+    case 1: co = s; si = c; break;
+    case 2: co = -s; si = c; break;
+    case 3: co = -c; si = s; break;
+    case 4: co = -c; si = -s; break;
+    case 5: co = -s; si = -c; break;
+    case 6: co = s; si = -c; break;
+    default: co = c; si = -s; break;
+    }
+    *c_out = co;
+    *s_out = si;
+#endif
+}
+
+void ORC(sincos2pi)(const real *u, uint32_t n, real *c, real *s)
+{
+    for (uint32_t i = 0; i < n; ++i) sincos_2pi(u[i], &c[i], &s[i]);
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Halton jitter of the spawn tile (Section 2.1.1): one jitter per frame, index f+1, bases 2
+ * and 3, taken as floor(8 * radical_inverse) in exact integer arithmetic.  READING: the
+ * paper does not say whether the jitter is per frame or per tile; per frame keeps the probe
+ * grid regular for interpolation.
+ * ------------------------------------------------------------------------------------- */
+static uint32_t halton8(uint32_t index, uint32_t base)
+{
+    /* radical inverse as num/den, den = base^digits */
+    uint64_t num = 0, den = 1;
+    uint32_t i = index;
+    while (i > 0) {
+        num = num * base + (i % base);
+        den *= base;
+        i /= base;
+    }
+    return (uint32_t)((8u * num) / den);
+}
+
+void ORC(halton_jitter)(uint32_t frame, uint32_t *jx, uint32_t *jy)
+{
+    *jx = halton8(frame + 1u, 2u);
+    *jy = halton8(frame + 1u, 3u);
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Scene: triangles, unit geometric normals, emitters
+ * ------------------------------------------------------------------------------------- */
+typedef struct bnode {
+    float lo[3], hi[3];
+    uint32_t left;    /* inner: index of first child (second is left+1); leaf: first tri slot */
+    uint32_t count;   /* 0 = inner node, else number of triangles */
+} bnode;
+
+typedef struct scene {
+    uint32_t nt, nd, nm;
+    float *tv;          /* [(nt+nd)][9] triangle vertices */
+    real *tn;           /* [(nt+nd)][3] unit winding normal */
+    uint32_t *tmat;     /* [(nt+nd)] */
+    float *mats;        /* [nm][6] albedo rgb, Le rgb */
+    uint32_t nd_cap;
+    /* emitters over static and dynamic triangles */
+    uint32_t ne;
+    uint32_t *etri;
+    uint32_t *ethr;
+    real area_total;
+    /* binary BVH over static triangles */
+    bnode *nodes;
+    uint32_t nnodes;
+    uint32_t *order;
+    int use_bvh;
+} scene;
+
+static void tri_normal(const float *v, real *n)
+{
+    real e1x = (real)v[3] - (real)v[0], e1y = (real)v[4] - (real)v[1], e1z = (real)v[5] - (real)v[2];
+    real e2x = (real)v[6] - (real)v[0], e2y = (real)v[7] - (real)v[1], e2z = (real)v[8] - (real)v[2];
+    real cx = e1y * e2z - e1z * e2y;
+    real cy = e1z * e2x - e1x * e2z;
+    real cz = e1x * e2y - e1y * e2x;
+    real len = RSQRT(cx * cx + cy * cy + cz * cz);
+    if (len > RC(0.0)) {
+        n[0] = cx / len;
+        n[1] = cy / len;
+        n[2] = cz / len;
+    } else {
+        n[0] = n[1] = n[2] = RC(0.0);
+    }
+}
+
+static double tri_area_f64(const float *v)
+{
+    double e1x = (double)v[3] - v[0], e1y = (double)v[4] - v[1], e1z = (double)v[5] - v[2];
+    double e2x = (double)v[6] - v[0], e2y = (double)v[7] - v[1], e2z = (double)v[8] - v[2];
+    double cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
+    return 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+static int is_emitter(const scene *sc, uint32_t tri)
+{
+    const float *m = sc->mats + 6 * sc->tmat[tri];
+    return m[3] > 0.0f || m[4] > 0.0f || m[5] > 0.0f;
+}
+
+/* Area-proportional emitter selection (one light sample per hit, the single-sample form of
+ * the light sampling of Section 2.3.1).  Thresholds are the float64 running area sums,
+ * scaled to 2^32; the last threshold is 2^32-1. */
+static void build_emitters(scene *sc)
+{
+    uint32_t total = sc->nt + sc->nd;
+    free(sc->etri);
+    free(sc->ethr);
+    sc->etri = NULL;
+    sc->ethr = NULL;
+    sc->ne = 0;
+    uint32_t n = 0;
+    for (uint32_t i = 0; i < total; ++i) n += is_emitter(sc, i) ? 1u : 0u;
+    sc->area_total = RC(0.0);
+    if (n == 0) return;
+    sc->etri = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    sc->ethr = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    double *pre = (double *)malloc(sizeof(double) * n);
+    double acc = 0.0;
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < total; ++i) {
+        if (!is_emitter(sc, i)) continue;
+        acc += tri_area_f64(sc->tv + 9 * (size_t)i);
+        pre[k] = acc;
+        sc->etri[k++] = i;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        double t = floor(pre[i] / acc * 4294967296.0);
+        sc->ethr[i] = (i + 1 == n || t >= 4294967295.0) ? 4294967295u : (uint32_t)t;
+    }
+    sc->ne = n;
+    sc->area_total = (real)acc;
+    free(pre);
+}
+
+static uint32_t pick_emitter(const scene *sc, uint32_t r)
+{
+    uint32_t lo = 0, hi = sc->ne - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2u;
+        if (r < sc->ethr[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Watertight ray/triangle intersection (Woop, Benthin and Wald, JCGT 2013), two-sided,
+ * accepting 0 < t < tmax.  The paper traces closest-hit and any-hit queries (Section 2.1.3,
+ * Section 4) with hardware traversal; the query result is defined here triangle by triangle.
+ * ------------------------------------------------------------------------------------- */
+typedef struct rayp {
+    real o[3], d[3], inv[3];
+    int kx, ky, kz;
+    real sx, sy, sz;
+} rayp;
+
+static void ray_setup(rayp *r, const real *o, const real *d)
+{
+    for (int i = 0; i < 3; ++i) {
+        r->o[i] = o[i];
+        r->d[i] = d[i];
+        /* a tiny stand-in for zero components keeps the slab test finite and conservative */
+        real di = d[i];
+        if (RABS(di) < RC(1e-30)) di = (di < RC(0.0)) ? RC(-1e-30) : RC(1e-30);
+        r->inv[i] = RC(1.0) / di;
+    }
+    int kz = 0;
+    if (RABS(d[1]) > RABS(d[kz])) kz = 1;
+    if (RABS(d[2]) > RABS(d[kz])) kz = 2;
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    if (d[kz] < RC(0.0)) {
+        int tmp = kx;
+        kx = ky;
+        ky = tmp;
+    }
+    r->kx = kx;
+    r->ky = ky;
+    r->kz = kz;
+    r->sx = d[kx] / d[kz];
+    r->sy = d[ky] / d[kz];
+    r->sz = RC(1.0) / d[kz];
+}
+
+static int tri_intersect(const rayp *r, const float *v, real tmax, real *t_out)
+{
+    real A[3], B[3], C[3];
+    for (int i = 0; i < 3; ++i) {
+        A[i] = (real)v[i] - r->o[i];
+        B[i] = (real)v[3 + i] - r->o[i];
+        C[i] = (real)v[6 + i] - r->o[i];
+    }
+    real ax = A[r->kx] - r->sx * A[r->kz];
+    real ay = A[r->ky] - r->sy * A[r->kz];
+    real bx = B[r->kx] - r->sx * B[r->kz];
+    real by = B[r->ky] - r->sy * B[r->kz];
+    real cx = C[r->kx] - r->sx * C[r->kz];
+    real cy = C[r->ky] - r->sy * C[r->kz];
+    real U = cx * by - cy * bx;
+    real V = ax * cy - ay * cx;
+    real W = bx * ay - by * ax;
+#ifndef ORC_F64
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)cx * (double)by - (double)cy * (double)bx);
+        V = (float)((double)ax * (double)cy - (double)ay * (double)cx);
+        W = (float)((double)bx * (double)ay - (double)by * (double)ax);
+    }
+#endif
+    if ((U < RC(0.0) || V < RC(0.0) || W < RC(0.0)) && (U > RC(0.0) || V > RC(0.0) || W > RC(0.0)))
+        return 0;
+    real det = U + V + W;
+    if (det == RC(0.0)) return 0;
+    real az = r->sz * A[r->kz];
+    real bz = r->sz * B[r->kz];
+    real cz = r->sz * C[r->kz];
+    real T = U * az + V * bz + W * cz;
+    real t = T / det;
+    if (!(t > RC(0.0)) || !(t < tmax)) return 0;
+    *t_out = t;
+    return 1;
+}
+
+/* conservative slab test: exit distance is widened so that rounding never rejects a box
+ * that a triangle inside it is hit in */
+static int box_enter(const rayp *r, const float *lo, const float *hi, real tlim, real *tnear)
+{
+    real tn = RC(0.0), tf = RC(3.0e38);
+    for (int i = 0; i < 3; ++i) {
+        real t0 = ((real)lo[i] - r->o[i]) * r->inv[i];
+        real t1 = ((real)hi[i] - r->o[i]) * r->inv[i];
+        if (t0 > t1) {
+            real tmp = t0;
+            t0 = t1;
+            t1 = tmp;
+        }
+        tn = rmax(tn, t0);
+        tf = rmin(tf, t1);
+    }
+    tf = tf * RC(1.00001);
+    if (tn > tf) return 0;
+    if (tn > tlim * RC(1.0001)) return 0;
+    *tnear = tn;
+    return 1;
+}
+
+/* ---------------------------------------------------------------------------------------
+ * A plain binary BVH used only to make large scenes tractable.  The query result is the
+ * brute-force one by construction (conservative box tests, no early culling beyond the best
+ * distance); tests check BVH == brute force bit for bit.
+ * ------------------------------------------------------------------------------------- */
+typedef struct bref { float c; uint32_t tri; } bref;
+
+static void tri_bounds(const float *v, float *lo, float *hi)
+{
+    for (int a = 0; a < 3; ++a) {
+        float m0 = v[a], m1 = v[a];
+        for (int k = 1; k < 3; ++k) {
+            float x = v[3 * k + a];
+            if (x < m0) m0 = x;
+            if (x > m1) m1 = x;
+        }
+        lo[a] = m0;
+        hi[a] = m1;
+    }
+}
+
+static void select_kth(uint32_t *ids, const float *key, uint32_t n, uint32_t k)
+{
+    /* quickselect on key[ids[.]] so that ids[k] is the k-th smallest, stable by tri index */
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        float pv = key[ids[mid]];
+        uint32_t pt = ids[mid];
+        uint32_t i = lo, j = hi;
+        while (i <= j) {
+            while (key[ids[i]] < pv || (key[ids[i]] == pv && ids[i] < pt)) ++i;
+            while (key[ids[j]] > pv || (key[ids[j]] == pv && ids[j] > pt)) --j;
+            if (i <= j) {
+                uint32_t t = ids[i];
+                ids[i] = ids[j];
+                ids[j] = t;
+                ++i;
+                if (j == 0) break;
+                --j;
+            }
+        }
+        if (k <= j) hi = j;
+        else if (k >= i) lo = i;
+        else break;
+    }
+}
+
+static void bvh_build(scene *sc)
+{
+    uint32_t n = sc->nt;
+    free(sc->nodes);
+    free(sc->order);
+    sc->nodes = NULL;
+    sc->order = NULL;
+    sc->nnodes = 0;
+    if (n == 0) return;
+    float *cen = (float *)malloc(sizeof(float) * 3 * (size_t)n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const float *v = sc->tv + 9 * (size_t)i;
+        for (int a = 0; a < 3; ++a) cen[3 * (size_t)i + a] = (v[a] + v[3 + a] + v[6 + a]) / 3.0f;
+    }
+    uint32_t *ids = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    for (uint32_t i = 0; i < n; ++i) ids[i] = i;
+    uint32_t cap = 2 * n + 1;
+    bnode *nodes = (bnode *)malloc(sizeof(bnode) * cap);
+    float *keybuf = (float *)malloc(sizeof(float) * n);
+    /* explicit work stack of (node, first, count) */
+    uint32_t *ws = (uint32_t *)malloc(sizeof(uint32_t) * 3 * 128);
+    uint32_t wsp = 0, nn = 1;
+    ws[0] = 0; ws[1] = 0; ws[2] = n; wsp = 1;
+    while (wsp > 0) {
+        --wsp;
+        uint32_t node = ws[3 * wsp], first = ws[3 * wsp + 1], count = ws[3 * wsp + 2];
+        bnode *b = &nodes[node];
+        for (int a = 0; a < 3; ++a) { b->lo[a] = 3.0e38f; b->hi[a] = -3.0e38f; }
+        float clo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, chi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+        for (uint32_t i = first; i < first + count; ++i) {
+            float lo[3], hi[3];
+            tri_bounds(sc->tv + 9 * (size_t)ids[i], lo, hi);
+            for (int a = 0; a < 3; ++a) {
+                if (lo[a] < b->lo[a]) b->lo[a] = lo[a];
+                if (hi[a] > b->hi[a]) b->hi[a] = hi[a];
+                float c = cen[3 * (size_t)ids[i] + a];
+                if (c < clo[a]) clo[a] = c;
+                if (c > chi[a]) chi[a] = c;
+            }
+        }
+        if (count <= 4) {
+            b->left = first;
+            b->count = count;
+            continue;
+        }
+        int axis = 0;
+        for (int a = 1; a < 3; ++a)
+            if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+        for (uint32_t i = first; i < first + count; ++i) keybuf[ids[i]] = cen[3 * (size_t)ids[i] + axis];
+        uint32_t half = count / 2;
+        select_kth(ids + first, keybuf, count, half);
+        b->left = nn;
+        b->count = 0;
+        uint32_t l = nn, r = nn + 1;
+        nn += 2;
+        ws[3 * wsp] = r; ws[3 * wsp + 1] = first + half; ws[3 * wsp + 2] = count - half; ++wsp;
+        ws[3 * wsp] = l; ws[3 * wsp + 1] = first; ws[3 * wsp + 2] = half; ++wsp;
+    }
+    free(ws);
+    free(keybuf);
+    free(cen);
+    sc->nodes = nodes;
+    sc->nnodes = nn;
+    sc->order = ids;
+}
+
+/* closest hit over static and dynamic triangles: lexicographic minimum of (t, index) */
+static void closest_hit(const scene *sc, const real *o, const real *d, real tmax,
+                        uint32_t *tri_out, real *t_out)
+{
+    rayp r;
+    ray_setup(&r, o, d);
+    uint32_t best = MISS;
+    real bt = tmax;
+    real t;
+    if (sc->use_bvh && sc->nodes) {
+        uint32_t stack[256];
+        int sp = 0;
+        real tn;
+        if (box_enter(&r, sc->nodes[0].lo, sc->nodes[0].hi, bt, &tn)) stack[sp++] = 0;
+        while (sp > 0) {
+            const bnode *b = &sc->nodes[stack[--sp]];
+            if (!box_enter(&r, b->lo, b->hi, bt, &tn)) continue;
+            if (b->count) {
+                for (uint32_t i = 0; i < b->count; ++i) {
+                    uint32_t id = sc->order[b->left + i];
+                    if (tri_intersect(&r, sc->tv + 9 * (size_t)id, tmax, &t)) {
+                        if (t < bt || (t == bt && id < best)) { bt = t; best = id; }
+                    }
+                }
+            } else {
+                real t0, t1;
+                int h0 = box_enter(&r, sc->nodes[b->left].lo, sc->nodes[b->left].hi, bt, &t0);
+                int h1 = box_enter(&r, sc->nodes[b->left + 1].lo, sc->nodes[b->left + 1].hi, bt, &t1);
+                if (h0 && h1) {
+                    if (t0 <= t1) { stack[sp++] = b->left + 1; stack[sp++] = b->left; }
+                    else { stack[sp++] = b->left; stack[sp++] = b->left + 1; }
+                } else if (h0) stack[sp++] = b->left;
+                else if (h1) stack[sp++] = b->left + 1;
+            }
+        }
+    } else {
+        for (uint32_t id = 0; id < sc->nt; ++id) {
+            if (tri_intersect(&r, sc->tv + 9 * (size_t)id, tmax, &t)) {
+                if (t < bt || (t == bt && id < best)) { bt = t; best = id; }
+            }
+        }
+    }
+    for (uint32_t k = 0; k < sc->nd; ++k) {
+        uint32_t id = sc->nt + k;
+        if (tri_intersect(&r, sc->tv + 9 * (size_t)id, tmax, &t)) {
+            if (t < bt || (t == bt && id < best)) { bt = t; best = id; }
+        }
+    }
+    *tri_out = best;
+    *t_out = best == MISS ? RC(0.0) : bt;
+}
+
+/* any hit in (0, tmax) */
+static int any_hit(const scene *sc, const real *o, const real *d, real tmax)
+{
+    rayp r;
+    ray_setup(&r, o, d);
+    real t;
+    if (sc->use_bvh && sc->nodes) {
+        uint32_t stack[256];
+        int sp = 0;
+        stack[sp++] = 0;
+        real tn;
+        while (sp > 0) {
+            const bnode *b = &sc->nodes[stack[--sp]];
+            if (!box_enter(&r, b->lo, b->hi, tmax, &tn)) continue;
+            if (b->count) {
+                for (uint32_t i = 0; i < b->count; ++i)
+                    if (tri_intersect(&r, sc->tv + 9 * (size_t)sc->order[b->left + i], tmax, &t)) return 1;
+            } else {
+                stack[sp++] = b->left + 1;
+                stack[sp++] = b->left;
+            }
+        }
+    } else {
+        for (uint32_t id = 0; id < sc->nt; ++id)
+            if (tri_intersect(&r, sc->tv + 9 * (size_t)id, tmax, &t)) return 1;
+    }
+    for (uint32_t k = 0; k < sc->nd; ++k)
+        if (tri_intersect(&r, sc->tv + 9 * (size_t)(sc->nt + k), tmax, &t)) return 1;
+    return 0;
+}
+
+scene *ORC(scene_create)(const float *verts, uint32_t nv, const uint32_t *idx, uint32_t nt,
+                         const uint32_t *tri_mat, const float *mats, uint32_t nm, uint32_t nd_cap,
+                         int use_bvh)
+{
+    (void)nv;
+    scene *sc = (scene *)calloc(1, sizeof(scene));
+    sc->nt = nt;
+    sc->nm = nm;
+    sc->nd = 0;
+    sc->nd_cap = nd_cap;
+    size_t tot = (size_t)nt + nd_cap;
+    sc->tv = (float *)malloc(sizeof(float) * 9 * (tot ? tot : 1));
+    sc->tn = (real *)malloc(sizeof(real) * 3 * (tot ? tot : 1));
+    sc->tmat = (uint32_t *)malloc(sizeof(uint32_t) * (tot ? tot : 1));
+    sc->mats = (float *)malloc(sizeof(float) * 6 * (nm ? nm : 1));
+    memcpy(sc->mats, mats, sizeof(float) * 6 * nm);
+    for (uint32_t i = 0; i < nt; ++i) {
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a)
+                sc->tv[9 * (size_t)i + 3 * k + a] = verts[3 * (size_t)idx[3 * (size_t)i + k] + a];
+        tri_normal(sc->tv + 9 * (size_t)i, sc->tn + 3 * (size_t)i);
+        sc->tmat[i] = tri_mat[i];
+    }
+    sc->use_bvh = use_bvh;
+    if (use_bvh) bvh_build(sc);
+    build_emitters(sc);
+    return sc;
+}
+
+int ORC(scene_set_dynamic)(scene *sc, const float *tv, const uint32_t *mat, uint32_t nd)
+{
+    if (nd > sc->nd_cap) return -1;
+    for (uint32_t k = 0; k < nd; ++k) {
+        size_t id = (size_t)sc->nt + k;
+        memcpy(sc->tv + 9 * id, tv + 9 * (size_t)k, sizeof(float) * 9);
+        tri_normal(sc->tv + 9 * id, sc->tn + 3 * id);
+        sc->tmat[id] = mat[k];
+    }
+    sc->nd = nd;
+    build_emitters(sc);
+    return 0;
+}
+
+void ORC(scene_destroy)(scene *sc)
+{
+    if (!sc) return;
+    free(sc->tv); free(sc->tn); free(sc->tmat); free(sc->mats);
+    free(sc->etri); free(sc->ethr); free(sc->nodes); free(sc->order);
+    free(sc);
+}
+
+void ORC(scene_emitters)(const scene *sc, uint32_t *ne, uint32_t *etri, uint32_t *ethr, double *area)
+{
+    *ne = sc->ne;
+    if (etri) memcpy(etri, sc->etri, sizeof(uint32_t) * sc->ne);
+    if (ethr) memcpy(ethr, sc->ethr, sizeof(uint32_t) * sc->ne);
+    *area = (double)sc->area_total;
+}
+
+void ORC(scene_normals)(const scene *sc, real *out)
+{
+    memcpy(out, sc->tn, sizeof(real) * 3 * ((size_t)sc->nt + sc->nd));
+}
+
+/* batch queries for tests: rays [n][3] origins and directions */
+void ORC(trace_closest)(const scene *sc, const real *o, const real *d, uint32_t n, real tmax,
+                        uint32_t *tri, real *t)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (long i = 0; i < (long)n; ++i) closest_hit(sc, o + 3 * i, d + 3 * i, tmax, tri + i, t + i);
+}
+
+void ORC(trace_any)(const scene *sc, const real *o, const real *d, uint32_t n, const real *tmax,
+                    uint32_t *hit)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (long i = 0; i < (long)n; ++i) hit[i] = (uint32_t)any_hit(sc, o + 3 * i, d + 3 * i, tmax[i]);
+}
+
+uint32_t ORC(pick_emitter)(const scene *sc, uint32_t r) { return sc->ne ? sc->etri[pick_emitter(sc, r)] : MISS; }
+
+/* ---------------------------------------------------------------------------------------
+ * Configuration and frame (plain structs; the Python side fills them field by field)
+ * ------------------------------------------------------------------------------------- */
+typedef struct orc_config {
+    uint32_t width, height, rays_per_probe, table_log2;
+    uint32_t bounces, leak_bit, max_life, n_cap;
+    uint32_t seed, frac_bits, pad0, pad1;
+    float cell_scale, r_max, eps_scale, t_sky;
+    float sky[4];
+} orc_config;
+
+typedef struct orc_frame {
+    uint32_t index;
+    float fov_y, tan_half, pad;
+    float pos[4], fwd[4], right[4], up[4];
+} orc_frame;
+
+/* ---------------------------------------------------------------------------------------
+ * G-buffer (test input; the paper rasterises it, Section 2.1.1): one primary ray through
+ * every pixel centre, closest hit, face-forwarded normal, albedo, triangle index.
+ * ------------------------------------------------------------------------------------- */
+void ORC(render_gbuffer)(const scene *sc, const orc_frame *fr, uint32_t W, uint32_t H,
+                         real *pos, real *nrm, real *alb, uint32_t *prim)
+{
+    real aspect = (real)W / (real)H;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long y = 0; y < (long)H; ++y) {
+        for (uint32_t x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            real sx = (RC(2.0) * ((real)x + RC(0.5))) / (real)W - RC(1.0);
+            real sy = RC(1.0) - (RC(2.0) * ((real)y + RC(0.5))) / (real)H;
+            real a = (sx * (real)fr->tan_half) * aspect;
+            real b = sy * (real)fr->tan_half;
+            real d[3], o[3];
+            for (int k = 0; k < 3; ++k) d[k] = ((real)fr->fwd[k] + a * (real)fr->right[k]) + b * (real)fr->up[k];
+            real len = RSQRT(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (int k = 0; k < 3; ++k) { d[k] = d[k] / len; o[k] = (real)fr->pos[k]; }
+            uint32_t tri;
+            real t;
+            closest_hit(sc, o, d, RC(3.0e38), &tri, &t);
+            prim[p] = tri;
+            if (tri == MISS) {
+                for (int k = 0; k < 4; ++k) pos[4 * p + k] = nrm[4 * p + k] = alb[4 * p + k] = RC(0.0);
+                continue;
+            }
+            const real *n = sc->tn + 3 * (size_t)tri;
+            real dn = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+            real s = dn > RC(0.0) ? RC(-1.0) : RC(1.0);
+            const float *m = sc->mats + 6 * sc->tmat[tri];
+            for (int k = 0; k < 3; ++k) {
+                pos[4 * p + k] = o[k] + t * d[k];
+                nrm[4 * p + k] = s * n[k];
+                alb[4 * p + k] = (real)m[k];
+            }
+            pos[4 * p + 3] = t;
+            nrm[4 * p + 3] = RC(0.0);
+            alb[4 * p + 3] = RC(0.0);
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Per-frame state
+ * ------------------------------------------------------------------------------------- */
+typedef struct state {
+    orc_config cfg;
+    scene *sc;
+    uint32_t W, H, TW, TH, P, R, N;
+    uint32_t jx, jy;
+    uint32_t nmip, mip_w[32], mip_h[32], mip_off[32], mask_total;
+    uint32_t *mask;
+    real *ppos, *pnrm;
+    /* rays */
+    int32_t *r_slot;
+    real *r_t;
+    uint32_t *r_tri, *r_cell;
+    /* per-ray shading results (filled in the parallel phase, consumed in order) */
+    real *r_sample;
+    uint32_t *r_keylo, *r_keyhi, *r_valid;
+    int32_t *r_bslot;
+    /* world cache */
+    uint32_t *fp;
+    uint64_t *key;
+    uint32_t *acc;         /* [N][4] fixed-point r,g,b and count */
+    double *dacc;          /* [N][3] FP64 sums (reference mode) */
+    real *L;               /* [N][3] */
+    uint32_t *nhist, *life, *accessed;
+    /* probes */
+    real *atlas;           /* [P][64][4] */
+    real *sh;              /* [P][27] */
+    double mom[NCELL][10]; /* omega, m(3), M(xx,yy,zz,xy,xz,yz) */
+    uint64_t stats[16];
+    real kappa;
+} state;
+
+enum { ST_RAYS, ST_HITS, ST_INSERTS, ST_OVERFLOW, ST_NONFINITE, ST_WRAPS, ST_SHADOW, ST_OCCLUDED,
+       ST_EVICT, ST_LIVE, ST_RELAXED, ST_NOPROBE, ST_BOUNCE };
+
+/* ---------------------------------------------------------------------------------------
+ * Hemi-octahedral cell moments (float64 quadrature): for each of the 64 cells of the
+ * 8x8 atlas (Section 2.1: octahedral mapping of the oriented hemisphere), the solid angle,
+ * the first moment and the second moment of the direction.  Each cell is split into two
+ * triangles along the diagonal on which the map has a kink, and each triangle is integrated
+ * with a collapsed Gauss-Legendre product rule.
+ * ------------------------------------------------------------------------------------- */
+static const double GL16_X[16] = {
+    -0.9894009349916499, -0.9445750230732326, -0.8656312023878318, -0.7554044083550030,
+    -0.6178762444026438, -0.4580167776572274, -0.2816035507792589, -0.0950125098376374,
+    0.0950125098376374, 0.2816035507792589, 0.4580167776572274, 0.6178762444026438,
+    0.7554044083550030, 0.8656312023878318, 0.9445750230732326, 0.9894009349916499};
+static const double GL16_W[16] = {
+    0.0271524594117541, 0.0622535239386479, 0.0951585116824928, 0.1246289712555339,
+    0.1495959888165767, 0.1691565193950025, 0.1826034150449236, 0.1894506104550685,
+    0.1894506104550685, 0.1826034150449236, 0.1691565193950025, 0.1495959888165767,
+    0.1246289712555339, 0.0951585116824928, 0.0622535239386479, 0.0271524594117541};
+
+static void integrate_tri_uv(const double *p0, const double *p1, const double *p2, int sub, double *acc)
+{
+    /* subdivide the triangle into sub*sub similar triangles is awkward; instead split the
+     * square [0,1]^2 of the collapsed map into sub x sub blocks */
+    double e1u = p1[0] - p0[0], e1v = p1[1] - p0[1];
+    double e2u = p2[0] - p1[0], e2v = p2[1] - p1[1];
+    double jac = fabs(e1u * e2v - e1v * e2u);
+    for (int bs = 0; bs < sub; ++bs)
+        for (int bt = 0; bt < sub; ++bt)
+            for (int i = 0; i < 16; ++i)
+                for (int j = 0; j < 16; ++j) {
+                    double s = (bs + 0.5 + 0.5 * GL16_X[i]) / sub;
+                    double t = (bt + 0.5 + 0.5 * GL16_X[j]) / sub;
+                    double w = GL16_W[i] * GL16_W[j] * 0.25 / ((double)sub * sub) * s * jac;
+                    double u = p0[0] + s * e1u + s * t * e2u;
+                    double v = p0[1] + s * e1v + s * t * e2v;
+                    double a = 0.5 * (u + v), b = 0.5 * (u - v);
+                    double z = 1.0 - fabs(a) - fabs(b);
+                    double r2 = a * a + b * b + z * z;
+                    double r = sqrt(r2);
+                    double dw = w * 0.5 / (r2 * r);   /* d(omega) = du dv / (2 r^3) */
+                    double wx = a / r, wy = b / r, wz = z / r;
+                    acc[0] += dw;
+                    acc[1] += dw * wx; acc[2] += dw * wy; acc[3] += dw * wz;
+                    acc[4] += dw * wx * wx; acc[5] += dw * wy * wy; acc[6] += dw * wz * wz;
+                    acc[7] += dw * wx * wy; acc[8] += dw * wx * wz; acc[9] += dw * wy * wz;
+                }
+}
+
+void ORC(cell_moments)(double *out /* [64][10] */)
+{
+    for (int iy = 0; iy < 8; ++iy)
+        for (int ix = 0; ix < 8; ++ix) {
+            double u0 = -1.0 + ix * 0.25, u1 = u0 + 0.25, v0 = -1.0 + iy * 0.25, v1 = v0 + 0.25;
+            double acc[10] = {0};
+            double c00[2] = {u0, v0}, c10[2] = {u1, v0}, c01[2] = {u0, v1}, c11[2] = {u1, v1};
+            if (ix + iy == 7) {
+                /* kink along u = -v: split along the anti-diagonal c10-c01 */
+                integrate_tri_uv(c00, c10, c01, 4, acc);
+                integrate_tri_uv(c11, c01, c10, 4, acc);
+            } else {
+                /* split along the main diagonal c00-c11 (the kink u = v when ix == iy) */
+                integrate_tri_uv(c00, c10, c11, 4, acc);
+                integrate_tri_uv(c00, c11, c01, 4, acc);
+            }
+            for (int k = 0; k < 10; ++k) out[(iy * 8 + ix) * 10 + k] = acc[k];
+        }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Branchless orthonormal basis (Duff et al., JCGT 2017) around the probe normal
+ * ------------------------------------------------------------------------------------- */
+static void onb(const real *n, real *t, real *b)
+{
+    real sign = n[2] >= RC(0.0) ? RC(1.0) : RC(-1.0);
+    real a = RC(-1.0) / (sign + n[2]);
+    real bb = (n[0] * n[1]) * a;
+    t[0] = RC(1.0) + ((sign * n[0]) * n[0]) * a;
+    t[1] = sign * bb;
+    t[2] = -(sign * n[0]);
+    b[0] = bb;
+    b[1] = sign + (n[1] * n[1]) * a;
+    b[2] = -n[1];
+}
+
+/* cosine-distributed direction about n from two uniform numbers; also the hemi-oct cell of
+ * the local direction (8x8 atlas, Section 2.1) */
+static void cosine_dir(const real *n, real u0, real u1, real *d, uint32_t *cell)
+{
+    real c, s;
+    sincos_2pi(u1, &c, &s);
+    real r = RSQRT(u0);
+    real lx = r * c, ly = r * s;
+    real lz = RSQRT(rmax(RC(0.0), RC(1.0) - u0));
+    real t[3], b[3];
+    onb(n, t, b);
+    for (int k = 0; k < 3; ++k) d[k] = (lx * t[k] + ly * b[k]) + lz * n[k];
+    if (cell) {
+        real sum = (RABS(lx) + RABS(ly)) + lz;
+        real a = lx / sum, bb = ly / sum;
+        real uu = a + bb, vv = a - bb;
+        int ix = (int)RFLOOR(RC(4.0) * (uu + RC(1.0)));
+        int iy = (int)RFLOOR(RC(4.0) * (vv + RC(1.0)));
+        ix = ix < 0 ? 0 : (ix > 7 ? 7 : ix);
+        iy = iy < 0 ? 0 : (iy > 7 ? 7 : iy);
+        *cell = (uint32_t)(8 * iy + ix);
+    }
+}
+
+void ORC(cosine_dirs)(const real *n, const real *u0, const real *u1, uint32_t cnt, real *d, uint32_t *cell)
+{
+    for (uint32_t i = 0; i < cnt; ++i) cosine_dir(n + 3 * i, u0[i], u1[i], d + 3 * i, cell + i);
+}
+
+static real offset_eps(const orc_config *c, const real *p)
+{
+    real m = rmax(rmax(RABS(p[0]), RABS(p[1])), RABS(p[2]));
+    return (real)c->eps_scale * (RC(1.0) + m);
+}
+
+/* ---------------------------------------------------------------------------------------
+ * World-cache descriptor (Section 2.2.1 and 2.2.2).  READING: the descriptor is the
+ * quantised hit position floor(y * S) (S = 1 / cell size), a 6-way class of the
+ * face-forwarded surface normal, and the light-leak bit (ray length < cell size); LOD = 0.
+ * ------------------------------------------------------------------------------------- */
+static uint64_t cell_key(const orc_config *c, const real *y, const real *n, real t, int with_leak)
+{
+    real S = (real)c->cell_scale;
+    int32_t qx = (int32_t)RFLOOR(y[0] * S);
+    int32_t qy = (int32_t)RFLOOR(y[1] * S);
+    int32_t qz = (int32_t)RFLOOR(y[2] * S);
+    int axis = 0;
+    real best = RABS(n[0]);
+    if (RABS(n[1]) > best) { axis = 1; best = RABS(n[1]); }
+    if (RABS(n[2]) > best) { axis = 2; }
+    uint64_t cls = (uint64_t)(2 * axis + (n[axis] < RC(0.0) ? 1 : 0));
+    uint64_t leak = (with_leak && c->leak_bit && t * S < RC(1.0)) ? 1u : 0u;
+    return ((uint64_t)(uint32_t)qx & 0x3FFFFu) | (((uint64_t)(uint32_t)qy & 0x3FFFFu) << 18) |
+           (((uint64_t)(uint32_t)qz & 0x3FFFFu) << 36) | (cls << 54) | (leak << 57);
+}
+
+static uint32_t key_bucket(uint64_t key, uint32_t nbuckets)
+{
+    uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+    return pcg_hash(lo + pcg_hash(hi)) & (nbuckets - 1u);
+}
+
+static uint32_t key_fingerprint(uint64_t key)
+{
+    uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+    uint32_t h = xxh32_hash(lo + xxh32_hash(hi));
+    return h == 0u ? 1u : h;
+}
+
+void ORC(keys)(const orc_config *c, const real *y, const real *n, const real *t, uint32_t cnt,
+               uint64_t *key, uint32_t *bucket, uint32_t *fp)
+{
+    uint32_t nb = (1u << c->table_log2) / BUCKET;
+    for (uint32_t i = 0; i < cnt; ++i) {
+        key[i] = cell_key(c, y + 3 * i, n + 3 * i, t[i], 1);
+        bucket[i] = key_bucket(key[i], nb);
+        fp[i] = key_fingerprint(key[i]);
+    }
+}
+
+/* find an existing cell (lookup only): slot or -1 */
+static int32_t table_find(const state *st, uint64_t key)
+{
+    uint32_t nb = st->N / BUCKET;
+    uint32_t b = key_bucket(key, nb), f = key_fingerprint(key);
+    for (uint32_t s = 0; s < BUCKET; ++s)
+        if (st->fp[b * BUCKET + s] == f) return (int32_t)(b * BUCKET + s);
+    return -1;
+}
+
+/* find-or-insert with linear probing inside the bucket (Section 2.2.1): the fingerprint is
+ * searched first, otherwise the first empty slot is claimed; a full bucket drops the sample */
+static int32_t table_insert(state *st, uint64_t key)
+{
+    uint32_t nb = st->N / BUCKET;
+    uint32_t b = key_bucket(key, nb), f = key_fingerprint(key);
+    for (uint32_t s = 0; s < BUCKET; ++s)
+        if (st->fp[b * BUCKET + s] == f) return (int32_t)(b * BUCKET + s);
+    for (uint32_t s = 0; s < BUCKET; ++s) {
+        uint32_t slot = b * BUCKET + s;
+        if (st->fp[slot] == 0u) {
+            st->fp[slot] = f;
+            st->key[slot] = key;
+            st->stats[ST_INSERTS]++;
+            return (int32_t)slot;
+        }
+    }
+    st->stats[ST_OVERFLOW]++;
+    return -1;
+}
+
+state *ORC(create)(const orc_config *cfg, scene *sc)
+{
+    state *st = (state *)calloc(1, sizeof(state));
+    st->cfg = *cfg;
+    st->sc = sc;
+    st->W = cfg->width;
+    st->H = cfg->height;
+    st->TW = (cfg->width + 7) / 8;
+    st->TH = (cfg->height + 7) / 8;
+    st->P = st->TW * st->TH;
+    st->R = cfg->rays_per_probe;
+    st->N = 1u << cfg->table_log2;
+    uint32_t w = st->TW, h = st->TH, off = 0, k = 0;
+    for (;;) {
+        st->mip_w[k] = w;
+        st->mip_h[k] = h;
+        st->mip_off[k] = off;
+        off += w * h;
+        ++k;
+        if (w == 1 && h == 1) break;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    st->nmip = k;
+    st->mask_total = off;
+    size_t P = st->P, PR = (size_t)st->P * st->R, N = st->N;
+    st->mask = (uint32_t *)calloc(off, sizeof(uint32_t));
+    st->ppos = (real *)calloc(4 * P, sizeof(real));
+    st->pnrm = (real *)calloc(4 * P, sizeof(real));
+    st->r_slot = (int32_t *)calloc(PR, sizeof(int32_t));
+    st->r_t = (real *)calloc(PR, sizeof(real));
+    st->r_tri = (uint32_t *)calloc(PR, sizeof(uint32_t));
+    st->r_cell = (uint32_t *)calloc(PR, sizeof(uint32_t));
+    st->r_sample = (real *)calloc(3 * PR, sizeof(real));
+    st->r_keylo = (uint32_t *)calloc(PR, sizeof(uint32_t));
+    st->r_keyhi = (uint32_t *)calloc(PR, sizeof(uint32_t));
+    st->r_valid = (uint32_t *)calloc(PR, sizeof(uint32_t));
+    st->r_bslot = (int32_t *)calloc(PR, sizeof(int32_t));
+    st->fp = (uint32_t *)calloc(N, sizeof(uint32_t));
+    st->key = (uint64_t *)calloc(N, sizeof(uint64_t));
+    st->acc = (uint32_t *)calloc(4 * N, sizeof(uint32_t));
+    st->dacc = (double *)calloc(3 * N, sizeof(double));
+    st->L = (real *)calloc(3 * N, sizeof(real));
+    st->nhist = (uint32_t *)calloc(N, sizeof(uint32_t));
+    st->life = (uint32_t *)calloc(N, sizeof(uint32_t));
+    st->accessed = (uint32_t *)calloc(N, sizeof(uint32_t));
+    st->atlas = (real *)calloc(P * NCELL * 4, sizeof(real));
+    st->sh = (real *)calloc(P * 27, sizeof(real));
+    ORC(cell_moments)(&st->mom[0][0]);
+    return st;
+}
+
+void ORC(destroy)(state *st)
+{
+    if (!st) return;
+    free(st->mask); free(st->ppos); free(st->pnrm);
+    free(st->r_slot); free(st->r_t); free(st->r_tri); free(st->r_cell);
+    free(st->r_sample); free(st->r_keylo); free(st->r_keyhi); free(st->r_valid); free(st->r_bslot);
+    free(st->fp); free(st->key); free(st->acc); free(st->dacc); free(st->L);
+    free(st->nhist); free(st->life); free(st->accessed); free(st->atlas); free(st->sh);
+    free(st);
+}
+
+/* Algorithm 6: distance scale tan(fov_y * proj_size * max(1/H, H/W^2)), proj_size = 8,
+ * computed in float64 on the host and rounded once */
+float ORC(distance_scale)(float fov_y, uint32_t W, uint32_t H)
+{
+    double a = 1.0 / (double)H, b = (double)H / ((double)W * (double)W);
+    return (float)tan((double)fov_y * 8.0 * (a > b ? a : b));
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Spawn (Section 2.1.1) and probe mask with its MIP chain (Section 2.1.5).
+ * READING: a tile whose jittered pixel is off screen or sky gets the sentinel; the mask packs
+ * (y << 16) | x; each MIP entry keeps the first valid probe of its 2x2 children in raster order.
+ * ------------------------------------------------------------------------------------- */
+void ORC(spawn)(state *st, const orc_frame *fr, const real *gpos, const real *gnrm, const uint32_t *gprim)
+{
+    ORC(halton_jitter)(fr->index, &st->jx, &st->jy);
+    for (uint32_t ty = 0; ty < st->TH; ++ty)
+        for (uint32_t tx = 0; tx < st->TW; ++tx) {
+            uint32_t p = ty * st->TW + tx;
+            uint32_t px = 8 * tx + st->jx, py = 8 * ty + st->jy;
+            uint32_t m = SENTINEL;
+            if (px < st->W && py < st->H && gprim[(size_t)py * st->W + px] != MISS) m = (py << 16) | px;
+            st->mask[p] = m;
+            for (int k = 0; k < 4; ++k) {
+                if (m == SENTINEL) {
+                    st->ppos[4 * p + k] = st->pnrm[4 * p + k] = RC(0.0);
+                } else {
+                    size_t pix = (size_t)py * st->W + px;
+                    st->ppos[4 * p + k] = gpos[4 * pix + k];
+                    st->pnrm[4 * p + k] = gnrm[4 * pix + k];
+                }
+            }
+        }
+    for (uint32_t k = 1; k < st->nmip; ++k) {
+        const uint32_t *src = st->mask + st->mip_off[k - 1];
+        uint32_t *dst = st->mask + st->mip_off[k];
+        uint32_t sw = st->mip_w[k - 1], sh = st->mip_h[k - 1];
+        for (uint32_t y = 0; y < st->mip_h[k]; ++y)
+            for (uint32_t x = 0; x < st->mip_w[k]; ++x) {
+                uint32_t v = SENTINEL;
+                for (uint32_t c = 0; c < 4 && v == SENTINEL; ++c) {
+                    uint32_t cx = 2 * x + (c & 1), cy = 2 * y + (c >> 1);
+                    if (cx < sw && cy < sh) v = src[cy * sw + cx];
+                }
+                dst[y * st->mip_w[k] + x] = v;
+            }
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Trace (Sections 2.1.3, 2.2.1-2.2.4, 2.3.1): every probe ray finds its closest hit; a hit
+ * looks up (or creates) its world-cache cell and contributes one radiance sample to it:
+ * next-event estimation with one shadow ray towards an area-sampled emitter point, plus, with
+ * two bounces, the cached outgoing radiance found at the end of a cosine-sampled ray
+ * (temporal radiance feedback).  Samples are accumulated in fixed point (FP32 mode).
+ * ------------------------------------------------------------------------------------- */
+static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const real *y,
+                      const real *ny, real *s_out, int32_t *bslot, uint64_t *stat_shadow,
+                      uint64_t *stat_occ, uint64_t *stat_bounce)
+{
+    const orc_config *c = &st->cfg;
+    const scene *sc = st->sc;
+    real E[3] = {RC(0.0), RC(0.0), RC(0.0)};
+    real eps = offset_eps(c, y);
+    real yo[3];
+    for (int k = 0; k < 3; ++k) yo[k] = y[k] + ny[k] * eps;
+    if (sc->ne > 0) {
+        uint32_t e = sc->etri[pick_emitter(sc, rng_u32(c->seed, fr->index, gid, 2u))];
+        real u3 = rng_unit(rng_u32(c->seed, fr->index, gid, 3u));
+        real u4 = rng_unit(rng_u32(c->seed, fr->index, gid, 4u));
+        real su = RSQRT(u3);
+        real b0 = RC(1.0) - su, b1 = su * (RC(1.0) - u4), b2 = su * u4;
+        const float *v = sc->tv + 9 * (size_t)e;
+        real xl[3], w[3];
+        for (int k = 0; k < 3; ++k) xl[k] = (b0 * (real)v[k] + b1 * (real)v[3 + k]) + b2 * (real)v[6 + k];
+        for (int k = 0; k < 3; ++k) w[k] = xl[k] - yo[k];
+        real d2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+        if (d2 > RC(0.0)) {
+            real dist = RSQRT(d2);
+            real om[3] = {w[0] / dist, w[1] / dist, w[2] / dist};
+            const real *ne = sc->tn + 3 * (size_t)e;
+            real cos_y = (ny[0] * om[0] + ny[1] * om[1]) + ny[2] * om[2];
+            real cos_l = -((ne[0] * om[0] + ne[1] * om[1]) + ne[2] * om[2]);
+            if (cos_y > RC(0.0) && cos_l > RC(0.0)) {
+                (*stat_shadow)++;
+                if (!any_hit(sc, yo, om, dist * RC(0.9999))) {
+                    real g = ((cos_y * cos_l) * sc->area_total) / d2;
+                    const float *m = sc->mats + 6 * sc->tmat[e];
+                    for (int k = 0; k < 3; ++k) E[k] = (real)m[3 + k] * g;
+                } else {
+                    (*stat_occ)++;
+                }
+            }
+        }
+    }
+    real Lb[3] = {RC(0.0), RC(0.0), RC(0.0)};
+    *bslot = -1;
+    if (c->bounces >= 2) {
+        (*stat_bounce)++;
+        real u5 = rng_unit(rng_u32(c->seed, fr->index, gid, 5u));
+        real u6 = rng_unit(rng_u32(c->seed, fr->index, gid, 6u));
+        real d[3];
+        cosine_dir(ny, u5, u6, d, NULL);
+        uint32_t tri;
+        real t;
+        closest_hit(sc, yo, d, RC(3.0e38), &tri, &t);
+        if (tri == MISS) {
+            for (int k = 0; k < 3; ++k) Lb[k] = (real)c->sky[k];
+        } else {
+            real z[3], nz[3];
+            const real *n = sc->tn + 3 * (size_t)tri;
+            real dn = (n[0] * d[0] + n[1] * d[1]) + n[2] * d[2];
+            real sg = dn > RC(0.0) ? RC(-1.0) : RC(1.0);
+            for (int k = 0; k < 3; ++k) { z[k] = yo[k] + t * d[k]; nz[k] = sg * n[k]; }
+            int32_t slot = table_find(st, cell_key(c, z, nz, t, 1));
+            *bslot = slot;
+            if (slot >= 0)
+                for (int k = 0; k < 3; ++k) Lb[k] = st->L[3 * (size_t)slot + k];
+        }
+    }
+    for (int k = 0; k < 3; ++k) s_out[k] = E[k] * RC(0.31830988618379067) + Lb[k];
+}
+
+void ORC(trace)(state *st, const orc_frame *fr)
+{
+    const orc_config *c = &st->cfg;
+    const scene *sc = st->sc;
+    uint32_t R = st->R;
+    uint64_t nshadow = 0, nocc = 0, nbounce = 0;
+    /* parallel phase: rays, hits, keys, samples; nothing here writes the table */
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nshadow, nocc, nbounce)
+    for (long p = 0; p < (long)st->P; ++p) {
+        int valid = st->mask[p] != SENTINEL;
+        for (uint32_t r = 0; r < R; ++r) {
+            size_t gid = (size_t)p * R + r;
+            st->r_slot[gid] = -1;
+            st->r_t[gid] = RC(0.0);
+            st->r_tri[gid] = MISS;
+            st->r_cell[gid] = 0;
+            st->r_valid[gid] = 0;
+            st->r_bslot[gid] = -1;
+            if (!valid) continue;
+            const real *pp = st->ppos + 4 * p, *pn = st->pnrm + 4 * p;
+            real u0 = rng_unit(rng_u32(c->seed, fr->index, (uint32_t)gid, 0u));
+            real u1 = rng_unit(rng_u32(c->seed, fr->index, (uint32_t)gid, 1u));
+            real d[3], o[3];
+            uint32_t cell;
+            cosine_dir(pn, u0, u1, d, &cell);
+            real eps = offset_eps(c, pp);
+            for (int k = 0; k < 3; ++k) o[k] = pp[k] + pn[k] * eps;
+            uint32_t tri;
+            real t;
+            closest_hit(sc, o, d, RC(3.0e38), &tri, &t);
+            uint32_t flags = cell | 0x10000u;   /* bit 16: probe ray traced */
+            if (tri == MISS) {
+                st->r_t[gid] = (real)c->t_sky;
+                st->r_cell[gid] = flags;
+                continue;
+            }
+            const real *n = sc->tn + 3 * (size_t)tri;
+            real dn = (n[0] * d[0] + n[1] * d[1]) + n[2] * d[2];
+            real sg = dn > RC(0.0) ? RC(-1.0) : RC(1.0);
+            real y[3], ny[3];
+            for (int k = 0; k < 3; ++k) { y[k] = o[k] + t * d[k]; ny[k] = sg * n[k]; }
+            flags |= 0x100u;                     /* bit 8: hit */
+            if (dn < RC(0.0)) flags |= 0x200u;   /* bit 9: front face (one-sided emission) */
+            st->r_t[gid] = t;
+            st->r_tri[gid] = tri;
+            st->r_cell[gid] = flags;
+            uint64_t key = cell_key(c, y, ny, t, 1);
+            st->r_keylo[gid] = (uint32_t)key;
+            st->r_keyhi[gid] = (uint32_t)(key >> 32);
+            real s[3];
+            shade_hit(st, fr, (uint32_t)gid, y, ny, s, &st->r_bslot[gid], &nshadow, &nocc, &nbounce);
+            const float *m = sc->mats + 6 * sc->tmat[tri];
+            for (int k = 0; k < 3; ++k) st->r_sample[3 * gid + k] = (real)m[k] * s[k];
+            st->r_valid[gid] = 1;
+        }
+    }
+    st->stats[ST_SHADOW] += nshadow;
+    st->stats[ST_OCCLUDED] += nocc;
+    st->stats[ST_BOUNCE] += nbounce;
+    /* sequential phase: cell lookup/creation and accumulation in ray order */
+    size_t PR = (size_t)st->P * R;
+    for (size_t gid = 0; gid < PR; ++gid) {
+        if (!(st->r_cell[gid] & 0x10000u)) continue;
+        st->stats[ST_RAYS]++;
+        if (!st->r_valid[gid]) continue;
+        st->stats[ST_HITS]++;
+        uint64_t key = (uint64_t)st->r_keylo[gid] | ((uint64_t)st->r_keyhi[gid] << 32);
+        int32_t slot = table_insert(st, key);
+        st->r_slot[gid] = slot;
+        if (slot < 0) continue;
+        st->accessed[slot] = 1;
+        const real *s = st->r_sample + 3 * gid;
+        if (!isfinite((double)s[0]) || !isfinite((double)s[1]) || !isfinite((double)s[2])) {
+            st->stats[ST_NONFINITE]++;
+            continue;
+        }
+        for (int k = 0; k < 3; ++k) {
+            real v = rmin(rmax(s[k], RC(0.0)), (real)c->r_max);
+#ifdef ORC_F64
+            st->dacc[3 * (size_t)slot + k] += v;
+#else
+            float scaled = v * (float)(1u << c->frac_bits);
+            uint32_t q = (uint32_t)rintf(scaled);
+            uint32_t old = st->acc[4 * (size_t)slot + k];
+            st->acc[4 * (size_t)slot + k] = old + q;
+            if (old + q < old) st->stats[ST_WRAPS]++;
+#endif
+        }
+        st->acc[4 * (size_t)slot + 3] += 1u;
+    }
+    /* cells found by bounce lookups count as accessed; the lookups saw the table as it was
+     * before this frame's insertions, so their order does not matter */
+    for (size_t gid = 0; gid < PR; ++gid)
+        if (st->r_bslot[gid] >= 0) st->accessed[st->r_bslot[gid]] = 1u;
+}
+
+/* NEE radiance estimate E/pi (before albedo) for a surface point and normal, one estimate per
+ * sample id: the estimator used when filling cells (test entry; bounces are not taken) */
+void ORC(nee_samples)(state *st, const orc_frame *fr, const real *y, const real *ny,
+                      const uint32_t *ids, uint32_t n, real *out)
+{
+    uint32_t saved = st->cfg.bounces;
+    st->cfg.bounces = 1;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < (long)n; ++i) {
+        uint64_t a = 0, b = 0, c = 0;
+        int32_t bs;
+        shade_hit(st, fr, ids[i], y, ny, out + 3 * i, &bs, &a, &b, &c);
+    }
+    st->cfg.bounces = saved;
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Cache update (Section 2.2.1 decay and deallocation; Section 2.2.3 temporal accumulation).
+ * READING: the frame's mean sample enters an exponential moving average weighted by sample
+ * counts, capped at n_cap samples of history; the decay value is an integer life reset to
+ * max_life on access, decremented otherwise, and the cell is freed at zero.
+ * ------------------------------------------------------------------------------------- */
+static void cache_update(state *st)
+{
+    const orc_config *c = &st->cfg;
+    double scale = (double)(1u << c->frac_bits);
+    (void)scale;
+    uint64_t live = 0;
+    for (uint32_t s = 0; s < st->N; ++s) {
+        if (st->fp[s] == 0u) continue;
+        uint32_t cnt = st->acc[4 * (size_t)s + 3];
+        if (cnt > 0) {
+            uint32_t h = st->nhist[s] < c->n_cap ? st->nhist[s] : c->n_cap;
+            real w = (real)cnt / (real)((double)h + (double)cnt);
+            for (int k = 0; k < 3; ++k) {
+#ifdef ORC_F64
+                real mean = st->dacc[3 * (size_t)s + k] / (double)cnt;
+#else
+                real mean = (float)((double)st->acc[4 * (size_t)s + k] / ((double)cnt * scale));
+#endif
+                real L = st->L[3 * (size_t)s + k];
+                st->L[3 * (size_t)s + k] = L + w * (mean - L);
+            }
+            uint64_t nh = (uint64_t)st->nhist[s] + cnt;
+            st->nhist[s] = nh < c->n_cap ? (uint32_t)nh : c->n_cap;
+        }
+        if (st->accessed[s]) st->life[s] = c->max_life;
+        else st->life[s] = st->life[s] - 1u;
+        if (st->life[s] == 0u) {
+            st->fp[s] = 0u;
+            st->key[s] = 0u;
+            st->nhist[s] = 0u;
+            for (int k = 0; k < 3; ++k) st->L[3 * (size_t)s + k] = RC(0.0);
+            st->stats[ST_EVICT]++;
+        } else {
+            ++live;
+        }
+        for (int k = 0; k < 4; ++k) st->acc[4 * (size_t)s + k] = 0u;
+        for (int k = 0; k < 3; ++k) st->dacc[3 * (size_t)s + k] = 0.0;
+        st->accessed[s] = 0u;
+    }
+    st->stats[ST_LIVE] = live;
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Probe gather (Section 2.1.4): per probe, every ray's radiance (sky on a miss, else the
+ * hit's front-face emission plus the updated cached outgoing radiance) is averaged per
+ * atlas cell in ray order; cells that received no ray get the mean of the populated cells
+ * (radiance backup); alpha holds the mean travelled distance.
+ * ------------------------------------------------------------------------------------- */
+static void gather(state *st)
+{
+    const orc_config *c = &st->cfg;
+    const scene *sc = st->sc;
+    uint32_t R = st->R;
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < (long)st->P; ++p) {
+        real *at = st->atlas + (size_t)p * NCELL * 4;
+        for (int i = 0; i < NCELL * 4; ++i) at[i] = RC(0.0);
+        if (st->mask[p] == SENTINEL) continue;
+        real sum[NCELL][4];
+        uint32_t cnt[NCELL];
+        memset(cnt, 0, sizeof(cnt));
+        for (int i = 0; i < NCELL; ++i) sum[i][0] = sum[i][1] = sum[i][2] = sum[i][3] = RC(0.0);
+        for (uint32_t r = 0; r < R; ++r) {
+            size_t gid = (size_t)p * R + r;
+            uint32_t fl = st->r_cell[gid];
+            uint32_t cell = fl & 63u;
+            real v[3];
+            if (!(fl & 0x100u)) {
+                for (int k = 0; k < 3; ++k) v[k] = (real)c->sky[k];
+            } else {
+                const float *m = sc->mats + 6 * sc->tmat[st->r_tri[gid]];
+                int32_t slot = st->r_slot[gid];
+                for (int k = 0; k < 3; ++k) {
+                    real le = (fl & 0x200u) ? (real)m[3 + k] : RC(0.0);
+                    real lr = slot >= 0 ? st->L[3 * (size_t)slot + k] : RC(0.0);
+                    v[k] = le + lr;
+                }
+            }
+            for (int k = 0; k < 3; ++k) sum[cell][k] = sum[cell][k] + v[k];
+            sum[cell][3] = sum[cell][3] + st->r_t[gid];
+            cnt[cell]++;
+        }
+        real mean[4] = {RC(0.0), RC(0.0), RC(0.0), RC(0.0)};
+        uint32_t npop = 0;
+        for (int i = 0; i < NCELL; ++i) {
+            if (!cnt[i]) continue;
+            for (int k = 0; k < 4; ++k) {
+                at[4 * i + k] = sum[i][k] / (real)cnt[i];
+                mean[k] = mean[k] + at[4 * i + k];
+            }
+            ++npop;
+        }
+        if (npop == 0) continue;
+        for (int k = 0; k < 4; ++k) mean[k] = mean[k] / (real)npop;
+        for (int i = 0; i < NCELL; ++i)
+            if (!cnt[i])
+                for (int k = 0; k < 4; ++k) at[4 * i + k] = mean[k];
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Spherical harmonics (Section 2.4.2): projection of the piecewise-constant atlas onto the
+ * real SH basis of bands 0..2, exact per cell through the cell's direction moments rotated
+ * into the probe frame; irradiance is the dot product with the projected clamped cosine
+ * (Ramamoorthi and Hanrahan 2001: band factors pi, 2pi/3, pi/4).
+ * ------------------------------------------------------------------------------------- */
+#define SH_C0 0.28209479177387814   /* 1/(2 sqrt(pi)) */
+#define SH_C1 0.48860251190291992   /* sqrt(3/(4 pi)) */
+#define SH_C2 1.09254843059207907   /* sqrt(15/pi)/2 */
+#define SH_C20 0.31539156525252005  /* sqrt(5/pi)/4 */
+#define SH_C22 0.54627421529603959  /* sqrt(15/pi)/4 */
+
+static void sh_project(state *st)
+{
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < (long)st->P; ++p) {
+        real *out = st->sh + (size_t)p * 27;
+        for (int i = 0; i < 27; ++i) out[i] = RC(0.0);
+        if (st->mask[p] == SENTINEL) continue;
+        const real *n = st->pnrm + 4 * p;
+        real t[3], b[3];
+        onb(n, t, b);
+        real Rm[3][3];   /* columns t, b, n */
+        for (int i = 0; i < 3; ++i) { Rm[i][0] = t[i]; Rm[i][1] = b[i]; Rm[i][2] = n[i]; }
+        const real *at = st->atlas + (size_t)p * NCELL * 4;
+        for (int cidx = 0; cidx < NCELL; ++cidx) {
+            const double *mo = st->mom[cidx];
+            real om = (real)mo[0];
+            real ml[3] = {(real)mo[1], (real)mo[2], (real)mo[3]};
+            real Ml[3][3] = {{(real)mo[4], (real)mo[7], (real)mo[8]},
+                             {(real)mo[7], (real)mo[5], (real)mo[9]},
+                             {(real)mo[8], (real)mo[9], (real)mo[6]}};
+            real mw[3], Mw[3][3];
+            for (int i = 0; i < 3; ++i) mw[i] = (Rm[i][0] * ml[0] + Rm[i][1] * ml[1]) + Rm[i][2] * ml[2];
+            real tmp[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    tmp[i][j] = (Rm[i][0] * Ml[0][j] + Rm[i][1] * Ml[1][j]) + Rm[i][2] * Ml[2][j];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    Mw[i][j] = (tmp[i][0] * Rm[j][0] + tmp[i][1] * Rm[j][1]) + tmp[i][2] * Rm[j][2];
+            real I[9];
+            I[0] = (real)SH_C0 * om;
+            I[1] = (real)SH_C1 * mw[1];
+            I[2] = (real)SH_C1 * mw[2];
+            I[3] = (real)SH_C1 * mw[0];
+            I[4] = (real)SH_C2 * Mw[0][1];
+            I[5] = (real)SH_C2 * Mw[1][2];
+            I[6] = (real)SH_C20 * (RC(3.0) * Mw[2][2] - om);
+            I[7] = (real)SH_C2 * Mw[0][2];
+            I[8] = (real)SH_C22 * (Mw[0][0] - Mw[1][1]);
+            for (int l = 0; l < 9; ++l)
+                for (int k = 0; k < 3; ++k) out[3 * l + k] = out[3 * l + k] + at[4 * cidx + k] * I[l];
+        }
+    }
+}
+
+static void sh_irradiance(const real *c, const real *n, real *E)
+{
+    real Y[9];
+    Y[0] = (real)SH_C0;
+    Y[1] = (real)SH_C1 * n[1];
+    Y[2] = (real)SH_C1 * n[2];
+    Y[3] = (real)SH_C1 * n[0];
+    Y[4] = (real)SH_C2 * (n[0] * n[1]);
+    Y[5] = (real)SH_C2 * (n[1] * n[2]);
+    Y[6] = (real)SH_C20 * (RC(3.0) * (n[2] * n[2]) - RC(1.0));
+    Y[7] = (real)SH_C2 * (n[0] * n[2]);
+    Y[8] = (real)SH_C22 * (n[0] * n[0] - n[1] * n[1]);
+    const real A[9] = {(real)3.14159265358979324, (real)2.09439510239319549, (real)2.09439510239319549,
+                       (real)2.09439510239319549, (real)0.78539816339744831, (real)0.78539816339744831,
+                       (real)0.78539816339744831, (real)0.78539816339744831, (real)0.78539816339744831};
+    for (int k = 0; k < 3; ++k) {
+        real acc = RC(0.0);
+        for (int l = 0; l < 9; ++l) acc = acc + (A[l] * c[3 * l + k]) * Y[l];
+        E[k] = acc;
+    }
+}
+
+void ORC(sh_eval)(const real *coef, const real *n, uint32_t cnt, real *E)
+{
+    for (uint32_t i = 0; i < cnt; ++i) sh_irradiance(coef + 27 * (size_t)i, n + 3 * (size_t)i, E + 3 * (size_t)i);
+}
+
+/* project arbitrary atlases [cnt][64][4] with given normals [cnt][3] (test entry) */
+void ORC(sh_project_atlas)(state *st, const real *atlas, const real *nrm, uint32_t cnt, real *out)
+{
+    real *sa = st->atlas, *ss = st->sh, *sn = st->pnrm;
+    uint32_t *sm = st->mask;
+    uint32_t sp = st->P;
+    st->atlas = (real *)atlas;
+    st->sh = out;
+    st->pnrm = (real *)calloc(4 * (size_t)cnt, sizeof(real));
+    st->mask = (uint32_t *)calloc(cnt, sizeof(uint32_t));
+    for (uint32_t i = 0; i < cnt; ++i)
+        for (int k = 0; k < 3; ++k) st->pnrm[4 * (size_t)i + k] = nrm[3 * (size_t)i + k];
+    st->P = cnt;
+    sh_project(st);
+    free(st->pnrm);
+    free(st->mask);
+    st->atlas = sa; st->sh = ss; st->pnrm = sn; st->mask = sm; st->P = sp;
+}
+
+void ORC(update)(state *st, const orc_frame *fr)
+{
+    (void)fr;
+    cache_update(st);
+    gather(st);
+    sh_project(st);
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Algorithm 4: sparse directional search through the probe-mask MIP chain.
+ * READING: "pixel /= 2" is a floor division (arithmetic shift), so negative lattice
+ * positions stay out of bounds.
+ * ------------------------------------------------------------------------------------- */
+static uint32_t find_closest_probe(const state *st, int32_t px, int32_t py, int32_t ox, int32_t oy)
+{
+    int32_t x = px >> 3, y = py >> 3;
+    for (uint32_t mip = 0; mip < st->nmip; ++mip) {
+        int32_t qx = x + ox, qy = y + oy;
+        if (qx < 0 || qy < 0 || qx >= (int32_t)st->mip_w[mip] || qy >= (int32_t)st->mip_h[mip]) break;
+        uint32_t v = st->mask[st->mip_off[mip] + (uint32_t)qy * st->mip_w[mip] + (uint32_t)qx];
+        if (v != SENTINEL) return v;
+        x >>= 1;
+        y >>= 1;
+    }
+    return SENTINEL;
+}
+
+uint32_t ORC(find_probe)(const state *st, int32_t px, int32_t py, int32_t ox, int32_t oy)
+{
+    return find_closest_probe(st, px, py, ox, oy);
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Per-pixel interpolation (Section 2.4.1) with the adaptive cell size of Algorithm 6.
+ * READING: the four neighbours are the 2x2 lattice probes around the pixel, each found with
+ * Algorithm 4 from its lattice tile; weight = bilinear * [plane distance <= cell size] *
+ * max(0, n_p . n_q); if every weight is zero but a probe was found, equal weights (relaxed,
+ * flag 1); no probe found: flag 2; sky pixel: flag 3.  Pixel jitter is off.
+ * ------------------------------------------------------------------------------------- */
+void ORC(interpolate)(state *st, const orc_frame *fr, const real *gpos, const real *gnrm,
+                      const uint32_t *gprim, real *out)
+{
+    real kappa = (real)ORC(distance_scale)(fr->fov_y, st->W, st->H);
+    st->kappa = kappa;
+    uint64_t relaxed = 0, noprobe = 0;
+#pragma omp parallel for schedule(static) reduction(+ : relaxed, noprobe)
+    for (long y = 0; y < (long)st->H; ++y) {
+        for (uint32_t x = 0; x < st->W; ++x) {
+            size_t pix = (size_t)y * st->W + x;
+            real *o = out + 4 * pix;
+            if (gprim[pix] == MISS) { o[0] = o[1] = o[2] = RC(0.0); o[3] = RC(3.0); continue; }
+            const real *pp = gpos + 4 * pix, *pn = gnrm + 4 * pix;
+            real dx = pp[0] - (real)fr->pos[0], dy = pp[1] - (real)fr->pos[1], dz = pp[2] - (real)fr->pos[2];
+            real cell_size = kappa * RSQRT((dx * dx + dy * dy) + dz * dz);
+            int32_t ux = (int32_t)x - (int32_t)st->jx, uy = (int32_t)y - (int32_t)st->jy;
+            int32_t bx = ux >> 3, by = uy >> 3;
+            real fx = (real)(ux - 8 * bx) * RC(0.125), fy = (real)(uy - 8 * by) * RC(0.125);
+            real acc[3] = {RC(0.0), RC(0.0), RC(0.0)}, wsum = RC(0.0);
+            real eq[4][3];
+            int nfound = 0;
+            for (int k = 0; k < 4; ++k) {
+                int32_t ox = k & 1, oy = k >> 1;
+                uint32_t m = find_closest_probe(st, 8 * bx, 8 * by, ox, oy);
+                if (m == SENTINEL) continue;
+                uint32_t qx = m & 0xFFFFu, qy = m >> 16;
+                uint32_t q = (qy >> 3) * st->TW + (qx >> 3);
+                const real *qp = st->ppos + 4 * (size_t)q, *qn = st->pnrm + 4 * (size_t)q;
+                real wb = (ox ? fx : RC(1.0) - fx) * (oy ? fy : RC(1.0) - fy);
+                real pd = RABS(((qp[0] - pp[0]) * pn[0] + (qp[1] - pp[1]) * pn[1]) + (qp[2] - pp[2]) * pn[2]);
+                real nd = (pn[0] * qn[0] + pn[1] * qn[1]) + pn[2] * qn[2];
+                real w = (pd <= cell_size) ? wb * rmax(RC(0.0), nd) : RC(0.0);
+                real E[3];
+                sh_irradiance(st->sh + 27 * (size_t)q, pn, E);
+                for (int c = 0; c < 3; ++c) { eq[nfound][c] = E[c]; acc[c] = acc[c] + w * E[c]; }
+                wsum = wsum + w;
+                ++nfound;
+            }
+            if (wsum > RC(0.0)) {
+                for (int c = 0; c < 3; ++c) o[c] = acc[c] / wsum;
+                o[3] = RC(0.0);
+            } else if (nfound > 0) {
+                for (int c = 0; c < 3; ++c) {
+                    real s = RC(0.0);
+                    for (int i = 0; i < nfound; ++i) s = s + eq[i][c];
+                    o[c] = s / (real)nfound;
+                }
+                o[3] = RC(1.0);
+                ++relaxed;
+            } else {
+                o[0] = o[1] = o[2] = RC(0.0);
+                o[3] = RC(2.0);
+                ++noprobe;
+            }
+        }
+    }
+    st->stats[ST_RELAXED] = relaxed;
+    st->stats[ST_NOPROBE] = noprobe;
+}
+
+/* lookup-only query of the world cache for caller points (pos.w >= 0 is the ray length for
+ * the leak bit); result rgb and a = 1 if the cell exists */
+void ORC(query)(const state *st, const real *pos, const real *nrm, uint32_t n, real *out)
+{
+    for (uint32_t i = 0; i < n; ++i) {
+        const real *p = pos + 4 * (size_t)i, *nn = nrm + 4 * (size_t)i;
+        int with_leak = p[3] >= RC(0.0);
+        uint64_t key = cell_key(&st->cfg, p, nn, with_leak ? p[3] : RC(0.0), with_leak);
+        int32_t slot = table_find(st, key);
+        for (int k = 0; k < 3; ++k) out[4 * (size_t)i + k] = slot >= 0 ? st->L[3 * (size_t)slot + k] : RC(0.0);
+        out[4 * (size_t)i + 3] = slot >= 0 ? RC(1.0) : RC(0.0);
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Exports for comparison
+ * ------------------------------------------------------------------------------------- */
+void ORC(dims)(const state *st, uint32_t *out /* P, R, N, TW, TH, nmip, mask_total, jx, jy */)
+{
+    out[0] = st->P; out[1] = st->R; out[2] = st->N; out[3] = st->TW; out[4] = st->TH;
+    out[5] = st->nmip; out[6] = st->mask_total; out[7] = st->jx; out[8] = st->jy;
+}
+
+void ORC(export_probes)(const state *st, uint32_t *mask, real *ppos, real *pnrm, real *atlas, real *sh)
+{
+    if (mask) memcpy(mask, st->mask, sizeof(uint32_t) * st->mask_total);
+    if (ppos) memcpy(ppos, st->ppos, sizeof(real) * 4 * st->P);
+    if (pnrm) memcpy(pnrm, st->pnrm, sizeof(real) * 4 * st->P);
+    if (atlas) memcpy(atlas, st->atlas, sizeof(real) * (size_t)st->P * NCELL * 4);
+    if (sh) memcpy(sh, st->sh, sizeof(real) * (size_t)st->P * 27);
+}
+
+void ORC(export_rays)(const state *st, int32_t *slot, real *t, uint32_t *tri, uint32_t *cell,
+                      uint64_t *key, real *sample)
+{
+    size_t PR = (size_t)st->P * st->R;
+    if (slot) memcpy(slot, st->r_slot, sizeof(int32_t) * PR);
+    if (t) memcpy(t, st->r_t, sizeof(real) * PR);
+    if (tri) memcpy(tri, st->r_tri, sizeof(uint32_t) * PR);
+    if (cell) memcpy(cell, st->r_cell, sizeof(uint32_t) * PR);
+    if (key)
+        for (size_t i = 0; i < PR; ++i) key[i] = (uint64_t)st->r_keylo[i] | ((uint64_t)st->r_keyhi[i] << 32);
+    if (sample) memcpy(sample, st->r_sample, sizeof(real) * 3 * PR);
+}
+
+/* live cells in slot order: bucket*2^32|fp, key, acc[4], L[3], nhist, life; returns count */
+uint32_t ORC(export_table)(const state *st, uint64_t *id, uint64_t *key, uint32_t *acc, real *L,
+                           uint32_t *nhist, uint32_t *life, uint32_t cap)
+{
+    uint32_t n = 0;
+    for (uint32_t s = 0; s < st->N; ++s) {
+        if (st->fp[s] == 0u) continue;
+        if (n < cap) {
+            id[n] = ((uint64_t)(s / BUCKET) << 32) | st->fp[s];
+            key[n] = st->key[s];
+            for (int k = 0; k < 4; ++k) acc[4 * (size_t)n + k] = st->acc[4 * (size_t)s + k];
+            for (int k = 0; k < 3; ++k) L[3 * (size_t)n + k] = st->L[3 * (size_t)s + k];
+            nhist[n] = st->nhist[s];
+            life[n] = st->life[s];
+        }
+        ++n;
+    }
+    return n;
+}
+
+/* write a cell directly (tests of update / gather rules) */
+int ORC(poke_cell)(state *st, uint64_t key, const uint32_t *acc4, const real *L3, uint32_t nhist,
+                   uint32_t life, uint32_t accessed)
+{
+    int32_t slot = table_insert(st, key);
+    if (slot < 0) return -1;
+    for (int k = 0; k < 4; ++k) st->acc[4 * (size_t)slot + k] = acc4[k];
+    for (int k = 0; k < 3; ++k) st->L[3 * (size_t)slot + k] = L3[k];
+    st->nhist[slot] = nhist;
+    st->life[slot] = life;
+    st->accessed[slot] = accessed;
+    return slot;
+}
+
+void ORC(cache_update_only)(state *st) { cache_update(st); }
+
+void ORC(stats)(const state *st, uint64_t *out) { memcpy(out, st->stats, sizeof(st->stats)); }
+
+real ORC(kappa)(const state *st) { return st->kappa; }
