@@ -1,0 +1,238 @@
+"""Benchmark of the per-frame GI pass on one MI355X.
+
+One step = one frame of the whole pass (gi_spawn_probes -> gi_trace_probes -> gi_cache_update
+(update, gather, SH) -> gi_interpolate_probes, plus the moving light's upload) on the 1080p
+field workload: 1920x1080 G-buffer over a seeded ~1.0M-triangle scene, 32,400 probes x 64
+rays, 2^20 world-cache slots, a camera orbit and one light on a circle.  G-buffers of every
+frame are rendered into HBM before the timed region (the paper rasterises them; they are an
+input of the pass).
+
+Prints one JSON line: ms/frame (value), probe Mrays/s, per-kernel times, the roofline of the
+dominant kernel and the CPU oracle's time on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES, TRI_BYTES = 128, 48
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2310_19855_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2310_19855_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel sources; else None"""
+    path = os.path.join(ROOT, "profiles", "traffic_field1080.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k or d.get("src_hash") != _src_hash():
+        return None
+    return k.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=55)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="field1080")
+    ap.add_argument("--profile-frames", type=int, default=5)
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2310_19855_amd import gi
+    from paper_2310_19855_amd import inputs as I
+
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    preset = dict(I.PRESETS[args.workload])
+    W, H, R = preset["width"], preset["height"], preset["rays_per_probe"]
+    scene = I.make_scene(preset["scene"])
+    cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=preset["table_log2"],
+               bounces=preset["bounces"], sky=scene.sky)
+    torch.cuda.set_device(0)
+    ctx = gi.Context(**cfg)
+    t0 = time.time()
+    ctx.build_bvh(scene)
+    t_bvh = time.time() - t0
+    dims = ctx.dims()
+    log(f"[bench] scene {scene.name}: {scene.n_tris} tris, BVH {int(dims[9])} nodes depth {int(dims[10])} "
+        f"built in {t_bvh:.2f}s")
+
+    n_frames = args.warmup + args.steps
+    n_gb = max(n_frames, args.profile_frames)
+    cams = [I.camera_for(scene.name, f) for f in range(n_gb)]
+    for f, c in enumerate(cams):
+        c.index = f
+    gbs = []
+    for f in range(n_gb):
+        if scene.dynamic is not None:
+            tv, m = scene.dynamic(f)
+            ctx.set_dynamic(tv, m)
+        g = gi.GBuffer(H, W)
+        ctx.render_gbuffer(cams[f], g.pos, g.nrm, g.alb, g.prim)
+        gbs.append(g)
+    torch.cuda.synchronize()
+    dyn = [scene.dynamic(f) if scene.dynamic is not None else None for f in range(n_gb)]
+    out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+    log(f"[bench] {n_gb} G-buffers resident ({n_gb * W * H * 52 / 2**30:.1f} GiB)")
+
+    def frame(f, fi):
+        g = gbs[f]
+        if dyn[f] is not None:
+            ctx.set_dynamic(*dyn[f])
+        cam = cams[f]
+        cam.index = fi
+        ctx.spawn_probes(cam, g.pos, g.nrm, g.prim)
+        ctx.trace_probes(cam)
+        ctx.cache_update(cam)
+        ctx.interpolate_probes(cam, g.pos, g.nrm, g.prim, out)
+
+    for f in range(args.warmup):
+        frame(f, f)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for k in range(args.steps):
+        f = args.warmup + k
+        frame(f, f)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    stats = ctx.stats()
+    ms_per_frame = wall * 1e3 / args.steps
+    log(f"[bench] {args.steps} frames: {ms_per_frame:.3f} ms/frame wall, {gpu_ms / args.steps:.3f} ms/frame events")
+
+    # per-kernel device times (HIP events on the launch stream), separate pass
+    ctx.profile(True)
+    ctx.profile_read()
+    for k in range(args.profile_frames):
+        f = k % n_gb
+        frame(f, n_frames + k)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    trav = ctx.measure_traversal()
+    pf = ctx.stats()
+    kern = {name: dict(launches=c, avg_ms=ms / max(c, 1)) for name, (c, ms) in prof.items()}
+
+    probes_valid = stats["rays"] / args.steps / R
+    rays_per_frame = stats["rays"] / args.steps
+    hits_per_frame = stats["hits"] / args.steps
+    trace_ms = kern.get("trace_probes", {}).get("avg_ms", float("nan"))
+    mrays = rays_per_frame / (trace_ms * 1e-3) / 1e6 if trace_ms == trace_ms else None
+
+    # algorithmic bytes per launch (the traffic the method must move), per kernel
+    P = int(dims[0])
+    N = int(dims[2])
+    pr_rays = max(trav["probe_rays"], 1)
+    alg = {
+        "trace_probes": trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES
+        + 16 * trav["probe_rays"] + 32 * P,
+        "shade_hits": trav["shadow_nodes"] * NODE_BYTES + trav["shadow_tris"] * TRI_BYTES
+        + hits_per_frame * (128 + 16 + 4 + 32 + 8 + 32),
+        "cache_update": 4 * N + 96 * stats["live"],
+        "gather_sh": rays_per_frame * 32 + P * (64 * 16 + 112 + 16),
+        "interpolate": W * H * (52 + 16) + P * 144,
+    }
+    total_ms = sum(v["avg_ms"] * v["launches"] for v in kern.values()) / max(args.profile_frames, 1)
+    dom = max(kern.items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])[0]
+    for name, v in kern.items():
+        if name in alg:
+            v["alg_bytes"] = int(alg[name])
+            v["gbs"] = alg[name] / (v["avg_ms"] * 1e-3) / 1e9
+            v["frac_hbm"] = v["gbs"] / HBM_PEAK_GBS
+        v["share"] = v["avg_ms"] * v["launches"] / max(args.profile_frames, 1) / total_ms if total_ms else None
+    dk = kern[dom]
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dk.get("gbs", 0.0), 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dk.get("frac_hbm", 0.0), 5),
+                "traffic": _traffic(dom, dk.get("alg_bytes")),
+                "alg_bytes_per_launch": dk.get("alg_bytes"), "avg_launch_ms": dk["avg_ms"],
+                "bytes_per_probe_ray": (trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES) / pr_rays,
+                "nodes_per_probe_ray": trav["probe_nodes"] / pr_rays,
+                "tris_per_probe_ray": trav["probe_tris"] / pr_rays}
+    log(f"[bench] kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms x{v['launches'] // max(args.profile_frames, 1)}"
+                                         for k, v in sorted(kern.items(), key=lambda kv: -kv[1]['avg_ms'] * kv[1]['launches'])))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cfg, cams, args.cpu_frames, log)
+
+    line = {
+        "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
+        "value": round(ms_per_frame, 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_frame, 4), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+u32",
+        "data": "synthetic (seeded procedural scene, camera orbit, moving light)",
+        "config": {"workload": f"{args.workload}: {W}x{H} G-buffer, {scene.n_tris} tris ({scene.name}), "
+                               f"{P} probe tiles x {R} rays, 2^{preset['table_log2']} cache slots, "
+                               f"{preset['bounces']} bounce(s), frames {args.warmup}..{n_frames - 1}",
+                   "cache": "plain"},
+        "probe_mrays_per_s": round(mrays, 1) if mrays else None,
+        "probe_rays_per_frame": int(rays_per_frame), "hits_per_frame": int(hits_per_frame),
+        "gpu_event_ms_per_frame": round(gpu_ms / args.steps, 4),
+        "bvh_build_s": round(t_bvh, 2),
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(scene, cfg, cams, frames, log):
+    """The oracle (plain C, all host threads) on the same scene, config and frames at full
+    resolution: spawn -> trace -> update -> interpolate, G-buffer excluded, averaged."""
+    import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
+    t0 = time.time()
+    osc = O.OracleScene(scene)
+    st = O.OracleFrameState(osc, dict(O.default_config(), **cfg))
+    t_build = time.time() - t0
+    tot = 0.0
+    for f in range(frames):
+        osc.set_frame_dynamic(f)
+        g = osc.gbuffer(cams[f], cfg["width"], cfg["height"])
+        t1 = time.time()
+        st.frame(cams[f], g)
+        tot += time.time() - t1
+        log(f"[bench] cpu oracle frame {f}: {time.time() - t1:.2f}s")
+    ms = tot * 1e3 / frames
+    return {"value": round(ms, 1), "unit": "ms/frame", "cores": cores, "kind": "oracle",
+            "sample": f"{frames} full frames (frames 0..{frames - 1}) of the same workload, "
+                      f"spawn..interpolate, G-buffer and BVH build ({t_build:.1f}s) excluded"}
+
+
+if __name__ == "__main__":
+    main()

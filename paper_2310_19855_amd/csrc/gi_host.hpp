@@ -1,0 +1,137 @@
+// Host-side context of the GI library and the launch interface of its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gi.h"
+#include "gi_types.hpp"
+
+namespace gi {
+
+void build_bvh4(const float* tv, uint32_t n, std::vector<Node4>& nodes, std::vector<uint32_t>& order,
+                uint32_t& depth);
+void cell_moment_table(double out[64][10]);
+
+// device arrays of the world cache (Section 2.2.1): structure of arrays over N slots
+struct Table {
+  uint32_t* fp = nullptr;        // fingerprint, 0 = empty
+  uint64_t* key = nullptr;       // descriptor of the cell (written by the inserting ray)
+  uint4* acc = nullptr;          // fixed-point r, g, b sums and sample count of this frame
+  float4* L = nullptr;           // cached outgoing radiance (rgb)
+  uint2* meta = nullptr;         // (history samples, life)
+  uint32_t* accessed = nullptr;  // touched this frame
+};
+
+struct LearnedState;  // learned surrogate (gi_learned.hip)
+
+struct FrameArgs {
+  uint32_t index;
+  float cam[3];
+  float kappa;      // Algorithm 6 distance scale
+  uint32_t jx, jy;
+};
+
+struct KernelTimer {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace gi
+
+struct gi_context {
+  gi_config cfg{};
+  int device = 0;
+  std::string err;
+  // sizes
+  uint32_t W = 0, H = 0, TW = 0, TH = 0, P = 0, R = 0, N = 0;
+  uint32_t nmip = 0, mask_total = 0;
+  uint32_t mip_w[32]{}, mip_h[32]{}, mip_off[32]{};
+  // scene
+  bool has_scene = false;
+  uint32_t nt = 0, n_mats = 0, n_nodes = 0, bvh_depth = 0, stack_depth = 0;
+  gi::Node4* d_nodes = nullptr;
+  float4* d_tris = nullptr;     // leaf-ordered triangles, 3 float4 each (v0.w = index)
+  float4* d_tnrm = nullptr;     // [nt + kMaxDyn] unit normal, w = material index
+  float4* d_mats = nullptr;     // [2 * n_mats]: albedo, emission
+  float4* d_dyn = nullptr;      // [3 * kMaxDyn]
+  uint32_t n_dyn = 0;
+  uint32_t* d_etri = nullptr;   // emitter triangles
+  uint32_t* d_ethr = nullptr;   // their cumulative-area thresholds (scaled to 2^32)
+  float4* d_evert = nullptr;    // their vertices, 3 float4 each
+  uint32_t n_emit = 0, emit_cap = 0;
+  float area_total = 0.0f;
+  std::vector<float> h_static_tv;       // static triangles [nt][9] (emitter rebuilds)
+  std::vector<uint32_t> h_static_mat;
+  std::vector<float> h_mats;
+  std::vector<uint32_t> h_static_emit;  // static emitter triangle indices
+  std::vector<double> h_static_emit_area;
+  float scene_lo[3]{}, scene_hi[3]{};
+  // frame state
+  uint32_t stage = 0;  // 0 none, 1 spawned, 2 traced, 3 updated
+  gi::FrameArgs fa{};
+  uint32_t* d_mask = nullptr;   // all MIP levels
+  float4* d_ppos = nullptr;
+  float4* d_pnrm = nullptr;
+  uint4* d_rec = nullptr;       // [P*R] slot, t bits, tri, flags
+  uint2* d_rkey = nullptr;      // [P*R] descriptor of the hit (export / learned training)
+  float4* d_atlas = nullptr;    // [P*64]
+  float* d_sh = nullptr;        // [P*28]
+  gi::Table tab;
+  unsigned long long* d_stats = nullptr;  // [GI_STAT_COUNT]
+  float* d_moments = nullptr;   // [64*10]
+  // learned
+  gi::LearnedState* learned = nullptr;
+  // pinned staging ring for per-frame host-to-device uploads (slot reuse waits on its event)
+  static constexpr int kStageSlots = 8;
+  char* stage_base = nullptr;
+  size_t stage_slot_bytes = 0;
+  hipEvent_t stage_ev[kStageSlots]{};
+  bool stage_used[kStageSlots]{};
+  int stage_next = 0;
+  std::vector<uint32_t> h_etri, h_ethr;   // current emitter table (host mirror)
+  std::vector<float> h_evert;
+  // profiling
+  bool prof = false;
+  std::vector<gi::KernelTimer> timers;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<std::string> prof_names;
+  std::vector<uint32_t> prof_counts;
+  std::vector<double> prof_ms;
+};
+
+namespace gi {
+
+// launch helpers (gi_kernels.hip)
+void timer_begin(gi_context* c, const char* name, hipStream_t s, hipEvent_t* a);
+void timer_end(gi_context* c, const char* name, hipStream_t s, hipEvent_t a);
+
+hipError_t launch_gbuffer(gi_context* c, const gi_frame* f, float4* pos, float4* nrm, float4* alb,
+                          uint32_t* prim, hipStream_t s);
+hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, hipStream_t s);
+hipError_t launch_trace(gi_context* c, hipStream_t s);
+hipError_t launch_update(gi_context* c, hipStream_t s);
+hipError_t launch_interpolate(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim,
+                              float4* out, hipStream_t s);
+hipError_t launch_query(gi_context* c, const float4* pos, const float4* nrm, uint32_t n, float4* out,
+                        hipStream_t s);
+hipError_t launch_trace_rays(gi_context* c, const float4* o, const float4* d, uint32_t n, uint32_t any,
+                             uint32_t* tri, float* t, hipStream_t s);
+hipError_t launch_zero_stats(gi_context* c, hipStream_t s);
+hipError_t launch_count_traversal(gi_context* c, unsigned long long* out, hipStream_t s);
+
+// learned surrogate (gi_learned.hip)
+hipError_t learned_create(gi_context* c);
+void learned_destroy(gi_context* c);
+hipError_t learned_train(gi_context* c, hipStream_t s);
+hipError_t learned_infer_rays(gi_context* c, hipStream_t s);
+hipError_t learned_query(gi_context* c, const float4* pos, const float4* nrm, uint32_t n, float4* out,
+                         hipStream_t s);
+size_t learned_blob_size(gi_context* c);
+hipError_t learned_save(gi_context* c, void* blob);
+hipError_t learned_load(gi_context* c, const void* blob);
+void learned_stats(gi_context* c, float* out8);
+
+}  // namespace gi

@@ -1,0 +1,923 @@
+// gfx950 kernels of the per-frame GI pass (plain world cache) and their launchers.
+#include <hip/hip_runtime.h>
+
+#include "gi_device.hpp"
+#include "gi_host.hpp"
+
+namespace gi {
+
+constexpr int kTraceBlock = 64;   // one wave per block: the LDS stack is [STACK][64]
+
+struct ShadeTables {
+  const float4* tnrm;    // unit normal, w = material index bits
+  const float4* mats;    // [2m] albedo, [2m+1] emission
+  const uint32_t* etri;
+  const uint32_t* ethr;
+  const float4* evert;   // [3 * n_emit] emitter vertices in emitter order
+  uint32_t n_emit;
+  float area_total;
+};
+
+// ------------------------------------------------------------------------------------------
+// G-buffer: one primary ray through each pixel centre (test input)
+// ------------------------------------------------------------------------------------------
+template <int STACK>
+__global__ __launch_bounds__(kTraceBlock) void k_gbuffer(SceneView sv, ShadeTables st, gi_frame f, uint32_t W,
+                                                         uint32_t H, float4* pos, float4* nrm, float4* alb,
+                                                         uint32_t* prim) {
+  __shared__ uint32_t stk[STACK * kTraceBlock];
+  const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
+  if (i >= W * H) return;
+  const uint32_t x = i % W, y = i / W;
+  const float aspect = (float)W / (float)H;
+  const float sx = (2.0f * ((float)x + 0.5f)) / (float)W - 1.0f;
+  const float sy = 1.0f - (2.0f * ((float)y + 0.5f)) / (float)H;
+  const float a = (sx * f.tan_half) * aspect;
+  const float b = sy * f.tan_half;
+  float dx = (f.fwd[0] + a * f.right[0]) + b * f.up[0];
+  float dy = (f.fwd[1] + a * f.right[1]) + b * f.up[1];
+  float dz = (f.fwd[2] + a * f.right[2]) + b * f.up[2];
+  const float len = sqrtf((dx * dx + dy * dy) + dz * dz);
+  dx = dx / len; dy = dy / len; dz = dz / len;
+  const RayQ r = make_ray(f.pos[0], f.pos[1], f.pos[2], dx, dy, dz);
+  uint32_t tri;
+  float t;
+  closest_hit<STACK, kTraceBlock>(sv, r, 3.0e38f, stk, threadIdx.x, tri, t);
+  prim[i] = tri;
+  if (tri == kMiss) {
+    pos[i] = nrm[i] = alb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const float4 n = st.tnrm[tri];
+  const float dn = (n.x * dx + n.y * dy) + n.z * dz;
+  const float sg = dn > 0.0f ? -1.0f : 1.0f;
+  pos[i] = make_float4(f.pos[0] + t * dx, f.pos[1] + t * dy, f.pos[2] + t * dz, t);
+  nrm[i] = make_float4(sg * n.x, sg * n.y, sg * n.z, 0.0f);
+  const float4 al = st.mats[2 * __float_as_uint(n.w)];
+  alb[i] = make_float4(al.x, al.y, al.z, 0.0f);
+}
+
+// ------------------------------------------------------------------------------------------
+// Spawn (Section 2.1.1) and probe mask (Section 2.1.5): one thread per tile
+// ------------------------------------------------------------------------------------------
+__global__ void k_spawn(const float4* gpos, const float4* gnrm, const uint32_t* gprim, uint32_t W, uint32_t H,
+                        uint32_t TW, uint32_t TH, uint32_t jx, uint32_t jy, uint32_t* mask, float4* ppos,
+                        float4* pnrm, unsigned long long* stats) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) {
+    stats[GI_STAT_LIVE] = 0;
+    stats[GI_STAT_RELAXED] = 0;
+    stats[GI_STAT_NOPROBE] = 0;
+  }
+  if (p >= TW * TH) return;
+  const uint32_t tx = p % TW, ty = p / TW;
+  const uint32_t px = 8u * tx + jx, py = 8u * ty + jy;
+  uint32_t m = kSentinel;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+  if (px < W && py < H) {
+    const uint32_t pix = py * W + px;
+    if (gprim[pix] != kMiss) {
+      m = (py << 16) | px;
+      a = gpos[pix];
+      b = gnrm[pix];
+    }
+  }
+  mask[p] = m;
+  ppos[p] = a;
+  pnrm[p] = b;
+}
+
+// one MIP level of the mask: first valid probe of the 2x2 children in raster order
+__global__ void k_mask_mip(const uint32_t* src, uint32_t sw, uint32_t sh, uint32_t* dst, uint32_t dw, uint32_t dh) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= dw * dh) return;
+  const uint32_t x = i % dw, y = i / dw;
+  uint32_t v = kSentinel;
+#pragma unroll
+  for (uint32_t c = 0; c < 4; ++c) {
+    const uint32_t cx = 2 * x + (c & 1), cy = 2 * y + (c >> 1);
+    if (v == kSentinel && cx < sw && cy < sh) v = src[cy * sw + cx];
+  }
+  dst[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Probe rays (Section 2.1.3): cosine-distributed direction, closest hit, ray record
+// ------------------------------------------------------------------------------------------
+struct ProbeRayArgs {
+  const uint32_t* mask;
+  const float4* ppos;
+  const float4* pnrm;
+  uint32_t P, R, seed, frame;
+  float eps_scale, t_sky;
+};
+
+__device__ inline void probe_ray(const ProbeRayArgs& a, uint32_t gid, uint32_t p, float& ox, float& oy, float& oz,
+                                 float& dx, float& dy, float& dz, uint32_t& cell) {
+  const float4 pp = a.ppos[p], pn = a.pnrm[p];
+  const float u0 = rand_unit(rand_u32(a.seed, a.frame, gid, 0u));
+  const float u1 = rand_unit(rand_u32(a.seed, a.frame, gid, 1u));
+  cosine_direction(pn.x, pn.y, pn.z, u0, u1, dx, dy, dz, cell);
+  const float eps = origin_offset(a.eps_scale, pp.x, pp.y, pp.z);
+  ox = pp.x + pn.x * eps;
+  oy = pp.y + pn.y * eps;
+  oz = pp.z + pn.z * eps;
+}
+
+template <int STACK>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, ShadeTables st, ProbeRayArgs a,
+                                                              uint4* rec, unsigned long long* stats) {
+  __shared__ uint32_t stk[STACK * kTraceBlock];
+  const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
+  if (gid >= a.P * a.R) return;
+  const uint32_t p = gid / a.R;
+  const bool valid = a.mask[p] != kSentinel;
+  stat_add(stats, GI_STAT_RAYS, valid);
+  if (!valid) {
+    rec[gid] = make_uint4(0xFFFFFFFFu, 0u, kMiss, 0u);
+    return;
+  }
+  float ox, oy, oz, dx, dy, dz;
+  uint32_t cell;
+  probe_ray(a, gid, p, ox, oy, oz, dx, dy, dz, cell);
+  const RayQ r = make_ray(ox, oy, oz, dx, dy, dz);
+  uint32_t tri;
+  float t;
+  closest_hit<STACK, kTraceBlock>(sv, r, 3.0e38f, stk, threadIdx.x, tri, t);
+  uint32_t flags = cell | GI_RAY_TRACED;
+  if (tri == kMiss) {
+    rec[gid] = make_uint4(0xFFFFFFFFu, __float_as_uint(a.t_sky), kMiss, flags);
+    return;
+  }
+  const float4 n = st.tnrm[tri];
+  const float dn = (n.x * dx + n.y * dy) + n.z * dz;
+  flags |= GI_RAY_HIT;
+  if (dn < 0.0f) flags |= GI_RAY_FRONT;
+  rec[gid] = make_uint4(0xFFFFFFFFu, __float_as_uint(t), tri, flags);
+}
+
+// ------------------------------------------------------------------------------------------
+// Hit shading (Sections 2.2.1-2.2.4, 2.3.1): descriptor -> find-or-insert -> one light
+// sample with a shadow ray (+ cached bounce) -> fixed-point accumulation
+// ------------------------------------------------------------------------------------------
+struct CacheArgs {
+  uint32_t* fp;
+  uint64_t* key;
+  uint4* acc;
+  const float4* L;
+  uint32_t* accessed;
+  uint32_t bucket_mask;
+  float cell_scale;
+  uint32_t leak_bit;
+  uint32_t frac_bits;
+  float r_max;
+  uint32_t bounces;
+  float sky[3];
+};
+
+__device__ inline int32_t table_lookup(const CacheArgs& c, uint64_t key) {
+  const uint32_t b = bucket_of(key, c.bucket_mask), f = fingerprint_of(key);
+  const uint4* line = reinterpret_cast<const uint4*>(c.fp + b * kBucket);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint4 v = line[q];
+    if (v.x == f) return (int32_t)(b * kBucket + 4 * q);
+    if (v.y == f) return (int32_t)(b * kBucket + 4 * q + 1);
+    if (v.z == f) return (int32_t)(b * kBucket + 4 * q + 2);
+    if (v.w == f) return (int32_t)(b * kBucket + 4 * q + 3);
+  }
+  return -1;
+}
+
+// find-or-insert: the fingerprint is searched in the whole bucket first; otherwise empty
+// slots are claimed in ascending order with compare-and-swap (a CAS that finds our own
+// fingerprint means another lane inserted the same cell)
+__device__ inline int32_t table_insert(const CacheArgs& c, uint64_t key, bool& inserted) {
+  inserted = false;
+  const int32_t found = table_lookup(c, key);
+  if (found >= 0) return found;
+  const uint32_t b = bucket_of(key, c.bucket_mask), f = fingerprint_of(key);
+  for (uint32_t s = 0; s < kBucket; ++s) {
+    uint32_t* slot = c.fp + b * kBucket + s;
+    uint32_t cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == f) return (int32_t)(b * kBucket + s);
+    if (cur != 0u) continue;
+    const uint32_t prev = atomicCAS(slot, 0u, f);
+    if (prev == 0u) {
+      c.key[b * kBucket + s] = key;
+      inserted = true;
+      return (int32_t)(b * kBucket + s);
+    }
+    if (prev == f) return (int32_t)(b * kBucket + s);
+  }
+  return -1;
+}
+
+// One light sample (the single-candidate form of the light sampling of Section 2.3.1): an
+// emitter triangle picked in proportion to its area, a uniform point on it, and the shadow
+// ray towards it.  g = cos_y cos_l A_E / d^2 is the estimator's geometry factor.
+struct LightSample {
+  bool cast;
+  RayQ ray;
+  float tmax;
+  float g;
+  uint32_t mat;
+};
+
+__device__ inline LightSample sample_light(const ShadeTables& st, uint32_t seed, uint32_t frame, uint32_t gid, float px,
+                                           float py, float pz, float nx, float ny, float nz) {
+  LightSample ls;
+  ls.cast = false;
+  ls.tmax = 0.0f;
+  ls.g = 0.0f;
+  ls.mat = 0;
+  if (st.n_emit == 0) return ls;
+  const uint32_t rsel = rand_u32(seed, frame, gid, 2u);
+  uint32_t lo = 0, hi = st.n_emit - 1u;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (rsel < st.ethr[mid]) hi = mid;
+    else lo = mid + 1u;
+  }
+  const uint32_t e = st.etri[lo];
+  const float u3 = rand_unit(rand_u32(seed, frame, gid, 3u));
+  const float u4 = rand_unit(rand_u32(seed, frame, gid, 4u));
+  const float su = sqrtf(u3);
+  const float b0 = 1.0f - su, b1 = su * (1.0f - u4), b2 = su * u4;
+  const float4 A = st.evert[3 * lo], B = st.evert[3 * lo + 1], C = st.evert[3 * lo + 2];
+  const float xlx = (b0 * A.x + b1 * B.x) + b2 * C.x;
+  const float xly = (b0 * A.y + b1 * B.y) + b2 * C.y;
+  const float xlz = (b0 * A.z + b1 * B.z) + b2 * C.z;
+  const float wx = xlx - px, wy = xly - py, wz = xlz - pz;
+  const float d2 = (wx * wx + wy * wy) + wz * wz;
+  if (!(d2 > 0.0f)) return ls;
+  const float dist = sqrtf(d2);
+  const float omx = wx / dist, omy = wy / dist, omz = wz / dist;
+  const float4 ne = st.tnrm[e];
+  const float cos_y = (nx * omx + ny * omy) + nz * omz;
+  const float cos_l = -((ne.x * omx + ne.y * omy) + ne.z * omz);
+  if (!(cos_y > 0.0f && cos_l > 0.0f)) return ls;
+  ls.cast = true;
+  ls.ray = make_ray(px, py, pz, omx, omy, omz);
+  ls.tmax = dist * 0.9999f;
+  ls.g = ((cos_y * cos_l) * st.area_total) / d2;
+  ls.mat = __float_as_uint(ne.w);
+  return ls;
+}
+
+template <int STACK>
+__global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeTables st, ProbeRayArgs a,
+                                                            CacheArgs c, uint4* rec, uint2* rkey,
+                                                            unsigned long long* stats) {
+  __shared__ uint32_t stk[STACK * kTraceBlock];
+  const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
+  if (gid >= a.P * a.R) return;
+  uint4 rr = rec[gid];
+  const bool hit = (rr.w & GI_RAY_HIT) != 0u;
+  stat_add(stats, GI_STAT_HITS, hit);
+  if (!hit) {
+    rkey[gid] = make_uint2(0u, 0u);
+    return;
+  }
+  const uint32_t p = gid / a.R;
+  float ox, oy, oz, dx, dy, dz;
+  uint32_t cell;
+  probe_ray(a, gid, p, ox, oy, oz, dx, dy, dz, cell);
+  const float t = __uint_as_float(rr.y);
+  const uint32_t tri = rr.z;
+  const float4 n = st.tnrm[tri];
+  const float dn = (n.x * dx + n.y * dy) + n.z * dz;
+  const float sg = dn > 0.0f ? -1.0f : 1.0f;
+  const float yx = ox + t * dx, yy = oy + t * dy, yz = oz + t * dz;
+  const float nx = sg * n.x, ny = sg * n.y, nz = sg * n.z;
+  const uint64_t key = descriptor(c.cell_scale, c.leak_bit, yx, yy, yz, nx, ny, nz, t, true);
+  rkey[gid] = make_uint2((uint32_t)key, (uint32_t)(key >> 32));
+  bool inserted;
+  const int32_t slot = table_insert(c, key, inserted);
+  stat_add(stats, GI_STAT_INSERTS, inserted);
+  stat_add(stats, GI_STAT_OVERFLOW, slot < 0);
+  if (slot >= 0) c.accessed[slot] = 1u;
+
+  // one light sample: area-proportional emitter, uniform point, one shadow ray
+  const float eps = origin_offset(a.eps_scale, yx, yy, yz);
+  const float px = yx + nx * eps, py = yy + ny * eps, pz = yz + nz * eps;
+  float E0 = 0.f, E1 = 0.f, E2 = 0.f;
+  const LightSample ls = sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
+  const bool cast = ls.cast;
+  bool occl = false;
+  if (cast) {
+    occl = any_hit<STACK, kTraceBlock>(sv, ls.ray, ls.tmax, stk, threadIdx.x);
+    if (!occl) {
+      const float4 le = st.mats[2 * ls.mat + 1];
+      E0 = le.x * ls.g;
+      E1 = le.y * ls.g;
+      E2 = le.z * ls.g;
+    }
+  }
+  stat_add(stats, GI_STAT_SHADOW, cast);
+  stat_add(stats, GI_STAT_OCCLUDED, occl);
+  // cached bounce (temporal radiance feedback, Section 2.2.4)
+  float Lb0 = 0.f, Lb1 = 0.f, Lb2 = 0.f;
+  if (c.bounces >= 2) {
+    stat_add(stats, GI_STAT_BOUNCE, true);
+    const float u5 = rand_unit(rand_u32(a.seed, a.frame, gid, 5u));
+    const float u6 = rand_unit(rand_u32(a.seed, a.frame, gid, 6u));
+    float bx, by, bz;
+    uint32_t bcell;
+    cosine_direction(nx, ny, nz, u5, u6, bx, by, bz, bcell);
+    const RayQ br = make_ray(px, py, pz, bx, by, bz);
+    uint32_t btri;
+    float bt;
+    closest_hit<STACK, kTraceBlock>(sv, br, 3.0e38f, stk, threadIdx.x, btri, bt);
+    if (btri == kMiss) {
+      Lb0 = c.sky[0]; Lb1 = c.sky[1]; Lb2 = c.sky[2];
+    } else {
+      const float4 bn = st.tnrm[btri];
+      const float bdn = (bn.x * bx + bn.y * by) + bn.z * bz;
+      const float bs = bdn > 0.0f ? -1.0f : 1.0f;
+      const uint64_t bkey = descriptor(c.cell_scale, c.leak_bit, px + bt * bx, py + bt * by, pz + bt * bz,
+                                       bs * bn.x, bs * bn.y, bs * bn.z, bt, true);
+      const int32_t bslot = table_lookup(c, bkey);
+      if (bslot >= 0) {
+        c.accessed[bslot] = 1u;
+        const float4 lv = c.L[bslot];
+        Lb0 = lv.x; Lb1 = lv.y; Lb2 = lv.z;
+      }
+    }
+  }
+  rec[gid].x = (uint32_t)slot;
+  if (slot < 0) return;
+  const float4 alb = st.mats[2 * __float_as_uint(n.w)];
+  const float s0 = alb.x * (E0 * 0.31830988618379067f + Lb0);
+  const float s1 = alb.y * (E1 * 0.31830988618379067f + Lb1);
+  const float s2 = alb.z * (E2 * 0.31830988618379067f + Lb2);
+  const bool finite = isfinite(s0) && isfinite(s1) && isfinite(s2);
+  stat_add(stats, GI_STAT_NONFINITE, !finite);
+  if (!finite) return;
+  const float scale = (float)(1u << c.frac_bits);
+  const uint32_t q0 = (uint32_t)rintf(fminf(fmaxf(s0, 0.0f), c.r_max) * scale);
+  const uint32_t q1 = (uint32_t)rintf(fminf(fmaxf(s1, 0.0f), c.r_max) * scale);
+  const uint32_t q2 = (uint32_t)rintf(fminf(fmaxf(s2, 0.0f), c.r_max) * scale);
+  uint32_t* accp = reinterpret_cast<uint32_t*>(c.acc + slot);
+  uint32_t wraps = 0;
+  const uint32_t o0 = atomicAdd(accp + 0, q0);
+  const uint32_t o1 = atomicAdd(accp + 1, q1);
+  const uint32_t o2 = atomicAdd(accp + 2, q2);
+  atomicAdd(accp + 3, 1u);
+  wraps += (o0 + q0 < o0) + (o1 + q1 < o1) + (o2 + q2 < o2);
+  if (wraps) atomicAdd(&stats[GI_STAT_WRAPS], (unsigned long long)wraps);
+}
+
+// ------------------------------------------------------------------------------------------
+// Cache update (Section 2.2.1 decay, Section 2.2.3 moving average): one thread per slot
+// ------------------------------------------------------------------------------------------
+__global__ void k_cache_update(uint32_t N, uint32_t* fp, uint64_t* key, uint4* acc, float4* L, uint2* meta,
+                               uint32_t* accessed, uint32_t n_cap, uint32_t max_life, uint32_t frac_bits,
+                               unsigned long long* stats) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  bool live = false, evicted = false;
+  if (s < N && fp[s] != 0u) {
+    const uint4 a = acc[s];
+    float4 l = L[s];
+    uint2 m = meta[s];
+    if (a.w > 0u) {
+      const uint32_t h = m.x < n_cap ? m.x : n_cap;
+      const float w = (float)a.w / (float)((double)h + (double)a.w);
+      const double den = (double)a.w * (double)(1u << frac_bits);
+      const float m0 = (float)((double)a.x / den);
+      const float m1 = (float)((double)a.y / den);
+      const float m2 = (float)((double)a.z / den);
+      l.x = l.x + w * (m0 - l.x);
+      l.y = l.y + w * (m1 - l.y);
+      l.z = l.z + w * (m2 - l.z);
+      const uint64_t nh = (uint64_t)m.x + a.w;
+      m.x = nh < n_cap ? (uint32_t)nh : n_cap;
+    }
+    m.y = accessed[s] ? max_life : m.y - 1u;
+    if (m.y == 0u) {
+      fp[s] = 0u;
+      key[s] = 0u;
+      m.x = 0u;
+      l = make_float4(0.f, 0.f, 0.f, 0.f);
+      evicted = true;
+    } else {
+      live = true;
+    }
+    L[s] = l;
+    meta[s] = m;
+    acc[s] = make_uint4(0u, 0u, 0u, 0u);
+    accessed[s] = 0u;
+  }
+  stat_add(stats, GI_STAT_LIVE, live);
+  stat_add(stats, GI_STAT_EVICT, evicted);
+}
+
+// ------------------------------------------------------------------------------------------
+// Probe gather + radiance backup (Section 2.1.4) + SH projection (Section 2.4.2):
+// one wave per probe, lane = atlas cell
+// ------------------------------------------------------------------------------------------
+constexpr int kGatherMaxR = 256;
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const float4* pnrm, const uint4* rec,
+                                                  const float4* L, const float4* tnrm, const float4* mats,
+                                                  const float* moments, uint32_t R, float s0, float s1, float s2,
+                                                  float4* atlas, float* sh) {
+  __shared__ float rv[kGatherMaxR][4];
+  __shared__ uint32_t rc[kGatherMaxR];
+  __shared__ float cv[64][4];
+  __shared__ uint32_t cc[64];
+  const uint32_t p = blockIdx.x;
+  const uint32_t lane = threadIdx.x;
+  if (mask[p] == kSentinel) {
+    atlas[(size_t)p * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane < 28) sh[(size_t)p * 28 + lane] = 0.0f;
+    return;
+  }
+  for (uint32_t j = lane; j < R; j += 64) {
+    const uint4 r = rec[(size_t)p * R + j];
+    float v0, v1, v2;
+    if (!(r.w & GI_RAY_HIT)) {
+      v0 = s0; v1 = s1; v2 = s2;
+    } else {
+      float le0 = 0.f, le1 = 0.f, le2 = 0.f;
+      if (r.w & GI_RAY_FRONT) {
+        const float4 e = mats[2 * __float_as_uint(tnrm[r.z].w) + 1];
+        le0 = e.x; le1 = e.y; le2 = e.z;
+      }
+      float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+      if ((int32_t)r.x >= 0) {
+        const float4 lv = L[r.x];
+        l0 = lv.x; l1 = lv.y; l2 = lv.z;
+      }
+      v0 = le0 + l0; v1 = le1 + l1; v2 = le2 + l2;
+    }
+    rv[j][0] = v0; rv[j][1] = v1; rv[j][2] = v2;
+    rv[j][3] = __uint_as_float(r.y);
+    rc[j] = r.w & 63u;
+  }
+  __syncthreads();
+  // per-cell sums in ray order (the same float32 order as a sequential loop)
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  uint32_t cnt = 0;
+  for (uint32_t j = 0; j < R; ++j) {
+    if (rc[j] == lane) {
+      a0 = a0 + rv[j][0]; a1 = a1 + rv[j][1]; a2 = a2 + rv[j][2]; a3 = a3 + rv[j][3];
+      ++cnt;
+    }
+  }
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+  if (cnt) {
+    const float fc = (float)cnt;
+    c0 = a0 / fc; c1 = a1 / fc; c2 = a2 / fc; c3 = a3 / fc;
+  }
+  cv[lane][0] = c0; cv[lane][1] = c1; cv[lane][2] = c2; cv[lane][3] = c3;
+  cc[lane] = cnt;
+  __syncthreads();
+  if (!cnt) {
+    // radiance backup: mean of the populated cells, summed in ascending cell order
+    float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+    uint32_t np = 0;
+    for (int i = 0; i < 64; ++i) {
+      if (cc[i]) {
+        m0 = m0 + cv[i][0]; m1 = m1 + cv[i][1]; m2 = m2 + cv[i][2]; m3 = m3 + cv[i][3];
+        ++np;
+      }
+    }
+    if (np) {
+      const float fn = (float)np;
+      c0 = m0 / fn; c1 = m1 / fn; c2 = m2 / fn; c3 = m3 / fn;
+    }
+  }
+  atlas[(size_t)p * 64 + lane] = make_float4(c0, c1, c2, c3);
+  // SH: exact integrals of the 9 real basis functions over this cell, from its direction
+  // moments rotated into the probe frame (columns t, b, n)
+  const float4 nn = pnrm[p];
+  const Basis B = make_basis(nn.x, nn.y, nn.z);
+  const float R00 = B.tx, R10 = B.ty, R20 = B.tz;
+  const float R01 = B.bx, R11 = B.by, R21 = B.bz;
+  const float R02 = nn.x, R12 = nn.y, R22 = nn.z;
+  const float* mo = moments + lane * 10;
+  const float om = mo[0];
+  const float mlx = mo[1], mly = mo[2], mlz = mo[3];
+  const float Mxx = mo[4], Myy = mo[5], Mzz = mo[6], Mxy = mo[7], Mxz = mo[8], Myz = mo[9];
+  const float mwx = R00 * mlx + R01 * mly + R02 * mlz;
+  const float mwy = R10 * mlx + R11 * mly + R12 * mlz;
+  const float mwz = R20 * mlx + R21 * mly + R22 * mlz;
+  // T = R M (rows i), W = T R^T
+  const float T00 = R00 * Mxx + R01 * Mxy + R02 * Mxz, T01 = R00 * Mxy + R01 * Myy + R02 * Myz,
+              T02 = R00 * Mxz + R01 * Myz + R02 * Mzz;
+  const float T10 = R10 * Mxx + R11 * Mxy + R12 * Mxz, T11 = R10 * Mxy + R11 * Myy + R12 * Myz,
+              T12 = R10 * Mxz + R11 * Myz + R12 * Mzz;
+  const float T20 = R20 * Mxx + R21 * Mxy + R22 * Mxz, T21 = R20 * Mxy + R21 * Myy + R22 * Myz,
+              T22 = R20 * Mxz + R21 * Myz + R22 * Mzz;
+  const float Wxx = T00 * R00 + T01 * R01 + T02 * R02;
+  const float Wyy = T10 * R10 + T11 * R11 + T12 * R12;
+  const float Wzz = T20 * R20 + T21 * R21 + T22 * R22;
+  const float Wxy = T00 * R10 + T01 * R11 + T02 * R12;
+  const float Wxz = T00 * R20 + T01 * R21 + T02 * R22;
+  const float Wyz = T10 * R20 + T11 * R21 + T12 * R22;
+  const float k0 = 0.28209479177387814f, k1 = 0.48860251190291992f, k2 = 1.09254843059207907f,
+              k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
+  const float I[9] = {k0 * om, k1 * mwy, k1 * mwz, k1 * mwx, k2 * Wxy, k2 * Wyz, k20 * (3.0f * Wzz - om),
+                      k2 * Wxz, k22 * (Wxx - Wyy)};
+  float out = 0.0f;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const float r0 = wave_sum(c0 * I[l]);
+    const float r1 = wave_sum(c1 * I[l]);
+    const float r2 = wave_sum(c2 * I[l]);
+    if (lane == (uint32_t)(3 * l)) out = r0;
+    if (lane == (uint32_t)(3 * l + 1)) out = r1;
+    if (lane == (uint32_t)(3 * l + 2)) out = r2;
+  }
+  if (lane < 28) sh[(size_t)p * 28 + lane] = lane < 27 ? out : 0.0f;
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-pixel interpolation (Section 2.4.1, Algorithms 4 and 6)
+// ------------------------------------------------------------------------------------------
+struct MipInfo {
+  uint32_t n;
+  uint32_t w[16], h[16], off[16];
+};
+
+__device__ inline uint32_t find_closest_probe(const uint32_t* mask, const MipInfo& mi, int32_t px, int32_t py,
+                                              int32_t ox, int32_t oy) {
+  int32_t x = px >> 3, y = py >> 3;
+  for (uint32_t m = 0; m < mi.n; ++m) {
+    const int32_t qx = x + ox, qy = y + oy;
+    if (qx < 0 || qy < 0 || qx >= (int32_t)mi.w[m] || qy >= (int32_t)mi.h[m]) break;
+    const uint32_t v = mask[mi.off[m] + (uint32_t)qy * mi.w[m] + (uint32_t)qx];
+    if (v != kSentinel) return v;
+    x >>= 1;
+    y >>= 1;
+  }
+  return kSentinel;
+}
+
+__device__ inline void sh_irradiance(const float* c, float nx, float ny, float nz, float& e0, float& e1, float& e2) {
+  const float k0 = 0.28209479177387814f, k1 = 0.48860251190291992f, k2 = 1.09254843059207907f,
+              k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
+  const float Y[9] = {k0, k1 * ny, k1 * nz, k1 * nx, k2 * (nx * ny), k2 * (ny * nz),
+                      k20 * (3.0f * (nz * nz) - 1.0f), k2 * (nx * nz), k22 * (nx * nx - ny * ny)};
+  const float A[9] = {3.14159265358979324f, 2.09439510239319549f, 2.09439510239319549f, 2.09439510239319549f,
+                      0.78539816339744831f, 0.78539816339744831f, 0.78539816339744831f, 0.78539816339744831f,
+                      0.78539816339744831f};
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    s0 = s0 + (A[l] * c[3 * l]) * Y[l];
+    s1 = s1 + (A[l] * c[3 * l + 1]) * Y[l];
+    s2 = s2 + (A[l] * c[3 * l + 2]) * Y[l];
+  }
+  e0 = s0; e1 = s1; e2 = s2;
+}
+
+__global__ void k_interpolate(const float4* gpos, const float4* gnrm, const uint32_t* gprim, uint32_t W, uint32_t H,
+                              uint32_t TW, const uint32_t* mask, MipInfo mi, const float4* ppos, const float4* pnrm,
+                              const float* sh, float cx, float cy, float cz, float kappa, int32_t jx, int32_t jy,
+                              float4* out, unsigned long long* stats) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool relaxed = false, none = false;
+  if (i < W * H) {
+    if (gprim[i] == kMiss) {
+      out[i] = make_float4(0.f, 0.f, 0.f, GI_INTERP_SKY);
+    } else {
+      const int32_t x = (int32_t)(i % W), y = (int32_t)(i / W);
+      const float4 pp = gpos[i], pn = gnrm[i];
+      const float dx = pp.x - cx, dy = pp.y - cy, dz = pp.z - cz;
+      const float cell_size = kappa * sqrtf((dx * dx + dy * dy) + dz * dz);
+      const int32_t ux = x - jx, uy = y - jy;
+      const int32_t bx = ux >> 3, by = uy >> 3;
+      const float fx = (float)(ux - 8 * bx) * 0.125f, fy = (float)(uy - 8 * by) * 0.125f;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, ws = 0.f;
+      float e[4][3];
+      int nf = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t ox = k & 1, oy = k >> 1;
+        const uint32_t m = find_closest_probe(mask, mi, 8 * bx, 8 * by, ox, oy);
+        if (m == kSentinel) continue;
+        const uint32_t q = ((m >> 16) >> 3) * TW + ((m & 0xFFFFu) >> 3);
+        const float4 qp = ppos[q], qn = pnrm[q];
+        const float wb = (ox ? fx : 1.0f - fx) * (oy ? fy : 1.0f - fy);
+        const float pd = fabsf(((qp.x - pp.x) * pn.x + (qp.y - pp.y) * pn.y) + (qp.z - pp.z) * pn.z);
+        const float nd = (pn.x * qn.x + pn.y * qn.y) + pn.z * qn.z;
+        const float w = (pd <= cell_size) ? wb * fmaxf(0.0f, nd) : 0.0f;
+        float c[27];
+        const float4* s4 = reinterpret_cast<const float4*>(sh + (size_t)q * 28);
+#pragma unroll
+        for (int v = 0; v < 7; ++v) {
+          const float4 t = s4[v];
+          if (4 * v < 27) c[4 * v] = t.x;
+          if (4 * v + 1 < 27) c[4 * v + 1] = t.y;
+          if (4 * v + 2 < 27) c[4 * v + 2] = t.z;
+          if (4 * v + 3 < 27) c[4 * v + 3] = t.w;
+        }
+        float E0, E1, E2;
+        sh_irradiance(c, pn.x, pn.y, pn.z, E0, E1, E2);
+        e[nf][0] = E0; e[nf][1] = E1; e[nf][2] = E2;
+        a0 = a0 + w * E0; a1 = a1 + w * E1; a2 = a2 + w * E2;
+        ws = ws + w;
+        ++nf;
+      }
+      if (ws > 0.0f) {
+        out[i] = make_float4(a0 / ws, a1 / ws, a2 / ws, GI_INTERP_OK);
+      } else if (nf > 0) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int k = 0; k < nf; ++k) { s0 = s0 + e[k][0]; s1 = s1 + e[k][1]; s2 = s2 + e[k][2]; }
+        const float fn = (float)nf;
+        out[i] = make_float4(s0 / fn, s1 / fn, s2 / fn, GI_INTERP_RELAXED);
+        relaxed = true;
+      } else {
+        out[i] = make_float4(0.f, 0.f, 0.f, GI_INTERP_NO_PROBE);
+        none = true;
+      }
+    }
+  }
+  stat_add(stats, GI_STAT_RELAXED, relaxed);
+  stat_add(stats, GI_STAT_NOPROBE, none);
+}
+
+// ------------------------------------------------------------------------------------------
+// Lookup-only query for caller points
+// ------------------------------------------------------------------------------------------
+__global__ void k_query(const float4* pos, const float4* nrm, uint32_t n, CacheArgs c, float4* out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 p = pos[i], q = nrm[i];
+  const bool wl = p.w >= 0.0f;
+  const uint64_t key = descriptor(c.cell_scale, c.leak_bit, p.x, p.y, p.z, q.x, q.y, q.z, wl ? p.w : 0.0f, wl);
+  const int32_t s = table_lookup(c, key);
+  if (s < 0) {
+    out[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    const float4 l = c.L[s];
+    out[i] = make_float4(l.x, l.y, l.z, 1.0f);
+  }
+}
+
+// traversal only
+template <int STACK>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_rays(SceneView sv, const float4* o, const float4* d, uint32_t n,
+                                                            uint32_t any, uint32_t* tri, float* t) {
+  __shared__ uint32_t stk[STACK * kTraceBlock];
+  const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
+  if (i >= n) return;
+  const float4 a = o[i], b = d[i];
+  const RayQ r = make_ray(a.x, a.y, a.z, b.x, b.y, b.z);
+  if (any) {
+    tri[i] = any_hit<STACK, kTraceBlock>(sv, r, a.w, stk, threadIdx.x) ? 1u : 0u;
+    t[i] = 0.0f;
+  } else {
+    uint32_t h;
+    float tt;
+    closest_hit<STACK, kTraceBlock>(sv, r, a.w, stk, threadIdx.x, h, tt);
+    tri[i] = h;
+    t[i] = tt;
+  }
+}
+
+// instrumented copy of the probe-ray and shadow-ray walks: nodes visited and triangles
+// tested (the algorithmic traffic of the traversal), no other side effect
+template <int STACK>
+__global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, ShadeTables st, ProbeRayArgs a,
+                                                                 CacheArgs c, const uint4* rec,
+                                                                 unsigned long long* out) {
+  __shared__ uint32_t stk[STACK * kTraceBlock];
+  const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
+  uint32_t pn = 0, pt = 0, sn = 0, st_ = 0;
+  bool probe = false, shadow = false;
+  if (gid < a.P * a.R) {
+    const uint32_t p = gid / a.R;
+    if (a.mask[p] != kSentinel) {
+      probe = true;
+      float ox, oy, oz, dx, dy, dz;
+      uint32_t cell;
+      probe_ray(a, gid, p, ox, oy, oz, dx, dy, dz, cell);
+      const RayQ r = make_ray(ox, oy, oz, dx, dy, dz);
+      uint32_t tri;
+      float t;
+      closest_hit<STACK, kTraceBlock, true>(sv, r, 3.0e38f, stk, threadIdx.x, tri, t, &pn, &pt);
+      const uint4 rr = rec[gid];
+      if (rr.w & GI_RAY_HIT) {
+        const float4 n = st.tnrm[tri];
+        const float dn = (n.x * dx + n.y * dy) + n.z * dz;
+        const float sg = dn > 0.0f ? -1.0f : 1.0f;
+        const float yx = ox + t * dx, yy = oy + t * dy, yz = oz + t * dz;
+        const float nx = sg * n.x, ny = sg * n.y, nz = sg * n.z;
+        const float eps = origin_offset(a.eps_scale, yx, yy, yz);
+        const LightSample ls = sample_light(st, a.seed, a.frame, gid, yx + nx * eps, yy + ny * eps, yz + nz * eps,
+                                            nx, ny, nz);
+        if (ls.cast) {
+          shadow = true;
+          (void)any_hit<STACK, kTraceBlock, true>(sv, ls.ray, ls.tmax, stk, threadIdx.x, &sn, &st_);
+        }
+      }
+    }
+  }
+  if (probe) {
+    atomicAdd(&out[0], 1ull);
+    atomicAdd(&out[1], (unsigned long long)pn);
+    atomicAdd(&out[2], (unsigned long long)pt);
+  }
+  if (shadow) {
+    atomicAdd(&out[3], 1ull);
+    atomicAdd(&out[4], (unsigned long long)sn);
+    atomicAdd(&out[5], (unsigned long long)st_);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static SceneView scene_view(const gi_context* c) {
+  SceneView v;
+  v.nodes = c->d_nodes;
+  v.tris = c->d_tris;
+  v.dyn = c->d_dyn;
+  v.n_dyn = c->n_dyn;
+  v.has_bvh = c->nt > 0 ? 1u : 0u;
+  return v;
+}
+
+static ShadeTables shade_tables(const gi_context* c) {
+  ShadeTables t;
+  t.tnrm = c->d_tnrm;
+  t.mats = c->d_mats;
+  t.etri = c->d_etri;
+  t.ethr = c->d_ethr;
+  t.evert = c->d_evert;
+  t.n_emit = c->n_emit;
+  t.area_total = c->area_total;
+  return t;
+}
+
+static ProbeRayArgs probe_args(const gi_context* c) {
+  ProbeRayArgs a;
+  a.mask = c->d_mask;
+  a.ppos = c->d_ppos;
+  a.pnrm = c->d_pnrm;
+  a.P = c->P;
+  a.R = c->R;
+  a.seed = c->cfg.seed;
+  a.frame = c->fa.index;
+  a.eps_scale = c->cfg.eps_scale;
+  a.t_sky = c->cfg.t_sky;
+  return a;
+}
+
+static CacheArgs cache_args(const gi_context* c) {
+  CacheArgs a;
+  a.fp = c->tab.fp;
+  a.key = c->tab.key;
+  a.acc = c->tab.acc;
+  a.L = c->tab.L;
+  a.accessed = c->tab.accessed;
+  a.bucket_mask = c->N / kBucket - 1u;
+  a.cell_scale = c->cfg.cell_scale;
+  a.leak_bit = c->cfg.leak_bit;
+  a.frac_bits = c->cfg.frac_bits;
+  a.r_max = c->cfg.r_max;
+  a.bounces = c->cfg.bounces;
+  a.sky[0] = c->cfg.sky[0];
+  a.sky[1] = c->cfg.sky[1];
+  a.sky[2] = c->cfg.sky[2];
+  return a;
+}
+
+void timer_begin(gi_context* c, const char* name, hipStream_t s, hipEvent_t* a) {
+  (void)name;
+  *a = nullptr;
+  if (!c->prof) return;
+  if (c->event_pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    c->event_pool.push_back(e);
+  }
+  *a = c->event_pool.back();
+  c->event_pool.pop_back();
+  (void)hipEventRecord(*a, s);
+}
+
+void timer_end(gi_context* c, const char* name, hipStream_t s, hipEvent_t a) {
+  if (!c->prof || !a) return;
+  hipEvent_t b;
+  if (c->event_pool.empty()) {
+    if (hipEventCreate(&b) != hipSuccess) return;
+  } else {
+    b = c->event_pool.back();
+    c->event_pool.pop_back();
+  }
+  (void)hipEventRecord(b, s);
+  c->timers.push_back(KernelTimer{name, a, b});
+}
+
+#define GI_TIMED(ctx, name, stream, launch_stmt) \
+  do {                                            \
+    hipEvent_t ev_;                               \
+    timer_begin(ctx, name, stream, &ev_);         \
+    launch_stmt;                                  \
+    timer_end(ctx, name, stream, ev_);            \
+  } while (0)
+
+static inline uint32_t blocks(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
+
+hipError_t launch_gbuffer(gi_context* c, const gi_frame* f, float4* pos, float4* nrm, float4* alb, uint32_t* prim,
+                          hipStream_t s) {
+  const uint32_t n = c->W * c->H;
+  if (c->stack_depth <= 32)
+    GI_TIMED(c, "gbuffer", s, (k_gbuffer<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), *f, c->W, c->H, pos, nrm, alb, prim)));
+  else
+    GI_TIMED(c, "gbuffer", s, (k_gbuffer<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), *f, c->W, c->H, pos, nrm, alb, prim)));
+  return hipGetLastError();
+}
+
+hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, hipStream_t s) {
+  GI_TIMED(c, "spawn", s, (k_spawn<<<blocks(c->P, 256), 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats)));
+  for (uint32_t k = 1; k < c->nmip; ++k) {
+    const uint32_t n = c->mip_w[k] * c->mip_h[k];
+    GI_TIMED(c, "mask_mip", s, (k_mask_mip<<<blocks(n, 256), 256, 0, s>>>(c->d_mask + c->mip_off[k - 1], c->mip_w[k - 1], c->mip_h[k - 1], c->d_mask + c->mip_off[k], c->mip_w[k], c->mip_h[k])));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(gi_context* c, hipStream_t s) {
+  const uint64_t n = (uint64_t)c->P * c->R;
+  const SceneView sv = scene_view(c);
+  const ShadeTables st = shade_tables(c);
+  const ProbeRayArgs a = probe_args(c);
+  const CacheArgs ca = cache_args(c);
+  if (c->stack_depth <= 32) {
+    GI_TIMED(c, "trace_probes", s, (k_trace_probes<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_stats)));
+    GI_TIMED(c, "shade_hits", s, (k_shade_hits<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, c->d_stats)));
+  } else {
+    GI_TIMED(c, "trace_probes", s, (k_trace_probes<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_stats)));
+    GI_TIMED(c, "shade_hits", s, (k_shade_hits<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, c->d_stats)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(gi_context* c, hipStream_t s) {
+  GI_TIMED(c, "cache_update", s, (k_cache_update<<<blocks(c->N, 256), 256, 0, s>>>(c->N, c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->d_stats)));
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], c->d_atlas, c->d_sh)));
+  return hipGetLastError();
+}
+
+hipError_t launch_interpolate(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, float4* out,
+                              hipStream_t s) {
+  MipInfo mi;
+  mi.n = c->nmip < 16 ? c->nmip : 16;
+  for (uint32_t k = 0; k < mi.n; ++k) {
+    mi.w[k] = c->mip_w[k];
+    mi.h[k] = c->mip_h[k];
+    mi.off[k] = c->mip_off[k];
+  }
+  const uint32_t n = c->W * c->H;
+  GI_TIMED(c, "interpolate", s, (k_interpolate<<<blocks(n, 256), 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->d_mask, mi, c->d_ppos, c->d_pnrm, c->d_sh, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, (int32_t)c->fa.jx, (int32_t)c->fa.jy, out, c->d_stats)));
+  return hipGetLastError();
+}
+
+hipError_t launch_query(gi_context* c, const float4* pos, const float4* nrm, uint32_t n, float4* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  GI_TIMED(c, "cache_query", s, (k_query<<<blocks(n, 256), 256, 0, s>>>(pos, nrm, n, cache_args(c), out)));
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(gi_context* c, const float4* o, const float4* d, uint32_t n, uint32_t any, uint32_t* tri,
+                             float* t, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (c->stack_depth <= 32)
+    GI_TIMED(c, "trace_rays", s, (k_trace_rays<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), o, d, n, any, tri, t)));
+  else
+    GI_TIMED(c, "trace_rays", s, (k_trace_rays<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), o, d, n, any, tri, t)));
+  return hipGetLastError();
+}
+
+hipError_t launch_count_traversal(gi_context* c, unsigned long long* out, hipStream_t s) {
+  const uint64_t n = (uint64_t)c->P * c->R;
+  k_zero_u64<<<1, 64, 0, s>>>(out, 8);
+  if (c->stack_depth <= 32)
+    k_count_traversal<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), probe_args(c), cache_args(c), c->d_rec, out);
+  else
+    k_count_traversal<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), probe_args(c), cache_args(c), c->d_rec, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_stats(gi_context* c, hipStream_t s) {
+  k_zero_u64<<<1, 64, 0, s>>>(c->d_stats, GI_STAT_COUNT);
+  return hipGetLastError();
+}
+
+}  // namespace gi

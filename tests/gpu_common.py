@@ -1,0 +1,56 @@
+"""Helpers shared by the GPU parity tests: run the HIP path and the CPU oracle on the same
+seeded inputs and compare them."""
+import numpy as np
+
+import oracle as O
+from paper_2310_19855_amd import gi
+from paper_2310_19855_amd import inputs as I
+
+REL_TOL = 1e-4   # float radiance tolerance, relative, evaluated in float64
+
+
+def rel_err(gpu, ref, floor_frac=1e-3):
+    """per-element |g - r| / max(|r|, floor) in float64; floor = floor_frac * max|r| so that
+    values near zero (SH coefficients that cancel) are judged against the array's scale"""
+    g = np.asarray(gpu, np.float64)
+    r = np.asarray(ref, np.float64)
+    floor = max(floor_frac * float(np.abs(r).max(initial=0.0)), 1e-30)
+    return np.abs(g - r) / np.maximum(np.abs(r), floor)
+
+
+def assert_close(gpu, ref, tol=REL_TOL, what=""):
+    e = rel_err(gpu, ref)
+    assert e.size == 0 or e.max() <= tol, f"{what}: max rel err {e.max():.3g} at {np.unravel_index(e.argmax(), e.shape)}"
+
+
+def bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+class Pair:
+    """HIP context and oracle state over one scene and config"""
+
+    def __init__(self, scene, cfg, f64_oracle=False):
+        import torch
+        self.scene = scene
+        self.cfg = dict(O.default_config(), **cfg)
+        self.ctx = gi.Context(**cfg)
+        self.ctx.build_bvh(scene)
+        self.osc = O.OracleScene(scene, f64=f64_oracle)
+        self.ost = O.OracleFrameState(self.osc, self.cfg)
+        self.W, self.H = self.cfg["width"], self.cfg["height"]
+        self.gb = gi.GBuffer(self.H, self.W)
+        self.out = torch.zeros((self.H, self.W, 4), dtype=torch.float32, device="cuda")
+
+    def set_frame_dynamic(self, idx):
+        if self.scene.dynamic is not None:
+            tv, m = self.scene.dynamic(idx)
+            self.ctx.set_dynamic(tv, m)
+            self.osc.set_dynamic(tv, m)
+
+    def gbuffer(self, fr):
+        import torch
+        self.ctx.render_gbuffer(fr, self.gb.pos, self.gb.nrm, self.gb.alb, self.gb.prim)
+        torch.cuda.synchronize()
+        return self.gb.host(), self.osc.gbuffer(fr, self.W, self.H)
