@@ -203,6 +203,8 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->tab.meta);
   dfree(c->tab.accessed);
   dfree(c->d_stats);
+  dfree(c->d_hit_ids);
+  dfree(c->d_hit_count);
   dfree(c->d_moments);
 }
 
@@ -303,7 +305,14 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
   A(dalloc(&c->tab.L, c->N));
   A(dalloc(&c->tab.meta, c->N));
   A(dalloc(&c->tab.accessed, c->N));
-  A(dalloc(&c->d_stats, GI_STAT_COUNT));
+  A(dalloc(&c->d_stats, (size_t)GI_STAT_COUNT * gi::kStatStripesHost));
+  {
+    const uint32_t nblk = (uint32_t)((PR + 63) / 64);
+    c->hit_blocks_per_stripe = (nblk + gi::kStatStripesHost - 1) / gi::kStatStripesHost;
+    c->hit_stripe_cap = c->hit_blocks_per_stripe * 64;
+    A(dalloc(&c->d_hit_ids, (size_t)c->hit_stripe_cap * gi::kStatStripesHost));
+    A(dalloc(&c->d_hit_count, gi::kStatStripesHost));
+  }
   A(dalloc(&c->d_moments, 640));
   if (e == hipSuccess) {
     A(hipMemset(c->tab.fp, 0, 4 * (size_t)c->N));
@@ -312,7 +321,8 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
     A(hipMemset(c->tab.L, 0, 16 * (size_t)c->N));
     A(hipMemset(c->tab.meta, 0, 8 * (size_t)c->N));
     A(hipMemset(c->tab.accessed, 0, 4 * (size_t)c->N));
-    A(hipMemset(c->d_stats, 0, 8 * GI_STAT_COUNT));
+    A(hipMemset(c->d_stats, 0, 8 * (size_t)GI_STAT_COUNT * gi::kStatStripesHost));
+    A(hipMemset(c->d_hit_count, 0, 4 * gi::kStatStripesHost));
     A(hipMemset(c->d_rec, 0, 16 * PR));
     A(hipMemset(c->d_rkey, 0, 8 * PR));
     A(hipMemset(c->d_atlas, 0, 16 * (size_t)c->P * 64));
@@ -755,7 +765,13 @@ gi_status gi_get_dims(gi_context* c, uint32_t* out) {
 gi_status gi_get_stats(gi_context* c, uint64_t* out) {
   if (!c || !out) return GI_ERR_INVALID_ARG;
   GI_TRY_HIP(c, hipDeviceSynchronize());
-  GI_TRY_HIP(c, hipMemcpy(out, c->d_stats, 8 * GI_STAT_COUNT, hipMemcpyDeviceToHost));
+  std::vector<uint64_t> st((size_t)GI_STAT_COUNT * gi::kStatStripesHost);
+  GI_TRY_HIP(c, hipMemcpy(st.data(), c->d_stats, 8 * st.size(), hipMemcpyDeviceToHost));
+  for (int k = 0; k < GI_STAT_COUNT; ++k) {
+    uint64_t v = 0;
+    for (uint32_t s = 0; s < gi::kStatStripesHost; ++s) v += st[(size_t)s * GI_STAT_COUNT + k];
+    out[k] = v;
+  }
   return GI_OK;
 }
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/gi.h"
 #include "gi_types.hpp"
 
 namespace gi {
@@ -250,23 +251,31 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
         float tn[4];
         uint32_t m = enter_children(r, n, best_t * 1.0001221f, tn);
         // order the entered children by entry distance: nearest first
-        uint32_t ids[4];
-        float ts[4];
-        int cnt = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (m & (1u << c)) {
-            // insertion into a short sorted list
-            int pos = cnt;
-            while (pos > 0 && ts[pos - 1] > tn[c]) { ts[pos] = ts[pos - 1]; ids[pos] = ids[pos - 1]; --pos; }
-            ts[pos] = tn[c];
-            ids[pos] = n.child[c];
-            ++cnt;
-          }
-        }
+        // order the entered children nearest first with a 5-exchange sorting network held in
+        // registers (children not entered sort last with t = +inf)
+        float t0 = (m & 1u) ? tn[0] : __builtin_inff(), t1 = (m & 2u) ? tn[1] : __builtin_inff();
+        float t2 = (m & 4u) ? tn[2] : __builtin_inff(), t3 = (m & 8u) ? tn[3] : __builtin_inff();
+        uint32_t c0 = n.child[0], c1 = n.child[1], c2 = n.child[2], c3 = n.child[3];
+        auto cswap = [](float& ta, uint32_t& ca, float& tb, uint32_t& cb) {
+          const bool sw = tb < ta;
+          const float tt = sw ? tb : ta;
+          tb = sw ? ta : tb;
+          ta = tt;
+          const uint32_t cc = sw ? cb : ca;
+          cb = sw ? ca : cb;
+          ca = cc;
+        };
+        cswap(t0, c0, t1, c1);
+        cswap(t2, c2, t3, c3);
+        cswap(t0, c0, t2, c2);
+        cswap(t1, c1, t3, c3);
+        cswap(t1, c1, t2, c2);
+        const int cnt = __builtin_popcount(m);
         if (cnt > 0) {
-          for (int i = cnt - 1; i >= 1; --i) lds_stack[(sp++) * BLOCK + lane] = ids[i];
-          cur = ids[0];
+          if (cnt > 3) lds_stack[(sp++) * BLOCK + lane] = c3;
+          if (cnt > 2) lds_stack[(sp++) * BLOCK + lane] = c2;
+          if (cnt > 1) lds_stack[(sp++) * BLOCK + lane] = c1;
+          cur = c0;
           continue;
         }
       } else {
@@ -309,14 +318,22 @@ __device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, u
       float tn[4];
       uint32_t m = enter_children(r, n, tcull, tn);
       if (m) {
-        const int first = __builtin_ctz(m);
-        m &= m - 1u;
-        while (m) {
-          const int c = __builtin_ctz(m);
-          m &= m - 1u;
-          lds_stack[(sp++) * BLOCK + lane] = n.child[c];
+        // continue with the first entered child, push the others (constant indices only, so
+        // the node stays in registers)
+        bool taken = false;
+        uint32_t next = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (m & (1u << c)) {
+            if (!taken) {
+              next = n.child[c];
+              taken = true;
+            } else {
+              lds_stack[(sp++) * BLOCK + lane] = n.child[c];
+            }
+          }
         }
-        cur = n.child[first];
+        cur = next;
         continue;
       }
     } else {
@@ -338,10 +355,17 @@ __device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, u
 // ---- wave helpers ----
 __device__ inline uint32_t wave_popc(bool pred) { return (uint32_t)__popcll(__ballot(pred)); }
 
+// Counters are striped over kStatStripes copies (chosen by block) so that concurrent waves do
+// not serialise on one address; the host sums the stripes.
+constexpr uint32_t kStatStripes = 64;
+
 __device__ inline void stat_add(unsigned long long* stats, int idx, bool pred) {
   const uint64_t m = __ballot(pred);
   if (m != 0 && (threadIdx.x & 63u) == (uint32_t)__ffsll((long long)__ballot(1)) - 1u)
-    atomicAdd(&stats[idx], (unsigned long long)__popcll(m));
+    atomicAdd(&stats[(blockIdx.x % kStatStripes) * GI_STAT_COUNT + idx], (unsigned long long)__popcll(m));
 }
+
+// lanes below this one in the wave
+__device__ inline uint64_t lanes_below() { return (1ull << (threadIdx.x & 63u)) - 1ull; }
 
 }  // namespace gi

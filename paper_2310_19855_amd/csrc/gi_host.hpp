@@ -80,7 +80,10 @@ struct gi_context {
   float4* d_atlas = nullptr;    // [P*64]
   float* d_sh = nullptr;        // [P*28]
   gi::Table tab;
-  unsigned long long* d_stats = nullptr;  // [GI_STAT_COUNT]
+  unsigned long long* d_stats = nullptr;  // [kStatStripes][GI_STAT_COUNT]
+  uint32_t* d_hit_ids = nullptr;          // compacted hit list, kStatStripes stripes
+  uint32_t* d_hit_count = nullptr;        // [kStatStripes]
+  uint32_t hit_blocks_per_stripe = 0, hit_stripe_cap = 0;
   float* d_moments = nullptr;   // [64*10]
   // learned
   gi::LearnedState* learned = nullptr;

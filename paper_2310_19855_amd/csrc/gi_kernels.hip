@@ -62,12 +62,14 @@ __global__ __launch_bounds__(kTraceBlock) void k_gbuffer(SceneView sv, ShadeTabl
 // ------------------------------------------------------------------------------------------
 __global__ void k_spawn(const float4* gpos, const float4* gnrm, const uint32_t* gprim, uint32_t W, uint32_t H,
                         uint32_t TW, uint32_t TH, uint32_t jx, uint32_t jy, uint32_t* mask, float4* ppos,
-                        float4* pnrm, unsigned long long* stats) {
+                        float4* pnrm, unsigned long long* stats, uint32_t* hit_count) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0) {
-    stats[GI_STAT_LIVE] = 0;
-    stats[GI_STAT_RELAXED] = 0;
-    stats[GI_STAT_NOPROBE] = 0;
+  if (p < kStatStripes) {
+    // per-frame counters restart; so do the hit-list stripes of this frame's trace
+    stats[p * GI_STAT_COUNT + GI_STAT_LIVE] = 0;
+    stats[p * GI_STAT_COUNT + GI_STAT_RELAXED] = 0;
+    stats[p * GI_STAT_COUNT + GI_STAT_NOPROBE] = 0;
+    hit_count[p] = 0;
   }
   if (p >= TW * TH) return;
   const uint32_t tx = p % TW, ty = p / TW;
@@ -124,9 +126,21 @@ __device__ inline void probe_ray(const ProbeRayArgs& a, uint32_t gid, uint32_t p
   oz = pp.z + pn.z * eps;
 }
 
+// Hits are regrouped for the shading pass: each wave ballots its hit lanes and appends their
+// ray ids to the list stripe of its block range with one atomic per wave, so the shading
+// waves run dense.  The list order is not deterministic; nothing downstream depends on it
+// (cell sums are integer and the cell map is order-free).
+struct HitList {
+  uint32_t* ids;          // [kStatStripes * stripe_cap]
+  uint32_t* count;        // [kStatStripes]
+  uint32_t stripe_cap;    // ray slots per stripe (= blocks per stripe * 64)
+  uint32_t blocks_per_stripe;
+};
+
 template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, ShadeTables st, ProbeRayArgs a,
-                                                              uint4* rec, unsigned long long* stats) {
+                                                              uint4* rec, uint2* rkey, HitList hl,
+                                                              unsigned long long* stats) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
   const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
   if (gid >= a.P * a.R) return;
@@ -135,6 +149,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, Shad
   stat_add(stats, GI_STAT_RAYS, valid);
   if (!valid) {
     rec[gid] = make_uint4(0xFFFFFFFFu, 0u, kMiss, 0u);
+    rkey[gid] = make_uint2(0u, 0u);
     return;
   }
   float ox, oy, oz, dx, dy, dz;
@@ -145,15 +160,26 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, Shad
   float t;
   closest_hit<STACK, kTraceBlock>(sv, r, 3.0e38f, stk, threadIdx.x, tri, t);
   uint32_t flags = cell | GI_RAY_TRACED;
-  if (tri == kMiss) {
+  const bool hit = tri != kMiss;
+  if (!hit) {
     rec[gid] = make_uint4(0xFFFFFFFFu, __float_as_uint(a.t_sky), kMiss, flags);
-    return;
+    rkey[gid] = make_uint2(0u, 0u);
+  } else {
+    const float4 n = st.tnrm[tri];
+    const float dn = (n.x * dx + n.y * dy) + n.z * dz;
+    flags |= GI_RAY_HIT;
+    if (dn < 0.0f) flags |= GI_RAY_FRONT;
+    rec[gid] = make_uint4(0xFFFFFFFFu, __float_as_uint(t), tri, flags);
   }
-  const float4 n = st.tnrm[tri];
-  const float dn = (n.x * dx + n.y * dy) + n.z * dz;
-  flags |= GI_RAY_HIT;
-  if (dn < 0.0f) flags |= GI_RAY_FRONT;
-  rec[gid] = make_uint4(0xFFFFFFFFu, __float_as_uint(t), tri, flags);
+  const uint64_t m = __ballot(hit);
+  if (m) {
+    const uint32_t stripe = blockIdx.x / hl.blocks_per_stripe;
+    const uint32_t leader = (uint32_t)__ffsll((long long)__ballot(1)) - 1u;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63u) == leader) base = atomicAdd(&hl.count[stripe], (uint32_t)__popcll(m));
+    base = __shfl(base, (int)leader, 64);
+    if (hit) hl.ids[stripe * hl.stripe_cap + base + (uint32_t)__popcll(m & lanes_below())] = gid;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -267,18 +293,16 @@ __device__ inline LightSample sample_light(const ShadeTables& st, uint32_t seed,
 
 template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeTables st, ProbeRayArgs a,
-                                                            CacheArgs c, uint4* rec, uint2* rkey,
+                                                            CacheArgs c, uint4* rec, uint2* rkey, HitList hl,
                                                             unsigned long long* stats) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
-  const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
-  if (gid >= a.P * a.R) return;
-  uint4 rr = rec[gid];
-  const bool hit = (rr.w & GI_RAY_HIT) != 0u;
-  stat_add(stats, GI_STAT_HITS, hit);
-  if (!hit) {
-    rkey[gid] = make_uint2(0u, 0u);
-    return;
-  }
+  // block b shades items [w * 64, w * 64 + 64) of list stripe b / blocks_per_stripe
+  const uint32_t stripe = blockIdx.x / hl.blocks_per_stripe;
+  const uint32_t item = (blockIdx.x % hl.blocks_per_stripe) * kTraceBlock + threadIdx.x;
+  if (stripe >= kStatStripes || item >= hl.count[stripe]) return;
+  const uint32_t gid = hl.ids[stripe * hl.stripe_cap + item];
+  const uint4 rr = rec[gid];
+  stat_add(stats, GI_STAT_HITS, true);
   const uint32_t p = gid / a.R;
   float ox, oy, oz, dx, dy, dz;
   uint32_t cell;
@@ -597,7 +621,7 @@ __global__ void k_interpolate(const float4* gpos, const float4* gnrm, const uint
       const int32_t bx = ux >> 3, by = uy >> 3;
       const float fx = (float)(ux - 8 * bx) * 0.125f, fy = (float)(uy - 8 * by) * 0.125f;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, ws = 0.f;
-      float e[4][3];
+      float r0 = 0.f, r1 = 0.f, r2 = 0.f;   // equal-weight sum for the relaxed fallback
       int nf = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -622,7 +646,7 @@ __global__ void k_interpolate(const float4* gpos, const float4* gnrm, const uint
         }
         float E0, E1, E2;
         sh_irradiance(c, pn.x, pn.y, pn.z, E0, E1, E2);
-        e[nf][0] = E0; e[nf][1] = E1; e[nf][2] = E2;
+        r0 = r0 + E0; r1 = r1 + E1; r2 = r2 + E2;
         a0 = a0 + w * E0; a1 = a1 + w * E1; a2 = a2 + w * E2;
         ws = ws + w;
         ++nf;
@@ -630,10 +654,8 @@ __global__ void k_interpolate(const float4* gpos, const float4* gnrm, const uint
       if (ws > 0.0f) {
         out[i] = make_float4(a0 / ws, a1 / ws, a2 / ws, GI_INTERP_OK);
       } else if (nf > 0) {
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-        for (int k = 0; k < nf; ++k) { s0 = s0 + e[k][0]; s1 = s1 + e[k][1]; s2 = s2 + e[k][2]; }
         const float fn = (float)nf;
-        out[i] = make_float4(s0 / fn, s1 / fn, s2 / fn, GI_INTERP_RELAXED);
+        out[i] = make_float4(r0 / fn, r1 / fn, r2 / fn, GI_INTERP_RELAXED);
         relaxed = true;
       } else {
         out[i] = make_float4(0.f, 0.f, 0.f, GI_INTERP_NO_PROBE);
@@ -778,6 +800,15 @@ static ProbeRayArgs probe_args(const gi_context* c) {
   return a;
 }
 
+static HitList hit_list(const gi_context* c) {
+  HitList h;
+  h.ids = c->d_hit_ids;
+  h.count = c->d_hit_count;
+  h.stripe_cap = c->hit_stripe_cap;
+  h.blocks_per_stripe = c->hit_blocks_per_stripe;
+  return h;
+}
+
 static CacheArgs cache_args(const gi_context* c) {
   CacheArgs a;
   a.fp = c->tab.fp;
@@ -845,7 +876,7 @@ hipError_t launch_gbuffer(gi_context* c, const gi_frame* f, float4* pos, float4*
 }
 
 hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, hipStream_t s) {
-  GI_TIMED(c, "spawn", s, (k_spawn<<<blocks(c->P, 256), 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats)));
+  GI_TIMED(c, "spawn", s, (k_spawn<<<blocks(c->P, 256), 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
   for (uint32_t k = 1; k < c->nmip; ++k) {
     const uint32_t n = c->mip_w[k] * c->mip_h[k];
     GI_TIMED(c, "mask_mip", s, (k_mask_mip<<<blocks(n, 256), 256, 0, s>>>(c->d_mask + c->mip_off[k - 1], c->mip_w[k - 1], c->mip_h[k - 1], c->d_mask + c->mip_off[k], c->mip_w[k], c->mip_h[k])));
@@ -860,11 +891,11 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
   const ProbeRayArgs a = probe_args(c);
   const CacheArgs ca = cache_args(c);
   if (c->stack_depth <= 32) {
-    GI_TIMED(c, "trace_probes", s, (k_trace_probes<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_stats)));
-    GI_TIMED(c, "shade_hits", s, (k_shade_hits<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, c->d_stats)));
+    GI_TIMED(c, "trace_probes", s, (k_trace_probes<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
+    GI_TIMED(c, "shade_hits", s, (k_shade_hits<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
   } else {
-    GI_TIMED(c, "trace_probes", s, (k_trace_probes<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_stats)));
-    GI_TIMED(c, "shade_hits", s, (k_shade_hits<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, c->d_stats)));
+    GI_TIMED(c, "trace_probes", s, (k_trace_probes<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
+    GI_TIMED(c, "shade_hits", s, (k_shade_hits<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
   }
   return hipGetLastError();
 }
@@ -916,7 +947,7 @@ hipError_t launch_count_traversal(gi_context* c, unsigned long long* out, hipStr
 }
 
 hipError_t launch_zero_stats(gi_context* c, hipStream_t s) {
-  k_zero_u64<<<1, 64, 0, s>>>(c->d_stats, GI_STAT_COUNT);
+  k_zero_u64<<<blocks((uint64_t)GI_STAT_COUNT * kStatStripes, 256), 256, 0, s>>>(c->d_stats, GI_STAT_COUNT * kStatStripes);
   return hipGetLastError();
 }
 
