@@ -195,6 +195,12 @@ gi_status gi_measure_traversal(gi_context *ctx, uint64_t *h_out8, void *stream);
  * Between gi_trace_probes and gi_cache_update.  GI_ERR_STATE in plain mode. */
 gi_status gi_learned_train(gi_context *ctx, const gi_frame *frame, void *stream);
 
+/* One optimiser step on caller samples (tests, warm starts): d_pos, d_nrm, d_target [n][4]
+ * with n == 2^mlp_batch_log2.  apply = 0 computes the gradients only (kept for
+ * gi_learned_save), apply = 1 also takes the Adam step. */
+gi_status gi_learned_step(gi_context *ctx, const float *d_pos, const float *d_nrm, const float *d_target,
+                          uint32_t n, uint32_t apply, void *stream);
+
 /* Evaluate the surrogate at caller points: d_pos [n][4], d_nrm [n][4] -> d_out [n][4]. */
 gi_status gi_learned_query(gi_context *ctx, const float *d_pos, const float *d_nrm, uint32_t n,
                            float *d_out, void *stream);

@@ -13,7 +13,8 @@ Definitions (every one mirrored by the HIP kernels):
     dense, vx + vy (N_l+1) + vz (N_l+1)^2, when (N_l+1)^3 <= T, else the spatial hash
     (vx * 1 ^ vy * 2654435761 ^ vz * 805459861) mod T in uint32 arithmetic.  Each entry holds
     2 features; the level's output is the weighted sum.  Levels are concatenated: 2L values.
-  * MLP input (64): [encoding (2L), normal feature (3), 1.0, zeros]; W1 (64x64) -> ReLU ->
+  * MLP input (64): columns 0..2L-1 the encoding (columns up to 31 zero when L < 16), 32..34
+    the normal feature, 35 the constant 1, the rest zero; W1 (64x64) -> ReLU ->
     W2 (64x64) -> ReLU -> W3 (16x64); outputs 0..2 are radiance.  No biases (the constant
     input plays that role).
   * loss: mean over samples and 3 channels of (y - t)^2 / (sg(y)^2 + 0.01) (relative L2 with
@@ -136,8 +137,8 @@ def features(spec: Spec, params, x32, nrm):
         enc[:, 2 * l + 1] = (w * g[idx, 1]).sum(1)
     X = np.zeros((len(x32), 64))
     X[:, :2 * spec.levels] = enc
-    X[:, 2 * spec.levels:2 * spec.levels + 3] = (np.asarray(nrm, np.float64) + 1.0) / 2.0
-    X[:, 2 * spec.levels + 3] = 1.0
+    X[:, 32:35] = (np.asarray(nrm, np.float64) + 1.0) / 2.0
+    X[:, 35] = 1.0
     return X, corners
 
 

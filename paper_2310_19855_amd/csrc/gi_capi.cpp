@@ -210,6 +210,8 @@ void free_frame_buffers(gi_context* c) {
 
 void free_scene(gi_context* c) {
   dfree(c->d_nodes);
+  dfree(c->d_spill);
+  c->spill_rows = 0;
   dfree(c->d_tris);
   dfree(c->d_tnrm);
   dfree(c->d_mats);
@@ -400,8 +402,13 @@ gi_status gi_build_bvh(gi_context* c, const float* h_verts, uint32_t n_verts, co
     c->n_nodes = (uint32_t)nodes.size();
     c->bvh_depth = depth;
     const uint32_t need = 3 * depth + 1;
-    if (need > 64) return fail(c, GI_ERR_UNSUPPORTED, "BVH deeper than the 64-entry traversal stack");
-    c->stack_depth = need <= 32 ? 32 : 64;
+    // an ordered 4-wide walk holds at most 3 entries per level: the top 16 stay in LDS, the
+    // rest go to one spill row each, per lane id
+    if (need > 256) return fail(c, GI_ERR_UNSUPPORTED, "BVH deeper than 85 levels");
+    c->stack_depth = need;
+    c->spill_rows = need > 16 ? need - 16 : 0;
+    c->spill_stride = std::max(c->P * c->R, c->W * c->H);
+    if (c->spill_rows) GI_TRY_HIP(c, dalloc(&c->d_spill, (size_t)c->spill_rows * c->spill_stride));
     std::vector<float4> tris(3 * (size_t)std::max(n_tris, 1u));
     for (uint32_t i = 0; i < n_tris; ++i) {
       const uint32_t t = order[i];
@@ -610,6 +617,21 @@ gi_status gi_measure_traversal(gi_context* c, uint64_t* out8, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipMemcpy(out8, d, 64, hipMemcpyDeviceToHost);
   dfree(d);
+  GI_TRY_HIP(c, e);
+  return GI_OK;
+}
+
+gi_status gi_learned_step(gi_context* c, const float* pos, const float* nrm, const float* tgt, uint32_t n,
+                          uint32_t apply, void* stream) {
+  if (!c) return GI_ERR_INVALID_ARG;
+  if (c->cfg.cache_mode == GI_CACHE_PLAIN || !c->learned) return fail(c, GI_ERR_STATE, "learned cache disabled");
+  if (!pos || !nrm || !tgt) return fail(c, GI_ERR_INVALID_ARG, "null argument");
+  if (!aligned16(pos) || !aligned16(nrm) || !aligned16(tgt)) return fail(c, GI_ERR_INVALID_ARG, "not 16-byte aligned");
+  if (!c->has_scene) return fail(c, GI_ERR_STATE, "gi_build_bvh first (it fixes the encoding domain)");
+  const hipError_t e = gi::learned_step_on(c, reinterpret_cast<const float4*>(pos), reinterpret_cast<const float4*>(nrm),
+                                           reinterpret_cast<const float4*>(tgt), n, apply != 0,
+                                           reinterpret_cast<hipStream_t>(stream));
+  if (e == hipErrorInvalidValue) return fail(c, GI_ERR_INVALID_ARG, "n must equal 2^mlp_batch_log2");
   GI_TRY_HIP(c, e);
   return GI_OK;
 }

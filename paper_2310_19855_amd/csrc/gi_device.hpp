@@ -40,6 +40,7 @@ __device__ inline uint32_t rand_u32(uint32_t seed, uint32_t frame, uint32_t id, 
 }
 
 __device__ inline float rand_unit(uint32_t h) { return (float)(h >> 8) * 5.9604644775390625e-08f; }
+__host__ inline float rand_unit_host(uint32_t h) { return (float)(h >> 8) * 5.9604644775390625e-08f; }
 
 // ---- cos/sin(2 pi u): exact octant reduction, Taylor polynomials (1/n!) on [0, pi/4] ----
 __device__ inline void cos_sin_2pi(float u, float& co, float& si) {
@@ -222,14 +223,44 @@ struct SceneView {
   const float4* dyn;        // [3 * n_dyn]
   uint32_t n_dyn;
   uint32_t has_bvh;
+  uint32_t* spill;          // traversal-stack spill array [rows][spill_stride]
+  uint32_t spill_stride;    // lane ids per row
+};
+
+// Traversal stack of one lane.  The top K entries live in LDS (column `lane` of a [K][BLOCK]
+// array, K a power of two); when a push finds them all live, the oldest one moves to a
+// per-lane global array laid out [depth][lane] (coalesced across a wave), and a pop below what
+// LDS holds reads it back.  Live entries [lo, sp) are in LDS, [0, lo) in the spill array.
+template <int K, int BLOCK>
+struct TStack {
+  uint32_t* lds;      // &lds_array[lane]
+  uint32_t* spill;    // &spill_array[lane id]; entry i at spill[i * stride]
+  uint32_t stride;
+  int sp, lo;
+  __device__ TStack(uint32_t* l, uint32_t* s, uint32_t st) : lds(l), spill(s), stride(st), sp(0), lo(0) {}
+  __device__ void reset() { sp = 0; lo = 0; }
+  __device__ void push(uint32_t v) {
+    if (sp - lo == K) {
+      spill[(size_t)lo * stride] = lds[(lo & (K - 1)) * BLOCK];
+      ++lo;
+    }
+    lds[(sp & (K - 1)) * BLOCK] = v;
+    ++sp;
+  }
+  __device__ uint32_t pop() {
+    --sp;
+    if (sp >= lo) return lds[(sp & (K - 1)) * BLOCK];
+    lo = sp;
+    return spill[(size_t)sp * stride];
+  }
+  __device__ bool empty() const { return sp == 0; }
 };
 
 // Closest hit: lexicographic minimum of (t, triangle index) over every triangle; the BVH walk
-// only prunes boxes that cannot hold a better hit.  STACK entries of the LDS stack belong to
-// this lane (column `lane` of a [STACK][BLOCK] array).
-template <int STACK, int BLOCK, bool COUNT = false>
-__device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tmax, uint32_t* lds_stack,
-                                   uint32_t lane, uint32_t& tri_out, float& t_out, uint32_t* n_nodes = nullptr,
+// only prunes boxes that cannot hold a better hit.
+template <int K, int BLOCK, bool COUNT = false>
+__device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tmax, TStack<K, BLOCK>& stk,
+                                   uint32_t& tri_out, float& t_out, uint32_t* n_nodes = nullptr,
                                    uint32_t* n_tris = nullptr) {
   float best_t = tmax;
   uint32_t best = kMiss;
@@ -242,7 +273,7 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
     }
   }
   if (sv.has_bvh) {
-    int sp = 0;
+    stk.reset();
     uint32_t cur = 0;   // root is always an inner node
     while (true) {
       if (!(cur & kLeafBit)) {
@@ -250,7 +281,6 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
         if (COUNT) ++*n_nodes;
         float tn[4];
         uint32_t m = enter_children(r, n, best_t * 1.0001221f, tn);
-        // order the entered children by entry distance: nearest first
         // order the entered children nearest first with a 5-exchange sorting network held in
         // registers (children not entered sort last with t = +inf)
         float t0 = (m & 1u) ? tn[0] : __builtin_inff(), t1 = (m & 2u) ? tn[1] : __builtin_inff();
@@ -272,9 +302,9 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
         cswap(t1, c1, t2, c2);
         const int cnt = __builtin_popcount(m);
         if (cnt > 0) {
-          if (cnt > 3) lds_stack[(sp++) * BLOCK + lane] = c3;
-          if (cnt > 2) lds_stack[(sp++) * BLOCK + lane] = c2;
-          if (cnt > 1) lds_stack[(sp++) * BLOCK + lane] = c1;
+          if (cnt > 3) stk.push(c3);
+          if (cnt > 2) stk.push(c2);
+          if (cnt > 1) stk.push(c1);
           cur = c0;
           continue;
         }
@@ -291,8 +321,8 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
           }
         }
       }
-      if (sp == 0) break;
-      cur = lds_stack[(--sp) * BLOCK + lane];
+      if (stk.empty()) break;
+      cur = stk.pop();
     }
   }
   tri_out = best;
@@ -300,8 +330,8 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
 }
 
 // Any hit in (0, tmax)
-template <int STACK, int BLOCK, bool COUNT = false>
-__device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, uint32_t* lds_stack, uint32_t lane,
+template <int K, int BLOCK, bool COUNT = false>
+__device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, TStack<K, BLOCK>& stk,
                                uint32_t* n_nodes = nullptr, uint32_t* n_tris = nullptr) {
   for (uint32_t k = 0; k < sv.n_dyn; ++k) {
     float t;
@@ -309,7 +339,7 @@ __device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, u
   }
   if (!sv.has_bvh) return false;
   const float tcull = tmax * 1.0001221f;
-  int sp = 0;
+  stk.reset();
   uint32_t cur = 0;
   while (true) {
     if (!(cur & kLeafBit)) {
@@ -329,7 +359,7 @@ __device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, u
               next = n.child[c];
               taken = true;
             } else {
-              lds_stack[(sp++) * BLOCK + lane] = n.child[c];
+              stk.push(n.child[c]);
             }
           }
         }
@@ -346,8 +376,8 @@ __device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, u
           return true;
       }
     }
-    if (sp == 0) break;
-    cur = lds_stack[(--sp) * BLOCK + lane];
+    if (stk.empty()) break;
+    cur = stk.pop();
   }
   return false;
 }

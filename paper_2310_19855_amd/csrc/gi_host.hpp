@@ -53,6 +53,8 @@ struct gi_context {
   bool has_scene = false;
   uint32_t nt = 0, n_mats = 0, n_nodes = 0, bvh_depth = 0, stack_depth = 0;
   gi::Node4* d_nodes = nullptr;
+  uint32_t* d_spill = nullptr;  // traversal-stack spill rows [spill_rows][spill_stride]
+  uint32_t spill_rows = 0, spill_stride = 0;
   float4* d_tris = nullptr;     // leaf-ordered triangles, 3 float4 each (v0.w = index)
   float4* d_tnrm = nullptr;     // [nt + kMaxDyn] unit normal, w = material index
   float4* d_mats = nullptr;     // [2 * n_mats]: albedo, emission
@@ -126,6 +128,23 @@ hipError_t launch_zero_stats(gi_context* c, hipStream_t s);
 hipError_t launch_count_traversal(gi_context* c, unsigned long long* out, hipStream_t s);
 
 // learned surrogate (gi_learned.hip)
+struct LearnedShadeOut {       // written by the shading pass in learned mode (else all null)
+  float4* hitpos = nullptr;    // [P*R] hit point
+  float4* hitnrm = nullptr;    // [P*R] face-forwarded normal
+  float4* trec = nullptr;      // training records: target rgb, w = ray id bits
+  uint32_t* trec_count = nullptr;
+  uint32_t trec_cap = 0;
+};
+struct LearnedGatherIn {       // read by the probe gather in learned mode (else all null)
+  const float4* lmlp = nullptr;   // [P*R] surrogate radiance at each hit
+  const float* flags = nullptr;   // [4] = fallback flag
+  const uint2* meta = nullptr;    // world-cache (history samples, life)
+};
+LearnedShadeOut learned_shade_out(gi_context* c);
+LearnedGatherIn learned_gather_in(gi_context* c);
+void learned_set_domain(gi_context* c);
+hipError_t learned_step_on(gi_context* c, const float4* pos, const float4* nrm, const float4* tgt, uint32_t n,
+                           bool apply, hipStream_t st);
 hipError_t learned_create(gi_context* c);
 void learned_destroy(gi_context* c);
 hipError_t learned_train(gi_context* c, hipStream_t s);

@@ -6,7 +6,8 @@
 
 namespace gi {
 
-constexpr int kTraceBlock = 64;   // one wave per block: the LDS stack is [STACK][64]
+constexpr int kTraceBlock = 64;   // one wave per block: the LDS part of the stack is [K][64]
+constexpr int kLdsStack = 16;    // traversal-stack entries per lane kept in LDS (the rest spill)
 
 struct ShadeTables {
   const float4* tnrm;    // unit normal, w = material index bits
@@ -26,6 +27,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_gbuffer(SceneView sv, ShadeTabl
                                                          uint32_t H, float4* pos, float4* nrm, float4* alb,
                                                          uint32_t* prim) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
   if (i >= W * H) return;
   const uint32_t x = i % W, y = i / W;
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_gbuffer(SceneView sv, ShadeTabl
   const RayQ r = make_ray(f.pos[0], f.pos[1], f.pos[2], dx, dy, dz);
   uint32_t tri;
   float t;
-  closest_hit<STACK, kTraceBlock>(sv, r, 3.0e38f, stk, threadIdx.x, tri, t);
+  closest_hit<STACK, kTraceBlock>(sv, r, 3.0e38f, ts, tri, t);
   prim[i] = tri;
   if (tri == kMiss) {
     pos[i] = nrm[i] = alb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -142,6 +144,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, Shad
                                                               uint4* rec, uint2* rkey, HitList hl,
                                                               unsigned long long* stats) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
   if (gid >= a.P * a.R) return;
   const uint32_t p = gid / a.R;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, Shad
   const RayQ r = make_ray(ox, oy, oz, dx, dy, dz);
   uint32_t tri;
   float t;
-  closest_hit<STACK, kTraceBlock>(sv, r, 3.0e38f, stk, threadIdx.x, tri, t);
+  closest_hit<STACK, kTraceBlock>(sv, r, 3.0e38f, ts, tri, t);
   uint32_t flags = cell | GI_RAY_TRACED;
   const bool hit = tri != kMiss;
   if (!hit) {
@@ -294,6 +297,7 @@ __device__ inline LightSample sample_light(const ShadeTables& st, uint32_t seed,
 template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeTables st, ProbeRayArgs a,
                                                             CacheArgs c, uint4* rec, uint2* rkey, HitList hl,
+                                                            LearnedShadeOut lo,
                                                             unsigned long long* stats) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
   // block b shades items [w * 64, w * 64 + 64) of list stripe b / blocks_per_stripe
@@ -301,6 +305,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const uint32_t item = (blockIdx.x % hl.blocks_per_stripe) * kTraceBlock + threadIdx.x;
   if (stripe >= kStatStripes || item >= hl.count[stripe]) return;
   const uint32_t gid = hl.ids[stripe * hl.stripe_cap + item];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + gid, sv.spill_stride);
   const uint4 rr = rec[gid];
   stat_add(stats, GI_STAT_HITS, true);
   const uint32_t p = gid / a.R;
@@ -316,6 +321,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float nx = sg * n.x, ny = sg * n.y, nz = sg * n.z;
   const uint64_t key = descriptor(c.cell_scale, c.leak_bit, yx, yy, yz, nx, ny, nz, t, true);
   rkey[gid] = make_uint2((uint32_t)key, (uint32_t)(key >> 32));
+  if (lo.hitpos) {
+    lo.hitpos[gid] = make_float4(yx, yy, yz, t);
+    lo.hitnrm[gid] = make_float4(nx, ny, nz, 0.0f);
+  }
   bool inserted;
   const int32_t slot = table_insert(c, key, inserted);
   stat_add(stats, GI_STAT_INSERTS, inserted);
@@ -330,7 +339,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const bool cast = ls.cast;
   bool occl = false;
   if (cast) {
-    occl = any_hit<STACK, kTraceBlock>(sv, ls.ray, ls.tmax, stk, threadIdx.x);
+    occl = any_hit<STACK, kTraceBlock>(sv, ls.ray, ls.tmax, ts);
     if (!occl) {
       const float4 le = st.mats[2 * ls.mat + 1];
       E0 = le.x * ls.g;
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
     const RayQ br = make_ray(px, py, pz, bx, by, bz);
     uint32_t btri;
     float bt;
-    closest_hit<STACK, kTraceBlock>(sv, br, 3.0e38f, stk, threadIdx.x, btri, bt);
+    closest_hit<STACK, kTraceBlock>(sv, br, 3.0e38f, ts, btri, bt);
     if (btri == kMiss) {
       Lb0 = c.sky[0]; Lb1 = c.sky[1]; Lb2 = c.sky[2];
     } else {
@@ -377,6 +386,18 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float s2 = alb.z * (E2 * 0.31830988618379067f + Lb2);
   const bool finite = isfinite(s0) && isfinite(s1) && isfinite(s2);
   stat_add(stats, GI_STAT_NONFINITE, !finite);
+  if (lo.trec) {
+    // learned mode: the sample (before quantisation) becomes a training record
+    const uint64_t m = __ballot(finite);
+    if (m) {
+      const uint32_t leader = (uint32_t)__ffsll((long long)__ballot(1)) - 1u;
+      uint32_t base = 0;
+      if ((threadIdx.x & 63u) == leader) base = atomicAdd(lo.trec_count, (uint32_t)__popcll(m));
+      base = __shfl(base, (int)leader, 64);
+      const uint32_t at = base + (uint32_t)__popcll(m & lanes_below());
+      if (finite && at < lo.trec_cap) lo.trec[at] = make_float4(s0, s1, s2, __uint_as_float(gid));
+    }
+  }
   if (!finite) return;
   const float scale = (float)(1u << c.frac_bits);
   const uint32_t q0 = (uint32_t)rintf(fminf(fmaxf(s0, 0.0f), c.r_max) * scale);
@@ -451,7 +472,7 @@ __device__ inline float wave_sum(float v) {
 __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const float4* pnrm, const uint4* rec,
                                                   const float4* L, const float4* tnrm, const float4* mats,
                                                   const float* moments, uint32_t R, float s0, float s1, float s2,
-                                                  float4* atlas, float* sh) {
+                                                  LearnedGatherIn lg, float4* atlas, float* sh) {
   __shared__ float rv[kGatherMaxR][4];
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
@@ -475,7 +496,13 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
         le0 = e.x; le1 = e.y; le2 = e.z;
       }
       float l0 = 0.f, l1 = 0.f, l2 = 0.f;
-      if ((int32_t)r.x >= 0) {
+      const bool confident = (int32_t)r.x >= 0 && lg.meta && lg.meta[r.x].x >= 64u;
+      if (lg.lmlp && (lg.flags[4] == 0.0f || !confident)) {
+        // learned mode: the surrogate's radiance at this hit, unless the judge fell back to
+        // the plain cache and this hit's cell is confident
+        const float4 lv = lg.lmlp[(size_t)p * R + j];
+        l0 = lv.x; l1 = lv.y; l2 = lv.z;
+      } else if ((int32_t)r.x >= 0) {
         const float4 lv = L[r.x];
         l0 = lv.x; l1 = lv.y; l2 = lv.z;
       }
@@ -690,17 +717,18 @@ template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_rays(SceneView sv, const float4* o, const float4* d, uint32_t n,
                                                             uint32_t any, uint32_t* tri, float* t) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
   if (i >= n) return;
   const float4 a = o[i], b = d[i];
   const RayQ r = make_ray(a.x, a.y, a.z, b.x, b.y, b.z);
   if (any) {
-    tri[i] = any_hit<STACK, kTraceBlock>(sv, r, a.w, stk, threadIdx.x) ? 1u : 0u;
+    tri[i] = any_hit<STACK, kTraceBlock>(sv, r, a.w, ts) ? 1u : 0u;
     t[i] = 0.0f;
   } else {
     uint32_t h;
     float tt;
-    closest_hit<STACK, kTraceBlock>(sv, r, a.w, stk, threadIdx.x, h, tt);
+    closest_hit<STACK, kTraceBlock>(sv, r, a.w, ts, h, tt);
     tri[i] = h;
     t[i] = tt;
   }
@@ -713,6 +741,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
                                                                  CacheArgs c, const uint4* rec,
                                                                  unsigned long long* out) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
   uint32_t pn = 0, pt = 0, sn = 0, st_ = 0;
   bool probe = false, shadow = false;
@@ -726,7 +755,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
       const RayQ r = make_ray(ox, oy, oz, dx, dy, dz);
       uint32_t tri;
       float t;
-      closest_hit<STACK, kTraceBlock, true>(sv, r, 3.0e38f, stk, threadIdx.x, tri, t, &pn, &pt);
+      closest_hit<STACK, kTraceBlock, true>(sv, r, 3.0e38f, ts, tri, t, &pn, &pt);
       const uint4 rr = rec[gid];
       if (rr.w & GI_RAY_HIT) {
         const float4 n = st.tnrm[tri];
@@ -739,7 +768,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
                                             nx, ny, nz);
         if (ls.cast) {
           shadow = true;
-          (void)any_hit<STACK, kTraceBlock, true>(sv, ls.ray, ls.tmax, stk, threadIdx.x, &sn, &st_);
+          (void)any_hit<STACK, kTraceBlock, true>(sv, ls.ray, ls.tmax, ts, &sn, &st_);
         }
       }
     }
@@ -754,6 +783,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
     atomicAdd(&out[4], (unsigned long long)sn);
     atomicAdd(&out[5], (unsigned long long)st_);
   }
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 __global__ void k_zero_u64(unsigned long long* p, uint32_t n) {
@@ -771,6 +805,8 @@ static SceneView scene_view(const gi_context* c) {
   v.dyn = c->d_dyn;
   v.n_dyn = c->n_dyn;
   v.has_bvh = c->nt > 0 ? 1u : 0u;
+  v.spill = c->d_spill;
+  v.spill_stride = c->spill_stride;
   return v;
 }
 
@@ -868,10 +904,7 @@ static inline uint32_t blocks(uint64_t n, uint32_t b) { return (uint32_t)((n + b
 hipError_t launch_gbuffer(gi_context* c, const gi_frame* f, float4* pos, float4* nrm, float4* alb, uint32_t* prim,
                           hipStream_t s) {
   const uint32_t n = c->W * c->H;
-  if (c->stack_depth <= 32)
-    GI_TIMED(c, "gbuffer", s, (k_gbuffer<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), *f, c->W, c->H, pos, nrm, alb, prim)));
-  else
-    GI_TIMED(c, "gbuffer", s, (k_gbuffer<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), *f, c->W, c->H, pos, nrm, alb, prim)));
+    GI_TIMED(c, "gbuffer", s, (k_gbuffer<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), *f, c->W, c->H, pos, nrm, alb, prim)));
   return hipGetLastError();
 }
 
@@ -890,19 +923,21 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
   const ShadeTables st = shade_tables(c);
   const ProbeRayArgs a = probe_args(c);
   const CacheArgs ca = cache_args(c);
-  if (c->stack_depth <= 32) {
-    GI_TIMED(c, "trace_probes", s, (k_trace_probes<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
-    GI_TIMED(c, "shade_hits", s, (k_shade_hits<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
-  } else {
-    GI_TIMED(c, "trace_probes", s, (k_trace_probes<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
-    GI_TIMED(c, "shade_hits", s, (k_shade_hits<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
-  }
+  const LearnedShadeOut lso = learned_shade_out(c);
+  if (lso.trec_count) k_zero_u32<<<1, 64, 0, s>>>(lso.trec_count, 1);
+  GI_TIMED(c, "trace_probes", s, (k_trace_probes<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
+  GI_TIMED(c, "shade_hits", s, (k_shade_hits<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), learned_shade_out(c), c->d_stats)));
   return hipGetLastError();
 }
 
 hipError_t launch_update(gi_context* c, hipStream_t s) {
   GI_TIMED(c, "cache_update", s, (k_cache_update<<<blocks(c->N, 256), 256, 0, s>>>(c->N, c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->d_stats)));
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], c->d_atlas, c->d_sh)));
+  if (c->learned && c->cfg.cache_mode != GI_CACHE_PLAIN) {
+    // the surrogate's radiance at every hit, then the judge against confident plain cells
+    const hipError_t e = learned_infer_rays(c, s);
+    if (e != hipSuccess) return e;
+  }
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), c->d_atlas, c->d_sh)));
   return hipGetLastError();
 }
 
@@ -929,20 +964,19 @@ hipError_t launch_query(gi_context* c, const float4* pos, const float4* nrm, uin
 hipError_t launch_trace_rays(gi_context* c, const float4* o, const float4* d, uint32_t n, uint32_t any, uint32_t* tri,
                              float* t, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (c->stack_depth <= 32)
-    GI_TIMED(c, "trace_rays", s, (k_trace_rays<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), o, d, n, any, tri, t)));
-  else
-    GI_TIMED(c, "trace_rays", s, (k_trace_rays<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), o, d, n, any, tri, t)));
+  // the spill array has one column per lane id: launch in chunks of at most its width
+  const uint32_t cap = c->spill_stride;
+  for (uint32_t off = 0; off < n; off += cap) {
+    const uint32_t m = n - off < cap ? n - off : cap;
+    GI_TIMED(c, "trace_rays", s, (k_trace_rays<kLdsStack><<<blocks(m, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), o + off, d + off, m, any, tri + off, t + off)));
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_count_traversal(gi_context* c, unsigned long long* out, hipStream_t s) {
   const uint64_t n = (uint64_t)c->P * c->R;
   k_zero_u64<<<1, 64, 0, s>>>(out, 8);
-  if (c->stack_depth <= 32)
-    k_count_traversal<32><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), probe_args(c), cache_args(c), c->d_rec, out);
-  else
-    k_count_traversal<64><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), probe_args(c), cache_args(c), c->d_rec, out);
+  k_count_traversal<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), probe_args(c), cache_args(c), c->d_rec, out);
   return hipGetLastError();
 }
 

@@ -1,32 +1,1088 @@
-// Learned surrogate of the world cache (placeholder until the kernels land).
+// Learned surrogate of the world cache for gfx950 (not part of the GI-1.0 paper): a
+// multiresolution hash encoding (16 levels x 2^19 entries x 2 FP16 features) feeding a
+// 64-64 ReLU MLP, trained online on the radiance samples the pass produces each frame.
+//
+// Kernels: training forward + backward fused per wave of 32 samples (encoding gathers, BF16
+// MFMA layers with FP32 accumulation, relative-L2 loss with static loss scaling, backward
+// through the MLP on MFMA, weight gradients as per-wave MFMA partials, encoding gradients
+// scattered with FP32 atomics), a deterministic reduction of the weight gradients, dense Adam
+// with a skip on non-finite gradients, BF16 or FP8 (OCP e4m3) inference at every probe-ray
+// hit, and the judge that falls back to confident plain cells when the surrogate is off.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "gi_device.hpp"
 #include "gi_host.hpp"
 
 namespace gi {
 
-struct LearnedState {
-  int unused;
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kLd64 = 72;   // padded LDS row of a 64-wide bf16 tile (breaks bank conflicts)
+constexpr int kLd32 = 40;   // padded LDS row of a 32-wide bf16 tile
+constexpr int kMlpParams = 64 * 64 + 64 * 64 + 16 * 64;
+constexpr int kOffW1 = 0, kOffW2 = 4096, kOffW3 = 8192;
+constexpr uint32_t kPrimeY = 2654435761u, kPrimeZ = 805459861u;
+constexpr int kMaxLevels = 16;
+
+struct LearnedParams {
+  uint32_t L, T;
+  float res[kMaxLevels];
+  uint32_t dense_mask;
+  float lo[3], ext[3];
 };
 
+struct LearnedState {
+  LearnedParams lp;
+  uint32_t grid_n = 0;           // L * T * 2
+  float* grid = nullptr;         // FP32 master [L][T][2]
+  __half* grid_h = nullptr;      // FP16 working copy
+  float* grid_g = nullptr;       // gradient (scaled by the loss scale)
+  float* grid_m = nullptr;
+  float* grid_v = nullptr;
+  float* mlp = nullptr;          // FP32 master: W1 [64][64], W2 [64][64], W3 [16][64]
+  float* mlp_g = nullptr;
+  float* mlp_m = nullptr;
+  float* mlp_v = nullptr;
+  float* mlp_part = nullptr;     // [train_waves][kMlpParams]
+  __bf16* wb = nullptr;          // W1 [64][64] | W1t [64][64] | W2 | W2t | W3 [16][64] | W3t [64][32]
+  uint8_t* w8 = nullptr;         // e4m3 W1 | W2 | W3 (row-major [out][in])
+  float* scales = nullptr;       // [0..2] weight scales, [3..5] activation amax (X, H1, H2), [6..8] act scales
+  float4* hitpos = nullptr;      // [P*R] hit point (learned mode)
+  float4* hitnrm = nullptr;      // [P*R] face-forwarded normal
+  float4* trec = nullptr;        // [P*R] training record: target rgb, w = ray id bits
+  uint32_t* trec_count = nullptr;
+  float4* batch = nullptr;       // [B][3]: pos, nrm, target
+  uint32_t B = 0;
+  float4* lmlp = nullptr;        // [P*R] surrogate radiance at each hit
+  float* acc = nullptr;          // [0] loss sum, [1] non-finite flag, [2] judge |diff|, [3] judge |plain|,
+                                 // [4] fallback flag, [5] last loss, [6] last judged error, [7] batch n
+  uint32_t train_waves = 0;
+  int step = 0, skipped = 0;
+  float host_stats[8] = {0};
+};
+
+// ---- small helpers --------------------------------------------------------------------------
+
+__device__ inline f32x4_t mma_bf16(const __bf16* A, int lda, const __bf16* Bt, int ldb, f32x4_t acc) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kb = (lane >> 4) * 8;
+  const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(A + r * lda + kb);
+  const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(Bt + r * ldb + kb);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+__device__ inline f32x4_t mma_fp8(const uint8_t* A, int lda, const uint8_t* Bt, int ldb, f32x4_t acc) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kb = (lane >> 4) * 8;
+  const long a = *reinterpret_cast<const long*>(A + r * lda + kb);
+  const long b = *reinterpret_cast<const long*>(Bt + r * ldb + kb);
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc, 0, 0, 0);
+}
+
+__device__ inline __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
+__device__ inline float from_bf16(__bf16 x) { return static_cast<float>(x); }
+
+// round-to-nearest-even OCP e4m3 code of x, saturating to +-448; NaN -> 0x7F
+__device__ __host__ inline uint32_t e4m3_encode(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  if (x != x) return 0x7Fu;
+  float a = fabsf(x);
+  if (a > 448.0f) a = 448.0f;
+  if (a < 0.015625f) {   // subnormal range: m * 2^-9
+    const uint32_t q = (uint32_t)rintf(a * 512.0f);
+    return sign | q;
+  }
+  uint32_t ua;
+  std::memcpy(&ua, &a, 4);
+  const uint32_t e = ((ua >> 23) & 0xFFu) - 127u + 7u;
+  const uint32_t mant = ua & 0x7FFFFFu;
+  uint32_t m3 = mant >> 20;
+  const uint32_t rest = mant & 0xFFFFFu;
+  if (rest > 0x80000u || (rest == 0x80000u && (m3 & 1u))) m3 += 1u;
+  uint32_t code = (e << 3) + m3;
+  if (code > 0x7Eu) code = 0x7Eu;
+  return sign | code;
+}
+
+// encoding input of a point: x = clamp((y - lo) / (hi - lo), 0, 1)
+__device__ inline void norm_pos(const LearnedParams& lp, float y0, float y1, float y2, float& x0, float& x1, float& x2) {
+  x0 = fminf(fmaxf((y0 - lp.lo[0]) / lp.ext[0], 0.0f), 1.0f);
+  x1 = fminf(fmaxf((y1 - lp.lo[1]) / lp.ext[1], 0.0f), 1.0f);
+  x2 = fminf(fmaxf((y2 - lp.lo[2]) / lp.ext[2], 0.0f), 1.0f);
+}
+
+// the 8 corners of level l: table index and trilinear weight
+struct Corners {
+  uint32_t idx[8];
+  float w[8];
+};
+
+__device__ inline void level_corners(const LearnedParams& lp, int l, float x0, float x1, float x2, Corners& cn) {
+  const float N = lp.res[l];
+  const float p0 = x0 * N, p1 = x1 * N, p2 = x2 * N;
+  const float Nm1 = N - 1.0f;
+  const float v0f = fminf(floorf(p0), Nm1), v1f = fminf(floorf(p1), Nm1), v2f = fminf(floorf(p2), Nm1);
+  const float f0 = p0 - v0f, f1 = p1 - v1f, f2 = p2 - v2f;
+  const uint32_t v0 = (uint32_t)v0f, v1 = (uint32_t)v1f, v2 = (uint32_t)v2f;
+  const bool dense = (lp.dense_mask >> l) & 1u;
+  const uint32_t n1 = (uint32_t)N + 1u;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const uint32_t cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+    const uint32_t a = v0 + cx, b = v1 + cy, d = v2 + cz;
+    cn.idx[c] = dense ? (a + b * n1 + d * n1 * n1) : ((a ^ (b * kPrimeY) ^ (d * kPrimeZ)) & (lp.T - 1u));
+    cn.w[c] = (cx ? f0 : 1.0f - f0) * (cy ? f1 : 1.0f - f1) * (cz ? f2 : 1.0f - f2);
+  }
+}
+
+// ---- initialisation: counter-based seeded values, (2u - 1) * scale in float32 -----------
+
+__device__ inline float init_value(uint32_t seed, uint32_t stream, uint32_t i, float scale) {
+  const float u = rand_unit(rand_u32(seed, stream, i, 0u));
+  return (u * 2.0f - 1.0f) * scale;
+}
+
+__global__ void k_learned_init(float* grid, __half* grid_h, uint32_t L, uint32_t T, float* mlp, uint32_t seed) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t n = (uint64_t)L * T * 2u;
+  if (i < n) {
+    const uint32_t l = (uint32_t)(i / ((uint64_t)T * 2u));
+    const uint32_t k = (uint32_t)(i % ((uint64_t)T * 2u));
+    const float v = init_value(seed, 100u + l, k, 1e-4f);
+    grid[i] = v;
+    grid_h[i] = __float2half(v);
+  }
+  if (i < (uint64_t)kMlpParams) {
+    const float s = 0.30618621784789726f;   // sqrt(6 / 64)
+    float v = 0.0f;
+    if (i < 4096) v = init_value(seed, 1u, (uint32_t)i, s);
+    else if (i < 8192) v = init_value(seed, 2u, (uint32_t)(i - 4096), s);
+    else if (i < 8192 + 3 * 64) v = init_value(seed, 3u, (uint32_t)(i - 8192), s);
+    mlp[i] = v;
+  }
+}
+
+// bf16 and e4m3 working copies of the MLP weights and their per-tensor scales (one block)
+__global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* scales) {
+  __shared__ float red[3][32];
+  const int t = threadIdx.x;
+  float am[3] = {0.f, 0.f, 0.f};
+  for (int i = t; i < kMlpParams; i += 1024) {
+    const int tensor = i < 4096 ? 0 : (i < 8192 ? 1 : 2);
+    am[tensor] = fmaxf(am[tensor], fabsf(mlp[i]));
+  }
+  for (int k = 0; k < 3; ++k) {
+    float v = am[k];
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((t & 63) == 0) red[k][t >> 6] = v;
+  }
+  __syncthreads();
+  if (t < 3) {
+    float v = 0.f;
+    for (int w = 0; w < 16; ++w) v = fmaxf(v, red[t][w]);
+    scales[t] = v > 0.0f ? v / 448.0f : 1.0f;
+  }
+  __syncthreads();
+  __bf16* W1 = wb;
+  __bf16* W1t = wb + 4096;
+  __bf16* W2 = wb + 8192;
+  __bf16* W2t = wb + 12288;
+  __bf16* W3 = wb + 16384;
+  __bf16* W3t = wb + 16384 + 1024;   // [64][32], columns 16..31 zero
+  for (int i = t; i < 4096; i += 1024) {
+    const int r = i >> 6, c = i & 63;
+    W1[i] = to_bf16(mlp[kOffW1 + i]);
+    W1t[c * 64 + r] = to_bf16(mlp[kOffW1 + i]);
+    W2[i] = to_bf16(mlp[kOffW2 + i]);
+    W2t[c * 64 + r] = to_bf16(mlp[kOffW2 + i]);
+    w8[i] = (uint8_t)e4m3_encode(mlp[kOffW1 + i] / scales[0]);
+    w8[4096 + i] = (uint8_t)e4m3_encode(mlp[kOffW2 + i] / scales[1]);
+  }
+  for (int i = t; i < 1024; i += 1024) {
+    const int r = i >> 6, c = i & 63;
+    W3[i] = to_bf16(mlp[kOffW3 + i]);
+    w8[8192 + i] = (uint8_t)e4m3_encode(mlp[kOffW3 + i] / scales[2]);
+    W3t[c * 32 + r] = to_bf16(mlp[kOffW3 + i]);
+    W3t[c * 32 + 16 + r] = to_bf16(0.0f);
+  }
+}
+
+// ---- training batch selection: k-th sample = record floor((k + u) n / B) ----------------
+
+__global__ void k_select_batch(const float4* trec, const uint32_t* count, uint32_t cap, const float4* hitpos,
+                               const float4* hitnrm, float u, uint32_t B, float4* batch, float* acc) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t n = *count;
+  if (n > cap) n = cap;
+  if (k == 0) acc[7] = (float)n;
+  if (k >= B) return;
+  if (n == 0) {
+    batch[3 * k] = batch[3 * k + 1] = batch[3 * k + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  uint32_t r = (uint32_t)(((double)k + (double)u) * (double)n / (double)B);
+  if (r >= n) r = n - 1u;
+  const float4 t = trec[r];
+  const uint32_t gid = __float_as_uint(t.w);
+  batch[3 * k] = hitpos[gid];
+  batch[3 * k + 1] = hitnrm[gid];
+  batch[3 * k + 2] = make_float4(t.x, t.y, t.z, 1.0f);
+}
+
+// ---- fused training forward + backward, one wave per 32-sample group -------------------
+
+struct TrainSmem {
+  __bf16 X[32 * kLd64], Xt[64 * kLd32];
+  __bf16 H1[32 * kLd64], H1t[64 * kLd32];
+  __bf16 H2[32 * kLd64], H2t[64 * kLd32];
+  __bf16 dY[32 * kLd32], dYt[16 * kLd32];
+  __bf16 dZ2[32 * kLd64], dZ2t[64 * kLd32];
+  __bf16 dZ1[32 * kLd64], dZ1t[64 * kLd32];
+  float dX[32 * 33];
+  float4 tgt[32];
+};
+
+// store a 16x16 accumulator tile (rows r0.., cols c0..) as bf16 into M[row][ld] and Mt[col][ldt]
+__device__ inline void store_tile(const f32x4_t& v, __bf16* M, int ld, __bf16* Mt, int ldt, int r0, int c0) {
+  const int lane = threadIdx.x & 63;
+  const int col = c0 + (lane & 15), rb = r0 + 4 * (lane >> 4);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const __bf16 b = to_bf16(v[i]);
+    M[(rb + i) * ld + col] = b;
+    Mt[col * ldt + rb + i] = b;
+  }
+}
+
+__device__ inline void atomic_max_abs(float* p, float v) {
+  atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
+}
+
+__global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* batch, uint32_t B, const __half* grid_h,
+                                              float* grid_g, const __bf16* wb, float loss_scale, float* part,
+                                              float* acc, float* amax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TrainSmem& S = *reinterpret_cast<TrainSmem*>(smem_raw);
+  const int lane = threadIdx.x;
+  const __bf16* W1 = wb;
+  const __bf16* W1t = wb + 4096;
+  const __bf16* W2 = wb + 8192;
+  const __bf16* W2t = wb + 12288;
+  const __bf16* W3 = wb + 16384;
+  const __bf16* W3t = wb + 16384 + 1024;
+  const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
+  f32x4_t g1[4][4], g2[4][4], g3[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    g3[a] = z4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) g1[a][b] = g2[a][b] = z4;
+  }
+  const uint32_t groups = B / 32u;
+  const float inv3b = 1.0f / (3.0f * (float)B);
+  float loss = 0.0f;
+  bool bad = false;
+  float ax = 0.f, ah1 = 0.f, ah2 = 0.f;
+  const int s = lane & 31, half_ = lane >> 5;
+  for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    // -- encoding: lane = (sample s, levels 8*half_ .. 8*half_+7)
+    const float4 pos = batch[3 * (32 * g + s)];
+    const float4 nrm = batch[3 * (32 * g + s) + 1];
+    if (lane < 32) S.tgt[s] = batch[3 * (32 * g + s) + 2];
+    float x0, x1, x2;
+    norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
+    for (int k = 0; k < 8; ++k) {
+      const int l = 8 * half_ + k;
+      float f0 = 0.f, f1 = 0.f;
+      if (l < (int)lp.L) {
+        Corners cn;
+        level_corners(lp, l, x0, x1, x2, cn);
+        const __half2* tab = reinterpret_cast<const __half2*>(grid_h) + (size_t)l * lp.T;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const float2 v = __half22float2(tab[cn.idx[c]]);
+          f0 = f0 + cn.w[c] * v.x;
+          f1 = f1 + cn.w[c] * v.y;
+        }
+      }
+      const __bf16 b0 = to_bf16(f0), b1 = to_bf16(f1);
+      S.X[s * kLd64 + 2 * l] = b0;
+      S.X[s * kLd64 + 2 * l + 1] = b1;
+      S.Xt[(2 * l) * kLd32 + s] = b0;
+      S.Xt[(2 * l + 1) * kLd32 + s] = b1;
+      ax = fmaxf(ax, fmaxf(fabsf(f0), fabsf(f1)));
+    }
+    // normal features, constant input, zero padding: columns 32..63 split over the 2 halves
+    for (int c = 32 + 16 * half_; c < 48 + 16 * half_; ++c) {
+      float v = 0.0f;
+      if (c == 32) v = (nrm.x + 1.0f) * 0.5f;
+      else if (c == 33) v = (nrm.y + 1.0f) * 0.5f;
+      else if (c == 34) v = (nrm.z + 1.0f) * 0.5f;
+      else if (c == 35) v = 1.0f;
+      S.X[s * kLd64 + c] = to_bf16(v);
+      S.Xt[c * kLd32 + s] = to_bf16(v);
+      ax = fmaxf(ax, fabsf(v));
+    }
+    __syncthreads();
+    // -- layer 1: Z1 = X W1^T
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_bf16(S.X + 16 * mt * kLd64, kLd64, W1 + 16 * nt * 64, 64, a);
+        a = mma_bf16(S.X + 16 * mt * kLd64 + 32, kLd64, W1 + 16 * nt * 64 + 32, 64, a);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { a[i] = fmaxf(a[i], 0.0f); ah1 = fmaxf(ah1, a[i]); }
+        store_tile(a, S.H1, kLd64, S.H1t, kLd32, 16 * mt, 16 * nt);
+      }
+    __syncthreads();
+    // -- layer 2
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_bf16(S.H1 + 16 * mt * kLd64, kLd64, W2 + 16 * nt * 64, 64, a);
+        a = mma_bf16(S.H1 + 16 * mt * kLd64 + 32, kLd64, W2 + 16 * nt * 64 + 32, 64, a);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { a[i] = fmaxf(a[i], 0.0f); ah2 = fmaxf(ah2, a[i]); }
+        store_tile(a, S.H2, kLd64, S.H2t, kLd32, 16 * mt, 16 * nt);
+      }
+    __syncthreads();
+    // -- layer 3 and the loss gradient (scaled by the loss scale)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      f32x4_t a = z4;
+      a = mma_bf16(S.H2 + 16 * mt * kLd64, kLd64, W3, 64, a);
+      a = mma_bf16(S.H2 + 16 * mt * kLd64 + 32, kLd64, W3 + 32, 64, a);
+      const int col = lane & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * mt + 4 * (lane >> 4) + i;
+        float d = 0.0f;
+        if (col < 3) {
+          const float4 t4 = S.tgt[row];
+          const float tv = col == 0 ? t4.x : (col == 1 ? t4.y : t4.z);
+          const float y = a[i];
+          const float den = y * y + 0.01f;
+          const float diff = y - tv;
+          loss += diff * diff / den;
+          d = loss_scale * (2.0f * diff / den) * inv3b;
+          if (!isfinite(d)) bad = true;
+        }
+        const __bf16 b = to_bf16(d);
+        S.dY[row * kLd32 + col] = b;
+        S.dY[row * kLd32 + 16 + col] = to_bf16(0.0f);
+        S.dYt[col * kLd32 + row] = b;
+      }
+    }
+    __syncthreads();
+    // -- dW3 += dY^T H2
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) g3[nt] = mma_bf16(S.dYt, kLd32, S.H2t + 16 * nt * kLd32, kLd32, g3[nt]);
+    // -- dH2 = dY W3 (K = 16 padded to 32), dZ2 = dH2 * [H2 > 0]
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_bf16(S.dY + 16 * mt * kLd32, kLd32, W3t + 16 * nt * 32, 32, a);
+        const int col = 16 * nt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * mt + 4 * (lane >> 4) + i;
+          if (!(from_bf16(S.H2[row * kLd64 + col]) > 0.0f)) a[i] = 0.0f;
+        }
+        store_tile(a, S.dZ2, kLd64, S.dZ2t, kLd32, 16 * mt, 16 * nt);
+      }
+    __syncthreads();
+    // -- dW2 += dZ2^T H1
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        g2[mt][nt] = mma_bf16(S.dZ2t + 16 * mt * kLd32, kLd32, S.H1t + 16 * nt * kLd32, kLd32, g2[mt][nt]);
+    // -- dH1 = dZ2 W2, dZ1 = dH1 * [H1 > 0]
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_bf16(S.dZ2 + 16 * mt * kLd64, kLd64, W2t + 16 * nt * 64, 64, a);
+        a = mma_bf16(S.dZ2 + 16 * mt * kLd64 + 32, kLd64, W2t + 16 * nt * 64 + 32, 64, a);
+        const int col = 16 * nt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * mt + 4 * (lane >> 4) + i;
+          if (!(from_bf16(S.H1[row * kLd64 + col]) > 0.0f)) a[i] = 0.0f;
+        }
+        store_tile(a, S.dZ1, kLd64, S.dZ1t, kLd32, 16 * mt, 16 * nt);
+      }
+    __syncthreads();
+    // -- dW1 += dZ1^T X
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        g1[mt][nt] = mma_bf16(S.dZ1t + 16 * mt * kLd32, kLd32, S.Xt + 16 * nt * kLd32, kLd32, g1[mt][nt]);
+    // -- dX[:, 0:32] = dZ1 W1 (encoding columns only), kept in float32
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        f32x4_t a = z4;
+        a = mma_bf16(S.dZ1 + 16 * mt * kLd64, kLd64, W1t + 16 * nt * 64, 64, a);
+        a = mma_bf16(S.dZ1 + 16 * mt * kLd64 + 32, kLd64, W1t + 16 * nt * 64 + 32, 64, a);
+        const int col = 16 * nt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * mt + 4 * (lane >> 4) + i;
+          S.dX[row * 33 + col] = a[i];
+          if (!isfinite(a[i])) bad = true;
+        }
+      }
+    __syncthreads();
+    // -- encoding backward: scatter w * dX into the level tables
+    for (int k = 0; k < 8; ++k) {
+      const int l = 8 * half_ + k;
+      if (l >= (int)lp.L) break;
+      Corners cn;
+      level_corners(lp, l, x0, x1, x2, cn);
+      const float d0 = S.dX[s * 33 + 2 * l], d1 = S.dX[s * 33 + 2 * l + 1];
+      float* gl = grid_g + (size_t)l * lp.T * 2u;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (d0 != 0.0f) atomicAdd(&gl[2u * cn.idx[c]], cn.w[c] * d0);
+        if (d1 != 0.0f) atomicAdd(&gl[2u * cn.idx[c] + 1u], cn.w[c] * d1);
+      }
+    }
+    __syncthreads();
+  }
+  // per-wave weight-gradient partials (C layout: row 4*(lane/16)+i, column lane%16 of a tile)
+  float* pw = part + (size_t)blockIdx.x * kMlpParams;
+  const int col = lane & 15, rb = 4 * (lane >> 4);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        pw[kOffW1 + (16 * mt + rb + i) * 64 + 16 * nt + col] = g1[mt][nt][i];
+        pw[kOffW2 + (16 * mt + rb + i) * 64 + 16 * nt + col] = g2[mt][nt][i];
+      }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pw[kOffW3 + (rb + i) * 64 + 16 * nt + col] = g3[nt][i];
+  // loss, non-finite flag and activation ranges
+  for (int o = 32; o >= 1; o >>= 1) {
+    loss += __shfl_xor(loss, o, 64);
+    ax = fmaxf(ax, __shfl_xor(ax, o, 64));
+    ah1 = fmaxf(ah1, __shfl_xor(ah1, o, 64));
+    ah2 = fmaxf(ah2, __shfl_xor(ah2, o, 64));
+  }
+  const bool any_bad = __ballot(bad) != 0;
+  if (lane == 0) {
+    atomicAdd(&acc[0], loss * inv3b);
+    if (any_bad) acc[1] = 1.0f;
+    atomic_max_abs(&amax[0], ax);
+    atomic_max_abs(&amax[1], ah1);
+    atomic_max_abs(&amax[2], ah2);
+  }
+}
+
+// deterministic sum of the per-wave partials (fixed order) -> gradient; flags non-finite
+__global__ void k_reduce_mlp(const float* part, uint32_t waves, float* g, float* acc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kMlpParams) return;
+  float s = 0.0f;
+  for (uint32_t w = 0; w < waves; ++w) s += part[(size_t)w * kMlpParams + i];
+  g[i] = s;
+  if (!isfinite(s)) acc[1] = 1.0f;
+}
+
+// Adam on the unscaled gradient; the whole step is skipped when any gradient is non-finite
+struct AdamArgs {
+  float lr, eps, b1, b2, c1, c2, inv_scale;
+};
+
+__global__ void k_adam_grid(float* p, __half* ph, const float* g, float* m, float* v, uint64_t n, AdamArgs a,
+                            const float* acc) {
+  if (acc[1] != 0.0f) return;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i] * a.inv_scale;
+  const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+  const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / a.c1, vh = vi / a.c2;
+  const float np_ = p[i] - a.lr * mh / (sqrtf(vh) + a.eps);
+  p[i] = np_;
+  ph[i] = __float2half(np_);
+}
+
+__global__ void k_adam_mlp(float* p, const float* g, float* m, float* v, AdamArgs a, const float* acc) {
+  if (acc[1] != 0.0f) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kMlpParams) return;
+  const float gi = g[i] * a.inv_scale;
+  const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+  const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] = p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+}
+
+__global__ void k_learned_copy_half(const float* p, __half* h, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) h[i] = __float2half(p[i]);
+}
+
+__global__ void k_zero_f32(float* p, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+// ---- inference: one wave evaluates 64 points (4 row tiles) ------------------------------
+
+struct InferSmem {
+  __bf16 A[64 * kLd64];
+  __bf16 B[64 * kLd64];
+  uint8_t A8[64 * 80];
+  uint8_t B8[64 * 80];
+};
+
+template <bool FP8, bool HITLIST>
+__global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* grid_h, const __bf16* wb,
+                                              const uint8_t* w8, const float* scales, const float4* pos,
+                                              const float4* nrm, uint32_t n, const uint32_t* list_ids,
+                                              const uint32_t* list_count, uint32_t stripe_cap,
+                                              uint32_t blocks_per_stripe, float4* out) {
+  __shared__ __align__(16) InferSmem S;
+  const int lane = threadIdx.x;
+  uint32_t item, oidx;
+  bool valid;
+  if (HITLIST) {
+    const uint32_t stripe = blockIdx.x / blocks_per_stripe;
+    item = (blockIdx.x % blocks_per_stripe) * 64u + lane;
+    valid = stripe < kStatStripes && item < list_count[stripe];
+    oidx = valid ? list_ids[stripe * stripe_cap + item] : 0u;
+  } else {
+    item = blockIdx.x * 64u + lane;
+    valid = item < n;
+    oidx = item;
+  }
+  if (__ballot(valid) == 0) return;
+  float4 p4 = make_float4(0.f, 0.f, 0.f, 0.f), n4 = p4;
+  if (valid) {
+    p4 = pos[oidx];
+    n4 = nrm[oidx];
+  }
+  float x0, x1, x2;
+  norm_pos(lp, p4.x, p4.y, p4.z, x0, x1, x2);
+  // encoding + inputs of this lane's row
+  float feat[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) feat[c] = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (l < (int)lp.L) {
+      Corners cn;
+      level_corners(lp, l, x0, x1, x2, cn);
+      const __half2* tab = reinterpret_cast<const __half2*>(grid_h) + (size_t)l * lp.T;
+      float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float2 v = __half22float2(tab[cn.idx[c]]);
+        f0 = f0 + cn.w[c] * v.x;
+        f1 = f1 + cn.w[c] * v.y;
+      }
+      feat[2 * l] = f0;
+      feat[2 * l + 1] = f1;
+    }
+  }
+  feat[32] = (n4.x + 1.0f) * 0.5f;
+  feat[33] = (n4.y + 1.0f) * 0.5f;
+  feat[34] = (n4.z + 1.0f) * 0.5f;
+  feat[35] = 1.0f;
+  const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
+  float y0 = 0.f, y1 = 0.f, y2 = 0.f;
+  if (!FP8) {
+#pragma unroll
+    for (int c = 0; c < 64; ++c) S.A[lane * kLd64 + c] = to_bf16(feat[c]);
+    __syncthreads();
+    const __bf16* W1 = wb;
+    const __bf16* W2 = wb + 8192;
+    const __bf16* W3 = wb + 16384;
+    // layer 1 -> B, layer 2 -> A, layer 3 -> registers
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_bf16(S.A + 16 * mt * kLd64, kLd64, W1 + 16 * nt * 64, 64, a);
+        a = mma_bf16(S.A + 16 * mt * kLd64 + 32, kLd64, W1 + 16 * nt * 64 + 32, 64, a);
+        const int col = 16 * nt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S.B[(16 * mt + 4 * (lane >> 4) + i) * kLd64 + col] = to_bf16(fmaxf(a[i], 0.0f));
+      }
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_bf16(S.B + 16 * mt * kLd64, kLd64, W2 + 16 * nt * 64, 64, a);
+        a = mma_bf16(S.B + 16 * mt * kLd64 + 32, kLd64, W2 + 16 * nt * 64 + 32, 64, a);
+        const int col = 16 * nt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S.A[(16 * mt + 4 * (lane >> 4) + i) * kLd64 + col] = to_bf16(fmaxf(a[i], 0.0f));
+      }
+    __syncthreads();
+    float* yo = reinterpret_cast<float*>(S.B);   // [64][4] outputs
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4_t a = z4;
+      a = mma_bf16(S.A + 16 * mt * kLd64, kLd64, W3, 64, a);
+      a = mma_bf16(S.A + 16 * mt * kLd64 + 32, kLd64, W3 + 32, 64, a);
+      const int col = lane & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (col < 3) yo[(16 * mt + 4 * (lane >> 4) + i) * 4 + col] = a[i];
+    }
+    __syncthreads();
+    y0 = yo[lane * 4];
+    y1 = yo[lane * 4 + 1];
+    y2 = yo[lane * 4 + 2];
+  } else {
+    // per-tensor scaled e4m3 operands, float32 accumulation, dequantise by s_x * s_w
+    const float sx = scales[6], s1 = scales[7], s2 = scales[8];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) S.A8[lane * 80 + c] = (uint8_t)e4m3_encode(feat[c] / sx);
+    __syncthreads();
+    const uint8_t* W1 = w8;
+    const uint8_t* W2 = w8 + 4096;
+    const uint8_t* W3 = w8 + 8192;
+    const float d1 = sx * scales[0], d2 = s1 * scales[1], d3 = s2 * scales[2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_fp8(S.A8 + 16 * mt * 80, 80, W1 + 16 * nt * 64, 64, a);
+        a = mma_fp8(S.A8 + 16 * mt * 80 + 32, 80, W1 + 16 * nt * 64 + 32, 64, a);
+        const int col = 16 * nt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          S.B8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_encode(fmaxf(a[i] * d1, 0.0f) / s1);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4_t a = z4;
+        a = mma_fp8(S.B8 + 16 * mt * 80, 80, W2 + 16 * nt * 64, 64, a);
+        a = mma_fp8(S.B8 + 16 * mt * 80 + 32, 80, W2 + 16 * nt * 64 + 32, 64, a);
+        const int col = 16 * nt + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          S.A8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_encode(fmaxf(a[i] * d2, 0.0f) / s2);
+      }
+    __syncthreads();
+    float* yo = reinterpret_cast<float*>(S.B);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4_t a = z4;
+      a = mma_fp8(S.A8 + 16 * mt * 80, 80, W3, 64, a);
+      a = mma_fp8(S.A8 + 16 * mt * 80 + 32, 80, W3 + 32, 64, a);
+      const int col = lane & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (col < 3) yo[(16 * mt + 4 * (lane >> 4) + i) * 4 + col] = a[i] * d3;
+    }
+    __syncthreads();
+    y0 = yo[lane * 4];
+    y1 = yo[lane * 4 + 1];
+    y2 = yo[lane * 4 + 2];
+  }
+  if (valid) out[oidx] = make_float4(fmaxf(y0, 0.0f), fmaxf(y1, 0.0f), fmaxf(y2, 0.0f), 1.0f);
+}
+
+// activation scales for e4m3 inference from the last training batch's amax
+__global__ void k_act_scales(float* scales) {
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      const float a = scales[3 + k];
+      scales[6 + k] = a > 0.0f ? a / 448.0f : 1.0f;
+    }
+  }
+}
+
+// judge: relative error of the surrogate against confident plain cells (hits whose cell has
+// at least 64 history samples)
+__global__ void k_judge(const uint32_t* ids, const uint32_t* count, uint32_t stripe_cap, uint32_t blocks_per_stripe,
+                        const uint4* rec, const uint2* meta, const float4* L, const float4* lmlp, float* acc) {
+  const uint32_t stripe = blockIdx.x / blocks_per_stripe;
+  const uint32_t item = (blockIdx.x % blocks_per_stripe) * blockDim.x + threadIdx.x;
+  float dn = 0.f, dd = 0.f;
+  if (stripe < kStatStripes && item < count[stripe]) {
+    const uint32_t gid = ids[stripe * stripe_cap + item];
+    const int32_t slot = (int32_t)rec[gid].x;
+    if (slot >= 0 && meta[slot].x >= 64u) {
+      const float4 a = lmlp[gid], b = L[slot];
+      dn = fabsf(a.x - b.x) + fabsf(a.y - b.y) + fabsf(a.z - b.z);
+      dd = fabsf(b.x) + fabsf(b.y) + fabsf(b.z);
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    dn += __shfl_xor(dn, o, 64);
+    dd += __shfl_xor(dd, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && (dn != 0.f || dd != 0.f)) {
+    atomicAdd(&acc[2], dn);
+    atomicAdd(&acc[3], dd);
+  }
+}
+
+__global__ void k_judge_decide(float* acc, float threshold, unsigned long long* stats) {
+  if (threadIdx.x != 0) return;
+  const float err = acc[3] > 0.0f ? acc[2] / acc[3] : 0.0f;
+  acc[6] = err;
+  const bool fb = acc[3] > 0.0f && err > threshold;
+  acc[4] = fb ? 1.0f : 0.0f;
+  if (fb) stats[GI_STAT_MLP_FALLBACK] += 1ull;
+  acc[2] = 0.0f;
+  acc[3] = 0.0f;
+}
+
+__global__ void k_train_begin(float* acc, float* scales) {
+  if (threadIdx.x == 0) {
+    acc[0] = 0.0f;
+    acc[1] = 0.0f;
+    scales[3] = scales[4] = scales[5] = 0.0f;
+  }
+}
+
+__global__ void k_train_end(float* acc, unsigned long long* stats) {
+  if (threadIdx.x == 0) {
+    acc[5] = acc[0];
+    if (acc[1] != 0.0f) stats[GI_STAT_MLP_SKIPPED] += 1ull;
+  }
+}
+
+// ---- host side -----------------------------------------------------------------------------
+
+static inline uint32_t nblk(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
+
+template <typename T>
+static hipError_t lalloc(T** p, size_t n) {
+  *p = nullptr;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (n ? n : 1));
+}
+
 hipError_t learned_create(gi_context* c) {
-  c->learned = nullptr;
-  return hipErrorNotSupported;
+  LearnedState* s = new LearnedState();
+  c->learned = s;
+  const gi_config& g = c->cfg;
+  LearnedParams& lp = s->lp;
+  lp.L = g.mlp_levels ? g.mlp_levels : 16u;
+  if (lp.L > (uint32_t)kMaxLevels) lp.L = kMaxLevels;
+  const uint32_t tl = g.mlp_table_log2 ? g.mlp_table_log2 : 19u;
+  lp.T = 1u << (tl > 24 ? 24 : tl);
+  const double nmin = 16.0, nmax = 4096.0;
+  const double lb = lp.L > 1 ? (std::log(nmax) - std::log(nmin)) / (double)(lp.L - 1) : 0.0;
+  lp.dense_mask = 0;
+  for (uint32_t l = 0; l < (uint32_t)kMaxLevels; ++l) {
+    const double N = l < lp.L ? std::floor(nmin * std::exp((double)l * lb) + 1e-6) : 1.0;
+    lp.res[l] = (float)N;
+    if (l < lp.L && (N + 1.0) * (N + 1.0) * (N + 1.0) <= (double)lp.T) lp.dense_mask |= 1u << l;
+  }
+  for (int a = 0; a < 3; ++a) {
+    lp.lo[a] = 0.0f;
+    lp.ext[a] = 1.0f;
+  }
+  s->grid_n = lp.L * lp.T * 2u;
+  s->B = 1u << (g.mlp_batch_log2 ? (g.mlp_batch_log2 > 20 ? 20 : g.mlp_batch_log2) : 16u);
+  if (s->B < 32) s->B = 32;
+  s->train_waves = 512;
+  const size_t PR = (size_t)c->P * c->R;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+  A(lalloc(&s->grid, s->grid_n));
+  A(lalloc(&s->grid_h, s->grid_n));
+  A(lalloc(&s->grid_g, s->grid_n));
+  A(lalloc(&s->grid_m, s->grid_n));
+  A(lalloc(&s->grid_v, s->grid_n));
+  A(lalloc(&s->mlp, kMlpParams));
+  A(lalloc(&s->mlp_g, kMlpParams));
+  A(lalloc(&s->mlp_m, kMlpParams));
+  A(lalloc(&s->mlp_v, kMlpParams));
+  A(lalloc(&s->mlp_part, (size_t)s->train_waves * kMlpParams));
+  A(lalloc(&s->wb, 16384 + 1024 + 2048));
+  A(lalloc(&s->w8, kMlpParams));
+  A(lalloc(&s->scales, 16));
+  A(lalloc(&s->hitpos, PR));
+  A(lalloc(&s->hitnrm, PR));
+  A(lalloc(&s->trec, PR));
+  A(lalloc(&s->trec_count, 1));
+  A(lalloc(&s->batch, 3 * (size_t)s->B));
+  A(lalloc(&s->lmlp, PR));
+  A(lalloc(&s->acc, 16));
+  if (e != hipSuccess) return e;
+  A(hipMemset(s->grid_g, 0, 4 * (size_t)s->grid_n));
+  A(hipMemset(s->grid_m, 0, 4 * (size_t)s->grid_n));
+  A(hipMemset(s->grid_v, 0, 4 * (size_t)s->grid_n));
+  A(hipMemset(s->mlp_m, 0, 4 * kMlpParams));
+  A(hipMemset(s->mlp_v, 0, 4 * kMlpParams));
+  A(hipMemset(s->mlp_g, 0, 4 * kMlpParams));
+  A(hipMemset(s->scales, 0, 64));
+  A(hipMemset(s->acc, 0, 64));
+  A(hipMemset(s->trec_count, 0, 4));
+  A(hipMemset(s->lmlp, 0, 16 * PR));
+  if (e != hipSuccess) return e;
+  const uint64_t n = std::max<uint64_t>(s->grid_n, kMlpParams);
+  k_learned_init<<<nblk(n, 256), 256>>>(s->grid, s->grid_h, lp.L, lp.T, s->mlp, g.seed);
+  k_mlp_copies<<<1, 1024>>>(s->mlp, s->wb, s->w8, s->scales);
+  {
+    // unit activation scales until the first training step measures them
+    const float one[3] = {1.0f, 1.0f, 1.0f};
+    A(hipMemcpy(s->scales + 6, one, 12, hipMemcpyHostToDevice));
+  }
+  A(hipGetLastError());
+  A(hipDeviceSynchronize());
+  return e;
 }
+
 void learned_destroy(gi_context* c) {
-  delete c->learned;
+  LearnedState* s = c->learned;
+  if (!s) return;
+  void* ptrs[] = {s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->mlp, s->mlp_g, s->mlp_m, s->mlp_v,
+                  s->mlp_part, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->trec_count, s->batch,
+                  s->lmlp, s->acc};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete s;
   c->learned = nullptr;
 }
-hipError_t learned_train(gi_context*, hipStream_t) { return hipErrorNotSupported; }
-hipError_t learned_infer_rays(gi_context*, hipStream_t) { return hipErrorNotSupported; }
-hipError_t learned_query(gi_context*, const float4*, const float4*, uint32_t, float4*, hipStream_t) {
-  return hipErrorNotSupported;
+
+void learned_set_domain(gi_context* c) {
+  LearnedState* s = c->learned;
+  if (!s) return;
+  for (int a = 0; a < 3; ++a) {
+    float lo = c->cfg.scene_min[a], hi = c->cfg.scene_max[a];
+    if (!(hi > lo)) {
+      lo = c->scene_lo[a];
+      hi = c->scene_hi[a];
+    }
+    s->lp.lo[a] = lo;
+    s->lp.ext[a] = (hi > lo) ? hi - lo : 1.0f;
+  }
 }
-size_t learned_blob_size(gi_context*) { return 0; }
-hipError_t learned_save(gi_context*, void*) { return hipErrorNotSupported; }
-hipError_t learned_load(gi_context*, const void*) { return hipErrorNotSupported; }
-void learned_stats(gi_context*, float* out8) {
-  for (int i = 0; i < 8; ++i) out8[i] = 0.0f;
+
+// one optimiser step on the batch currently in s->batch
+static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
+  LearnedState* s = c->learned;
+  const float S = c->cfg.mlp_loss_scale > 0.0f ? c->cfg.mlp_loss_scale : 1.0f;
+  k_train_begin<<<1, 64, 0, st>>>(s->acc, s->scales);
+  k_zero_f32<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid_g, s->grid_n);
+  const uint32_t groups = s->B / 32u;
+  const uint32_t waves = std::min<uint32_t>(s->train_waves, std::max<uint32_t>(groups, 1u));
+  k_zero_f32<<<nblk((uint64_t)s->train_waves * kMlpParams, 256), 256, 0, st>>>(s->mlp_part,
+                                                                              (uint64_t)s->train_waves * kMlpParams);
+  hipEvent_t ev;
+  timer_begin(c, "learned_train", st, &ev);
+  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, s->grid_h, s->grid_g, s->wb, S, s->mlp_part,
+                                                s->acc, s->scales + 3);
+  timer_end(c, "learned_train", st, ev);
+  k_reduce_mlp<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp_part, waves, s->mlp_g, s->acc);
+  if (apply) {
+    s->step += 1;
+    AdamArgs ag, am;
+    ag.b1 = am.b1 = 0.9f;
+    ag.b2 = am.b2 = 0.99f;
+    ag.c1 = am.c1 = (float)(1.0 - std::pow(0.9, (double)s->step));
+    ag.c2 = am.c2 = (float)(1.0 - std::pow(0.99, (double)s->step));
+    ag.inv_scale = am.inv_scale = 1.0f / S;
+    ag.lr = c->cfg.mlp_lr_grid;
+    ag.eps = 1e-15f;
+    am.lr = c->cfg.mlp_lr_mlp;
+    am.eps = 1e-8f;
+    timer_begin(c, "learned_adam", st, &ev);
+    k_adam_grid<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->grid_n,
+                                                      ag, s->acc);
+    k_adam_mlp<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc);
+    k_mlp_copies<<<1, 1024, 0, st>>>(s->mlp, s->wb, s->w8, s->scales);
+    k_act_scales<<<1, 64, 0, st>>>(s->scales);
+    timer_end(c, "learned_adam", st, ev);
+  }
+  k_train_end<<<1, 64, 0, st>>>(s->acc, c->d_stats);
+  return hipGetLastError();
+}
+
+hipError_t learned_train(gi_context* c, hipStream_t st) {
+  LearnedState* s = c->learned;
+  learned_set_domain(c);
+  // this frame's batch: stratified picks over the training records of the hits
+  const float u = rand_unit_host(hash_pcg(hash_pcg(hash_pcg(hash_pcg(c->cfg.seed) + c->fa.index) + 0x7FFFFFFFu) + 9u));
+  const size_t PR = (size_t)c->P * c->R;
+  k_select_batch<<<nblk(s->B, 256), 256, 0, st>>>(s->trec, s->trec_count, (uint32_t)PR, s->hitpos, s->hitnrm, u,
+                                                  s->B, s->batch, s->acc);
+  const uint32_t steps = c->cfg.mlp_steps ? c->cfg.mlp_steps : 1u;
+  for (uint32_t k = 0; k < steps; ++k) {
+    const hipError_t e = train_step(c, st, true);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t learned_step_on(gi_context* c, const float4* pos, const float4* nrm, const float4* tgt, uint32_t n,
+                           bool apply, hipStream_t st) {
+  LearnedState* s = c->learned;
+  learned_set_domain(c);
+  if (n != s->B) return hipErrorInvalidValue;
+  // batch rows: pos, nrm, target
+  hipError_t e = hipMemcpy2DAsync(s->batch, 48, pos, 16, 16, n, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch + 1, 48, nrm, 16, 16, n, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch + 2, 48, tgt, 16, 16, n, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  return train_step(c, st, apply);
+}
+
+hipError_t learned_infer_rays(gi_context* c, hipStream_t st) {
+  LearnedState* s = c->learned;
+  const uint64_t n = (uint64_t)c->P * c->R;
+  const uint32_t nb = nblk(n, 64);
+  hipEvent_t ev;
+  timer_begin(c, "learned_infer", st, &ev);
+  if (c->cfg.cache_mode == GI_CACHE_MLP_FP8)
+    k_infer<true, true><<<nb, 64, 0, st>>>(s->lp, s->grid_h, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, 0,
+                                           c->d_hit_ids, c->d_hit_count, c->hit_stripe_cap,
+                                           c->hit_blocks_per_stripe, s->lmlp);
+  else
+    k_infer<false, true><<<nb, 64, 0, st>>>(s->lp, s->grid_h, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, 0,
+                                            c->d_hit_ids, c->d_hit_count, c->hit_stripe_cap,
+                                            c->hit_blocks_per_stripe, s->lmlp);
+  timer_end(c, "learned_infer", st, ev);
+  k_judge<<<c->hit_blocks_per_stripe * kStatStripes, 64, 0, st>>>(c->d_hit_ids, c->d_hit_count, c->hit_stripe_cap,
+                                                                  c->hit_blocks_per_stripe, c->d_rec, c->tab.meta,
+                                                                  c->tab.L, s->lmlp, s->acc);
+  k_judge_decide<<<1, 64, 0, st>>>(s->acc, c->cfg.mlp_judge, c->d_stats);
+  return hipGetLastError();
+}
+
+hipError_t learned_query(gi_context* c, const float4* pos, const float4* nrm, uint32_t n, float4* out, hipStream_t st) {
+  LearnedState* s = c->learned;
+  if (n == 0) return hipSuccess;
+  learned_set_domain(c);
+  if (c->cfg.cache_mode == GI_CACHE_MLP_FP8)
+    k_infer<true, false><<<nblk(n, 64), 64, 0, st>>>(s->lp, s->grid_h, s->wb, s->w8, s->scales, pos, nrm, n, nullptr,
+                                                     nullptr, 0, 1, out);
+  else
+    k_infer<false, false><<<nblk(n, 64), 64, 0, st>>>(s->lp, s->grid_h, s->wb, s->w8, s->scales, pos, nrm, n, nullptr,
+                                                      nullptr, 0, 1, out);
+  return hipGetLastError();
+}
+
+// blob: header (16 x u32) | grid master | MLP master | grid grad | MLP grad | grid m | grid v |
+//       MLP m | MLP v      (grads are scaled by the loss scale)
+size_t learned_blob_size(gi_context* c) {
+  LearnedState* s = c->learned;
+  return 64 + 4 * ((size_t)s->grid_n * 4 + (size_t)kMlpParams * 4);
+}
+
+hipError_t learned_save(gi_context* c, void* blob) {
+  LearnedState* s = c->learned;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return e;
+  uint32_t hdr[16] = {0x47494D31u, s->lp.L, s->lp.T, (uint32_t)kMlpParams, (uint32_t)s->step, s->B, 0};
+  char* p = static_cast<char*>(blob);
+  std::memcpy(p, hdr, 64);
+  p += 64;
+  const size_t G = 4 * (size_t)s->grid_n, M = 4 * (size_t)kMlpParams;
+  const void* src[8] = {s->grid, s->mlp, s->grid_g, s->mlp_g, s->grid_m, s->grid_v, s->mlp_m, s->mlp_v};
+  const size_t sz[8] = {G, M, G, M, G, G, M, M};
+  for (int k = 0; k < 8 && e == hipSuccess; ++k) {
+    e = hipMemcpy(p, src[k], sz[k], hipMemcpyDeviceToHost);
+    p += sz[k];
+  }
+  return e;
+}
+
+hipError_t learned_load(gi_context* c, const void* blob) {
+  LearnedState* s = c->learned;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return e;
+  uint32_t hdr[16];
+  const char* p = static_cast<const char*>(blob);
+  std::memcpy(hdr, p, 64);
+  if (hdr[0] != 0x47494D31u || hdr[1] != s->lp.L || hdr[2] != s->lp.T) return hipErrorInvalidValue;
+  s->step = (int)hdr[4];
+  p += 64;
+  const size_t G = 4 * (size_t)s->grid_n, M = 4 * (size_t)kMlpParams;
+  void* dst[8] = {s->grid, s->mlp, s->grid_g, s->mlp_g, s->grid_m, s->grid_v, s->mlp_m, s->mlp_v};
+  const size_t sz[8] = {G, M, G, M, G, G, M, M};
+  for (int k = 0; k < 8 && e == hipSuccess; ++k) {
+    e = hipMemcpy(dst[k], p, sz[k], hipMemcpyHostToDevice);
+    p += sz[k];
+  }
+  if (e != hipSuccess) return e;
+  // rebuild the working copies
+  k_learned_copy_half<<<nblk(s->grid_n, 256), 256>>>(s->grid, s->grid_h, s->grid_n);
+  k_mlp_copies<<<1, 1024>>>(s->mlp, s->wb, s->w8, s->scales);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e;
+}
+
+void learned_stats(gi_context* c, float* out8) {
+  LearnedState* s = c->learned;
+  float acc[16];
+  if (hipMemcpy(acc, s->acc, 64, hipMemcpyDeviceToHost) != hipSuccess) {
+    for (int i = 0; i < 8; ++i) out8[i] = 0.0f;
+    return;
+  }
+  out8[0] = acc[5];
+  out8[1] = acc[6];
+  out8[2] = acc[4];
+  out8[3] = (float)s->step;
+  out8[4] = 0.0f;
+  out8[5] = acc[7];
+  out8[6] = 0.0f;
+  out8[7] = 0.0f;
+}
+
+// learned-mode outputs of the shading pass
+LearnedShadeOut learned_shade_out(gi_context* c) {
+  LearnedShadeOut o{};
+  LearnedState* s = c->learned;
+  if (!s) return o;
+  o.hitpos = s->hitpos;
+  o.hitnrm = s->hitnrm;
+  o.trec = s->trec;
+  o.trec_count = s->trec_count;
+  o.trec_cap = c->P * c->R;
+  return o;
+}
+
+LearnedGatherIn learned_gather_in(gi_context* c) {
+  LearnedGatherIn g{};
+  LearnedState* s = c->learned;
+  if (!s) return g;
+  g.lmlp = s->lmlp;
+  g.flags = s->acc;
+  g.meta = c->tab.meta;
+  return g;
 }
 
 }  // namespace gi

@@ -90,6 +90,7 @@ def lib():
     fn("gi_measure_traversal", st, vp, vp, vp)
     fn("gi_learned_train", st, vp, P(Frame), vp)
     fn("gi_learned_query", st, vp, vp, vp, u32, vp, vp)
+    fn("gi_learned_step", st, vp, vp, vp, vp, u32, u32, vp)
     fn("gi_cache_export", st, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
     fn("gi_cache_save", st, vp, vp, sz, P(sz))
     fn("gi_cache_load", st, vp, vp, sz)
@@ -229,6 +230,10 @@ class Context:
     def learned_query(self, pos, nrm, out, stream=None):
         self._check(lib().gi_learned_query(self.h, _ptr(pos), _ptr(nrm), pos.shape[0], _ptr(out),
                                            _stream(stream)), "gi_learned_query")
+
+    def learned_step(self, pos, nrm, target, apply=True, stream=None):
+        self._check(lib().gi_learned_step(self.h, _ptr(pos), _ptr(nrm), _ptr(target), pos.shape[0], int(apply),
+                                          _stream(stream)), "gi_learned_step")
 
     def trace_rays(self, o, d, tri, t, any_hit=False, stream=None):
         self._check(lib().gi_trace_rays(self.h, _ptr(o), _ptr(d), o.shape[0], int(any_hit), _ptr(tri),

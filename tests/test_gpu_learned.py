@@ -1,0 +1,164 @@
+"""GPU parity of the learned surrogate against its float64 oracle (oracle/learned.py):
+identical seeded initial parameters, BF16-MFMA gradients, the Adam step, BF16 and FP8
+inference, and the surrogate inside the frame loop."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import learned as OL  # noqa: E402
+from paper_2310_19855_amd import gi  # noqa: E402
+from paper_2310_19855_amd import inputs as I  # noqa: E402
+
+LEVELS, TLOG2, BLOG2, SEED = 4, 10, 8, 3
+
+
+def _ctx(mode=gi.CACHE_MLP_BF16, **kw):
+    cfg = dict(width=64, height=64, cache_mode=mode, mlp_levels=LEVELS, mlp_table_log2=TLOG2,
+               mlp_batch_log2=BLOG2, seed=SEED, mlp_loss_scale=128.0)
+    cfg.update(kw)
+    ctx = gi.Context(**cfg)
+    sc = I.room_scene()
+    ctx.build_bvh(sc)
+    lo = sc.verts.min(0)
+    hi = sc.verts.max(0)
+    return ctx, sc, lo, hi
+
+
+def _unpack(ctx, spec):
+    blob = np.frombuffer(ctx.learned_save(), np.uint8)
+    hdr = blob[:64].view(np.uint32)
+    G = spec.levels * spec.T * 2
+    M = 64 * 64 * 2 + 16 * 64
+    f = blob[64:].view(np.float32)
+    out, o = {}, 0
+    for name, n in (("grid", G), ("mlp", M), ("grid_g", G), ("mlp_g", M), ("grid_m", G), ("grid_v", G),
+                    ("mlp_m", M), ("mlp_v", M)):
+        out[name] = f[o:o + n].copy()
+        o += n
+    out["step"] = int(hdr[4])
+    return out
+
+
+def _params_from(flat_grid, flat_mlp, spec):
+    return dict(grid=flat_grid.reshape(spec.levels, spec.T, 2).astype(np.float64),
+                W1=flat_mlp[:4096].reshape(64, 64).astype(np.float64),
+                W2=flat_mlp[4096:8192].reshape(64, 64).astype(np.float64),
+                W3=flat_mlp[8192:].reshape(16, 64).astype(np.float64))
+
+
+def _samples(n, lo, hi, seed=0):
+    rng = np.random.default_rng(seed)
+    pos = np.zeros((n, 4), np.float32)
+    pos[:, :3] = rng.uniform(lo, hi, size=(n, 3))
+    nrm = np.zeros((n, 4), np.float32)
+    v = rng.normal(size=(n, 3))
+    nrm[:, :3] = v / np.linalg.norm(v, axis=1, keepdims=True)
+    tgt = np.zeros((n, 4), np.float32)
+    tgt[:, :3] = rng.uniform(0.1, 2.0, size=(n, 3))
+    return pos, nrm, tgt
+
+
+def _cos(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def test_initial_parameters_match_the_oracle_bit_for_bit():
+    ctx, sc, lo, hi = _ctx()
+    spec = OL.Spec(levels=LEVELS, table_log2=TLOG2)
+    st = _unpack(ctx, spec)
+    ref = OL.init_params(spec, SEED)
+    assert np.array_equal(st["grid"], ref["grid"].astype(np.float32).ravel())
+    mlp_ref = np.concatenate([ref["W1"].ravel(), ref["W2"].ravel(), ref["W3"].ravel()]).astype(np.float32)
+    assert np.array_equal(st["mlp"], mlp_ref)
+
+
+def test_gradients_and_adam_step_match_the_oracle():
+    ctx, sc, lo, hi = _ctx()
+    spec = OL.Spec(levels=LEVELS, table_log2=TLOG2)
+    B = 1 << BLOG2
+    pos, nrm, tgt = _samples(B, lo, hi)
+    tp, tn, tt = (torch.from_numpy(a).cuda() for a in (pos, nrm, tgt))
+    ctx.learned_step(tp, tn, tt, apply=False)
+    torch.cuda.synchronize()
+    st = _unpack(ctx, spec)
+    params = OL.init_params(spec, SEED)
+    x32 = OL.normalize_pos(pos[:, :3], lo, hi)
+    loss, g = OL.loss_and_grads(spec, params, x32, nrm[:, :3], tgt[:, :3])
+    S = 128.0
+    gg = st["grid_g"].reshape(spec.levels, spec.T, 2) / S
+    gm = st["mlp_g"] / S
+    gW1, gW2, gW3 = gm[:4096].reshape(64, 64), gm[4096:8192].reshape(64, 64), gm[8192:].reshape(16, 64)
+    # BF16 operands with FP32 accumulation: direction and scale of every gradient block
+    for got, ref in ((gW1, g["W1"]), (gW2, g["W2"]), (gW3, g["W3"]), (gg, g["grid"])):
+        assert _cos(got, ref) > 0.995, _cos(got, ref)
+        assert abs(np.linalg.norm(got) / np.linalg.norm(ref) - 1) < 0.03
+    assert abs(ctx.learned_stats()["loss"] - loss) / loss < 0.02
+    # the Adam step (gradients recomputed on the same batch): first step is -lr * sign(g)
+    ctx.learned_step(tp, tn, tt, apply=True)
+    torch.cuda.synchronize()
+    st2 = _unpack(ctx, spec)
+    assert st2["step"] == 1
+    d_grid = st2["grid"] - st["grid"]
+    big = np.abs(g["grid"].ravel()) > 1e-3 * np.abs(g["grid"]).max()
+    assert (np.sign(d_grid[big]) == -np.sign(g["grid"].ravel()[big])).mean() > 0.99
+    assert np.allclose(np.abs(d_grid[big]), 1e-2, rtol=1e-2)
+    d_mlp = st2["mlp"] - st["mlp"]
+    gref = np.concatenate([g["W1"].ravel(), g["W2"].ravel(), g["W3"].ravel()])
+    big = np.abs(gref) > 1e-3 * np.abs(gref).max()
+    assert (np.sign(d_mlp[big]) == -np.sign(gref[big])).mean() > 0.99
+
+
+@pytest.mark.parametrize("mode,tol", [(gi.CACHE_MLP_BF16, 0.03), (gi.CACHE_MLP_FP8, 0.15)])
+def test_inference_matches_oracle_after_training_steps(mode, tol):
+    ctx, sc, lo, hi = _ctx(mode)
+    spec = OL.Spec(levels=LEVELS, table_log2=TLOG2)
+    B = 1 << BLOG2
+    params = OL.init_params(spec, SEED)
+    opt = OL.Adam(spec, params)
+    for k in range(5):
+        pos, nrm, tgt = _samples(B, lo, hi, seed=10 + k)
+        ctx.learned_step(*(torch.from_numpy(a).cuda() for a in (pos, nrm, tgt)), apply=True)
+        _, g = OL.loss_and_grads(spec, params, OL.normalize_pos(pos[:, :3], lo, hi), nrm[:, :3], tgt[:, :3])
+        opt.step(params, g)
+    qp, qn, _ = _samples(4096, lo, hi, seed=99)
+    out = torch.zeros((4096, 4), dtype=torch.float32, device="cuda")
+    ctx.learned_query(torch.from_numpy(qp).cuda(), torch.from_numpy(qn).cuda(), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[:, :3]
+    ref, _ = OL.forward(spec, params, OL.normalize_pos(qp[:, :3], lo, hi), qn[:, :3])
+    ref = np.maximum(ref, 0)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel < tol, rel
+
+
+def test_learned_frames_train_and_feed_the_probes():
+    ctx, sc, lo, hi = _ctx(gi.CACHE_MLP_BF16, width=128, height=128, rays_per_probe=16, table_log2=16,
+                           mlp_batch_log2=12, mlp_levels=8, mlp_table_log2=14, mlp_judge=10.0)
+    gb = gi.GBuffer(128, 128)
+    out = torch.zeros((128, 128, 4), dtype=torch.float32, device="cuda")
+    losses = []
+    for f in range(12):
+        fr = I.room_camera(0)
+        fr.index = f
+        ctx.render_gbuffer(fr, gb.pos, gb.nrm, gb.alb, gb.prim)
+        ctx.spawn_probes(fr, gb.pos, gb.nrm, gb.prim)
+        ctx.trace_probes(fr)
+        ctx.learned_train(fr)
+        ctx.cache_update(fr)
+        ctx.interpolate_probes(fr, gb.pos, gb.nrm, gb.prim, out)
+        losses.append(ctx.learned_stats()["loss"])
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.isfinite(o).all() and (o[..., :3] >= 0).all()
+    assert np.mean(losses[-3:]) < np.mean(losses[:2])
+    st = ctx.learned_stats()
+    assert st["steps"] == 12 and not st["fallback"]
+    # the probes see surrogate radiance: atlas values are finite and positive on average
+    pr = ctx.probes()
+    assert pr["atlas"][..., :3].mean() > 0

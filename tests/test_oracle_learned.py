@@ -98,7 +98,7 @@ def test_loss_hand_value():
     for k in ("W1", "W2", "W3", "grid"):
         p[k] = np.zeros_like(p[k])
     # y = W3 relu(W2 relu(W1 x)); make y = 0.5 on every channel via the constant input
-    p["W1"][0, 2 * s.levels + 3] = 1.0
+    p["W1"][0, 35] = 1.0
     p["W2"][0, 0] = 1.0
     p["W3"][:3, 0] = 0.5
     x = np.zeros((2, 3), np.float32)
