@@ -58,6 +58,7 @@ def main():
     ap.add_argument("--profile-frames", type=int, default=5)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the plain / MLP-BF16 / MLP-FP8 comparison")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -188,6 +189,12 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, cfg, cams, args.cpu_frames, log)
+    forms = None
+    if not args.no_forms:
+        del gbs
+        del ctx
+        torch.cuda.empty_cache()
+        forms = forms_comparison(log)
 
     line = {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
@@ -207,8 +214,139 @@ def main():
                     for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cache_forms": forms,
     }
     print(json.dumps(line), flush=True)
+
+
+FORMS = {"plain": 0, "mlp_bf16": 1, "mlp_fp8": 2}
+MLP_CFG = dict(mlp_batch_log2=16, mlp_levels=16, mlp_table_log2=19, mlp_steps=4, mlp_lr_grid=1e-2,
+               mlp_lr_mlp=1e-2, mlp_judge=0.5)
+SWEEP_R = (8, 16, 32, 64, 128)
+SWEEP_FRAMES, SWEEP_TIMED_FROM = 16, 8
+
+
+def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, profile=False):
+    """Frames of the pass with the camera and lights frozen at frame 0 (the reference's frame
+    state).  Returns GPU ms per timed frame, per-kernel ms, learned stats and, with points
+    (pos, nrm device tensors), the plain cache's lookups and the form's radiance there."""
+    import torch
+
+    from paper_2310_19855_amd import gi
+    from paper_2310_19855_amd import inputs as I
+    cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, cache_mode=FORMS[form])
+    if form != "plain":
+        cfg.update(MLP_CFG)
+    ctx = gi.Context(**cfg)
+    ctx.build_bvh(scene)
+    if scene.dynamic is not None:
+        ctx.set_dynamic(*scene.dynamic(0))
+    gb = gi.GBuffer(H, W)
+    out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+    ctx.render_gbuffer(I.camera_for(scene_name, 0), gb.pos, gb.nrm, gb.alb, gb.prim)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for f in range(frames):
+        if f == timed_from:
+            torch.cuda.synchronize()
+            if profile:
+                ctx.profile(True)
+                ctx.profile_read()
+            ev0.record()
+        cam = I.camera_for(scene_name, 0)
+        cam.index = f
+        ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
+        ctx.trace_probes(cam)
+        if form != "plain":
+            ctx.learned_train(cam)
+        ctx.cache_update(cam)
+        ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, out)
+    ev1.record()
+    torch.cuda.synchronize()
+    n = max(frames - timed_from, 1)
+    ms = ev0.elapsed_time(ev1) / n
+    kern = {}
+    if profile:
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        kern = {k: round(v[1] / n, 4) for k, v in prof.items()}
+    res = {"ms": ms, "kernels": kern, "learned": ctx.learned_stats() if form != "plain" else None}
+    if points is not None:
+        pp, pn = points
+        q = torch.zeros((pp.shape[0], 4), dtype=torch.float32, device="cuda")
+        ctx.cache_query(pp, pn, q)
+        res["plain_at_points"] = q.cpu().numpy()
+        if form != "plain":
+            ctx.learned_query(pp, pn, q)
+            res["form_at_points"] = q.cpu().numpy()
+        else:
+            res["form_at_points"] = res["plain_at_points"]
+        torch.cuda.synchronize()
+    ctx.close()
+    return res
+
+
+def forms_comparison(log, W=1920, H=1080):
+    """Plain vs learned cache forms at equal relative radiance error.  For each scene with a
+    stored float64 reference (the oracle converged at seeded visible surface points), each
+    form and each rays-per-probe R: 16 frames with the frame-0 camera and lights, GPU time of
+    frames 8..15, then the relative mean absolute error of the form's radiance at the points
+    whose cell the plain cache holds at that R.  Reported: the cheapest R (and its ms/frame)
+    with error <= 5% per form, and at the lowest error level every form reaches."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19855_amd import inputs as I
+    out = {"protocol": f"{W}x{H}, frames 0..{SWEEP_FRAMES - 1} with the frame-0 camera and lights, "
+                       f"ms/frame over frames {SWEEP_TIMED_FROM}..{SWEEP_FRAMES - 1}; relMAE of the cache "
+                       "radiance at seeded visible surface points vs the float64 oracle's converged NEE "
+                       "radiance there, over the points whose cell the plain cache holds",
+           "mlp": dict(MLP_CFG), "scenes": {}}
+    for scene_name in ("room", "field"):
+        path = os.path.join(ROOT, "tests", "golden", f"{scene_name}480x270_reference.npz")
+        if not os.path.exists(path):
+            continue
+        ref = np.load(path)
+        scene = I.make_scene(scene_name)
+        pts = (torch.from_numpy(ref["point_pos"]).cuda(), torch.from_numpy(ref["point_nrm"]).cuda())
+        Lr = ref["point_L"].astype(np.float64)
+        table = {}
+        for form in FORMS:
+            table[form] = {}
+            for R in SWEEP_R:
+                r = run_form(scene_name, scene, W, H, R, form, SWEEP_FRAMES, SWEEP_TIMED_FROM, points=pts,
+                             profile=(R == 64))
+                found = r["plain_at_points"][:, 3] > 0
+                L = r["form_at_points"][found, :3].astype(np.float64)
+                e = float(np.abs(L - Lr[found]).sum() / max(np.abs(Lr[found]).sum(), 1e-30))
+                row = {"ms_per_frame": round(r["ms"], 4), "relMAE": round(e, 5), "points": int(found.sum())}
+                if r["kernels"]:
+                    row["kernels_ms"] = r["kernels"]
+                if r["learned"]:
+                    row["loss"] = round(r["learned"]["loss"], 5)
+                    row["fallback"] = r["learned"]["fallback"]
+                table[form][R] = row
+            log(f"[bench] {scene_name} {form}: " + ", ".join(
+                f"R={R} {v['relMAE']:.3f} @ {v['ms_per_frame']:.2f}ms" for R, v in table[form].items()))
+
+        def cheapest(form, level):
+            ok = [(v["ms_per_frame"], R) for R, v in table[form].items() if v["relMAE"] <= level]
+            if not ok:
+                return None
+            ms, R = min(ok)
+            return {"rays_per_probe": R, "ms_per_frame": ms, "relMAE": table[form][R]["relMAE"]}
+        common = max(min(v["relMAE"] for v in table[f].values()) for f in FORMS)
+        out["scenes"][scene_name] = {
+            "sweep": table,
+            "reference": f"{len(Lr)} points, {int(ref['point_samples'])} NEE samples each, relative "
+                         f"standard error {float(ref['point_se'].sum() / ref['point_L'].sum()):.4f}",
+            "equal_error_5pct": {f: cheapest(f, 0.05) for f in FORMS},
+            "equal_error_common": {"level": round(common, 5), **{f: cheapest(f, common) for f in FORMS}},
+        }
+        log(f"[bench] {scene_name} equal error at {common:.3f}: " + ", ".join(
+            f"{f} {v['ms_per_frame']:.2f}ms (R={v['rays_per_probe']})"
+            for f, v in out["scenes"][scene_name]["equal_error_common"].items() if isinstance(v, dict)))
+    return out
 
 
 def cpu_baseline(scene, cfg, cams, frames, log):

@@ -933,13 +933,15 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
 hipError_t learned_train(gi_context* c, hipStream_t st) {
   LearnedState* s = c->learned;
   learned_set_domain(c);
-  // this frame's batch: stratified picks over the training records of the hits
-  const float u = rand_unit_host(hash_pcg(hash_pcg(hash_pcg(hash_pcg(c->cfg.seed) + c->fa.index) + 0x7FFFFFFFu) + 9u));
+  // each step's batch: stratified picks over this frame's training records, with a fresh
+  // offset per step so that steps see different hits when there are more hits than picks
   const size_t PR = (size_t)c->P * c->R;
-  k_select_batch<<<nblk(s->B, 256), 256, 0, st>>>(s->trec, s->trec_count, (uint32_t)PR, s->hitpos, s->hitnrm, u,
-                                                  s->B, s->batch, s->acc);
   const uint32_t steps = c->cfg.mlp_steps ? c->cfg.mlp_steps : 1u;
   for (uint32_t k = 0; k < steps; ++k) {
+    const float u = rand_unit_host(
+        hash_pcg(hash_pcg(hash_pcg(hash_pcg(c->cfg.seed) + c->fa.index) + 0x7FFFFFFFu) + 9u + k));
+    k_select_batch<<<nblk(s->B, 256), 256, 0, st>>>(s->trec, s->trec_count, (uint32_t)PR, s->hitpos, s->hitnrm,
+                                                    u, s->B, s->batch, s->acc);
     const hipError_t e = train_step(c, st, true);
     if (e != hipSuccess) return e;
   }

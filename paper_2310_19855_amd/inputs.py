@@ -462,3 +462,4 @@ def query_points(n: int, lo, hi, seed: int = 11):
     nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
     nrm = np.concatenate([nrm, np.zeros((n, 1))], 1)
     return p.astype(np.float32), nrm.astype(np.float32)
+

@@ -54,3 +54,4 @@ class Pair:
         self.ctx.render_gbuffer(fr, self.gb.pos, self.gb.nrm, self.gb.alb, self.gb.prim)
         torch.cuda.synchronize()
         return self.gb.host(), self.osc.gbuffer(fr, self.W, self.H)
+

@@ -162,3 +162,59 @@ def test_learned_frames_train_and_feed_the_probes():
     # the probes see surrogate radiance: atlas values are finite and positive on average
     pr = ctx.probes()
     assert pr["atlas"][..., :3].mean() > 0
+
+
+def _run_frames(scene, sc, W, H, R, frames, mode, **kw):
+    ctx = gi.Context(width=W, height=H, rays_per_probe=R, table_log2=20, cache_mode=mode, sky=sc.sky, **kw)
+    ctx.build_bvh(sc)
+    if sc.dynamic is not None:
+        ctx.set_dynamic(*sc.dynamic(0))           # lights frozen at frame 0, as in the reference
+    gb = gi.GBuffer(H, W)
+    out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+    ctx.render_gbuffer(I.camera_for(scene, 0), gb.pos, gb.nrm, gb.alb, gb.prim)
+    for f in range(frames):
+        fr = I.camera_for(scene, 0)
+        fr.index = f
+        ctx.spawn_probes(fr, gb.pos, gb.nrm, gb.prim)
+        ctx.trace_probes(fr)
+        if mode != gi.CACHE_PLAIN:
+            ctx.learned_train(fr)
+        ctx.cache_update(fr)
+        ctx.interpolate_probes(fr, gb.pos, gb.nrm, gb.prim, out)
+    torch.cuda.synchronize()
+    return ctx
+
+
+def test_surrogate_gain_over_plain_cache_on_the_field_scene():
+    """What the trained network gains: on the 1M-triangle field scene (five emitters, heavy
+    occlusion, so single NEE samples are noisy and most cells see few of them), after 8 frames
+    at 64 rays per probe the surrogate's radiance at visible surface points is closer to the
+    converged float64 oracle (tests/golden/field480x270_reference.npz, written by
+    oracle/make_reference.py: 16,384 NEE samples per point) than the plain cache's cell values,
+    compared on the points whose cell the plain cache holds (relative mean absolute error)."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "field480x270_reference.npz"))
+    sc = I.make_scene("field")
+    W, H = int(ref["width"]), int(ref["height"])
+    pp = torch.from_numpy(ref["point_pos"]).cuda()
+    pn = torch.from_numpy(ref["point_nrm"]).cuda()
+    Lr = ref["point_L"].astype(np.float64)
+    q = torch.zeros((len(Lr), 4), dtype=torch.float32, device="cuda")
+    plain = _run_frames("field", sc, W, H, 64, 8, gi.CACHE_PLAIN)
+    plain.cache_query(pp, pn, q)
+    torch.cuda.synchronize()
+    a = q.cpu().numpy()
+    plain.close()
+    found = a[:, 3] > 0
+    assert found.sum() > 2000
+    learned = _run_frames("field", sc, W, H, 64, 8, gi.CACHE_MLP_BF16, mlp_batch_log2=16, mlp_levels=16,
+                          mlp_table_log2=19, mlp_steps=4, mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_judge=10.0)
+    learned.learned_query(pp, pn, q)
+    torch.cuda.synchronize()
+    m = q.cpu().numpy()
+    learned.close()
+    assert np.isfinite(m).all()
+    e_plain = np.abs(a[found, :3] - Lr[found]).sum() / np.abs(Lr[found]).sum()
+    e_mlp = np.abs(m[found, :3] - Lr[found]).sum() / np.abs(Lr[found]).sum()
+    print(f"field, 8 frames at 64 rays, {found.sum()} points: relMAE plain {e_plain:.4f}, surrogate {e_mlp:.4f}")
+    assert e_mlp < 0.85 * e_plain
