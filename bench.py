@@ -220,7 +220,7 @@ def main():
 
 
 FORMS = {"plain": 0, "mlp_bf16": 1, "mlp_fp8": 2}
-MLP_CFG = dict(mlp_batch_log2=16, mlp_levels=16, mlp_table_log2=19, mlp_steps=4, mlp_lr_grid=1e-2,
+MLP_CFG = dict(mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4, mlp_lr_grid=1e-2,
                mlp_lr_mlp=1e-2, mlp_judge=0.5)
 SWEEP_R = (8, 16, 32, 64, 128)
 SWEEP_FRAMES, SWEEP_TIMED_FROM = 16, 8

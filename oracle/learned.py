@@ -71,6 +71,7 @@ class Spec:
     lr_grid: float = 1e-2
     lr_mlp: float = 1e-3
     loss_scale: float = 128.0
+    lazy_grid: bool = True      # grid entries with a zero gradient skip the step (m, v, value kept)
 
     @property
     def T(self):
@@ -193,11 +194,19 @@ class Adam:
         self.t += 1
         for k in params:
             lr, eps = (s.lr_grid, s.eps_grid) if k == "grid" else (s.lr_mlp, s.eps_mlp)
-            self.m[k] = s.beta1 * self.m[k] + (1 - s.beta1) * grads[k]
-            self.v[k] = s.beta2 * self.v[k] + (1 - s.beta2) * grads[k] ** 2
-            mh = self.m[k] / (1 - s.beta1 ** self.t)
-            vh = self.v[k] / (1 - s.beta2 ** self.t)
-            params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+            g = grads[k]
+            m = s.beta1 * self.m[k] + (1 - s.beta1) * g
+            v = s.beta2 * self.v[k] + (1 - s.beta2) * g ** 2
+            mh = m / (1 - s.beta1 ** self.t)
+            vh = v / (1 - s.beta2 ** self.t)
+            p = params[k] - lr * mh / (np.sqrt(vh) + eps)
+            if k == "grid" and s.lazy_grid:
+                # lazy form: only entries that received a gradient in this step move
+                on = g != 0
+                m = np.where(on, m, self.m[k])
+                v = np.where(on, v, self.v[k])
+                p = np.where(on, p, params[k])
+            self.m[k], self.v[k], params[k] = m, v, p
         return True
 
 

@@ -57,12 +57,15 @@ struct LearnedState {
   float4* hitnrm = nullptr;      // [P*R] face-forwarded normal
   float4* trec = nullptr;        // [P*R] training record: target rgb, w = ray id bits
   uint32_t* trec_count = nullptr;
-  float4* batch = nullptr;       // [B][3]: pos, nrm, target
+  float4* batch_raw = nullptr;   // [B][3]: pos, nrm, target as selected
+  float4* batch = nullptr;       // the same rows grouped by spatial (Morton) bucket
+  uint32_t* sort_cnt = nullptr;  // [kSortBuckets] bucket counters / offsets
   uint32_t B = 0;
   float4* lmlp = nullptr;        // [P*R] surrogate radiance at each hit
   float* acc = nullptr;          // [0] loss sum, [1] non-finite flag, [2] judge |diff|, [3] judge |plain|,
                                  // [4] fallback flag, [5] last loss, [6] last judged error, [7] batch n
   uint32_t train_waves = 0;
+  bool grad_dirty = false;       // grid_g holds a gradient-only step's result
   int step = 0, skipped = 0;
   float host_stats[8] = {0};
 };
@@ -170,8 +173,9 @@ __global__ void k_learned_init(float* grid, __half* grid_h, uint32_t L, uint32_t
   }
 }
 
-// bf16 and e4m3 working copies of the MLP weights and their per-tensor scales (one block)
-__global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* scales) {
+// bf16 and e4m3 working copies of the MLP weights and their per-tensor scales (one block of
+// 1024 threads)
+__device__ void mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* scales) {
   __shared__ float red[3][32];
   const int t = threadIdx.x;
   float am[3] = {0.f, 0.f, 0.f};
@@ -215,6 +219,10 @@ __global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* w
   }
 }
 
+__global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* scales) {
+  mlp_copies(mlp, wb, w8, scales);
+}
+
 // ---- training batch selection: k-th sample = record floor((k + u) n / B) ----------------
 
 __global__ void k_select_batch(const float4* trec, const uint32_t* count, uint32_t cap, const float4* hitpos,
@@ -235,6 +243,97 @@ __global__ void k_select_batch(const float4* trec, const uint32_t* count, uint32
   batch[3 * k] = hitpos[gid];
   batch[3 * k + 1] = hitnrm[gid];
   batch[3 * k + 2] = make_float4(t.x, t.y, t.z, 1.0f);
+}
+
+// ---- spatial order of a batch: rows grouped by a 15-bit Morton code of the normalised
+// position (32 cells per axis; counting sort: histogram, scan, scatter), so that neighbouring
+// lanes of a training wave share grid corners and their gradient atomics can be merged.  The
+// order inside a bucket is that of the scatter's atomics. -----------------------------------
+constexpr uint32_t kSortBuckets = 1u << 15;
+
+__device__ inline uint32_t spread5(uint32_t v) {
+  v &= 0x1Fu;
+  v = (v | (v << 8)) & 0x0000F00Fu;
+  v = (v | (v << 4)) & 0x000C30C3u;
+  v = (v | (v << 2)) & 0x00249249u;
+  return v;
+}
+
+__device__ inline uint32_t spread9(uint32_t v) {
+  v &= 0x1FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ inline uint32_t sort_bucket(const LearnedParams& lp, const float4& p) {
+  float x0, x1, x2;
+  norm_pos(lp, p.x, p.y, p.z, x0, x1, x2);
+  const uint32_t q0 = min((uint32_t)(x0 * 32.0f), 31u);
+  const uint32_t q1 = min((uint32_t)(x1 * 32.0f), 31u);
+  const uint32_t q2 = min((uint32_t)(x2 * 32.0f), 31u);
+  return spread5(q0) | (spread5(q1) << 1) | (spread5(q2) << 2);
+}
+
+__global__ void k_sort_count(LearnedParams lp, const float4* in, uint32_t B, uint32_t* cnt) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  atomicAdd(&cnt[sort_bucket(lp, in[3 * (size_t)i])], 1u);
+}
+
+// exclusive prefix sum of the kSortBuckets counters in place (one block of 1024 threads)
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* cnt) {
+  __shared__ uint32_t part[1024];
+  constexpr uint32_t per = kSortBuckets / 1024u;
+  const uint32_t t = threadIdx.x;
+  uint32_t v[per];
+  uint32_t sum = 0u;
+#pragma unroll
+  for (uint32_t j = 0; j < per; ++j) {
+    v[j] = cnt[t * per + j];
+    sum += v[j];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024u; d <<= 1) {
+    const uint32_t o = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += o;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+#pragma unroll
+  for (uint32_t j = 0; j < per; ++j) {
+    cnt[t * per + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ void k_sort_scatter(LearnedParams lp, const float4* in, float4* out, uint32_t B, uint32_t* off) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const float4 p = in[3 * (size_t)i];
+  const uint32_t d = atomicAdd(&off[sort_bucket(lp, p)], 1u);
+  out[3 * (size_t)d] = p;
+  out[3 * (size_t)d + 1] = in[3 * (size_t)i + 1];
+  out[3 * (size_t)d + 2] = in[3 * (size_t)i + 2];
+}
+
+__global__ void k_zero_f32(float* p, uint64_t n);
+static inline uint32_t nblk(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
+
+static hipError_t sort_batch(gi_context* c, hipStream_t st) {
+  LearnedState* s = c->learned;
+  hipEvent_t ev;
+  timer_begin(c, "learned_sort", st, &ev);
+  k_zero_f32<<<nblk(kSortBuckets, 256), 256, 0, st>>>(reinterpret_cast<float*>(s->sort_cnt), kSortBuckets);
+  k_sort_count<<<nblk(s->B, 256), 256, 0, st>>>(s->lp, s->batch_raw, s->B, s->sort_cnt);
+  k_sort_scan<<<1, 1024, 0, st>>>(s->sort_cnt);
+  k_sort_scatter<<<nblk(s->B, 256), 256, 0, st>>>(s->lp, s->batch_raw, s->batch, s->B, s->sort_cnt);
+  timer_end(c, "learned_sort", st, ev);
+  return hipGetLastError();
 }
 
 // ---- fused training forward + backward, one wave per 32-sample group -------------------
@@ -293,10 +392,31 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
   float ax = 0.f, ah1 = 0.f, ah2 = 0.f;
   const int s = lane & 31, half_ = lane >> 5;
   for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    // -- the group's 32 samples in Morton order (27-bit code, bitonic network over the lanes
+    // of each half), so that equal grid corners sit in neighbouring lanes
+    uint32_t row;
+    {
+      const float4 p0 = batch[3 * (32 * g + s)];
+      float y0, y1, y2;
+      norm_pos(lp, p0.x, p0.y, p0.z, y0, y1, y2);
+      const uint32_t code = spread9(min((uint32_t)(y0 * 512.0f), 511u)) |
+                            (spread9(min((uint32_t)(y1 * 512.0f), 511u)) << 1) |
+                            (spread9(min((uint32_t)(y2 * 512.0f), 511u)) << 2);
+      uint32_t key = (code << 5) | (uint32_t)s;
+#pragma unroll
+      for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          const uint32_t other = (uint32_t)__shfl_xor((int)key, j, 64);
+          const bool keep_min = ((s & j) == 0) == ((s & k) == 0);
+          key = keep_min ? min(key, other) : max(key, other);
+        }
+      row = 32 * g + (key & 31u);
+    }
     // -- encoding: lane = (sample s, levels 8*half_ .. 8*half_+7)
-    const float4 pos = batch[3 * (32 * g + s)];
-    const float4 nrm = batch[3 * (32 * g + s) + 1];
-    if (lane < 32) S.tgt[s] = batch[3 * (32 * g + s) + 2];
+    const float4 pos = batch[3 * row];
+    const float4 nrm = batch[3 * row + 1];
+    if (lane < 32) S.tgt[s] = batch[3 * row + 2];
     float x0, x1, x2;
     norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
     for (int k = 0; k < 8; ++k) {
@@ -451,18 +571,37 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
         }
       }
     __syncthreads();
-    // -- encoding backward: scatter w * dX into the level tables
+    // -- encoding backward: scatter w * dX into the level tables.  Lanes hold spatially
+    // sorted samples, so runs of neighbouring lanes often name the same table entry: each run
+    // is summed across lanes (segmented suffix sum) and only its first lane issues the atomics.
     for (int k = 0; k < 8; ++k) {
       const int l = 8 * half_ + k;
-      if (l >= (int)lp.L) break;
+      const bool on = l < (int)lp.L;
       Corners cn;
-      level_corners(lp, l, x0, x1, x2, cn);
-      const float d0 = S.dX[s * 33 + 2 * l], d1 = S.dX[s * 33 + 2 * l + 1];
-      float* gl = grid_g + (size_t)l * lp.T * 2u;
+      if (on) level_corners(lp, l, x0, x1, x2, cn);
+      const float d0 = on ? S.dX[s * 33 + 2 * l] : 0.0f, d1 = on ? S.dX[s * 33 + 2 * l + 1] : 0.0f;
+      float* gl = grid_g + (size_t)(on ? l : 0) * lp.T * 2u;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        if (d0 != 0.0f) atomicAdd(&gl[2u * cn.idx[c]], cn.w[c] * d0);
-        if (d1 != 0.0f) atomicAdd(&gl[2u * cn.idx[c] + 1u], cn.w[c] * d1);
+        const uint32_t a = on ? (uint32_t)l * lp.T + cn.idx[c] : 0xFFFFFFFFu;
+        float v0 = on ? cn.w[c] * d0 : 0.0f, v1 = on ? cn.w[c] * d1 : 0.0f;
+        const uint32_t prev = (uint32_t)__shfl_up((int)a, 1, 64);
+        const bool head = lane == 0 || prev != a;
+        const uint64_t heads = __ballot(head);
+        const uint32_t rid = (uint32_t)__popcll(heads & (~0ull >> (63 - lane)));
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const float o0 = __shfl_down(v0, d, 64), o1 = __shfl_down(v1, d, 64);
+          const uint32_t orid = (uint32_t)__shfl_down((int)rid, d, 64);
+          if (lane + d < 64 && orid == rid) {
+            v0 = v0 + o0;
+            v1 = v1 + o1;
+          }
+        }
+        if (on && head) {
+          if (v0 != 0.0f) atomicAdd(&gl[2u * cn.idx[c]], v0);
+          if (v1 != 0.0f) atomicAdd(&gl[2u * cn.idx[c] + 1u], v1);
+        }
       }
     }
     __syncthreads();
@@ -515,12 +654,18 @@ struct AdamArgs {
   float lr, eps, b1, b2, c1, c2, inv_scale;
 };
 
-__global__ void k_adam_grid(float* p, __half* ph, const float* g, float* m, float* v, uint64_t n, AdamArgs a,
+// Grid entries take the step only where this step's gradient is non-zero (lazy Adam: an
+// entry no sample touched keeps its value and moments).  The gradient buffer is left zeroed
+// for the next step, also when the step is skipped.
+__global__ void k_adam_grid(float* p, __half* ph, float* g, float* m, float* v, uint64_t n, AdamArgs a,
                             const float* acc) {
-  if (acc[1] != 0.0f) return;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i] * a.inv_scale;
+  const float graw = g[i];
+  if (graw == 0.0f) return;
+  g[i] = 0.0f;
+  if (acc[1] != 0.0f) return;
+  const float gi = graw * a.inv_scale;
   const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
   const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
   m[i] = mi;
@@ -531,16 +676,32 @@ __global__ void k_adam_grid(float* p, __half* ph, const float* g, float* m, floa
   ph[i] = __float2half(np_);
 }
 
-__global__ void k_adam_mlp(float* p, const float* g, float* m, float* v, AdamArgs a, const float* acc) {
-  if (acc[1] != 0.0f) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kMlpParams) return;
-  const float gi = g[i] * a.inv_scale;
-  const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
-  const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] = p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+// end of an applied step (one block of 1024 threads): Adam on the MLP weights, their bf16 and
+// e4m3 working copies, the e4m3 activation scales of the step's batch, the step's statistics
+__global__ __launch_bounds__(1024) void k_mlp_step(float* p, const float* g, float* m, float* v, AdamArgs a,
+                                                   float* acc, __bf16* wb, uint8_t* w8, float* scales,
+                                                   unsigned long long* stats) {
+  const bool skip = acc[1] != 0.0f;
+  if (!skip) {
+    for (int i = threadIdx.x; i < kMlpParams; i += 1024) {
+      const float gi = g[i] * a.inv_scale;
+      const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+      const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+      m[i] = mi;
+      v[i] = vi;
+      p[i] = p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    }
+  }
+  __syncthreads();
+  mlp_copies(p, wb, w8, scales);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      const float am = scales[3 + k];
+      scales[6 + k] = am > 0.0f ? am / 448.0f : 1.0f;
+    }
+    acc[5] = acc[0];
+    if (skip) stats[GI_STAT_MLP_SKIPPED] += 1ull;
+  }
 }
 
 __global__ void k_learned_copy_half(const float* p, __half* h, uint64_t n) {
@@ -719,16 +880,6 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
   if (valid) out[oidx] = make_float4(fmaxf(y0, 0.0f), fmaxf(y1, 0.0f), fmaxf(y2, 0.0f), 1.0f);
 }
 
-// activation scales for e4m3 inference from the last training batch's amax
-__global__ void k_act_scales(float* scales) {
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 3; ++k) {
-      const float a = scales[3 + k];
-      scales[6 + k] = a > 0.0f ? a / 448.0f : 1.0f;
-    }
-  }
-}
-
 // judge: relative error of the surrogate against confident plain cells (hits whose cell has
 // at least 64 history samples)
 __global__ void k_judge(const uint32_t* ids, const uint32_t* count, uint32_t stripe_cap, uint32_t blocks_per_stripe,
@@ -783,7 +934,6 @@ __global__ void k_train_end(float* acc, unsigned long long* stats) {
 
 // ---- host side -----------------------------------------------------------------------------
 
-static inline uint32_t nblk(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
 template <typename T>
 static hipError_t lalloc(T** p, size_t n) {
@@ -837,9 +987,13 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->trec, PR));
   A(lalloc(&s->trec_count, 1));
   A(lalloc(&s->batch, 3 * (size_t)s->B));
+  A(lalloc(&s->batch_raw, 3 * (size_t)s->B));
+  A(lalloc(&s->sort_cnt, kSortBuckets));
   A(lalloc(&s->lmlp, PR));
   A(lalloc(&s->acc, 16));
   if (e != hipSuccess) return e;
+  A(hipFuncSetAttribute(reinterpret_cast<const void*>(k_train), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)sizeof(TrainSmem)));
   A(hipMemset(s->grid_g, 0, 4 * (size_t)s->grid_n));
   A(hipMemset(s->grid_m, 0, 4 * (size_t)s->grid_n));
   A(hipMemset(s->grid_v, 0, 4 * (size_t)s->grid_n));
@@ -869,7 +1023,7 @@ void learned_destroy(gi_context* c) {
   if (!s) return;
   void* ptrs[] = {s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->mlp, s->mlp_g, s->mlp_m, s->mlp_v,
                   s->mlp_part, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->trec_count, s->batch,
-                  s->lmlp, s->acc};
+                  s->batch_raw, s->sort_cnt, s->lmlp, s->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -895,13 +1049,14 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
   LearnedState* s = c->learned;
   const float S = c->cfg.mlp_loss_scale > 0.0f ? c->cfg.mlp_loss_scale : 1.0f;
   k_train_begin<<<1, 64, 0, st>>>(s->acc, s->scales);
-  k_zero_f32<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid_g, s->grid_n);
+  // the applied step's grid Adam leaves the gradient zeroed; a gradient-only step does not
+  if (s->grad_dirty) k_zero_f32<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid_g, s->grid_n);
+  s->grad_dirty = false;
   const uint32_t groups = s->B / 32u;
   const uint32_t waves = std::min<uint32_t>(s->train_waves, std::max<uint32_t>(groups, 1u));
-  k_zero_f32<<<nblk((uint64_t)s->train_waves * kMlpParams, 256), 256, 0, st>>>(s->mlp_part,
-                                                                              (uint64_t)s->train_waves * kMlpParams);
   hipEvent_t ev;
   timer_begin(c, "learned_train", st, &ev);
+  // every launched wave writes its whole partial, so the partials need no clearing
   k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, s->grid_h, s->grid_g, s->wb, S, s->mlp_part,
                                                 s->acc, s->scales + 3);
   timer_end(c, "learned_train", st, ev);
@@ -921,12 +1076,13 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
     timer_begin(c, "learned_adam", st, &ev);
     k_adam_grid<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->grid_n,
                                                       ag, s->acc);
-    k_adam_mlp<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc);
-    k_mlp_copies<<<1, 1024, 0, st>>>(s->mlp, s->wb, s->w8, s->scales);
-    k_act_scales<<<1, 64, 0, st>>>(s->scales);
+    k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc, s->wb, s->w8, s->scales,
+                                   c->d_stats);
     timer_end(c, "learned_adam", st, ev);
+  } else {
+    s->grad_dirty = true;
+    k_train_end<<<1, 64, 0, st>>>(s->acc, c->d_stats);
   }
-  k_train_end<<<1, 64, 0, st>>>(s->acc, c->d_stats);
   return hipGetLastError();
 }
 
@@ -941,8 +1097,9 @@ hipError_t learned_train(gi_context* c, hipStream_t st) {
     const float u = rand_unit_host(
         hash_pcg(hash_pcg(hash_pcg(hash_pcg(c->cfg.seed) + c->fa.index) + 0x7FFFFFFFu) + 9u + k));
     k_select_batch<<<nblk(s->B, 256), 256, 0, st>>>(s->trec, s->trec_count, (uint32_t)PR, s->hitpos, s->hitnrm,
-                                                    u, s->B, s->batch, s->acc);
-    const hipError_t e = train_step(c, st, true);
+                                                    u, s->B, s->batch_raw, s->acc);
+    hipError_t e = sort_batch(c, st);
+    if (e == hipSuccess) e = train_step(c, st, true);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -954,9 +1111,10 @@ hipError_t learned_step_on(gi_context* c, const float4* pos, const float4* nrm, 
   learned_set_domain(c);
   if (n != s->B) return hipErrorInvalidValue;
   // batch rows: pos, nrm, target
-  hipError_t e = hipMemcpy2DAsync(s->batch, 48, pos, 16, 16, n, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch + 1, 48, nrm, 16, 16, n, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch + 2, 48, tgt, 16, 16, n, hipMemcpyDeviceToDevice, st);
+  hipError_t e = hipMemcpy2DAsync(s->batch_raw, 48, pos, 16, 16, n, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch_raw + 1, 48, nrm, 16, 16, n, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch_raw + 2, 48, tgt, 16, 16, n, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = sort_batch(c, st);
   if (e != hipSuccess) return e;
   return train_step(c, st, apply);
 }
@@ -1039,6 +1197,7 @@ hipError_t learned_load(gi_context* c, const void* blob) {
     p += sz[k];
   }
   if (e != hipSuccess) return e;
+  s->grad_dirty = true;   // the restored gradient is the saved state's, not a clean buffer
   // rebuild the working copies
   k_learned_copy_half<<<nblk(s->grid_n, 256), 256>>>(s->grid, s->grid_h, s->grid_n);
   k_mlp_copies<<<1, 1024>>>(s->mlp, s->wb, s->w8, s->scales);

@@ -51,8 +51,8 @@ class Frame(C.Structure):
 DEFAULTS = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                 max_life=32, n_cap=256, seed=3, frac_bits=12, cache_mode=CACHE_PLAIN,
                 cell_scale=10.0, r_max=64.0, eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0),
-                mlp_batch_log2=16, mlp_levels=16, mlp_table_log2=19, mlp_steps=1,
-                mlp_lr_grid=1e-2, mlp_lr_mlp=1e-3, mlp_loss_scale=128.0, mlp_judge=0.1)
+                mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4,
+                mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_loss_scale=128.0, mlp_judge=0.1)
 
 _lib = None
 

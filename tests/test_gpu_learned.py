@@ -18,7 +18,8 @@ LEVELS, TLOG2, BLOG2, SEED = 4, 10, 8, 3
 
 def _ctx(mode=gi.CACHE_MLP_BF16, **kw):
     cfg = dict(width=64, height=64, cache_mode=mode, mlp_levels=LEVELS, mlp_table_log2=TLOG2,
-               mlp_batch_log2=BLOG2, seed=SEED, mlp_loss_scale=128.0)
+               mlp_batch_log2=BLOG2, seed=SEED, mlp_loss_scale=128.0,
+               mlp_lr_grid=OL.Spec.lr_grid, mlp_lr_mlp=OL.Spec.lr_mlp)
     cfg.update(kw)
     ctx = gi.Context(**cfg)
     sc = I.room_scene()
@@ -139,7 +140,7 @@ def test_inference_matches_oracle_after_training_steps(mode, tol):
 
 def test_learned_frames_train_and_feed_the_probes():
     ctx, sc, lo, hi = _ctx(gi.CACHE_MLP_BF16, width=128, height=128, rays_per_probe=16, table_log2=16,
-                           mlp_batch_log2=12, mlp_levels=8, mlp_table_log2=14, mlp_judge=10.0)
+                           mlp_batch_log2=12, mlp_levels=8, mlp_table_log2=14, mlp_judge=10.0, mlp_steps=4)
     gb = gi.GBuffer(128, 128)
     out = torch.zeros((128, 128, 4), dtype=torch.float32, device="cuda")
     losses = []
@@ -158,7 +159,7 @@ def test_learned_frames_train_and_feed_the_probes():
     assert np.isfinite(o).all() and (o[..., :3] >= 0).all()
     assert np.mean(losses[-3:]) < np.mean(losses[:2])
     st = ctx.learned_stats()
-    assert st["steps"] == 12 and not st["fallback"]
+    assert st["steps"] == 12 * 4 and not st["fallback"]
     # the probes see surrogate radiance: atlas values are finite and positive on average
     pr = ctx.probes()
     assert pr["atlas"][..., :3].mean() > 0
@@ -207,7 +208,7 @@ def test_surrogate_gain_over_plain_cache_on_the_field_scene():
     plain.close()
     found = a[:, 3] > 0
     assert found.sum() > 2000
-    learned = _run_frames("field", sc, W, H, 64, 8, gi.CACHE_MLP_BF16, mlp_batch_log2=16, mlp_levels=16,
+    learned = _run_frames("field", sc, W, H, 64, 8, gi.CACHE_MLP_BF16, mlp_batch_log2=14, mlp_levels=16,
                           mlp_table_log2=19, mlp_steps=4, mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_judge=10.0)
     learned.learned_query(pp, pn, q)
     torch.cuda.synchronize()

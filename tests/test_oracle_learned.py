@@ -124,6 +124,29 @@ def test_adam_first_step_closed_form_and_skip():
     assert all(np.array_equal(p[k], snap[k]) for k in p) and opt.t == 1
 
 
+def test_lazy_grid_adam_moves_only_entries_with_a_gradient():
+    """The lazy grid step equals the dense step (pinned by the closed form above) wherever the
+    gradient is non-zero, and leaves an entry whose gradient is zero exactly as it was."""
+    import dataclasses
+    s, p, x, n, t = _tiny()
+    _, g1 = L.loss_and_grads(s, p, x, n, t)
+    g1["grid"][g1["grid"] == 0] = 1e-3            # step 1 touches every entry
+    g2 = {k: v * -0.5 for k, v in g1.items()}
+    g2["grid"].flat[0] = 0.0                       # an entry no sample touched at step 2
+    pd = {k: v.copy() for k, v in p.items()}
+    dense = L.Adam(dataclasses.replace(s, lazy_grid=False), pd)
+    lazy = L.Adam(s, p)
+    assert dense.step(pd, g1) and lazy.step(p, g1)
+    assert np.array_equal(p["grid"], pd["grid"])
+    after1 = p["grid"].flat[0]
+    assert dense.step(pd, g2) and lazy.step(p, g2)
+    on = g2["grid"] != 0
+    assert np.array_equal(p["grid"][on], pd["grid"][on])
+    assert np.array_equal(p["W1"], pd["W1"])
+    assert p["grid"].flat[0] == after1 and pd["grid"].flat[0] != after1
+    assert lazy.m["grid"].flat[0] == (1 - s.beta1) * g1["grid"].flat[0]
+
+
 def test_training_fits_a_smooth_radiance_field():
     s = L.Spec(levels=4, table_log2=10, n_min=4, n_max=32, lr_grid=1e-2, lr_mlp=1e-2)
     p = L.init_params(s, seed=2)
