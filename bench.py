@@ -11,7 +11,6 @@ Prints one JSON line: ms/frame (value), probe Mrays/s, per-kernel times, the roo
 dominant kernel and the CPU oracle's time on a bounded sample of the same workload.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -25,18 +24,10 @@ HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES = 128, 48
 
 
-def _src_hash():
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2310_19855_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2310_19855_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def _traffic(kernel, launches_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel sources; else None"""
-    path = os.path.join(ROOT, "profiles", "traffic_field1080.json")
+def _traffic(kernel, workload, form):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this workload and
+    form, if it was taken on the current kernel sources; else None"""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{form}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -44,7 +35,8 @@ def _traffic(kernel, launches_bytes):
     except Exception:
         return None
     k = d.get("kernels", {}).get(kernel)
-    if not k or d.get("src_hash") != _src_hash():
+    from paper_2310_19855_amd import pmc
+    if not k or k.get("src_hash") is None or k.get("src_hash") != pmc.kernel_src_hash(kernel):
         return None
     return k.get("bytes_per_launch")
 
@@ -59,8 +51,15 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the plain / MLP-BF16 / MLP-FP8 comparison")
+    ap.add_argument("--form", default="plain", choices=("plain", "mlp_bf16", "mlp_fp8"),
+                    help="cache form of the timed frames (learned forms train and infer every frame)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (scale of HBM byte counters)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -77,7 +76,9 @@ def main():
     W, H, R = preset["width"], preset["height"], preset["rays_per_probe"]
     scene = I.make_scene(preset["scene"])
     cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=preset["table_log2"],
-               bounces=preset["bounces"], sky=scene.sky)
+               bounces=preset["bounces"], sky=scene.sky, cache_mode=FORMS[args.form])
+    if args.form != "plain":
+        cfg.update(MLP_CFG)
     torch.cuda.set_device(0)
     ctx = gi.Context(**cfg)
     t0 = time.time()
@@ -113,6 +114,8 @@ def main():
         cam.index = fi
         ctx.spawn_probes(cam, g.pos, g.nrm, g.prim)
         ctx.trace_probes(cam)
+        if args.form != "plain":
+            ctx.learned_train(cam)
         ctx.cache_update(cam)
         ctx.interpolate_probes(cam, g.pos, g.nrm, g.prim, out)
 
@@ -178,7 +181,7 @@ def main():
     dk = kern[dom]
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dk.get("gbs", 0.0), 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dk.get("frac_hbm", 0.0), 5),
-                "traffic": _traffic(dom, dk.get("alg_bytes")),
+                "traffic": _traffic(dom, args.workload, args.form),
                 "alg_bytes_per_launch": dk.get("alg_bytes"), "avg_launch_ms": dk["avg_ms"],
                 "bytes_per_probe_ray": (trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES) / pr_rays,
                 "nodes_per_probe_ray": trav["probe_nodes"] / pr_rays,
@@ -187,7 +190,7 @@ def main():
                                          for k, v in sorted(kern.items(), key=lambda kv: -kv[1]['avg_ms'] * kv[1]['launches'])))
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.form == "plain":
         cpu = cpu_baseline(scene, cfg, cams, args.cpu_frames, log)
     forms = None
     if not args.no_forms:
@@ -205,7 +208,7 @@ def main():
         "config": {"workload": f"{args.workload}: {W}x{H} G-buffer, {scene.n_tris} tris ({scene.name}), "
                                f"{P} probe tiles x {R} rays, 2^{preset['table_log2']} cache slots, "
                                f"{preset['bounces']} bounce(s), frames {args.warmup}..{n_frames - 1}",
-                   "cache": "plain"},
+                   "cache": args.form},
         "probe_mrays_per_s": round(mrays, 1) if mrays else None,
         "probe_rays_per_frame": int(rays_per_frame), "hits_per_frame": int(hits_per_frame),
         "gpu_event_ms_per_frame": round(gpu_ms / args.steps, 4),
@@ -347,6 +350,19 @@ def forms_comparison(log, W=1920, H=1080):
             f"{f} {v['ms_per_frame']:.2f}ms (R={v['rays_per_probe']})"
             for f, v in out["scenes"][scene_name]["equal_error_common"].items() if isinstance(v, dict)))
     return out
+
+
+def calibrate_copy(mib):
+    """A plain elementwise device copy (read mib MiB, write mib MiB), five times: profiled with
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE it gives the scale of those counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_read_bytes": n * 4, "copy_write_bytes": n * 4, "launches": 5}), flush=True)
 
 
 def cpu_baseline(scene, cfg, cams, frames, log):

@@ -60,6 +60,7 @@ struct LearnedState {
   float4* batch_raw = nullptr;   // [B][3]: pos, nrm, target as selected
   float4* batch = nullptr;       // the same rows grouped by spatial (Morton) bucket
   uint32_t* sort_cnt = nullptr;  // [kSortBuckets] bucket counters / offsets
+  float2* judge_part = nullptr;  // per-wave (error, norm) partials of the judge
   uint32_t B = 0;
   float4* lmlp = nullptr;        // [P*R] surrogate radiance at each hit
   float* acc = nullptr;          // [0] loss sum, [1] non-finite flag, [2] judge |diff|, [3] judge |plain|,
@@ -640,13 +641,22 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
 }
 
 // deterministic sum of the per-wave partials (fixed order) -> gradient; flags non-finite
-__global__ void k_reduce_mlp(const float* part, uint32_t waves, float* g, float* acc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kMlpParams) return;
+// (64 parameters per block; 16 slices of the waves per parameter, summed in a fixed order)
+__global__ __launch_bounds__(1024) void k_reduce_mlp(const float* part, uint32_t waves, float* g, float* acc) {
+  __shared__ float red[16][64];
+  const int l = threadIdx.x & 63, slice = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + l;
   float s = 0.0f;
-  for (uint32_t w = 0; w < waves; ++w) s += part[(size_t)w * kMlpParams + i];
-  g[i] = s;
-  if (!isfinite(s)) acc[1] = 1.0f;
+  if (i < kMlpParams)
+    for (uint32_t w = slice; w < waves; w += 16u) s += part[(size_t)w * kMlpParams + i];
+  red[slice][l] = s;
+  __syncthreads();
+  if (slice == 0 && i < kMlpParams) {
+    float t = 0.0f;
+    for (int k = 0; k < 16; ++k) t += red[k][l];
+    g[i] = t;
+    if (!isfinite(t)) acc[1] = 1.0f;
+  }
 }
 
 // Adam on the unscaled gradient; the whole step is skipped when any gradient is non-finite
@@ -881,9 +891,9 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
 }
 
 // judge: relative error of the surrogate against confident plain cells (hits whose cell has
-// at least 64 history samples)
+// at least 64 history samples); one partial (error, norm) per wave, summed by k_judge_decide
 __global__ void k_judge(const uint32_t* ids, const uint32_t* count, uint32_t stripe_cap, uint32_t blocks_per_stripe,
-                        const uint4* rec, const uint2* meta, const float4* L, const float4* lmlp, float* acc) {
+                        const uint4* rec, const uint2* meta, const float4* L, const float4* lmlp, float2* part) {
   const uint32_t stripe = blockIdx.x / blocks_per_stripe;
   const uint32_t item = (blockIdx.x % blocks_per_stripe) * blockDim.x + threadIdx.x;
   float dn = 0.f, dd = 0.f;
@@ -900,21 +910,36 @@ __global__ void k_judge(const uint32_t* ids, const uint32_t* count, uint32_t str
     dn += __shfl_xor(dn, o, 64);
     dd += __shfl_xor(dd, o, 64);
   }
-  if ((threadIdx.x & 63) == 0 && (dn != 0.f || dd != 0.f)) {
-    atomicAdd(&acc[2], dn);
-    atomicAdd(&acc[3], dd);
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = make_float2(dn, dd);
 }
 
-__global__ void k_judge_decide(float* acc, float threshold, unsigned long long* stats) {
-  if (threadIdx.x != 0) return;
-  const float err = acc[3] > 0.0f ? acc[2] / acc[3] : 0.0f;
-  acc[6] = err;
-  const bool fb = acc[3] > 0.0f && err > threshold;
-  acc[4] = fb ? 1.0f : 0.0f;
-  if (fb) stats[GI_STAT_MLP_FALLBACK] += 1ull;
-  acc[2] = 0.0f;
-  acc[3] = 0.0f;
+__global__ __launch_bounds__(1024) void k_judge_decide(const float2* part, uint32_t n, float* acc, float threshold,
+                                                       unsigned long long* stats) {
+  __shared__ float sn[1024], sd[1024];
+  const uint32_t t = threadIdx.x;
+  float a = 0.f, b = 0.f;
+  for (uint32_t i = t; i < n; i += 1024u) {
+    const float2 v = part[i];
+    a += v.x;
+    b += v.y;
+  }
+  sn[t] = a;
+  sd[t] = b;
+  __syncthreads();
+  for (uint32_t h = 512; h >= 1; h >>= 1) {
+    if (t < h) {
+      sn[t] += sn[t + h];
+      sd[t] += sd[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const float err = sd[0] > 0.0f ? sn[0] / sd[0] : 0.0f;
+    acc[6] = err;
+    const bool fb = sd[0] > 0.0f && err > threshold;
+    acc[4] = fb ? 1.0f : 0.0f;
+    if (fb) stats[GI_STAT_MLP_FALLBACK] += 1ull;
+  }
 }
 
 __global__ void k_train_begin(float* acc, float* scales) {
@@ -989,6 +1014,7 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->batch, 3 * (size_t)s->B));
   A(lalloc(&s->batch_raw, 3 * (size_t)s->B));
   A(lalloc(&s->sort_cnt, kSortBuckets));
+  A(lalloc(&s->judge_part, (size_t)c->hit_blocks_per_stripe * kStatStripes));
   A(lalloc(&s->lmlp, PR));
   A(lalloc(&s->acc, 16));
   if (e != hipSuccess) return e;
@@ -1023,7 +1049,7 @@ void learned_destroy(gi_context* c) {
   if (!s) return;
   void* ptrs[] = {s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->mlp, s->mlp_g, s->mlp_m, s->mlp_v,
                   s->mlp_part, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->trec_count, s->batch,
-                  s->batch_raw, s->sort_cnt, s->lmlp, s->acc};
+                  s->batch_raw, s->sort_cnt, s->judge_part, s->lmlp, s->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -1060,7 +1086,7 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
   k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, s->grid_h, s->grid_g, s->wb, S, s->mlp_part,
                                                 s->acc, s->scales + 3);
   timer_end(c, "learned_train", st, ev);
-  k_reduce_mlp<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp_part, waves, s->mlp_g, s->acc);
+  k_reduce_mlp<<<nblk(kMlpParams, 64), 1024, 0, st>>>(s->mlp_part, waves, s->mlp_g, s->acc);
   if (apply) {
     s->step += 1;
     AdamArgs ag, am;
@@ -1134,10 +1160,10 @@ hipError_t learned_infer_rays(gi_context* c, hipStream_t st) {
                                             c->d_hit_ids, c->d_hit_count, c->hit_stripe_cap,
                                             c->hit_blocks_per_stripe, s->lmlp);
   timer_end(c, "learned_infer", st, ev);
-  k_judge<<<c->hit_blocks_per_stripe * kStatStripes, 64, 0, st>>>(c->d_hit_ids, c->d_hit_count, c->hit_stripe_cap,
-                                                                  c->hit_blocks_per_stripe, c->d_rec, c->tab.meta,
-                                                                  c->tab.L, s->lmlp, s->acc);
-  k_judge_decide<<<1, 64, 0, st>>>(s->acc, c->cfg.mlp_judge, c->d_stats);
+  const uint32_t jb = c->hit_blocks_per_stripe * kStatStripes;
+  k_judge<<<jb, 64, 0, st>>>(c->d_hit_ids, c->d_hit_count, c->hit_stripe_cap, c->hit_blocks_per_stripe, c->d_rec,
+                             c->tab.meta, c->tab.L, s->lmlp, s->judge_part);
+  k_judge_decide<<<1, 1024, 0, st>>>(s->judge_part, jb, s->acc, c->cfg.mlp_judge, c->d_stats);
   return hipGetLastError();
 }
 
