@@ -307,31 +307,31 @@ def city_scene(seed: int = SCENE_SEED, blocks: int = 100, block_size: float = 40
             ys = np.linspace(0.0, h, ny + 1)
             mat = len(b.mats)
             b.mats.append(list(rng.uniform(0.1, 0.9, 3)) + [0.0, 0.0, 0.0])
-            for e in range(k):
-                x0, z0 = px[e], pz[e]
-                x1, z1 = px[(e + 1) % k], pz[(e + 1) % k]
-                L = math.hypot(x1 - x0, z1 - z0)
-                nx = max(1, int(round(L / facade_quad)))
-                ts = np.linspace(0.0, 1.0, nx + 1)
-                ex = x0 + (x1 - x0) * ts
-                ez = z0 + (z1 - z0) * ts
-                gvx = np.repeat(ex[None, :], ny + 1, 0)
-                gvz = np.repeat(ez[None, :], ny + 1, 0)
-                gvy = np.repeat(ys[:, None], nx + 1, 1)
-                fv = np.stack([gvx.ravel(), gvy.ravel(), gvz.ravel()], 1)
-                ci = np.arange(nx)
-                ri = np.arange(ny)
-                cc, rr = np.meshgrid(ci, ri, indexing="xy")
-                q0 = (rr * (nx + 1) + cc).ravel()
-                q1 = q0 + 1
-                q2 = q0 + (nx + 1)
-                q3 = q2 + 1
-                # counter-clockwise footprint -> outward facade normals with this winding
-                ff = np.concatenate([np.stack([q0, q2, q1], 1), np.stack([q1, q2, q3], 1)])
-                all_v.append(fv)
-                all_f.append(ff + nv)
-                all_m.append(np.full(len(ff), mat, np.uint32))
-                nv += len(fv)
+            # all facades of the building as one vertex grid: (ny + 1) rows by the edges'
+            # columns side by side; quads never join the last column of an edge to the next
+            x0, z0 = px, pz
+            x1, z1 = np.roll(px, -1), np.roll(pz, -1)
+            nxs = np.maximum(1, np.rint(np.hypot(x1 - x0, z1 - z0) / facade_quad).astype(np.int64))
+            ncol = nxs + 1
+            C = int(ncol.sum())
+            first = np.concatenate([[0], np.cumsum(ncol)[:-1]])
+            edge = np.repeat(np.arange(k), ncol)
+            t = (np.arange(C) - first[edge]) / nxs[edge]
+            ex = x0[edge] + (x1 - x0)[edge] * t
+            ez = z0[edge] + (z1 - z0)[edge] * t
+            fv = np.stack([np.tile(ex, ny + 1), np.repeat(ys, C), np.tile(ez, ny + 1)], 1)
+            cols = np.nonzero(np.arange(C) != (first + nxs)[edge])[0]
+            cc, rr = np.meshgrid(cols, np.arange(ny), indexing="xy")
+            q0 = (rr * C + cc).ravel()
+            q1 = q0 + 1
+            q2 = q0 + C
+            q3 = q2 + 1
+            # counter-clockwise footprint -> outward facade normals with this winding
+            ff = np.concatenate([np.stack([q0, q2, q1], 1), np.stack([q1, q2, q3], 1)])
+            all_v.append(fv)
+            all_f.append(ff + nv)
+            all_m.append(np.full(len(ff), mat, np.uint32))
+            nv += len(fv)
             rv = np.concatenate([[[cx, h, cz]], np.stack([px, np.full(k, h), pz], 1)])
             rf = np.array([[0, 1 + (e + 1) % k, 1 + e] for e in range(k)])
             all_v.append(rv)

@@ -18,8 +18,15 @@ def rel_err(gpu, ref, floor_frac=1e-3):
     return np.abs(g - r) / np.maximum(np.abs(r), floor)
 
 
-def assert_close(gpu, ref, tol=REL_TOL, what=""):
-    e = rel_err(gpu, ref)
+# SH coefficients are sums over the 64 atlas cells of radiance times basis moments; band 1-2
+# terms as large as the band-0 coefficient can cancel to near zero, so their float32 rounding
+# is judged against 1 % of the array's largest coefficient (one float32 ulp of that scale is
+# 1.2e-5 of it)
+SH_FLOOR = 1e-2
+
+
+def assert_close(gpu, ref, tol=REL_TOL, what="", floor_frac=1e-3):
+    e = rel_err(gpu, ref, floor_frac)
     assert e.size == 0 or e.max() <= tol, f"{what}: max rel err {e.max():.3g} at {np.unravel_index(e.argmax(), e.shape)}"
 
 

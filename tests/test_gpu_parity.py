@@ -2,10 +2,12 @@
 
 Integers (probe mask, hit triangle, hit distance bits, cell keys, fixed-point sums and counts,
 flags) must be bit-exact; float radiance within 1e-4 relative error (float64 evaluation)."""
+import math
+
 import numpy as np
 import pytest
 
-from gpu_common import Pair, assert_close, bits
+from gpu_common import SH_FLOOR, Pair, assert_close, bits
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +70,7 @@ def _run_stage_parity(scene, cfg, frames, check_every=True):
         assert_close(gt["L"], ot["L"], what="cached radiance")
         gpr, opr = pr.ctx.probes(), pr.ost.probes()
         assert_close(gpr["atlas"], opr["atlas"], what="probe atlas")
-        assert_close(gpr["sh"], opr["sh"], what="SH coefficients")
+        assert_close(gpr["sh"], opr["sh"], what="SH coefficients", floor_frac=SH_FLOOR)
         # interpolate
         pr.ctx.interpolate_probes(fr, pr.gb.pos, pr.gb.nrm, pr.gb.prim, pr.out)
         go = pr.out.cpu().numpy()
@@ -142,6 +144,100 @@ def test_field_small_frames_with_moving_light():
     """the ~1.0M-triangle field at 160x96, 64 rays, a light moving between frames"""
     _run_stage_parity(I.field_scene(), dict(width=160, height=96, rays_per_probe=64, table_log2=18,
                                             sky=(0.05, 0.05, 0.05)), [0, 1])
+
+
+def test_field1080_full_frames_in_the_benchmark_configuration():
+    """the benchmark's own configuration at full size: 1920x1080 over the ~1.0M-triangle
+    field, 64 rays per probe, 2^20 slots, camera orbit and moving light, frames 0 and 1 (every
+    pixel, probe, ray, cell and atlas entry compared)"""
+    p = I.PRESETS["field1080"]
+    sc = I.field_scene()
+    _run_stage_parity(sc, dict(width=p["width"], height=p["height"], rays_per_probe=p["rays_per_probe"],
+                               table_log2=p["table_log2"], bounces=p["bounces"], sky=sc.sky), [0, 1])
+
+
+def test_city4k_full_frames_two_bounces():
+    """the 4K city at full size: 3840x2160 over ~9.4M triangles, 128 rays per probe, two
+    bounces (the second read from the previous frame's cache), frames 0 and 1.  Most of the
+    16.6M rays hit a 10 cm cell of their own on this 4 km city, so the table has 2^26 slots
+    here and no bucket overflows (which keys win a full bucket depends on the order of
+    insertion; the configured 2^22 slots are checked by the next test)"""
+    p = I.PRESETS["city4k"]
+    sc = I.city_scene()
+    pr = _run_stage_parity(sc, dict(width=p["width"], height=p["height"], rays_per_probe=p["rays_per_probe"],
+                                    table_log2=26, bounces=p["bounces"], sky=sc.sky), [0, 1])
+    assert pr.ctx.stats()["overflow"] == 0
+
+
+def test_city4k_configured_table_overflow():
+    """the 4K city with its configured 2^22 slots, where buckets overflow: hits, keys and the
+    per-key fixed-point sums of every key both sides hold are bit-exact; a key held by one
+    side only sits in a bucket the other side filled; a held key received all its samples;
+    a ray holds a slot exactly when its key is held"""
+    p = I.PRESETS["city4k"]
+    sc = I.city_scene()
+    pr = Pair(sc, dict(width=p["width"], height=p["height"], rays_per_probe=p["rays_per_probe"],
+                       table_log2=p["table_log2"], bounces=p["bounces"], sky=sc.sky))
+    fr = I.camera_for("city", 0)
+    fr.index = 0
+    (gp, gn, ga, gprim), (op, on, oa, oprim) = pr.gbuffer(fr)
+    assert np.array_equal(gprim, oprim)
+    pr.ctx.spawn_probes(fr, pr.gb.pos, pr.gb.nrm, pr.gb.prim)
+    pr.ost.spawn(fr, op, on, oprim)
+    pr.ctx.trace_probes(fr)
+    pr.ost.trace(fr)
+    gr, orr = pr.ctx.rays(), pr.ost.rays()
+    assert np.array_equal(gr["tri"], orr["tri"]) and np.array_equal(bits(gr["t"]), bits(orr["t"]))
+    hit = (orr["cell"] & gi.RAY_HIT) != 0
+    assert np.array_equal(gr["key"][hit], orr["key"][hit])
+    gt, ot = pr.ctx.table(), pr.ost.table()
+    gs, os_ = pr.ctx.stats(), pr.ost.stats()
+    assert gs["overflow"] > 0 and os_["overflow"] > 0
+    keys, n_rays = np.unique(orr["key"][hit], return_counts=True)
+    per_key = dict(zip(keys.tolist(), n_rays.tolist()))
+    for t, r, st in ((gt, gr, gs), (ot, orr, os_)):
+        held = t["key"]
+        # each held key received all its samples, and rays hold a slot exactly for held keys
+        assert np.array_equal(t["acc"][:, 3], np.array([per_key[int(k)] for k in held], np.uint32))
+        assert np.array_equal(r["slot"][hit] >= 0, np.isin(r["key"][hit], held))
+        assert st["overflow"] + st["nonfinite"] == int(hit.sum()) - int(t["acc"][:, 3].sum())
+    # keys held by both sides: identical sums; keys held by one side: the other side's bucket is full
+    common, gi_idx, oi_idx = np.intersect1d(gt["key"], ot["key"], return_indices=True)
+    assert np.array_equal(gt["acc"][gi_idx], ot["acc"][oi_idx])
+    assert np.array_equal(gt["id"][gi_idx], ot["id"][oi_idx])
+    for t_one, t_other in ((gt, ot), (ot, gt)):
+        only = ~np.isin(t_one["key"], t_other["key"])
+        buckets_other, fill_other = np.unique(t_other["id"] >> np.uint64(32), return_counts=True)
+        fill = dict(zip(buckets_other.tolist(), fill_other.tolist()))
+        for b in np.unique(t_one["id"][only] >> np.uint64(32)).tolist():
+            assert fill.get(b, 0) == 32, f"bucket {b} not full on the other side"
+
+
+def test_furnace_parity_and_closed_form():
+    """closed diffuse sphere (Le = 1, albedo 0.8, ~200k triangles), feedback through the
+    cache with replacement: two frames against the oracle, then the GPU alone follows the
+    recurrence L_f = albedo (Le + L_{f-1}) towards Le / (1 - albedo) = 5"""
+    sc = I.furnace_scene()
+    cfg = dict(width=96, height=96, rays_per_probe=64, table_log2=18, cell_scale=0.5, n_cap=0, leak_bit=0,
+               bounces=2)
+    pr = _run_stage_parity(sc, cfg, [0, 1])
+    rho, le = 0.8, 1.0
+    L = rho * (le + rho * le)
+    for f in range(2, 40):
+        fr = I.camera_for("furnace", 0)
+        fr.index = f
+        pr.ctx.spawn_probes(fr, pr.gb.pos, pr.gb.nrm, pr.gb.prim)
+        pr.ctx.trace_probes(fr)
+        pr.ctx.cache_update(fr)
+        L = rho * (le + L)
+        p = pr.ctx.probes()
+        valid = p["mask"][:len(p["pos"])] != SENT
+        assert abs(p["atlas"][valid][..., :3].mean() / (le + L) - 1) < 8e-3, f
+    assert abs((le + L) / (le / (1 - rho)) - 1) < 2e-4
+    pr.ctx.interpolate_probes(fr, pr.gb.pos, pr.gb.nrm, pr.gb.prim, pr.out)
+    o = pr.out.cpu().numpy()
+    assert (o[..., 3] == 0).all()
+    assert abs(o[..., :3].mean() / (math.pi * (le + L)) - 1) < 8e-3
 
 
 def test_cache_query_matches_oracle():
