@@ -56,6 +56,7 @@ enum { GI_CACHE_PLAIN = 0, GI_CACHE_MLP_BF16 = 1, GI_CACHE_MLP_FP8 = 2 };
 /* ray-record flag bits (gi_rays_export): bits 0..5 hemisphere cell of the probe atlas */
 #define GI_RAY_HIT 0x100u     /* the probe ray hit a triangle */
 #define GI_RAY_FRONT 0x200u   /* ... on the side its winding normal faces (emission side) */
+#define GI_RAY_EMIT 0x400u    /* ... on that side of a triangle whose material emits */
 #define GI_RAY_TRACED 0x10000u
 
 /* interpolation flag (alpha of gi_interpolate_probes output) */

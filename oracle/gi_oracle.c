@@ -1184,7 +1184,11 @@ void ORC(trace)(state *st, const orc_frame *fr)
             real y[3], ny[3];
             for (int k = 0; k < 3; ++k) { y[k] = o[k] + t * d[k]; ny[k] = sg * n[k]; }
             flags |= 0x100u;                     /* bit 8: hit */
-            if (dn < RC(0.0)) flags |= 0x200u;   /* bit 9: front face (one-sided emission) */
+            if (dn < RC(0.0)) {
+                flags |= 0x200u;                 /* bit 9: front face (one-sided emission) */
+                const float *mt = sc->mats + 6 * sc->tmat[tri];
+                if (mt[3] > 0.0f || mt[4] > 0.0f || mt[5] > 0.0f) flags |= 0x400u;   /* bit 10: emitter */
+            }
             st->r_t[gid] = t;
             st->r_tri[gid] = tri;
             st->r_cell[gid] = flags;

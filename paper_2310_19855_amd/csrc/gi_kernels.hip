@@ -60,49 +60,89 @@ __global__ __launch_bounds__(kTraceBlock) void k_gbuffer(SceneView sv, ShadeTabl
 }
 
 // ------------------------------------------------------------------------------------------
-// Spawn (Section 2.1.1) and probe mask (Section 2.1.5): one thread per tile
+// Spawn (Section 2.1.1), probe mask and its MIP chain (Section 2.1.5).  A MIP entry is the
+// first valid probe of its 2x2 children in raster order (out-of-bounds children skipped).
+// One block spawns a 16x16 patch of tiles and builds MIP levels 1..4 of that patch in LDS
+// (a level-k entry of the patch depends on that patch only); levels 5+ are built from level
+// 4 by one block.
 // ------------------------------------------------------------------------------------------
-__global__ void k_spawn(const float4* gpos, const float4* gnrm, const uint32_t* gprim, uint32_t W, uint32_t H,
-                        uint32_t TW, uint32_t TH, uint32_t jx, uint32_t jy, uint32_t* mask, float4* ppos,
-                        float4* pnrm, unsigned long long* stats, uint32_t* hit_count) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < kStatStripes) {
+struct MipInfo {
+  uint32_t n;
+  uint32_t w[16], h[16], off[16];
+};
+
+__global__ __launch_bounds__(256) void k_spawn_mips(const float4* gpos, const float4* gnrm, const uint32_t* gprim,
+                                                    uint32_t W, uint32_t H, uint32_t TW, uint32_t TH, uint32_t jx,
+                                                    uint32_t jy, MipInfo mi, uint32_t* mask, float4* ppos,
+                                                    float4* pnrm, unsigned long long* stats, uint32_t* hit_count) {
+  __shared__ uint32_t lv[2][256];
+  const uint32_t t = threadIdx.x;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && t < kStatStripes) {
     // per-frame counters restart; so do the hit-list stripes of this frame's trace
-    stats[p * GI_STAT_COUNT + GI_STAT_LIVE] = 0;
-    stats[p * GI_STAT_COUNT + GI_STAT_RELAXED] = 0;
-    stats[p * GI_STAT_COUNT + GI_STAT_NOPROBE] = 0;
-    hit_count[p] = 0;
+    stats[t * GI_STAT_COUNT + GI_STAT_LIVE] = 0;
+    stats[t * GI_STAT_COUNT + GI_STAT_RELAXED] = 0;
+    stats[t * GI_STAT_COUNT + GI_STAT_NOPROBE] = 0;
+    hit_count[t] = 0;
   }
-  if (p >= TW * TH) return;
-  const uint32_t tx = p % TW, ty = p / TW;
-  const uint32_t px = 8u * tx + jx, py = 8u * ty + jy;
+  const uint32_t tx = blockIdx.x * 16u + (t & 15u), ty = blockIdx.y * 16u + (t >> 4);
   uint32_t m = kSentinel;
-  float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-  if (px < W && py < H) {
-    const uint32_t pix = py * W + px;
-    if (gprim[pix] != kMiss) {
-      m = (py << 16) | px;
-      a = gpos[pix];
-      b = gnrm[pix];
+  if (tx < TW && ty < TH) {
+    const uint32_t px = 8u * tx + jx, py = 8u * ty + jy;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+    if (px < W && py < H) {
+      const uint32_t pix = py * W + px;
+      if (gprim[pix] != kMiss) {
+        m = (py << 16) | px;
+        a = gpos[pix];
+        b = gnrm[pix];
+      }
     }
+    const uint32_t p = ty * TW + tx;
+    mask[p] = m;
+    ppos[p] = a;
+    pnrm[p] = b;
   }
-  mask[p] = m;
-  ppos[p] = a;
-  pnrm[p] = b;
+  // tiles outside the grid hold the sentinel, which the child scan skips like an absent child
+  lv[0][t] = m;
+  __syncthreads();
+  uint32_t side = 16u, cur = 0u;
+  for (uint32_t k = 1; k < mi.n && k <= 4u; ++k) {
+    const uint32_t ns = side >> 1;
+    if (t < ns * ns) {
+      const uint32_t x = t % ns, y = t / ns;
+      uint32_t v = kSentinel;
+#pragma unroll
+      for (uint32_t c = 0; c < 4; ++c) {
+        const uint32_t cx = 2u * x + (c & 1u), cy = 2u * y + (c >> 1);
+        if (v == kSentinel) v = lv[cur][cy * side + cx];
+      }
+      lv[cur ^ 1u][t] = v;
+      const uint32_t gx = blockIdx.x * ns + x, gy = blockIdx.y * ns + y;
+      if (gx < mi.w[k] && gy < mi.h[k]) mask[mi.off[k] + gy * mi.w[k] + gx] = v;
+    }
+    __syncthreads();
+    cur ^= 1u;
+    side = ns;
+  }
 }
 
-// one MIP level of the mask: first valid probe of the 2x2 children in raster order
-__global__ void k_mask_mip(const uint32_t* src, uint32_t sw, uint32_t sh, uint32_t* dst, uint32_t dw, uint32_t dh) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= dw * dh) return;
-  const uint32_t x = i % dw, y = i / dw;
-  uint32_t v = kSentinel;
+// MIP levels 5.. from level 4 (one block; levels in sequence)
+__global__ __launch_bounds__(1024) void k_mask_mips_top(MipInfo mi, uint32_t* mask) {
+  for (uint32_t k = 5; k < mi.n; ++k) {
+    const uint32_t sw = mi.w[k - 1], sh = mi.h[k - 1], dw = mi.w[k], dh = mi.h[k];
+    const uint32_t* src = mask + mi.off[k - 1];
+    for (uint32_t i = threadIdx.x; i < dw * dh; i += blockDim.x) {
+      const uint32_t x = i % dw, y = i / dw;
+      uint32_t v = kSentinel;
 #pragma unroll
-  for (uint32_t c = 0; c < 4; ++c) {
-    const uint32_t cx = 2 * x + (c & 1), cy = 2 * y + (c >> 1);
-    if (v == kSentinel && cx < sw && cy < sh) v = src[cy * sw + cx];
+      for (uint32_t c = 0; c < 4; ++c) {
+        const uint32_t cx = 2u * x + (c & 1u), cy = 2u * y + (c >> 1);
+        if (v == kSentinel && cx < sw && cy < sh) v = src[cy * sw + cx];
+      }
+      mask[mi.off[k] + i] = v;
+    }
+    __syncthreads();
   }
-  dst[i] = v;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -171,7 +211,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, Shad
     const float4 n = st.tnrm[tri];
     const float dn = (n.x * dx + n.y * dy) + n.z * dz;
     flags |= GI_RAY_HIT;
-    if (dn < 0.0f) flags |= GI_RAY_FRONT;
+    if (dn < 0.0f) {
+      flags |= GI_RAY_FRONT;
+      const float4 e = st.mats[2 * __float_as_uint(n.w) + 1];
+      if (e.x > 0.0f || e.y > 0.0f || e.z > 0.0f) flags |= GI_RAY_EMIT;
+    }
     rec[gid] = make_uint4(0xFFFFFFFFu, __float_as_uint(t), tri, flags);
   }
   const uint64_t m = __ballot(hit);
@@ -491,7 +535,7 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
       v0 = s0; v1 = s1; v2 = s2;
     } else {
       float le0 = 0.f, le1 = 0.f, le2 = 0.f;
-      if (r.w & GI_RAY_FRONT) {
+      if (r.w & GI_RAY_EMIT) {
         const float4 e = mats[2 * __float_as_uint(tnrm[r.z].w) + 1];
         le0 = e.x; le1 = e.y; le2 = e.z;
       }
@@ -593,11 +637,6 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
 // ------------------------------------------------------------------------------------------
 // Per-pixel interpolation (Section 2.4.1, Algorithms 4 and 6)
 // ------------------------------------------------------------------------------------------
-struct MipInfo {
-  uint32_t n;
-  uint32_t w[16], h[16], off[16];
-};
-
 __device__ inline uint32_t find_closest_probe(const uint32_t* mask, const MipInfo& mi, int32_t px, int32_t py,
                                               int32_t ox, int32_t oy) {
   int32_t x = px >> 3, y = py >> 3;
@@ -908,12 +947,22 @@ hipError_t launch_gbuffer(gi_context* c, const gi_frame* f, float4* pos, float4*
   return hipGetLastError();
 }
 
-hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, hipStream_t s) {
-  GI_TIMED(c, "spawn", s, (k_spawn<<<blocks(c->P, 256), 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
-  for (uint32_t k = 1; k < c->nmip; ++k) {
-    const uint32_t n = c->mip_w[k] * c->mip_h[k];
-    GI_TIMED(c, "mask_mip", s, (k_mask_mip<<<blocks(n, 256), 256, 0, s>>>(c->d_mask + c->mip_off[k - 1], c->mip_w[k - 1], c->mip_h[k - 1], c->d_mask + c->mip_off[k], c->mip_w[k], c->mip_h[k])));
+static MipInfo mip_info(const gi_context* c) {
+  MipInfo mi;
+  mi.n = c->nmip < 16 ? c->nmip : 16;
+  for (uint32_t k = 0; k < 16; ++k) {
+    mi.w[k] = k < mi.n ? c->mip_w[k] : 0u;
+    mi.h[k] = k < mi.n ? c->mip_h[k] : 0u;
+    mi.off[k] = k < mi.n ? c->mip_off[k] : 0u;
   }
+  return mi;
+}
+
+hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, hipStream_t s) {
+  const MipInfo mi = mip_info(c);
+  const dim3 grid((c->TW + 15u) / 16u, (c->TH + 15u) / 16u);
+  GI_TIMED(c, "spawn", s, (k_spawn_mips<<<grid, 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, mi, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
+  if (mi.n > 5) GI_TIMED(c, "mask_mip", s, (k_mask_mips_top<<<1, 1024, 0, s>>>(mi, c->d_mask)));
   return hipGetLastError();
 }
 
@@ -943,13 +992,7 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
 
 hipError_t launch_interpolate(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, float4* out,
                               hipStream_t s) {
-  MipInfo mi;
-  mi.n = c->nmip < 16 ? c->nmip : 16;
-  for (uint32_t k = 0; k < mi.n; ++k) {
-    mi.w[k] = c->mip_w[k];
-    mi.h[k] = c->mip_h[k];
-    mi.off[k] = c->mip_off[k];
-  }
+  const MipInfo mi = mip_info(c);
   const uint32_t n = c->W * c->H;
   GI_TIMED(c, "interpolate", s, (k_interpolate<<<blocks(n, 256), 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->d_mask, mi, c->d_ppos, c->d_pnrm, c->d_sh, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, (int32_t)c->fa.jx, (int32_t)c->fa.jy, out, c->d_stats)));
   return hipGetLastError();
