@@ -191,9 +191,11 @@ gi_status gi_measure_traversal(gi_context *ctx, uint64_t *h_out8, void *stream);
 
 /* ---- learned radiance-cache surrogate (not in the paper) ------------------------------ */
 
-/* Select 2^mlp_batch_log2 of this frame's hit samples and take mlp_steps optimiser steps
- * (hash-grid + MLP forward, relative-L2 loss, backward, Adam) with the library's kernels.
- * Between gi_trace_probes and gi_cache_update.  GI_ERR_STATE in plain mode. */
+/* Select mlp_steps * 2^mlp_batch_log2 of this frame's hit samples (stratified over the hits)
+ * and take mlp_steps optimiser steps of 2^mlp_batch_log2 samples each, step k on every
+ * mlp_steps-th of them (hash-grid + MLP forward, relative-L2 loss, backward, Adam) with the
+ * library's kernels.  Between gi_trace_probes and gi_cache_update.  GI_ERR_STATE in plain
+ * mode. */
 gi_status gi_learned_train(gi_context *ctx, const gi_frame *frame, void *stream);
 
 /* One optimiser step on caller samples (tests, warm starts): d_pos, d_nrm, d_target [n][4]

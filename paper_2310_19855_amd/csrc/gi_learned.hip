@@ -62,6 +62,7 @@ struct LearnedState {
   uint32_t* sort_cnt = nullptr;  // [kSortBuckets] bucket counters / offsets
   float2* judge_part = nullptr;  // per-wave (error, norm) partials of the judge
   uint32_t B = 0;
+  uint32_t sub = 1;              // sub-batches held by the frame's batch (rows = sub * B)
   float4* lmlp = nullptr;        // [P*R] surrogate radiance at each hit
   float* acc = nullptr;          // [0] loss sum, [1] non-finite flag, [2] judge |diff|, [3] judge |plain|,
                                  // [4] fallback flag, [5] last loss, [6] last judged error, [7] batch n
@@ -325,14 +326,14 @@ __global__ void k_sort_scatter(LearnedParams lp, const float4* in, float4* out, 
 __global__ void k_zero_f32(float* p, uint64_t n);
 static inline uint32_t nblk(uint64_t n, uint32_t b) { return (uint32_t)((n + b - 1) / b); }
 
-static hipError_t sort_batch(gi_context* c, hipStream_t st) {
+static hipError_t sort_batch(gi_context* c, hipStream_t st, uint32_t rows) {
   LearnedState* s = c->learned;
   hipEvent_t ev;
   timer_begin(c, "learned_sort", st, &ev);
   k_zero_f32<<<nblk(kSortBuckets, 256), 256, 0, st>>>(reinterpret_cast<float*>(s->sort_cnt), kSortBuckets);
-  k_sort_count<<<nblk(s->B, 256), 256, 0, st>>>(s->lp, s->batch_raw, s->B, s->sort_cnt);
+  k_sort_count<<<nblk(rows, 256), 256, 0, st>>>(s->lp, s->batch_raw, rows, s->sort_cnt);
   k_sort_scan<<<1, 1024, 0, st>>>(s->sort_cnt);
-  k_sort_scatter<<<nblk(s->B, 256), 256, 0, st>>>(s->lp, s->batch_raw, s->batch, s->B, s->sort_cnt);
+  k_sort_scatter<<<nblk(rows, 256), 256, 0, st>>>(s->lp, s->batch_raw, s->batch, rows, s->sort_cnt);
   timer_end(c, "learned_sort", st, ev);
   return hipGetLastError();
 }
@@ -366,9 +367,11 @@ __device__ inline void atomic_max_abs(float* p, float v) {
   atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
 }
 
-__global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* batch, uint32_t B, const __half* grid_h,
-                                              float* grid_g, const __bf16* wb, float loss_scale, float* part,
-                                              float* acc, float* amax) {
+// sample i of the step is row off + stride * i of the batch array
+__global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
+                                              uint32_t stride, const __half* grid_h, float* grid_g,
+                                              const __bf16* wb, float loss_scale, float* part, float* acc,
+                                              float* amax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TrainSmem& S = *reinterpret_cast<TrainSmem*>(smem_raw);
   const int lane = threadIdx.x;
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
     // of each half), so that equal grid corners sit in neighbouring lanes
     uint32_t row;
     {
-      const float4 p0 = batch[3 * (32 * g + s)];
+      const float4 p0 = batch[3 * (off + stride * (32 * g + s))];
       float y0, y1, y2;
       norm_pos(lp, p0.x, p0.y, p0.z, y0, y1, y2);
       const uint32_t code = spread9(min((uint32_t)(y0 * 512.0f), 511u)) |
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
           const bool keep_min = ((s & j) == 0) == ((s & k) == 0);
           key = keep_min ? min(key, other) : max(key, other);
         }
-      row = 32 * g + (key & 31u);
+      row = off + stride * (32 * g + (key & 31u));
     }
     // -- encoding: lane = (sample s, levels 8*half_ .. 8*half_+7)
     const float4 pos = batch[3 * row];
@@ -1011,8 +1014,11 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->hitnrm, PR));
   A(lalloc(&s->trec, PR));
   A(lalloc(&s->trec_count, 1));
-  A(lalloc(&s->batch, 3 * (size_t)s->B));
-  A(lalloc(&s->batch_raw, 3 * (size_t)s->B));
+  // the frame's batch holds one sub-batch per optimiser step (at most 2^20 rows)
+  const uint32_t steps = g.mlp_steps ? g.mlp_steps : 1u;
+  s->sub = std::max<uint32_t>(1u, std::min<uint32_t>(steps, (1u << 20) / s->B));
+  A(lalloc(&s->batch, 3 * (size_t)s->B * s->sub));
+  A(lalloc(&s->batch_raw, 3 * (size_t)s->B * s->sub));
   A(lalloc(&s->sort_cnt, kSortBuckets));
   A(lalloc(&s->judge_part, (size_t)c->hit_blocks_per_stripe * kStatStripes));
   A(lalloc(&s->lmlp, PR));
@@ -1071,7 +1077,7 @@ void learned_set_domain(gi_context* c) {
 }
 
 // one optimiser step on the batch currently in s->batch
-static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
+static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t off, uint32_t stride) {
   LearnedState* s = c->learned;
   const float S = c->cfg.mlp_loss_scale > 0.0f ? c->cfg.mlp_loss_scale : 1.0f;
   k_train_begin<<<1, 64, 0, st>>>(s->acc, s->scales);
@@ -1083,8 +1089,8 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
   hipEvent_t ev;
   timer_begin(c, "learned_train", st, &ev);
   // every launched wave writes its whole partial, so the partials need no clearing
-  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, s->grid_h, s->grid_g, s->wb, S, s->mlp_part,
-                                                s->acc, s->scales + 3);
+  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->grid_g, s->wb, S,
+                                                s->mlp_part, s->acc, s->scales + 3);
   timer_end(c, "learned_train", st, ev);
   k_reduce_mlp<<<nblk(kMlpParams, 64), 1024, 0, st>>>(s->mlp_part, waves, s->mlp_g, s->acc);
   if (apply) {
@@ -1115,19 +1121,18 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply) {
 hipError_t learned_train(gi_context* c, hipStream_t st) {
   LearnedState* s = c->learned;
   learned_set_domain(c);
-  // each step's batch: stratified picks over this frame's training records, with a fresh
-  // offset per step so that steps see different hits when there are more hits than picks
+  // the frame's batch: sub * B stratified picks over this frame's training records, grouped
+  // by Morton bucket once; step k trains on rows k, k + sub, k + 2 sub, ... (each step spans
+  // the whole scene and its rows stay in spatial order)
   const size_t PR = (size_t)c->P * c->R;
   const uint32_t steps = c->cfg.mlp_steps ? c->cfg.mlp_steps : 1u;
-  for (uint32_t k = 0; k < steps; ++k) {
-    const float u = rand_unit_host(
-        hash_pcg(hash_pcg(hash_pcg(hash_pcg(c->cfg.seed) + c->fa.index) + 0x7FFFFFFFu) + 9u + k));
-    k_select_batch<<<nblk(s->B, 256), 256, 0, st>>>(s->trec, s->trec_count, (uint32_t)PR, s->hitpos, s->hitnrm,
-                                                    u, s->B, s->batch_raw, s->acc);
-    hipError_t e = sort_batch(c, st);
-    if (e == hipSuccess) e = train_step(c, st, true);
-    if (e != hipSuccess) return e;
-  }
+  const uint32_t rows = s->B * s->sub;
+  const float u = rand_unit_host(hash_pcg(hash_pcg(hash_pcg(hash_pcg(c->cfg.seed) + c->fa.index) + 0x7FFFFFFFu) + 9u));
+  k_select_batch<<<nblk(rows, 256), 256, 0, st>>>(s->trec, s->trec_count, (uint32_t)PR, s->hitpos, s->hitnrm, u,
+                                                  rows, s->batch_raw, s->acc);
+  hipError_t e = sort_batch(c, st, rows);
+  for (uint32_t k = 0; k < steps && e == hipSuccess; ++k) e = train_step(c, st, true, k % s->sub, s->sub);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -1140,9 +1145,9 @@ hipError_t learned_step_on(gi_context* c, const float4* pos, const float4* nrm, 
   hipError_t e = hipMemcpy2DAsync(s->batch_raw, 48, pos, 16, 16, n, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch_raw + 1, 48, nrm, 16, 16, n, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpy2DAsync(s->batch_raw + 2, 48, tgt, 16, 16, n, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = sort_batch(c, st);
+  if (e == hipSuccess) e = sort_batch(c, st, n);
   if (e != hipSuccess) return e;
-  return train_step(c, st, apply);
+  return train_step(c, st, apply, 0u, 1u);
 }
 
 hipError_t learned_infer_rays(gi_context* c, hipStream_t st) {
