@@ -670,23 +670,53 @@ struct AdamArgs {
 // Grid entries take the step only where this step's gradient is non-zero (lazy Adam: an
 // entry no sample touched keeps its value and moments).  The gradient buffer is left zeroed
 // for the next step, also when the step is skipped.
+__device__ inline void adam_lazy(float graw, float& p, float& m, float& v, const AdamArgs& a) {
+  if (graw == 0.0f) return;
+  const float gi = graw * a.inv_scale;
+  m = a.b1 * m + (1.0f - a.b1) * gi;
+  v = a.b2 * v + (1.0f - a.b2) * gi * gi;
+  const float mh = m / a.c1, vh = v / a.c2;
+  p = p - a.lr * mh / (sqrtf(vh) + a.eps);
+}
+
+// four parameters per thread: a group whose four gradients are zero is left untouched
 __global__ void k_adam_grid(float* p, __half* ph, float* g, float* m, float* v, uint64_t n, AdamArgs a,
                             const float* acc) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float graw = g[i];
-  if (graw == 0.0f) return;
-  g[i] = 0.0f;
-  if (acc[1] != 0.0f) return;
-  const float gi = graw * a.inv_scale;
-  const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
-  const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float mh = mi / a.c1, vh = vi / a.c2;
-  const float np_ = p[i] - a.lr * mh / (sqrtf(vh) + a.eps);
-  p[i] = np_;
-  ph[i] = __float2half(np_);
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i0 = 4 * q;
+  if (i0 >= n) return;
+  if (i0 + 4 <= n) {
+    const float4 g4 = reinterpret_cast<const float4*>(g)[q];
+    if (g4.x == 0.0f && g4.y == 0.0f && g4.z == 0.0f && g4.w == 0.0f) return;
+    reinterpret_cast<float4*>(g)[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (acc[1] != 0.0f) return;
+    float4 p4 = reinterpret_cast<const float4*>(p)[q];
+    float4 m4 = reinterpret_cast<const float4*>(m)[q];
+    float4 v4 = reinterpret_cast<const float4*>(v)[q];
+    adam_lazy(g4.x, p4.x, m4.x, v4.x, a);
+    adam_lazy(g4.y, p4.y, m4.y, v4.y, a);
+    adam_lazy(g4.z, p4.z, m4.z, v4.z, a);
+    adam_lazy(g4.w, p4.w, m4.w, v4.w, a);
+    reinterpret_cast<float4*>(p)[q] = p4;
+    reinterpret_cast<float4*>(m)[q] = m4;
+    reinterpret_cast<float4*>(v)[q] = v4;
+    __half2* h2 = reinterpret_cast<__half2*>(ph) + 2 * q;
+    h2[0] = __halves2half2(__float2half(p4.x), __float2half(p4.y));
+    h2[1] = __halves2half2(__float2half(p4.z), __float2half(p4.w));
+    return;
+  }
+  for (uint64_t i = i0; i < n; ++i) {
+    const float graw = g[i];
+    if (graw == 0.0f) continue;
+    g[i] = 0.0f;
+    if (acc[1] != 0.0f) continue;
+    float pi = p[i], mi = m[i], vi = v[i];
+    adam_lazy(graw, pi, mi, vi, a);
+    p[i] = pi;
+    m[i] = mi;
+    v[i] = vi;
+    ph[i] = __float2half(pi);
+  }
 }
 
 // end of an applied step (one block of 1024 threads): Adam on the MLP weights, their bf16 and
@@ -1106,8 +1136,8 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
     am.lr = c->cfg.mlp_lr_mlp;
     am.eps = 1e-8f;
     timer_begin(c, "learned_adam", st, &ev);
-    k_adam_grid<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->grid_n,
-                                                      ag, s->acc);
+    k_adam_grid<<<nblk((s->grid_n + 3) / 4, 256), 256, 0, st>>>(s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v,
+                                                                s->grid_n, ag, s->acc);
     k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc, s->wb, s->w8, s->scales,
                                    c->d_stats);
     timer_end(c, "learned_adam", st, ev);
