@@ -165,6 +165,64 @@ def test_learned_frames_train_and_feed_the_probes():
     assert pr["atlas"][..., :3].mean() > 0
 
 
+def test_judge_falls_back_to_confident_plain_cells():
+    """The plain cache judges the surrogate: with a threshold every error exceeds, the gather
+    reads the plain cache wherever the hit's cell is confident (at least 64 samples of
+    history), so a probe whose hits all land in confident cells has exactly the plain
+    method's atlas; with a threshold no error reaches, there is no fallback."""
+    W = H = 128
+    R = 64
+    kw = dict(width=W, height=H, rays_per_probe=R, table_log2=16, mlp_batch_log2=12, mlp_levels=8,
+              mlp_table_log2=14, mlp_steps=2)
+    sc = I.room_scene()
+    ctxs = {"plain": gi.Context(cache_mode=gi.CACHE_PLAIN, **kw),
+            "strict": gi.Context(cache_mode=gi.CACHE_MLP_BF16, mlp_judge=1e-9, **kw),
+            "lenient": gi.Context(cache_mode=gi.CACHE_MLP_BF16, mlp_judge=1e9, **kw)}
+    gb = gi.GBuffer(H, W)
+    out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+    for ctx in ctxs.values():
+        ctx.build_bvh(sc)
+    fr = I.room_camera(0)
+    ctxs["plain"].render_gbuffer(fr, gb.pos, gb.nrm, gb.alb, gb.prim)
+    for f in range(12):
+        fr = I.room_camera(0)
+        fr.index = f
+        for name, ctx in ctxs.items():
+            ctx.spawn_probes(fr, gb.pos, gb.nrm, gb.prim)
+            ctx.trace_probes(fr)
+            if name != "plain":
+                ctx.learned_train(fr)
+            ctx.cache_update(fr)
+            ctx.interpolate_probes(fr, gb.pos, gb.nrm, gb.prim, out)
+    torch.cuda.synchronize()
+    assert ctxs["strict"].learned_stats()["fallback"] and ctxs["strict"].stats()["mlp_fallback"] > 0
+    assert not ctxs["lenient"].learned_stats()["fallback"] and ctxs["lenient"].stats()["mlp_fallback"] == 0
+    # the caches themselves are the same in every mode (the surrogate only changes the gather)
+    tp, ts = ctxs["plain"].table(), ctxs["strict"].table()
+    assert np.array_equal(tp["key"], ts["key"]) and np.array_equal(tp["L"].view(np.uint32), ts["L"].view(np.uint32))
+    nhist = dict(zip(tp["key"].tolist(), tp["nhist"].tolist()))
+    r = ctxs["plain"].rays()
+    P = len(ctxs["plain"].probes()["pos"])
+    hit = (r["cell"] & gi.RAY_HIT) != 0
+    conf = (np.array([nhist.get(int(k), 0) >= 64 for k in r["key"]]) | ~hit).reshape(P, R)
+    cell = (r["cell"] & 63).reshape(P, R)
+    traced = ((r["cell"] & gi.RAY_TRACED) != 0).reshape(P, R)
+    # atlas cells (probe, cell) that received rays, all of them misses or hits in confident cells
+    n_rays = np.zeros((P, 64), int)
+    n_conf = np.zeros((P, 64), int)
+    pp = np.repeat(np.arange(P), R).reshape(P, R)
+    np.add.at(n_rays, (pp[traced], cell[traced]), 1)
+    np.add.at(n_conf, (pp[traced & conf], cell[traced & conf]), 1)
+    sel = (n_rays > 0) & (n_conf == n_rays)
+    assert sel.sum() > 100
+    ap, as_ = ctxs["plain"].probes()["atlas"], ctxs["strict"].probes()["atlas"]
+    assert np.array_equal(ap[sel].view(np.uint32), as_[sel].view(np.uint32))
+    # and where a cell holds a non-confident hit, the surrogate's value is used instead
+    assert not np.array_equal(ap[(n_rays > 0) & ~sel], as_[(n_rays > 0) & ~sel])
+    for ctx in ctxs.values():
+        ctx.close()
+
+
 def _run_frames(scene, sc, W, H, R, frames, mode, **kw):
     ctx = gi.Context(width=W, height=H, rays_per_probe=R, table_log2=20, cache_mode=mode, sky=sc.sky, **kw)
     ctx.build_bvh(sc)
