@@ -48,7 +48,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="field1080")
     ap.add_argument("--profile-frames", type=int, default=5)
-    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-frames", type=int, default=40,
+                    help="oracle frames timed for cpu_baseline (about 0.25 s each on 16 host threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the plain / MLP-BF16 / MLP-FP8 comparison")
     ap.add_argument("--form", default="plain", choices=("plain", "mlp_bf16", "mlp_fp8"),
