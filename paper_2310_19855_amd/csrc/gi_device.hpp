@@ -348,22 +348,30 @@ __device__ inline bool any_hit(const SceneView& sv, const RayQ& r, float tmax, T
       float tn[4];
       uint32_t m = enter_children(r, n, tcull, tn);
       if (m) {
-        // continue with the first entered child, push the others (constant indices only, so
-        // the node stays in registers)
-        bool taken = false;
-        uint32_t next = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (m & (1u << c)) {
-            if (!taken) {
-              next = n.child[c];
-              taken = true;
-            } else {
-              stk.push(n.child[c]);
-            }
-          }
-        }
-        cur = next;
+        // nearest entered child first (occluders near the ray's origin end the walk early),
+        // the others pushed farthest first; 5-exchange sorting network in registers
+        float t0 = (m & 1u) ? tn[0] : __builtin_inff(), t1 = (m & 2u) ? tn[1] : __builtin_inff();
+        float t2 = (m & 4u) ? tn[2] : __builtin_inff(), t3 = (m & 8u) ? tn[3] : __builtin_inff();
+        uint32_t c0 = n.child[0], c1 = n.child[1], c2 = n.child[2], c3 = n.child[3];
+        auto cswap = [](float& ta, uint32_t& ca, float& tb, uint32_t& cb) {
+          const bool sw = tb < ta;
+          const float tt = sw ? tb : ta;
+          tb = sw ? ta : tb;
+          ta = tt;
+          const uint32_t cc = sw ? cb : ca;
+          cb = sw ? ca : cb;
+          ca = cc;
+        };
+        cswap(t0, c0, t1, c1);
+        cswap(t2, c2, t3, c3);
+        cswap(t0, c0, t2, c2);
+        cswap(t1, c1, t3, c3);
+        cswap(t1, c1, t2, c2);
+        const int cnt = __builtin_popcount(m);
+        if (cnt > 3) stk.push(c3);
+        if (cnt > 2) stk.push(c2);
+        if (cnt > 1) stk.push(c1);
+        cur = c0;
         continue;
       }
     } else {

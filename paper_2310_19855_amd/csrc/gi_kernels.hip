@@ -251,37 +251,51 @@ struct CacheArgs {
 __device__ inline int32_t table_lookup(const CacheArgs& c, uint64_t key) {
   const uint32_t b = bucket_of(key, c.bucket_mask), f = fingerprint_of(key);
   const uint4* line = reinterpret_cast<const uint4*>(c.fp + b * kBucket);
+  // the whole 128-B line first (independent loads), then the first slot holding f
+  uint4 v[kBucket / 4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const uint4 v = line[q];
-    if (v.x == f) return (int32_t)(b * kBucket + 4 * q);
-    if (v.y == f) return (int32_t)(b * kBucket + 4 * q + 1);
-    if (v.z == f) return (int32_t)(b * kBucket + 4 * q + 2);
-    if (v.w == f) return (int32_t)(b * kBucket + 4 * q + 3);
+  for (int q = 0; q < (int)kBucket / 4; ++q) v[q] = line[q];
+  int32_t r = -1;
+#pragma unroll
+  for (int q = (int)kBucket / 4 - 1; q >= 0; --q) {
+    if (v[q].w == f) r = 4 * q + 3;
+    if (v[q].z == f) r = 4 * q + 2;
+    if (v[q].y == f) r = 4 * q + 1;
+    if (v[q].x == f) r = 4 * q;
   }
-  return -1;
+  return r < 0 ? -1 : (int32_t)(b * kBucket) + r;
 }
 
-// find-or-insert: the fingerprint is searched in the whole bucket first; otherwise empty
-// slots are claimed in ascending order with compare-and-swap (a CAS that finds our own
-// fingerprint means another lane inserted the same cell)
+// find-or-insert: the fingerprint is searched in the whole bucket first; otherwise the first
+// empty slot is claimed with compare-and-swap.  Each round reads the bucket's fingerprints
+// with coherent loads issued together; a CAS that finds our own fingerprint means another
+// lane inserted the same cell, one that finds another fingerprint starts a new round (at most
+// one per slot, so at most kBucket + 1 rounds).
 __device__ inline int32_t table_insert(const CacheArgs& c, uint64_t key, bool& inserted) {
   inserted = false;
   const int32_t found = table_lookup(c, key);
   if (found >= 0) return found;
   const uint32_t b = bucket_of(key, c.bucket_mask), f = fingerprint_of(key);
-  for (uint32_t s = 0; s < kBucket; ++s) {
-    uint32_t* slot = c.fp + b * kBucket + s;
-    uint32_t cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (cur == f) return (int32_t)(b * kBucket + s);
-    if (cur != 0u) continue;
-    const uint32_t prev = atomicCAS(slot, 0u, f);
-    if (prev == 0u) {
-      c.key[b * kBucket + s] = key;
-      inserted = true;
-      return (int32_t)(b * kBucket + s);
+  uint32_t* line = c.fp + b * kBucket;
+  for (uint32_t round = 0; round <= kBucket; ++round) {
+    uint32_t cur[kBucket];
+#pragma unroll
+    for (uint32_t s = 0; s < kBucket; ++s) cur[s] = __hip_atomic_load(line + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int32_t own = -1, empty = -1;
+#pragma unroll
+    for (int s = (int)kBucket - 1; s >= 0; --s) {
+      if (cur[s] == f) own = s;
+      if (cur[s] == 0u) empty = s;
     }
-    if (prev == f) return (int32_t)(b * kBucket + s);
+    if (own >= 0) return (int32_t)(b * kBucket) + own;
+    if (empty < 0) return -1;
+    const uint32_t prev = atomicCAS(line + empty, 0u, f);
+    if (prev == 0u) {
+      c.key[b * kBucket + (uint32_t)empty] = key;
+      inserted = true;
+      return (int32_t)(b * kBucket) + empty;
+    }
+    if (prev == f) return (int32_t)(b * kBucket) + empty;
   }
   return -1;
 }
