@@ -48,8 +48,8 @@ struct Builder {
   std::vector<BinNode> nodes;
   std::mutex mu;
 
-  static constexpr int kBins = 16;
-  static constexpr uint32_t kLeafMax = 4;
+  static constexpr int kBins = 64;
+  static constexpr uint32_t kLeafMax = 2;
 
   int32_t alloc_pair() {
     std::lock_guard<std::mutex> g(mu);

@@ -20,8 +20,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def kernel_src_hash(key):
-    """hash of the source that defines kernel k_<key> plus the shared headers (None for a kernel
-    that is not the library's): a traffic figure is only valid for the code it was taken on"""
+    """hash of the source that defines kernel k_<key>, the shared headers and the host sources
+    (which lay out what the kernels read, e.g. the BVH); None for a kernel that is not the
+    library's.  A traffic figure is only valid for the code it was taken on."""
     csrc = os.path.join(HERE, "csrc")
     files = sorted(os.listdir(csrc))
     owner = None
@@ -32,7 +33,7 @@ def kernel_src_hash(key):
     if owner is None:
         return None
     h = hashlib.sha256()
-    for f in [owner] + [f for f in files if f.endswith(".hpp")]:
+    for f in [owner] + [f for f in files if f.endswith(".hpp") or f.endswith(".cpp")]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
