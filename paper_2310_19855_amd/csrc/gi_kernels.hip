@@ -535,6 +535,8 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
   __shared__ uint32_t cc[64];
+  __shared__ float cs[64][4];
+  __shared__ uint32_t cn[64];
   const uint32_t p = blockIdx.x;
   const uint32_t lane = threadIdx.x;
   if (mask[p] == kSentinel) {
@@ -570,16 +572,40 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
     rv[j][3] = __uint_as_float(r.y);
     rc[j] = r.w & 63u;
   }
+  cs[lane][0] = cs[lane][1] = cs[lane][2] = cs[lane][3] = 0.0f;
+  cn[lane] = 0u;
   __syncthreads();
-  // per-cell sums in ray order (the same float32 order as a sequential loop)
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  uint32_t cnt = 0;
-  for (uint32_t j = 0; j < R; ++j) {
-    if (rc[j] == lane) {
-      a0 = a0 + rv[j][0]; a1 = a1 + rv[j][1]; a2 = a2 + rv[j][2]; a3 = a3 + rv[j][3];
-      ++cnt;
+  // per-cell sums in ray order (the same float32 order as a sequential loop over the rays):
+  // in each chunk of 64 rays, the lanes whose rays share a cell are found with one ballot per
+  // bit of the cell id, and the first of them folds their rays, in ascending order, into the
+  // cell's running sums
+  for (uint32_t base = 0; base < R; base += 64u) {
+    const uint32_t j = base + lane;
+    const bool on = j < R;
+    const uint32_t c = on ? rc[j] : 0u;
+    uint64_t same = __ballot(on);
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const uint64_t mb = __ballot(on && ((c >> b) & 1u));
+      same &= ((c >> b) & 1u) ? mb : ~mb;
     }
+    if (on && (uint32_t)__ffsll((long long)same) - 1u == lane) {
+      float x0 = cs[c][0], x1 = cs[c][1], x2 = cs[c][2], x3 = cs[c][3];
+      uint32_t k = cn[c];
+      uint64_t m = same;
+      while (m) {
+        const uint32_t i = base + (uint32_t)__ffsll((long long)m) - 1u;
+        m &= m - 1u;
+        x0 = x0 + rv[i][0]; x1 = x1 + rv[i][1]; x2 = x2 + rv[i][2]; x3 = x3 + rv[i][3];
+        ++k;
+      }
+      cs[c][0] = x0; cs[c][1] = x1; cs[c][2] = x2; cs[c][3] = x3;
+      cn[c] = k;
+    }
+    __syncthreads();
   }
+  const float a0 = cs[lane][0], a1 = cs[lane][1], a2 = cs[lane][2], a3 = cs[lane][3];
+  const uint32_t cnt = cn[lane];
   float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
   if (cnt) {
     const float fc = (float)cnt;
