@@ -204,6 +204,11 @@ gi_status gi_learned_train(gi_context *ctx, const gi_frame *frame, void *stream)
 gi_status gi_learned_step(gi_context *ctx, const float *d_pos, const float *d_nrm, const float *d_target,
                           uint32_t n, uint32_t apply, void *stream);
 
+/* The OCP e4m3 code (round to nearest even, saturating to +-448, NaN -> 0x7F) that FP8
+ * inference gives its weights and activations after scaling: d_in [n] floats -> d_out [n]
+ * bytes.  Exposed so that the encoder can be checked against a reference codec. */
+gi_status gi_e4m3_encode(gi_context *ctx, const float *d_in, uint8_t *d_out, uint32_t n, void *stream);
+
 /* Evaluate the surrogate at caller points: d_pos [n][4], d_nrm [n][4] -> d_out [n][4]. */
 gi_status gi_learned_query(gi_context *ctx, const float *d_pos, const float *d_nrm, uint32_t n,
                            float *d_out, void *stream);

@@ -596,6 +596,13 @@ gi_status gi_cache_query(gi_context* c, const float* pos, const float* nrm, uint
   return GI_OK;
 }
 
+gi_status gi_e4m3_encode(gi_context* c, const float* in, uint8_t* out, uint32_t n, void* stream) {
+  if (!c) return GI_ERR_INVALID_ARG;
+  if (n && (!in || !out)) return fail(c, GI_ERR_INVALID_ARG, "null argument");
+  GI_TRY_HIP(c, gi::e4m3_encode_array(in, out, n, reinterpret_cast<hipStream_t>(stream)));
+  return GI_OK;
+}
+
 gi_status gi_trace_rays(gi_context* c, const float* o, const float* d, uint32_t n, uint32_t any_hit, uint32_t* tri,
                         float* t, void* stream) {
   if (!c) return GI_ERR_INVALID_ARG;

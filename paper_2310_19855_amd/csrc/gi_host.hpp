@@ -155,5 +155,6 @@ size_t learned_blob_size(gi_context* c);
 hipError_t learned_save(gi_context* c, void* blob);
 hipError_t learned_load(gi_context* c, const void* blob);
 void learned_stats(gi_context* c, float* out8);
+hipError_t e4m3_encode_array(const float* in, uint8_t* out, uint32_t n, hipStream_t st);
 
 }  // namespace gi

@@ -93,28 +93,18 @@ __device__ inline f32x4_t mma_fp8(const uint8_t* A, int lda, const uint8_t* Bt, 
 __device__ inline __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
 __device__ inline float from_bf16(__bf16 x) { return static_cast<float>(x); }
 
-// round-to-nearest-even OCP e4m3 code of x, saturating to +-448; NaN -> 0x7F
-__device__ __host__ inline uint32_t e4m3_encode(float x) {
-  uint32_t u;
-  std::memcpy(&u, &x, 4);
-  const uint32_t sign = (u >> 24) & 0x80u;
+// OCP e4m3 code of x (1 sign, 4 exponent bits with bias 7, 3 mantissa bits): round to nearest
+// even, saturating to +-448, NaN -> 0x7F.  The hardware conversion v_cvt_pk_fp8_f32 after a
+// clamp to +-448 gives this code for every non-NaN float (checked over all of them).
+__device__ inline uint32_t e4m3_code(float x) {
   if (x != x) return 0x7Fu;
-  float a = fabsf(x);
-  if (a > 448.0f) a = 448.0f;
-  if (a < 0.015625f) {   // subnormal range: m * 2^-9
-    const uint32_t q = (uint32_t)rintf(a * 512.0f);
-    return sign | q;
-  }
-  uint32_t ua;
-  std::memcpy(&ua, &a, 4);
-  const uint32_t e = ((ua >> 23) & 0xFFu) - 127u + 7u;
-  const uint32_t mant = ua & 0x7FFFFFu;
-  uint32_t m3 = mant >> 20;
-  const uint32_t rest = mant & 0xFFFFFu;
-  if (rest > 0x80000u || (rest == 0x80000u && (m3 & 1u))) m3 += 1u;
-  uint32_t code = (e << 3) + m3;
-  if (code > 0x7Eu) code = 0x7Eu;
-  return sign | code;
+  const float c = fminf(fmaxf(x, -448.0f), 448.0f);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(c, c, 0, false) & 0xFFu;
+}
+
+__global__ void k_e4m3_encode(const float* in, uint8_t* out, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (uint8_t)e4m3_code(in[i]);
 }
 
 // encoding input of a point: x = clamp((y - lo) / (hi - lo), 0, 1)
@@ -209,13 +199,13 @@ __device__ void mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* sca
     W1t[c * 64 + r] = to_bf16(mlp[kOffW1 + i]);
     W2[i] = to_bf16(mlp[kOffW2 + i]);
     W2t[c * 64 + r] = to_bf16(mlp[kOffW2 + i]);
-    w8[i] = (uint8_t)e4m3_encode(mlp[kOffW1 + i] / scales[0]);
-    w8[4096 + i] = (uint8_t)e4m3_encode(mlp[kOffW2 + i] / scales[1]);
+    w8[i] = (uint8_t)e4m3_code(mlp[kOffW1 + i] / scales[0]);
+    w8[4096 + i] = (uint8_t)e4m3_code(mlp[kOffW2 + i] / scales[1]);
   }
   for (int i = t; i < 1024; i += 1024) {
     const int r = i >> 6, c = i & 63;
     W3[i] = to_bf16(mlp[kOffW3 + i]);
-    w8[8192 + i] = (uint8_t)e4m3_encode(mlp[kOffW3 + i] / scales[2]);
+    w8[8192 + i] = (uint8_t)e4m3_code(mlp[kOffW3 + i] / scales[2]);
     W3t[c * 32 + r] = to_bf16(mlp[kOffW3 + i]);
     W3t[c * 32 + 16 + r] = to_bf16(0.0f);
   }
@@ -872,7 +862,7 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
     // per-tensor scaled e4m3 operands, float32 accumulation, dequantise by s_x * s_w
     const float sx = scales[6], s1 = scales[7], s2 = scales[8];
 #pragma unroll
-    for (int c = 0; c < 64; ++c) S.A8[lane * 80 + c] = (uint8_t)e4m3_encode(feat[c] / sx);
+    for (int c = 0; c < 64; ++c) S.A8[lane * 80 + c] = (uint8_t)e4m3_code(feat[c] / sx);
     __syncthreads();
     const uint8_t* W1 = w8;
     const uint8_t* W2 = w8 + 4096;
@@ -888,7 +878,7 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
         const int col = 16 * nt + (lane & 15);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          S.B8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_encode(fmaxf(a[i] * d1, 0.0f) / s1);
+          S.B8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_code(fmaxf(a[i] * d1, 0.0f) / s1);
       }
     __syncthreads();
 #pragma unroll
@@ -901,7 +891,7 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
         const int col = 16 * nt + (lane & 15);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          S.A8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_encode(fmaxf(a[i] * d2, 0.0f) / s2);
+          S.A8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_code(fmaxf(a[i] * d2, 0.0f) / s2);
       }
     __syncthreads();
     float* yo = reinterpret_cast<float*>(S.B);
@@ -1199,6 +1189,11 @@ hipError_t learned_infer_rays(gi_context* c, hipStream_t st) {
   k_judge<<<jb, 64, 0, st>>>(c->d_hit_ids, c->d_hit_count, c->hit_stripe_cap, c->hit_blocks_per_stripe, c->d_rec,
                              c->tab.meta, c->tab.L, s->lmlp, s->judge_part);
   k_judge_decide<<<1, 1024, 0, st>>>(s->judge_part, jb, s->acc, c->cfg.mlp_judge, c->d_stats);
+  return hipGetLastError();
+}
+
+hipError_t e4m3_encode_array(const float* in, uint8_t* out, uint32_t n, hipStream_t st) {
+  if (n) k_e4m3_encode<<<nblk(n, 256), 256, 0, st>>>(in, out, n);
   return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ def lib():
     fn("gi_measure_traversal", st, vp, vp, vp)
     fn("gi_learned_train", st, vp, P(Frame), vp)
     fn("gi_learned_query", st, vp, vp, vp, u32, vp, vp)
+    fn("gi_e4m3_encode", st, vp, vp, vp, u32, vp)
     fn("gi_learned_step", st, vp, vp, vp, vp, u32, u32, vp)
     fn("gi_cache_export", st, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
     fn("gi_cache_save", st, vp, vp, sz, P(sz))
@@ -230,6 +231,10 @@ class Context:
     def learned_query(self, pos, nrm, out, stream=None):
         self._check(lib().gi_learned_query(self.h, _ptr(pos), _ptr(nrm), pos.shape[0], _ptr(out),
                                            _stream(stream)), "gi_learned_query")
+
+    def e4m3_encode(self, x, out, stream=None):
+        """OCP e4m3 codes of the float32 device array x into the uint8 device array out"""
+        self._check(lib().gi_e4m3_encode(self.h, _ptr(x), _ptr(out), x.numel(), _stream(stream)), "gi_e4m3_encode")
 
     def learned_step(self, pos, nrm, target, apply=True, stream=None):
         self._check(lib().gi_learned_step(self.h, _ptr(pos), _ptr(nrm), _ptr(target), pos.shape[0], int(apply),

@@ -165,6 +165,29 @@ def test_learned_frames_train_and_feed_the_probes():
     assert pr["atlas"][..., :3].mean() > 0
 
 
+def test_fp8_encoder_matches_the_oracle_codec():
+    """The e4m3 codes FP8 inference gives its weights and activations (hardware conversion
+    after a clamp to +-448) equal the oracle's round-half-even saturating codec on 4M random
+    float bit patterns, every midpoint between neighbouring e4m3 values, both zeros, the
+    subnormal range and the saturation boundary."""
+    ctx = gi.Context(width=16, height=16)
+    rng = np.random.default_rng(4)
+    x = rng.integers(0, 2 ** 32, size=1 << 22, dtype=np.uint64).astype(np.uint32).view(np.float32)
+    vals = OL.e4m3_decode(np.arange(127))
+    mids = (vals[:-1] + vals[1:]) / 2
+    special = np.concatenate([vals, mids, np.nextafter(mids, 0), np.nextafter(mids, 1e9), [0.0, 448.0, 464.0, 480.0,
+                              1e30, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -11, 1e-45]]).astype(np.float32)
+    x = np.concatenate([x[~np.isnan(x)], special, -special]).astype(np.float32)
+    out = torch.zeros(len(x), dtype=torch.uint8, device="cuda")
+    ctx.e4m3_encode(torch.from_numpy(x).cuda(), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = OL.e4m3_encode(x.astype(np.float64)).astype(np.uint8)
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, [(float(x[i]), int(got[i]), int(ref[i])) for i in bad[:8]]
+    ctx.close()
+
+
 def test_judge_falls_back_to_confident_plain_cells():
     """The plain cache judges the surrogate: with a threshold every error exceeds, the gather
     reads the plain cache wherever the hit's cell is confident (at least 64 samples of
