@@ -406,7 +406,8 @@ gi_status gi_build_bvh(gi_context* c, const float* h_verts, uint32_t n_verts, co
     // rest go to one spill row each, per lane id
     if (need > 256) return fail(c, GI_ERR_UNSUPPORTED, "BVH deeper than 85 levels");
     c->stack_depth = need;
-    c->spill_rows = need > 16 ? need - 16 : 0;
+    const uint32_t lds = (uint32_t)gi::kLdsStackEntries;
+    c->spill_rows = need > lds ? need - lds : 0;
     c->spill_stride = std::max(c->P * c->R, c->W * c->H);
     if (c->spill_rows) GI_TRY_HIP(c, dalloc(&c->d_spill, (size_t)c->spill_rows * c->spill_stride));
     std::vector<float4> tris(3 * (size_t)std::max(n_tris, 1u));

@@ -231,26 +231,42 @@ struct SceneView {
 // array, K a power of two); when a push finds them all live, the oldest one moves to a
 // per-lane global array laid out [depth][lane] (coalesced across a wave), and a pop below what
 // LDS holds reads it back.  Live entries [lo, sp) are in LDS, [0, lo) in the spill array.
+// Beside each LDS entry sits the upper half of its entry distance's float bits (a value at or
+// below the distance); spilled entries carry 0.
 template <int K, int BLOCK>
 struct TStack {
   uint32_t* lds;      // &lds_array[lane]
+  uint16_t* tlds;     // &lds_distance_array[lane]
   uint32_t* spill;    // &spill_array[lane id]; entry i at spill[i * stride]
   uint32_t stride;
   int sp, lo;
-  __device__ TStack(uint32_t* l, uint32_t* s, uint32_t st) : lds(l), spill(s), stride(st), sp(0), lo(0) {}
+  __device__ TStack(uint32_t* l, uint16_t* tl, uint32_t* s, uint32_t st)
+      : lds(l), tlds(tl), spill(s), stride(st), sp(0), lo(0) {}
   __device__ void reset() { sp = 0; lo = 0; }
-  __device__ void push(uint32_t v) {
+  __device__ void push(uint32_t v, float t = 0.0f) {
     if (sp - lo == K) {
       spill[(size_t)lo * stride] = lds[(lo & (K - 1)) * BLOCK];
       ++lo;
     }
     lds[(sp & (K - 1)) * BLOCK] = v;
+    tlds[(sp & (K - 1)) * BLOCK] = (uint16_t)(__float_as_uint(t) >> 16);
     ++sp;
   }
   __device__ uint32_t pop() {
     --sp;
     if (sp >= lo) return lds[(sp & (K - 1)) * BLOCK];
     lo = sp;
+    return spill[(size_t)sp * stride];
+  }
+  // pop with the entry's distance bound (0 for an entry read back from the spill array)
+  __device__ uint32_t pop(float& t) {
+    --sp;
+    if (sp >= lo) {
+      t = __uint_as_float((uint32_t)tlds[(sp & (K - 1)) * BLOCK] << 16);
+      return lds[(sp & (K - 1)) * BLOCK];
+    }
+    lo = sp;
+    t = 0.0f;
     return spill[(size_t)sp * stride];
   }
   __device__ bool empty() const { return sp == 0; }
@@ -302,9 +318,9 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
         cswap(t1, c1, t2, c2);
         const int cnt = __builtin_popcount(m);
         if (cnt > 0) {
-          if (cnt > 3) stk.push(c3);
-          if (cnt > 2) stk.push(c2);
-          if (cnt > 1) stk.push(c1);
+          if (cnt > 3) stk.push(c3, t3);
+          if (cnt > 2) stk.push(c2, t2);
+          if (cnt > 1) stk.push(c1, t1);
           cur = c0;
           continue;
         }
@@ -321,8 +337,20 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
           }
         }
       }
-      if (stk.empty()) break;
-      cur = stk.pop();
+      // next entry; an entry whose box starts beyond the best hit found since its push is
+      // dropped without reading its node (its distance bound is at or below its entry distance)
+      const float tcull = best_t * 1.0001221f;
+      bool more = false;
+      while (!stk.empty()) {
+        float te;
+        const uint32_t nx = stk.pop(te);
+        if (te <= tcull) {
+          cur = nx;
+          more = true;
+          break;
+        }
+      }
+      if (!more) break;
     }
   }
   tri_out = best;

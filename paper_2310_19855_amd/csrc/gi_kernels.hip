@@ -7,7 +7,7 @@
 namespace gi {
 
 constexpr int kTraceBlock = 64;   // one wave per block: the LDS part of the stack is [K][64]
-constexpr int kLdsStack = 16;    // traversal-stack entries per lane kept in LDS (the rest spill)
+constexpr int kLdsStack = kLdsStackEntries;   // traversal-stack entries per lane in LDS (the rest spill)
 
 struct ShadeTables {
   const float4* tnrm;    // unit normal, w = material index bits
@@ -27,7 +27,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_gbuffer(SceneView sv, ShadeTabl
                                                          uint32_t H, float4* pos, float4* nrm, float4* alb,
                                                          uint32_t* prim) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
-  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
+  __shared__ uint16_t stkt[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, stkt + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
   if (i >= W * H) return;
   const uint32_t x = i % W, y = i / W;
@@ -184,7 +185,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, Shad
                                                               uint4* rec, uint2* rkey, HitList hl,
                                                               unsigned long long* stats) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
-  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
+  __shared__ uint16_t stkt[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, stkt + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
   if (gid >= a.P * a.R) return;
   const uint32_t p = gid / a.R;
@@ -358,12 +360,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
                                                             LearnedShadeOut lo,
                                                             unsigned long long* stats) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
+  __shared__ uint16_t stkt[STACK * kTraceBlock];
   // block b shades items [w * 64, w * 64 + 64) of list stripe b / blocks_per_stripe
   const uint32_t stripe = blockIdx.x / hl.blocks_per_stripe;
   const uint32_t item = (blockIdx.x % hl.blocks_per_stripe) * kTraceBlock + threadIdx.x;
   if (stripe >= kStatStripes || item >= hl.count[stripe]) return;
   const uint32_t gid = hl.ids[stripe * hl.stripe_cap + item];
-  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + gid, sv.spill_stride);
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, stkt + threadIdx.x, sv.spill + gid, sv.spill_stride);
   const uint4 rr = rec[gid];
   stat_add(stats, GI_STAT_HITS, true);
   const uint32_t p = gid / a.R;
@@ -796,7 +799,8 @@ template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_rays(SceneView sv, const float4* o, const float4* d, uint32_t n,
                                                             uint32_t any, uint32_t* tri, float* t) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
-  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
+  __shared__ uint16_t stkt[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, stkt + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
   if (i >= n) return;
   const float4 a = o[i], b = d[i];
@@ -820,7 +824,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
                                                                  CacheArgs c, const uint4* rec,
                                                                  unsigned long long* out) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
-  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
+  __shared__ uint16_t stkt[STACK * kTraceBlock];
+  TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, stkt + threadIdx.x, sv.spill + (blockIdx.x * kTraceBlock + threadIdx.x), sv.spill_stride);
   const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
   uint32_t pn = 0, pt = 0, sn = 0, st_ = 0;
   bool probe = false, shadow = false;

@@ -23,6 +23,7 @@ constexpr uint32_t kNodeEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kBucketSlots = 32;   // world-cache slots per bucket (one 128-byte line of fingerprints)
 constexpr uint32_t kStatStripesHost = 64;   // copies of the stats counters (and hit-list stripes)
 constexpr int kMaxDyn = 64;
+constexpr int kLdsStackEntries = 16;           // traversal-stack entries per lane kept in LDS
 constexpr int kNumCells = 64;
 
 }  // namespace gi
