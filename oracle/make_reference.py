@@ -52,8 +52,8 @@ def point_reference(st, g, n_points, n_samples, seed=17):
     P = pos.reshape(-1, 4)[pick].astype(np.float64)
     Nn = nrm.reshape(-1, 4)[pick].astype(np.float64)
     A = alb.reshape(-1, 4)[pick, :3].astype(np.float64)
-    fr = I.camera_for("room", 0)
-    fr.index = 1 << 20          # RNG stream of its own
+    fr = I.camera_for("room", 0)  # only the frame index enters NEE: it picks the RNG stream
+    fr.index = 1 << 20            # a stream of its own, apart from the frames' streams
     ids = np.arange(n_samples, dtype=np.uint32)
     L = np.zeros((len(pick), 3))
     se = np.zeros((len(pick), 3))
