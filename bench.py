@@ -199,6 +199,7 @@ def main():
         del ctx
         torch.cuda.empty_cache()
         forms = forms_comparison(log)
+        forms.update(field4k_and_furnace(log))
 
     line = {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
@@ -230,10 +231,12 @@ SWEEP_R = (8, 16, 32, 64, 128)
 SWEEP_FRAMES, SWEEP_TIMED_FROM = 16, 8
 
 
-def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, profile=False):
+def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, profile=False, extra=None,
+             want_out=False):
     """Frames of the pass with the camera and lights frozen at frame 0 (the reference's frame
     state).  Returns GPU ms per timed frame, per-kernel ms, learned stats and, with points
-    (pos, nrm device tensors), the plain cache's lookups and the form's radiance there."""
+    (pos, nrm device tensors), the plain cache's lookups and the form's radiance there; with
+    want_out the last frame's irradiance image (rgb, flag)."""
     import torch
 
     from paper_2310_19855_amd import gi
@@ -241,6 +244,7 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
     cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, cache_mode=FORMS[form])
     if form != "plain":
         cfg.update(MLP_CFG)
+    cfg.update(extra or {})
     ctx = gi.Context(**cfg)
     ctx.build_bvh(scene)
     if scene.dynamic is not None:
@@ -275,6 +279,8 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
         ctx.profile(False)
         kern = {k: round(v[1] / n, 4) for k, v in prof.items()}
     res = {"ms": ms, "kernels": kern, "learned": ctx.learned_stats() if form != "plain" else None}
+    if want_out:
+        res["out"] = out.cpu().numpy()
     if points is not None:
         pp, pn = points
         q = torch.zeros((pp.shape[0], 4), dtype=torch.float32, device="cuda")
@@ -353,6 +359,58 @@ def forms_comparison(log, W=1920, H=1080):
     return out
 
 
+def field4k_and_furnace(log, W=3840, H=2160, R=64):
+    """The field scene at 3840x2160 with FP8 e4m3 inference beside BF16 and the plain cache:
+    ms/frame and the cache radiance's relMAE at the stored float64 point reference (seeded
+    world positions, valid at any resolution of the frame-0 view), 16 frozen frames.  Beside
+    it the closed furnace (Le = 1, albedo 0.8, two bounces, cache values replaced each frame):
+    after frame f every cell holds L_f = albedo (Le + L_{f-1}), L_0 = albedo Le, so a pixel's
+    irradiance is pi (Le + L_f); reported per form is the relMAE of the irradiance image of
+    the last frame against that value."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19855_amd import inputs as I
+    res = {"field4k": {"protocol": f"{W}x{H}, R={R}, frames 0..{SWEEP_FRAMES - 1} with the frame-0 camera "
+                                   f"and lights, ms/frame over frames {SWEEP_TIMED_FROM}..{SWEEP_FRAMES - 1}; "
+                                   "relMAE vs the float64 point reference over the points the plain cache holds"},
+           "furnace": {}}
+    path = os.path.join(ROOT, "tests", "golden", "field480x270_reference.npz")
+    if os.path.exists(path):
+        ref = np.load(path)
+        scene = I.make_scene("field")
+        pts = (torch.from_numpy(ref["point_pos"]).cuda(), torch.from_numpy(ref["point_nrm"]).cuda())
+        Lr = ref["point_L"].astype(np.float64)
+        for form in FORMS:
+            r = run_form("field", scene, W, H, R, form, SWEEP_FRAMES, SWEEP_TIMED_FROM, points=pts)
+            found = r["plain_at_points"][:, 3] > 0
+            L = r["form_at_points"][found, :3].astype(np.float64)
+            e = float(np.abs(L - Lr[found]).sum() / max(np.abs(Lr[found]).sum(), 1e-30))
+            res["field4k"][form] = {"ms_per_frame": round(r["ms"], 4), "relMAE": round(e, 5),
+                                    "points": int(found.sum())}
+            log(f"[bench] field {W}x{H} {form}: relMAE {e:.3f} @ {r['ms']:.2f} ms/frame")
+        del scene
+    fsc = I.make_scene("furnace")
+    fp = I.PRESETS["furnace"]
+    rho, le, frames = 0.8, 1.0, 42
+    L = rho * le
+    for _ in range(1, frames):
+        L = rho * (le + L)
+    E = math.pi * (le + L)
+    res["furnace"]["protocol"] = (f"{fp['width']}x{fp['height']}, R={fp['rays_per_probe']}, two bounces, cache "
+                                  f"values replaced each frame, {frames} frames; closed-form irradiance {E:.6f} "
+                                  f"(limit 5 pi); relMAE of the last frame's irradiance over pixels with a probe")
+    for form in FORMS:
+        r = run_form("furnace", fsc, fp["width"], fp["height"], fp["rays_per_probe"], form, frames, frames - 8,
+                     extra=dict(bounces=2, n_cap=0, cell_scale=0.5, leak_bit=0), want_out=True)
+        o = r["out"]
+        ok = o[..., 3] != 2
+        e = float(np.abs(o[ok][:, :3].astype(np.float64) - E).sum() / (E * 3 * max(int(ok.sum()), 1)))
+        res["furnace"][form] = {"ms_per_frame": round(r["ms"], 4), "relMAE": round(e, 6), "pixels": int(ok.sum())}
+        log(f"[bench] furnace {form}: relMAE {e:.2e} @ {r['ms']:.3f} ms/frame")
+    return res
+
+
 def calibrate_copy(mib):
     """A plain elementwise device copy (read mib MiB, write mib MiB), five times: profiled with
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE it gives the scale of those counters."""
@@ -366,11 +424,12 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_read_bytes": n * 4, "copy_write_bytes": n * 4, "launches": 5}), flush=True)
 
 
-def cpu_baseline(scene, cfg, cams, frames, log):
+def cpu_baseline(scene, cfg, cams, frames, log, single_frames=2):
     """The oracle (plain C, all host threads) on the same scene, config and frames at full
     resolution: spawn -> trace -> update -> interpolate, G-buffer excluded, averaged."""
     import oracle as O
-    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
+    cores = O.set_threads(1)        # the threads the parallel loops use (OMP_NUM_THREADS or all)
+    O.set_threads(cores)
     t0 = time.time()
     osc = O.OracleScene(scene)
     st = O.OracleFrameState(osc, dict(O.default_config(), **cfg))
@@ -384,9 +443,37 @@ def cpu_baseline(scene, cfg, cams, frames, log):
         tot += time.time() - t1
         log(f"[bench] cpu oracle frame {f}: {time.time() - t1:.2f}s")
     ms = tot * 1e3 / frames
+    # the same oracle on one thread: a fresh frame state over the first few frames
+    one = None
+    if single_frames:
+        prev = O.set_threads(1)
+        st1 = O.OracleFrameState(osc, dict(O.default_config(), **cfg))
+        tot1 = 0.0
+        for f in range(single_frames):
+            osc.set_frame_dynamic(f)
+            g = osc.gbuffer(cams[f], cfg["width"], cfg["height"])
+            t1 = time.time()
+            st1.frame(cams[f], g)
+            tot1 += time.time() - t1
+        O.set_threads(prev)
+        one = {"value": round(tot1 * 1e3 / single_frames, 1), "unit": "ms/frame", "cores": 1,
+               "sample": f"frames 0..{single_frames - 1}, fresh cache"}
+        log(f"[bench] cpu oracle, one thread: {one['value']:.0f} ms/frame")
     return {"value": round(ms, 1), "unit": "ms/frame", "cores": cores, "kind": "oracle",
             "sample": f"{frames} full frames (frames 0..{frames - 1}) of the same workload, "
-                      f"spawn..interpolate, G-buffer and BVH build ({t_build:.1f}s) excluded"}
+                      f"spawn..interpolate, G-buffer and BVH build ({t_build:.1f}s) excluded",
+            "host": _host_cpu(), "single_thread": one}
+
+
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -49,6 +49,16 @@ def default_config(**kw) -> dict:
     return cfg
 
 
+def set_threads(n: int) -> int:
+    """Sets the OpenMP thread count of the oracle's parallel loops (the libgomp the oracle
+    libraries link); returns the previous count."""
+    _lib(False)
+    gomp = C.CDLL("libgomp.so.1")
+    prev = int(gomp.omp_get_max_threads())
+    gomp.omp_set_num_threads(C.c_int(int(n)))
+    return prev
+
+
 def _lib(f64: bool):
     key = "64" if f64 else "32"
     if key in _LIBS:
