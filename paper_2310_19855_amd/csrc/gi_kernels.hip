@@ -480,6 +480,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
 __global__ void k_cache_update(uint32_t N, uint32_t* fp, uint64_t* key, uint4* acc, float4* L, uint2* meta,
                                uint32_t* accessed, uint32_t n_cap, uint32_t max_life, uint32_t frac_bits,
                                unsigned long long* stats) {
+  __shared__ uint32_t bcount[2];   // the block's live and evicted slots: one atomic each per block
+  if (threadIdx.x < 2u) bcount[threadIdx.x] = 0u;
+  __syncthreads();
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = false, evicted = false;
   if (s < N && fp[s] != 0u) {
@@ -514,20 +517,38 @@ __global__ void k_cache_update(uint32_t N, uint32_t* fp, uint64_t* key, uint4* a
     acc[s] = make_uint4(0u, 0u, 0u, 0u);
     accessed[s] = 0u;
   }
-  stat_add(stats, GI_STAT_LIVE, live);
-  stat_add(stats, GI_STAT_EVICT, evicted);
+  const uint64_t ml = __ballot(live), me = __ballot(evicted);
+  if ((threadIdx.x & 63u) == 0u) {
+    if (ml) atomicAdd(&bcount[0], (uint32_t)__popcll(ml));
+    if (me) atomicAdd(&bcount[1], (uint32_t)__popcll(me));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0u) {
+    unsigned long long* st = stats + (blockIdx.x % kStatStripes) * GI_STAT_COUNT;
+    if (bcount[0]) atomicAdd(&st[GI_STAT_LIVE], (unsigned long long)bcount[0]);
+    if (bcount[1]) atomicAdd(&st[GI_STAT_EVICT], (unsigned long long)bcount[1]);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
 // Probe gather + radiance backup (Section 2.1.4) + SH projection (Section 2.4.2):
 // one wave per probe, lane = atlas cell
 // ------------------------------------------------------------------------------------------
+
 constexpr int kGatherMaxR = 256;
 
-__device__ inline float wave_sum(float v) {
+// one butterfly step of a transpose-reduce over the first 2H entries of v: lanes whose bit
+// log2(2H) is set keep the upper half, the others the lower half, each adding its partner's copy
+template <int H>
+__device__ inline void transpose_reduce_step(float (&v)[32], uint32_t lane, uint32_t& coef) {
+  const bool up = (lane & (uint32_t)(2 * H)) != 0u;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  for (int i = 0; i < H; ++i) {
+    const float keep = up ? v[H + i] : v[i];
+    const float send = up ? v[i] : v[H + i];
+    v[i] = keep + __shfl_xor(send, 2 * H, 64);
+  }
+  coef += up ? (uint32_t)H : 0u;
 }
 
 __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const float4* pnrm, const uint4* rec,
@@ -537,7 +558,6 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
   __shared__ float rv[kGatherMaxR][4];
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
-  __shared__ uint32_t cc[64];
   __shared__ float cs[64][4];
   __shared__ uint32_t cn[64];
   const uint32_t p = blockIdx.x;
@@ -615,17 +635,15 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
     c0 = a0 / fc; c1 = a1 / fc; c2 = a2 / fc; c3 = a3 / fc;
   }
   cv[lane][0] = c0; cv[lane][1] = c1; cv[lane][2] = c2; cv[lane][3] = c3;
-  cc[lane] = cnt;
+  const uint64_t populated = __ballot(cnt != 0u);
   __syncthreads();
   if (!cnt) {
     // radiance backup: mean of the populated cells, summed in ascending cell order
     float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
-    uint32_t np = 0;
-    for (int i = 0; i < 64; ++i) {
-      if (cc[i]) {
-        m0 = m0 + cv[i][0]; m1 = m1 + cv[i][1]; m2 = m2 + cv[i][2]; m3 = m3 + cv[i][3];
-        ++np;
-      }
+    const uint32_t np = (uint32_t)__popcll(populated);
+    for (uint64_t m = populated; m; m &= m - 1u) {
+      const int i = __ffsll((long long)m) - 1;
+      m0 = m0 + cv[i][0]; m1 = m1 + cv[i][1]; m2 = m2 + cv[i][2]; m3 = m3 + cv[i][3];
     }
     if (np) {
       const float fn = (float)np;
@@ -664,17 +682,27 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
               k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
   const float I[9] = {k0 * om, k1 * mwy, k1 * mwz, k1 * mwx, k2 * Wxy, k2 * Wyz, k20 * (3.0f * Wzz - om),
                       k2 * Wxz, k22 * (Wxx - Wyy)};
-  float out = 0.0f;
+  // the 27 wave sums of c_ch I_l as one transpose-reduce: at each butterfly step a lane keeps
+  // half of its partial sums (the half its lane bit selects) and adds the partner's copy of that
+  // half; after the steps over lane bits 5..1 lane L holds coefficient
+  // k = 16 b5 + 8 b4 + 4 b3 + 2 b2 + b1 summed over 32 lanes, and the step over bit 0 completes it
+  float v[32];
 #pragma unroll
   for (int l = 0; l < 9; ++l) {
-    const float r0 = wave_sum(c0 * I[l]);
-    const float r1 = wave_sum(c1 * I[l]);
-    const float r2 = wave_sum(c2 * I[l]);
-    if (lane == (uint32_t)(3 * l)) out = r0;
-    if (lane == (uint32_t)(3 * l + 1)) out = r1;
-    if (lane == (uint32_t)(3 * l + 2)) out = r2;
+    v[3 * l] = c0 * I[l];
+    v[3 * l + 1] = c1 * I[l];
+    v[3 * l + 2] = c2 * I[l];
   }
-  if (lane < 28) sh[(size_t)p * 28 + lane] = lane < 27 ? out : 0.0f;
+#pragma unroll
+  for (int k = 27; k < 32; ++k) v[k] = 0.0f;
+  uint32_t coef = 0;
+  transpose_reduce_step<16>(v, lane, coef);
+  transpose_reduce_step<8>(v, lane, coef);
+  transpose_reduce_step<4>(v, lane, coef);
+  transpose_reduce_step<2>(v, lane, coef);
+  transpose_reduce_step<1>(v, lane, coef);
+  const float out = v[0] + __shfl_xor(v[0], 1, 64);
+  if ((lane & 1u) == 0u && coef < 28u) sh[(size_t)p * 28 + coef] = coef < 27u ? out : 0.0f;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -694,67 +722,89 @@ __device__ inline uint32_t find_closest_probe(const uint32_t* mask, const MipInf
   return kSentinel;
 }
 
-__device__ inline void sh_irradiance(const float* c, float nx, float ny, float nz, float& e0, float& e1, float& e2) {
-  const float k0 = 0.28209479177387814f, k1 = 0.48860251190291992f, k2 = 1.09254843059207907f,
-              k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
-  const float Y[9] = {k0, k1 * ny, k1 * nz, k1 * nx, k2 * (nx * ny), k2 * (ny * nz),
-                      k20 * (3.0f * (nz * nz) - 1.0f), k2 * (nx * nz), k22 * (nx * nx - ny * ny)};
-  const float A[9] = {3.14159265358979324f, 2.09439510239319549f, 2.09439510239319549f, 2.09439510239319549f,
-                      0.78539816339744831f, 0.78539816339744831f, 0.78539816339744831f, 0.78539816339744831f,
-                      0.78539816339744831f};
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    s0 = s0 + (A[l] * c[3 * l]) * Y[l];
-    s1 = s1 + (A[l] * c[3 * l + 1]) * Y[l];
-    s2 = s2 + (A[l] * c[3 * l + 2]) * Y[l];
+// One wave per 8x8 lattice cell of the jittered probe grid (WAVES cells per block, in a row):
+// all pixels of a cell share the same four neighbour probes (Algorithm 4 depends only on the
+// cell and the offset), so lanes 0..3 find them once and stage their position, normal and
+// A_l-weighted SH coefficients in LDS.  The pixel's G-buffer loads are issued first, so their
+// latency overlaps the search.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_interpolate(const float4* gpos, const float4* gnrm,
+                                                            const uint32_t* gprim, uint32_t W, uint32_t H,
+                                                            uint32_t TW, const uint32_t* mask, MipInfo mi,
+                                                            const float4* ppos, const float4* pnrm, const float* sh,
+                                                            float cx, float cy, float cz, float kappa, int32_t jx,
+                                                            int32_t jy, int32_t bx0, int32_t bx1, int32_t by0,
+                                                            float4* out, unsigned long long* stats) {
+  __shared__ uint32_t nq_s[WAVES][4];
+  __shared__ float4 np_s[WAVES][4], nn_s[WAVES][4];
+  __shared__ float ash_s[WAVES][4][28];
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  uint32_t* nq = nq_s[wv];
+  float4* np4 = np_s[wv];
+  float4* nn4 = nn_s[wv];
+  float(*ash)[28] = ash_s[wv];
+  const int32_t bx = (int32_t)(blockIdx.x * WAVES + wv) + bx0, by = (int32_t)blockIdx.y + by0;
+  const int32_t x = 8 * bx + jx + (int32_t)(lane & 7u), y = 8 * by + jy + (int32_t)(lane >> 3);
+  const bool on = bx <= bx1 && x >= 0 && y >= 0 && x < (int32_t)W && y < (int32_t)H;
+  const uint32_t i = on ? (uint32_t)y * W + (uint32_t)x : 0u;
+  uint32_t prim = kMiss;
+  float4 pp = make_float4(0.f, 0.f, 0.f, 0.f), pn = pp;
+  if (on) {
+    prim = gprim[i];
+    pp = gpos[i];
+    pn = gnrm[i];
   }
-  e0 = s0; e1 = s1; e2 = s2;
-}
-
-__global__ void k_interpolate(const float4* gpos, const float4* gnrm, const uint32_t* gprim, uint32_t W, uint32_t H,
-                              uint32_t TW, const uint32_t* mask, MipInfo mi, const float4* ppos, const float4* pnrm,
-                              const float* sh, float cx, float cy, float cz, float kappa, int32_t jx, int32_t jy,
-                              float4* out, unsigned long long* stats) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lane < 4) {
+    const int32_t ox = lane & 1, oy = lane >> 1;
+    const uint32_t m = bx <= bx1 ? find_closest_probe(mask, mi, 8 * bx, 8 * by, ox, oy) : kSentinel;
+    uint32_t q = kSentinel;
+    if (m != kSentinel) {
+      q = ((m >> 16) >> 3) * TW + ((m & 0xFFFFu) >> 3);
+      np4[lane] = ppos[q];
+      nn4[lane] = pnrm[q];
+    }
+    nq[lane] = q;
+  }
+  __syncthreads();
+  for (uint32_t e = lane; e < 4u * 27u; e += 64u) {
+    const uint32_t k = e / 27u, j = e - 27u * k;
+    const uint32_t q = nq[k];
+    const float A = j < 3u ? 3.14159265358979324f : (j < 12u ? 2.09439510239319549f : 0.78539816339744831f);
+    ash[k][j] = q != kSentinel ? A * sh[(size_t)q * 28 + j] : 0.0f;
+  }
+  __syncthreads();
   bool relaxed = false, none = false;
-  if (i < W * H) {
-    if (gprim[i] == kMiss) {
+  if (on) {
+    if (prim == kMiss) {
       out[i] = make_float4(0.f, 0.f, 0.f, GI_INTERP_SKY);
     } else {
-      const int32_t x = (int32_t)(i % W), y = (int32_t)(i / W);
-      const float4 pp = gpos[i], pn = gnrm[i];
       const float dx = pp.x - cx, dy = pp.y - cy, dz = pp.z - cz;
       const float cell_size = kappa * sqrtf((dx * dx + dy * dy) + dz * dz);
-      const int32_t ux = x - jx, uy = y - jy;
-      const int32_t bx = ux >> 3, by = uy >> 3;
-      const float fx = (float)(ux - 8 * bx) * 0.125f, fy = (float)(uy - 8 * by) * 0.125f;
+      const float fx = (float)(lane & 7u) * 0.125f, fy = (float)(lane >> 3) * 0.125f;
+      const float k0 = 0.28209479177387814f, k1 = 0.48860251190291992f, k2 = 1.09254843059207907f,
+                  k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
+      const float Y[9] = {k0, k1 * pn.y, k1 * pn.z, k1 * pn.x, k2 * (pn.x * pn.y), k2 * (pn.y * pn.z),
+                          k20 * (3.0f * (pn.z * pn.z) - 1.0f), k2 * (pn.x * pn.z), k22 * (pn.x * pn.x - pn.y * pn.y)};
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, ws = 0.f;
       float r0 = 0.f, r1 = 0.f, r2 = 0.f;   // equal-weight sum for the relaxed fallback
       int nf = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
+        if (nq[k] == kSentinel) continue;
         const int32_t ox = k & 1, oy = k >> 1;
-        const uint32_t m = find_closest_probe(mask, mi, 8 * bx, 8 * by, ox, oy);
-        if (m == kSentinel) continue;
-        const uint32_t q = ((m >> 16) >> 3) * TW + ((m & 0xFFFFu) >> 3);
-        const float4 qp = ppos[q], qn = pnrm[q];
+        const float4 qp = np4[k], qn = nn4[k];
         const float wb = (ox ? fx : 1.0f - fx) * (oy ? fy : 1.0f - fy);
         const float pd = fabsf(((qp.x - pp.x) * pn.x + (qp.y - pp.y) * pn.y) + (qp.z - pp.z) * pn.z);
         const float nd = (pn.x * qn.x + pn.y * qn.y) + pn.z * qn.z;
         const float w = (pd <= cell_size) ? wb * fmaxf(0.0f, nd) : 0.0f;
-        float c[27];
-        const float4* s4 = reinterpret_cast<const float4*>(sh + (size_t)q * 28);
+        // irradiance from the probe's SH at this pixel's normal: sum over l of (A_l c_l) Y_l(n)
+        float E0 = 0.f, E1 = 0.f, E2 = 0.f;
 #pragma unroll
-        for (int v = 0; v < 7; ++v) {
-          const float4 t = s4[v];
-          if (4 * v < 27) c[4 * v] = t.x;
-          if (4 * v + 1 < 27) c[4 * v + 1] = t.y;
-          if (4 * v + 2 < 27) c[4 * v + 2] = t.z;
-          if (4 * v + 3 < 27) c[4 * v + 3] = t.w;
+        for (int l = 0; l < 9; ++l) {
+          E0 = E0 + ash[k][3 * l] * Y[l];
+          E1 = E1 + ash[k][3 * l + 1] * Y[l];
+          E2 = E2 + ash[k][3 * l + 2] * Y[l];
         }
-        float E0, E1, E2;
-        sh_irradiance(c, pn.x, pn.y, pn.z, E0, E1, E2);
         r0 = r0 + E0; r1 = r1 + E1; r2 = r2 + E2;
         a0 = a0 + w * E0; a1 = a1 + w * E1; a2 = a2 + w * E2;
         ws = ws + w;
@@ -1038,8 +1088,13 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
 hipError_t launch_interpolate(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, float4* out,
                               hipStream_t s) {
   const MipInfo mi = mip_info(c);
-  const uint32_t n = c->W * c->H;
-  GI_TIMED(c, "interpolate", s, (k_interpolate<<<blocks(n, 256), 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->d_mask, mi, c->d_ppos, c->d_pnrm, c->d_sh, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, (int32_t)c->fa.jx, (int32_t)c->fa.jy, out, c->d_stats)));
+  // lattice cells (base = floor((pixel - jitter) / 8)) that hold at least one pixel
+  const int32_t jx = (int32_t)c->fa.jx, jy = (int32_t)c->fa.jy;
+  const int32_t bx0 = (0 - jx) >> 3, by0 = (0 - jy) >> 3;
+  const int32_t bx1 = ((int32_t)c->W - 1 - jx) >> 3, by1 = ((int32_t)c->H - 1 - jy) >> 3;
+  constexpr int kWaves = 4;
+  const dim3 grid((uint32_t)(bx1 - bx0 + kWaves) / kWaves, (uint32_t)(by1 - by0 + 1));
+  GI_TIMED(c, "interpolate", s, (k_interpolate<kWaves><<<grid, 64 * kWaves, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->d_mask, mi, c->d_ppos, c->d_pnrm, c->d_sh, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, jx, jy, bx0, bx1, by0, out, c->d_stats)));
   return hipGetLastError();
 }
 
