@@ -272,6 +272,88 @@ struct TStack {
   __device__ bool empty() const { return sp == 0; }
 };
 
+// ---- closest-hit BVH walks ----
+// Both visit every node whose box the ray enters at or before the best hit found so far (with
+// the conservative margins), so both return the same (t, triangle) minimum.
+
+// nearest-first order of the entered children; pushes the farther ones with their entry
+// distance and returns the nearest (kNodeEmpty when none is entered)
+template <int K, int BLOCK>
+__device__ inline uint32_t visit_node(const Node4& n, const RayQ& r, float tcull, TStack<K, BLOCK>& stk) {
+  float tn[4];
+  const uint32_t m = enter_children(r, n, tcull, tn);
+  // 5-exchange sorting network held in registers (children not entered sort last, t = +inf)
+  float t0 = (m & 1u) ? tn[0] : __builtin_inff(), t1 = (m & 2u) ? tn[1] : __builtin_inff();
+  float t2 = (m & 4u) ? tn[2] : __builtin_inff(), t3 = (m & 8u) ? tn[3] : __builtin_inff();
+  uint32_t c0 = n.child[0], c1 = n.child[1], c2 = n.child[2], c3 = n.child[3];
+  auto cswap = [](float& ta, uint32_t& ca, float& tb, uint32_t& cb) {
+    const bool sw = tb < ta;
+    const float tt = sw ? tb : ta;
+    tb = sw ? ta : tb;
+    ta = tt;
+    const uint32_t cc = sw ? cb : ca;
+    cb = sw ? ca : cb;
+    ca = cc;
+  };
+  cswap(t0, c0, t1, c1);
+  cswap(t2, c2, t3, c3);
+  cswap(t0, c0, t2, c2);
+  cswap(t1, c1, t3, c3);
+  cswap(t1, c1, t2, c2);
+  const int cnt = __builtin_popcount(m);
+  if (cnt > 3) stk.push(c3, t3);
+  if (cnt > 2) stk.push(c2, t2);
+  if (cnt > 1) stk.push(c1, t1);
+  return cnt > 0 ? c0 : kNodeEmpty;
+}
+
+// next stack entry whose box may still hold a better hit: an entry whose box starts beyond
+// tcull is dropped without reading its node (its distance bound is at or below its entry
+// distance); kNodeEmpty once the stack is empty
+template <int K, int BLOCK>
+__device__ inline uint32_t next_entry(TStack<K, BLOCK>& stk, float tcull) {
+  while (!stk.empty()) {
+    float te;
+    const uint32_t nx = stk.pop(te);
+    if (te <= tcull) return nx;
+  }
+  return kNodeEmpty;
+}
+
+template <bool COUNT>
+__device__ inline void test_leaf(const SceneView& sv, const RayQ& r, float tmax, uint32_t leaf, uint32_t& best,
+                                 float& best_t, uint32_t* n_tris) {
+  const uint32_t first = leaf & kLeafFirstMask;
+  const uint32_t count = ((leaf >> kLeafCountShift) & kLeafCountMask) + 1u;
+  if (COUNT) *n_tris += count;
+  for (uint32_t i = 0; i < count; ++i) {
+    const float4 a = sv.tris[3 * (first + i)], b = sv.tris[3 * (first + i) + 1], c = sv.tris[3 * (first + i) + 2];
+    float t;
+    if (hit_triangle(r, a, b, c, tmax, t)) {
+      const uint32_t id = __float_as_uint(a.w);
+      if (t < best_t || (t == best_t && id < best)) { best_t = t; best = id; }
+    }
+  }
+}
+
+// one node or one leaf per step
+template <int K, int BLOCK, bool COUNT>
+__device__ inline void walk_closest(const SceneView& sv, const RayQ& r, float tmax, TStack<K, BLOCK>& stk,
+                                    uint32_t& best, float& best_t, uint32_t* n_nodes, uint32_t* n_tris) {
+  stk.reset();
+  uint32_t cur = 0;   // root is always an inner node
+  while (cur != kNodeEmpty) {
+    if (!(cur & kLeafBit)) {
+      if (COUNT) ++*n_nodes;
+      cur = visit_node(sv.nodes[cur], r, best_t * 1.0001221f, stk);
+      if (cur != kNodeEmpty) continue;
+    } else {
+      test_leaf<COUNT>(sv, r, tmax, cur, best, best_t, n_tris);
+    }
+    cur = next_entry(stk, best_t * 1.0001221f);
+  }
+}
+
 // Closest hit: lexicographic minimum of (t, triangle index) over every triangle; the BVH walk
 // only prunes boxes that cannot hold a better hit.
 template <int K, int BLOCK, bool COUNT = false>
@@ -288,71 +370,7 @@ __device__ inline void closest_hit(const SceneView& sv, const RayQ& r, float tma
       if (t < best_t || (t == best_t && id < best)) { best_t = t; best = id; }
     }
   }
-  if (sv.has_bvh) {
-    stk.reset();
-    uint32_t cur = 0;   // root is always an inner node
-    while (true) {
-      if (!(cur & kLeafBit)) {
-        const Node4 n = sv.nodes[cur];
-        if (COUNT) ++*n_nodes;
-        float tn[4];
-        uint32_t m = enter_children(r, n, best_t * 1.0001221f, tn);
-        // order the entered children nearest first with a 5-exchange sorting network held in
-        // registers (children not entered sort last with t = +inf)
-        float t0 = (m & 1u) ? tn[0] : __builtin_inff(), t1 = (m & 2u) ? tn[1] : __builtin_inff();
-        float t2 = (m & 4u) ? tn[2] : __builtin_inff(), t3 = (m & 8u) ? tn[3] : __builtin_inff();
-        uint32_t c0 = n.child[0], c1 = n.child[1], c2 = n.child[2], c3 = n.child[3];
-        auto cswap = [](float& ta, uint32_t& ca, float& tb, uint32_t& cb) {
-          const bool sw = tb < ta;
-          const float tt = sw ? tb : ta;
-          tb = sw ? ta : tb;
-          ta = tt;
-          const uint32_t cc = sw ? cb : ca;
-          cb = sw ? ca : cb;
-          ca = cc;
-        };
-        cswap(t0, c0, t1, c1);
-        cswap(t2, c2, t3, c3);
-        cswap(t0, c0, t2, c2);
-        cswap(t1, c1, t3, c3);
-        cswap(t1, c1, t2, c2);
-        const int cnt = __builtin_popcount(m);
-        if (cnt > 0) {
-          if (cnt > 3) stk.push(c3, t3);
-          if (cnt > 2) stk.push(c2, t2);
-          if (cnt > 1) stk.push(c1, t1);
-          cur = c0;
-          continue;
-        }
-      } else {
-        const uint32_t first = cur & kLeafFirstMask;
-        const uint32_t count = ((cur >> kLeafCountShift) & kLeafCountMask) + 1u;
-        if (COUNT) *n_tris += count;
-        for (uint32_t i = 0; i < count; ++i) {
-          const float4 a = sv.tris[3 * (first + i)], b = sv.tris[3 * (first + i) + 1], c = sv.tris[3 * (first + i) + 2];
-          float t;
-          if (hit_triangle(r, a, b, c, tmax, t)) {
-            const uint32_t id = __float_as_uint(a.w);
-            if (t < best_t || (t == best_t && id < best)) { best_t = t; best = id; }
-          }
-        }
-      }
-      // next entry; an entry whose box starts beyond the best hit found since its push is
-      // dropped without reading its node (its distance bound is at or below its entry distance)
-      const float tcull = best_t * 1.0001221f;
-      bool more = false;
-      while (!stk.empty()) {
-        float te;
-        const uint32_t nx = stk.pop(te);
-        if (te <= tcull) {
-          cur = nx;
-          more = true;
-          break;
-        }
-      }
-      if (!more) break;
-    }
-  }
+  if (sv.has_bvh) walk_closest<K, BLOCK, COUNT>(sv, r, tmax, stk, best, best_t, n_nodes, n_tris);
   tri_out = best;
   t_out = best == kMiss ? 0.0f : best_t;
 }
