@@ -22,6 +22,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES = 128, 48
+# fp32 ALU operations of the traversal tests (adds, multiplies, min/max, compares, one divide
+# per triangle): 26 per child box of a 4-wide node (12 for the slab distances, 12 for entry and
+# exit, 2 compares), 53 per watertight triangle test (9 translations, 12 for the shear, 9 for
+# the edge functions, 9 sign and zero tests, 3 for the determinant, 8 for the scaled distance,
+# the divide and 2 range compares)
+NODE_OPS, TRI_OPS = 104, 53
+# one fp32 operation per lane per cycle without packed or fused forms: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (the 157.3 TFLOP/s vector peak counts a packed FMA as 4)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+ALU_BOUND = ("trace_probes", "shade_hits")
 
 
 def _traffic(kernel, workload, form):
@@ -179,14 +189,31 @@ def main():
             v["gbs"] = alg[name] / (v["avg_ms"] * 1e-3) / 1e9
             v["frac_hbm"] = v["gbs"] / HBM_PEAK_GBS
         v["share"] = v["avg_ms"] * v["launches"] / max(args.profile_frames, 1) / total_ms if total_ms else None
+    # the traversal kernels are bound by VALU issue (their node and triangle bytes come from L2
+    # and the Infinity Cache): their roofline is fp32 ALU operations against the VALU peak
+    alg_ops = {"trace_probes": trav["probe_nodes"] * NODE_OPS + trav["probe_tris"] * TRI_OPS,
+               "shade_hits": trav["shadow_nodes"] * NODE_OPS + trav["shadow_tris"] * TRI_OPS}
+    for name, v in kern.items():
+        if name in alg_ops:
+            v["alg_ops"] = int(alg_ops[name])
+            v["tops"] = alg_ops[name] / (v["avg_ms"] * 1e-3) / 1e12
+            v["frac_alu"] = v["tops"] / VALU_PEAK_TOPS
     dk = kern[dom]
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dk.get("gbs", 0.0), 2),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dk.get("frac_hbm", 0.0), 5),
-                "traffic": _traffic(dom, args.workload, args.form),
-                "alg_bytes_per_launch": dk.get("alg_bytes"), "avg_launch_ms": dk["avg_ms"],
-                "bytes_per_probe_ray": (trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES) / pr_rays,
-                "nodes_per_probe_ray": trav["probe_nodes"] / pr_rays,
-                "tris_per_probe_ray": trav["probe_tris"] / pr_rays}
+    view_hbm = {"alg_bytes_per_launch": dk.get("alg_bytes"), "achieved_gbs": round(dk.get("gbs", 0.0), 2),
+                "peak_gbs": HBM_PEAK_GBS, "frac": round(dk.get("frac_hbm", 0.0), 5)}
+    if dom in ALU_BOUND:
+        roofline = {"kernel": dom, "bound": "alu", "achieved": round(dk["tops"], 3), "peak": round(VALU_PEAK_TOPS, 2),
+                    "unit": "TFLOP/s", "frac": round(dk["frac_alu"], 5),
+                    "traffic": _traffic(dom, args.workload, args.form),
+                    "alg_ops_per_launch": dk["alg_ops"], "hbm_view": view_hbm}
+    else:
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": view_hbm["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": view_hbm["frac"], "traffic": _traffic(dom, args.workload, args.form),
+                    "alg_bytes_per_launch": dk.get("alg_bytes")}
+    roofline.update({"avg_launch_ms": dk["avg_ms"],
+                     "bytes_per_probe_ray": (trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES) / pr_rays,
+                     "nodes_per_probe_ray": trav["probe_nodes"] / pr_rays,
+                     "tris_per_probe_ray": trav["probe_tris"] / pr_rays})
     log(f"[bench] kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms x{v['launches'] // max(args.profile_frames, 1)}"
                                          for k, v in sorted(kern.items(), key=lambda kv: -kv[1]['avg_ms'] * kv[1]['launches'])))
 
