@@ -3,6 +3,8 @@
 #include "gi_host.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <stdexcept>
 #include <cmath>
 #include <cstring>
 #include <future>
@@ -38,18 +40,62 @@ struct Box {
 struct BinNode {
   Box box;
   int32_t left = -1, right = -1;   // children in the binary node array (inner)
-  uint32_t first = 0, count = 0;   // leaf range in the reordered triangle index array
+  uint32_t count = 0;              // leaf: number of triangles
+  uint32_t tri[2] = {0, 0};        // leaf: triangle indices
 };
 
+// A reference: one triangle, or the part of it inside a region of space left by spatial
+// splits, with a box that contains that part.
+struct Ref {
+  Box box;
+  uint32_t tri;
+};
+
+// the float at or below / at or above a double
+inline float round_down(double x) {
+  const float f = (float)x;
+  return (double)f > x ? std::nextafter(f, -INFINITY) : f;
+}
+inline float round_up(double x) {
+  const float f = (float)x;
+  return (double)f < x ? std::nextafter(f, INFINITY) : f;
+}
+
+inline bool empty(const Box& b) { return b.lo[0] > b.hi[0] || b.lo[1] > b.hi[1] || b.lo[2] > b.hi[2]; }
+
+inline Box intersect(const Box& a, const Box& b) {
+  Box r;
+  for (int k = 0; k < 3; ++k) {
+    r.lo[k] = std::max(a.lo[k], b.lo[k]);
+    r.hi[k] = std::min(a.hi[k], b.hi[k]);
+  }
+  return r;
+}
+
+// Binned SAH binary tree with spatial splits (Stich, Friedrich and Dietrich 2009).  Where the
+// best object split leaves children whose boxes overlap by more than a small fraction of the
+// scene's area, splitting space at a plane is tried as well: triangles that straddle the plane
+// go to both sides, each with the box of its part on that side.  Those boxes are computed in
+// double and rounded outward, so every point of a triangle lies in the box of one of its
+// references, and a conservative walk finds every hit.
 struct Builder {
-  const std::vector<Box>* tri_box;
-  const std::vector<float>* cen;   // [n][3]
-  std::vector<uint32_t>* ids;
+  const float* tv;                 // [n][9]
   std::vector<BinNode> nodes;
   std::mutex mu;
+  std::atomic<int64_t> budget{0};  // references spatial splits may still add
+  double min_overlap = 0.0;        // overlap area above which spatial splits are tried
 
   static constexpr int kBins = 64;
+  static constexpr int kSpatialBins = 32;
   static constexpr uint32_t kLeafMax = 2;
+
+  struct Split {
+    double cost = 1e300;
+    int axis = -1;
+    int bin = -1;
+    float pos = 0.0f;
+    Box lbox, rbox;
+  };
 
   int32_t alloc_pair() {
     std::lock_guard<std::mutex> g(mu);
@@ -58,37 +104,52 @@ struct Builder {
     return (int32_t)nodes.size() - 2;
   }
 
-  // builds node `ni` over ids[first, first+count); returns nothing, fills nodes[ni]
-  void build(int32_t ni, uint32_t first, uint32_t count, int depth) {
-    Box box, cbox;
-    for (uint32_t i = first; i < first + count; ++i) {
-      const uint32_t t = (*ids)[i];
-      box.grow((*tri_box)[t]);
-      cbox.grow(&(*cen)[3 * (size_t)t]);
+  // boxes of the parts of reference r on either side of the plane x_a = pos
+  void clip(const Ref& r, int a, float pos, Box& lb, Box& rb) const {
+    lb = Box();
+    rb = Box();
+    const float* v = tv + 9 * (size_t)r.tri;
+    for (int e = 0; e < 3; ++e) {
+      const float* p = v + 3 * e;
+      const float* q = v + 3 * ((e + 1) % 3);
+      if (p[a] <= pos) lb.grow(p);
+      if (p[a] >= pos) rb.grow(p);
+      if ((p[a] < pos && q[a] > pos) || (p[a] > pos && q[a] < pos)) {
+        const double t = ((double)pos - p[a]) / ((double)q[a] - p[a]);
+        Box x;
+        for (int k = 0; k < 3; ++k) {
+          if (k == a) {
+            x.lo[k] = x.hi[k] = pos;
+          } else {
+            const double c = p[k] + t * ((double)q[k] - p[k]);
+            x.lo[k] = round_down(c);
+            x.hi[k] = round_up(c);
+          }
+        }
+        lb.grow(x);
+        rb.grow(x);
+      }
     }
-    BinNode node;
-    node.box = box;
-    if (count <= kLeafMax) {
-      node.first = first;
-      node.count = count;
-      std::lock_guard<std::mutex> g(mu);
-      nodes[ni] = node;
-      return;
-    }
-    // binned SAH over all three axes
-    double best_cost = 1e300;
-    int best_axis = -1, best_split = -1;
+    lb = intersect(lb, r.box);
+    rb = intersect(rb, r.box);
+    lb.hi[a] = std::min(lb.hi[a], pos);
+    rb.lo[a] = std::max(rb.lo[a], pos);
+  }
+
+  // binned SAH over the centroids of the reference boxes, all three axes
+  Split object_split(const std::vector<Ref>& refs, const Box& cbox) const {
+    Split best;
     for (int a = 0; a < 3; ++a) {
       const float ext = cbox.hi[a] - cbox.lo[a];
       if (!(ext > 0.0f)) continue;
       Box bb[kBins];
       uint32_t bc[kBins] = {0};
       const double k = kBins / (double)ext * (1.0 - 1e-6);
-      for (uint32_t i = first; i < first + count; ++i) {
-        const uint32_t t = (*ids)[i];
-        int b = (int)((((*cen)[3 * (size_t)t + a]) - cbox.lo[a]) * k);
+      for (const Ref& r : refs) {
+        const float c = (r.box.lo[a] + r.box.hi[a]) * 0.5f;
+        int b = (int)((c - cbox.lo[a]) * k);
         b = std::min(std::max(b, 0), kBins - 1);
-        bb[b].grow((*tri_box)[t]);
+        bb[b].grow(r.box);
         bc[b]++;
       }
       Box lb[kBins];
@@ -109,27 +170,161 @@ struct Builder {
         const uint32_t l = lc[b - 1];
         if (l == 0 || rc == 0) continue;
         const double cost = lb[b - 1].area() * l + racc.area() * rc;
-        if (cost < best_cost) {
-          best_cost = cost;
-          best_axis = a;
-          best_split = b;
+        if (cost < best.cost) {
+          best.cost = cost;
+          best.axis = a;
+          best.bin = b;
+          best.lbox = lb[b - 1];
+          best.rbox = racc;
         }
       }
     }
-    uint32_t mid;
-    if (best_axis < 0) {
-      mid = first + count / 2;   // all centroids coincide: split the list in half
-    } else {
-      const float ext = cbox.hi[best_axis] - cbox.lo[best_axis];
-      const double k = kBins / (double)ext * (1.0 - 1e-6);
-      auto it = std::partition(ids->begin() + first, ids->begin() + first + count, [&](uint32_t t) {
-        int b = (int)((((*cen)[3 * (size_t)t + best_axis]) - cbox.lo[best_axis]) * k);
-        b = std::min(std::max(b, 0), kBins - 1);
-        return b < best_split;
-      });
-      mid = (uint32_t)(it - ids->begin());
-      if (mid == first || mid == first + count) mid = first + count / 2;
+    return best;
+  }
+
+  // spatial bins over the node's box: each reference is chopped into the bins it spans
+  Split spatial_split(const std::vector<Ref>& refs, const Box& box) const {
+    Split best;
+    for (int a = 0; a < 3; ++a) {
+      const float lo = box.lo[a], ext = box.hi[a] - box.lo[a];
+      if (!(ext > 0.0f)) continue;
+      float pos[kSpatialBins + 1];
+      for (int b = 0; b <= kSpatialBins; ++b) pos[b] = lo + ext * ((float)b / (float)kSpatialBins);
+      pos[kSpatialBins] = box.hi[a];
+      const double k = kSpatialBins / (double)ext;
+      auto bin_of = [&](float x) { return std::min(std::max((int)((x - lo) * k), 0), kSpatialBins - 1); };
+      Box bb[kSpatialBins];
+      uint32_t enter[kSpatialBins] = {0}, leave[kSpatialBins] = {0};
+      for (const Ref& r : refs) {
+        const int b0 = bin_of(r.box.lo[a]), b1 = bin_of(r.box.hi[a]);
+        Ref cur = r;
+        for (int b = b0; b < b1; ++b) {
+          Box l, rr;
+          clip(cur, a, pos[b + 1], l, rr);
+          if (!empty(l)) bb[b].grow(l);
+          cur.box = rr;
+        }
+        if (!empty(cur.box)) bb[b1].grow(cur.box);
+        enter[b0]++;
+        leave[b1]++;
+      }
+      Box lb[kSpatialBins];
+      uint32_t lc[kSpatialBins];
+      Box acc;
+      uint32_t c = 0;
+      for (int b = 0; b < kSpatialBins; ++b) {
+        acc.grow(bb[b]);
+        c += enter[b];
+        lb[b] = acc;
+        lc[b] = c;
+      }
+      Box racc;
+      uint32_t rc = 0;
+      for (int b = kSpatialBins - 1; b >= 1; --b) {
+        racc.grow(bb[b]);
+        rc += leave[b];
+        const uint32_t l = lc[b - 1];
+        if (l == 0 || rc == 0) continue;
+        const double cost = lb[b - 1].area() * l + racc.area() * rc;
+        if (cost < best.cost) {
+          best.cost = cost;
+          best.axis = a;
+          best.bin = b;
+          best.pos = pos[b];
+          best.lbox = lb[b - 1];
+          best.rbox = racc;
+        }
+      }
     }
+    return best;
+  }
+
+  // splits refs by the plane; false (refs untouched) if one side would keep every reference
+  // or the reference budget is spent
+  bool apply_spatial(std::vector<Ref>& refs, const Split& sp, std::vector<Ref>& left,
+                     std::vector<Ref>& right) {
+    const int a = sp.axis;
+    int64_t extra = 0;
+    for (const Ref& r : refs) extra += r.box.lo[a] < sp.pos && r.box.hi[a] > sp.pos;
+    if (budget.fetch_sub(extra) < extra) {
+      budget.fetch_add(extra);
+      return false;
+    }
+    left.clear();
+    right.clear();
+    for (const Ref& r : refs) {
+      if (r.box.hi[a] <= sp.pos) {
+        left.push_back(r);
+      } else if (r.box.lo[a] >= sp.pos) {
+        right.push_back(r);
+      } else {
+        Box lb, rb;
+        clip(r, a, sp.pos, lb, rb);
+        if (!empty(lb)) left.push_back(Ref{lb, r.tri});
+        if (!empty(rb)) right.push_back(Ref{rb, r.tri});
+      }
+    }
+    if (left.size() == refs.size() || right.size() == refs.size() || left.empty() || right.empty()) {
+      budget.fetch_add(extra);
+      return false;
+    }
+    return true;
+  }
+
+  // builds node ni over refs (consumed)
+  void build(int32_t ni, std::vector<Ref>& refs, int depth) {
+    Box box, cbox;
+    for (const Ref& r : refs) {
+      box.grow(r.box);
+      const float c[3] = {(r.box.lo[0] + r.box.hi[0]) * 0.5f, (r.box.lo[1] + r.box.hi[1]) * 0.5f,
+                          (r.box.lo[2] + r.box.hi[2]) * 0.5f};
+      cbox.grow(c);
+    }
+    BinNode node;
+    node.box = box;
+    if (refs.size() <= kLeafMax) {
+      node.count = (uint32_t)refs.size();
+      for (uint32_t i = 0; i < node.count; ++i) node.tri[i] = refs[i].tri;
+      std::lock_guard<std::mutex> g(mu);
+      nodes[ni] = node;
+      return;
+    }
+    const Split os = object_split(refs, cbox);
+    std::vector<Ref> left, right;
+    bool done = false;
+    if (os.axis >= 0 && budget.load() > 0 && intersect(os.lbox, os.rbox).area() > min_overlap &&
+        !empty(intersect(os.lbox, os.rbox))) {
+      const Split ss = spatial_split(refs, box);
+      if (ss.axis >= 0 && ss.cost < os.cost) done = apply_spatial(refs, ss, left, right);
+    }
+    if (!done) {
+      left.clear();
+      right.clear();
+      if (os.axis < 0) {
+        // all centroids coincide: split the list in half
+        const size_t h = refs.size() / 2;
+        left.assign(refs.begin(), refs.begin() + h);
+        right.assign(refs.begin() + h, refs.end());
+      } else {
+        const int a = os.axis;
+        const float ext = cbox.hi[a] - cbox.lo[a];
+        const double k = kBins / (double)ext * (1.0 - 1e-6);
+        for (const Ref& r : refs) {
+          const float c = (r.box.lo[a] + r.box.hi[a]) * 0.5f;
+          int b = (int)((c - cbox.lo[a]) * k);
+          b = std::min(std::max(b, 0), kBins - 1);
+          (b < os.bin ? left : right).push_back(r);
+        }
+        if (left.empty() || right.empty()) {
+          left.clear();
+          right.clear();
+          const size_t h = refs.size() / 2;
+          left.assign(refs.begin(), refs.begin() + h);
+          right.assign(refs.begin() + h, refs.end());
+        }
+      }
+    }
+    std::vector<Ref>().swap(refs);
     const int32_t l = alloc_pair();
     node.left = l;
     node.right = l + 1;
@@ -137,26 +332,30 @@ struct Builder {
       std::lock_guard<std::mutex> g(mu);
       nodes[ni] = node;
     }
-    const uint32_t nl = mid - first, nr = first + count - mid;
-    if (count > 200000 && depth < 5) {
-      auto fut = std::async(std::launch::async, [&, l, first, nl, depth] { build(l, first, nl, depth + 1); });
-      build(l + 1, mid, nr, depth + 1);
+    if (left.size() + right.size() > 200000 && depth < 5) {
+      auto fut = std::async(std::launch::async, [&, l, depth] { build(l, left, depth + 1); });
+      build(l + 1, right, depth + 1);
       fut.get();
     } else {
-      build(l, first, nl, depth + 1);
-      build(l + 1, mid, nr, depth + 1);
+      build(l, left, depth + 1);
+      build(l + 1, right, depth + 1);
     }
   }
 };
 
-// copy of a binary node snapshot (the vector may not grow any more at collapse time)
+// copy of a binary node snapshot (the vector may not grow any more at collapse time); leaves
+// receive their triangle ranges in the order they are emitted
 struct Collapser {
   const std::vector<BinNode>& bin;
   std::vector<Node4>& out;
+  std::vector<uint32_t>& order;
   uint32_t max_depth = 0;
 
-  uint32_t leaf_ref(const BinNode& b) const {
-    return kLeafBit | ((b.count - 1u) << kLeafCountShift) | (b.first & kLeafFirstMask);
+  uint32_t leaf_ref(const BinNode& b) {
+    const uint32_t first = (uint32_t)order.size();
+    if (first + b.count - 1u > kLeafFirstMask) throw std::length_error("too many triangle references for a leaf index");
+    for (uint32_t i = 0; i < b.count; ++i) order.push_back(b.tri[i]);
+    return kLeafBit | ((b.count - 1u) << kLeafCountShift) | (first & kLeafFirstMask);
   }
 
   uint32_t emit(int32_t bi, uint32_t depth) {
@@ -213,53 +412,27 @@ struct Collapser {
 
 }  // namespace
 
+// Spatial splits: references they may add, as a fraction of the triangles, and the overlap of
+// the best object split's children (a fraction of the scene box's area) above which they are
+// tried
+constexpr double kSpatialBudget = 2.0;
+constexpr double kSpatialOverlap = 1e-4;
+
 // Build from a triangle soup [n][9]; returns nodes (root at 0, always an inner node), the
-// leaf order of the triangles and the depth of the 4-wide tree.
+// triangle index of every leaf slot (a triangle split in space fills several) and the depth of
+// the 4-wide tree.
 void build_bvh4(const float* tv, uint32_t n, std::vector<Node4>& nodes, std::vector<uint32_t>& order,
                 uint32_t& depth) {
-  std::vector<Box> tri_box(n);
-  std::vector<float> cen(3 * (size_t)n);
-  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  {
-    std::vector<std::thread> th;
-    for (unsigned w = 0; w < nth; ++w)
-      th.emplace_back([&, w] {
-        for (size_t i = w; i < n; i += nth) {
-          const float* v = tv + 9 * i;
-          Box b;
-          b.grow(v);
-          b.grow(v + 3);
-          b.grow(v + 6);
-          tri_box[i] = b;
-          for (int a = 0; a < 3; ++a) cen[3 * i + a] = (b.lo[a] + b.hi[a]) * 0.5f;
-        }
-      });
-    for (auto& t : th) t.join();
-  }
-  order.resize(n);
-  std::iota(order.begin(), order.end(), 0u);
-  Builder B;
-  B.tri_box = &tri_box;
-  B.cen = &cen;
-  B.ids = &order;
-  B.nodes.reserve(2 * (size_t)n + 8);
-  B.nodes.emplace_back();
+  nodes.clear();
+  order.clear();
   if (n <= Builder::kLeafMax) {
-    // force an inner root with a single leaf child so the walk always starts at a node
+    // an inner root with a single leaf child, so that the walk always starts at a node
     Box box;
-    for (uint32_t i = 0; i < n; ++i) box.grow(tri_box[i]);
-    BinNode leaf;
-    leaf.box = box;
-    leaf.first = 0;
-    leaf.count = n;
-    BinNode empty;
-    empty.first = 0;
-    empty.count = 0;
-    B.nodes[0].box = box;
-    B.nodes.push_back(leaf);
-    B.nodes[0].left = 1;
-    B.nodes[0].right = -1;
-    nodes.clear();
+    for (uint32_t i = 0; i < n; ++i) {
+      box.grow(tv + 9 * (size_t)i);
+      box.grow(tv + 9 * (size_t)i + 3);
+      box.grow(tv + 9 * (size_t)i + 6);
+    }
     Node4 r;
     std::memset(&r, 0, sizeof(r));
     for (int i = 0; i < 4; ++i) {
@@ -272,15 +445,41 @@ void build_bvh4(const float* tv, uint32_t n, std::vector<Node4>& nodes, std::vec
       r.loy[0] = box.lo[1]; r.hiy[0] = box.hi[1];
       r.loz[0] = box.lo[2]; r.hiz[0] = box.hi[2];
       r.child[0] = kLeafBit | ((n - 1u) << kLeafCountShift);
+      for (uint32_t i = 0; i < n; ++i) order.push_back(i);
     }
     nodes.push_back(r);
     depth = 1;
     return;
   }
-  B.build(0, 0, n, 0);
-  nodes.clear();
+  std::vector<Ref> refs(n);
+  {
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nth; ++w)
+      th.emplace_back([&, w] {
+        for (size_t i = w; i < n; i += nth) {
+          Box b;
+          b.grow(tv + 9 * i);
+          b.grow(tv + 9 * i + 3);
+          b.grow(tv + 9 * i + 6);
+          refs[i] = Ref{b, (uint32_t)i};
+        }
+      });
+    for (auto& t : th) t.join();
+  }
+  Box root;
+  for (const Ref& r : refs) root.grow(r.box);
+  Builder B;
+  B.tv = tv;
+  // extra references at most kSpatialBudget n, and leaf indices within 24 bits
+  B.budget = std::min<int64_t>((int64_t)(kSpatialBudget * n), (int64_t)kLeafFirstMask - (int64_t)n);
+  B.min_overlap = kSpatialOverlap * root.area();
+  B.nodes.reserve(3 * (size_t)n + 8);
+  B.nodes.emplace_back();
+  B.build(0, refs, 0);
   nodes.reserve(B.nodes.size() / 2 + 8);
-  Collapser Cl{B.nodes, nodes};
+  order.reserve((size_t)n + (size_t)std::max<int64_t>(0, (int64_t)n / 2 - B.budget.load()));
+  Collapser Cl{B.nodes, nodes, order};
   Cl.emit(0, 1);
   depth = Cl.max_depth;
 }

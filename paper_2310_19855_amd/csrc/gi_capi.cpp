@@ -410,8 +410,9 @@ gi_status gi_build_bvh(gi_context* c, const float* h_verts, uint32_t n_verts, co
     c->spill_rows = need > lds ? need - lds : 0;
     c->spill_stride = std::max(c->P * c->R, c->W * c->H);
     if (c->spill_rows) GI_TRY_HIP(c, dalloc(&c->d_spill, (size_t)c->spill_rows * c->spill_stride));
-    std::vector<float4> tris(3 * (size_t)std::max(n_tris, 1u));
-    for (uint32_t i = 0; i < n_tris; ++i) {
+    // leaf slots in order; a triangle split in space by the builder fills several
+    std::vector<float4> tris(3 * std::max<size_t>(order.size(), 1));
+    for (size_t i = 0; i < order.size(); ++i) {
       const uint32_t t = order[i];
       const float* v = &c->h_static_tv[9 * (size_t)t];
       uint32_t bits = t;
