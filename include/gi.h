@@ -123,8 +123,9 @@ const char *gi_version(void);
 
 /* ---- scene ---------------------------------------------------------------------------- */
 
-/* Build the ray-tracing acceleration structure on the host (binned-SAH binary tree collapsed
- * to a 4-wide BVH, nodes of one 128-byte line, triangles in leaf order) and upload it,
+/* Build the ray-tracing acceleration structure on the host (binned-SAH binary tree with
+ * spatial splits, collapsed to a 4-wide BVH, nodes of one 128-byte line, triangles in leaf
+ * order; a triangle split in space fills several leaf slots) and upload it,
  * together with unit triangle normals, materials and the area-proportional emitter table.
  * h_verts [n_verts][3] float; h_idx [n_tris][3]; h_tri_mat [n_tris]; h_mats [n_mats][6]
  * (albedo rgb, emitted radiance rgb).  Synchronous.  The paper traverses with hardware
@@ -132,6 +133,19 @@ const char *gi_version(void);
 gi_status gi_build_bvh(gi_context *ctx, const float *h_verts, uint32_t n_verts,
                        const uint32_t *h_idx, uint32_t n_tris, const uint32_t *h_tri_mat,
                        const float *h_mats, uint32_t n_mats);
+
+/* Host only (no context, no device): the 4-wide BVH that gi_build_bvh builds, for inspection
+ * and tests.  h_tri_verts [n_tris][9] float: the vertex positions of each triangle.
+ * A node record is 128 bytes: child boxes as float[4] each of lo x, hi x, lo y, hi y, lo z,
+ * hi z, then uint32 child[4] (an inner node index; a leaf 0x80000000 | (count - 1) << 24 |
+ * first leaf slot; 0xFFFFFFFF empty), then 16 bytes of padding.  Node 0 is the root, always
+ * an inner node.  Leaf slots hold triangle indices.  *n_nodes, *n_slots and *depth (levels
+ * of the 4-wide tree) are always set; h_nodes (cap_nodes records) and h_slots (cap_slots
+ * entries) are filled when not null, and a capacity smaller than the result is
+ * GI_ERR_INVALID_ARG.  GI_ERR_OOM if host memory runs out. */
+gi_status gi_bvh_build_host(const float *h_tri_verts, uint32_t n_tris, void *h_nodes, uint32_t cap_nodes,
+                            uint32_t *h_slots, uint32_t cap_slots, uint32_t *n_nodes, uint32_t *n_slots,
+                            uint32_t *depth);
 
 /* Replace the set of moving triangles tested beside the BVH (at most 64): h_tri_verts
  * [n][9] float, h_tri_mat [n].  Their indices follow the static ones.  Rebuilds the emitter

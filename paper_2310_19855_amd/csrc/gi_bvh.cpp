@@ -82,7 +82,6 @@ struct Builder {
   const float* tv;                 // [n][9]
   std::vector<BinNode> nodes;
   std::mutex mu;
-  std::atomic<int64_t> budget{0};  // references spatial splits may still add
   double min_overlap = 0.0;        // overlap area above which spatial splits are tried
 
   static constexpr int kBins = 64;
@@ -239,17 +238,14 @@ struct Builder {
     return best;
   }
 
-  // splits refs by the plane; false (refs untouched) if one side would keep every reference
-  // or the reference budget is spent
-  bool apply_spatial(std::vector<Ref>& refs, const Split& sp, std::vector<Ref>& left,
-                     std::vector<Ref>& right) {
+  // splits refs by the plane, spending the references it adds from budget; false (refs
+  // untouched) if the budget is too small or one side would keep every reference
+  bool apply_spatial(std::vector<Ref>& refs, const Split& sp, std::vector<Ref>& left, std::vector<Ref>& right,
+                     int64_t& budget) const {
     const int a = sp.axis;
     int64_t extra = 0;
     for (const Ref& r : refs) extra += r.box.lo[a] < sp.pos && r.box.hi[a] > sp.pos;
-    if (budget.fetch_sub(extra) < extra) {
-      budget.fetch_add(extra);
-      return false;
-    }
+    if (extra > budget) return false;
     left.clear();
     right.clear();
     for (const Ref& r : refs) {
@@ -264,15 +260,15 @@ struct Builder {
         if (!empty(rb)) right.push_back(Ref{rb, r.tri});
       }
     }
-    if (left.size() == refs.size() || right.size() == refs.size() || left.empty() || right.empty()) {
-      budget.fetch_add(extra);
-      return false;
-    }
+    if (left.size() == refs.size() || right.size() == refs.size() || left.empty() || right.empty()) return false;
+    budget -= (int64_t)(left.size() + right.size() - refs.size());
     return true;
   }
 
-  // builds node ni over refs (consumed)
-  void build(int32_t ni, std::vector<Ref>& refs, int depth) {
+  // builds node ni over refs (consumed); budget: references spatial splits in this subtree may
+  // add (handed to the children in proportion to their references, so the tree does not depend
+  // on the order in which threads build subtrees)
+  void build(int32_t ni, std::vector<Ref>& refs, int depth, int64_t budget) {
     Box box, cbox;
     for (const Ref& r : refs) {
       box.grow(r.box);
@@ -292,10 +288,10 @@ struct Builder {
     const Split os = object_split(refs, cbox);
     std::vector<Ref> left, right;
     bool done = false;
-    if (os.axis >= 0 && budget.load() > 0 && intersect(os.lbox, os.rbox).area() > min_overlap &&
+    if (os.axis >= 0 && budget > 0 && intersect(os.lbox, os.rbox).area() > min_overlap &&
         !empty(intersect(os.lbox, os.rbox))) {
       const Split ss = spatial_split(refs, box);
-      if (ss.axis >= 0 && ss.cost < os.cost) done = apply_spatial(refs, ss, left, right);
+      if (ss.axis >= 0 && ss.cost < os.cost) done = apply_spatial(refs, ss, left, right, budget);
     }
     if (!done) {
       left.clear();
@@ -332,13 +328,15 @@ struct Builder {
       std::lock_guard<std::mutex> g(mu);
       nodes[ni] = node;
     }
+    const int64_t bl = budget * (int64_t)left.size() / (int64_t)(left.size() + right.size());
+    const int64_t br = budget - bl;
     if (left.size() + right.size() > 200000 && depth < 5) {
-      auto fut = std::async(std::launch::async, [&, l, depth] { build(l, left, depth + 1); });
-      build(l + 1, right, depth + 1);
+      auto fut = std::async(std::launch::async, [&, l, depth, bl] { build(l, left, depth + 1, bl); });
+      build(l + 1, right, depth + 1, br);
       fut.get();
     } else {
-      build(l, left, depth + 1);
-      build(l + 1, right, depth + 1);
+      build(l, left, depth + 1, bl);
+      build(l + 1, right, depth + 1, br);
     }
   }
 };
@@ -415,7 +413,7 @@ struct Collapser {
 // Spatial splits: references they may add, as a fraction of the triangles, and the overlap of
 // the best object split's children (a fraction of the scene box's area) above which they are
 // tried
-constexpr double kSpatialBudget = 2.0;
+constexpr double kSpatialBudget = 6.0;
 constexpr double kSpatialOverlap = 1e-4;
 
 // Build from a triangle soup [n][9]; returns nodes (root at 0, always an inner node), the
@@ -472,13 +470,13 @@ void build_bvh4(const float* tv, uint32_t n, std::vector<Node4>& nodes, std::vec
   Builder B;
   B.tv = tv;
   // extra references at most kSpatialBudget n, and leaf indices within 24 bits
-  B.budget = std::min<int64_t>((int64_t)(kSpatialBudget * n), (int64_t)kLeafFirstMask - (int64_t)n);
+  const int64_t budget = std::min<int64_t>((int64_t)(kSpatialBudget * n), (int64_t)kLeafFirstMask - (int64_t)n);
   B.min_overlap = kSpatialOverlap * root.area();
-  B.nodes.reserve(3 * (size_t)n + 8);
+  B.nodes.reserve(2 * (size_t)n + 8);
   B.nodes.emplace_back();
-  B.build(0, refs, 0);
+  B.build(0, refs, 0, std::max<int64_t>(budget, 0));
   nodes.reserve(B.nodes.size() / 2 + 8);
-  order.reserve((size_t)n + (size_t)std::max<int64_t>(0, (int64_t)n / 2 - B.budget.load()));
+  order.reserve(B.nodes.size() / 2 + 8);
   Collapser Cl{B.nodes, nodes, order};
   Cl.emit(0, 1);
   depth = Cl.max_depth;

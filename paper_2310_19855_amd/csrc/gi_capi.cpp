@@ -474,6 +474,33 @@ gi_status gi_build_bvh(gi_context* c, const float* h_verts, uint32_t n_verts, co
   }
 }
 
+gi_status gi_bvh_build_host(const float* h_tv, uint32_t n_tris, void* h_nodes, uint32_t cap_nodes, uint32_t* h_slots,
+                            uint32_t cap_slots, uint32_t* n_nodes, uint32_t* n_slots, uint32_t* depth) {
+  if ((!h_tv && n_tris) || !n_nodes || !n_slots || !depth) return GI_ERR_INVALID_ARG;
+  try {
+    std::vector<Node4> nodes;
+    std::vector<uint32_t> order;
+    uint32_t d = 0;
+    gi::build_bvh4(h_tv, n_tris, nodes, order, d);
+    *n_nodes = (uint32_t)nodes.size();
+    *n_slots = (uint32_t)order.size();
+    *depth = d;
+    if (h_nodes) {
+      if (cap_nodes < nodes.size()) return GI_ERR_INVALID_ARG;
+      std::memcpy(h_nodes, nodes.data(), sizeof(Node4) * nodes.size());
+    }
+    if (h_slots) {
+      if (cap_slots < order.size()) return GI_ERR_INVALID_ARG;
+      std::memcpy(h_slots, order.data(), sizeof(uint32_t) * order.size());
+    }
+    return GI_OK;
+  } catch (const std::bad_alloc&) {
+    return GI_ERR_OOM;
+  } catch (...) {
+    return GI_ERR_INTERNAL;
+  }
+}
+
 gi_status gi_set_dynamic_triangles(gi_context* c, const float* h_tv, const uint32_t* h_mat, uint32_t n, void* stream) {
   if (!c) return GI_ERR_INVALID_ARG;
   if (!c->has_scene) return fail(c, GI_ERR_STATE, "gi_build_bvh first");

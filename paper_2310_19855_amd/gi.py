@@ -79,6 +79,7 @@ def lib():
     fn("gi_destroy", None, vp)
     fn("gi_last_error", C.c_char_p, vp)
     fn("gi_build_bvh", st, vp, vp, u32, vp, u32, vp, vp, u32)
+    fn("gi_bvh_build_host", st, vp, u32, vp, u32, vp, u32, P(u32), P(u32), P(u32))
     fn("gi_set_dynamic_triangles", st, vp, vp, vp, u32, vp)
     fn("gi_render_gbuffer", st, vp, P(Frame), vp, vp, vp, vp, vp)
     fn("gi_spawn_probes", st, vp, P(Frame), vp, vp, vp, vp)
@@ -107,6 +108,30 @@ def lib():
     fn("gi_learned_stats", st, vp, vp)
     _lib = L
     return L
+
+
+NODE_DTYPE = np.dtype([("lo_x", "<f4", 4), ("hi_x", "<f4", 4), ("lo_y", "<f4", 4), ("hi_y", "<f4", 4),
+                       ("lo_z", "<f4", 4), ("hi_z", "<f4", 4), ("child", "<u4", 4), ("pad", "<u4", 4)])
+
+
+def build_bvh_host(tri_verts):
+    """The 4-wide BVH that gi_build_bvh builds, on the host: (nodes as a NODE_DTYPE array,
+    triangle index of every leaf slot, depth).  tri_verts: float32 [n][9]."""
+    tv = np.ascontiguousarray(tri_verts, np.float32).reshape(-1, 9)
+    n = C.c_uint32(0)
+    ns = C.c_uint32(0)
+    d = C.c_uint32(0)
+    L = lib()
+    st = L.gi_bvh_build_host(tv.ctypes.data, tv.shape[0], None, 0, None, 0, C.byref(n), C.byref(ns), C.byref(d))
+    if st != 0:
+        raise GIError(f"gi_bvh_build_host: status {st}")
+    nodes = np.zeros(n.value, NODE_DTYPE)
+    slots = np.zeros(ns.value, np.uint32)
+    st = L.gi_bvh_build_host(tv.ctypes.data, tv.shape[0], nodes.ctypes.data, n.value, slots.ctypes.data, ns.value,
+                             C.byref(n), C.byref(ns), C.byref(d))
+    if st != 0:
+        raise GIError(f"gi_bvh_build_host: status {st}")
+    return nodes, slots, int(d.value)
 
 
 def make_config(**kw) -> Config:
