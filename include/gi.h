@@ -76,7 +76,7 @@ typedef struct gi_config {
     uint32_t seed;               /* seed of the counter-based random streams              */
     uint32_t frac_bits;          /* fixed-point fraction bits F of cell sums (1..16)       */
     uint32_t cache_mode;         /* GI_CACHE_*                                            */
-    uint32_t reserved0;
+    uint32_t probe_filter;       /* 1: separable 7x7 probe-space filter (Algorithm 5) before SH */
     float cell_scale;            /* S = 1 / cell size of the position quantiser (2.2.1)    */
     float r_max;                 /* clamp of a cache sample before quantisation           */
     float eps_scale;             /* ray origin offset = eps_scale * (1 + max|p_i|)        */

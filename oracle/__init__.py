@@ -30,7 +30,7 @@ class OrcConfig(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("rays_per_probe", C.c_uint32),
                 ("table_log2", C.c_uint32), ("bounces", C.c_uint32), ("leak_bit", C.c_uint32),
                 ("max_life", C.c_uint32), ("n_cap", C.c_uint32), ("seed", C.c_uint32),
-                ("frac_bits", C.c_uint32), ("pad0", C.c_uint32), ("pad1", C.c_uint32),
+                ("frac_bits", C.c_uint32), ("probe_filter", C.c_uint32), ("pad1", C.c_uint32),
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4)]
 
@@ -44,7 +44,7 @@ class OrcFrame(C.Structure):
 def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
-               eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0))
+               eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0)
     cfg.update(kw)
     return cfg
 
@@ -113,6 +113,7 @@ def _lib(f64: bool):
     fn("find_probe", C.c_uint32, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32)
     fn("sh_eval", None, R, R, C.c_uint32, R)
     fn("sh_project_atlas", None, vp, R, R, C.c_uint32, R)
+    fn("filter_atlas", None, vp, C.POINTER(OrcFrame), C.c_int32, C.c_int32, R, R)
     fn("nee_samples", None, vp, C.POINTER(OrcFrame), R, R, U32P, C.c_uint32, R)
     _LIBS[key] = (lib, p)
     return _LIBS[key]
@@ -414,6 +415,15 @@ class OracleFrameState:
         f = make_frame(frame)
         _call(self.f64, "nee_samples", self.h, C.byref(f), np.ascontiguousarray(y, self.dt),
               np.ascontiguousarray(ny, self.dt), ids, len(ids), out)
+        return out
+
+    def filter_atlas(self, frame, axis, atlas):
+        """one pass of the probe-space filter (Algorithm 5) along axis 0 (x) or 1 (y) over an
+        atlas [P][64][4], with the probes of the last spawn"""
+        a = np.ascontiguousarray(atlas, self.dt).reshape(-1, NCELL, 4)
+        out = np.zeros_like(a)
+        f = make_frame(frame)
+        _call(self.f64, "filter_atlas", self.h, C.byref(f), 1 if axis == 0 else 0, 1 if axis == 1 else 0, a, out)
         return out
 
     def sh_project(self, atlas, nrm):

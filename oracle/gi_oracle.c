@@ -670,7 +670,7 @@ uint32_t ORC(pick_emitter)(const scene *sc, uint32_t r) { return sc->ne ? sc->et
 typedef struct orc_config {
     uint32_t width, height, rays_per_probe, table_log2;
     uint32_t bounces, leak_bit, max_life, n_cap;
-    uint32_t seed, frac_bits, pad0, pad1;
+    uint32_t seed, frac_bits, probe_filter, pad1;
     float cell_scale, r_max, eps_scale, t_sky;
     float sky[4];
 } orc_config;
@@ -1467,11 +1467,104 @@ void ORC(sh_project_atlas)(state *st, const real *atlas, const real *nrm, uint32
     st->atlas = sa; st->sh = ss; st->pnrm = sn; st->mask = sm; st->P = sp;
 }
 
+/* ---------------------------------------------------------------------------------------
+ * Algorithm 5: separable 7x7 sparse filter of the probes' radiance in probe space, one pass
+ * along x, then one along y.  For every cell of a probe p, the probes found by Algorithm 4
+ * at tile steps -1, +1, -2, +2, -3, +3 along the pass axis contribute their cell of the same
+ * index, unless the plane distance exceeds p's cell size (Algorithm 6), the cell direction
+ * points below their surface, or the hit point their ray reached (at the smaller of the two
+ * travelled distances) is seen from p more than pi/50 away from the cell direction.
+ * Contributions are depth-weighted; the travelled distance is re-averaged after each one.
+ * READING: the test's undefined `direction` is the cell direction; the depth weight, which
+ * the paper leaves undefined, is cs / (cs + |d_q - d_p|) with cs p's cell size and d the
+ * primary-ray distance; the cell direction is the normalised centre of the hemi-octahedral
+ * cell, rotated into the probe frame; a hit point at p itself is rejected.
+ * ------------------------------------------------------------------------------------- */
+#define COS_PI_50 0.9980267284282716
+
+static uint32_t find_closest_probe(const state *st, int32_t px, int32_t py, int32_t ox, int32_t oy);
+
+static void cell_direction(int cell, const real *n, real *d)
+{
+    real u = (real)(2 * (cell & 7) + 1) / RC(8.0) - RC(1.0);
+    real v = (real)(2 * (cell >> 3) + 1) / RC(8.0) - RC(1.0);
+    real a = (u + v) * RC(0.5), b = (u - v) * RC(0.5);
+    real z = (RC(1.0) - RABS(a)) - RABS(b);
+    real len = RSQRT((a * a + b * b) + z * z);
+    real lx = a / len, ly = b / len, lz = z / len;
+    real t[3], bb[3];
+    onb(n, t, bb);
+    for (int k = 0; k < 3; ++k) d[k] = (lx * t[k] + ly * bb[k]) + lz * n[k];
+}
+
+static void filter_pass(const state *st, const real *cam, real kappa, int32_t ax, int32_t ay, const real *in,
+                        real *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < (long)st->P; ++p) {
+        const real *ip = in + (size_t)p * NCELL * 4;
+        real *op = out + (size_t)p * NCELL * 4;
+        if (st->mask[p] == SENTINEL) {
+            for (int i = 0; i < NCELL * 4; ++i) op[i] = ip[i];
+            continue;
+        }
+        int32_t px = (int32_t)(st->mask[p] & 0xFFFFu), py = (int32_t)(st->mask[p] >> 16);
+        const real *wp = st->ppos + 4 * (size_t)p, *np = st->pnrm + 4 * (size_t)p;
+        real cx = wp[0] - cam[0], cy = wp[1] - cam[1], cz = wp[2] - cam[2];
+        real cs = kappa * RSQRT((cx * cx + cy * cy) + cz * cz);
+        for (int cell = 0; cell < NCELL; ++cell) {
+            real dir[3];
+            cell_direction(cell, np, dir);
+            real rad[4] = {ip[4 * cell], ip[4 * cell + 1], ip[4 * cell + 2], ip[4 * cell + 3]};
+            real hit = rad[3], wsum = RC(1.0);
+            for (int i = 0; i < 6; ++i) {
+                int32_t step = (((i & 1) << 1) - 1) * ((i >> 1) + 1);
+                uint32_t qm = find_closest_probe(st, px, py, step * ax, step * ay);
+                if (qm == SENTINEL) continue;
+                uint32_t q = ((qm >> 16) >> 3) * st->TW + ((qm & 0xFFFFu) >> 3);
+                const real *wq = st->ppos + 4 * (size_t)q, *nq = st->pnrm + 4 * (size_t)q;
+                real pd = RABS(((wq[0] - wp[0]) * np[0] + (wq[1] - wp[1]) * np[1]) + (wq[2] - wp[2]) * np[2]);
+                real nc = (dir[0] * nq[0] + dir[1] * nq[1]) + dir[2] * nq[2];
+                if (pd > cs || nc < RC(0.0)) continue;
+                const real *rq = in + (size_t)q * NCELL * 4 + 4 * cell;
+                real hd = rmin(rq[3], hit);
+                real e[3];
+                for (int k = 0; k < 3; ++k) e[k] = (wq[k] + dir[k] * hd) - wp[k];
+                real el = RSQRT((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
+                if (!(el > RC(0.0))) continue;
+                real ang = (dir[0] * (e[0] / el) + dir[1] * (e[1] / el)) + dir[2] * (e[2] / el);
+                if (ang < (real)COS_PI_50) continue;
+                real w = cs / (cs + RABS(wq[3] - wp[3]));
+                for (int k = 0; k < 3; ++k) rad[k] = rad[k] + w * rq[k];
+                rad[3] = rad[3] + w * hd;
+                wsum = wsum + w;
+                hit = rad[3] / wsum;
+            }
+            for (int k = 0; k < 4; ++k) op[4 * cell + k] = rad[k] / wsum;
+        }
+    }
+}
+
+/* the filter on caller data (test entry): atlas [P][64][4] in, out; probes as in the state */
+void ORC(filter_atlas)(const state *st, const orc_frame *fr, int32_t ax, int32_t ay, const real *in, real *out)
+{
+    real cam[3] = {(real)fr->pos[0], (real)fr->pos[1], (real)fr->pos[2]};
+    real kappa = (real)ORC(distance_scale)(fr->fov_y, st->W, st->H);
+    filter_pass(st, cam, kappa, ax, ay, in, out);
+}
+
 void ORC(update)(state *st, const orc_frame *fr)
 {
-    (void)fr;
     cache_update(st);
     gather(st);
+    if (st->cfg.probe_filter) {
+        real cam[3] = {(real)fr->pos[0], (real)fr->pos[1], (real)fr->pos[2]};
+        real kappa = (real)ORC(distance_scale)(fr->fov_y, st->W, st->H);
+        real *tmp = (real *)malloc(sizeof(real) * (size_t)st->P * NCELL * 4);
+        filter_pass(st, cam, kappa, 1, 0, st->atlas, tmp);
+        filter_pass(st, cam, kappa, 0, 1, tmp, st->atlas);
+        free(tmp);
+    }
     sh_project(st);
 }
 

@@ -195,6 +195,7 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->d_rec);
   dfree(c->d_rkey);
   dfree(c->d_atlas);
+  dfree(c->d_atlas_tmp);
   dfree(c->d_sh);
   dfree(c->tab.fp);
   dfree(c->tab.key);
@@ -233,6 +234,7 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->max_life < 1) { why = "max_life must be >= 1"; return GI_ERR_INVALID_ARG; }
   if (!(g->cell_scale > 0.0f) || !(g->r_max > 0.0f) || !(g->eps_scale >= 0.0f)) { why = "cell_scale, r_max must be > 0"; return GI_ERR_INVALID_ARG; }
   if (g->cache_mode > GI_CACHE_MLP_FP8) { why = "unknown cache_mode"; return GI_ERR_INVALID_ARG; }
+  if (g->probe_filter > 1) { why = "probe_filter must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   return GI_OK;
 }
 
@@ -300,6 +302,7 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
   A(dalloc(&c->d_rec, PR));
   A(dalloc(&c->d_rkey, PR));
   A(dalloc(&c->d_atlas, (size_t)c->P * 64));
+  if (cfg->probe_filter) A(dalloc(&c->d_atlas_tmp, (size_t)c->P * 64));
   A(dalloc(&c->d_sh, (size_t)c->P * 28));
   A(dalloc(&c->tab.fp, c->N));
   A(dalloc(&c->tab.key, c->N));

@@ -80,6 +80,7 @@ struct gi_context {
   uint4* d_rec = nullptr;       // [P*R] slot, t bits, tri, flags
   uint2* d_rkey = nullptr;      // [P*R] descriptor of the hit (export / learned training)
   float4* d_atlas = nullptr;    // [P*64]
+  float4* d_atlas_tmp = nullptr;  // [P*64] between the two filter passes (probe_filter only)
   float* d_sh = nullptr;        // [P*28]
   gi::Table tab;
   unsigned long long* d_stats = nullptr;  // [kStatStripes][GI_STAT_COUNT]

@@ -551,10 +551,65 @@ __device__ inline void transpose_reduce_step(float (&v)[32], uint32_t lane, uint
   coef += up ? (uint32_t)H : 0u;
 }
 
+// SH projection of one probe's atlas (Section 2.4.2), one wave per probe, lane = cell:
+// exact integrals of the 9 real basis functions over the cell from its direction moments
+// rotated into the probe frame (columns t, b, n); c0..c2 = the cell's radiance
+__device__ inline void probe_sh(uint32_t p, uint32_t lane, float4 nn, const float* moments, float c0, float c1,
+                                float c2, float* sh) {
+  const Basis B = make_basis(nn.x, nn.y, nn.z);
+  const float R00 = B.tx, R10 = B.ty, R20 = B.tz;
+  const float R01 = B.bx, R11 = B.by, R21 = B.bz;
+  const float R02 = nn.x, R12 = nn.y, R22 = nn.z;
+  const float* mo = moments + lane * 10;
+  const float om = mo[0];
+  const float mlx = mo[1], mly = mo[2], mlz = mo[3];
+  const float Mxx = mo[4], Myy = mo[5], Mzz = mo[6], Mxy = mo[7], Mxz = mo[8], Myz = mo[9];
+  const float mwx = R00 * mlx + R01 * mly + R02 * mlz;
+  const float mwy = R10 * mlx + R11 * mly + R12 * mlz;
+  const float mwz = R20 * mlx + R21 * mly + R22 * mlz;
+  // T = R M (rows i), W = T R^T
+  const float T00 = R00 * Mxx + R01 * Mxy + R02 * Mxz, T01 = R00 * Mxy + R01 * Myy + R02 * Myz,
+              T02 = R00 * Mxz + R01 * Myz + R02 * Mzz;
+  const float T10 = R10 * Mxx + R11 * Mxy + R12 * Mxz, T11 = R10 * Mxy + R11 * Myy + R12 * Myz,
+              T12 = R10 * Mxz + R11 * Myz + R12 * Mzz;
+  const float T20 = R20 * Mxx + R21 * Mxy + R22 * Mxz, T21 = R20 * Mxy + R21 * Myy + R22 * Myz,
+              T22 = R20 * Mxz + R21 * Myz + R22 * Mzz;
+  const float Wxx = T00 * R00 + T01 * R01 + T02 * R02;
+  const float Wyy = T10 * R10 + T11 * R11 + T12 * R12;
+  const float Wzz = T20 * R20 + T21 * R21 + T22 * R22;
+  const float Wxy = T00 * R10 + T01 * R11 + T02 * R12;
+  const float Wxz = T00 * R20 + T01 * R21 + T02 * R22;
+  const float Wyz = T10 * R20 + T11 * R21 + T12 * R22;
+  const float k0 = 0.28209479177387814f, k1 = 0.48860251190291992f, k2 = 1.09254843059207907f,
+              k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
+  const float I[9] = {k0 * om, k1 * mwy, k1 * mwz, k1 * mwx, k2 * Wxy, k2 * Wyz, k20 * (3.0f * Wzz - om),
+                      k2 * Wxz, k22 * (Wxx - Wyy)};
+  // the 27 wave sums of c_ch I_l as one transpose-reduce: at each butterfly step a lane keeps
+  // half of its partial sums (the half its lane bit selects) and adds the partner's copy of that
+  // half; after the steps over lane bits 5..1 lane L holds coefficient
+  // k = 16 b5 + 8 b4 + 4 b3 + 2 b2 + b1 summed over 32 lanes, and the step over bit 0 completes it
+  float v[32];
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    v[3 * l] = c0 * I[l];
+    v[3 * l + 1] = c1 * I[l];
+    v[3 * l + 2] = c2 * I[l];
+  }
+#pragma unroll
+  for (int k = 27; k < 32; ++k) v[k] = 0.0f;
+  uint32_t coef = 0;
+  transpose_reduce_step<16>(v, lane, coef);
+  transpose_reduce_step<8>(v, lane, coef);
+  transpose_reduce_step<4>(v, lane, coef);
+  transpose_reduce_step<2>(v, lane, coef);
+  transpose_reduce_step<1>(v, lane, coef);
+  const float out = v[0] + __shfl_xor(v[0], 1, 64);
+  if ((lane & 1u) == 0u && coef < 28u) sh[(size_t)p * 28 + coef] = coef < 27u ? out : 0.0f;}
+
 __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const float4* pnrm, const uint4* rec,
                                                   const float4* L, const float4* tnrm, const float4* mats,
                                                   const float* moments, uint32_t R, float s0, float s1, float s2,
-                                                  LearnedGatherIn lg, float4* atlas, float* sh) {
+                                                  LearnedGatherIn lg, uint32_t do_sh, float4* atlas, float* sh) {
   __shared__ float rv[kGatherMaxR][4];
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
@@ -564,7 +619,7 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
   const uint32_t lane = threadIdx.x;
   if (mask[p] == kSentinel) {
     atlas[(size_t)p * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (lane < 28) sh[(size_t)p * 28 + lane] = 0.0f;
+    if (do_sh && lane < 28) sh[(size_t)p * 28 + lane] = 0.0f;
     return;
   }
   for (uint32_t j = lane; j < R; j += 64) {
@@ -651,63 +706,10 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
     }
   }
   atlas[(size_t)p * 64 + lane] = make_float4(c0, c1, c2, c3);
-  // SH: exact integrals of the 9 real basis functions over this cell, from its direction
-  // moments rotated into the probe frame (columns t, b, n)
-  const float4 nn = pnrm[p];
-  const Basis B = make_basis(nn.x, nn.y, nn.z);
-  const float R00 = B.tx, R10 = B.ty, R20 = B.tz;
-  const float R01 = B.bx, R11 = B.by, R21 = B.bz;
-  const float R02 = nn.x, R12 = nn.y, R22 = nn.z;
-  const float* mo = moments + lane * 10;
-  const float om = mo[0];
-  const float mlx = mo[1], mly = mo[2], mlz = mo[3];
-  const float Mxx = mo[4], Myy = mo[5], Mzz = mo[6], Mxy = mo[7], Mxz = mo[8], Myz = mo[9];
-  const float mwx = R00 * mlx + R01 * mly + R02 * mlz;
-  const float mwy = R10 * mlx + R11 * mly + R12 * mlz;
-  const float mwz = R20 * mlx + R21 * mly + R22 * mlz;
-  // T = R M (rows i), W = T R^T
-  const float T00 = R00 * Mxx + R01 * Mxy + R02 * Mxz, T01 = R00 * Mxy + R01 * Myy + R02 * Myz,
-              T02 = R00 * Mxz + R01 * Myz + R02 * Mzz;
-  const float T10 = R10 * Mxx + R11 * Mxy + R12 * Mxz, T11 = R10 * Mxy + R11 * Myy + R12 * Myz,
-              T12 = R10 * Mxz + R11 * Myz + R12 * Mzz;
-  const float T20 = R20 * Mxx + R21 * Mxy + R22 * Mxz, T21 = R20 * Mxy + R21 * Myy + R22 * Myz,
-              T22 = R20 * Mxz + R21 * Myz + R22 * Mzz;
-  const float Wxx = T00 * R00 + T01 * R01 + T02 * R02;
-  const float Wyy = T10 * R10 + T11 * R11 + T12 * R12;
-  const float Wzz = T20 * R20 + T21 * R21 + T22 * R22;
-  const float Wxy = T00 * R10 + T01 * R11 + T02 * R12;
-  const float Wxz = T00 * R20 + T01 * R21 + T02 * R22;
-  const float Wyz = T10 * R20 + T11 * R21 + T12 * R22;
-  const float k0 = 0.28209479177387814f, k1 = 0.48860251190291992f, k2 = 1.09254843059207907f,
-              k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
-  const float I[9] = {k0 * om, k1 * mwy, k1 * mwz, k1 * mwx, k2 * Wxy, k2 * Wyz, k20 * (3.0f * Wzz - om),
-                      k2 * Wxz, k22 * (Wxx - Wyy)};
-  // the 27 wave sums of c_ch I_l as one transpose-reduce: at each butterfly step a lane keeps
-  // half of its partial sums (the half its lane bit selects) and adds the partner's copy of that
-  // half; after the steps over lane bits 5..1 lane L holds coefficient
-  // k = 16 b5 + 8 b4 + 4 b3 + 2 b2 + b1 summed over 32 lanes, and the step over bit 0 completes it
-  float v[32];
-#pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    v[3 * l] = c0 * I[l];
-    v[3 * l + 1] = c1 * I[l];
-    v[3 * l + 2] = c2 * I[l];
-  }
-#pragma unroll
-  for (int k = 27; k < 32; ++k) v[k] = 0.0f;
-  uint32_t coef = 0;
-  transpose_reduce_step<16>(v, lane, coef);
-  transpose_reduce_step<8>(v, lane, coef);
-  transpose_reduce_step<4>(v, lane, coef);
-  transpose_reduce_step<2>(v, lane, coef);
-  transpose_reduce_step<1>(v, lane, coef);
-  const float out = v[0] + __shfl_xor(v[0], 1, 64);
-  if ((lane & 1u) == 0u && coef < 28u) sh[(size_t)p * 28 + coef] = coef < 27u ? out : 0.0f;
+  if (do_sh) probe_sh(p, lane, pnrm[p], moments, c0, c1, c2, sh);
 }
 
-// ------------------------------------------------------------------------------------------
-// Per-pixel interpolation (Section 2.4.1, Algorithms 4 and 6)
-// ------------------------------------------------------------------------------------------
+// Algorithm 4: first valid probe of the probe-mask MIP chain at a tile offset from a pixel's tile
 __device__ inline uint32_t find_closest_probe(const uint32_t* mask, const MipInfo& mi, int32_t px, int32_t py,
                                               int32_t ox, int32_t oy) {
   int32_t x = px >> 3, y = py >> 3;
@@ -721,6 +723,86 @@ __device__ inline uint32_t find_closest_probe(const uint32_t* mask, const MipInf
   }
   return kSentinel;
 }
+
+// ------------------------------------------------------------------------------------------
+// Probe-space filter (Section 2.1.6, Algorithm 5): separable 7x7 sparse blur of the atlas, one
+// pass along x, then one along y (which also projects the result to SH).  One wave per probe,
+// lane = cell.  For each tap at -1, +1, -2, +2, -3, +3 tiles, Algorithm 4 finds the probe in
+// that direction (the same for every lane); its cell of the same index contributes unless the
+// plane distance exceeds the probe's cell size (Algorithm 6), the cell direction points below
+// the neighbour's surface, or the neighbour's hit point (at the smaller travelled distance) is
+// seen more than pi/50 away from the cell direction.  Depth weight cs / (cs + |d_q - d_p|);
+// the travelled distance is re-averaged after each contribution.  The cell direction is the
+// normalised centre of the hemi-octahedral cell in the probe frame.
+// ------------------------------------------------------------------------------------------
+__device__ inline void cell_centre_direction(uint32_t cell, float nx, float ny, float nz, float& dx, float& dy,
+                                             float& dz) {
+  const float u = (float)(2 * (cell & 7u) + 1) / 8.0f - 1.0f;
+  const float v = (float)(2 * (cell >> 3) + 1) / 8.0f - 1.0f;
+  const float a = (u + v) * 0.5f, b = (u - v) * 0.5f;
+  const float z = (1.0f - fabsf(a)) - fabsf(b);
+  const float len = sqrtf((a * a + b * b) + z * z);
+  const float lx = a / len, ly = b / len, lz = z / len;
+  const Basis B = make_basis(nx, ny, nz);
+  dx = (lx * B.tx + ly * B.bx) + lz * nx;
+  dy = (lx * B.ty + ly * B.by) + lz * ny;
+  dz = (lx * B.tz + ly * B.bz) + lz * nz;
+}
+
+template <bool VERTICAL>
+__global__ __launch_bounds__(64) void k_filter_probes(const uint32_t* mask, MipInfo mi, uint32_t TW, const float4* ppos,
+                                                      const float4* pnrm, const float4* in, float4* out, float cx,
+                                                      float cy, float cz, float kappa, const float* moments,
+                                                      float* sh) {
+  const uint32_t p = blockIdx.x, lane = threadIdx.x;
+  const float4 self = in[(size_t)p * 64 + lane];
+  const uint32_t m = mask[p];
+  if (m == kSentinel) {
+    out[(size_t)p * 64 + lane] = self;
+    if (VERTICAL && lane < 28) sh[(size_t)p * 28 + lane] = 0.0f;
+    return;
+  }
+  const int32_t px = (int32_t)(m & 0xFFFFu), py = (int32_t)(m >> 16);
+  const float4 wp = ppos[p], np = pnrm[p];
+  const float ex = wp.x - cx, ey = wp.y - cy, ez = wp.z - cz;
+  const float cs = kappa * sqrtf((ex * ex + ey * ey) + ez * ez);
+  float dx, dy, dz;
+  cell_centre_direction(lane, np.x, np.y, np.z, dx, dy, dz);
+  float r0 = self.x, r1 = self.y, r2 = self.z, r3 = self.w;
+  float hit = r3, wsum = 1.0f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int32_t step = (((i & 1) << 1) - 1) * ((i >> 1) + 1);
+    const uint32_t qm = find_closest_probe(mask, mi, px, py, VERTICAL ? 0 : step, VERTICAL ? step : 0);
+    if (qm == kSentinel) continue;
+    const uint32_t q = ((qm >> 16) >> 3) * TW + ((qm & 0xFFFFu) >> 3);
+    const float4 wq = ppos[q], nq = pnrm[q];
+    const float pd = fabsf(((wq.x - wp.x) * np.x + (wq.y - wp.y) * np.y) + (wq.z - wp.z) * np.z);
+    const float nc = (dx * nq.x + dy * nq.y) + dz * nq.z;
+    if (pd > cs || nc < 0.0f) continue;
+    const float4 rq = in[(size_t)q * 64 + lane];
+    const float hd = fminf(rq.w, hit);
+    const float e0 = (wq.x + dx * hd) - wp.x, e1 = (wq.y + dy * hd) - wp.y, e2 = (wq.z + dz * hd) - wp.z;
+    const float el = sqrtf((e0 * e0 + e1 * e1) + e2 * e2);
+    if (!(el > 0.0f)) continue;
+    const float ang = (dx * (e0 / el) + dy * (e1 / el)) + dz * (e2 / el);
+    if (ang < 0.9980267284282716f) continue;
+    const float w = cs / (cs + fabsf(wq.w - wp.w));
+    r0 = r0 + w * rq.x;
+    r1 = r1 + w * rq.y;
+    r2 = r2 + w * rq.z;
+    r3 = r3 + w * hd;
+    wsum = wsum + w;
+    hit = r3 / wsum;
+  }
+  const float o0 = r0 / wsum, o1 = r1 / wsum, o2 = r2 / wsum, o3 = r3 / wsum;
+  out[(size_t)p * 64 + lane] = make_float4(o0, o1, o2, o3);
+  if (VERTICAL) probe_sh(p, lane, np, moments, o0, o1, o2, sh);
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-pixel interpolation (Section 2.4.1, Algorithms 4 and 6)
+// ------------------------------------------------------------------------------------------
 
 // One wave per 8x8 lattice cell of the jittered probe grid (WAVES cells per block, in a row):
 // all pixels of a cell share the same four neighbour probes (Algorithm 4 depends only on the
@@ -1081,7 +1163,14 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
     const hipError_t e = learned_infer_rays(c, s);
     if (e != hipSuccess) return e;
   }
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), c->d_atlas, c->d_sh)));
+  const uint32_t filt = c->cfg.probe_filter;
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->d_atlas, c->d_sh)));
+  if (filt) {
+    // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
+    const MipInfo mi = mip_info(c);
+    GI_TIMED(c, "filter_x", s, (k_filter_probes<false><<<c->P, 64, 0, s>>>(c->d_mask, mi, c->TW, c->d_ppos, c->d_pnrm, c->d_atlas, c->d_atlas_tmp, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, c->d_moments, c->d_sh)));
+    GI_TIMED(c, "filter_y", s, (k_filter_probes<true><<<c->P, 64, 0, s>>>(c->d_mask, mi, c->TW, c->d_ppos, c->d_pnrm, c->d_atlas_tmp, c->d_atlas, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, c->d_moments, c->d_sh)));
+  }
   return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ class Config(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("rays_per_probe", C.c_uint32),
                 ("table_log2", C.c_uint32), ("bounces", C.c_uint32), ("leak_bit", C.c_uint32),
                 ("max_life", C.c_uint32), ("n_cap", C.c_uint32), ("seed", C.c_uint32),
-                ("frac_bits", C.c_uint32), ("cache_mode", C.c_uint32), ("reserved0", C.c_uint32),
+                ("frac_bits", C.c_uint32), ("cache_mode", C.c_uint32), ("probe_filter", C.c_uint32),
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4),
                 ("mlp_batch_log2", C.c_uint32), ("mlp_levels", C.c_uint32),
