@@ -227,6 +227,7 @@ def main():
         torch.cuda.empty_cache()
         forms = forms_comparison(log)
         forms.update(field4k_and_furnace(log))
+        forms["probe_filter"] = probe_filter_measure(log)
 
     line = {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
@@ -436,6 +437,59 @@ def field4k_and_furnace(log, W=3840, H=2160, R=64):
         res["furnace"][form] = {"ms_per_frame": round(r["ms"], 4), "relMAE": round(e, 6), "pixels": int(ok.sum())}
         log(f"[bench] furnace {form}: relMAE {e:.2e} @ {r['ms']:.3f} ms/frame")
     return res
+
+
+def probe_filter_measure(log, scene_name="field", W=1920, H=1080, R=64, with_cpu=True):
+    """The probe-space filter of Algorithm 5 on the benchmark workload's view: 16 frames with
+    the frame-0 camera and lights, filter on, per-pass launch time (HIP events) and the
+    fraction of the HBM peak at its algorithmic bytes: per probe and pass, its atlas read once
+    and written once (2 x 1 KiB; neighbours' cells are re-read from L2), plus the SH (112 B) on
+    the y pass, plus position and normal (32 B)."""
+    from paper_2310_19855_amd import inputs as I
+    scene = I.make_scene(scene_name)
+    r = run_form(scene_name, scene, W, H, R, "plain", SWEEP_FRAMES, SWEEP_TIMED_FROM, profile=True,
+                 extra=dict(probe_filter=1))
+    P = ((W + 7) // 8) * ((H + 7) // 8)
+    out = {"workload": f"{scene_name} {W}x{H}, R={R}, frozen frame-0 view", "ms_per_frame_with_filter": round(r["ms"], 4)}
+    for name, extra in (("filter_x", 0), ("filter_y", 112)):
+        ms = r["kernels"].get(name)
+        if not ms:
+            continue
+        b = P * (2 * 1024 + 32 + extra)
+        out[name] = {"avg_ms": ms, "alg_bytes": b, "gbs": round(b / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"[bench] probe filter: " + ", ".join(f"{k} {v['avg_ms']:.4f} ms ({v['frac_hbm']:.2f} of HBM peak)"
+                                            for k, v in out.items() if isinstance(v, dict)))
+    if with_cpu:
+        out["cpu_baseline"] = probe_filter_cpu(scene, scene_name, W, H, R)
+        log(f"[bench] probe filter, CPU oracle: {out['cpu_baseline']['value']:.1f} ms for both passes")
+    return out
+
+
+def probe_filter_cpu(scene, scene_name, W, H, R):
+    """The oracle's two filter passes (plain C, all host threads) over the same view's probes,
+    on a seeded synthetic atlas (radiance U[0,1], travelled distance U[0.1, 50] m)"""
+    import numpy as np
+
+    import oracle as O
+    from paper_2310_19855_amd import inputs as I
+    cores = O.set_threads(1)
+    O.set_threads(cores)
+    osc = O.OracleScene(scene)
+    st = O.OracleFrameState(osc, dict(O.default_config(), width=W, height=H, rays_per_probe=R, table_log2=20,
+                                      probe_filter=1))
+    fr = I.camera_for(scene_name, 0)
+    gp, gn, ga, gprim = osc.gbuffer(fr, W, H)
+    st.spawn(fr, gp, gn, gprim)
+    P = ((W + 7) // 8) * ((H + 7) // 8)
+    rng = np.random.default_rng(21)
+    atlas = np.concatenate([rng.uniform(0, 1, (P, 64, 3)), rng.uniform(0.1, 50.0, (P, 64, 1))], -1).astype(np.float32)
+    t0 = time.time()
+    a1 = st.filter_atlas(fr, 0, atlas)
+    st.filter_atlas(fr, 1, a1)
+    ms = (time.time() - t0) * 1e3
+    return {"value": round(ms, 1), "unit": "ms per frame (x and y passes)", "cores": cores, "kind": "oracle",
+            "sample": f"{P} probe tiles of the frame-0 view, one frame"}
 
 
 def calibrate_copy(mib):

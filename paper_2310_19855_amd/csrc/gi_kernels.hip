@@ -754,6 +754,8 @@ __global__ __launch_bounds__(64) void k_filter_probes(const uint32_t* mask, MipI
                                                       const float4* pnrm, const float4* in, float4* out, float cx,
                                                       float cy, float cz, float kappa, const float* moments,
                                                       float* sh) {
+  __shared__ uint32_t tap_q[6];        // neighbour probe of each tap (sentinel: none, or off the plane)
+  __shared__ float4 tap_w[6], tap_n[6];
   const uint32_t p = blockIdx.x, lane = threadIdx.x;
   const float4 self = in[(size_t)p * 64 + lane];
   const uint32_t m = mask[p];
@@ -766,21 +768,40 @@ __global__ __launch_bounds__(64) void k_filter_probes(const uint32_t* mask, MipI
   const float4 wp = ppos[p], np = pnrm[p];
   const float ex = wp.x - cx, ey = wp.y - cy, ez = wp.z - cz;
   const float cs = kappa * sqrtf((ex * ex + ey * ey) + ez * ez);
+  // the six searches and the plane test are the same for every cell: lanes 0..5 take one tap
+  // each and publish the neighbour
+  if (lane < 6) {
+    const int32_t step = (((lane & 1) << 1) - 1) * ((lane >> 1) + 1);
+    const uint32_t qm = find_closest_probe(mask, mi, px, py, VERTICAL ? 0 : step, VERTICAL ? step : 0);
+    uint32_t q = kSentinel;
+    if (qm != kSentinel) {
+      const uint32_t qi = ((qm >> 16) >> 3) * TW + ((qm & 0xFFFFu) >> 3);
+      const float4 wq = ppos[qi];
+      const float pd = fabsf(((wq.x - wp.x) * np.x + (wq.y - wp.y) * np.y) + (wq.z - wp.z) * np.z);
+      tap_w[lane] = wq;
+      tap_n[lane] = pnrm[qi];
+      if (!(pd > cs)) q = qi;
+    }
+    tap_q[lane] = q;
+  }
+  __syncthreads();
+  float4 rqs[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const uint32_t q = tap_q[i];
+    rqs[i] = q != kSentinel ? in[(size_t)q * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   float dx, dy, dz;
   cell_centre_direction(lane, np.x, np.y, np.z, dx, dy, dz);
   float r0 = self.x, r1 = self.y, r2 = self.z, r3 = self.w;
   float hit = r3, wsum = 1.0f;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const int32_t step = (((i & 1) << 1) - 1) * ((i >> 1) + 1);
-    const uint32_t qm = find_closest_probe(mask, mi, px, py, VERTICAL ? 0 : step, VERTICAL ? step : 0);
-    if (qm == kSentinel) continue;
-    const uint32_t q = ((qm >> 16) >> 3) * TW + ((qm & 0xFFFFu) >> 3);
-    const float4 wq = ppos[q], nq = pnrm[q];
-    const float pd = fabsf(((wq.x - wp.x) * np.x + (wq.y - wp.y) * np.y) + (wq.z - wp.z) * np.z);
+    if (tap_q[i] == kSentinel) continue;
+    const float4 wq = tap_w[i], nq = tap_n[i];
     const float nc = (dx * nq.x + dy * nq.y) + dz * nq.z;
-    if (pd > cs || nc < 0.0f) continue;
-    const float4 rq = in[(size_t)q * 64 + lane];
+    if (nc < 0.0f) continue;
+    const float4 rq = rqs[i];
     const float hd = fminf(rq.w, hit);
     const float e0 = (wq.x + dx * hd) - wp.x, e1 = (wq.y + dy * hd) - wp.y, e2 = (wq.z + dz * hd) - wp.z;
     const float el = sqrtf((e0 * e0 + e1 * e1) + e2 * e2);
