@@ -91,6 +91,13 @@ typedef struct gi_config {
     float mlp_loss_scale;        /* static loss scale                                     */
     float mlp_judge;             /* max rel. error vs confident plain cells before fallback */
     float scene_min[4], scene_max[4];  /* encoding domain (set by gi_build_bvh if zero)   */
+    /* levels of detail of the world cache (Section 2.2.1): at a hit d metres from the camera
+     * of the frame's spawn, cells are 2^lod times the base size, lod the smallest integer
+     * (<= 7) with 2^lod >= lod_scale * d * cell_scale, and lod enters the descriptor (bits
+     * 58-60).  lod_scale = Algorithm 6's distance scale keeps world cells about the size of the
+     * screen cache's adaptive cell; 0 = a single level. */
+    float lod_scale;
+    uint32_t reserved1[3];
 } gi_config;
 
 typedef struct gi_frame {

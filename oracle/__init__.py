@@ -30,7 +30,7 @@ class OrcConfig(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("rays_per_probe", C.c_uint32),
                 ("table_log2", C.c_uint32), ("bounces", C.c_uint32), ("leak_bit", C.c_uint32),
                 ("max_life", C.c_uint32), ("n_cap", C.c_uint32), ("seed", C.c_uint32),
-                ("frac_bits", C.c_uint32), ("probe_filter", C.c_uint32), ("pad1", C.c_uint32),
+                ("frac_bits", C.c_uint32), ("probe_filter", C.c_uint32), ("lod_scale", C.c_float),
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4)]
 
@@ -44,7 +44,7 @@ class OrcFrame(C.Structure):
 def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
-               eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0)
+               eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0)
     cfg.update(kw)
     return cfg
 
@@ -94,7 +94,7 @@ def _lib(f64: bool):
     fn("render_gbuffer", None, vp, C.POINTER(OrcFrame), C.c_uint32, C.c_uint32, R, R, R, U32P)
     fn("cell_moments", None, F64P)
     fn("cosine_dirs", None, R, R, R, C.c_uint32, R, U32P)
-    fn("keys", None, C.POINTER(OrcConfig), R, R, R, C.c_uint32, U64P, U32P, U32P)
+    fn("keys", None, C.POINTER(OrcConfig), R, R, R, R, C.c_uint32, U64P, U32P, U32P)
     fn("create", vp, C.POINTER(OrcConfig), vp)
     fn("destroy", None, vp)
     fn("distance_scale", C.c_float, C.c_float, C.c_uint32, C.c_uint32)
@@ -176,8 +176,11 @@ def cosine_dirs(n, u0, u1, f64=False):
     return d, cell
 
 
-def keys(cfg: dict, y, n, t, f64=False):
+def keys(cfg: dict, y, n, t, f64=False, cam=(0.0, 0.0, 0.0)):
+    """descriptor, bucket and fingerprint of points y with normals n and ray lengths t; cam is
+    the camera position the levels of detail are measured from"""
     dt = np.float64 if f64 else np.float32
+    cam = np.ascontiguousarray(cam, dt)
     y = np.ascontiguousarray(y, dt)
     n = np.ascontiguousarray(n, dt)
     t = np.ascontiguousarray(t, dt)
@@ -186,7 +189,7 @@ def keys(cfg: dict, y, n, t, f64=False):
     b = np.zeros(cnt, np.uint32)
     fp = np.zeros(cnt, np.uint32)
     c = make_config(cfg)
-    _call(f64, "keys", C.byref(c), y, n, t, cnt, key, b, fp)
+    _call(f64, "keys", C.byref(c), cam, y, n, t, cnt, key, b, fp)
     return key, b, fp
 
 

@@ -670,7 +670,8 @@ uint32_t ORC(pick_emitter)(const scene *sc, uint32_t r) { return sc->ne ? sc->et
 typedef struct orc_config {
     uint32_t width, height, rays_per_probe, table_log2;
     uint32_t bounces, leak_bit, max_life, n_cap;
-    uint32_t seed, frac_bits, probe_filter, pad1;
+    uint32_t seed, frac_bits, probe_filter;
+    float lod_scale;
     float cell_scale, r_max, eps_scale, t_sky;
     float sky[4];
 } orc_config;
@@ -757,6 +758,7 @@ typedef struct state {
     double mom[NCELL][10]; /* omega, m(3), M(xx,yy,zz,xy,xz,yz) */
     uint64_t stats[16];
     real kappa;
+    real cam[3];           /* camera of the last spawn (descriptor levels of detail) */
 } state;
 
 enum { ST_RAYS, ST_HITS, ST_INSERTS, ST_OVERFLOW, ST_NONFINITE, ST_WRAPS, ST_SHADOW, ST_OCCLUDED,
@@ -885,9 +887,27 @@ static real offset_eps(const orc_config *c, const real *p)
  * quantised hit position floor(y * S) (S = 1 / cell size), a 6-way class of the
  * face-forwarded surface normal, and the light-leak bit (ray length < cell size); LOD = 0.
  * ------------------------------------------------------------------------------------- */
-static uint64_t cell_key(const orc_config *c, const real *y, const real *n, real t, int with_leak)
+/* READING (Section 2.2.1, levels of detail of the world cache): the position quantisation is
+ * coarsened with the distance d from the camera so that a cell keeps roughly the size of
+ * Algorithm 6's adaptive cell, lod_scale * d: the cell size is the base size times 2^lod, the
+ * smallest power of two (lod <= 7) with 2^lod >= lod_scale * d * S; lod enters the descriptor
+ * and the leak test uses that level's cell size.  lod_scale = 0 keeps a single level. */
+static uint32_t cell_lod(const orc_config *c, const real *cam, const real *y)
 {
-    real S = (real)c->cell_scale;
+    if (!(c->lod_scale > 0.0f)) return 0;
+    real dx = y[0] - cam[0], dy = y[1] - cam[1], dz = y[2] - cam[2];
+    real d = RSQRT((dx * dx + dy * dy) + dz * dz);
+    real x = ((real)c->lod_scale * d) * (real)c->cell_scale;
+    uint32_t lod = 0;
+    real p = RC(1.0);
+    while (p < x && lod < 7) { p = p * RC(2.0); ++lod; }
+    return lod;
+}
+
+static uint64_t cell_key(const orc_config *c, const real *cam, const real *y, const real *n, real t, int with_leak)
+{
+    uint32_t lod = cell_lod(c, cam, y);
+    real S = (real)c->cell_scale * (RC(1.0) / (real)(1u << lod));
     int32_t qx = (int32_t)RFLOOR(y[0] * S);
     int32_t qy = (int32_t)RFLOOR(y[1] * S);
     int32_t qz = (int32_t)RFLOOR(y[2] * S);
@@ -898,7 +918,7 @@ static uint64_t cell_key(const orc_config *c, const real *y, const real *n, real
     uint64_t cls = (uint64_t)(2 * axis + (n[axis] < RC(0.0) ? 1 : 0));
     uint64_t leak = (with_leak && c->leak_bit && t * S < RC(1.0)) ? 1u : 0u;
     return ((uint64_t)(uint32_t)qx & 0x3FFFFu) | (((uint64_t)(uint32_t)qy & 0x3FFFFu) << 18) |
-           (((uint64_t)(uint32_t)qz & 0x3FFFFu) << 36) | (cls << 54) | (leak << 57);
+           (((uint64_t)(uint32_t)qz & 0x3FFFFu) << 36) | (cls << 54) | (leak << 57) | ((uint64_t)lod << 58);
 }
 
 static uint32_t key_bucket(uint64_t key, uint32_t nbuckets)
@@ -914,12 +934,12 @@ static uint32_t key_fingerprint(uint64_t key)
     return h == 0u ? 1u : h;
 }
 
-void ORC(keys)(const orc_config *c, const real *y, const real *n, const real *t, uint32_t cnt,
+void ORC(keys)(const orc_config *c, const real *cam, const real *y, const real *n, const real *t, uint32_t cnt,
                uint64_t *key, uint32_t *bucket, uint32_t *fp)
 {
     uint32_t nb = (1u << c->table_log2) / BUCKET;
     for (uint32_t i = 0; i < cnt; ++i) {
-        key[i] = cell_key(c, y + 3 * i, n + 3 * i, t[i], 1);
+        key[i] = cell_key(c, cam, y + 3 * i, n + 3 * i, t[i], 1);
         bucket[i] = key_bucket(key[i], nb);
         fp[i] = key_fingerprint(key[i]);
     }
@@ -1035,6 +1055,7 @@ float ORC(distance_scale)(float fov_y, uint32_t W, uint32_t H)
 void ORC(spawn)(state *st, const orc_frame *fr, const real *gpos, const real *gnrm, const uint32_t *gprim)
 {
     ORC(halton_jitter)(fr->index, &st->jx, &st->jy);
+    for (int k = 0; k < 3; ++k) st->cam[k] = (real)fr->pos[k];
     for (uint32_t ty = 0; ty < st->TH; ++ty)
         for (uint32_t tx = 0; tx < st->TW; ++tx) {
             uint32_t p = ty * st->TW + tx;
@@ -1133,7 +1154,7 @@ static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const 
             real dn = (n[0] * d[0] + n[1] * d[1]) + n[2] * d[2];
             real sg = dn > RC(0.0) ? RC(-1.0) : RC(1.0);
             for (int k = 0; k < 3; ++k) { z[k] = yo[k] + t * d[k]; nz[k] = sg * n[k]; }
-            int32_t slot = table_find(st, cell_key(c, z, nz, t, 1));
+            int32_t slot = table_find(st, cell_key(c, st->cam, z, nz, t, 1));
             *bslot = slot;
             if (slot >= 0)
                 for (int k = 0; k < 3; ++k) Lb[k] = st->L[3 * (size_t)slot + k];
@@ -1192,7 +1213,7 @@ void ORC(trace)(state *st, const orc_frame *fr)
             st->r_t[gid] = t;
             st->r_tri[gid] = tri;
             st->r_cell[gid] = flags;
-            uint64_t key = cell_key(c, y, ny, t, 1);
+            uint64_t key = cell_key(c, st->cam, y, ny, t, 1);
             st->r_keylo[gid] = (uint32_t)key;
             st->r_keyhi[gid] = (uint32_t)(key >> 32);
             real s[3];
@@ -1666,7 +1687,7 @@ void ORC(query)(const state *st, const real *pos, const real *nrm, uint32_t n, r
     for (uint32_t i = 0; i < n; ++i) {
         const real *p = pos + 4 * (size_t)i, *nn = nrm + 4 * (size_t)i;
         int with_leak = p[3] >= RC(0.0);
-        uint64_t key = cell_key(&st->cfg, p, nn, with_leak ? p[3] : RC(0.0), with_leak);
+        uint64_t key = cell_key(&st->cfg, st->cam, p, nn, with_leak ? p[3] : RC(0.0), with_leak);
         int32_t slot = table_find(st, key);
         for (int k = 0; k < 3; ++k) out[4 * (size_t)i + k] = slot >= 0 ? st->L[3 * (size_t)slot + k] : RC(0.0);
         out[4 * (size_t)i + 3] = slot >= 0 ? RC(1.0) : RC(0.0);

@@ -235,6 +235,7 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (!(g->cell_scale > 0.0f) || !(g->r_max > 0.0f) || !(g->eps_scale >= 0.0f)) { why = "cell_scale, r_max must be > 0"; return GI_ERR_INVALID_ARG; }
   if (g->cache_mode > GI_CACHE_MLP_FP8) { why = "unknown cache_mode"; return GI_ERR_INVALID_ARG; }
   if (g->probe_filter > 1) { why = "probe_filter must be 0 or 1"; return GI_ERR_INVALID_ARG; }
+  if (!(g->lod_scale >= 0.0f) || !(g->lod_scale < 1e30f)) { why = "lod_scale must be finite and >= 0"; return GI_ERR_INVALID_ARG; }
   return GI_OK;
 }
 

@@ -108,8 +108,29 @@ __device__ inline float origin_offset(float scale, float px, float py, float pz)
 }
 
 // ---- world-cache descriptor (Section 2.2.1, 2.2.2) ----
-__device__ inline uint64_t descriptor(float S, uint32_t leak_on, float yx, float yy, float yz,
-                                      float nx, float ny, float nz, float t, bool with_leak) {
+// Level of detail: the cell size is the base size times 2^lod, the smallest power of two
+// (lod <= 7) with 2^lod >= lod_scale * d * S, d the distance from the camera; 0 when lod_scale
+// is 0.  Doubling in a loop keeps the decision exact.
+__device__ inline uint32_t cell_lod(float S, float lod_scale, float cx, float cy, float cz, float yx, float yy,
+                                    float yz) {
+  if (!(lod_scale > 0.0f)) return 0u;
+  const float dx = yx - cx, dy = yy - cy, dz = yz - cz;
+  const float d = sqrtf((dx * dx + dy * dy) + dz * dz);
+  const float x = (lod_scale * d) * S;
+  uint32_t lod = 0;
+  float p = 1.0f;
+  while (p < x && lod < 7u) {
+    p = p * 2.0f;
+    ++lod;
+  }
+  return lod;
+}
+
+__device__ inline uint64_t descriptor(float S0, uint32_t leak_on, float lod_scale, float cx, float cy, float cz,
+                                      float yx, float yy, float yz, float nx, float ny, float nz, float t,
+                                      bool with_leak) {
+  const uint32_t lod = cell_lod(S0, lod_scale, cx, cy, cz, yx, yy, yz);
+  const float S = S0 * (1.0f / (float)(1u << lod));
   const int32_t qx = (int32_t)floorf(yx * S);
   const int32_t qy = (int32_t)floorf(yy * S);
   const int32_t qz = (int32_t)floorf(yz * S);
@@ -122,7 +143,7 @@ __device__ inline uint64_t descriptor(float S, uint32_t leak_on, float yx, float
   const uint64_t cls = 2u * axis + (comp < 0.0f ? 1u : 0u);
   const uint64_t leak = (with_leak && leak_on && t * S < 1.0f) ? 1u : 0u;
   return ((uint64_t)((uint32_t)qx & 0x3FFFFu)) | ((uint64_t)((uint32_t)qy & 0x3FFFFu) << 18) |
-         ((uint64_t)((uint32_t)qz & 0x3FFFFu) << 36) | (cls << 54) | (leak << 57);
+         ((uint64_t)((uint32_t)qz & 0x3FFFFu) << 36) | (cls << 54) | (leak << 57) | ((uint64_t)lod << 58);
 }
 
 __device__ inline uint32_t bucket_of(uint64_t key, uint32_t bucket_mask) {

@@ -248,6 +248,8 @@ struct CacheArgs {
   float r_max;
   uint32_t bounces;
   float sky[3];
+  float lod_scale;     // levels of detail of the descriptor (0 = one level)
+  float cam[3];        // camera of the frame's spawn
 };
 
 __device__ inline int32_t table_lookup(const CacheArgs& c, uint64_t key) {
@@ -380,7 +382,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float sg = dn > 0.0f ? -1.0f : 1.0f;
   const float yx = ox + t * dx, yy = oy + t * dy, yz = oz + t * dz;
   const float nx = sg * n.x, ny = sg * n.y, nz = sg * n.z;
-  const uint64_t key = descriptor(c.cell_scale, c.leak_bit, yx, yy, yz, nx, ny, nz, t, true);
+  const uint64_t key = descriptor(c.cell_scale, c.leak_bit, c.lod_scale, c.cam[0], c.cam[1], c.cam[2], yx, yy, yz, nx,
+                                  ny, nz, t, true);
   rkey[gid] = make_uint2((uint32_t)key, (uint32_t)(key >> 32));
   if (lo.hitpos) {
     lo.hitpos[gid] = make_float4(yx, yy, yz, t);
@@ -429,7 +432,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
       const float4 bn = st.tnrm[btri];
       const float bdn = (bn.x * bx + bn.y * by) + bn.z * bz;
       const float bs = bdn > 0.0f ? -1.0f : 1.0f;
-      const uint64_t bkey = descriptor(c.cell_scale, c.leak_bit, px + bt * bx, py + bt * by, pz + bt * bz,
+      const uint64_t bkey = descriptor(c.cell_scale, c.leak_bit, c.lod_scale, c.cam[0], c.cam[1], c.cam[2],
+                                       px + bt * bx, py + bt * by, pz + bt * bz,
                                        bs * bn.x, bs * bn.y, bs * bn.z, bt, true);
       const int32_t bslot = table_lookup(c, bkey);
       if (bslot >= 0) {
@@ -937,7 +941,8 @@ __global__ void k_query(const float4* pos, const float4* nrm, uint32_t n, CacheA
   if (i >= n) return;
   const float4 p = pos[i], q = nrm[i];
   const bool wl = p.w >= 0.0f;
-  const uint64_t key = descriptor(c.cell_scale, c.leak_bit, p.x, p.y, p.z, q.x, q.y, q.z, wl ? p.w : 0.0f, wl);
+  const uint64_t key = descriptor(c.cell_scale, c.leak_bit, c.lod_scale, c.cam[0], c.cam[1], c.cam[2], p.x, p.y, p.z,
+                                  q.x, q.y, q.z, wl ? p.w : 0.0f, wl);
   const int32_t s = table_lookup(c, key);
   if (s < 0) {
     out[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1098,6 +1103,8 @@ static CacheArgs cache_args(const gi_context* c) {
   a.sky[0] = c->cfg.sky[0];
   a.sky[1] = c->cfg.sky[1];
   a.sky[2] = c->cfg.sky[2];
+  a.lod_scale = c->cfg.lod_scale;
+  for (int k = 0; k < 3; ++k) a.cam[k] = c->fa.cam[k];
   return a;
 }
 

@@ -39,7 +39,8 @@ class Config(C.Structure):
                 ("mlp_table_log2", C.c_uint32), ("mlp_steps", C.c_uint32),
                 ("mlp_lr_grid", C.c_float), ("mlp_lr_mlp", C.c_float),
                 ("mlp_loss_scale", C.c_float), ("mlp_judge", C.c_float),
-                ("scene_min", C.c_float * 4), ("scene_max", C.c_float * 4)]
+                ("scene_min", C.c_float * 4), ("scene_max", C.c_float * 4),
+                ("lod_scale", C.c_float), ("reserved1", C.c_uint32 * 3)]
 
 
 class Frame(C.Structure):

@@ -112,6 +112,49 @@ def test_field_probe_filter_frames():
                                probe_filter=1), [0, 1])
 
 
+def test_room_levels_of_detail_frames():
+    """descriptor levels of detail on (lod_scale 0.065, Algorithm 6's distance scale at
+    128x128): room distances of 1-6 m give levels 0-3; two bounces, so the bounce lookups use
+    the levels too; keys, fixed-point sums, cells, atlas and irradiance as everywhere"""
+    pr = _run_stage_parity(I.room_scene(), dict(width=128, height=128, rays_per_probe=16, table_log2=16,
+                                                bounces=2, lod_scale=0.065), [0, 1])
+    lods = (pr.ost.table()["key"].astype(np.int64) >> 58) & 7
+    assert len(np.unique(lods)) >= 3, np.unique(lods)
+
+
+def test_field_levels_of_detail_frames_and_query():
+    """levels of detail on the field at 160x96 (lod_scale 0.05: 2-80 m give levels 0-6), two
+    frames with the moving light, then lookup-only queries at random points and at the
+    frame's hit points (measured from the last spawn's camera on both sides)"""
+    sc = I.field_scene()
+    pr = _run_stage_parity(sc, dict(width=160, height=96, rays_per_probe=64, table_log2=18, sky=sc.sky,
+                                    lod_scale=0.05), [0, 1])
+    lods = (pr.ost.table()["key"].astype(np.int64) >> 58) & 7
+    assert len(np.unique(lods)) >= 4, np.unique(lods)
+    pos, nrm = I.query_points(4000, -40.0, 40.0)
+    pos[:, 1] = np.abs(pos[:, 1]) % 3.0
+    # visible surface points of the last frame (the oracle's G-buffer), where probe rays of
+    # neighbouring probes have created cells
+    fr = I.camera_for("field", 1)
+    fr.index = 1
+    _, (op, on, oa, oprim) = pr.gbuffer(fr)
+    vis = np.nonzero(oprim.reshape(-1) != 0xFFFFFFFF)[0][::7]
+    sp = op.reshape(-1, 4)[vis].copy()
+    sp[:, 3] = -1.0
+    sn = on.reshape(-1, 4)[vis].copy()
+    sn[:, 3] = 0.0
+    pos = np.concatenate([pos, sp.astype(np.float32)])
+    nrm = np.concatenate([nrm, sn.astype(np.float32)])
+    out = torch.zeros((len(pos), 4), dtype=torch.float32, device="cuda")
+    pr.ctx.cache_query(torch.from_numpy(pos).cuda(), torch.from_numpy(nrm).cuda(), out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    o = pr.ost.query(pos, nrm)
+    assert np.array_equal(g[:, 3], o[:, 3])
+    assert o[4000:, 3].sum() > 100, "the surface queries should find cells"
+    assert_close(g[:, :3], o[:, :3], what="query")
+
+
 def test_room_overflowing_table_invariants():
     pr = Pair(I.room_scene(), dict(width=64, height=64, rays_per_probe=32, table_log2=6))
     fr = I.room_camera(0)

@@ -190,6 +190,34 @@ def test_key_hand_cases():
     assert [(int(v) >> 54) & 7 for v in ks] == [0, 1, 2, 3, 4, 5, 0, 3]
 
 
+@pytest.mark.parametrize("f64", [False, True])
+def test_key_levels_of_detail_hand_cases(f64):
+    """Section 2.2.1 levels of detail (READING: cell size = base size x 2^lod, lod the smallest
+    integer <= 7 with 2^lod >= lod_scale * d * S).  Camera at the origin, S = 10 (0.1 m cells),
+    lod_scale = 0.01: x = 0.1 d, so d = 5, 15, 19, 21, 45 m give lod 0, 1, 1, 2, 3 and a point
+    100 km away is capped at 7.  The position is quantised at the level's cell size and the
+    leak test uses it too."""
+    cfg = O.default_config(lod_scale=0.01)
+    d = np.array([5.0, 15.0, 19.0, 21.0, 45.0, 1e5])
+    y = np.stack([d, np.zeros(6), np.zeros(6)], 1)
+    key = O.keys(cfg, y, np.tile([0, 1, 0], (6, 1)), np.ones(6), f64=f64)[0].astype(np.int64)
+    assert list((key >> 58) & 7) == [0, 1, 1, 2, 3, 7]
+    qx = key & 0x3FFFF
+    # floor(d * 10 / 2^lod): 50, 75, 95, 52 (52.5), 56 (56.25), (1e6 / 128 = 7812) mod 2^18
+    assert list(qx) == [50, 75, 95, 52, 56, 7812]
+    # leak bit: t = 0.15 m is shorter than a 0.2 m cell (lod 1) but not than a 0.1 m cell
+    k0 = int(O.keys(cfg, [[5.0, 0, 0]], [[0, 1, 0]], [0.15], f64=f64)[0][0])
+    k1 = int(O.keys(cfg, [[15.0, 0, 0]], [[0, 1, 0]], [0.15], f64=f64)[0][0])
+    assert (k0 >> 57) & 1 == 0 and (k1 >> 57) & 1 == 1
+    # lod_scale 0: one level, the same keys as without levels
+    k_off = O.keys(O.default_config(), y, np.tile([0, 1, 0], (6, 1)), np.ones(6), f64=f64)[0].astype(np.int64)
+    assert ((k_off >> 58) == 0).all()
+    assert list(k_off & 0x3FFFF) == [50, 150, 190, 210, 450, 1000000 % (1 << 18)]
+    # the distance is measured from the camera
+    k_cam = O.keys(cfg, y, np.tile([0, 1, 0], (6, 1)), np.ones(6), f64=f64, cam=(15.0, 0.0, 0.0))[0].astype(np.int64)
+    assert int(k_cam[1] >> 58) == 0
+
+
 def test_key_quantiser_is_the_float32_product():
     cfg = O.default_config()
     rng = np.random.default_rng(3)
