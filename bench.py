@@ -252,7 +252,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-FORMS = {"plain": 0, "mlp_bf16": 1, "mlp_fp8": 2}
+FORMS = {"plain": 0, "plain_lod": 0, "mlp_bf16": 1, "mlp_fp8": 2}
 MLP_CFG = dict(mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4, mlp_lr_grid=1e-2,
                mlp_lr_mlp=1e-2, mlp_judge=0.5)
 SWEEP_R = (8, 16, 32, 64, 128)
@@ -270,8 +270,12 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
     from paper_2310_19855_amd import gi
     from paper_2310_19855_amd import inputs as I
     cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, cache_mode=FORMS[form])
-    if form != "plain":
+    if form in ("mlp_bf16", "mlp_fp8"):
         cfg.update(MLP_CFG)
+    if form == "plain_lod":
+        # levels of detail that follow Algorithm 6's adaptive cell size of this view
+        fov = I.camera_for(scene_name, 0).fov_y
+        cfg["lod_scale"] = math.tan(fov * 8.0 * max(1.0 / H, H / (W * W)))
     cfg.update(extra or {})
     ctx = gi.Context(**cfg)
     ctx.build_bvh(scene)
@@ -293,7 +297,7 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
         cam.index = f
         ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
         ctx.trace_probes(cam)
-        if form != "plain":
+        if form in ("mlp_bf16", "mlp_fp8"):
             ctx.learned_train(cam)
         ctx.cache_update(cam)
         ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, out)
@@ -306,7 +310,8 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
         prof = ctx.profile_read()
         ctx.profile(False)
         kern = {k: round(v[1] / n, 4) for k, v in prof.items()}
-    res = {"ms": ms, "kernels": kern, "learned": ctx.learned_stats() if form != "plain" else None}
+    learned = form in ("mlp_bf16", "mlp_fp8")
+    res = {"ms": ms, "kernels": kern, "learned": ctx.learned_stats() if learned else None}
     if want_out:
         res["out"] = out.cpu().numpy()
     if points is not None:
@@ -314,7 +319,7 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
         q = torch.zeros((pp.shape[0], 4), dtype=torch.float32, device="cuda")
         ctx.cache_query(pp, pn, q)
         res["plain_at_points"] = q.cpu().numpy()
-        if form != "plain":
+        if learned:
             ctx.learned_query(pp, pn, q)
             res["form_at_points"] = q.cpu().numpy()
         else:
