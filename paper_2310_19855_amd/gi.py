@@ -20,6 +20,8 @@ ERRORS = {-1: "GI_ERR_INVALID_ARG", -2: "GI_ERR_OOM", -3: "GI_ERR_HIP", -4: "GI_
           -5: "GI_ERR_UNSUPPORTED", -6: "GI_ERR_INTERNAL"}
 CACHE_PLAIN, CACHE_MLP_BF16, CACHE_MLP_FP8 = 0, 1, 2
 RAY_HIT, RAY_FRONT, RAY_EMIT, RAY_TRACED = 0x100, 0x200, 0x400, 0x10000
+# per-pixel flags of the interpolation output (alpha channel): GI_INTERP_* of include/gi.h
+INTERP_OK, INTERP_RELAXED, INTERP_NO_PROBE, INTERP_SKY = 0.0, 1.0, 2.0, 3.0
 STAT_NAMES = ["rays", "hits", "inserts", "overflow", "nonfinite", "wraps", "shadow", "occluded",
               "evict", "live", "relaxed", "noprobe", "bounce", "mlp_skipped", "mlp_fallback", "_15"]
 

@@ -28,10 +28,13 @@ def _compare_table(gt, ot):
     assert np.array_equal(gt["acc"], ot["acc"]), "fixed-point sums differ"
 
 
-def _run_stage_parity(scene, cfg, frames, check_every=True):
+def _run_stage_parity(scene, cfg, frames, check_every=True, camera=None):
     pr = Pair(scene, cfg)
     for f in frames:
-        fr = I.camera_for(scene.name, f) if scene.name != "room" else I.room_camera(0)
+        if camera is not None:
+            fr = camera(f)
+        else:
+            fr = I.camera_for(scene.name, f) if scene.name != "room" else I.room_camera(0)
         fr.index = f
         pr.set_frame_dynamic(f)
         (gp, gn, ga, gprim), (op, on, oa, oprim) = pr.gbuffer(fr)
@@ -153,6 +156,43 @@ def test_field_levels_of_detail_frames_and_query():
     assert np.array_equal(g[:, 3], o[:, 3])
     assert o[4000:, 3].sum() > 100, "the surface queries should find cells"
     assert_close(g[:, :3], o[:, :3], what="query")
+
+
+@pytest.mark.parametrize("R", [1, 256])
+def test_extreme_rays_per_probe(R):
+    """the smallest and the largest number of rays per probe (256 rays: four waves per probe
+    in the trace, four chunks in the gather's per-cell sums)"""
+    _run_stage_parity(I.room_scene(), dict(width=72, height=40, rays_per_probe=R, table_log2=16, bounces=2), [0, 1])
+
+
+def test_minimum_frame_one_tile():
+    """an 8x8 frame: one probe tile, a MIP chain of one level"""
+    _run_stage_parity(I.room_scene(), dict(width=8, height=8, rays_per_probe=32, table_log2=10), [0, 1, 2])
+
+
+def test_all_sky_view_has_no_probes():
+    """a camera looking straight up over the field: every primary ray misses, so every tile
+    is empty, no probe ray is traced and every pixel is flagged as sky"""
+    sc = I.field_scene()
+    cam = lambda f: I.look_frame(f, (0.0, 30.0, 0.0), (0.0, 1.0, 0.0), world_up=(0.0, 0.0, 1.0))
+    pr = _run_stage_parity(sc, dict(width=64, height=48, rays_per_probe=16, table_log2=12, sky=sc.sky), [0],
+                           camera=cam)
+    assert pr.ctx.stats()["rays"] == 0
+    assert (pr.out.cpu().numpy()[..., 3] == gi.INTERP_SKY).all()
+
+
+@pytest.mark.parametrize("n_tris", [1, 2])
+def test_one_and_two_triangle_scenes(n_tris):
+    """the smallest scenes: a floor triangle (and, with two, an emitting triangle above it
+    facing down); the BVH is a root holding one leaf"""
+    v = np.array([[-5, 0, -5], [5, 0, -5], [0, 0, 8], [-1, 3, -1], [0, 3, 1], [1, 3, -1]], np.float32)
+    idx = np.array([[0, 2, 1], [3, 4, 5]], np.uint32)[:n_tris]
+    mats = np.array([[0.6, 0.5, 0.4, 0, 0, 0], [0, 0, 0, 20, 20, 20]], np.float32)
+    sc = I.Scene(name="tri", verts=v, idx=idx, tri_mat=np.arange(n_tris, dtype=np.uint32), materials=mats,
+                 sky=(0.1, 0.1, 0.1))
+    cam = lambda f: I.look_frame(f, (0.0, 1.5, -4.0), (0.0, -0.3, 1.0))
+    _run_stage_parity(sc, dict(width=48, height=40, rays_per_probe=32, table_log2=10, sky=sc.sky), [0, 1],
+                      camera=cam)
 
 
 def test_room_overflowing_table_invariants():
