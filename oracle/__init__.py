@@ -32,7 +32,8 @@ class OrcConfig(C.Structure):
                 ("max_life", C.c_uint32), ("n_cap", C.c_uint32), ("seed", C.c_uint32),
                 ("frac_bits", C.c_uint32), ("probe_filter", C.c_uint32), ("lod_scale", C.c_float),
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
-                ("t_sky", C.c_float), ("sky", C.c_float * 4)]
+                ("t_sky", C.c_float), ("sky", C.c_float * 4),
+                ("temporal", C.c_uint32), ("pad2", C.c_uint32), ("pad3", C.c_uint32), ("pad4", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -44,7 +45,8 @@ class OrcFrame(C.Structure):
 def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
-               eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0)
+               eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
+               temporal=0)
     cfg.update(kw)
     return cfg
 
@@ -114,6 +116,9 @@ def _lib(f64: bool):
     fn("sh_eval", None, R, R, C.c_uint32, R)
     fn("sh_project_atlas", None, vp, R, R, C.c_uint32, R)
     fn("filter_atlas", None, vp, C.POINTER(OrcFrame), C.c_int32, C.c_int32, R, R)
+    fn("half_bits", C.c_uint32, C.c_float)
+    fn("temporal_blend_atlas", None, R, R, C.c_uint32, R)
+    fn("temporal_export", None, vp, U32P, U32P)
     fn("nee_samples", None, vp, C.POINTER(OrcFrame), R, R, U32P, C.c_uint32, R)
     _LIBS[key] = (lib, p)
     return _LIBS[key]
@@ -174,6 +179,21 @@ def cosine_dirs(n, u0, u1, f64=False):
     cell = np.zeros(len(u0), np.uint32)
     _call(f64, "cosine_dirs", n, u0, u1, len(u0), d, cell)
     return d, cell
+
+
+def half_bits(x: float) -> int:
+    """IEEE binary16 bits of a non-negative float32, round to nearest even"""
+    return int(_call(False, "half_bits", float(x)))
+
+
+def temporal_blend(curr, prev, f64=True):
+    """Algorithm 3 on cells [n][4] (rgb, travelled distance)"""
+    dt = np.float64 if f64 else np.float32
+    c = np.ascontiguousarray(curr, dt).reshape(-1, 4)
+    q = np.ascontiguousarray(prev, dt).reshape(-1, 4)
+    out = np.zeros_like(c)
+    _call(f64, "temporal_blend_atlas", c, q, len(c), out)
+    return out
 
 
 def keys(cfg: dict, y, n, t, f64=False, cam=(0.0, 0.0, 0.0)):
@@ -419,6 +439,15 @@ class OracleFrameState:
         _call(self.f64, "nee_samples", self.h, C.byref(f), np.ascontiguousarray(y, self.dt),
               np.ascontiguousarray(ny, self.dt), ids, len(ids), out)
         return out
+
+    def temporal(self):
+        """per tile: the pixel (mask encoding) the previous frame's probe moved to and the
+        previous tile it came from (SENTINEL where none), after the last spawn"""
+        P = int(self.dims()[0])
+        win = np.zeros(P, np.uint32)
+        hist = np.zeros(P, np.uint32)
+        _call(self.f64, "temporal_export", self.h, win, hist)
+        return win, hist
 
     def filter_atlas(self, frame, axis, atlas):
         """one pass of the probe-space filter (Algorithm 5) along axis 0 (x) or 1 (y) over an

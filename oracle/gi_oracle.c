@@ -674,6 +674,7 @@ typedef struct orc_config {
     float lod_scale;
     float cell_scale, r_max, eps_scale, t_sky;
     float sky[4];
+    uint32_t temporal, pad2, pad3, pad4;
 } orc_config;
 
 typedef struct orc_frame {
@@ -759,6 +760,13 @@ typedef struct state {
     uint64_t stats[16];
     real kappa;
     real cam[3];           /* camera of the last spawn (descriptor levels of detail) */
+    /* temporal reuse of probes (Algorithms 1 and 3) */
+    uint32_t has_prev;
+    orc_frame prev_fr;     /* camera of the previous frame */
+    uint32_t *prev_mask;   /* [P] level 0 of the previous frame's probe mask */
+    real *prev_pos, *prev_nrm, *prev_atlas;
+    uint32_t *win;         /* [P] pixel (mask encoding) the previous probe moved to, or SENTINEL */
+    uint32_t *hist;        /* [P] previous tile of that probe, or SENTINEL */
 } state;
 
 enum { ST_RAYS, ST_HITS, ST_INSERTS, ST_OVERFLOW, ST_NONFINITE, ST_WRAPS, ST_SHADOW, ST_OCCLUDED,
@@ -1024,6 +1032,13 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->accessed = (uint32_t *)calloc(N, sizeof(uint32_t));
     st->atlas = (real *)calloc(P * NCELL * 4, sizeof(real));
     st->sh = (real *)calloc(P * 27, sizeof(real));
+    st->prev_mask = (uint32_t *)calloc(P, sizeof(uint32_t));
+    st->prev_pos = (real *)calloc(4 * P, sizeof(real));
+    st->prev_nrm = (real *)calloc(4 * P, sizeof(real));
+    st->prev_atlas = (real *)calloc(P * NCELL * 4, sizeof(real));
+    st->win = (uint32_t *)calloc(P, sizeof(uint32_t));
+    st->hist = (uint32_t *)calloc(P, sizeof(uint32_t));
+    for (size_t i = 0; i < P; ++i) st->win[i] = st->hist[i] = SENTINEL;
     ORC(cell_moments)(&st->mom[0][0]);
     return st;
 }
@@ -1036,6 +1051,8 @@ void ORC(destroy)(state *st)
     free(st->r_sample); free(st->r_keylo); free(st->r_keyhi); free(st->r_valid); free(st->r_bslot);
     free(st->fp); free(st->key); free(st->acc); free(st->dacc); free(st->L);
     free(st->nhist); free(st->life); free(st->accessed); free(st->atlas); free(st->sh);
+    free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
+    free(st->hist);
     free(st);
 }
 
@@ -1048,6 +1065,105 @@ float ORC(distance_scale)(float fov_y, uint32_t W, uint32_t H)
 }
 
 /* ---------------------------------------------------------------------------------------
+ * Temporal reuse of screen probes: probe reprojection (Section 2.1.1, Algorithm 1).
+ * Every pixel p of a tile that is not sky looks up, in the previous frame, the pixel q it was
+ * seen at and the probe of q's tile; if that probe lies within the cell size (Algorithm 6) of
+ * p's tangent plane and its normal is within the 0.95 cosine of p's, p bids the half-precision
+ * distance to it, packed above its lane index; the smallest bid wins, and the tile's probe
+ * moves to that pixel with the previous probe's radiance as history.
+ * READING: motion vectors are the reprojection of the pixel's world position with the
+ * previous frame's camera (static geometry; the moving light is not geometry of the G-buffer);
+ * q is the pixel whose centre region holds the projection; lane = 8 (y % 8) + (x % 8); with
+ * temporal reuse on, a tile with a winner places its probe at the winning pixel instead of
+ * the frame's Halton pixel (upscale 1x1: every tile traces every frame).
+ * ------------------------------------------------------------------------------------- */
+/* float -> IEEE binary16 bits, round to nearest even (for x >= 0 or NaN) */
+static uint32_t half_bits(float x)
+{
+    uint32_t f;
+    memcpy(&f, &x, 4);
+    f &= 0x7FFFFFFFu;
+    if (f >= 0x7F800000u) return f > 0x7F800000u ? 0x7E00u : 0x7C00u;
+    int32_t e = (int32_t)(f >> 23) - 127 + 15;
+    if (e >= 31) return 0x7C00u;
+    if (e <= 0) {
+        if (e < -10) return 0u;
+        uint32_t m = (f & 0x7FFFFFu) | 0x800000u;
+        uint32_t sh = (uint32_t)(14 - e);
+        uint32_t h = m >> sh, rem = m & ((1u << sh) - 1u), hf = 1u << (sh - 1u);
+        if (rem > hf || (rem == hf && (h & 1u))) ++h;
+        return h;
+    }
+    uint32_t h = ((uint32_t)e << 10) | ((f & 0x7FFFFFu) >> 13);
+    uint32_t rem = f & 0x1FFFu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) ++h;
+    return h;
+}
+
+uint32_t ORC(half_bits)(float x) { return half_bits(x); }
+
+/* pixel of the previous frame in which world point X was seen; 0 if behind or off screen */
+static int project_prev(const state *st, const real *X, int32_t *qx, int32_t *qy)
+{
+    const orc_frame *pf = &st->prev_fr;
+    real v[3] = {X[0] - (real)pf->pos[0], X[1] - (real)pf->pos[1], X[2] - (real)pf->pos[2]};
+    real z = (v[0] * (real)pf->fwd[0] + v[1] * (real)pf->fwd[1]) + v[2] * (real)pf->fwd[2];
+    if (!(z > RC(0.0))) return 0;
+    real a = ((v[0] * (real)pf->right[0] + v[1] * (real)pf->right[1]) + v[2] * (real)pf->right[2]) / z;
+    real b = ((v[0] * (real)pf->up[0] + v[1] * (real)pf->up[1]) + v[2] * (real)pf->up[2]) / z;
+    real aspect = (real)st->W / (real)st->H;
+    real sx = a / ((real)pf->tan_half * aspect), sy = b / (real)pf->tan_half;
+    real fx = ((sx + RC(1.0)) * (real)st->W) * RC(0.5), fy = ((RC(1.0) - sy) * (real)st->H) * RC(0.5);
+    if (!(fx >= RC(0.0) && fx < (real)st->W && fy >= RC(0.0) && fy < (real)st->H)) return 0;
+    *qx = (int32_t)fx;
+    *qy = (int32_t)fy;
+    return 1;
+}
+
+static void reproject(state *st, const orc_frame *fr, const real *gpos, const real *gnrm, const uint32_t *gprim)
+{
+    real kappa = (real)ORC(distance_scale)(fr->fov_y, st->W, st->H);
+    const uint32_t init = (half_bits(65504.0f) << 16) | 0xFFFFu;
+#pragma omp parallel for schedule(static)
+    for (long t = 0; t < (long)st->P; ++t) {
+        uint32_t tx = (uint32_t)t % st->TW, ty = (uint32_t)t / st->TW;
+        uint32_t best = init, best_q = SENTINEL;
+        for (uint32_t lane = 0; lane < 64; ++lane) {
+            uint32_t x = 8 * tx + (lane & 7u), y = 8 * ty + (lane >> 3);
+            if (x >= st->W || y >= st->H) continue;
+            size_t pix = (size_t)y * st->W + x;
+            if (gprim[pix] == MISS) continue;
+            const real *X = gpos + 4 * pix, *n = gnrm + 4 * pix;
+            int32_t qx, qy;
+            if (!project_prev(st, X, &qx, &qy)) continue;
+            uint32_t q = (uint32_t)(qy >> 3) * st->TW + (uint32_t)(qx >> 3);
+            if (st->prev_mask[q] == SENTINEL) continue;
+            const real *wq = st->prev_pos + 4 * (size_t)q, *nq = st->prev_nrm + 4 * (size_t)q;
+            real dx = X[0] - (real)fr->pos[0], dy = X[1] - (real)fr->pos[1], dz = X[2] - (real)fr->pos[2];
+            real cs = kappa * RSQRT((dx * dx + dy * dy) + dz * dz);
+            real pd = RABS(((wq[0] - X[0]) * n[0] + (wq[1] - X[1]) * n[1]) + (wq[2] - X[2]) * n[2]);
+            real nc = (nq[0] * n[0] + nq[1] * n[1]) + nq[2] * n[2];
+            if (pd < cs && nc > RC(0.95)) {
+                real ex = wq[0] - X[0], ey = wq[1] - X[1], ez = wq[2] - X[2];
+                real dist = RSQRT((ex * ex + ey * ey) + ez * ez);
+                uint32_t score = (half_bits((float)dist) << 16) | lane;
+                if (score < best) {
+                    best = score;
+                    best_q = q;
+                }
+            }
+        }
+        if (best_q != SENTINEL) {
+            uint32_t lane = best & 0xFFFFu;
+            st->win[t] = ((8 * ty + (lane >> 3)) << 16) | (8 * tx + (lane & 7u));
+            st->hist[t] = best_q;
+        } else {
+            st->win[t] = st->hist[t] = SENTINEL;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------------------
  * Spawn (Section 2.1.1) and probe mask with its MIP chain (Section 2.1.5).
  * READING: a tile whose jittered pixel is off screen or sky gets the sentinel; the mask packs
  * (y << 16) | x; each MIP entry keeps the first valid probe of its 2x2 children in raster order.
@@ -1056,12 +1172,19 @@ void ORC(spawn)(state *st, const orc_frame *fr, const real *gpos, const real *gn
 {
     ORC(halton_jitter)(fr->index, &st->jx, &st->jy);
     for (int k = 0; k < 3; ++k) st->cam[k] = (real)fr->pos[k];
+    if (st->cfg.temporal && st->has_prev) reproject(st, fr, gpos, gnrm, gprim);
     for (uint32_t ty = 0; ty < st->TH; ++ty)
         for (uint32_t tx = 0; tx < st->TW; ++tx) {
             uint32_t p = ty * st->TW + tx;
             uint32_t px = 8 * tx + st->jx, py = 8 * ty + st->jy;
             uint32_t m = SENTINEL;
-            if (px < st->W && py < st->H && gprim[(size_t)py * st->W + px] != MISS) m = (py << 16) | px;
+            if (st->cfg.temporal && st->win[p] != SENTINEL) {
+                m = st->win[p];
+                px = m & 0xFFFFu;
+                py = m >> 16;
+            } else if (px < st->W && py < st->H && gprim[(size_t)py * st->W + px] != MISS) {
+                m = (py << 16) | px;
+            }
             st->mask[p] = m;
             for (int k = 0; k < 4; ++k) {
                 if (m == SENTINEL) {
@@ -1574,10 +1697,72 @@ void ORC(filter_atlas)(const state *st, const orc_frame *fr, int32_t ax, int32_t
     filter_pass(st, cam, kappa, ax, ay, in, out);
 }
 
+/* ---------------------------------------------------------------------------------------
+ * Radiance blending (Section 2.1.4) with the biased shadow-preserving temporal hysteresis of
+ * Algorithm 3: per cell, the luminances l1 (new) and l2 (history) give
+ * alpha = clamp(max(l1 - l2 - min(l1, l2), 0) / max(max(l1, l2), 1e-4), 0, 0.95)^2 and the
+ * cell becomes lerp(new, history, alpha): a cell brighter than twice its history is held back,
+ * a darker one is taken at once.
+ * READING: the history is the reprojected probe's final radiance of the previous frame; the
+ * travelled distance is blended with the same alpha.
+ * ------------------------------------------------------------------------------------- */
+static void temporal_blend(state *st)
+{
+    const real third = RC(1.0) / RC(3.0);
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < (long)st->P; ++p) {
+        if (st->hist[p] == SENTINEL || st->mask[p] == SENTINEL) continue;
+        real *at = st->atlas + (size_t)p * NCELL * 4;
+        const real *pv = st->prev_atlas + (size_t)st->hist[p] * NCELL * 4;
+        for (int cell = 0; cell < NCELL; ++cell) {
+            real *c = at + 4 * cell;
+            const real *q = pv + 4 * cell;
+            real l1 = (c[0] * third + c[1] * third) + c[2] * third;
+            real l2 = (q[0] * third + q[1] * third) + q[2] * third;
+            real a = rmax((l1 - l2) - rmin(l1, l2), RC(0.0)) / rmax(rmax(l1, l2), RC(1e-4));
+            a = a < RC(0.0) ? RC(0.0) : (a > RC(0.95) ? RC(0.95) : a);
+            a = a * a;
+            for (int k = 0; k < 4; ++k) c[k] = c[k] + a * (q[k] - c[k]);
+        }
+    }
+}
+
+static void save_history(state *st, const orc_frame *fr)
+{
+    memcpy(st->prev_mask, st->mask, sizeof(uint32_t) * st->P);
+    memcpy(st->prev_pos, st->ppos, sizeof(real) * 4 * st->P);
+    memcpy(st->prev_nrm, st->pnrm, sizeof(real) * 4 * st->P);
+    memcpy(st->prev_atlas, st->atlas, sizeof(real) * 4 * NCELL * st->P);
+    st->prev_fr = *fr;
+    st->has_prev = 1;
+}
+
+void ORC(temporal_blend_atlas)(const real *curr, const real *prev, uint32_t n, real *out)
+{
+    /* Algorithm 3 on caller cells [n][4] (test entry) */
+    const real third = RC(1.0) / RC(3.0);
+    for (uint32_t i = 0; i < n; ++i) {
+        const real *c = curr + 4 * (size_t)i, *q = prev + 4 * (size_t)i;
+        real l1 = (c[0] * third + c[1] * third) + c[2] * third;
+        real l2 = (q[0] * third + q[1] * third) + q[2] * third;
+        real a = rmax((l1 - l2) - rmin(l1, l2), RC(0.0)) / rmax(rmax(l1, l2), RC(1e-4));
+        a = a < RC(0.0) ? RC(0.0) : (a > RC(0.95) ? RC(0.95) : a);
+        a = a * a;
+        for (int k = 0; k < 4; ++k) out[4 * (size_t)i + k] = c[k] + a * (q[k] - c[k]);
+    }
+}
+
+void ORC(temporal_export)(const state *st, uint32_t *win, uint32_t *hist)
+{
+    memcpy(win, st->win, sizeof(uint32_t) * st->P);
+    memcpy(hist, st->hist, sizeof(uint32_t) * st->P);
+}
+
 void ORC(update)(state *st, const orc_frame *fr)
 {
     cache_update(st);
     gather(st);
+    if (st->cfg.temporal) temporal_blend(st);
     if (st->cfg.probe_filter) {
         real cam[3] = {(real)fr->pos[0], (real)fr->pos[1], (real)fr->pos[2]};
         real kappa = (real)ORC(distance_scale)(fr->fov_y, st->W, st->H);
@@ -1587,6 +1772,7 @@ void ORC(update)(state *st, const orc_frame *fr)
         free(tmp);
     }
     sh_project(st);
+    if (st->cfg.temporal) save_history(st, fr);
 }
 
 /* ---------------------------------------------------------------------------------------
