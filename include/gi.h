@@ -97,7 +97,11 @@ typedef struct gi_config {
      * 58-60).  lod_scale = Algorithm 6's distance scale keeps world cells about the size of the
      * screen cache's adaptive cell; 0 = a single level. */
     float lod_scale;
-    uint32_t reserved1[3];
+    /* 1: temporal reuse of screen probes (Section 2.1.1, Algorithm 1: a tile whose previous
+     * probe reprojects onto one of its pixels keeps it there; Section 2.1.4, Algorithm 3: its
+     * new radiance is blended with that history).  Every tile still traces every frame. */
+    uint32_t temporal;
+    uint32_t reserved1[2];
 } gi_config;
 
 typedef struct gi_frame {

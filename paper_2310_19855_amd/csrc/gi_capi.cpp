@@ -196,6 +196,12 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->d_rkey);
   dfree(c->d_atlas);
   dfree(c->d_atlas_tmp);
+  dfree(c->d_prev_mask);
+  dfree(c->d_prev_pos);
+  dfree(c->d_prev_nrm);
+  dfree(c->d_prev_atlas);
+  dfree(c->d_win);
+  dfree(c->d_hist);
   dfree(c->d_sh);
   dfree(c->tab.fp);
   dfree(c->tab.key);
@@ -236,6 +242,7 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->cache_mode > GI_CACHE_MLP_FP8) { why = "unknown cache_mode"; return GI_ERR_INVALID_ARG; }
   if (g->probe_filter > 1) { why = "probe_filter must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   if (!(g->lod_scale >= 0.0f) || !(g->lod_scale < 1e30f)) { why = "lod_scale must be finite and >= 0"; return GI_ERR_INVALID_ARG; }
+  if (g->temporal > 1) { why = "temporal must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   return GI_OK;
 }
 
@@ -304,6 +311,14 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
   A(dalloc(&c->d_rkey, PR));
   A(dalloc(&c->d_atlas, (size_t)c->P * 64));
   if (cfg->probe_filter) A(dalloc(&c->d_atlas_tmp, (size_t)c->P * 64));
+  if (cfg->temporal) {
+    A(dalloc(&c->d_prev_mask, (size_t)c->P));
+    A(dalloc(&c->d_prev_pos, (size_t)c->P));
+    A(dalloc(&c->d_prev_nrm, (size_t)c->P));
+    A(dalloc(&c->d_prev_atlas, (size_t)c->P * 64));
+    A(dalloc(&c->d_win, (size_t)c->P));
+    A(dalloc(&c->d_hist, (size_t)c->P));
+  }
   A(dalloc(&c->d_sh, (size_t)c->P * 28));
   A(dalloc(&c->tab.fp, c->N));
   A(dalloc(&c->tab.key, c->N));
@@ -605,6 +620,15 @@ gi_status gi_cache_update(gi_context* c, const gi_frame* f, void* stream) {
   if (c->stage != 2) return fail(c, GI_ERR_STATE, "gi_trace_probes of this frame first");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   GI_TRY_HIP(c, gi::launch_update(c, s));
+  if (c->cfg.temporal) {
+    // this frame's final probes become the history of the next one
+    GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_mask, c->d_mask, 4 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
+    GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_pos, c->d_ppos, 16 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
+    GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_nrm, c->d_pnrm, 16 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
+    GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_atlas, c->d_atlas, 16 * 64 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
+    c->prev_frame = *f;
+    c->has_prev = true;
+  }
   c->stage = 3;
   return GI_OK;
 }

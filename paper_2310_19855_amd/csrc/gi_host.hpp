@@ -81,6 +81,16 @@ struct gi_context {
   uint2* d_rkey = nullptr;      // [P*R] descriptor of the hit (export / learned training)
   float4* d_atlas = nullptr;    // [P*64]
   float4* d_atlas_tmp = nullptr;  // [P*64] between the two filter passes (probe_filter only)
+  // temporal reuse (config temporal): the previous frame's final probes and their camera
+  uint32_t* d_prev_mask = nullptr;   // [P] level 0
+  float4* d_prev_pos = nullptr;      // [P]
+  float4* d_prev_nrm = nullptr;      // [P]
+  float4* d_prev_atlas = nullptr;    // [P*64]
+  uint32_t* d_win = nullptr;         // [P] pixel the previous probe moved to, or sentinel
+  uint32_t* d_hist = nullptr;        // [P] previous tile of that probe, or sentinel
+  bool has_prev = false;             // a previous frame's probes are stored
+  bool reprojected = false;          // this frame's spawn reprojected them
+  gi_frame prev_frame{};
   float* d_sh = nullptr;        // [P*28]
   gi::Table tab;
   unsigned long long* d_stats = nullptr;  // [kStatStripes][GI_STAT_COUNT]

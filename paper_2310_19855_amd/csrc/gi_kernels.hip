@@ -1,4 +1,5 @@
 // gfx950 kernels of the per-frame GI pass (plain world cache) and their launchers.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "gi_device.hpp"
@@ -61,6 +62,77 @@ __global__ __launch_bounds__(kTraceBlock) void k_gbuffer(SceneView sv, ShadeTabl
 }
 
 // ------------------------------------------------------------------------------------------
+// Probe reprojection (Section 2.1.1, Algorithm 1): one wave per tile, lane = pixel
+// 8 (y % 8) + (x % 8).  A pixel that is not sky projects its world position with the previous
+// frame's camera; if the previous probe of that tile lies within the cell size (Algorithm 6)
+// of the pixel's tangent plane with a normal cosine above 0.95, the pixel bids
+// (half(distance) << 16) | lane; the smallest bid wins and the tile's probe moves there.
+// ------------------------------------------------------------------------------------------
+struct PrevCamera {
+  float pos[3], fwd[3], right[3], up[3];
+  float tan_half;
+};
+
+__global__ __launch_bounds__(64) void k_reproject(const float4* gpos, const float4* gnrm, const uint32_t* gprim,
+                                                  uint32_t W, uint32_t H, uint32_t TW, const uint32_t* prev_mask,
+                                                  const float4* prev_pos, const float4* prev_nrm, PrevCamera pc,
+                                                  float cx, float cy, float cz, float kappa, uint32_t* win,
+                                                  uint32_t* hist) {
+  __shared__ uint32_t best;
+  const uint32_t t = blockIdx.x, lane = threadIdx.x;
+  const uint32_t tx = t % TW, ty = t / TW;
+  const uint32_t init = (0x7BFFu << 16) | 0xFFFFu;   // half(65504) above an impossible lane
+  if (lane == 0) best = init;
+  __syncthreads();
+  const uint32_t x = 8u * tx + (lane & 7u), y = 8u * ty + (lane >> 3);
+  uint32_t myq = kSentinel;
+  if (x < W && y < H) {
+    const uint32_t pix = y * W + x;
+    if (gprim[pix] != kMiss) {
+      const float4 X = gpos[pix], n = gnrm[pix];
+      const float v0 = X.x - pc.pos[0], v1 = X.y - pc.pos[1], v2 = X.z - pc.pos[2];
+      const float z = (v0 * pc.fwd[0] + v1 * pc.fwd[1]) + v2 * pc.fwd[2];
+      if (z > 0.0f) {
+        const float a = ((v0 * pc.right[0] + v1 * pc.right[1]) + v2 * pc.right[2]) / z;
+        const float b = ((v0 * pc.up[0] + v1 * pc.up[1]) + v2 * pc.up[2]) / z;
+        const float aspect = (float)W / (float)H;
+        const float sx = a / (pc.tan_half * aspect), sy = b / pc.tan_half;
+        const float fx = ((sx + 1.0f) * (float)W) * 0.5f, fy = ((1.0f - sy) * (float)H) * 0.5f;
+        if (fx >= 0.0f && fx < (float)W && fy >= 0.0f && fy < (float)H) {
+          const uint32_t qx = (uint32_t)fx, qy = (uint32_t)fy;
+          const uint32_t q = (qy >> 3) * TW + (qx >> 3);
+          if (prev_mask[q] != kSentinel) {
+            const float4 wq = prev_pos[q], nq = prev_nrm[q];
+            const float dx = X.x - cx, dy = X.y - cy, dz = X.z - cz;
+            const float cs = kappa * sqrtf((dx * dx + dy * dy) + dz * dz);
+            const float pd = fabsf(((wq.x - X.x) * n.x + (wq.y - X.y) * n.y) + (wq.z - X.z) * n.z);
+            const float nc = (nq.x * n.x + nq.y * n.y) + nq.z * n.z;
+            if (pd < cs && nc > 0.95f) {
+              const float ex = wq.x - X.x, ey = wq.y - X.y, ez = wq.z - X.z;
+              const float dist = sqrtf((ex * ex + ey * ey) + ez * ez);
+              const uint32_t score = ((uint32_t)__half_as_ushort(__float2half_rn(dist)) << 16) | lane;
+              atomicMin(&best, score);
+              myq = q;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t b = best;
+  if ((b & 0xFFFFu) != 0xFFFFu) {
+    if (lane == (b & 0xFFFFu)) {
+      win[t] = (y << 16) | x;
+      hist[t] = myq;
+    }
+  } else if (lane == 0) {
+    win[t] = kSentinel;
+    hist[t] = kSentinel;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Spawn (Section 2.1.1), probe mask and its MIP chain (Section 2.1.5).  A MIP entry is the
 // first valid probe of its 2x2 children in raster order (out-of-bounds children skipped).
 // One block spawns a 16x16 patch of tiles and builds MIP levels 1..4 of that patch in LDS
@@ -74,8 +146,9 @@ struct MipInfo {
 
 __global__ __launch_bounds__(256) void k_spawn_mips(const float4* gpos, const float4* gnrm, const uint32_t* gprim,
                                                     uint32_t W, uint32_t H, uint32_t TW, uint32_t TH, uint32_t jx,
-                                                    uint32_t jy, MipInfo mi, uint32_t* mask, float4* ppos,
-                                                    float4* pnrm, unsigned long long* stats, uint32_t* hit_count) {
+                                                    uint32_t jy, MipInfo mi, const uint32_t* win, uint32_t* mask,
+                                                    float4* ppos, float4* pnrm, unsigned long long* stats,
+                                                    uint32_t* hit_count) {
   __shared__ uint32_t lv[2][256];
   const uint32_t t = threadIdx.x;
   if (blockIdx.x == 0 && blockIdx.y == 0 && t < kStatStripes) {
@@ -88,9 +161,18 @@ __global__ __launch_bounds__(256) void k_spawn_mips(const float4* gpos, const fl
   const uint32_t tx = blockIdx.x * 16u + (t & 15u), ty = blockIdx.y * 16u + (t >> 4);
   uint32_t m = kSentinel;
   if (tx < TW && ty < TH) {
-    const uint32_t px = 8u * tx + jx, py = 8u * ty + jy;
+    uint32_t px = 8u * tx + jx, py = 8u * ty + jy;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-    if (px < W && py < H) {
+    const uint32_t p = ty * TW + tx;
+    // temporal reuse: a reprojected previous probe keeps its pixel instead of the Halton one
+    const uint32_t w = win ? win[p] : kSentinel;
+    if (w != kSentinel) {
+      px = w & 0xFFFFu;
+      py = w >> 16;
+      m = w;
+      a = gpos[py * W + px];
+      b = gnrm[py * W + px];
+    } else if (px < W && py < H) {
       const uint32_t pix = py * W + px;
       if (gprim[pix] != kMiss) {
         m = (py << 16) | px;
@@ -98,7 +180,6 @@ __global__ __launch_bounds__(256) void k_spawn_mips(const float4* gpos, const fl
         b = gnrm[pix];
       }
     }
-    const uint32_t p = ty * TW + tx;
     mask[p] = m;
     ppos[p] = a;
     pnrm[p] = b;
@@ -613,7 +694,8 @@ __device__ inline void probe_sh(uint32_t p, uint32_t lane, float4 nn, const floa
 __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const float4* pnrm, const uint4* rec,
                                                   const float4* L, const float4* tnrm, const float4* mats,
                                                   const float* moments, uint32_t R, float s0, float s1, float s2,
-                                                  LearnedGatherIn lg, uint32_t do_sh, float4* atlas, float* sh) {
+                                                  LearnedGatherIn lg, uint32_t do_sh, const uint32_t* hist,
+                                                  const float4* prev_atlas, float4* atlas, float* sh) {
   __shared__ float rv[kGatherMaxR][4];
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
@@ -707,6 +789,23 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
     if (np) {
       const float fn = (float)np;
       c0 = m0 / fn; c1 = m1 / fn; c2 = m2 / fn; c3 = m3 / fn;
+    }
+  }
+  if (hist) {
+    // Algorithm 3: biased shadow-preserving hysteresis against the reprojected history
+    const uint32_t hp = hist[p];
+    if (hp != kSentinel) {
+      const float4 q = prev_atlas[(size_t)hp * 64 + lane];
+      const float third = 1.0f / 3.0f;
+      const float l1 = (c0 * third + c1 * third) + c2 * third;
+      const float l2 = (q.x * third + q.y * third) + q.z * third;
+      float a = fmaxf((l1 - l2) - fminf(l1, l2), 0.0f) / fmaxf(fmaxf(l1, l2), 1e-4f);
+      a = a < 0.0f ? 0.0f : (a > 0.95f ? 0.95f : a);
+      a = a * a;
+      c0 = c0 + a * (q.x - c0);
+      c1 = c1 + a * (q.y - c1);
+      c2 = c2 + a * (q.z - c2);
+      c3 = c3 + a * (q.w - c3);
     }
   }
   atlas[(size_t)p * 64 + lane] = make_float4(c0, c1, c2, c3);
@@ -1166,7 +1265,20 @@ static MipInfo mip_info(const gi_context* c) {
 hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, const uint32_t* prim, hipStream_t s) {
   const MipInfo mi = mip_info(c);
   const dim3 grid((c->TW + 15u) / 16u, (c->TH + 15u) / 16u);
-  GI_TIMED(c, "spawn", s, (k_spawn_mips<<<grid, 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, mi, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
+  c->reprojected = c->cfg.temporal && c->has_prev;
+  if (c->reprojected) {
+    const gi_frame& pf = c->prev_frame;
+    PrevCamera pc;
+    for (int k = 0; k < 3; ++k) {
+      pc.pos[k] = pf.pos[k];
+      pc.fwd[k] = pf.fwd[k];
+      pc.right[k] = pf.right[k];
+      pc.up[k] = pf.up[k];
+    }
+    pc.tan_half = pf.tan_half;
+    GI_TIMED(c, "reproject", s, (k_reproject<<<c->P, 64, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->d_prev_mask, c->d_prev_pos, c->d_prev_nrm, pc, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, c->d_win, c->d_hist)));
+  }
+  GI_TIMED(c, "spawn", s, (k_spawn_mips<<<grid, 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, mi, c->reprojected ? c->d_win : nullptr, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
   if (mi.n > 5) GI_TIMED(c, "mask_mip", s, (k_mask_mips_top<<<1, 1024, 0, s>>>(mi, c->d_mask)));
   return hipGetLastError();
 }
@@ -1192,7 +1304,7 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const uint32_t filt = c->cfg.probe_filter;
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->d_atlas, c->d_sh)));
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
   if (filt) {
     // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
     const MipInfo mi = mip_info(c);

@@ -195,6 +195,30 @@ def test_one_and_two_triangle_scenes(n_tris):
                       camera=cam)
 
 
+def test_temporal_reuse_static_camera():
+    """temporal reuse (Algorithm 1 reprojection, Algorithm 3 hysteresis) with a fixed camera:
+    every probe stays on its pixel from frame 1 on, and the atlas is the new estimate blended
+    with the history; masks, atlas, SH and irradiance against the oracle over four frames"""
+    pr = _run_stage_parity(I.room_scene(), dict(width=96, height=72, rays_per_probe=32, table_log2=17, bounces=2,
+                                                temporal=1), [0, 1, 2, 3], camera=lambda f: I.room_camera(0))
+    assert pr.ctx.stats()["overflow"] == 0
+    m = pr.ctx.probes()["mask"][:pr.ost.dims()[0]]
+    win, hist = pr.ost.temporal()
+    valid = m != SENT
+    assert np.array_equal(win[valid], m[valid])
+
+
+def test_temporal_reuse_orbit_and_filter():
+    """temporal reuse on the field with the orbiting camera (1 degree per frame) and the moving
+    light, the probe filter on: reprojection under motion, blending, filtering of the blended
+    atlas; three frames"""
+    sc = I.field_scene()
+    pr = _run_stage_parity(sc, dict(width=160, height=96, rays_per_probe=64, table_log2=18, sky=sc.sky, temporal=1,
+                                    probe_filter=1), [0, 1, 2])
+    win, hist = pr.ost.temporal()
+    assert (hist != SENT).sum() > 100, "the orbit should keep most probes"
+
+
 def test_room_overflowing_table_invariants():
     pr = Pair(I.room_scene(), dict(width=64, height=64, rays_per_probe=32, table_log2=6))
     fr = I.room_camera(0)
