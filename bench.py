@@ -228,6 +228,7 @@ def main():
         forms = forms_comparison(log)
         forms.update(field4k_and_furnace(log))
         forms["probe_filter"] = probe_filter_measure(log)
+        forms["temporal_reuse"] = temporal_measure(log)
 
     line = {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
@@ -469,6 +470,83 @@ def probe_filter_measure(log, scene_name="field", W=1920, H=1080, R=64, with_cpu
         out["cpu_baseline"] = probe_filter_cpu(scene, scene_name, W, H, R)
         log(f"[bench] probe filter, CPU oracle: {out['cpu_baseline']['value']:.1f} ms for both passes")
     return out
+
+
+def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, timed_from=8, with_cpu=True):
+    """Temporal reuse of screen probes (Algorithm 1 reprojection, Algorithm 3 hysteresis) on the
+    benchmark workload's moving camera: frames 0..23 of the orbit with the moving light,
+    ms/frame over frames 8..23, the reprojection kernel's launch time and its fraction of the
+    HBM peak at its algorithmic bytes (per pixel the G-buffer position, normal and primary hit,
+    36 B; per tile the winner and history, 8 B; the previous probes come from L2)."""
+    import torch
+
+    from paper_2310_19855_amd import gi
+    from paper_2310_19855_amd import inputs as I
+    scene = I.make_scene(scene_name)
+    ctx = gi.Context(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, temporal=1)
+    ctx.build_bvh(scene)
+    gb = gi.GBuffer(H, W)
+    out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+    for f in range(frames):
+        cam = I.camera_for(scene_name, f)
+        cam.index = f
+        if scene.dynamic is not None:
+            ctx.set_dynamic(*scene.dynamic(f))
+        ctx.render_gbuffer(cam, gb.pos, gb.nrm, gb.alb, gb.prim)
+        if f == timed_from:
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            ctx.profile_read()
+        ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
+        ctx.trace_probes(cam)
+        ctx.cache_update(cam)
+        ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, out)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    n = frames - timed_from
+    P = ((W + 7) // 8) * ((H + 7) // 8)
+    res = {"workload": f"{scene_name} {W}x{H}, R={R}, orbit camera and moving light, frames {timed_from}..{frames - 1}"}
+    if "reproject" in prof:
+        # the pass's kernels (each frame also renders its G-buffer, which is not part of it)
+        pass_ms = sum(v[1] for k, v in prof.items() if k != "gbuffer") / n
+        res["pass_ms_per_frame"] = round(pass_ms, 4)
+        ms = prof["reproject"][1] / max(prof["reproject"][0], 1)
+        b = W * H * 36 + P * 8
+        res["reproject"] = {"avg_ms": round(ms, 5), "alg_bytes": b, "gbs": round(b / (ms * 1e-3) / 1e9, 1),
+                            "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ctx.close()
+    log(f"[bench] temporal reuse: pass {res.get('pass_ms_per_frame')} ms/frame, reproject "
+        f"{res.get('reproject', {}).get('avg_ms')} ms ({res.get('reproject', {}).get('frac_hbm')} of HBM peak)")
+    if with_cpu:
+        res["cpu_baseline"] = temporal_cpu(scene, scene_name, W, H, R)
+        log(f"[bench] temporal reuse, CPU oracle spawn with reprojection: {res['cpu_baseline']['value']:.1f} ms")
+    return res
+
+
+def temporal_cpu(scene, scene_name, W, H, R):
+    """The oracle's spawn with reprojection (plain C, all host threads) for frame 1 of the orbit,
+    after a full oracle frame 0 that leaves the history"""
+    import oracle as O
+    from paper_2310_19855_amd import inputs as I
+    cores = O.set_threads(1)
+    O.set_threads(cores)
+    osc = O.OracleScene(scene)
+    st = O.OracleFrameState(osc, dict(O.default_config(), width=W, height=H, rays_per_probe=R, table_log2=20,
+                                      sky=scene.sky, temporal=1))
+    f0 = I.camera_for(scene_name, 0)
+    f0.index = 0
+    osc.set_frame_dynamic(0)
+    st.frame(f0, osc.gbuffer(f0, W, H))
+    f1 = I.camera_for(scene_name, 1)
+    f1.index = 1
+    osc.set_frame_dynamic(1)
+    gp, gn, ga, gprim = osc.gbuffer(f1, W, H)
+    t0 = time.time()
+    st.spawn(f1, gp, gn, gprim)
+    ms = (time.time() - t0) * 1e3
+    return {"value": round(ms, 1), "unit": "ms (spawn with reprojection, one frame)", "cores": cores, "kind": "oracle",
+            "sample": "frame 1 of the orbit after an oracle frame 0"}
 
 
 def probe_filter_cpu(scene, scene_name, W, H, R):
