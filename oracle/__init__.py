@@ -33,7 +33,7 @@ class OrcConfig(C.Structure):
                 ("frac_bits", C.c_uint32), ("probe_filter", C.c_uint32), ("lod_scale", C.c_float),
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4),
-                ("temporal", C.c_uint32), ("pad2", C.c_uint32), ("pad3", C.c_uint32), ("pad4", C.c_uint32)]
+                ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("pad3", C.c_uint32), ("pad4", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -46,7 +46,7 @@ def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
-               temporal=0)
+               temporal=0, upscale=0)
     cfg.update(kw)
     return cfg
 
@@ -83,7 +83,7 @@ def _lib(f64: bool):
     fn("xxh32", C.c_uint32, C.c_uint32)
     fn("rng", C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32)
     fn("sincos2pi", None, R, C.c_uint32, R, R)
-    fn("halton_jitter", None, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32))
+    fn("halton_jitter", None, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32))
     fn("scene_create", vp, F32P, C.c_uint32, U32P, C.c_uint32, U32P, F32P, C.c_uint32, C.c_uint32,
        C.c_int)
     fn("scene_set_dynamic", C.c_int, vp, F32P, U32P, C.c_uint32)
@@ -118,7 +118,7 @@ def _lib(f64: bool):
     fn("filter_atlas", None, vp, C.POINTER(OrcFrame), C.c_int32, C.c_int32, R, R)
     fn("half_bits", C.c_uint32, C.c_float)
     fn("temporal_blend_atlas", None, R, R, C.c_uint32, R)
-    fn("temporal_export", None, vp, U32P, U32P)
+    fn("temporal_export", None, vp, U32P, U32P, U32P)
     fn("nee_samples", None, vp, C.POINTER(OrcFrame), R, R, U32P, C.c_uint32, R)
     _LIBS[key] = (lib, p)
     return _LIBS[key]
@@ -154,9 +154,10 @@ def sincos2pi(u, f64=False):
     return c, s
 
 
-def halton_jitter(frame: int):
+def halton_jitter(frame: int, n: int = 8):
+    """floor(n * Halton(frame + 1)) in bases 2 and 3"""
     jx, jy = C.c_uint32(), C.c_uint32()
-    _call(False, "halton_jitter", frame, C.byref(jx), C.byref(jy))
+    _call(False, "halton_jitter", frame, n, C.byref(jx), C.byref(jy))
     return jx.value, jy.value
 
 
@@ -440,14 +441,16 @@ class OracleFrameState:
               np.ascontiguousarray(ny, self.dt), ids, len(ids), out)
         return out
 
-    def temporal(self):
+    def temporal(self, with_traced=False):
         """per tile: the pixel (mask encoding) the previous frame's probe moved to and the
-        previous tile it came from (SENTINEL where none), after the last spawn"""
+        previous tile it came from (SENTINEL where none), after the last spawn; with_traced
+        adds whether the tile's probe traces rays this frame"""
         P = int(self.dims()[0])
         win = np.zeros(P, np.uint32)
         hist = np.zeros(P, np.uint32)
-        _call(self.f64, "temporal_export", self.h, win, hist)
-        return win, hist
+        traced = np.zeros(P, np.uint32)
+        _call(self.f64, "temporal_export", self.h, win, hist, traced)
+        return (win, hist, traced) if with_traced else (win, hist)
 
     def filter_atlas(self, frame, axis, atlas):
         """one pass of the probe-space filter (Algorithm 5) along axis 0 (x) or 1 (y) over an

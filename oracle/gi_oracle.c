@@ -162,9 +162,9 @@ void ORC(sincos2pi)(const real *u, uint32_t n, real *c, real *s)
  * paper does not say whether the jitter is per frame or per tile; per frame keeps the probe
  * grid regular for interpolation.
  * ------------------------------------------------------------------------------------- */
-static uint32_t halton8(uint32_t index, uint32_t base)
+/* floor(n * radical inverse of index in base), exactly: the radical inverse is num / den */
+static uint32_t halton_n(uint32_t index, uint32_t base, uint32_t n)
 {
-    /* radical inverse as num/den, den = base^digits */
     uint64_t num = 0, den = 1;
     uint32_t i = index;
     while (i > 0) {
@@ -172,13 +172,14 @@ static uint32_t halton8(uint32_t index, uint32_t base)
         den *= base;
         i /= base;
     }
-    return (uint32_t)((8u * num) / den);
+    return (uint32_t)(((uint64_t)n * num) / den);
 }
 
-void ORC(halton_jitter)(uint32_t frame, uint32_t *jx, uint32_t *jy)
+
+void ORC(halton_jitter)(uint32_t frame, uint32_t n, uint32_t *jx, uint32_t *jy)
 {
-    *jx = halton8(frame + 1u, 2u);
-    *jy = halton8(frame + 1u, 3u);
+    *jx = halton_n(frame + 1u, 2u, n);
+    *jy = halton_n(frame + 1u, 3u, n);
 }
 
 /* ---------------------------------------------------------------------------------------
@@ -674,7 +675,7 @@ typedef struct orc_config {
     float lod_scale;
     float cell_scale, r_max, eps_scale, t_sky;
     float sky[4];
-    uint32_t temporal, pad2, pad3, pad4;
+    uint32_t temporal, upscale, pad3, pad4;
 } orc_config;
 
 typedef struct orc_frame {
@@ -767,6 +768,8 @@ typedef struct state {
     real *prev_pos, *prev_nrm, *prev_atlas;
     uint32_t *win;         /* [P] pixel (mask encoding) the previous probe moved to, or SENTINEL */
     uint32_t *hist;        /* [P] previous tile of that probe, or SENTINEL */
+    uint32_t *traced;      /* [P] the tile's probe traces rays this frame */
+    uint32_t sjx, sjy;     /* this frame's jitter inside the spawn tile of 8 upscale pixels */
 } state;
 
 enum { ST_RAYS, ST_HITS, ST_INSERTS, ST_OVERFLOW, ST_NONFINITE, ST_WRAPS, ST_SHADOW, ST_OCCLUDED,
@@ -1038,6 +1041,7 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->prev_atlas = (real *)calloc(P * NCELL * 4, sizeof(real));
     st->win = (uint32_t *)calloc(P, sizeof(uint32_t));
     st->hist = (uint32_t *)calloc(P, sizeof(uint32_t));
+    st->traced = (uint32_t *)calloc(P, sizeof(uint32_t));
     for (size_t i = 0; i < P; ++i) st->win[i] = st->hist[i] = SENTINEL;
     ORC(cell_moments)(&st->mom[0][0]);
     return st;
@@ -1052,7 +1056,7 @@ void ORC(destroy)(state *st)
     free(st->fp); free(st->key); free(st->acc); free(st->dacc); free(st->L);
     free(st->nhist); free(st->life); free(st->accessed); free(st->atlas); free(st->sh);
     free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
-    free(st->hist);
+    free(st->hist); free(st->traced);
     free(st);
 }
 
@@ -1075,7 +1079,7 @@ float ORC(distance_scale)(float fov_y, uint32_t W, uint32_t H)
  * previous frame's camera (static geometry; the moving light is not geometry of the G-buffer);
  * q is the pixel whose centre region holds the projection; lane = 8 (y % 8) + (x % 8); with
  * temporal reuse on, a tile with a winner places its probe at the winning pixel instead of
- * the frame's Halton pixel (upscale 1x1: every tile traces every frame).
+ * the frame's Halton pixel; with upscale 1x1 every tile that holds a probe traces every frame.
  * ------------------------------------------------------------------------------------- */
 /* float -> IEEE binary16 bits, round to nearest even (for x >= 0 or NaN) */
 static uint32_t half_bits(float x)
@@ -1168,23 +1172,82 @@ static void reproject(state *st, const orc_frame *fr, const real *gpos, const re
  * READING: a tile whose jittered pixel is off screen or sky gets the sentinel; the mask packs
  * (y << 16) | x; each MIP entry keeps the first valid probe of its 2x2 children in raster order.
  * ------------------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------------------
+ * Temporal upscaling and adaptive sampling (Section 2.1.1 spawn tiles; Section 2.1.2,
+ * Algorithm 2).  With upscale u, a spawn tile is u x u probe tiles; the frame's Halton jitter
+ * in [0, 8u)^2 picks one pixel per spawn tile, and only the probe tile that holds it (if the
+ * pixel is not sky) is spawned and traces.  A tile whose previous probe reprojected keeps it:
+ * it traces if spawned (an "override" tile), else it keeps its history without rays.  A tile
+ * neither spawned nor reprojected is empty; each empty tile picks a random override tile and
+ * takes its rays, placing a new probe at its own pixel of the jitter.
+ * READING: an empty tile can take rays only if that pixel (jitter mod 8 inside the tile) is
+ * not sky; the override tiles are listed in tile order and the pick is a counter-based
+ * random number (seed, frame, tile, dimension 7) modulo their count; where several empty
+ * tiles pick the same override tile (the paper's atomic exchange leaves this to timing), the
+ * lowest-numbered one takes it and the others stay empty.  With u = 1 every tile that holds
+ * a probe traces, as without temporal upscaling.
+ * ------------------------------------------------------------------------------------- */
+static uint32_t in_tile_pixel(const state *st, uint32_t tx, uint32_t ty, const uint32_t *gprim)
+{
+    uint32_t px = 8 * tx + st->sjx % 8u, py = 8 * ty + st->sjy % 8u;
+    if (px < st->W && py < st->H && gprim[(size_t)py * st->W + px] != MISS) return (py << 16) | px;
+    return SENTINEL;
+}
+
+static void place_probes(state *st, const orc_frame *fr, const uint32_t *gprim, uint32_t *place)
+{
+    const uint32_t u = st->cfg.upscale > 1 ? st->cfg.upscale : 1u;
+    uint32_t *over = (uint32_t *)malloc(sizeof(uint32_t) * st->P);
+    uint32_t *assigned = (uint32_t *)malloc(sizeof(uint32_t) * st->P);
+    uint32_t nover = 0;
+    for (uint32_t t = 0; t < st->P; ++t) {
+        uint32_t tx = t % st->TW, ty = t / st->TW;
+        uint32_t spx = 8u * u * (tx / u) + st->sjx, spy = 8u * u * (ty / u) + st->sjy;
+        int spawned = spx / 8u == tx && spy / 8u == ty && spx < st->W && spy < st->H &&
+                      gprim[(size_t)spy * st->W + spx] != MISS;
+        int reproj = st->cfg.temporal && st->win[t] != SENTINEL;
+        place[t] = reproj ? st->win[t] : (spawned ? ((spy << 16) | spx) : SENTINEL);
+        st->traced[t] = u == 1 ? place[t] != SENTINEL : (uint32_t)spawned;
+        assigned[t] = SENTINEL;
+        if (u > 1 && spawned && reproj) over[nover++] = t;
+    }
+    if (u > 1 && nover > 0) {
+        for (uint32_t e = 0; e < st->P; ++e) {
+            int reproj = st->cfg.temporal && st->win[e] != SENTINEL;
+            if (place[e] != SENTINEL || reproj) continue;
+            if (in_tile_pixel(st, e % st->TW, e / st->TW, gprim) == SENTINEL) continue;
+            uint32_t o = over[rng_u32(st->cfg.seed, fr->index, e, 7u) % nover];
+            if (e < assigned[o]) assigned[o] = e;
+        }
+        for (uint32_t k = 0; k < nover; ++k) {
+            uint32_t o = over[k], e = assigned[o];
+            if (e == SENTINEL) continue;
+            st->traced[o] = 0;
+            st->traced[e] = 1;
+            place[e] = in_tile_pixel(st, e % st->TW, e / st->TW, gprim);
+        }
+    }
+    free(over);
+    free(assigned);
+}
+
 void ORC(spawn)(state *st, const orc_frame *fr, const real *gpos, const real *gnrm, const uint32_t *gprim)
 {
-    ORC(halton_jitter)(fr->index, &st->jx, &st->jy);
+    const uint32_t u = st->cfg.upscale > 1 ? st->cfg.upscale : 1u;
+    st->sjx = halton_n(fr->index + 1u, 2u, 8u * u);
+    st->sjy = halton_n(fr->index + 1u, 3u, 8u * u);
+    st->jx = st->sjx % 8u;    /* lattice offset of the interpolation */
+    st->jy = st->sjy % 8u;
     for (int k = 0; k < 3; ++k) st->cam[k] = (real)fr->pos[k];
     if (st->cfg.temporal && st->has_prev) reproject(st, fr, gpos, gnrm, gprim);
+    else for (uint32_t t = 0; t < st->P; ++t) st->win[t] = st->hist[t] = SENTINEL;
+    uint32_t *place = (uint32_t *)malloc(sizeof(uint32_t) * st->P);
+    place_probes(st, fr, gprim, place);
     for (uint32_t ty = 0; ty < st->TH; ++ty)
         for (uint32_t tx = 0; tx < st->TW; ++tx) {
             uint32_t p = ty * st->TW + tx;
-            uint32_t px = 8 * tx + st->jx, py = 8 * ty + st->jy;
-            uint32_t m = SENTINEL;
-            if (st->cfg.temporal && st->win[p] != SENTINEL) {
-                m = st->win[p];
-                px = m & 0xFFFFu;
-                py = m >> 16;
-            } else if (px < st->W && py < st->H && gprim[(size_t)py * st->W + px] != MISS) {
-                m = (py << 16) | px;
-            }
+            uint32_t m = place[p];
+            uint32_t px = m & 0xFFFFu, py = m >> 16;
             st->mask[p] = m;
             for (int k = 0; k < 4; ++k) {
                 if (m == SENTINEL) {
@@ -1295,7 +1358,7 @@ void ORC(trace)(state *st, const orc_frame *fr)
     /* parallel phase: rays, hits, keys, samples; nothing here writes the table */
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : nshadow, nocc, nbounce)
     for (long p = 0; p < (long)st->P; ++p) {
-        int valid = st->mask[p] != SENTINEL;
+        int valid = st->traced[p] != 0;
         for (uint32_t r = 0; r < R; ++r) {
             size_t gid = (size_t)p * R + r;
             st->r_slot[gid] = -1;
@@ -1466,6 +1529,13 @@ static void gather(state *st)
         real *at = st->atlas + (size_t)p * NCELL * 4;
         for (int i = 0; i < NCELL * 4; ++i) at[i] = RC(0.0);
         if (st->mask[p] == SENTINEL) continue;
+        if (!st->traced[p]) {
+            /* a kept probe that traces nothing this frame (temporal upscaling) keeps the
+             * radiance of the probe it was reprojected from */
+            if (st->hist[p] != SENTINEL)
+                memcpy(at, st->prev_atlas + (size_t)st->hist[p] * NCELL * 4, sizeof(real) * NCELL * 4);
+            continue;
+        }
         real sum[NCELL][4];
         uint32_t cnt[NCELL];
         memset(cnt, 0, sizeof(cnt));
@@ -1711,7 +1781,7 @@ static void temporal_blend(state *st)
     const real third = RC(1.0) / RC(3.0);
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < (long)st->P; ++p) {
-        if (st->hist[p] == SENTINEL || st->mask[p] == SENTINEL) continue;
+        if (st->hist[p] == SENTINEL || st->mask[p] == SENTINEL || !st->traced[p]) continue;
         real *at = st->atlas + (size_t)p * NCELL * 4;
         const real *pv = st->prev_atlas + (size_t)st->hist[p] * NCELL * 4;
         for (int cell = 0; cell < NCELL; ++cell) {
@@ -1752,10 +1822,11 @@ void ORC(temporal_blend_atlas)(const real *curr, const real *prev, uint32_t n, r
     }
 }
 
-void ORC(temporal_export)(const state *st, uint32_t *win, uint32_t *hist)
+void ORC(temporal_export)(const state *st, uint32_t *win, uint32_t *hist, uint32_t *traced)
 {
     memcpy(win, st->win, sizeof(uint32_t) * st->P);
     memcpy(hist, st->hist, sizeof(uint32_t) * st->P);
+    memcpy(traced, st->traced, sizeof(uint32_t) * st->P);
 }
 
 void ORC(update)(state *st, const orc_frame *fr)
