@@ -229,6 +229,7 @@ def main():
         forms.update(field4k_and_furnace(log))
         forms["probe_filter"] = probe_filter_measure(log)
         forms["temporal_reuse"] = temporal_measure(log)
+        forms["temporal_upscale_2x2"] = temporal_measure(log, upscale=2, with_cpu=False)
 
     line = {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
@@ -472,18 +473,22 @@ def probe_filter_measure(log, scene_name="field", W=1920, H=1080, R=64, with_cpu
     return out
 
 
-def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, timed_from=8, with_cpu=True):
+def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, timed_from=8, with_cpu=True,
+                     upscale=1):
     """Temporal reuse of screen probes (Algorithm 1 reprojection, Algorithm 3 hysteresis) on the
     benchmark workload's moving camera: frames 0..23 of the orbit with the moving light,
     ms/frame over frames 8..23, the reprojection kernel's launch time and its fraction of the
     HBM peak at its algorithmic bytes (per pixel the G-buffer position, normal and primary hit,
-    36 B; per tile the winner and history, 8 B; the previous probes come from L2)."""
+    36 B; per tile the winner and history, 8 B; the previous probes come from L2).  With
+    upscale 2, temporal upscaling and adaptive sampling (Algorithm 2) on top: probe rays per
+    frame and the placement kernels' time."""
     import torch
 
     from paper_2310_19855_amd import gi
     from paper_2310_19855_amd import inputs as I
     scene = I.make_scene(scene_name)
-    ctx = gi.Context(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, temporal=1)
+    ctx = gi.Context(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, temporal=1,
+                     upscale=upscale)
     ctx.build_bvh(scene)
     gb = gi.GBuffer(H, W)
     out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
@@ -497,6 +502,7 @@ def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, t
             torch.cuda.synchronize()
             ctx.profile(True)
             ctx.profile_read()
+            rays0 = ctx.stats()["rays"]
         ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
         ctx.trace_probes(cam)
         ctx.cache_update(cam)
@@ -506,7 +512,13 @@ def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, t
     ctx.profile(False)
     n = frames - timed_from
     P = ((W + 7) // 8) * ((H + 7) // 8)
-    res = {"workload": f"{scene_name} {W}x{H}, R={R}, orbit camera and moving light, frames {timed_from}..{frames - 1}"}
+    rays = (ctx.stats()["rays"] - rays0) / n
+    res = {"workload": f"{scene_name} {W}x{H}, R={R}, orbit camera and moving light, frames {timed_from}..{frames - 1}"
+                       + (f", temporal upscaling {upscale}x{upscale}" if upscale > 1 else ""),
+           "probe_rays_per_frame": int(rays), "ray_fraction": round(rays / (P * R), 4)}
+    if upscale > 1:
+        up = [k for k in prof if k.startswith("upscale_")]
+        res["placement_ms_per_frame"] = round(sum(prof[k][1] for k in up) / n, 5)
     if "reproject" in prof:
         # the pass's kernels (each frame also renders its G-buffer, which is not part of it)
         pass_ms = sum(v[1] for k, v in prof.items() if k != "gbuffer") / n
@@ -516,7 +528,8 @@ def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, t
         res["reproject"] = {"avg_ms": round(ms, 5), "alg_bytes": b, "gbs": round(b / (ms * 1e-3) / 1e9, 1),
                             "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     ctx.close()
-    log(f"[bench] temporal reuse: pass {res.get('pass_ms_per_frame')} ms/frame, reproject "
+    log(f"[bench] temporal reuse (upscale {upscale}): pass {res.get('pass_ms_per_frame')} ms/frame, "
+        f"{res['ray_fraction']} of the rays, reproject "
         f"{res.get('reproject', {}).get('avg_ms')} ms ({res.get('reproject', {}).get('frac_hbm')} of HBM peak)")
     if with_cpu:
         res["cpu_baseline"] = temporal_cpu(scene, scene_name, W, H, R)

@@ -99,9 +99,17 @@ typedef struct gi_config {
     float lod_scale;
     /* 1: temporal reuse of screen probes (Section 2.1.1, Algorithm 1: a tile whose previous
      * probe reprojects onto one of its pixels keeps it there; Section 2.1.4, Algorithm 3: its
-     * new radiance is blended with that history).  Every tile still traces every frame. */
+     * new radiance is blended with that history). */
     uint32_t temporal;
-    uint32_t reserved1[2];
+    /* temporal upscaling (Section 2.1.1 spawn tiles, Section 2.1.2 Algorithm 2), 0 or 1 =
+     * off, 2..4 = u (needs temporal = 1): a spawn tile is u x u probe tiles and the frame's
+     * Halton jitter in [0, 8u)^2 picks one pixel in it; only the probe tile holding that pixel
+     * (if not sky) traces new rays.  Tiles whose probe reprojected keep it, traced or not
+     * (untraced ones keep their history radiance); a tile with neither takes the rays of a
+     * randomly picked tile that is both (adaptive sampling), the lowest-numbered of several
+     * such takers winning.  About 1/u^2 of the rays of upscale 1. */
+    uint32_t upscale;
+    uint32_t reserved1;
 } gi_config;
 
 typedef struct gi_frame {

@@ -43,14 +43,14 @@ void dfree(T*& p) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// floor(8 * radical_inverse_base(index)) in exact integer arithmetic (Section 2.1.1 jitter)
-uint32_t halton_cell8(uint32_t index, uint32_t base) {
+// floor(n * radical_inverse_base(index)) in exact integer arithmetic (Section 2.1.1 jitter)
+uint32_t halton_cell(uint32_t index, uint32_t base, uint32_t n) {
   uint64_t num = 0, den = 1;
   for (uint32_t i = index; i > 0; i /= base) {
     num = num * base + (i % base);
     den *= base;
   }
-  return (uint32_t)((8u * num) / den);
+  return (uint32_t)(((uint64_t)n * num) / den);
 }
 
 double tri_area(const float* v) {
@@ -202,6 +202,12 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->d_prev_atlas);
   dfree(c->d_win);
   dfree(c->d_hist);
+  dfree(c->d_place);
+  dfree(c->d_traced);
+  dfree(c->d_cls);
+  dfree(c->d_assigned);
+  dfree(c->d_over);
+  dfree(c->d_over_count);
   dfree(c->d_sh);
   dfree(c->tab.fp);
   dfree(c->tab.key);
@@ -243,6 +249,8 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->probe_filter > 1) { why = "probe_filter must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   if (!(g->lod_scale >= 0.0f) || !(g->lod_scale < 1e30f)) { why = "lod_scale must be finite and >= 0"; return GI_ERR_INVALID_ARG; }
   if (g->temporal > 1) { why = "temporal must be 0 or 1"; return GI_ERR_INVALID_ARG; }
+  if (g->upscale > 4) { why = "upscale must be 0..4"; return GI_ERR_INVALID_ARG; }
+  if (g->upscale > 1 && !g->temporal) { why = "upscale > 1 needs temporal = 1"; return GI_ERR_INVALID_ARG; }
   return GI_OK;
 }
 
@@ -318,6 +326,14 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
     A(dalloc(&c->d_prev_atlas, (size_t)c->P * 64));
     A(dalloc(&c->d_win, (size_t)c->P));
     A(dalloc(&c->d_hist, (size_t)c->P));
+  }
+  if (cfg->upscale > 1) {
+    A(dalloc(&c->d_place, (size_t)c->P));
+    A(dalloc(&c->d_traced, (size_t)c->P));
+    A(dalloc(&c->d_cls, (size_t)c->P));
+    A(dalloc(&c->d_assigned, (size_t)c->P));
+    A(dalloc(&c->d_over, (size_t)c->P));
+    A(dalloc(&c->d_over_count, 1));
   }
   A(dalloc(&c->d_sh, (size_t)c->P * 28));
   A(dalloc(&c->tab.fp, c->N));
@@ -582,8 +598,11 @@ gi_status gi_spawn_probes(gi_context* c, const gi_frame* f, const float* pos, co
   if (!aligned16(pos) || !aligned16(nrm)) return fail(c, GI_ERR_INVALID_ARG, "G-buffer not 16-byte aligned");
   if (!c->has_scene) return fail(c, GI_ERR_STATE, "gi_build_bvh first");
   c->fa.index = f->index;
-  c->fa.jx = halton_cell8(f->index + 1u, 2u);
-  c->fa.jy = halton_cell8(f->index + 1u, 3u);
+  const uint32_t u = c->cfg.upscale > 1 ? c->cfg.upscale : 1u;
+  c->fa.sjx = halton_cell(f->index + 1u, 2u, 8u * u);
+  c->fa.sjy = halton_cell(f->index + 1u, 3u, 8u * u);
+  c->fa.jx = c->fa.sjx % 8u;
+  c->fa.jy = c->fa.sjy % 8u;
   for (int k = 0; k < 3; ++k) c->fa.cam[k] = f->pos[k];
   {
     // Algorithm 6: distance scale on the host in float64, rounded once

@@ -31,7 +31,8 @@ struct FrameArgs {
   uint32_t index;
   float cam[3];
   float kappa;      // Algorithm 6 distance scale
-  uint32_t jx, jy;
+  uint32_t jx, jy;   // lattice offset of the interpolation (the jitter modulo 8)
+  uint32_t sjx, sjy; // the jitter inside a spawn tile of 8 * upscale pixels
 };
 
 struct KernelTimer {
@@ -88,6 +89,13 @@ struct gi_context {
   float4* d_prev_atlas = nullptr;    // [P*64]
   uint32_t* d_win = nullptr;         // [P] pixel the previous probe moved to, or sentinel
   uint32_t* d_hist = nullptr;        // [P] previous tile of that probe, or sentinel
+  // temporal upscaling (config upscale > 1, Algorithm 2): placement, traced flags, override list
+  uint32_t* d_place = nullptr;       // [P] final probe pixel of each tile, or sentinel
+  uint32_t* d_traced = nullptr;      // [P] 1 where the tile's probe traces rays this frame
+  uint32_t* d_cls = nullptr;         // [P] 1 override tile, 2 empty tile that may take rays
+  uint32_t* d_assigned = nullptr;    // [P] per override tile: the lowest empty tile that picked it
+  uint32_t* d_over = nullptr;        // [P] override tiles in tile order
+  uint32_t* d_over_count = nullptr;  // [1]
   bool has_prev = false;             // a previous frame's probes are stored
   bool reprojected = false;          // this frame's spawn reprojected them
   gi_frame prev_frame{};

@@ -133,6 +133,98 @@ __global__ __launch_bounds__(64) void k_reproject(const float4* gpos, const floa
 }
 
 // ------------------------------------------------------------------------------------------
+// Temporal upscaling and adaptive sampling (Section 2.1.1 spawn tiles, Section 2.1.2,
+// Algorithm 2).  A spawn tile is u x u probe tiles; the frame's jitter (sjx, sjy) in
+// [0, 8u)^2 picks one pixel per spawn tile, and the probe tile holding it is spawned if the
+// pixel is not sky.  Placement: a reprojected probe keeps its pixel, else a spawned tile
+// takes the jittered pixel.  Only spawned tiles trace; a spawned tile whose probe also
+// reprojected is an override tile, and a tile with neither ("empty") whose own pixel of the
+// jitter (modulo 8 inside the tile) is not sky picks one override tile at random (counter
+// hash, dimension 7) and, if it is the lowest-numbered tile to pick it, takes its rays and
+// places a probe at that pixel.  Four small launches: classify, ordered override list (one
+// block), pick (atomic minimum per override tile), apply.
+// ------------------------------------------------------------------------------------------
+struct UpscaleArgs {
+  uint32_t W, H, TW, P, u, sjx, sjy, seed, frame;
+};
+
+__device__ inline uint32_t own_jitter_pixel(const UpscaleArgs& ua, const uint32_t* gprim, uint32_t t) {
+  const uint32_t tx = t % ua.TW, ty = t / ua.TW;
+  const uint32_t px = 8u * tx + ua.sjx % 8u, py = 8u * ty + ua.sjy % 8u;
+  if (px < ua.W && py < ua.H && gprim[py * ua.W + px] != kMiss) return (py << 16) | px;
+  return kSentinel;
+}
+
+__global__ __launch_bounds__(256) void k_upscale_classify(const uint32_t* gprim, UpscaleArgs ua, const uint32_t* win,
+                                                          uint32_t* place, uint32_t* traced, uint32_t* cls,
+                                                          uint32_t* assigned) {
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= ua.P) return;
+  const uint32_t tx = t % ua.TW, ty = t / ua.TW;
+  const uint32_t spx = 8u * ua.u * (tx / ua.u) + ua.sjx, spy = 8u * ua.u * (ty / ua.u) + ua.sjy;
+  const bool spawned = spx / 8u == tx && spy / 8u == ty && spx < ua.W && spy < ua.H && gprim[spy * ua.W + spx] != kMiss;
+  const uint32_t w = win ? win[t] : kSentinel;
+  const bool reproj = w != kSentinel;
+  place[t] = reproj ? w : (spawned ? ((spy << 16) | spx) : kSentinel);
+  traced[t] = spawned ? 1u : 0u;
+  uint32_t k = 0u;
+  if (spawned && reproj) k = 1u;
+  else if (!spawned && !reproj && own_jitter_pixel(ua, gprim, t) != kSentinel) k = 2u;
+  cls[t] = k;
+  assigned[t] = kSentinel;
+}
+
+// one block of 1024: override tiles (class 1) compacted in tile order, 1024 tiles per pass
+__global__ __launch_bounds__(1024) void k_upscale_list(const uint32_t* cls, uint32_t P, uint32_t* over,
+                                                       uint32_t* count) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t base;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  if (tid == 0) base = 0u;
+  __syncthreads();
+  for (uint32_t start = 0; start < P; start += 1024u) {
+    const uint32_t t = start + tid;
+    const bool on = t < P && cls[t] == 1u;
+    const uint64_t b = __ballot(on);
+    if (lane == 0) wsum[w] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t off = base;
+    for (uint32_t i = 0; i < w; ++i) off += wsum[i];
+    if (on) over[off + (uint32_t)__popcll(b & ((1ull << lane) - 1ull))] = t;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t s = base;
+      for (uint32_t i = 0; i < 16u; ++i) s += wsum[i];
+      base = s;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) count[0] = base;
+}
+
+__global__ __launch_bounds__(256) void k_upscale_pick(const uint32_t* cls, UpscaleArgs ua, const uint32_t* over,
+                                                      const uint32_t* count, uint32_t* assigned) {
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= ua.P || cls[t] != 2u) return;
+  const uint32_t n = count[0];
+  if (n == 0u) return;
+  const uint32_t o = over[rand_u32(ua.seed, ua.frame, t, 7u) % n];
+  atomicMin(&assigned[o], t);
+}
+
+__global__ __launch_bounds__(256) void k_upscale_apply(const uint32_t* gprim, UpscaleArgs ua, const uint32_t* over,
+                                                       const uint32_t* count, const uint32_t* assigned,
+                                                       uint32_t* place, uint32_t* traced) {
+  const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+  if (k >= count[0]) return;
+  const uint32_t o = over[k], e = assigned[o];
+  if (e == kSentinel) return;
+  traced[o] = 0u;
+  traced[e] = 1u;
+  place[e] = own_jitter_pixel(ua, gprim, e);
+}
+
+// ------------------------------------------------------------------------------------------
 // Spawn (Section 2.1.1), probe mask and its MIP chain (Section 2.1.5).  A MIP entry is the
 // first valid probe of its 2x2 children in raster order (out-of-bounds children skipped).
 // One block spawns a 16x16 patch of tiles and builds MIP levels 1..4 of that patch in LDS
@@ -146,7 +238,8 @@ struct MipInfo {
 
 __global__ __launch_bounds__(256) void k_spawn_mips(const float4* gpos, const float4* gnrm, const uint32_t* gprim,
                                                     uint32_t W, uint32_t H, uint32_t TW, uint32_t TH, uint32_t jx,
-                                                    uint32_t jy, MipInfo mi, const uint32_t* win, uint32_t* mask,
+                                                    uint32_t jy, MipInfo mi, const uint32_t* win,
+                                                    const uint32_t* place, uint32_t* mask,
                                                     float4* ppos, float4* pnrm, unsigned long long* stats,
                                                     uint32_t* hit_count) {
   __shared__ uint32_t lv[2][256];
@@ -165,8 +258,11 @@ __global__ __launch_bounds__(256) void k_spawn_mips(const float4* gpos, const fl
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
     const uint32_t p = ty * TW + tx;
     // temporal reuse: a reprojected previous probe keeps its pixel instead of the Halton one
-    const uint32_t w = win ? win[p] : kSentinel;
-    if (w != kSentinel) {
+    // temporal upscaling: the placement is final (kept, spawned or adaptive-sampling probes)
+    const uint32_t w = place ? place[p] : (win ? win[p] : kSentinel);
+    if (place && w == kSentinel) {
+      // no probe in this tile
+    } else if (w != kSentinel) {
       px = w & 0xFFFFu;
       py = w >> 16;
       m = w;
@@ -232,6 +328,7 @@ __global__ __launch_bounds__(1024) void k_mask_mips_top(MipInfo mi, uint32_t* ma
 // ------------------------------------------------------------------------------------------
 struct ProbeRayArgs {
   const uint32_t* mask;
+  const uint32_t* traced;   // temporal upscaling: probes that trace this frame (else every probe)
   const float4* ppos;
   const float4* pnrm;
   uint32_t P, R, seed, frame;
@@ -271,7 +368,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_probes(SceneView sv, Shad
   const uint32_t gid = blockIdx.x * kTraceBlock + threadIdx.x;
   if (gid >= a.P * a.R) return;
   const uint32_t p = gid / a.R;
-  const bool valid = a.mask[p] != kSentinel;
+  const bool valid = a.traced ? a.traced[p] != 0u : a.mask[p] != kSentinel;
   stat_add(stats, GI_STAT_RAYS, valid);
   if (!valid) {
     rec[gid] = make_uint4(0xFFFFFFFFu, 0u, kMiss, 0u);
@@ -695,7 +792,8 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
                                                   const float4* L, const float4* tnrm, const float4* mats,
                                                   const float* moments, uint32_t R, float s0, float s1, float s2,
                                                   LearnedGatherIn lg, uint32_t do_sh, const uint32_t* hist,
-                                                  const float4* prev_atlas, float4* atlas, float* sh) {
+                                                  const uint32_t* traced, const float4* prev_atlas, float4* atlas,
+                                                  float* sh) {
   __shared__ float rv[kGatherMaxR][4];
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
@@ -706,6 +804,15 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
   if (mask[p] == kSentinel) {
     atlas[(size_t)p * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (do_sh && lane < 28) sh[(size_t)p * 28 + lane] = 0.0f;
+    return;
+  }
+  if (traced && traced[p] == 0u) {
+    // a kept probe that traces nothing this frame (temporal upscaling) keeps the radiance of
+    // the probe it was reprojected from
+    const uint32_t hp = hist ? hist[p] : kSentinel;
+    const float4 q = hp != kSentinel ? prev_atlas[(size_t)hp * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    atlas[(size_t)p * 64 + lane] = q;
+    if (do_sh) probe_sh(p, lane, pnrm[p], moments, q.x, q.y, q.z, sh);
     return;
   }
   for (uint32_t j = lane; j < R; j += 64) {
@@ -1088,7 +1195,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
   bool probe = false, shadow = false;
   if (gid < a.P * a.R) {
     const uint32_t p = gid / a.R;
-    if (a.mask[p] != kSentinel) {
+    if (a.traced ? a.traced[p] != 0u : a.mask[p] != kSentinel) {
       probe = true;
       float ox, oy, oz, dx, dy, dz;
       uint32_t cell;
@@ -1166,6 +1273,7 @@ static ShadeTables shade_tables(const gi_context* c) {
 static ProbeRayArgs probe_args(const gi_context* c) {
   ProbeRayArgs a;
   a.mask = c->d_mask;
+  a.traced = c->cfg.upscale > 1 ? c->d_traced : nullptr;
   a.ppos = c->d_ppos;
   a.pnrm = c->d_pnrm;
   a.P = c->P;
@@ -1278,7 +1386,27 @@ hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, con
     pc.tan_half = pf.tan_half;
     GI_TIMED(c, "reproject", s, (k_reproject<<<c->P, 64, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->d_prev_mask, c->d_prev_pos, c->d_prev_nrm, pc, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, c->d_win, c->d_hist)));
   }
-  GI_TIMED(c, "spawn", s, (k_spawn_mips<<<grid, 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, mi, c->reprojected ? c->d_win : nullptr, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
+  const uint32_t* place = nullptr;
+  if (c->cfg.upscale > 1) {
+    UpscaleArgs ua;
+    ua.W = c->W;
+    ua.H = c->H;
+    ua.TW = c->TW;
+    ua.P = c->P;
+    ua.u = c->cfg.upscale;
+    ua.sjx = c->fa.sjx;
+    ua.sjy = c->fa.sjy;
+    ua.seed = c->cfg.seed;
+    ua.frame = c->fa.index;
+    const uint32_t nb = (c->P + 255u) / 256u;
+    const uint32_t* win = c->reprojected ? c->d_win : nullptr;
+    GI_TIMED(c, "upscale_classify", s, (k_upscale_classify<<<nb, 256, 0, s>>>(prim, ua, win, c->d_place, c->d_traced, c->d_cls, c->d_assigned)));
+    GI_TIMED(c, "upscale_list", s, (k_upscale_list<<<1, 1024, 0, s>>>(c->d_cls, c->P, c->d_over, c->d_over_count)));
+    GI_TIMED(c, "upscale_pick", s, (k_upscale_pick<<<nb, 256, 0, s>>>(c->d_cls, ua, c->d_over, c->d_over_count, c->d_assigned)));
+    GI_TIMED(c, "upscale_apply", s, (k_upscale_apply<<<nb, 256, 0, s>>>(prim, ua, c->d_over, c->d_over_count, c->d_assigned, c->d_place, c->d_traced)));
+    place = c->d_place;
+  }
+  GI_TIMED(c, "spawn", s, (k_spawn_mips<<<grid, 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, mi, c->reprojected ? c->d_win : nullptr, place, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
   if (mi.n > 5) GI_TIMED(c, "mask_mip", s, (k_mask_mips_top<<<1, 1024, 0, s>>>(mi, c->d_mask)));
   return hipGetLastError();
 }
@@ -1304,7 +1432,7 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const uint32_t filt = c->cfg.probe_filter;
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
   if (filt) {
     // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
     const MipInfo mi = mip_info(c);

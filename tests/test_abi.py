@@ -31,14 +31,16 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2310_19855_amd import gi
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gi.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gi_config), sizeof(gi_frame),'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gi_config), sizeof(gi_frame),'
                     ' offsetof(gi_config, cell_scale), offsetof(gi_config, mlp_batch_log2),'
-                    ' offsetof(gi_config, scene_max), offsetof(gi_frame, up)); return 0;}\n')
+                    ' offsetof(gi_config, scene_max), offsetof(gi_frame, up), offsetof(gi_config, upscale));'
+                    ' return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [C.sizeof(gi.Config), C.sizeof(gi.Frame), gi.Config.cell_scale.offset,
-            gi.Config.mlp_batch_log2.offset, gi.Config.scene_max.offset, gi.Frame.up.offset]
+            gi.Config.mlp_batch_log2.offset, gi.Config.scene_max.offset, gi.Frame.up.offset,
+            gi.Config.upscale.offset]
     assert got == want
 
 

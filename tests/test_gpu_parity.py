@@ -219,6 +219,30 @@ def test_temporal_reuse_orbit_and_filter():
     assert (hist != SENT).sum() > 100, "the orbit should keep most probes"
 
 
+def test_temporal_upscale_fixed_camera_ragged():
+    """temporal upscaling 2x2 with adaptive sampling (Algorithm 2) on a ragged 100x76 room
+    (spawn tiles cut by both screen edges), fixed camera, six frames: one traced probe per
+    spawn tile, kept probes copying their history, empty tiles taking override tiles' rays;
+    the traced flags of every ray, masks, atlas, SH and irradiance against the oracle"""
+    pr = _run_stage_parity(I.room_scene(), dict(width=100, height=76, rays_per_probe=32, table_log2=17, bounces=2,
+                                                temporal=1, upscale=2), list(range(6)),
+                           camera=lambda f: I.room_camera(0))
+    assert pr.ctx.stats()["overflow"] == 0
+    win, hist, traced = pr.ost.temporal(with_traced=True)
+    m = pr.ctx.probes()["mask"][:pr.ost.dims()[0]]
+    assert (m != SENT).sum() > 0.9 * len(m) and traced.sum() < len(m) // 3
+
+
+def test_temporal_upscale_orbit_and_filter():
+    """temporal upscaling 2x2 on the field with the orbiting camera, the moving light and the
+    filter on: sky tiles, probes lost to motion, adaptive sampling into them; four frames"""
+    sc = I.field_scene()
+    pr = _run_stage_parity(sc, dict(width=160, height=96, rays_per_probe=64, table_log2=18, sky=sc.sky, temporal=1,
+                                    upscale=2, probe_filter=1), [0, 1, 2, 3])
+    win, hist, traced = pr.ost.temporal(with_traced=True)
+    assert 0 < traced.sum() < len(traced) // 2
+
+
 def test_room_overflowing_table_invariants():
     pr = Pair(I.room_scene(), dict(width=64, height=64, rays_per_probe=32, table_log2=6))
     fr = I.room_camera(0)
@@ -455,3 +479,7 @@ def test_invalid_arguments_and_frame_order():
         gi.Context(width=4, height=64)
     with pytest.raises(gi.GIError):
         gi.Context(rays_per_probe=1000)
+    with pytest.raises(gi.GIError, match="INVALID"):
+        gi.Context(width=64, height=64, upscale=2)          # upscaling needs temporal reuse
+    with pytest.raises(gi.GIError):
+        gi.Context(width=64, height=64, temporal=1, upscale=5)
