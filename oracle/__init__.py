@@ -33,7 +33,7 @@ class OrcConfig(C.Structure):
                 ("frac_bits", C.c_uint32), ("probe_filter", C.c_uint32), ("lod_scale", C.c_float),
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4),
-                ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("pad3", C.c_uint32), ("pad4", C.c_uint32)]
+                ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32), ("pad4", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -46,7 +46,7 @@ def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
-               temporal=0, upscale=0)
+               temporal=0, upscale=0, ray_guiding=0)
     cfg.update(kw)
     return cfg
 
@@ -119,6 +119,9 @@ def _lib(f64: bool):
     fn("half_bits", C.c_uint32, C.c_float)
     fn("temporal_blend_atlas", None, R, R, C.c_uint32, R)
     fn("temporal_export", None, vp, U32P, U32P, U32P)
+    fn("guiding_export", None, vp, R, U32P)
+    fn("guided_dirs", None, R, U32P, U32P, R, R, C.c_uint32, R, U32P)
+    fn("reconstruct_probe", None, R, R, C.c_double if f64 else C.c_float, C.c_uint32, R, R, R, R, U32P)
     fn("nee_samples", None, vp, C.POINTER(OrcFrame), R, R, U32P, C.c_uint32, R)
     _LIBS[key] = (lib, p)
     return _LIBS[key]
@@ -180,6 +183,40 @@ def cosine_dirs(n, u0, u1, f64=False):
     cell = np.zeros(len(u0), np.uint32)
     _call(f64, "cosine_dirs", n, u0, u1, len(u0), d, cell)
     return d, cell
+
+
+def guided_dirs(n, cdf, r, u0, u1, f64=False):
+    """ray guiding's sampling for one probe with unit normal n and inclusive weight sums cdf
+    [64]: per ray, the cell picked by the 32-bit number r and the direction of the point
+    (u0, u1) inside it"""
+    dt = np.float64 if f64 else np.float32
+    n = np.ascontiguousarray(n, dt)
+    cdf = np.ascontiguousarray(cdf, np.uint32)
+    r = np.ascontiguousarray(r, np.uint32)
+    u0 = np.ascontiguousarray(u0, dt)
+    u1 = np.ascontiguousarray(u1, dt)
+    d = np.zeros((len(r), 3), dt)
+    cell = np.zeros(len(r), np.uint32)
+    _call(f64, "guided_dirs", n, cdf, r, u0, u1, len(r), d, cell)
+    return d, cell
+
+
+def reconstruct_probe(pp, pn, cs, qpos, qnrm, qatlas, f64=True):
+    """ray guiding's parallax-corrected reconstruction of one probe (position pp, unit normal
+    pn, cell size cs) from up to 9 previous probes (positions, normals, atlases [n, 64, 4]);
+    returns the reconstruction [64, 4] (distance -1 where empty) and the weight sums [64]"""
+    dt = np.float64 if f64 else np.float32
+    qpos = np.zeros((0, 4), dt) if len(qpos) == 0 else np.ascontiguousarray(np.asarray(qpos, dt).reshape(-1, 4))
+    qnrm = np.zeros((0, 4), dt) if len(qnrm) == 0 else np.ascontiguousarray(np.asarray(qnrm, dt).reshape(-1, 4))
+    qatlas = np.zeros((0, NCELL, 4), dt) if len(qatlas) == 0 else np.ascontiguousarray(qatlas, dt)
+    recon = np.zeros((NCELL, 4), dt)
+    cdf = np.zeros(NCELL, np.uint32)
+    p3 = np.zeros(4, dt)
+    p3[:3] = pp[:3]
+    n3 = np.zeros(4, dt)
+    n3[:3] = pn[:3]
+    _call(f64, "reconstruct_probe", p3, n3, cs, len(qpos), qpos, qnrm, qatlas, recon, cdf)
+    return recon, cdf
 
 
 def half_bits(x: float) -> int:
@@ -451,6 +488,14 @@ class OracleFrameState:
         traced = np.zeros(P, np.uint32)
         _call(self.f64, "temporal_export", self.h, win, hist, traced)
         return (win, hist, traced) if with_traced else (win, hist)
+
+    def guiding(self):
+        """after a spawn with ray guiding: the reconstruction [P, 64, 4] (rgb, distance; the
+        distance is -1 in empty cells) and the inclusive weight sums [P, 64]"""
+        recon = np.zeros((self.P, NCELL, 4), self.dt)
+        cdf = np.zeros((self.P, NCELL), np.uint32)
+        _call(self.f64, "guiding_export", self.h, recon, cdf)
+        return recon, cdf
 
     def filter_atlas(self, frame, axis, atlas):
         """one pass of the probe-space filter (Algorithm 5) along axis 0 (x) or 1 (y) over an

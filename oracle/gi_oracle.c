@@ -675,7 +675,7 @@ typedef struct orc_config {
     float lod_scale;
     float cell_scale, r_max, eps_scale, t_sky;
     float sky[4];
-    uint32_t temporal, upscale, pad3, pad4;
+    uint32_t temporal, upscale, ray_guiding, pad4;
 } orc_config;
 
 typedef struct orc_frame {
@@ -770,6 +770,9 @@ typedef struct state {
     uint32_t *hist;        /* [P] previous tile of that probe, or SENTINEL */
     uint32_t *traced;      /* [P] the tile's probe traces rays this frame */
     uint32_t sjx, sjy;     /* this frame's jitter inside the spawn tile of 8 upscale pixels */
+    real *recon;           /* [P][64][4] reconstructed history radiance, distance; w < 0: empty */
+    uint32_t *cdf;         /* [P][64] inclusive sums of the guiding weights; last 0: unguided */
+    int guided;            /* this frame's probes have a reconstruction (ray guiding) */
 } state;
 
 enum { ST_RAYS, ST_HITS, ST_INSERTS, ST_OVERFLOW, ST_NONFINITE, ST_WRAPS, ST_SHADOW, ST_OCCLUDED,
@@ -1042,6 +1045,8 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->win = (uint32_t *)calloc(P, sizeof(uint32_t));
     st->hist = (uint32_t *)calloc(P, sizeof(uint32_t));
     st->traced = (uint32_t *)calloc(P, sizeof(uint32_t));
+    st->recon = (real *)calloc(P * NCELL * 4, sizeof(real));
+    st->cdf = (uint32_t *)calloc(P * NCELL, sizeof(uint32_t));
     for (size_t i = 0; i < P; ++i) st->win[i] = st->hist[i] = SENTINEL;
     ORC(cell_moments)(&st->mom[0][0]);
     return st;
@@ -1056,7 +1061,7 @@ void ORC(destroy)(state *st)
     free(st->fp); free(st->key); free(st->acc); free(st->dacc); free(st->L);
     free(st->nhist); free(st->life); free(st->accessed); free(st->atlas); free(st->sh);
     free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
-    free(st->hist); free(st->traced);
+    free(st->hist); free(st->traced); free(st->recon); free(st->cdf);
     free(st);
 }
 
@@ -1231,6 +1236,175 @@ static void place_probes(state *st, const orc_frame *fr, const uint32_t *gprim, 
     free(assigned);
 }
 
+/* ---------------------------------------------------------------------------------------
+ * Ray guiding (Section 2.1.2): parallax-corrected reconstruction of each new probe's
+ * hemisphere from the previous frame's probes, and the sampling distribution built from it.
+ * For a new probe p: the previous probes in the 3x3 tiles around the previous-frame tile that
+ * holds p's projection are taken if they pass the cell-size tests of the reprojection (plane
+ * distance below p's cell size, normal cosine above 0.95).  Each of their 64 cells gives the
+ * point its radiance came from (probe position + travelled distance along the cell's centre
+ * direction); seen from p that point falls in one of p's cells, which receives the radiance
+ * and the new distance.  Cells receiving nothing are empty.
+ * The weights are the reconstruction's luminance (channel mean), quantised as
+ * floor(2^20 lum / max lum); a ray picks a cell with probability proportional to its weight
+ * (integer inverse CDF of a 32-bit counter hash, dimension 8) and a uniform point inside
+ * that cell of the 8x8 hemi-octahedral square (dimensions 0 and 1).
+ * READING: previous-frame neighbourhood around p's own projection (not its history tile); the
+ * same plane and normal tests as Algorithm 1; cells accumulated in (tile, cell) order; a
+ * probe with no reconstruction or zero total weight samples the cosine distribution as
+ * without guiding; a ray keeps the picked cell as its atlas cell.
+ * ------------------------------------------------------------------------------------- */
+static void cell_direction(int cell, const real *n, real *d);
+
+static uint32_t local_cell(real lx, real ly, real lz)
+{
+    real sum = (RABS(lx) + RABS(ly)) + lz;
+    real a = lx / sum, bb = ly / sum;
+    real uu = a + bb, vv = a - bb;
+    int ix = (int)RFLOOR(RC(4.0) * (uu + RC(1.0)));
+    int iy = (int)RFLOOR(RC(4.0) * (vv + RC(1.0)));
+    ix = ix < 0 ? 0 : (ix > 7 ? 7 : ix);
+    iy = iy < 0 ? 0 : (iy > 7 ? 7 : iy);
+    return (uint32_t)(8 * iy + ix);
+}
+
+/* the reconstruction of one probe (position pp, unit normal pn, cell size cs) from nq
+ * candidate previous probes; recon [64][4] (w = -1 where empty) and cdf [64] */
+static void recon_probe(const real *pp, const real *pn, real cs, uint32_t nq, const real *const *qpos,
+                        const real *const *qnrm, const real *const *qatlas, real *rc, uint32_t *cdf)
+{
+    const real third = RC(1.0) / RC(3.0);
+    real sum[NCELL][4];
+    uint32_t cnt[NCELL];
+    memset(cnt, 0, sizeof(cnt));
+    for (int i = 0; i < NCELL; ++i) sum[i][0] = sum[i][1] = sum[i][2] = sum[i][3] = RC(0.0);
+    real t[3], b[3];
+    onb(pn, t, b);
+    for (uint32_t j = 0; j < nq; ++j) {
+        const real *wq = qpos[j], *nq3 = qnrm[j], *qa = qatlas[j];
+        real pd = RABS(((wq[0] - pp[0]) * pn[0] + (wq[1] - pp[1]) * pn[1]) + (wq[2] - pp[2]) * pn[2]);
+        real nc = (nq3[0] * pn[0] + nq3[1] * pn[1]) + nq3[2] * pn[2];
+        if (!(pd < cs && nc > RC(0.95))) continue;
+        for (int c = 0; c < NCELL; ++c) {
+            real d[3];
+            cell_direction(c, nq3, d);
+            real al = qa[4 * c + 3];
+            real v[3];
+            for (int k = 0; k < 3; ++k) v[k] = (wq[k] + al * d[k]) - pp[k];
+            real lz = (v[0] * pn[0] + v[1] * pn[1]) + v[2] * pn[2];
+            if (!(lz > RC(0.0))) continue;
+            real lx = (v[0] * t[0] + v[1] * t[1]) + v[2] * t[2];
+            real ly = (v[0] * b[0] + v[1] * b[1]) + v[2] * b[2];
+            uint32_t k = local_cell(lx, ly, lz);
+            real dist = RSQRT((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+            for (int i = 0; i < 3; ++i) sum[k][i] = sum[k][i] + qa[4 * c + i];
+            sum[k][3] = sum[k][3] + dist;
+            cnt[k]++;
+        }
+    }
+    real maxl = RC(0.0);
+    real lum[NCELL];
+    for (int i = 0; i < NCELL; ++i) {
+        if (!cnt[i]) {
+            rc[4 * i] = rc[4 * i + 1] = rc[4 * i + 2] = RC(0.0);
+            rc[4 * i + 3] = RC(-1.0);
+            lum[i] = RC(0.0);
+            continue;
+        }
+        real fc = (real)cnt[i];
+        for (int k = 0; k < 4; ++k) rc[4 * i + k] = sum[i][k] / fc;
+        lum[i] = (rc[4 * i] * third + rc[4 * i + 1] * third) + rc[4 * i + 2] * third;
+        maxl = rmax(maxl, lum[i]);
+    }
+    uint32_t acc = 0;
+    for (int i = 0; i < NCELL; ++i) {
+        uint32_t w = 0;
+        if (cnt[i] && maxl > RC(0.0)) w = (uint32_t)((lum[i] / maxl) * RC(1048576.0));
+        acc += w;
+        cdf[i] = acc;
+    }
+}
+
+void ORC(reconstruct_probe)(const real *pp, const real *pn, real cs, uint32_t nq, const real *qpos,
+                            const real *qnrm, const real *qatlas, real *recon, uint32_t *cdf)
+{
+    /* test entry: candidates given as arrays [nq][4], [nq][4], [nq][64][4] */
+    const real *a[9], *b[9], *c[9];
+    uint32_t n = nq > 9 ? 9 : nq;
+    for (uint32_t j = 0; j < n; ++j) {
+        a[j] = qpos + 4 * (size_t)j;
+        b[j] = qnrm + 4 * (size_t)j;
+        c[j] = qatlas + (size_t)j * NCELL * 4;
+    }
+    recon_probe(pp, pn, cs, n, a, b, c, recon, cdf);
+}
+
+static void reconstruct(state *st, const orc_frame *fr)
+{
+    real kappa = (real)ORC(distance_scale)(fr->fov_y, st->W, st->H);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long p = 0; p < (long)st->P; ++p) {
+        real *rc = st->recon + (size_t)p * NCELL * 4;
+        uint32_t *cdf = st->cdf + (size_t)p * NCELL;
+        const real *qp[9], *qn[9], *qa[9];
+        uint32_t nq = 0;
+        const real *pp = st->ppos + 4 * p, *pn = st->pnrm + 4 * p;
+        real cs = RC(0.0);
+        int32_t qx = 0, qy = 0;
+        if (st->mask[p] != SENTINEL && project_prev(st, pp, &qx, &qy)) {
+            real ex = pp[0] - st->cam[0], ey = pp[1] - st->cam[1], ez = pp[2] - st->cam[2];
+            cs = kappa * RSQRT((ex * ex + ey * ey) + ez * ez);
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int32_t tx = (qx >> 3) + dx, ty = (qy >> 3) + dy;
+                    if (tx < 0 || ty < 0 || tx >= (int32_t)st->TW || ty >= (int32_t)st->TH) continue;
+                    uint32_t q = (uint32_t)ty * st->TW + (uint32_t)tx;
+                    if (st->prev_mask[q] == SENTINEL) continue;
+                    qp[nq] = st->prev_pos + 4 * (size_t)q;
+                    qn[nq] = st->prev_nrm + 4 * (size_t)q;
+                    qa[nq] = st->prev_atlas + (size_t)q * NCELL * 4;
+                    ++nq;
+                }
+        }
+        recon_probe(pp, pn, cs, nq, qp, qn, qa, rc, cdf);
+    }
+}
+
+/* a ray's direction inside atlas cell k: uniform point (u0, u1) of the cell's square in the
+ * hemi-octahedral domain, mapped back to the hemisphere about n */
+static void guided_dir(const real *n, uint32_t k, real u0, real u1, real *d)
+{
+    real uu = ((real)(k & 7u) + u0) * RC(0.25) - RC(1.0);
+    real vv = ((real)(k >> 3) + u1) * RC(0.25) - RC(1.0);
+    real a = (uu + vv) * RC(0.5), b = (uu - vv) * RC(0.5);
+    real z = (RC(1.0) - RABS(a)) - RABS(b);
+    real len = RSQRT((a * a + b * b) + z * z);
+    real lx = a / len, ly = b / len, lz = z / len;
+    real t[3], bb[3];
+    onb(n, t, bb);
+    for (int j = 0; j < 3; ++j) d[j] = (lx * t[j] + ly * bb[j]) + lz * n[j];
+}
+
+/* cell picked by a 32-bit random number r: the first whose inclusive weight sum exceeds
+ * floor(r * total / 2^32) */
+static uint32_t pick_cell(const uint32_t *cdf, uint32_t r)
+{
+    uint32_t target = (uint32_t)(((uint64_t)r * cdf[NCELL - 1]) >> 32);
+    uint32_t k = 0;
+    while (cdf[k] <= target) ++k;
+    return k;
+}
+
+void ORC(guided_dirs)(const real *n, const uint32_t *cdf, const uint32_t *r, const real *u0, const real *u1,
+                      uint32_t cnt, real *d, uint32_t *cell)
+{
+    /* test entry: ray directions of a probe with normal n and weight sums cdf */
+    for (uint32_t i = 0; i < cnt; ++i) {
+        cell[i] = pick_cell(cdf, r[i]);
+        guided_dir(n, cell[i], u0[i], u1[i], d + 3 * i);
+    }
+}
+
 void ORC(spawn)(state *st, const orc_frame *fr, const real *gpos, const real *gnrm, const uint32_t *gprim)
 {
     const uint32_t u = st->cfg.upscale > 1 ? st->cfg.upscale : 1u;
@@ -1259,6 +1433,9 @@ void ORC(spawn)(state *st, const orc_frame *fr, const real *gpos, const real *gn
                 }
             }
         }
+    free(place);
+    st->guided = st->cfg.ray_guiding && st->cfg.temporal && st->has_prev;
+    if (st->guided) reconstruct(st, fr);
     for (uint32_t k = 1; k < st->nmip; ++k) {
         const uint32_t *src = st->mask + st->mip_off[k - 1];
         uint32_t *dst = st->mask + st->mip_off[k];
@@ -1373,7 +1550,13 @@ void ORC(trace)(state *st, const orc_frame *fr)
             real u1 = rng_unit(rng_u32(c->seed, fr->index, (uint32_t)gid, 1u));
             real d[3], o[3];
             uint32_t cell;
-            cosine_dir(pn, u0, u1, d, &cell);
+            const uint32_t *cdf = st->cdf + (size_t)p * NCELL;
+            if (st->guided && cdf[NCELL - 1] > 0) {
+                cell = pick_cell(cdf, rng_u32(c->seed, fr->index, (uint32_t)gid, 8u));
+                guided_dir(pn, cell, u0, u1, d);
+            } else {
+                cosine_dir(pn, u0, u1, d, &cell);
+            }
             real eps = offset_eps(c, pp);
             for (int k = 0; k < 3; ++k) o[k] = pp[k] + pn[k] * eps;
             uint32_t tri;
@@ -1531,9 +1714,25 @@ static void gather(state *st)
         if (st->mask[p] == SENTINEL) continue;
         if (!st->traced[p]) {
             /* a kept probe that traces nothing this frame (temporal upscaling) keeps the
-             * radiance of the probe it was reprojected from */
-            if (st->hist[p] != SENTINEL)
+             * radiance of the probe it was reprojected from; with ray guiding, the
+             * parallax-corrected reconstruction, its empty cells filled with the mean of the
+             * others */
+            if (st->guided) {
+                const real *rc = st->recon + (size_t)p * NCELL * 4;
+                real mean[4] = {RC(0.0), RC(0.0), RC(0.0), RC(0.0)};
+                uint32_t npop = 0;
+                for (int i = 0; i < NCELL; ++i) {
+                    if (rc[4 * i + 3] < RC(0.0)) continue;
+                    for (int k = 0; k < 4; ++k) mean[k] = mean[k] + rc[4 * i + k];
+                    ++npop;
+                }
+                if (npop == 0) continue;
+                for (int k = 0; k < 4; ++k) mean[k] = mean[k] / (real)npop;
+                for (int i = 0; i < NCELL; ++i)
+                    for (int k = 0; k < 4; ++k) at[4 * i + k] = rc[4 * i + 3] < RC(0.0) ? mean[k] : rc[4 * i + k];
+            } else if (st->hist[p] != SENTINEL) {
                 memcpy(at, st->prev_atlas + (size_t)st->hist[p] * NCELL * 4, sizeof(real) * NCELL * 4);
+            }
             continue;
         }
         real sum[NCELL][4];
@@ -1781,12 +1980,17 @@ static void temporal_blend(state *st)
     const real third = RC(1.0) / RC(3.0);
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < (long)st->P; ++p) {
-        if (st->hist[p] == SENTINEL || st->mask[p] == SENTINEL || !st->traced[p]) continue;
+        if (st->mask[p] == SENTINEL || !st->traced[p]) continue;
+        /* the history: the reprojected probe's atlas, or with ray guiding the reconstruction
+         * (its empty cells take the new estimate as it is) */
+        if (!st->guided && st->hist[p] == SENTINEL) continue;
         real *at = st->atlas + (size_t)p * NCELL * 4;
-        const real *pv = st->prev_atlas + (size_t)st->hist[p] * NCELL * 4;
+        const real *pv = st->guided ? st->recon + (size_t)p * NCELL * 4
+                                    : st->prev_atlas + (size_t)st->hist[p] * NCELL * 4;
         for (int cell = 0; cell < NCELL; ++cell) {
             real *c = at + 4 * cell;
             const real *q = pv + 4 * cell;
+            if (st->guided && q[3] < RC(0.0)) continue;
             real l1 = (c[0] * third + c[1] * third) + c[2] * third;
             real l2 = (q[0] * third + q[1] * third) + q[2] * third;
             real a = rmax((l1 - l2) - rmin(l1, l2), RC(0.0)) / rmax(rmax(l1, l2), RC(1e-4));
@@ -1820,6 +2024,12 @@ void ORC(temporal_blend_atlas)(const real *curr, const real *prev, uint32_t n, r
         a = a * a;
         for (int k = 0; k < 4; ++k) out[4 * (size_t)i + k] = c[k] + a * (q[k] - c[k]);
     }
+}
+
+void ORC(guiding_export)(const state *st, real *recon, uint32_t *cdf)
+{
+    memcpy(recon, st->recon, sizeof(real) * 4 * NCELL * st->P);
+    memcpy(cdf, st->cdf, sizeof(uint32_t) * NCELL * st->P);
 }
 
 void ORC(temporal_export)(const state *st, uint32_t *win, uint32_t *hist, uint32_t *traced)
