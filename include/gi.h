@@ -109,7 +109,13 @@ typedef struct gi_config {
      * randomly picked tile that is both (adaptive sampling), the lowest-numbered of several
      * such takers winning.  About 1/u^2 of the rays of upscale 1. */
     uint32_t upscale;
-    uint32_t reserved1;
+    /* 1: ray guiding (Section 2.1.2; needs temporal = 1).  Each new probe's hemisphere is
+     * reconstructed from the previous probes of the 3x3 tiles around its projection that pass
+     * the reprojection's plane and normal tests, parallax-corrected through their travelled
+     * distances; rays pick cells in proportion to the reconstruction's luminance (integer
+     * inverse CDF) and a uniform point inside the cell.  The reconstruction is the history
+     * of Algorithm 3 and the radiance of probes kept without tracing. */
+    uint32_t ray_guiding;
 } gi_config;
 
 typedef struct gi_frame {

@@ -208,6 +208,8 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->d_assigned);
   dfree(c->d_over);
   dfree(c->d_over_count);
+  dfree(c->d_recon);
+  dfree(c->d_cdf);
   dfree(c->d_sh);
   dfree(c->tab.fp);
   dfree(c->tab.key);
@@ -251,6 +253,8 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->temporal > 1) { why = "temporal must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   if (g->upscale > 4) { why = "upscale must be 0..4"; return GI_ERR_INVALID_ARG; }
   if (g->upscale > 1 && !g->temporal) { why = "upscale > 1 needs temporal = 1"; return GI_ERR_INVALID_ARG; }
+  if (g->ray_guiding > 1) { why = "ray_guiding must be 0 or 1"; return GI_ERR_INVALID_ARG; }
+  if (g->ray_guiding && !g->temporal) { why = "ray_guiding needs temporal = 1"; return GI_ERR_INVALID_ARG; }
   return GI_OK;
 }
 
@@ -334,6 +338,10 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
     A(dalloc(&c->d_assigned, (size_t)c->P));
     A(dalloc(&c->d_over, (size_t)c->P));
     A(dalloc(&c->d_over_count, 1));
+  }
+  if (cfg->ray_guiding) {
+    A(dalloc(&c->d_recon, (size_t)c->P * 64));
+    A(dalloc(&c->d_cdf, (size_t)c->P * 64));
   }
   A(dalloc(&c->d_sh, (size_t)c->P * 28));
   A(dalloc(&c->tab.fp, c->N));

@@ -102,6 +102,48 @@ __device__ inline void cosine_direction(float nx, float ny, float nz, float u0, 
   cell = (uint32_t)(8 * iy + ix);
 }
 
+// normalised centre of hemi-octahedral cell `cell` in the frame about n
+__device__ inline void cell_centre_direction(uint32_t cell, float nx, float ny, float nz, float& dx, float& dy,
+                                             float& dz) {
+  const float u = (float)(2 * (cell & 7u) + 1) / 8.0f - 1.0f;
+  const float v = (float)(2 * (cell >> 3) + 1) / 8.0f - 1.0f;
+  const float a = (u + v) * 0.5f, b = (u - v) * 0.5f;
+  const float z = (1.0f - fabsf(a)) - fabsf(b);
+  const float len = sqrtf((a * a + b * b) + z * z);
+  const float lx = a / len, ly = b / len, lz = z / len;
+  const Basis B = make_basis(nx, ny, nz);
+  dx = (lx * B.tx + ly * B.bx) + lz * nx;
+  dy = (lx * B.ty + ly * B.by) + lz * ny;
+  dz = (lx * B.tz + ly * B.bz) + lz * nz;
+}
+
+// the atlas cell of a local direction (lx, ly, lz >= 0), not necessarily unit
+__device__ inline uint32_t local_cell(float lx, float ly, float lz) {
+  const float sum = (fabsf(lx) + fabsf(ly)) + lz;
+  const float a = lx / sum, b = ly / sum;
+  int ix = (int)floorf(4.0f * ((a + b) + 1.0f));
+  int iy = (int)floorf(4.0f * ((a - b) + 1.0f));
+  ix = ix < 0 ? 0 : (ix > 7 ? 7 : ix);
+  iy = iy < 0 ? 0 : (iy > 7 ? 7 : iy);
+  return (uint32_t)(8 * iy + ix);
+}
+
+// ray guiding: the direction of the point (u0, u1) of atlas cell k's square in the
+// hemi-octahedral domain, about n
+__device__ inline void guided_direction(float nx, float ny, float nz, uint32_t k, float u0, float u1, float& dx,
+                                        float& dy, float& dz) {
+  const float uu = ((float)(k & 7u) + u0) * 0.25f - 1.0f;
+  const float vv = ((float)(k >> 3) + u1) * 0.25f - 1.0f;
+  const float a = (uu + vv) * 0.5f, b = (uu - vv) * 0.5f;
+  const float z = (1.0f - fabsf(a)) - fabsf(b);
+  const float len = sqrtf((a * a + b * b) + z * z);
+  const float lx = a / len, ly = b / len, lz = z / len;
+  const Basis B = make_basis(nx, ny, nz);
+  dx = (lx * B.tx + ly * B.bx) + lz * nx;
+  dy = (lx * B.ty + ly * B.by) + lz * ny;
+  dz = (lx * B.tz + ly * B.bz) + lz * nz;
+}
+
 __device__ inline float origin_offset(float scale, float px, float py, float pz) {
   const float m = fmaxf(fmaxf(fabsf(px), fabsf(py)), fabsf(pz));
   return scale * (1.0f + m);

@@ -96,6 +96,10 @@ struct gi_context {
   uint32_t* d_assigned = nullptr;    // [P] per override tile: the lowest empty tile that picked it
   uint32_t* d_over = nullptr;        // [P] override tiles in tile order
   uint32_t* d_over_count = nullptr;  // [1]
+  // ray guiding (config ray_guiding): reconstruction and sampling weights of this frame's probes
+  float4* d_recon = nullptr;         // [P*64] rgb, distance (-1: empty cell)
+  uint32_t* d_cdf = nullptr;         // [P*64] inclusive weight sums
+  bool guided = false;               // this frame's spawn built them
   bool has_prev = false;             // a previous frame's probes are stored
   bool reprojected = false;          // this frame's spawn reprojected them
   gi_frame prev_frame{};

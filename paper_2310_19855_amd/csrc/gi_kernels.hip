@@ -73,6 +73,23 @@ struct PrevCamera {
   float tan_half;
 };
 
+// the previous frame's pixel (qx, qy) whose centre region holds the projection of X
+__device__ inline bool project_prev(const PrevCamera& pc, uint32_t W, uint32_t H, float Xx, float Xy, float Xz,
+                                    uint32_t& qx, uint32_t& qy) {
+  const float v0 = Xx - pc.pos[0], v1 = Xy - pc.pos[1], v2 = Xz - pc.pos[2];
+  const float z = (v0 * pc.fwd[0] + v1 * pc.fwd[1]) + v2 * pc.fwd[2];
+  if (!(z > 0.0f)) return false;
+  const float a = ((v0 * pc.right[0] + v1 * pc.right[1]) + v2 * pc.right[2]) / z;
+  const float b = ((v0 * pc.up[0] + v1 * pc.up[1]) + v2 * pc.up[2]) / z;
+  const float aspect = (float)W / (float)H;
+  const float sx = a / (pc.tan_half * aspect), sy = b / pc.tan_half;
+  const float fx = ((sx + 1.0f) * (float)W) * 0.5f, fy = ((1.0f - sy) * (float)H) * 0.5f;
+  if (!(fx >= 0.0f && fx < (float)W && fy >= 0.0f && fy < (float)H)) return false;
+  qx = (uint32_t)fx;
+  qy = (uint32_t)fy;
+  return true;
+}
+
 __global__ __launch_bounds__(64) void k_reproject(const float4* gpos, const float4* gnrm, const uint32_t* gprim,
                                                   uint32_t W, uint32_t H, uint32_t TW, const uint32_t* prev_mask,
                                                   const float4* prev_pos, const float4* prev_nrm, PrevCamera pc,
@@ -90,30 +107,21 @@ __global__ __launch_bounds__(64) void k_reproject(const float4* gpos, const floa
     const uint32_t pix = y * W + x;
     if (gprim[pix] != kMiss) {
       const float4 X = gpos[pix], n = gnrm[pix];
-      const float v0 = X.x - pc.pos[0], v1 = X.y - pc.pos[1], v2 = X.z - pc.pos[2];
-      const float z = (v0 * pc.fwd[0] + v1 * pc.fwd[1]) + v2 * pc.fwd[2];
-      if (z > 0.0f) {
-        const float a = ((v0 * pc.right[0] + v1 * pc.right[1]) + v2 * pc.right[2]) / z;
-        const float b = ((v0 * pc.up[0] + v1 * pc.up[1]) + v2 * pc.up[2]) / z;
-        const float aspect = (float)W / (float)H;
-        const float sx = a / (pc.tan_half * aspect), sy = b / pc.tan_half;
-        const float fx = ((sx + 1.0f) * (float)W) * 0.5f, fy = ((1.0f - sy) * (float)H) * 0.5f;
-        if (fx >= 0.0f && fx < (float)W && fy >= 0.0f && fy < (float)H) {
-          const uint32_t qx = (uint32_t)fx, qy = (uint32_t)fy;
-          const uint32_t q = (qy >> 3) * TW + (qx >> 3);
-          if (prev_mask[q] != kSentinel) {
-            const float4 wq = prev_pos[q], nq = prev_nrm[q];
-            const float dx = X.x - cx, dy = X.y - cy, dz = X.z - cz;
-            const float cs = kappa * sqrtf((dx * dx + dy * dy) + dz * dz);
-            const float pd = fabsf(((wq.x - X.x) * n.x + (wq.y - X.y) * n.y) + (wq.z - X.z) * n.z);
-            const float nc = (nq.x * n.x + nq.y * n.y) + nq.z * n.z;
-            if (pd < cs && nc > 0.95f) {
-              const float ex = wq.x - X.x, ey = wq.y - X.y, ez = wq.z - X.z;
-              const float dist = sqrtf((ex * ex + ey * ey) + ez * ez);
-              const uint32_t score = ((uint32_t)__half_as_ushort(__float2half_rn(dist)) << 16) | lane;
-              atomicMin(&best, score);
-              myq = q;
-            }
+      uint32_t qx, qy;
+      if (project_prev(pc, W, H, X.x, X.y, X.z, qx, qy)) {
+        const uint32_t q = (qy >> 3) * TW + (qx >> 3);
+        if (prev_mask[q] != kSentinel) {
+          const float4 wq = prev_pos[q], nq = prev_nrm[q];
+          const float dx = X.x - cx, dy = X.y - cy, dz = X.z - cz;
+          const float cs = kappa * sqrtf((dx * dx + dy * dy) + dz * dz);
+          const float pd = fabsf(((wq.x - X.x) * n.x + (wq.y - X.y) * n.y) + (wq.z - X.z) * n.z);
+          const float nc = (nq.x * n.x + nq.y * n.y) + nq.z * n.z;
+          if (pd < cs && nc > 0.95f) {
+            const float ex = wq.x - X.x, ey = wq.y - X.y, ez = wq.z - X.z;
+            const float dist = sqrtf((ex * ex + ey * ey) + ez * ez);
+            const uint32_t score = ((uint32_t)__half_as_ushort(__float2half_rn(dist)) << 16) | lane;
+            atomicMin(&best, score);
+            myq = q;
           }
         }
       }
@@ -324,11 +332,117 @@ __global__ __launch_bounds__(1024) void k_mask_mips_top(MipInfo mi, uint32_t* ma
 }
 
 // ------------------------------------------------------------------------------------------
+// Ray guiding (Section 2.1.2): parallax-corrected reconstruction of each new probe's
+// hemisphere from the previous frame's probes, one wave per probe.  Candidates are the
+// previous probes of the 3x3 tiles around the previous-frame tile that holds the probe's
+// projection, if they pass the reprojection's tests (plane distance below the probe's cell
+// size, normal cosine above 0.95).  Lane c of a candidate takes its cell c's hit point
+// (position + travelled distance along the cell's centre direction) and sends the cell's
+// radiance and the point's distance to the new probe's cell of that point.  Lanes sending
+// to one cell are folded by the first of them in ascending lane order, candidates in row
+// then column order, so every float sum has one fixed order.  Then per cell the weight
+// floor(2^20 lum / max lum) (lum = channel mean) and the inclusive sums that the trace
+// inverts; an empty cell holds distance -1.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_reconstruct(const uint32_t* mask, const float4* ppos, const float4* pnrm,
+                                                    uint32_t W, uint32_t H, uint32_t TW, uint32_t TH, PrevCamera pc,
+                                                    float cx, float cy, float cz, float kappa,
+                                                    const uint32_t* prev_mask, const float4* prev_pos,
+                                                    const float4* prev_nrm, const float4* prev_atlas, float4* recon,
+                                                    uint32_t* cdf) {
+  __shared__ float sum[64][4];
+  __shared__ uint32_t cnt[64];
+  __shared__ float rv[64][4];
+  const uint32_t p = blockIdx.x, lane = threadIdx.x;
+  sum[lane][0] = sum[lane][1] = sum[lane][2] = sum[lane][3] = 0.0f;
+  cnt[lane] = 0u;
+  __syncthreads();
+  const float4 pp = ppos[p], pn = pnrm[p];
+  uint32_t qx = 0, qy = 0;
+  if (mask[p] != kSentinel && project_prev(pc, W, H, pp.x, pp.y, pp.z, qx, qy)) {
+    const float ex = pp.x - cx, ey = pp.y - cy, ez = pp.z - cz;
+    const float cs = kappa * sqrtf((ex * ex + ey * ey) + ez * ez);
+    const Basis B = make_basis(pn.x, pn.y, pn.z);
+    for (int dy = -1; dy <= 1; ++dy) {
+      for (int dx = -1; dx <= 1; ++dx) {
+        // tile, validity and the tests are the same for every lane: the wave takes one branch
+        const int32_t tx = (int32_t)(qx >> 3) + dx, ty = (int32_t)(qy >> 3) + dy;
+        if (tx < 0 || ty < 0 || tx >= (int32_t)TW || ty >= (int32_t)TH) continue;
+        const uint32_t q = (uint32_t)ty * TW + (uint32_t)tx;
+        if (prev_mask[q] == kSentinel) continue;
+        const float4 wq = prev_pos[q], nq = prev_nrm[q];
+        const float pd = fabsf(((wq.x - pp.x) * pn.x + (wq.y - pp.y) * pn.y) + (wq.z - pp.z) * pn.z);
+        const float nc = (nq.x * pn.x + nq.y * pn.y) + nq.z * pn.z;
+        if (!(pd < cs && nc > 0.95f)) continue;
+        const float4 qa = prev_atlas[(size_t)q * 64 + lane];
+        float d0, d1, d2;
+        cell_centre_direction(lane, nq.x, nq.y, nq.z, d0, d1, d2);
+        const float v0 = (wq.x + qa.w * d0) - pp.x;
+        const float v1 = (wq.y + qa.w * d1) - pp.y;
+        const float v2 = (wq.z + qa.w * d2) - pp.z;
+        const float lz = (v0 * pn.x + v1 * pn.y) + v2 * pn.z;
+        const bool on = lz > 0.0f;
+        uint32_t k = 0u;
+        if (on) {
+          const float lx = (v0 * B.tx + v1 * B.ty) + v2 * B.tz;
+          const float ly = (v0 * B.bx + v1 * B.by) + v2 * B.bz;
+          k = local_cell(lx, ly, lz);
+        }
+        rv[lane][0] = qa.x;
+        rv[lane][1] = qa.y;
+        rv[lane][2] = qa.z;
+        rv[lane][3] = sqrtf((v0 * v0 + v1 * v1) + v2 * v2);
+        uint64_t same = __ballot(on);
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+          const uint64_t mb = __ballot(on && ((k >> b) & 1u));
+          same &= ((k >> b) & 1u) ? mb : ~mb;
+        }
+        __syncthreads();
+        if (on && (uint32_t)__ffsll((long long)same) - 1u == lane) {
+          float x0 = sum[k][0], x1 = sum[k][1], x2 = sum[k][2], x3 = sum[k][3];
+          uint32_t m = cnt[k];
+          for (uint64_t s = same; s; s &= s - 1u) {
+            const int i = __ffsll((long long)s) - 1;
+            x0 = x0 + rv[i][0]; x1 = x1 + rv[i][1]; x2 = x2 + rv[i][2]; x3 = x3 + rv[i][3];
+            ++m;
+          }
+          sum[k][0] = x0; sum[k][1] = x1; sum[k][2] = x2; sum[k][3] = x3;
+          cnt[k] = m;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const uint32_t n = cnt[lane];
+  float4 r = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+  float lum = 0.0f;
+  if (n) {
+    const float fn = (float)n;
+    r = make_float4(sum[lane][0] / fn, sum[lane][1] / fn, sum[lane][2] / fn, sum[lane][3] / fn);
+    const float third = 1.0f / 3.0f;
+    lum = (r.x * third + r.y * third) + r.z * third;
+  }
+  float maxl = lum;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) maxl = fmaxf(maxl, __shfl_xor(maxl, o, 64));
+  uint32_t w = (n && maxl > 0.0f) ? (uint32_t)((lum / maxl) * 1048576.0f) : 0u;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t up = __shfl_up(w, o, 64);
+    if (lane >= (uint32_t)o) w += up;
+  }
+  recon[(size_t)p * 64 + lane] = r;
+  cdf[(size_t)p * 64 + lane] = w;
+}
+
+// ------------------------------------------------------------------------------------------
 // Probe rays (Section 2.1.3): cosine-distributed direction, closest hit, ray record
 // ------------------------------------------------------------------------------------------
 struct ProbeRayArgs {
   const uint32_t* mask;
   const uint32_t* traced;   // temporal upscaling: probes that trace this frame (else every probe)
+  const uint32_t* cdf;      // ray guiding: per probe the 64 inclusive weight sums (else none)
   const float4* ppos;
   const float4* pnrm;
   uint32_t P, R, seed, frame;
@@ -340,7 +454,23 @@ __device__ inline void probe_ray(const ProbeRayArgs& a, uint32_t gid, uint32_t p
   const float4 pp = a.ppos[p], pn = a.pnrm[p];
   const float u0 = rand_unit(rand_u32(a.seed, a.frame, gid, 0u));
   const float u1 = rand_unit(rand_u32(a.seed, a.frame, gid, 1u));
-  cosine_direction(pn.x, pn.y, pn.z, u0, u1, dx, dy, dz, cell);
+  const uint32_t* cdf = a.cdf ? a.cdf + (size_t)p * 64 : nullptr;
+  const uint32_t total = cdf ? cdf[63] : 0u;
+  if (total) {
+    // ray guiding: the first cell whose inclusive weight sum exceeds floor(r * total / 2^32),
+    // then a uniform point of that cell
+    const uint32_t target = (uint32_t)(((uint64_t)rand_u32(a.seed, a.frame, gid, 8u) * total) >> 32);
+    uint32_t lo = 0u, hi = 63u;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (cdf[mid] > target) hi = mid;
+      else lo = mid + 1u;
+    }
+    cell = lo;
+    guided_direction(pn.x, pn.y, pn.z, cell, u0, u1, dx, dy, dz);
+  } else {
+    cosine_direction(pn.x, pn.y, pn.z, u0, u1, dx, dy, dz, cell);
+  }
   const float eps = origin_offset(a.eps_scale, pp.x, pp.y, pp.z);
   ox = pp.x + pn.x * eps;
   oy = pp.y + pn.y * eps;
@@ -792,8 +922,8 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
                                                   const float4* L, const float4* tnrm, const float4* mats,
                                                   const float* moments, uint32_t R, float s0, float s1, float s2,
                                                   LearnedGatherIn lg, uint32_t do_sh, const uint32_t* hist,
-                                                  const uint32_t* traced, const float4* prev_atlas, float4* atlas,
-                                                  float* sh) {
+                                                  const uint32_t* traced, const float4* recon,
+                                                  const float4* prev_atlas, float4* atlas, float* sh) {
   __shared__ float rv[kGatherMaxR][4];
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
@@ -808,9 +938,29 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
   }
   if (traced && traced[p] == 0u) {
     // a kept probe that traces nothing this frame (temporal upscaling) keeps the radiance of
-    // the probe it was reprojected from
-    const uint32_t hp = hist ? hist[p] : kSentinel;
-    const float4 q = hp != kSentinel ? prev_atlas[(size_t)hp * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // the probe it was reprojected from; with ray guiding, the reconstruction, its empty
+    // cells filled with the mean of the others (summed in ascending cell order)
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (recon) {
+      const float4 r = recon[(size_t)p * 64 + lane];
+      cv[lane][0] = r.x; cv[lane][1] = r.y; cv[lane][2] = r.z; cv[lane][3] = r.w;
+      const uint64_t pop = __ballot(r.w >= 0.0f);
+      __syncthreads();
+      if (r.w >= 0.0f) {
+        q = r;
+      } else if (pop) {
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+        for (uint64_t m = pop; m; m &= m - 1u) {
+          const int i = __ffsll((long long)m) - 1;
+          m0 = m0 + cv[i][0]; m1 = m1 + cv[i][1]; m2 = m2 + cv[i][2]; m3 = m3 + cv[i][3];
+        }
+        const float fn = (float)__popcll(pop);
+        q = make_float4(m0 / fn, m1 / fn, m2 / fn, m3 / fn);
+      }
+    } else {
+      const uint32_t hp = hist ? hist[p] : kSentinel;
+      if (hp != kSentinel) q = prev_atlas[(size_t)hp * 64 + lane];
+    }
     atlas[(size_t)p * 64 + lane] = q;
     if (do_sh) probe_sh(p, lane, pnrm[p], moments, q.x, q.y, q.z, sh);
     return;
@@ -898,11 +1048,13 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
       c0 = m0 / fn; c1 = m1 / fn; c2 = m2 / fn; c3 = m3 / fn;
     }
   }
-  if (hist) {
-    // Algorithm 3: biased shadow-preserving hysteresis against the reprojected history
-    const uint32_t hp = hist[p];
-    if (hp != kSentinel) {
-      const float4 q = prev_atlas[(size_t)hp * 64 + lane];
+  if (recon || hist) {
+    // Algorithm 3: biased shadow-preserving hysteresis against the history: the reprojected
+    // probe's atlas, or with ray guiding the reconstruction (its empty cells keep the new value)
+    const uint32_t hp = recon ? 0u : hist[p];
+    const float4 q = recon ? recon[(size_t)p * 64 + lane]
+                           : (hp != kSentinel ? prev_atlas[(size_t)hp * 64 + lane] : make_float4(0.f, 0.f, 0.f, -1.f));
+    if (recon ? q.w >= 0.0f : hp != kSentinel) {
       const float third = 1.0f / 3.0f;
       const float l1 = (c0 * third + c1 * third) + c2 * third;
       const float l2 = (q.x * third + q.y * third) + q.z * third;
@@ -945,19 +1097,6 @@ __device__ inline uint32_t find_closest_probe(const uint32_t* mask, const MipInf
 // the travelled distance is re-averaged after each contribution.  The cell direction is the
 // normalised centre of the hemi-octahedral cell in the probe frame.
 // ------------------------------------------------------------------------------------------
-__device__ inline void cell_centre_direction(uint32_t cell, float nx, float ny, float nz, float& dx, float& dy,
-                                             float& dz) {
-  const float u = (float)(2 * (cell & 7u) + 1) / 8.0f - 1.0f;
-  const float v = (float)(2 * (cell >> 3) + 1) / 8.0f - 1.0f;
-  const float a = (u + v) * 0.5f, b = (u - v) * 0.5f;
-  const float z = (1.0f - fabsf(a)) - fabsf(b);
-  const float len = sqrtf((a * a + b * b) + z * z);
-  const float lx = a / len, ly = b / len, lz = z / len;
-  const Basis B = make_basis(nx, ny, nz);
-  dx = (lx * B.tx + ly * B.bx) + lz * nx;
-  dy = (lx * B.ty + ly * B.by) + lz * ny;
-  dz = (lx * B.tz + ly * B.bz) + lz * nz;
-}
 
 template <bool VERTICAL>
 __global__ __launch_bounds__(64) void k_filter_probes(const uint32_t* mask, MipInfo mi, uint32_t TW, const float4* ppos,
@@ -1274,6 +1413,7 @@ static ProbeRayArgs probe_args(const gi_context* c) {
   ProbeRayArgs a;
   a.mask = c->d_mask;
   a.traced = c->cfg.upscale > 1 ? c->d_traced : nullptr;
+  a.cdf = c->guided ? c->d_cdf : nullptr;
   a.ppos = c->d_ppos;
   a.pnrm = c->d_pnrm;
   a.P = c->P;
@@ -1408,6 +1548,19 @@ hipError_t launch_spawn(gi_context* c, const float4* pos, const float4* nrm, con
   }
   GI_TIMED(c, "spawn", s, (k_spawn_mips<<<grid, 256, 0, s>>>(pos, nrm, prim, c->W, c->H, c->TW, c->TH, c->fa.jx, c->fa.jy, mi, c->reprojected ? c->d_win : nullptr, place, c->d_mask, c->d_ppos, c->d_pnrm, c->d_stats, c->d_hit_count)));
   if (mi.n > 5) GI_TIMED(c, "mask_mip", s, (k_mask_mips_top<<<1, 1024, 0, s>>>(mi, c->d_mask)));
+  c->guided = c->reprojected && c->cfg.ray_guiding;
+  if (c->guided) {
+    const gi_frame& pf = c->prev_frame;
+    PrevCamera pc;
+    for (int k = 0; k < 3; ++k) {
+      pc.pos[k] = pf.pos[k];
+      pc.fwd[k] = pf.fwd[k];
+      pc.right[k] = pf.right[k];
+      pc.up[k] = pf.up[k];
+    }
+    pc.tan_half = pf.tan_half;
+    GI_TIMED(c, "reconstruct", s, (k_reconstruct<<<c->P, 64, 0, s>>>(c->d_mask, c->d_ppos, c->d_pnrm, c->W, c->H, c->TW, c->TH, pc, c->fa.cam[0], c->fa.cam[1], c->fa.cam[2], c->fa.kappa, c->d_prev_mask, c->d_prev_pos, c->d_prev_nrm, c->d_prev_atlas, c->d_recon, c->d_cdf)));
+  }
   return hipGetLastError();
 }
 
@@ -1432,7 +1585,7 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const uint32_t filt = c->cfg.probe_filter;
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
   if (filt) {
     // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
     const MipInfo mi = mip_info(c);

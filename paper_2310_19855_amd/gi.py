@@ -43,7 +43,7 @@ class Config(C.Structure):
                 ("mlp_loss_scale", C.c_float), ("mlp_judge", C.c_float),
                 ("scene_min", C.c_float * 4), ("scene_max", C.c_float * 4),
                 ("lod_scale", C.c_float), ("temporal", C.c_uint32), ("upscale", C.c_uint32),
-                ("reserved1", C.c_uint32)]
+                ("ray_guiding", C.c_uint32)]
 
 
 class Frame(C.Structure):

@@ -243,6 +243,29 @@ def test_temporal_upscale_orbit_and_filter():
     assert 0 < traced.sum() < len(traced) // 2
 
 
+def test_ray_guiding_fixed_camera_ragged():
+    """ray guiding (Section 2.1.2) with temporal reuse on a ragged 100x76 room, fixed camera,
+    two bounces, four frames: the parallax-corrected reconstruction, the integer inverse-CDF
+    cell picks and the in-cell directions (every ray's cell, hit and distance bit-exact), the
+    reconstruction as Algorithm 3's history; atlas, SH and irradiance against the oracle"""
+    pr = _run_stage_parity(I.room_scene(), dict(width=100, height=76, rays_per_probe=32, table_log2=17, bounces=2,
+                                                temporal=1, ray_guiding=1), [0, 1, 2, 3],
+                           camera=lambda f: I.room_camera(0))
+    recon, cdf = pr.ost.guiding()
+    assert (cdf[:, 63] > 0).sum() > 0.9 * (pr.ost.probes()["mask"][:pr.ost.P] != SENT).sum()
+
+
+def test_ray_guiding_upscale_orbit_and_filter():
+    """everything of the temporal screen cache at once on the field: the orbit, the moving
+    light, 2x2 upscaling with adaptive sampling, ray guiding (kept probes take the
+    reconstruction) and the filter; four frames"""
+    sc = I.field_scene()
+    pr = _run_stage_parity(sc, dict(width=160, height=96, rays_per_probe=64, table_log2=18, sky=sc.sky, temporal=1,
+                                    upscale=2, ray_guiding=1, probe_filter=1), [0, 1, 2, 3])
+    recon, cdf = pr.ost.guiding()
+    assert (cdf[:, 63] > 0).sum() > 50
+
+
 def test_room_overflowing_table_invariants():
     pr = Pair(I.room_scene(), dict(width=64, height=64, rays_per_probe=32, table_log2=6))
     fr = I.room_camera(0)
@@ -483,3 +506,5 @@ def test_invalid_arguments_and_frame_order():
         gi.Context(width=64, height=64, upscale=2)          # upscaling needs temporal reuse
     with pytest.raises(gi.GIError):
         gi.Context(width=64, height=64, temporal=1, upscale=5)
+    with pytest.raises(gi.GIError, match="INVALID"):
+        gi.Context(width=64, height=64, ray_guiding=1)      # guiding needs temporal reuse
