@@ -230,6 +230,8 @@ def main():
         forms["probe_filter"] = probe_filter_measure(log)
         forms["temporal_reuse"] = temporal_measure(log)
         forms["temporal_upscale_2x2"] = temporal_measure(log, upscale=2, with_cpu=False)
+        forms["temporal_upscale_2x2_guided"] = temporal_measure(log, upscale=2, ray_guiding=1, with_cpu=False)
+        forms["temporal_quality"] = temporal_quality(log)
 
     line = {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
@@ -474,21 +476,24 @@ def probe_filter_measure(log, scene_name="field", W=1920, H=1080, R=64, with_cpu
 
 
 def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, timed_from=8, with_cpu=True,
-                     upscale=1):
+                     upscale=1, ray_guiding=0):
     """Temporal reuse of screen probes (Algorithm 1 reprojection, Algorithm 3 hysteresis) on the
     benchmark workload's moving camera: frames 0..23 of the orbit with the moving light,
     ms/frame over frames 8..23, the reprojection kernel's launch time and its fraction of the
     HBM peak at its algorithmic bytes (per pixel the G-buffer position, normal and primary hit,
     36 B; per tile the winner and history, 8 B; the previous probes come from L2).  With
     upscale 2, temporal upscaling and adaptive sampling (Algorithm 2) on top: probe rays per
-    frame and the placement kernels' time."""
+    frame and the placement kernels' time.  With ray guiding, the reconstruction kernel against
+    the HBM peak at its algorithmic bytes: per probe the previous atlas (1 KiB, each previous
+    probe read from HBM once, its other readers hit L2), position and normal (32 B), and the
+    written reconstruction and weight sums (1 KiB + 256 B)."""
     import torch
 
     from paper_2310_19855_amd import gi
     from paper_2310_19855_amd import inputs as I
     scene = I.make_scene(scene_name)
     ctx = gi.Context(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, temporal=1,
-                     upscale=upscale)
+                     upscale=upscale, ray_guiding=ray_guiding)
     ctx.build_bvh(scene)
     gb = gi.GBuffer(H, W)
     out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
@@ -514,8 +519,15 @@ def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, t
     P = ((W + 7) // 8) * ((H + 7) // 8)
     rays = (ctx.stats()["rays"] - rays0) / n
     res = {"workload": f"{scene_name} {W}x{H}, R={R}, orbit camera and moving light, frames {timed_from}..{frames - 1}"
-                       + (f", temporal upscaling {upscale}x{upscale}" if upscale > 1 else ""),
-           "probe_rays_per_frame": int(rays), "ray_fraction": round(rays / (P * R), 4)}
+                       + (f", temporal upscaling {upscale}x{upscale}" if upscale > 1 else "")
+                       + (", ray guiding" if ray_guiding else ""),
+           "probe_rays_per_frame": int(rays), "ray_fraction": round(rays / (P * R), 4),
+           "kernels_ms_per_frame": {k: round(v[1] / n, 5) for k, v in sorted(prof.items()) if k != "gbuffer"}}
+    if "reconstruct" in prof:
+        ms = prof["reconstruct"][1] / max(prof["reconstruct"][0], 1)
+        b = P * (1024 + 32 + 1024 + 256)
+        res["reconstruct"] = {"avg_ms": round(ms, 5), "alg_bytes": b, "gbs": round(b / (ms * 1e-3) / 1e9, 1),
+                              "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if upscale > 1:
         up = [k for k in prof if k.startswith("upscale_")]
         res["placement_ms_per_frame"] = round(sum(prof[k][1] for k in up) / n, 5)
@@ -528,12 +540,65 @@ def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, t
         res["reproject"] = {"avg_ms": round(ms, 5), "alg_bytes": b, "gbs": round(b / (ms * 1e-3) / 1e9, 1),
                             "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     ctx.close()
-    log(f"[bench] temporal reuse (upscale {upscale}): pass {res.get('pass_ms_per_frame')} ms/frame, "
+    log(f"[bench] temporal reuse (upscale {upscale}, guiding {ray_guiding}): pass {res.get('pass_ms_per_frame')} ms/frame, "
         f"{res['ray_fraction']} of the rays, reproject "
         f"{res.get('reproject', {}).get('avg_ms')} ms ({res.get('reproject', {}).get('frac_hbm')} of HBM peak)")
     if with_cpu:
         res["cpu_baseline"] = temporal_cpu(scene, scene_name, W, H, R)
         log(f"[bench] temporal reuse, CPU oracle spawn with reprojection: {res['cpu_baseline']['value']:.1f} ms")
+    return res
+
+
+def temporal_quality(log, W=512, H=288, R=64, frames=32, ref_R=256, ref_frames=96):
+    """What the temporal screen cache buys per ray (room, fixed camera, 512x288, 64 rays per
+    probe): the per-pixel irradiance of frames 24..31 against a converged reference (the mean
+    of 88 frames of 256 rays per probe without temporal reuse), as the relative L1 error over
+    the image and the ratio of mean levels, for: no reuse; reuse (Algorithms 1, 3); reuse with
+    ray guiding; 2x2 upscaling with adaptive sampling; upscaling with guiding.  The rays per
+    frame are measured by the context's counters."""
+    import torch
+
+    from paper_2310_19855_amd import gi
+    from paper_2310_19855_amd import inputs as I
+    scene = I.room_scene()
+    cam = I.room_camera(0)
+
+    def run(R_, nframes, keep_from, **kw):
+        ctx = gi.Context(width=W, height=H, rays_per_probe=R_, table_log2=18, bounces=2, **kw)
+        ctx.build_bvh(scene)
+        gb = gi.GBuffer(H, W)
+        out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+        acc, kept, rays0 = [], 0, 0
+        for f in range(nframes):
+            cam.index = f
+            if f == keep_from:
+                rays0 = ctx.stats()["rays"]
+            ctx.render_gbuffer(cam, gb.pos, gb.nrm, gb.alb, gb.prim)
+            ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
+            ctx.trace_probes(cam)
+            ctx.cache_update(cam)
+            ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, out)
+            if f >= keep_from:
+                acc.append(out[..., :3].clone())
+                kept += 1
+        rays = (ctx.stats()["rays"] - rays0) / max(kept, 1)
+        ctx.close()
+        return torch.stack(acc), rays
+
+    ref_frames_t, _ = run(ref_R, ref_frames, 8)
+    ref = ref_frames_t.mean(0)
+    lum = ref.mean(-1)
+    on = lum > 1e-3 * lum.max()
+    modes = {"no_reuse": {}, "reuse": dict(temporal=1), "reuse_guided": dict(temporal=1, ray_guiding=1),
+             "upscale_2x2": dict(temporal=1, upscale=2), "upscale_2x2_guided": dict(temporal=1, upscale=2, ray_guiding=1)}
+    res = {"workload": f"room {W}x{H}, fixed camera, R={R}, two bounces, frames 24..{frames - 1}; reference "
+                       f"R={ref_R} without reuse, mean of {ref_frames} frames", "modes": {}}
+    for name, kw in modes.items():
+        fr, rays = run(R, frames, 24, **kw)
+        err = ((fr - ref).abs().mean(-1)[:, on] / lum[on]).mean().item()
+        level = (fr.mean(-1)[:, on].mean() / lum[on].mean()).item()
+        res["modes"][name] = {"rel_l1": round(err, 4), "level": round(level, 4), "rays_per_frame": int(rays)}
+        log(f"[bench] temporal quality {name}: rel L1 {err:.4f}, level {level:.3f}, {int(rays)} rays/frame")
     return res
 
 
