@@ -33,7 +33,9 @@ class OrcConfig(C.Structure):
                 ("frac_bits", C.c_uint32), ("probe_filter", C.c_uint32), ("lod_scale", C.c_float),
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4),
-                ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32), ("pad4", C.c_uint32)]
+                ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32),
+                ("cache_tiles", C.c_uint32), ("tile_min", C.c_uint32), ("pad5", C.c_uint32), ("pad6", C.c_uint32),
+                ("pad7", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -46,7 +48,7 @@ def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
-               temporal=0, upscale=0, ray_guiding=0)
+               temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min=16)
     cfg.update(kw)
     return cfg
 
@@ -109,6 +111,9 @@ def _lib(f64: bool):
     fn("export_probes", None, vp, U32P, R, R, R, R)
     fn("export_rays", None, vp, I32P, R, U32P, U32P, U64P, R)
     fn("export_table", C.c_uint32, vp, U64P, U64P, U32P, R, U32P, U32P, C.c_uint32)
+    fn("export_tiles", C.c_uint32, vp, U64P, U64P, U32P, U32P, R, U32P, R, C.c_uint32)
+    fn("tile_keys", None, C.POINTER(OrcConfig), R, R, R, R, C.c_uint32, U64P, U32P)
+    fn("prefilter", None, R, U32P, C.c_uint32, R)
     fn("poke_cell", C.c_int, vp, C.c_uint64, U32P, R, C.c_uint32, C.c_uint32, C.c_uint32)
     fn("cache_update_only", None, vp)
     fn("stats", None, vp, U64P)
@@ -249,6 +254,28 @@ def keys(cfg: dict, y, n, t, f64=False, cam=(0.0, 0.0, 0.0)):
     c = make_config(cfg)
     _call(f64, "keys", C.byref(c), cam, y, n, t, cnt, key, b, fp)
     return key, b, fp
+
+
+def tile_keys(cfg: dict, y, n, t, f64=False, cam=(0.0, 0.0, 0.0)):
+    """two-level cache: tile descriptor and the cell inside the tile of points y with normals n"""
+    dt = np.float64 if f64 else np.float32
+    cam = np.ascontiguousarray(cam, dt)
+    y = np.ascontiguousarray(y, dt)
+    n = np.ascontiguousarray(n, dt)
+    t = np.ascontiguousarray(t, dt)
+    key = np.zeros(len(t), np.uint64)
+    cell = np.zeros(len(t), np.uint32)
+    c = make_config(dict(cfg, cache_tiles=1))
+    _call(f64, "tile_keys", C.byref(c), cam, y, n, t, len(t), key, cell)
+    return key, cell
+
+
+def prefilter(L0, n0, T, f64=True):
+    """the tile MIP levels and query radiance of one tile's 64 cells (rgb [64, 3], samples [64])"""
+    dt = np.float64 if f64 else np.float32
+    out = np.zeros((NCELL, 3), dt)
+    _call(f64, "prefilter", np.ascontiguousarray(L0, dt), np.ascontiguousarray(n0, np.uint32), T, out)
+    return out
 
 
 def sh_eval(coef, n, f64=False):
@@ -453,6 +480,22 @@ class OracleFrameState:
         order = np.argsort(ident[:n], kind="stable")
         return dict(id=ident[:n][order], key=key[:n][order], acc=acc[:n][order], L=L[:n][order],
                     nhist=nh[:n][order], life=life[:n][order])
+
+    def tiles(self):
+        """two-level cache: live tiles sorted by (bucket, fingerprint), with per-cell fixed-point
+        sums, moving averages, sample counts and the prefiltered query radiance"""
+        cap = self.N
+        ident = np.zeros(cap, np.uint64)
+        key = np.zeros(cap, np.uint64)
+        life = np.zeros(cap, np.uint32)
+        acc = np.zeros((cap, NCELL, 4), np.uint32)
+        L = np.zeros((cap, NCELL, 3), self.dt)
+        nh = np.zeros((cap, NCELL), np.uint32)
+        Lq = np.zeros((cap, NCELL, 3), self.dt)
+        n = _call(self.f64, "export_tiles", self.h, ident, key, life, acc, L, nh, Lq, cap)
+        o = np.argsort(ident[:n], kind="stable")
+        return dict(id=ident[:n][o], key=key[:n][o], life=life[:n][o], acc=acc[:n][o], L=L[:n][o],
+                    nhist=nh[:n][o], Lq=Lq[:n][o])
 
     def poke_cell(self, key, acc4, L3, nhist, life, accessed):
         return _call(self.f64, "poke_cell", self.h, key, np.ascontiguousarray(acc4, np.uint32),

@@ -675,7 +675,8 @@ typedef struct orc_config {
     float lod_scale;
     float cell_scale, r_max, eps_scale, t_sky;
     float sky[4];
-    uint32_t temporal, upscale, ray_guiding, pad4;
+    uint32_t temporal, upscale, ray_guiding, cache_tiles;
+    uint32_t tile_min, pad5, pad6, pad7;
 } orc_config;
 
 typedef struct orc_frame {
@@ -752,8 +753,10 @@ typedef struct state {
     uint64_t *key;
     uint32_t *acc;         /* [N][4] fixed-point r,g,b and count */
     double *dacc;          /* [N][3] FP64 sums (reference mode) */
-    real *L;               /* [N][3] */
-    uint32_t *nhist, *life, *accessed;
+    real *L;               /* [N][3]; tiled: [N][64][3] level-0 cells */
+    uint32_t *nhist, *life, *accessed;   /* nhist per cell ([N][64] tiled), life and accessed per slot */
+    real *Lq;              /* tiled: [N][64][3] radiance returned to queries (prefiltered level) */
+    uint32_t *r_tcell;     /* tiled: [P*R] cell of the hit inside its tile */
     /* probes */
     real *atlas;           /* [P][64][4] */
     real *sh;              /* [P][27] */
@@ -918,7 +921,16 @@ static uint32_t cell_lod(const orc_config *c, const real *cam, const real *y)
     return lod;
 }
 
-static uint64_t cell_key(const orc_config *c, const real *cam, const real *y, const real *n, real t, int with_leak)
+/* floor(v / 8) for signed v */
+static int32_t floor_div8(int32_t v) { return v >= 0 ? v / 8 : -((-v + 7) / 8); }
+
+/* Two-level world cache (Section 2.2.3, prefiltering): with cache_tiles, the descriptor names
+ * a tile of 8x8x8 cells (quantised position divided by 8, floor), and the hit's cell inside
+ * the tile is 2D: the position's remainders modulo 8 along the two axes other than the main
+ * axis of the normal (the axis of the normal class), u the lower-numbered one:
+ * cell = 8 (v mod 8) + (u mod 8). */
+static uint64_t cell_key_cell(const orc_config *c, const real *cam, const real *y, const real *n, real t,
+                              int with_leak, uint32_t *tcell)
 {
     uint32_t lod = cell_lod(c, cam, y);
     real S = (real)c->cell_scale * (RC(1.0) / (real)(1u << lod));
@@ -929,11 +941,35 @@ static uint64_t cell_key(const orc_config *c, const real *cam, const real *y, co
     real best = RABS(n[0]);
     if (RABS(n[1]) > best) { axis = 1; best = RABS(n[1]); }
     if (RABS(n[2]) > best) { axis = 2; }
+    if (tcell) *tcell = 0;
+    if (c->cache_tiles) {
+        int32_t q[3] = {qx, qy, qz};
+        int32_t u = q[axis == 0 ? 1 : 0], v = q[axis == 2 ? 1 : 2];
+        if (tcell) *tcell = 8u * (uint32_t)(v - 8 * floor_div8(v)) + (uint32_t)(u - 8 * floor_div8(u));
+        qx = floor_div8(qx);
+        qy = floor_div8(qy);
+        qz = floor_div8(qz);
+    }
     uint64_t cls = (uint64_t)(2 * axis + (n[axis] < RC(0.0) ? 1 : 0));
     uint64_t leak = (with_leak && c->leak_bit && t * S < RC(1.0)) ? 1u : 0u;
     return ((uint64_t)(uint32_t)qx & 0x3FFFFu) | (((uint64_t)(uint32_t)qy & 0x3FFFFu) << 18) |
            (((uint64_t)(uint32_t)qz & 0x3FFFFu) << 36) | (cls << 54) | (leak << 57) | ((uint64_t)lod << 58);
 }
+
+static uint64_t cell_key(const orc_config *c, const real *cam, const real *y, const real *n, real t, int with_leak)
+{
+    return cell_key_cell(c, cam, y, n, t, with_leak, NULL);
+}
+
+/* world-cache entry of a hit: slot, or with tiles slot * 64 + cell inside the tile */
+static int32_t cache_entry(const state *st, int32_t slot, uint32_t tcell)
+{
+    if (slot < 0) return slot;
+    return st->cfg.cache_tiles ? slot * NCELL + (int32_t)tcell : slot;
+}
+
+/* the radiance readers see per entry: the cell's own, or with tiles its prefiltered level */
+static const real *cache_L(const state *st) { return st->cfg.cache_tiles ? st->Lq : st->L; }
 
 static uint32_t key_bucket(uint64_t key, uint32_t nbuckets)
 {
@@ -1030,10 +1066,13 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->r_bslot = (int32_t *)calloc(PR, sizeof(int32_t));
     st->fp = (uint32_t *)calloc(N, sizeof(uint32_t));
     st->key = (uint64_t *)calloc(N, sizeof(uint64_t));
-    st->acc = (uint32_t *)calloc(4 * N, sizeof(uint32_t));
-    st->dacc = (double *)calloc(3 * N, sizeof(double));
-    st->L = (real *)calloc(3 * N, sizeof(real));
-    st->nhist = (uint32_t *)calloc(N, sizeof(uint32_t));
+    size_t G = cfg->cache_tiles ? NCELL : 1;   /* cells per slot */
+    st->acc = (uint32_t *)calloc(4 * N * G, sizeof(uint32_t));
+    st->dacc = (double *)calloc(3 * N * G, sizeof(double));
+    st->L = (real *)calloc(3 * N * G, sizeof(real));
+    st->nhist = (uint32_t *)calloc(N * G, sizeof(uint32_t));
+    st->Lq = (real *)calloc(cfg->cache_tiles ? 3 * N * G : 1, sizeof(real));
+    st->r_tcell = (uint32_t *)calloc(PR, sizeof(uint32_t));
     st->life = (uint32_t *)calloc(N, sizeof(uint32_t));
     st->accessed = (uint32_t *)calloc(N, sizeof(uint32_t));
     st->atlas = (real *)calloc(P * NCELL * 4, sizeof(real));
@@ -1060,6 +1099,7 @@ void ORC(destroy)(state *st)
     free(st->r_sample); free(st->r_keylo); free(st->r_keyhi); free(st->r_valid); free(st->r_bslot);
     free(st->fp); free(st->key); free(st->acc); free(st->dacc); free(st->L);
     free(st->nhist); free(st->life); free(st->accessed); free(st->atlas); free(st->sh);
+    free(st->Lq); free(st->r_tcell);
     free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
     free(st->hist); free(st->traced); free(st->recon); free(st->cdf);
     free(st);
@@ -1517,10 +1557,12 @@ static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const 
             real dn = (n[0] * d[0] + n[1] * d[1]) + n[2] * d[2];
             real sg = dn > RC(0.0) ? RC(-1.0) : RC(1.0);
             for (int k = 0; k < 3; ++k) { z[k] = yo[k] + t * d[k]; nz[k] = sg * n[k]; }
-            int32_t slot = table_find(st, cell_key(c, st->cam, z, nz, t, 1));
-            *bslot = slot;
-            if (slot >= 0)
-                for (int k = 0; k < 3; ++k) Lb[k] = st->L[3 * (size_t)slot + k];
+            uint32_t tc;
+            uint64_t bkey = cell_key_cell(c, st->cam, z, nz, t, 1, &tc);
+            int32_t e = cache_entry(st, table_find(st, bkey), tc);
+            *bslot = e;
+            if (e >= 0)
+                for (int k = 0; k < 3; ++k) Lb[k] = cache_L(st)[3 * (size_t)e + k];
         }
     }
     for (int k = 0; k < 3; ++k) s_out[k] = E[k] * RC(0.31830988618379067) + Lb[k];
@@ -1582,7 +1624,7 @@ void ORC(trace)(state *st, const orc_frame *fr)
             st->r_t[gid] = t;
             st->r_tri[gid] = tri;
             st->r_cell[gid] = flags;
-            uint64_t key = cell_key(c, st->cam, y, ny, t, 1);
+            uint64_t key = cell_key_cell(c, st->cam, y, ny, t, 1, &st->r_tcell[gid]);
             st->r_keylo[gid] = (uint32_t)key;
             st->r_keyhi[gid] = (uint32_t)(key >> 32);
             real s[3];
@@ -1603,10 +1645,11 @@ void ORC(trace)(state *st, const orc_frame *fr)
         if (!st->r_valid[gid]) continue;
         st->stats[ST_HITS]++;
         uint64_t key = (uint64_t)st->r_keylo[gid] | ((uint64_t)st->r_keyhi[gid] << 32);
-        int32_t slot = table_insert(st, key);
+        int32_t tslot = table_insert(st, key);
+        int32_t slot = cache_entry(st, tslot, st->r_tcell[gid]);
         st->r_slot[gid] = slot;
         if (slot < 0) continue;
-        st->accessed[slot] = 1;
+        st->accessed[tslot] = 1;
         const real *s = st->r_sample + 3 * gid;
         if (!isfinite((double)s[0]) || !isfinite((double)s[1]) || !isfinite((double)s[2])) {
             st->stats[ST_NONFINITE]++;
@@ -1629,7 +1672,8 @@ void ORC(trace)(state *st, const orc_frame *fr)
     /* cells found by bounce lookups count as accessed; the lookups saw the table as it was
      * before this frame's insertions, so their order does not matter */
     for (size_t gid = 0; gid < PR; ++gid)
-        if (st->r_bslot[gid] >= 0) st->accessed[st->r_bslot[gid]] = 1u;
+        if (st->r_bslot[gid] >= 0)
+            st->accessed[st->cfg.cache_tiles ? st->r_bslot[gid] / NCELL : st->r_bslot[gid]] = 1u;
 }
 
 /* NEE radiance estimate E/pi (before albedo) for a surface point and normal, one estimate per
@@ -1654,43 +1698,115 @@ void ORC(nee_samples)(state *st, const orc_frame *fr, const real *y, const real 
  * counts, capped at n_cap samples of history; the decay value is an integer life reset to
  * max_life on access, decremented otherwise, and the cell is freed at zero.
  * ------------------------------------------------------------------------------------- */
-static void cache_update(state *st)
+/* moving average of one cell (entry e) with this frame's samples (Section 2.2.3) */
+static void ema_entry(state *st, size_t e)
 {
     const orc_config *c = &st->cfg;
     double scale = (double)(1u << c->frac_bits);
     (void)scale;
+    uint32_t cnt = st->acc[4 * e + 3];
+    if (cnt == 0) return;
+    uint32_t h = st->nhist[e] < c->n_cap ? st->nhist[e] : c->n_cap;
+    real w = (real)cnt / (real)((double)h + (double)cnt);
+    for (int k = 0; k < 3; ++k) {
+#ifdef ORC_F64
+        real mean = st->dacc[3 * e + k] / (double)cnt;
+#else
+        real mean = (float)((double)st->acc[4 * e + k] / ((double)cnt * scale));
+#endif
+        real L = st->L[3 * e + k];
+        st->L[3 * e + k] = L + w * (mean - L);
+    }
+    uint64_t nh = (uint64_t)st->nhist[e] + cnt;
+    st->nhist[e] = nh < c->n_cap ? (uint32_t)nh : c->n_cap;
+}
+
+/* Tile MIP levels (Section 2.2.3): level k+1 entry = sample-weighted box filter of its 2x2
+ * children at level k (children in raster order), samples summed; each level-0 cell then
+ * answers queries with the finest of its level and its parents that holds at least tile_min
+ * samples, else the coarsest level if it holds any, else zero.
+ * READING: "box filtering of radiance samples" weights each child by its sample count; the
+ * levels are rebuilt from level 0 at every update, after the moving average. */
+static void prefilter_cells(const real *L0, const uint32_t *n0, uint32_t T, real *Lq)
+{
+    real Lv[4][NCELL][3];
+    uint32_t nv[4][NCELL];
+    for (int i = 0; i < NCELL; ++i) {
+        nv[0][i] = n0[i];
+        for (int k = 0; k < 3; ++k) Lv[0][i][k] = L0[3 * i + k];
+    }
+    for (int lv = 1; lv < 4; ++lv) {
+        int side = 8 >> lv;
+        for (int y = 0; y < side; ++y)
+            for (int x = 0; x < side; ++x) {
+                real ws[3] = {RC(0.0), RC(0.0), RC(0.0)};
+                uint32_t ns = 0;
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        int ch = (2 * y + dy) * (2 * side) + (2 * x + dx);
+                        real fn = (real)nv[lv - 1][ch];
+                        for (int k = 0; k < 3; ++k) ws[k] = ws[k] + fn * Lv[lv - 1][ch][k];
+                        ns += nv[lv - 1][ch];
+                    }
+                int o = y * side + x;
+                nv[lv][o] = ns;
+                for (int k = 0; k < 3; ++k) Lv[lv][o][k] = ns ? ws[k] / (real)ns : RC(0.0);
+            }
+    }
+    for (int i = 0; i < NCELL; ++i) {
+        int x = i & 7, y = i >> 3;
+        int pick = -1, o = 0;
+        for (int lv = 0; lv < 4; ++lv) {
+            o = (y >> lv) * (8 >> lv) + (x >> lv);
+            if (nv[lv][o] >= T) { pick = lv; break; }
+        }
+        if (pick < 0 && nv[3][0] > 0) { pick = 3; o = 0; }
+        for (int k = 0; k < 3; ++k) Lq[3 * i + k] = pick < 0 ? RC(0.0) : Lv[pick][o][k];
+    }
+}
+
+static void prefilter_tile(state *st, uint32_t s)
+{
+    size_t e = (size_t)s * NCELL;
+    prefilter_cells(st->L + 3 * e, st->nhist + e, st->cfg.tile_min, st->Lq + 3 * e);
+}
+
+void ORC(prefilter)(const real *L0, const uint32_t *n0, uint32_t T, real *Lq)
+{
+    /* test entry: one tile's 64 level-0 cells */
+    prefilter_cells(L0, n0, T, Lq);
+}
+
+static void cache_update(state *st)
+{
+    const orc_config *c = &st->cfg;
+    const size_t G = c->cache_tiles ? NCELL : 1;
     uint64_t live = 0;
     for (uint32_t s = 0; s < st->N; ++s) {
         if (st->fp[s] == 0u) continue;
-        uint32_t cnt = st->acc[4 * (size_t)s + 3];
-        if (cnt > 0) {
-            uint32_t h = st->nhist[s] < c->n_cap ? st->nhist[s] : c->n_cap;
-            real w = (real)cnt / (real)((double)h + (double)cnt);
-            for (int k = 0; k < 3; ++k) {
-#ifdef ORC_F64
-                real mean = st->dacc[3 * (size_t)s + k] / (double)cnt;
-#else
-                real mean = (float)((double)st->acc[4 * (size_t)s + k] / ((double)cnt * scale));
-#endif
-                real L = st->L[3 * (size_t)s + k];
-                st->L[3 * (size_t)s + k] = L + w * (mean - L);
-            }
-            uint64_t nh = (uint64_t)st->nhist[s] + cnt;
-            st->nhist[s] = nh < c->n_cap ? (uint32_t)nh : c->n_cap;
-        }
+        for (size_t i = 0; i < G; ++i) ema_entry(st, (size_t)s * G + i);
         if (st->accessed[s]) st->life[s] = c->max_life;
         else st->life[s] = st->life[s] - 1u;
         if (st->life[s] == 0u) {
             st->fp[s] = 0u;
             st->key[s] = 0u;
-            st->nhist[s] = 0u;
-            for (int k = 0; k < 3; ++k) st->L[3 * (size_t)s + k] = RC(0.0);
+            for (size_t i = 0; i < G; ++i) {
+                size_t e = (size_t)s * G + i;
+                st->nhist[e] = 0u;
+                for (int k = 0; k < 3; ++k) st->L[3 * e + k] = RC(0.0);
+                if (c->cache_tiles)
+                    for (int k = 0; k < 3; ++k) st->Lq[3 * e + k] = RC(0.0);
+            }
             st->stats[ST_EVICT]++;
         } else {
             ++live;
+            if (c->cache_tiles) prefilter_tile(st, s);
         }
-        for (int k = 0; k < 4; ++k) st->acc[4 * (size_t)s + k] = 0u;
-        for (int k = 0; k < 3; ++k) st->dacc[3 * (size_t)s + k] = 0.0;
+        for (size_t i = 0; i < G; ++i) {
+            size_t e = (size_t)s * G + i;
+            for (int k = 0; k < 4; ++k) st->acc[4 * e + k] = 0u;
+            for (int k = 0; k < 3; ++k) st->dacc[3 * e + k] = 0.0;
+        }
         st->accessed[s] = 0u;
     }
     st->stats[ST_LIVE] = live;
@@ -1751,7 +1867,7 @@ static void gather(state *st)
                 int32_t slot = st->r_slot[gid];
                 for (int k = 0; k < 3; ++k) {
                     real le = (fl & 0x200u) ? (real)m[3 + k] : RC(0.0);
-                    real lr = slot >= 0 ? st->L[3 * (size_t)slot + k] : RC(0.0);
+                    real lr = slot >= 0 ? cache_L(st)[3 * (size_t)slot + k] : RC(0.0);
                     v[k] = le + lr;
                 }
             }
@@ -2154,9 +2270,10 @@ void ORC(query)(const state *st, const real *pos, const real *nrm, uint32_t n, r
     for (uint32_t i = 0; i < n; ++i) {
         const real *p = pos + 4 * (size_t)i, *nn = nrm + 4 * (size_t)i;
         int with_leak = p[3] >= RC(0.0);
-        uint64_t key = cell_key(&st->cfg, st->cam, p, nn, with_leak ? p[3] : RC(0.0), with_leak);
-        int32_t slot = table_find(st, key);
-        for (int k = 0; k < 3; ++k) out[4 * (size_t)i + k] = slot >= 0 ? st->L[3 * (size_t)slot + k] : RC(0.0);
+        uint32_t tc;
+        uint64_t key = cell_key_cell(&st->cfg, st->cam, p, nn, with_leak ? p[3] : RC(0.0), with_leak, &tc);
+        int32_t slot = cache_entry(st, table_find(st, key), tc);
+        for (int k = 0; k < 3; ++k) out[4 * (size_t)i + k] = slot >= 0 ? cache_L(st)[3 * (size_t)slot + k] : RC(0.0);
         out[4 * (size_t)i + 3] = slot >= 0 ? RC(1.0) : RC(0.0);
     }
 }
@@ -2210,6 +2327,40 @@ uint32_t ORC(export_table)(const state *st, uint64_t *id, uint64_t *key, uint32_
         ++n;
     }
     return n;
+}
+
+/* live tiles in slot order: bucket*2^32|fp, key, life, and per cell acc[4], L[3], nhist and
+ * the query radiance Lq[3]; returns count */
+uint32_t ORC(export_tiles)(const state *st, uint64_t *id, uint64_t *key, uint32_t *life, uint32_t *acc, real *L,
+                           uint32_t *nhist, real *Lq, uint32_t cap)
+{
+    uint32_t n = 0;
+    if (!st->cfg.cache_tiles) return 0;
+    for (uint32_t s = 0; s < st->N; ++s) {
+        if (st->fp[s] == 0u) continue;
+        if (n < cap) {
+            id[n] = ((uint64_t)(s / BUCKET) << 32) | st->fp[s];
+            key[n] = st->key[s];
+            life[n] = st->life[s];
+            for (int i = 0; i < NCELL; ++i) {
+                size_t e = (size_t)s * NCELL + (size_t)i, o = (size_t)n * NCELL + (size_t)i;
+                for (int k = 0; k < 4; ++k) acc[4 * o + k] = st->acc[4 * e + k];
+                for (int k = 0; k < 3; ++k) L[3 * o + k] = st->L[3 * e + k];
+                for (int k = 0; k < 3; ++k) Lq[3 * o + k] = st->Lq[3 * e + k];
+                nhist[o] = st->nhist[e];
+            }
+        }
+        ++n;
+    }
+    return n;
+}
+
+/* keys and in-tile cells of caller hits (test entry) */
+void ORC(tile_keys)(const orc_config *c, const real *cam, const real *y, const real *n, const real *t, uint32_t cnt,
+                    uint64_t *keys, uint32_t *cells)
+{
+    for (uint32_t i = 0; i < cnt; ++i)
+        keys[i] = cell_key_cell(c, cam, y + 3 * (size_t)i, n + 3 * (size_t)i, t[i], 1, &cells[i]);
 }
 
 /* write a cell directly (tests of update / gather rules) */
