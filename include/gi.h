@@ -116,6 +116,17 @@ typedef struct gi_config {
      * inverse CDF) and a uniform point inside the cell.  The reconstruction is the history
      * of Algorithm 3 and the radiance of probes kept without tracing. */
     uint32_t ray_guiding;
+    /* 1: two-level world cache (Section 2.2.3; plain cache_mode only).  The hash table holds
+     * 2^table_log2 tiles instead of cells; a tile covers 8x8x8 cells of the descriptor's grid
+     * (position quantised, divided by 8) and stores 8x8 2D cells: the remainders modulo 8 of
+     * the two axes other than the main axis of the normal class.  Each update takes the
+     * moving average of every cell, rebuilds MIP levels 4x4, 2x2, 1x1 as sample-weighted
+     * means of 2x2 children, and every reader (probe rays, bounces, gi_cache_query) sees the
+     * finest of the cell's level and its parents holding at least tile_min_samples samples
+     * (else the coarsest level if it holds any).  Export with gi_tiles_export. */
+    uint32_t cache_tiles;
+    uint32_t tile_min_samples;
+    uint32_t reserved2[2];
 } gi_config;
 
 typedef struct gi_frame {
@@ -254,9 +265,18 @@ gi_status gi_learned_query(gi_context *ctx, const float *d_pos, const float *d_n
 
 /* ---- parity, resume and observability (host-synchronous, host pointers) --------------- */
 
+/* Two-level cache export (cache_tiles = 1; host-synchronous): the live tiles in slot order,
+ * at most cap of them; id = bucket << 32 | fingerprint, key = tile descriptor, life, and per
+ * cell (64 per tile, [n][64][...]) the fixed-point sums and count of this frame, the moving
+ * average, its sample count and the prefiltered radiance that readers see.  Any output
+ * pointer may be null.  GI_ERR_UNSUPPORTED without tiles. */
+gi_status gi_tiles_export(gi_context *ctx, uint64_t *h_id, uint64_t *h_key, uint32_t *h_life, uint32_t *h_acc,
+                          float *h_L, uint32_t *h_nhist, float *h_Lq, uint32_t cap, uint32_t *n_out);
+
 /* Live cells in slot order: id = bucket << 32 | fingerprint, key (descriptor bits), acc
  * [n][4] (fixed-point r,g,b sums and count of the current frame), L [n][3] cached radiance,
- * nhist, life.  Writes at most cap cells; *n_out = number of live cells. */
+ * nhist, life.  Writes at most cap cells; *n_out = number of live cells.
+ * GI_ERR_UNSUPPORTED with cache_tiles (see gi_tiles_export); so are save and load. */
 gi_status gi_cache_export(gi_context *ctx, uint64_t *h_id, uint64_t *h_key, uint32_t *h_acc,
                           float *h_L, uint32_t *h_nhist, uint32_t *h_life, uint32_t cap,
                           uint32_t *n_out);

@@ -34,7 +34,7 @@ class OrcConfig(C.Structure):
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4),
                 ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32),
-                ("cache_tiles", C.c_uint32), ("tile_min", C.c_uint32), ("pad5", C.c_uint32), ("pad6", C.c_uint32),
+                ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32), ("pad5", C.c_uint32), ("pad6", C.c_uint32),
                 ("pad7", C.c_uint32)]
 
 
@@ -48,7 +48,7 @@ def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
-               temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min=16)
+               temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min_samples=16)
     cfg.update(kw)
     return cfg
 

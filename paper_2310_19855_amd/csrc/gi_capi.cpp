@@ -217,6 +217,8 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->tab.L);
   dfree(c->tab.meta);
   dfree(c->tab.accessed);
+  dfree(c->tab.cn);
+  dfree(c->tab.Lq);
   dfree(c->d_stats);
   dfree(c->d_hit_ids);
   dfree(c->d_hit_count);
@@ -255,6 +257,9 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->upscale > 1 && !g->temporal) { why = "upscale > 1 needs temporal = 1"; return GI_ERR_INVALID_ARG; }
   if (g->ray_guiding > 1) { why = "ray_guiding must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   if (g->ray_guiding && !g->temporal) { why = "ray_guiding needs temporal = 1"; return GI_ERR_INVALID_ARG; }
+  if (g->cache_tiles > 1) { why = "cache_tiles must be 0 or 1"; return GI_ERR_INVALID_ARG; }
+  if (g->cache_tiles && g->cache_mode != GI_CACHE_PLAIN) { why = "cache_tiles needs the plain cache"; return GI_ERR_INVALID_ARG; }
+  if (g->cache_tiles && g->table_log2 > 22) { why = "cache_tiles: table_log2 (tiles) out of [6, 22]"; return GI_ERR_INVALID_ARG; }
   return GI_OK;
 }
 
@@ -346,8 +351,13 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
   A(dalloc(&c->d_sh, (size_t)c->P * 28));
   A(dalloc(&c->tab.fp, c->N));
   A(dalloc(&c->tab.key, c->N));
-  A(dalloc(&c->tab.acc, c->N));
-  A(dalloc(&c->tab.L, c->N));
+  const size_t NC = (size_t)c->N * (cfg->cache_tiles ? 64u : 1u);   // cells
+  A(dalloc(&c->tab.acc, NC));
+  A(dalloc(&c->tab.L, NC));
+  if (cfg->cache_tiles) {
+    A(dalloc(&c->tab.cn, NC));
+    A(dalloc(&c->tab.Lq, NC));
+  }
   A(dalloc(&c->tab.meta, c->N));
   A(dalloc(&c->tab.accessed, c->N));
   A(dalloc(&c->d_stats, (size_t)GI_STAT_COUNT * gi::kStatStripesHost));
@@ -362,8 +372,12 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
   if (e == hipSuccess) {
     A(hipMemset(c->tab.fp, 0, 4 * (size_t)c->N));
     A(hipMemset(c->tab.key, 0, 8 * (size_t)c->N));
-    A(hipMemset(c->tab.acc, 0, 16 * (size_t)c->N));
-    A(hipMemset(c->tab.L, 0, 16 * (size_t)c->N));
+    A(hipMemset(c->tab.acc, 0, 16 * NC));
+    A(hipMemset(c->tab.L, 0, 16 * NC));
+    if (cfg->cache_tiles) {
+      A(hipMemset(c->tab.cn, 0, 4 * NC));
+      A(hipMemset(c->tab.Lq, 0, 16 * NC));
+    }
     A(hipMemset(c->tab.meta, 0, 8 * (size_t)c->N));
     A(hipMemset(c->tab.accessed, 0, 4 * (size_t)c->N));
     A(hipMemset(c->d_stats, 0, 8 * (size_t)GI_STAT_COUNT * gi::kStatStripesHost));
@@ -739,9 +753,66 @@ gi_status gi_learned_query(gi_context* c, const float* pos, const float* nrm, ui
 
 // ---- exports ------------------------------------------------------------------------------
 
+gi_status gi_tiles_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, uint32_t* h_life, uint32_t* h_acc,
+                          float* h_L, uint32_t* h_nhist, float* h_Lq, uint32_t cap, uint32_t* n_out) {
+  if (!c || !n_out) return GI_ERR_INVALID_ARG;
+  if (!c->cfg.cache_tiles) return fail(c, GI_ERR_UNSUPPORTED, "gi_tiles_export needs cache_tiles = 1");
+  try {
+    GI_TRY_HIP(c, hipDeviceSynchronize());
+    const size_t N = c->N, NC = N * 64;
+    std::vector<uint32_t> fp(N), cn(NC);
+    std::vector<uint64_t> key(N);
+    std::vector<uint2> meta(N);
+    std::vector<uint4> acc(NC);
+    std::vector<float4> L(NC), Lq(NC);
+    GI_TRY_HIP(c, hipMemcpy(fp.data(), c->tab.fp, 4 * N, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(key.data(), c->tab.key, 8 * N, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(meta.data(), c->tab.meta, 8 * N, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(acc.data(), c->tab.acc, 16 * NC, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(L.data(), c->tab.L, 16 * NC, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(cn.data(), c->tab.cn, 4 * NC, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(Lq.data(), c->tab.Lq, 16 * NC, hipMemcpyDeviceToHost));
+    uint32_t n = 0;
+    for (size_t s = 0; s < N; ++s) {
+      if (!fp[s]) continue;
+      if (n < cap) {
+        if (h_id) h_id[n] = ((uint64_t)(s / gi::kBucketSlots) << 32) | fp[s];
+        if (h_key) h_key[n] = key[s];
+        if (h_life) h_life[n] = meta[s].y;
+        for (size_t i = 0; i < 64; ++i) {
+          const size_t e = s * 64 + i, o = (size_t)n * 64 + i;
+          if (h_acc) {
+            h_acc[4 * o] = acc[e].x;
+            h_acc[4 * o + 1] = acc[e].y;
+            h_acc[4 * o + 2] = acc[e].z;
+            h_acc[4 * o + 3] = acc[e].w;
+          }
+          if (h_L) {
+            h_L[3 * o] = L[e].x;
+            h_L[3 * o + 1] = L[e].y;
+            h_L[3 * o + 2] = L[e].z;
+          }
+          if (h_nhist) h_nhist[o] = cn[e];
+          if (h_Lq) {
+            h_Lq[3 * o] = Lq[e].x;
+            h_Lq[3 * o + 1] = Lq[e].y;
+            h_Lq[3 * o + 2] = Lq[e].z;
+          }
+        }
+      }
+      ++n;
+    }
+    *n_out = n;
+    return GI_OK;
+  } catch (const std::exception& ex) {
+    return fail(c, GI_ERR_INTERNAL, ex.what());
+  }
+}
+
 gi_status gi_cache_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, uint32_t* h_acc, float* h_L,
                           uint32_t* h_nhist, uint32_t* h_life, uint32_t cap, uint32_t* n_out) {
   if (!c || !n_out) return GI_ERR_INVALID_ARG;
+  if (c->cfg.cache_tiles) return fail(c, GI_ERR_UNSUPPORTED, "two-level cache: use gi_tiles_export");
   try {
     GI_TRY_HIP(c, hipDeviceSynchronize());
     const size_t N = c->N;
@@ -786,6 +857,7 @@ gi_status gi_cache_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, uint32
 
 gi_status gi_cache_save(gi_context* c, void* blob, size_t cap, size_t* size_out) {
   if (!c || !size_out) return GI_ERR_INVALID_ARG;
+  if (c->cfg.cache_tiles) return fail(c, GI_ERR_UNSUPPORTED, "two-level cache: use gi_tiles_export");
   const size_t N = c->N;
   const size_t bytes = 16 + N * (4 + 8 + 16 + 16 + 8 + 4);
   *size_out = bytes;
@@ -807,6 +879,7 @@ gi_status gi_cache_save(gi_context* c, void* blob, size_t cap, size_t* size_out)
 
 gi_status gi_cache_load(gi_context* c, const void* blob, size_t size) {
   if (!c || !blob) return GI_ERR_INVALID_ARG;
+  if (c->cfg.cache_tiles) return fail(c, GI_ERR_UNSUPPORTED, "two-level cache: use gi_tiles_export");
   const size_t N = c->N;
   const size_t bytes = 16 + N * (4 + 8 + 16 + 16 + 8 + 4);
   if (size != bytes) return fail(c, GI_ERR_INVALID_ARG, "blob size does not match this config");

@@ -168,20 +168,32 @@ __device__ inline uint32_t cell_lod(float S, float lod_scale, float cx, float cy
   return lod;
 }
 
+// Two-level cache (Section 2.2.3): with `tiled` the descriptor names a tile of 8x8x8 cells
+// (quantised position >> 3, a floor division) and `tcell` is the hit's 2D cell inside it:
+// 8 (v & 7) + (u & 7), u and v the quantised coordinates along the two axes other than the
+// main axis of the normal class, u the lower-numbered one.
 __device__ inline uint64_t descriptor(float S0, uint32_t leak_on, float lod_scale, float cx, float cy, float cz,
                                       float yx, float yy, float yz, float nx, float ny, float nz, float t,
-                                      bool with_leak) {
+                                      bool with_leak, uint32_t tiled, uint32_t& tcell) {
   const uint32_t lod = cell_lod(S0, lod_scale, cx, cy, cz, yx, yy, yz);
   const float S = S0 * (1.0f / (float)(1u << lod));
-  const int32_t qx = (int32_t)floorf(yx * S);
-  const int32_t qy = (int32_t)floorf(yy * S);
-  const int32_t qz = (int32_t)floorf(yz * S);
+  int32_t qx = (int32_t)floorf(yx * S);
+  int32_t qy = (int32_t)floorf(yy * S);
+  int32_t qz = (int32_t)floorf(yz * S);
   const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
   uint32_t axis = 0;
   float best = ax;
   float comp = nx;
   if (ay > best) { axis = 1; best = ay; comp = ny; }
   if (az > best) { axis = 2; comp = nz; }
+  tcell = 0u;
+  if (tiled) {
+    const int32_t u = axis == 0u ? qy : qx, v = axis == 2u ? qy : qz;
+    tcell = 8u * (uint32_t)(v & 7) + (uint32_t)(u & 7);
+    qx >>= 3;
+    qy >>= 3;
+    qz >>= 3;
+  }
   const uint64_t cls = 2u * axis + (comp < 0.0f ? 1u : 0u);
   const uint64_t leak = (with_leak && leak_on && t * S < 1.0f) ? 1u : 0u;
   return ((uint64_t)((uint32_t)qx & 0x3FFFFu)) | ((uint64_t)((uint32_t)qy & 0x3FFFFu) << 18) |

@@ -558,7 +558,13 @@ struct CacheArgs {
   float sky[3];
   float lod_scale;     // levels of detail of the descriptor (0 = one level)
   float cam[3];        // camera of the frame's spawn
+  uint32_t tiled;      // two-level cache: slots are tiles of 64 cells, L is the prefiltered radiance
 };
+
+// world-cache entry of a hit: its slot, or with tiles slot * 64 + cell inside the tile
+__device__ inline int32_t cache_entry(const CacheArgs& c, int32_t slot, uint32_t tcell) {
+  return slot < 0 ? slot : (c.tiled ? slot * 64 + (int32_t)tcell : slot);
+}
 
 __device__ inline int32_t table_lookup(const CacheArgs& c, uint64_t key) {
   const uint32_t b = bucket_of(key, c.bucket_mask), f = fingerprint_of(key);
@@ -690,18 +696,20 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float sg = dn > 0.0f ? -1.0f : 1.0f;
   const float yx = ox + t * dx, yy = oy + t * dy, yz = oz + t * dz;
   const float nx = sg * n.x, ny = sg * n.y, nz = sg * n.z;
+  uint32_t tcell;
   const uint64_t key = descriptor(c.cell_scale, c.leak_bit, c.lod_scale, c.cam[0], c.cam[1], c.cam[2], yx, yy, yz, nx,
-                                  ny, nz, t, true);
+                                  ny, nz, t, true, c.tiled, tcell);
   rkey[gid] = make_uint2((uint32_t)key, (uint32_t)(key >> 32));
   if (lo.hitpos) {
     lo.hitpos[gid] = make_float4(yx, yy, yz, t);
     lo.hitnrm[gid] = make_float4(nx, ny, nz, 0.0f);
   }
   bool inserted;
-  const int32_t slot = table_insert(c, key, inserted);
+  const int32_t tslot = table_insert(c, key, inserted);
   stat_add(stats, GI_STAT_INSERTS, inserted);
-  stat_add(stats, GI_STAT_OVERFLOW, slot < 0);
-  if (slot >= 0) c.accessed[slot] = 1u;
+  stat_add(stats, GI_STAT_OVERFLOW, tslot < 0);
+  if (tslot >= 0) c.accessed[tslot] = 1u;
+  const int32_t slot = cache_entry(c, tslot, tcell);
 
   // one light sample: area-proportional emitter, uniform point, one shadow ray
   const float eps = origin_offset(a.eps_scale, yx, yy, yz);
@@ -740,13 +748,14 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
       const float4 bn = st.tnrm[btri];
       const float bdn = (bn.x * bx + bn.y * by) + bn.z * bz;
       const float bs = bdn > 0.0f ? -1.0f : 1.0f;
+      uint32_t btcell;
       const uint64_t bkey = descriptor(c.cell_scale, c.leak_bit, c.lod_scale, c.cam[0], c.cam[1], c.cam[2],
                                        px + bt * bx, py + bt * by, pz + bt * bz,
-                                       bs * bn.x, bs * bn.y, bs * bn.z, bt, true);
+                                       bs * bn.x, bs * bn.y, bs * bn.z, bt, true, c.tiled, btcell);
       const int32_t bslot = table_lookup(c, bkey);
       if (bslot >= 0) {
         c.accessed[bslot] = 1u;
-        const float4 lv = c.L[bslot];
+        const float4 lv = c.L[cache_entry(c, bslot, btcell)];
         Lb0 = lv.x; Lb1 = lv.y; Lb2 = lv.z;
       }
     }
@@ -1281,14 +1290,112 @@ __global__ __launch_bounds__(64 * WAVES) void k_interpolate(const float4* gpos, 
 // ------------------------------------------------------------------------------------------
 // Lookup-only query for caller points
 // ------------------------------------------------------------------------------------------
+// ------------------------------------------------------------------------------------------
+// Two-level cache update (Section 2.2.3): one wave per tile, lane = cell.  Each cell's moving
+// average as in k_cache_update; the tile's life and eviction; then MIP levels 4x4, 2x2, 1x1
+// as sample-weighted means of their 2x2 children (children in raster order) in LDS, and each
+// cell's radiance for readers from the finest of its level and its parents that holds at
+// least tile_min samples, else the coarsest level if it holds any, else zero.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_cache_update_tiles(uint32_t* fp, uint64_t* key, uint4* acc, float4* L,
+                                                           uint32_t* cn, float4* Lq, uint2* meta, uint32_t* accessed,
+                                                           uint32_t n_cap, uint32_t max_life, uint32_t frac_bits,
+                                                           uint32_t tile_min, unsigned long long* stats) {
+  __shared__ float lv[85][3];   // level 0 at 0..63, level 1 at 64..79, level 2 at 80..83, level 3 at 84
+  __shared__ uint32_t nv[85];
+  const uint32_t s = blockIdx.x, lane = threadIdx.x;
+  if (fp[s] == 0u) return;
+  const size_t e = (size_t)s * 64 + lane;
+  const uint4 a = acc[e];
+  float4 l = L[e];
+  uint32_t nh = cn[e];
+  if (a.w > 0u) {
+    const uint32_t h = nh < n_cap ? nh : n_cap;
+    const float w = (float)a.w / (float)((double)h + (double)a.w);
+    const double den = (double)a.w * (double)(1u << frac_bits);
+    const float m0 = (float)((double)a.x / den);
+    const float m1 = (float)((double)a.y / den);
+    const float m2 = (float)((double)a.z / den);
+    l.x = l.x + w * (m0 - l.x);
+    l.y = l.y + w * (m1 - l.y);
+    l.z = l.z + w * (m2 - l.z);
+    const uint64_t t = (uint64_t)nh + a.w;
+    nh = t < n_cap ? (uint32_t)t : n_cap;
+  }
+  acc[e] = make_uint4(0u, 0u, 0u, 0u);
+  const uint32_t life = accessed[s] ? max_life : meta[s].y - 1u;
+  unsigned long long* st = stats + (s % kStatStripes) * GI_STAT_COUNT;
+  if (life == 0u) {
+    L[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    cn[e] = 0u;
+    Lq[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane == 0u) {
+      fp[s] = 0u;
+      key[s] = 0u;
+      meta[s] = make_uint2(0u, 0u);
+      accessed[s] = 0u;
+      atomicAdd(&st[GI_STAT_EVICT], 1ull);
+    }
+    return;
+  }
+  L[e] = l;
+  cn[e] = nh;
+  if (lane == 0u) {
+    meta[s] = make_uint2(0u, life);
+    accessed[s] = 0u;
+    atomicAdd(&st[GI_STAT_LIVE], 1ull);
+  }
+  lv[lane][0] = l.x;
+  lv[lane][1] = l.y;
+  lv[lane][2] = l.z;
+  nv[lane] = nh;
+  __syncthreads();
+  // level k + 1 entry j (side 8 >> (k+1)) from level k (side 8 >> k)
+  const uint32_t base[4] = {0u, 64u, 80u, 84u};
+#pragma unroll
+  for (uint32_t k = 0; k < 3; ++k) {
+    const uint32_t side = 8u >> (k + 1u);
+    if (lane < side * side) {
+      const uint32_t x = lane % side, y = lane / side;
+      float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+      uint32_t ns = 0u;
+#pragma unroll
+      for (uint32_t c = 0; c < 4; ++c) {
+        const uint32_t ch = base[k] + (2u * y + (c >> 1)) * (2u * side) + (2u * x + (c & 1u));
+        const float fn = (float)nv[ch];
+        w0 = w0 + fn * lv[ch][0];
+        w1 = w1 + fn * lv[ch][1];
+        w2 = w2 + fn * lv[ch][2];
+        ns += nv[ch];
+      }
+      const uint32_t o = base[k + 1u] + lane;
+      nv[o] = ns;
+      lv[o][0] = ns ? w0 / (float)ns : 0.0f;
+      lv[o][1] = ns ? w1 / (float)ns : 0.0f;
+      lv[o][2] = ns ? w2 / (float)ns : 0.0f;
+    }
+    __syncthreads();
+  }
+  const uint32_t x = lane & 7u, y = lane >> 3;
+  int32_t pick = -1;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint32_t o = base[k] + (y >> k) * (8u >> k) + (x >> k);
+    if (pick < 0 && nv[o] >= tile_min) pick = (int32_t)o;
+  }
+  if (pick < 0 && nv[84] > 0u) pick = 84;
+  Lq[e] = pick < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(lv[pick][0], lv[pick][1], lv[pick][2], 0.f);
+}
+
 __global__ void k_query(const float4* pos, const float4* nrm, uint32_t n, CacheArgs c, float4* out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = pos[i], q = nrm[i];
   const bool wl = p.w >= 0.0f;
+  uint32_t tcell;
   const uint64_t key = descriptor(c.cell_scale, c.leak_bit, c.lod_scale, c.cam[0], c.cam[1], c.cam[2], p.x, p.y, p.z,
-                                  q.x, q.y, q.z, wl ? p.w : 0.0f, wl);
-  const int32_t s = table_lookup(c, key);
+                                  q.x, q.y, q.z, wl ? p.w : 0.0f, wl, c.tiled, tcell);
+  const int32_t s = cache_entry(c, table_lookup(c, key), tcell);
   if (s < 0) {
     out[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   } else {
@@ -1439,8 +1546,9 @@ static CacheArgs cache_args(const gi_context* c) {
   a.fp = c->tab.fp;
   a.key = c->tab.key;
   a.acc = c->tab.acc;
-  a.L = c->tab.L;
+  a.L = c->cfg.cache_tiles ? c->tab.Lq : c->tab.L;
   a.accessed = c->tab.accessed;
+  a.tiled = c->cfg.cache_tiles;
   a.bucket_mask = c->N / kBucket - 1u;
   a.cell_scale = c->cfg.cell_scale;
   a.leak_bit = c->cfg.leak_bit;
@@ -1578,14 +1686,18 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
 }
 
 hipError_t launch_update(gi_context* c, hipStream_t s) {
-  GI_TIMED(c, "cache_update", s, (k_cache_update<<<blocks(c->N, 256), 256, 0, s>>>(c->N, c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->d_stats)));
+  if (c->cfg.cache_tiles) {
+    GI_TIMED(c, "cache_update_tiles", s, (k_cache_update_tiles<<<c->N, 64, 0, s>>>(c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.cn, c->tab.Lq, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->cfg.tile_min_samples, c->d_stats)));
+  } else {
+    GI_TIMED(c, "cache_update", s, (k_cache_update<<<blocks(c->N, 256), 256, 0, s>>>(c->N, c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->d_stats)));
+  }
   if (c->learned && c->cfg.cache_mode != GI_CACHE_PLAIN) {
     // the surrogate's radiance at every hit, then the judge against confident plain cells
     const hipError_t e = learned_infer_rays(c, s);
     if (e != hipSuccess) return e;
   }
   const uint32_t filt = c->cfg.probe_filter;
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->cfg.cache_tiles ? c->tab.Lq : c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
   if (filt) {
     // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
     const MipInfo mi = mip_info(c);

@@ -43,7 +43,8 @@ class Config(C.Structure):
                 ("mlp_loss_scale", C.c_float), ("mlp_judge", C.c_float),
                 ("scene_min", C.c_float * 4), ("scene_max", C.c_float * 4),
                 ("lod_scale", C.c_float), ("temporal", C.c_uint32), ("upscale", C.c_uint32),
-                ("ray_guiding", C.c_uint32)]
+                ("ray_guiding", C.c_uint32), ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32),
+                ("reserved2", C.c_uint32 * 2)]
 
 
 class Frame(C.Structure):
@@ -56,7 +57,7 @@ DEFAULTS = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces
                 max_life=32, n_cap=256, seed=3, frac_bits=12, cache_mode=CACHE_PLAIN,
                 cell_scale=10.0, r_max=64.0, eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0),
                 mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4,
-                mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_loss_scale=128.0, mlp_judge=0.1)
+                mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_loss_scale=128.0, mlp_judge=0.1, tile_min_samples=16)
 
 _lib = None
 
@@ -84,6 +85,7 @@ def lib():
     fn("gi_last_error", C.c_char_p, vp)
     fn("gi_build_bvh", st, vp, vp, u32, vp, u32, vp, vp, u32)
     fn("gi_bvh_build_host", st, vp, u32, vp, u32, vp, u32, P(u32), P(u32), P(u32))
+    fn("gi_tiles_export", st, vp, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
     fn("gi_set_dynamic_triangles", st, vp, vp, vp, u32, vp)
     fn("gi_render_gbuffer", st, vp, P(Frame), vp, vp, vp, vp, vp)
     fn("gi_spawn_probes", st, vp, P(Frame), vp, vp, vp, vp)
@@ -334,6 +336,26 @@ class Context:
         order = np.argsort(ident[:k], kind="stable")
         return dict(id=ident[:k][order], key=key[:k][order], acc=acc[:k][order], L=L[:k][order],
                     nhist=nh[:k][order], life=life[:k][order])
+
+    def tiles(self):
+        """two-level cache (cache_tiles = 1): live tiles sorted by (bucket, fingerprint) with
+        per-cell sums, moving averages, sample counts and prefiltered radiance"""
+        N = int(self.dims()[2])
+        ident = np.zeros(N, np.uint64)
+        key = np.zeros(N, np.uint64)
+        life = np.zeros(N, np.uint32)
+        acc = np.zeros((N, 64, 4), np.uint32)
+        L = np.zeros((N, 64, 3), np.float32)
+        nh = np.zeros((N, 64), np.uint32)
+        Lq = np.zeros((N, 64, 3), np.float32)
+        n = C.c_uint32()
+        self._check(lib().gi_tiles_export(self.h, ident.ctypes.data, key.ctypes.data, life.ctypes.data,
+                                          acc.ctypes.data, L.ctypes.data, nh.ctypes.data, Lq.ctypes.data, N,
+                                          C.byref(n)), "gi_tiles_export")
+        k = n.value
+        o = np.argsort(ident[:k], kind="stable")
+        return dict(id=ident[:k][o], key=key[:k][o], life=life[:k][o], acc=acc[:k][o], L=L[:k][o],
+                    nhist=nh[:k][o], Lq=Lq[:k][o])
 
     def cache_save(self) -> bytes:
         n = C.c_size_t()

@@ -59,7 +59,8 @@ def _run_stage_parity(scene, cfg, frames, check_every=True, camera=None):
         hit = (orr["cell"] & gi.RAY_HIT) != 0
         assert np.array_equal(gr["key"][hit], orr["key"][hit]), "cell keys differ"
         assert np.array_equal(gr["slot"] >= 0, orr["slot"] >= 0)
-        gt, ot = pr.ctx.table(), pr.ost.table()
+        tiled = cfg.get("cache_tiles", 0)
+        gt, ot = (pr.ctx.tiles(), pr.ost.tiles()) if tiled else (pr.ctx.table(), pr.ost.table())
         _compare_table(gt, ot)
         gs, os_ = pr.ctx.stats(), pr.ost.stats()
         for k in ("rays", "hits", "inserts", "overflow", "nonfinite", "wraps", "shadow", "occluded", "bounce"):
@@ -67,10 +68,12 @@ def _run_stage_parity(scene, cfg, frames, check_every=True, camera=None):
         # update + gather + SH
         pr.ctx.cache_update(fr)
         pr.ost.update(fr)
-        gt, ot = pr.ctx.table(), pr.ost.table()
+        gt, ot = (pr.ctx.tiles(), pr.ost.tiles()) if tiled else (pr.ctx.table(), pr.ost.table())
         assert np.array_equal(gt["id"], ot["id"])
         assert np.array_equal(gt["nhist"], ot["nhist"]) and np.array_equal(gt["life"], ot["life"])
         assert_close(gt["L"], ot["L"], what="cached radiance")
+        if tiled:
+            assert_close(gt["Lq"], ot["Lq"], what="prefiltered radiance")
         gpr, opr = pr.ctx.probes(), pr.ost.probes()
         # radiance and travelled distance apart (a miss records 1e4 m, which would set the
         # floor of a joint comparison far above the radiance values)
@@ -264,6 +267,43 @@ def test_ray_guiding_upscale_orbit_and_filter():
                                     upscale=2, ray_guiding=1, probe_filter=1), [0, 1, 2, 3])
     recon, cdf = pr.ost.guiding()
     assert (cdf[:, 63] > 0).sum() > 50
+
+
+def test_two_level_cache_room_frames_ragged():
+    """the two-level world cache (Section 2.2.3) on a ragged 100x76 room, two bounces (bounce
+    lookups read the prefiltered radiance), four frames with eviction (max_life 2): tile ids,
+    keys and per-cell fixed-point sums bit-exact, per-cell moving averages, sample counts, tile
+    lives, the prefiltered radiance of every cell, atlas, SH and irradiance"""
+    pr = _run_stage_parity(I.room_scene(), dict(width=100, height=76, rays_per_probe=33, table_log2=10, bounces=2,
+                                                max_life=2, n_cap=16, cache_tiles=1, tile_min_samples=8),
+                           [0, 1, 2, 3])
+    t = pr.ctx.tiles()
+    assert len(t["id"]) > 10 and pr.ctx.stats()["overflow"] == 0
+    # cells below the threshold read a coarser level
+    few = (t["nhist"] > 0) & (t["nhist"] < 8)
+    assert few.any() and not np.allclose(t["Lq"][few], t["L"][few])
+
+
+def test_two_level_cache_field_levels_of_detail_and_query():
+    """tiles on the field with levels of detail, the moving light and temporal reuse, two
+    frames; then lookup-only queries at visible surface points read the prefiltered cells"""
+    sc = I.field_scene()
+    cfg = dict(width=160, height=96, rays_per_probe=64, table_log2=14, sky=sc.sky, cache_tiles=1,
+               tile_min_samples=16, lod_scale=0.05, temporal=1)
+    pr = _run_stage_parity(sc, cfg, [0, 1])
+    (gp, gn, ga, gprim), _ = pr.gbuffer(I.camera_for(sc.name, 1))
+    hit = gprim.reshape(-1) != 0xFFFFFFFF
+    pos = gp.reshape(-1, 4)[hit][::7].copy()
+    nrm = gn.reshape(-1, 4)[hit][::7].copy()
+    pos[:, 3] = -1.0
+    import torch
+    out = torch.zeros((len(pos), 4), dtype=torch.float32, device="cuda")
+    pr.ctx.cache_query(torch.from_numpy(pos).cuda(), torch.from_numpy(nrm).cuda(), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = pr.ost.query(pos, nrm)
+    assert np.array_equal(got[:, 3], want[:, 3]) and got[:, 3].sum() > 0.5 * len(pos)
+    assert_close(got[:, :3], want[:, :3], what="queried prefiltered radiance")
 
 
 def test_room_overflowing_table_invariants():
@@ -508,3 +548,9 @@ def test_invalid_arguments_and_frame_order():
         gi.Context(width=64, height=64, temporal=1, upscale=5)
     with pytest.raises(gi.GIError, match="INVALID"):
         gi.Context(width=64, height=64, ray_guiding=1)      # guiding needs temporal reuse
+    with pytest.raises(gi.GIError, match="INVALID"):
+        gi.Context(width=64, height=64, cache_tiles=1, cache_mode=gi.CACHE_MLP_BF16)   # tiles: plain cache only
+    ctx = gi.Context(width=64, height=64, cache_tiles=1, table_log2=8)
+    with pytest.raises(gi.GIError, match="UNSUPPORTED"):
+        ctx.table()                                          # per-cell export of the single-level cache
+    ctx.close()

@@ -120,7 +120,7 @@ def test_furnace_one_bounce_with_tiles(furnace):
     fr = I.furnace_camera(0)
     g = osc.gbuffer(fr, 64, 64)
     st = O.OracleFrameState(osc, O.default_config(width=64, height=64, rays_per_probe=64, table_log2=14,
-                                                   cell_scale=2.0, cache_tiles=1, tile_min=4))
+                                                   cell_scale=2.0, cache_tiles=1, tile_min_samples=4))
     st.spawn(fr, g[0], g[1], g[3])
     st.trace(fr)
     t = st.tiles()
@@ -151,9 +151,9 @@ def test_furnace_feedback_with_tiles(furnace):
     g = osc.gbuffer(fr, 64, 64)
     st = O.OracleFrameState(osc, O.default_config(width=64, height=64, rays_per_probe=64, table_log2=14,
                                                    cell_scale=0.5, n_cap=0, leak_bit=0, bounces=2, cache_tiles=1,
-                                                   tile_min=0))
+                                                   tile_min_samples=0))
     # n_cap = 0 keeps no history (each update takes the frame's mean and counts no samples), so
-    # the levels are reached with tile_min = 0: every cell answers with its own value
+    # the levels are reached with tile_min_samples = 0: every cell answers with its own value
     rho, le = 0.8, 1.0
     L = 0.0
     for f in range(8):
