@@ -256,7 +256,9 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-FORMS = {"plain": 0, "plain_lod": 0, "mlp_bf16": 1, "mlp_fp8": 2}
+FORMS = {"plain": 0, "plain_lod": 0, "plain_tiles": 0, "plain_lod_tiles": 0, "mlp_bf16": 1, "mlp_fp8": 2}
+# two-level cache forms: 2^16 tiles of 64 cells, queries from the finest level with 16 samples
+TILES_CFG = dict(cache_tiles=1, table_log2=16, tile_min_samples=16)
 MLP_CFG = dict(mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4, mlp_lr_grid=1e-2,
                mlp_lr_mlp=1e-2, mlp_judge=0.5)
 SWEEP_R = (8, 16, 32, 64, 128)
@@ -276,10 +278,12 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
     cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, cache_mode=FORMS[form])
     if form in ("mlp_bf16", "mlp_fp8"):
         cfg.update(MLP_CFG)
-    if form == "plain_lod":
+    if form in ("plain_lod", "plain_lod_tiles"):
         # levels of detail that follow Algorithm 6's adaptive cell size of this view
         fov = I.camera_for(scene_name, 0).fov_y
         cfg["lod_scale"] = math.tan(fov * 8.0 * max(1.0 / H, H / (W * W)))
+    if form in ("plain_tiles", "plain_lod_tiles"):
+        cfg.update(TILES_CFG)
     cfg.update(extra or {})
     ctx = gi.Context(**cfg)
     ctx.build_bvh(scene)
@@ -439,7 +443,10 @@ def field4k_and_furnace(log, W=3840, H=2160, R=64):
                                   f"(limit 5 pi); relMAE of the last frame's irradiance over pixels with a probe")
     for form in FORMS:
         r = run_form("furnace", fsc, fp["width"], fp["height"], fp["rays_per_probe"], form, frames, frames - 8,
-                     extra=dict(bounces=2, n_cap=0, cell_scale=0.5, leak_bit=0), want_out=True)
+                     extra=dict(bounces=2, n_cap=0, cell_scale=0.5, leak_bit=0,
+                                # no history (n_cap 0) counts no samples: tiles answer from level 0
+                                **({"tile_min_samples": 0} if "tiles" in form else {})),
+                     want_out=True)
         o = r["out"]
         ok = o[..., 3] != 2
         e = float(np.abs(o[ok][:, :3].astype(np.float64) - E).sum() / (E * 3 * max(int(ok.sum()), 1)))

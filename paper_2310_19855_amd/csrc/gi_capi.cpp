@@ -780,7 +780,7 @@ gi_status gi_tiles_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, uint32
         if (h_key) h_key[n] = key[s];
         if (h_life) h_life[n] = meta[s].y;
         for (size_t i = 0; i < 64; ++i) {
-          const size_t e = s * 64 + i, o = (size_t)n * 64 + i;
+          const size_t e = i * N + s, o = (size_t)n * 64 + i;   // cell-major on the device
           if (h_acc) {
             h_acc[4 * o] = acc[e].x;
             h_acc[4 * o + 1] = acc[e].y;

@@ -23,9 +23,10 @@ struct Table {
   float4* L = nullptr;           // cached outgoing radiance (rgb)
   uint2* meta = nullptr;         // (history samples, life)
   uint32_t* accessed = nullptr;  // touched this frame
-  // two-level cache (config cache_tiles): slots are tiles; acc and L are per cell [N*64]
-  uint32_t* cn = nullptr;        // [N*64] history samples of each cell
-  float4* Lq = nullptr;          // [N*64] prefiltered radiance the readers see
+  // two-level cache (config cache_tiles): slots are tiles; acc and L are per cell [64][N]
+  // (cell-major: entry = cell * N + slot)
+  uint32_t* cn = nullptr;        // [64][N] history samples of each cell
+  float4* Lq = nullptr;          // [64][N] prefiltered radiance the readers see
 };
 
 struct LearnedState;  // learned surrogate (gi_learned.hip)

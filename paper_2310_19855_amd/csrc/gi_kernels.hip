@@ -559,11 +559,15 @@ struct CacheArgs {
   float lod_scale;     // levels of detail of the descriptor (0 = one level)
   float cam[3];        // camera of the frame's spawn
   uint32_t tiled;      // two-level cache: slots are tiles of 64 cells, L is the prefiltered radiance
+  uint32_t n_slots;    // table slots (tiles)
 };
 
-// world-cache entry of a hit: its slot, or with tiles slot * 64 + cell inside the tile
+// World-cache entry of a hit: its slot, or with tiles cell * n_slots + slot.  Cell-major: the
+// 64 cells of one tile lie in 64 different cache lines (each shared with the same cell of
+// neighbouring slots), so the atomics of a tile that collects thousands of hits per frame
+// spread over 64 lines instead of queueing at the 8 lines of a tile-major block.
 __device__ inline int32_t cache_entry(const CacheArgs& c, int32_t slot, uint32_t tcell) {
-  return slot < 0 ? slot : (c.tiled ? slot * 64 + (int32_t)tcell : slot);
+  return slot < 0 ? slot : (c.tiled ? (int32_t)tcell * (int32_t)c.n_slots + slot : slot);
 }
 
 __device__ inline int32_t table_lookup(const CacheArgs& c, uint64_t key) {
@@ -708,7 +712,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const int32_t tslot = table_insert(c, key, inserted);
   stat_add(stats, GI_STAT_INSERTS, inserted);
   stat_add(stats, GI_STAT_OVERFLOW, tslot < 0);
-  if (tslot >= 0) c.accessed[tslot] = 1u;
+  // set once: with tiles thousands of hits share one flag, and a store from each would queue
+  // at its L2 line
+  if (tslot >= 0 && c.accessed[tslot] == 0u) c.accessed[tslot] = 1u;
   const int32_t slot = cache_entry(c, tslot, tcell);
 
   // one light sample: area-proportional emitter, uniform point, one shadow ray
@@ -754,7 +760,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
                                        bs * bn.x, bs * bn.y, bs * bn.z, bt, true, c.tiled, btcell);
       const int32_t bslot = table_lookup(c, bkey);
       if (bslot >= 0) {
-        c.accessed[bslot] = 1u;
+        if (c.accessed[bslot] == 0u) c.accessed[bslot] = 1u;
         const float4 lv = c.L[cache_entry(c, bslot, btcell)];
         Lb0 = lv.x; Lb1 = lv.y; Lb2 = lv.z;
       }
@@ -785,14 +791,36 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const uint32_t q0 = (uint32_t)rintf(fminf(fmaxf(s0, 0.0f), c.r_max) * scale);
   const uint32_t q1 = (uint32_t)rintf(fminf(fmaxf(s1, 0.0f), c.r_max) * scale);
   const uint32_t q2 = (uint32_t)rintf(fminf(fmaxf(s2, 0.0f), c.r_max) * scale);
-  uint32_t* accp = reinterpret_cast<uint32_t*>(c.acc + slot);
-  uint32_t wraps = 0;
-  const uint32_t o0 = atomicAdd(accp + 0, q0);
-  const uint32_t o1 = atomicAdd(accp + 1, q1);
-  const uint32_t o2 = atomicAdd(accp + 2, q2);
-  atomicAdd(accp + 3, 1u);
-  wraps += (o0 + q0 < o0) + (o1 + q1 < o1) + (o2 + q2 < o2);
-  if (wraps) atomicAdd(&stats[GI_STAT_WRAPS], (unsigned long long)wraps);
+  // the lanes of this wave that add to one entry are summed first, by the first of them, which
+  // issues the entry's atomics once (integer sums: the grouping does not change the result,
+  // nor the number of carries, as every partial sum stays below 2^32)
+  const uint32_t ent = (uint32_t)slot;
+  const uint64_t active = __ballot(true);
+  uint64_t same = active;
+#pragma unroll
+  for (int b = 0; b < 32; ++b) {
+    const uint64_t mb = __ballot((ent >> b) & 1u);
+    same &= ((ent >> b) & 1u) ? mb : ~mb;
+  }
+  uint32_t g0 = 0u, g1 = 0u, g2 = 0u;
+  for (uint64_t m = active; m; m &= m - 1u) {
+    const int i = __ffsll((long long)m) - 1;
+    const uint32_t v0 = __shfl(q0, i, 64), v1 = __shfl(q1, i, 64), v2 = __shfl(q2, i, 64);
+    if ((same >> i) & 1u) {
+      g0 += v0;
+      g1 += v1;
+      g2 += v2;
+    }
+  }
+  if ((uint32_t)__ffsll((long long)same) - 1u == (threadIdx.x & 63u)) {
+    uint32_t* accp = reinterpret_cast<uint32_t*>(c.acc + slot);
+    const uint32_t o0 = atomicAdd(accp + 0, g0);
+    const uint32_t o1 = atomicAdd(accp + 1, g1);
+    const uint32_t o2 = atomicAdd(accp + 2, g2);
+    atomicAdd(accp + 3, (uint32_t)__popcll(same));
+    const uint32_t wraps = (o0 + g0 < o0) + (o1 + g1 < o1) + (o2 + g2 < o2);
+    if (wraps) atomicAdd(&stats[GI_STAT_WRAPS], (unsigned long long)wraps);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1291,100 +1319,123 @@ __global__ __launch_bounds__(64 * WAVES) void k_interpolate(const float4* gpos, 
 // Lookup-only query for caller points
 // ------------------------------------------------------------------------------------------
 // ------------------------------------------------------------------------------------------
-// Two-level cache update (Section 2.2.3): one wave per tile, lane = cell.  Each cell's moving
-// average as in k_cache_update; the tile's life and eviction; then MIP levels 4x4, 2x2, 1x1
-// as sample-weighted means of their 2x2 children (children in raster order) in LDS, and each
-// cell's radiance for readers from the finest of its level and its parents that holds at
-// least tile_min samples, else the coarsest level if it holds any, else zero.
+// Two-level cache update (Section 2.2.3): a workgroup of 512 updates 8 consecutive slots.
+// Entries are cell-major (see cache_entry): one cache line holds one cell of 8 consecutive
+// slots, so thread (wave w, lane l) takes cell 8 w + l / 8 of slot l % 8 and every load or
+// store of a wave covers 8 whole lines.  Phase 1: each cell's moving average as in
+// k_cache_update, the tile's life and eviction, level 0 into LDS.  Phase 2: MIP levels 4x4,
+// 2x2, 1x1 of the 8 tiles as sample-weighted means of their 2x2 children (children in raster
+// order).  Phase 3: each cell's radiance for readers from the finest of its level and its
+// parents that holds at least tile_min samples, else the coarsest level if it holds any, else
+// zero.  Every thread reaches every barrier; empty and evicted tiles skip the work.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_cache_update_tiles(uint32_t* fp, uint64_t* key, uint4* acc, float4* L,
-                                                           uint32_t* cn, float4* Lq, uint2* meta, uint32_t* accessed,
-                                                           uint32_t n_cap, uint32_t max_life, uint32_t frac_bits,
-                                                           uint32_t tile_min, unsigned long long* stats) {
-  __shared__ float lv[85][3];   // level 0 at 0..63, level 1 at 64..79, level 2 at 80..83, level 3 at 84
-  __shared__ uint32_t nv[85];
-  const uint32_t s = blockIdx.x, lane = threadIdx.x;
-  if (fp[s] == 0u) return;
-  const size_t e = (size_t)s * 64 + lane;
-  const uint4 a = acc[e];
-  float4 l = L[e];
-  uint32_t nh = cn[e];
-  if (a.w > 0u) {
-    const uint32_t h = nh < n_cap ? nh : n_cap;
-    const float w = (float)a.w / (float)((double)h + (double)a.w);
-    const double den = (double)a.w * (double)(1u << frac_bits);
-    const float m0 = (float)((double)a.x / den);
-    const float m1 = (float)((double)a.y / den);
-    const float m2 = (float)((double)a.z / den);
-    l.x = l.x + w * (m0 - l.x);
-    l.y = l.y + w * (m1 - l.y);
-    l.z = l.z + w * (m2 - l.z);
-    const uint64_t t = (uint64_t)nh + a.w;
-    nh = t < n_cap ? (uint32_t)t : n_cap;
+__global__ __launch_bounds__(512) void k_cache_update_tiles(uint32_t* fp, uint64_t* key, uint4* acc, float4* L,
+                                                            uint32_t* cn, float4* Lq, uint2* meta, uint32_t* accessed,
+                                                            uint32_t n_cap, uint32_t max_life, uint32_t frac_bits,
+                                                            uint32_t tile_min, unsigned long long* stats) {
+  __shared__ float lv[8][85][3];   // per tile: level 0 at 0..63, 1 at 64..79, 2 at 80..83, 3 at 84
+  __shared__ uint32_t nv[8][85];
+  __shared__ uint32_t keep_s[8], live_s[8], life_s[8];
+  const uint32_t t = threadIdx.x, w = t >> 6, l = t & 63u;
+  const uint32_t j = l & 7u, cell = 8u * w + (l >> 3);
+  const uint32_t N = gridDim.x * 8u;
+  const uint32_t s = blockIdx.x * 8u + j;
+  const size_t e = (size_t)cell * N + s;
+  // the tile's state, read once before the thread of cell 0 rewrites it
+  if (t < 8u) {
+    const uint32_t st = blockIdx.x * 8u + t;
+    keep_s[t] = 0u;
+    live_s[t] = fp[st] != 0u;
+    life_s[t] = live_s[t] ? (accessed[st] ? max_life : meta[st].y - 1u) : 0u;
   }
-  acc[e] = make_uint4(0u, 0u, 0u, 0u);
-  const uint32_t life = accessed[s] ? max_life : meta[s].y - 1u;
-  unsigned long long* st = stats + (s % kStatStripes) * GI_STAT_COUNT;
-  if (life == 0u) {
-    L[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-    cn[e] = 0u;
-    Lq[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (lane == 0u) {
-      fp[s] = 0u;
-      key[s] = 0u;
-      meta[s] = make_uint2(0u, 0u);
-      accessed[s] = 0u;
-      atomicAdd(&st[GI_STAT_EVICT], 1ull);
-    }
-    return;
-  }
-  L[e] = l;
-  cn[e] = nh;
-  if (lane == 0u) {
-    meta[s] = make_uint2(0u, life);
-    accessed[s] = 0u;
-    atomicAdd(&st[GI_STAT_LIVE], 1ull);
-  }
-  lv[lane][0] = l.x;
-  lv[lane][1] = l.y;
-  lv[lane][2] = l.z;
-  nv[lane] = nh;
   __syncthreads();
-  // level k + 1 entry j (side 8 >> (k+1)) from level k (side 8 >> k)
+  if (live_s[j]) {
+    const uint4 a = acc[e];
+    float4 lc = L[e];
+    uint32_t nh = cn[e];
+    if (a.w > 0u) {
+      const uint32_t h = nh < n_cap ? nh : n_cap;
+      const float wt = (float)a.w / (float)((double)h + (double)a.w);
+      const double den = (double)a.w * (double)(1u << frac_bits);
+      const float m0 = (float)((double)a.x / den);
+      const float m1 = (float)((double)a.y / den);
+      const float m2 = (float)((double)a.z / den);
+      lc.x = lc.x + wt * (m0 - lc.x);
+      lc.y = lc.y + wt * (m1 - lc.y);
+      lc.z = lc.z + wt * (m2 - lc.z);
+      const uint64_t u = (uint64_t)nh + a.w;
+      nh = u < n_cap ? (uint32_t)u : n_cap;
+    }
+    acc[e] = make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t life = life_s[j];
+    unsigned long long* st = stats + (s % kStatStripes) * GI_STAT_COUNT;
+    if (life == 0u) {
+      L[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      cn[e] = 0u;
+      Lq[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (cell == 0u) {
+        fp[s] = 0u;
+        key[s] = 0u;
+        meta[s] = make_uint2(0u, 0u);
+        accessed[s] = 0u;
+        atomicAdd(&st[GI_STAT_EVICT], 1ull);
+      }
+    } else {
+      L[e] = lc;
+      cn[e] = nh;
+      if (cell == 0u) {
+        meta[s] = make_uint2(0u, life);
+        accessed[s] = 0u;
+        keep_s[j] = 1u;
+        atomicAdd(&st[GI_STAT_LIVE], 1ull);
+      }
+      lv[j][cell][0] = lc.x;
+      lv[j][cell][1] = lc.y;
+      lv[j][cell][2] = lc.z;
+      nv[j][cell] = nh;
+    }
+  }
+  __syncthreads();
+  // level k + 1 (side 8 >> (k+1), 8 tiles x side^2 entries) from level k (side 8 >> k)
   const uint32_t base[4] = {0u, 64u, 80u, 84u};
 #pragma unroll
   for (uint32_t k = 0; k < 3; ++k) {
-    const uint32_t side = 8u >> (k + 1u);
-    if (lane < side * side) {
-      const uint32_t x = lane % side, y = lane / side;
-      float w0 = 0.f, w1 = 0.f, w2 = 0.f;
-      uint32_t ns = 0u;
+    const uint32_t side = 8u >> (k + 1u), per = side * side;
+    if (t < 8u * per) {
+      const uint32_t tj = t / per, i = t % per;
+      if (keep_s[tj]) {
+        const uint32_t x = i % side, y = i / side;
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+        uint32_t ns = 0u;
 #pragma unroll
-      for (uint32_t c = 0; c < 4; ++c) {
-        const uint32_t ch = base[k] + (2u * y + (c >> 1)) * (2u * side) + (2u * x + (c & 1u));
-        const float fn = (float)nv[ch];
-        w0 = w0 + fn * lv[ch][0];
-        w1 = w1 + fn * lv[ch][1];
-        w2 = w2 + fn * lv[ch][2];
-        ns += nv[ch];
+        for (uint32_t c = 0; c < 4; ++c) {
+          const uint32_t ch = base[k] + (2u * y + (c >> 1)) * (2u * side) + (2u * x + (c & 1u));
+          const float fn = (float)nv[tj][ch];
+          w0 = w0 + fn * lv[tj][ch][0];
+          w1 = w1 + fn * lv[tj][ch][1];
+          w2 = w2 + fn * lv[tj][ch][2];
+          ns += nv[tj][ch];
+        }
+        const uint32_t o = base[k + 1u] + i;
+        nv[tj][o] = ns;
+        lv[tj][o][0] = ns ? w0 / (float)ns : 0.0f;
+        lv[tj][o][1] = ns ? w1 / (float)ns : 0.0f;
+        lv[tj][o][2] = ns ? w2 / (float)ns : 0.0f;
       }
-      const uint32_t o = base[k + 1u] + lane;
-      nv[o] = ns;
-      lv[o][0] = ns ? w0 / (float)ns : 0.0f;
-      lv[o][1] = ns ? w1 / (float)ns : 0.0f;
-      lv[o][2] = ns ? w2 / (float)ns : 0.0f;
     }
     __syncthreads();
   }
-  const uint32_t x = lane & 7u, y = lane >> 3;
+  if (!keep_s[j]) return;
+  const uint32_t x = cell & 7u, y = cell >> 3;
   int32_t pick = -1;
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
     const uint32_t o = base[k] + (y >> k) * (8u >> k) + (x >> k);
-    if (pick < 0 && nv[o] >= tile_min) pick = (int32_t)o;
+    if (pick < 0 && nv[j][o] >= tile_min) pick = (int32_t)o;
   }
-  if (pick < 0 && nv[84] > 0u) pick = 84;
-  Lq[e] = pick < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : make_float4(lv[pick][0], lv[pick][1], lv[pick][2], 0.f);
+  if (pick < 0 && nv[j][84] > 0u) pick = 84;
+  Lq[e] = pick < 0 ? make_float4(0.f, 0.f, 0.f, 0.f)
+                   : make_float4(lv[j][pick][0], lv[j][pick][1], lv[j][pick][2], 0.f);
 }
 
 __global__ void k_query(const float4* pos, const float4* nrm, uint32_t n, CacheArgs c, float4* out) {
@@ -1549,6 +1600,7 @@ static CacheArgs cache_args(const gi_context* c) {
   a.L = c->cfg.cache_tiles ? c->tab.Lq : c->tab.L;
   a.accessed = c->tab.accessed;
   a.tiled = c->cfg.cache_tiles;
+  a.n_slots = c->N;
   a.bucket_mask = c->N / kBucket - 1u;
   a.cell_scale = c->cfg.cell_scale;
   a.leak_bit = c->cfg.leak_bit;
@@ -1687,7 +1739,7 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
 
 hipError_t launch_update(gi_context* c, hipStream_t s) {
   if (c->cfg.cache_tiles) {
-    GI_TIMED(c, "cache_update_tiles", s, (k_cache_update_tiles<<<c->N, 64, 0, s>>>(c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.cn, c->tab.Lq, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->cfg.tile_min_samples, c->d_stats)));
+    GI_TIMED(c, "cache_update_tiles", s, (k_cache_update_tiles<<<c->N / 8u, 512, 0, s>>>(c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.cn, c->tab.Lq, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->cfg.tile_min_samples, c->d_stats)));
   } else {
     GI_TIMED(c, "cache_update", s, (k_cache_update<<<blocks(c->N, 256), 256, 0, s>>>(c->N, c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->d_stats)));
   }
