@@ -34,8 +34,9 @@ class OrcConfig(C.Structure):
                 ("cell_scale", C.c_float), ("r_max", C.c_float), ("eps_scale", C.c_float),
                 ("t_sky", C.c_float), ("sky", C.c_float * 4),
                 ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32),
-                ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32), ("pad5", C.c_uint32), ("pad6", C.c_uint32),
-                ("pad7", C.c_uint32)]
+                ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32), ("light_grid", C.c_uint32),
+                ("lgrid_dim", C.c_uint32), ("lgrid_k", C.c_uint32), ("ris_m", C.c_uint32), ("lgrid_tau", C.c_float),
+                ("pad8", C.c_uint32), ("pad9", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -48,7 +49,8 @@ def default_config(**kw) -> dict:
     cfg = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces=1, leak_bit=1,
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
-               temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min_samples=16)
+               temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min_samples=16, light_grid=0,
+               lgrid_dim=16, lgrid_k=8, ris_m=4, lgrid_tau=1e-3)
     cfg.update(kw)
     return cfg
 
@@ -114,6 +116,8 @@ def _lib(f64: bool):
     fn("export_tiles", C.c_uint32, vp, U64P, U64P, U32P, U32P, R, U32P, R, C.c_uint32)
     fn("tile_keys", None, C.POINTER(OrcConfig), R, R, R, R, C.c_uint32, U64P, U32P)
     fn("prefilter", None, R, U32P, C.c_uint32, R)
+    fn("light_grid_export", None, vp, R, U32P, U32P, U32P)
+    fn("light_grid_set", None, vp, R, R)
     fn("poke_cell", C.c_int, vp, C.c_uint64, U32P, R, C.c_uint32, C.c_uint32, C.c_uint32)
     fn("cache_update_only", None, vp)
     fn("stats", None, vp, U64P)
@@ -128,6 +132,10 @@ def _lib(f64: bool):
     fn("guided_dirs", None, R, U32P, U32P, R, R, C.c_uint32, R, U32P)
     fn("reconstruct_probe", None, R, R, C.c_double if f64 else C.c_float, C.c_uint32, R, R, R, R, U32P)
     fn("nee_samples", None, vp, C.POINTER(OrcFrame), R, R, U32P, C.c_uint32, R)
+    fn("config_size", C.c_uint32)
+    got = int(getattr(lib, p + "config_size")())
+    if got != C.sizeof(OrcConfig):
+        raise RuntimeError(f"oracle config struct is {got} bytes, its Python mirror {C.sizeof(OrcConfig)}")
     _LIBS[key] = (lib, p)
     return _LIBS[key]
 
@@ -496,6 +504,23 @@ class OracleFrameState:
         o = np.argsort(ident[:n], kind="stable")
         return dict(id=ident[:n][o], key=key[:n][o], life=life[:n][o], acc=acc[:n][o], L=L[:n][o],
                     nhist=nh[:n][o], Lq=Lq[:n][o])
+
+    def light_grid_set(self, lo, hi):
+        """build the light grid over the box [lo, hi] (as a trace does over its hit points)"""
+        _call(self.f64, "light_grid_set", self.h, np.ascontiguousarray(lo, self.dt), np.ascontiguousarray(hi, self.dt))
+
+    def light_grid(self):
+        """after a trace with light_grid: origin and cell side, dims, per cell the light list
+        (indices into the emitter list) and its length"""
+        geom = np.zeros(4, self.dt)
+        dims = np.zeros(3, np.uint32)
+        D = int(self.cfg.get("lgrid_dim", 16))
+        K = int(self.cfg.get("lgrid_k", 8))
+        lst = np.zeros(D * D * D * K, np.uint32)
+        cnt = np.zeros(D * D * D, np.uint32)
+        _call(self.f64, "light_grid_export", self.h, geom, dims, lst, cnt)
+        n = int(np.prod(dims))
+        return dict(lo=geom[:3].copy(), h=float(geom[3]), dims=dims, list=lst[:n * K].reshape(n, K), count=cnt[:n])
 
     def poke_cell(self, key, acc4, L3, nhist, life, accessed):
         return _call(self.f64, "poke_cell", self.h, key, np.ascontiguousarray(acc4, np.uint32),

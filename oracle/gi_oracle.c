@@ -676,7 +676,10 @@ typedef struct orc_config {
     float cell_scale, r_max, eps_scale, t_sky;
     float sky[4];
     uint32_t temporal, upscale, ray_guiding, cache_tiles;
-    uint32_t tile_min, pad5, pad6, pad7;
+    uint32_t tile_min, light_grid, lgrid_dim, lgrid_k;
+    uint32_t ris_m;
+    float lgrid_tau;
+    uint32_t pad8, pad9;
 } orc_config;
 
 typedef struct orc_frame {
@@ -684,6 +687,9 @@ typedef struct orc_frame {
     float fov_y, tan_half, pad;
     float pos[4], fwd[4], right[4], up[4];
 } orc_frame;
+
+/* struct sizes, checked by the Python loader against its mirror */
+uint32_t ORC(config_size)(void) { return (uint32_t)sizeof(orc_config); }
 
 /* ---------------------------------------------------------------------------------------
  * G-buffer (test input; the paper rasterises it, Section 2.1.1): one primary ray through
@@ -757,6 +763,12 @@ typedef struct state {
     uint32_t *nhist, *life, *accessed;   /* nhist per cell ([N][64] tiled), life and accessed per slot */
     real *Lq;              /* tiled: [N][64][3] radiance returned to queries (prefiltered level) */
     uint32_t *r_tcell;     /* tiled: [P*R] cell of the hit inside its tile */
+    real *r_y, *r_ny;      /* [P*R][3] hit point and face-forwarded normal */
+    /* light grid (Section 2.3.2) */
+    real lg_lo[3], lg_h;
+    uint32_t lg_dim[3];
+    uint32_t *lg_list;     /* [dim^3 cap][K] emitter indices (into etri) */
+    uint32_t *lg_count;    /* [dim^3 cap] */
     /* probes */
     real *atlas;           /* [P][64][4] */
     real *sh;              /* [P][27] */
@@ -1073,6 +1085,13 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->nhist = (uint32_t *)calloc(N * G, sizeof(uint32_t));
     st->Lq = (real *)calloc(cfg->cache_tiles ? 3 * N * G : 1, sizeof(real));
     st->r_tcell = (uint32_t *)calloc(PR, sizeof(uint32_t));
+    st->r_y = (real *)calloc(3 * PR, sizeof(real));
+    st->r_ny = (real *)calloc(3 * PR, sizeof(real));
+    if (cfg->light_grid) {
+        size_t ncell = (size_t)cfg->lgrid_dim * cfg->lgrid_dim * cfg->lgrid_dim;
+        st->lg_list = (uint32_t *)calloc(ncell * (cfg->lgrid_k ? cfg->lgrid_k : 1), sizeof(uint32_t));
+        st->lg_count = (uint32_t *)calloc(ncell, sizeof(uint32_t));
+    }
     st->life = (uint32_t *)calloc(N, sizeof(uint32_t));
     st->accessed = (uint32_t *)calloc(N, sizeof(uint32_t));
     st->atlas = (real *)calloc(P * NCELL * 4, sizeof(real));
@@ -1099,7 +1118,7 @@ void ORC(destroy)(state *st)
     free(st->r_sample); free(st->r_keylo); free(st->r_keyhi); free(st->r_valid); free(st->r_bslot);
     free(st->fp); free(st->key); free(st->acc); free(st->dacc); free(st->L);
     free(st->nhist); free(st->life); free(st->accessed); free(st->atlas); free(st->sh);
-    free(st->Lq); free(st->r_tcell);
+    free(st->Lq); free(st->r_tcell); free(st->r_y); free(st->r_ny); free(st->lg_list); free(st->lg_count);
     free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
     free(st->hist); free(st->traced); free(st->recon); free(st->cdf);
     free(st);
@@ -1499,6 +1518,200 @@ void ORC(spawn)(state *st, const orc_frame *fr, const real *gpos, const real *gn
  * two bounces, the cached outgoing radiance found at the end of a cosine-sampled ray
  * (temporal radiance feedback).  Samples are accumulated in fixed point (FP32 mode).
  * ------------------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------------------
+ * Light grid and resampled light sampling (Section 2.3: importance sampling of the lights
+ * with RIS and weighted reservoir sampling; the light grid of Section 2.3.2 feeds the
+ * candidates).  Lights are the emitter triangles: area A, centroid c, unit normal n (the
+ * emitting side), luminance l of Le (Rec. 709), power-like weight phi = l A.
+ * Light grid: over the axis-aligned box of this frame's probe-ray hit points, cubic cells of
+ * side h = (largest extent) / lgrid_dim, at most lgrid_dim per axis.  A light is culled from
+ * a cell when the cell's bounding sphere (centre, radius h sqrt(3) / 2) lies entirely behind
+ * the light's plane, or farther from its centroid than its range sqrt(phi / lgrid_tau) plus
+ * the radius.  Importance = the mean over the cell's 8 corners of phi cos / max(d^2, A) (a
+ * small-source contribution, cos from the light's normal; the mean of the corners is the
+ * volume integral of their trilinear interpolant over the cell volume); each cell keeps the
+ * min(lgrid_k, lights) most important lights with importance > 0 (ties: lower index first).
+ * RIS: ris_m candidates, each a light picked uniformly from the hit's cell list and a
+ * uniform point on it (source pdf 1 / (count A)), target l cos_y cos_l / d^2, weight
+ * target / source pdf; streaming weighted reservoir sampling keeps one candidate; one
+ * shadow ray; the estimate is Le cos_y cos_l / d^2 * (sum of weights) / (ris_m target).
+ * READING: grid bounds from the probe-ray hits (the shading points); no spotlights or point
+ * lights (the scenes' lights are emissive triangles); the reservoirs are not stored in a
+ * hash grid and not reused over time (not built).
+ * ------------------------------------------------------------------------------------- */
+static real lum709(const float *le)
+{
+    return ((real)0.2126f * (real)le[0] + (real)0.7152f * (real)le[1]) + (real)0.0722f * (real)le[2];
+}
+
+static void light_attr(const scene *sc, uint32_t k, real *cen, real *A, const real **n, const float **le)
+{
+    uint32_t t = sc->etri[k];
+    const float *v = sc->tv + 9 * (size_t)t;
+    for (int j = 0; j < 3; ++j) cen[j] = (real)((((double)v[j] + (double)v[3 + j]) + (double)v[6 + j]) / 3.0);
+    *A = (real)tri_area_f64(v);
+    *n = sc->tn + 3 * (size_t)t;
+    *le = sc->mats + 6 * sc->tmat[t] + 3;
+}
+
+static uint32_t lgrid_cell_of(const state *st, const real *y)
+{
+    uint32_t ix[3];
+    for (int k = 0; k < 3; ++k) {
+        real f = RFLOOR((y[k] - st->lg_lo[k]) / st->lg_h);
+        int32_t i = f < RC(0.0) ? 0 : (f > (real)(st->lg_dim[k] - 1) ? (int32_t)st->lg_dim[k] - 1 : (int32_t)f);
+        ix[k] = (uint32_t)i;
+    }
+    return (ix[2] * st->lg_dim[1] + ix[1]) * st->lg_dim[0] + ix[0];
+}
+
+static real light_importance(const state *st, uint32_t cx, uint32_t cy, uint32_t cz, uint32_t k)
+{
+    const scene *sc = st->sc;
+    real cen[3], A;
+    const real *n;
+    const float *le;
+    light_attr(sc, k, cen, &A, &n, &le);
+    real phi = lum709(le) * A;
+    real h = st->lg_h;
+    uint32_t ci[3] = {cx, cy, cz};
+    real cc[3];
+    for (int j = 0; j < 3; ++j) cc[j] = st->lg_lo[j] + ((real)ci[j] + RC(0.5)) * h;
+    real R = h * RC(0.8660254037844386);
+    real sd = ((cc[0] - cen[0]) * n[0] + (cc[1] - cen[1]) * n[1]) + (cc[2] - cen[2]) * n[2];
+    if (sd < -R) return RC(-1.0);
+    real dx = cc[0] - cen[0], dy = cc[1] - cen[1], dz = cc[2] - cen[2];
+    real dist = RSQRT((dx * dx + dy * dy) + dz * dz);
+    real range = RSQRT(phi / (real)st->cfg.lgrid_tau);
+    if (dist > range + R) return RC(-1.0);
+    real imp = RC(0.0);
+    for (uint32_t q = 0; q < 8; ++q) {
+        real v[3];
+        for (int j = 0; j < 3; ++j) v[j] = (st->lg_lo[j] + (real)(ci[j] + ((q >> j) & 1u)) * h) - cen[j];
+        real vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+        real len = RSQRT(vv);
+        real cs = len > RC(0.0) ? ((v[0] * n[0] + v[1] * n[1]) + v[2] * n[2]) / len : RC(0.0);
+        if (cs > RC(0.0)) imp = imp + (phi * cs) / rmax(vv, A);
+    }
+    return imp * RC(0.125);
+}
+
+static void light_grid_build(state *st, const real *lo, const real *hi)
+{
+    const orc_config *c = &st->cfg;
+    real emax = RC(0.0);
+    for (int k = 0; k < 3; ++k) {
+        st->lg_lo[k] = lo[k];
+        emax = rmax(emax, hi[k] - lo[k]);
+    }
+    real h = emax / (real)c->lgrid_dim;
+    st->lg_h = h > RC(0.0) ? h : RC(1.0);
+    for (int k = 0; k < 3; ++k) {
+        real q = -RFLOOR(-((hi[k] - lo[k]) / st->lg_h));
+        uint32_t d = q < RC(1.0) ? 1u : (uint32_t)q;
+        st->lg_dim[k] = d > c->lgrid_dim ? c->lgrid_dim : d;
+    }
+    uint32_t K = c->lgrid_k < st->sc->ne ? c->lgrid_k : st->sc->ne;
+    uint32_t ncell = st->lg_dim[0] * st->lg_dim[1] * st->lg_dim[2];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long ci = 0; ci < (long)ncell; ++ci) {
+        uint32_t cx = (uint32_t)ci % st->lg_dim[0], cy = ((uint32_t)ci / st->lg_dim[0]) % st->lg_dim[1];
+        uint32_t cz = (uint32_t)ci / (st->lg_dim[0] * st->lg_dim[1]);
+        uint32_t ne = st->sc->ne, cnt = 0;
+        real *imp = (real *)malloc(sizeof(real) * (ne ? ne : 1));
+        for (uint32_t k = 0; k < ne; ++k) imp[k] = light_importance(st, cx, cy, cz, k);
+        /* the K largest, ties by lower index (selection by repeated maximum) */
+        for (uint32_t r = 0; r < K; ++r) {
+            uint32_t best = 0xFFFFFFFFu;
+            for (uint32_t k = 0; k < ne; ++k)
+                if (imp[k] > RC(0.0) && (best == 0xFFFFFFFFu || imp[k] > imp[best])) best = k;
+            if (best == 0xFFFFFFFFu) break;
+            st->lg_list[(size_t)ci * c->lgrid_k + cnt++] = best;
+            imp[best] = RC(-1.0);
+        }
+        st->lg_count[ci] = cnt;
+        free(imp);
+    }
+}
+
+void ORC(light_grid_set)(state *st, const real *lo, const real *hi)
+{
+    /* test entry: build the grid over a given box */
+    light_grid_build(st, lo, hi);
+}
+
+void ORC(light_grid_export)(const state *st, real *geom /* lo[3], h */, uint32_t *dims, uint32_t *list,
+                            uint32_t *count)
+{
+    for (int k = 0; k < 3; ++k) geom[k] = st->lg_lo[k];
+    geom[3] = st->lg_h;
+    for (int k = 0; k < 3; ++k) dims[k] = st->lg_dim[k];
+    uint32_t n = st->lg_dim[0] * st->lg_dim[1] * st->lg_dim[2];
+    memcpy(list, st->lg_list, sizeof(uint32_t) * (size_t)n * st->cfg.lgrid_k);
+    memcpy(count, st->lg_count, sizeof(uint32_t) * n);
+}
+
+/* RIS over the cell's light list: E (irradiance estimate times pi, before albedo) */
+static void ris_light(const state *st, const orc_frame *fr, uint32_t gid, const real *y, const real *yo,
+                      const real *ny, real *E, uint64_t *stat_shadow, uint64_t *stat_occ)
+{
+    const orc_config *c = &st->cfg;
+    const scene *sc = st->sc;
+    uint32_t cell = lgrid_cell_of(st, y);
+    uint32_t m = st->lg_count[cell];
+    const uint32_t *list = st->lg_list + (size_t)cell * c->lgrid_k;
+    if (m == 0) return;
+    real wsum = RC(0.0), ph_sel = RC(0.0), g_sel = RC(0.0), dist_sel = RC(0.0);
+    real om_sel[3] = {RC(0.0), RC(0.0), RC(0.0)};
+    uint32_t k_sel = 0xFFFFFFFFu;
+    for (uint32_t j = 0; j < c->ris_m; ++j) {
+        uint32_t rp = rng_u32(c->seed, fr->index, gid, 16u + 4u * j);
+        uint32_t k = list[(uint32_t)(((uint64_t)rp * m) >> 32)];
+        real u3 = rng_unit(rng_u32(c->seed, fr->index, gid, 17u + 4u * j));
+        real u4 = rng_unit(rng_u32(c->seed, fr->index, gid, 18u + 4u * j));
+        real us = rng_unit(rng_u32(c->seed, fr->index, gid, 19u + 4u * j));
+        uint32_t t = sc->etri[k];
+        real su = RSQRT(u3);
+        real b0 = RC(1.0) - su, b1 = su * (RC(1.0) - u4), b2 = su * u4;
+        const float *v = sc->tv + 9 * (size_t)t;
+        real w[3];
+        for (int q = 0; q < 3; ++q) w[q] = ((b0 * (real)v[q] + b1 * (real)v[3 + q]) + b2 * (real)v[6 + q]) - yo[q];
+        real d2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+        real ph = RC(0.0), g = RC(0.0), dist = RC(0.0);
+        real om[3] = {RC(0.0), RC(0.0), RC(0.0)};
+        if (d2 > RC(0.0)) {
+            dist = RSQRT(d2);
+            for (int q = 0; q < 3; ++q) om[q] = w[q] / dist;
+            const real *nl = sc->tn + 3 * (size_t)t;
+            real cos_y = (ny[0] * om[0] + ny[1] * om[1]) + ny[2] * om[2];
+            real cos_l = -((nl[0] * om[0] + nl[1] * om[1]) + nl[2] * om[2]);
+            if (cos_y > RC(0.0) && cos_l > RC(0.0)) {
+                g = (cos_y * cos_l) / d2;
+                ph = lum709(sc->mats + 6 * sc->tmat[t] + 3) * g;
+            }
+        }
+        real A = (real)tri_area_f64(v);
+        real wj = (ph * (real)m) * A;
+        wsum = wsum + wj;
+        if (wj > RC(0.0) && us * wsum < wj) {
+            k_sel = k;
+            ph_sel = ph;
+            g_sel = g;
+            dist_sel = dist;
+            for (int q = 0; q < 3; ++q) om_sel[q] = om[q];
+        }
+    }
+    if (k_sel == 0xFFFFFFFFu) return;
+    (*stat_shadow)++;
+    if (any_hit(sc, yo, om_sel, dist_sel * RC(0.9999))) {
+        (*stat_occ)++;
+        return;
+    }
+    real W = wsum / ((real)c->ris_m * ph_sel);
+    const float *le = sc->mats + 6 * sc->tmat[sc->etri[k_sel]] + 3;
+    for (int q = 0; q < 3; ++q) E[q] = ((real)le[q] * g_sel) * W;
+}
+
 static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const real *y,
                       const real *ny, real *s_out, int32_t *bslot, uint64_t *stat_shadow,
                       uint64_t *stat_occ, uint64_t *stat_bounce)
@@ -1509,7 +1722,9 @@ static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const 
     real eps = offset_eps(c, y);
     real yo[3];
     for (int k = 0; k < 3; ++k) yo[k] = y[k] + ny[k] * eps;
-    if (sc->ne > 0) {
+    if (sc->ne > 0 && c->light_grid) {
+        ris_light(st, fr, gid, y, yo, ny, E, stat_shadow, stat_occ);
+    } else if (sc->ne > 0) {
         uint32_t e = sc->etri[pick_emitter(sc, rng_u32(c->seed, fr->index, gid, 2u))];
         real u3 = rng_unit(rng_u32(c->seed, fr->index, gid, 3u));
         real u4 = rng_unit(rng_u32(c->seed, fr->index, gid, 4u));
@@ -1627,18 +1842,41 @@ void ORC(trace)(state *st, const orc_frame *fr)
             uint64_t key = cell_key_cell(c, st->cam, y, ny, t, 1, &st->r_tcell[gid]);
             st->r_keylo[gid] = (uint32_t)key;
             st->r_keyhi[gid] = (uint32_t)(key >> 32);
-            real s[3];
-            shade_hit(st, fr, (uint32_t)gid, y, ny, s, &st->r_bslot[gid], &nshadow, &nocc, &nbounce);
-            const float *m = sc->mats + 6 * sc->tmat[tri];
-            for (int k = 0; k < 3; ++k) st->r_sample[3 * gid + k] = (real)m[k] * s[k];
-            st->r_valid[gid] = 1;
+            for (int k = 0; k < 3; ++k) { st->r_y[3 * gid + k] = y[k]; st->r_ny[3 * gid + k] = ny[k]; }
         }
+    }
+    size_t PR = (size_t)st->P * R;
+    if (c->light_grid) {
+        /* the light grid over the box of this frame's hit points */
+        real lo[3] = {RC(0.0), RC(0.0), RC(0.0)}, hi[3] = {RC(0.0), RC(0.0), RC(0.0)};
+        int any = 0;
+        for (size_t gid = 0; gid < PR; ++gid) {
+            if (!(st->r_cell[gid] & 0x100u)) continue;
+            for (int k = 0; k < 3; ++k) {
+                real v = st->r_y[3 * gid + k];
+                if (!any || v < lo[k]) lo[k] = v;
+                if (!any || v > hi[k]) hi[k] = v;
+            }
+            any = 1;
+        }
+        light_grid_build(st, lo, hi);
+    }
+    /* shading of the hits (light sample, cached bounce) */
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nshadow, nocc, nbounce)
+    for (long g = 0; g < (long)PR; ++g) {
+        size_t gid = (size_t)g;
+        if (!(st->r_cell[gid] & 0x100u)) continue;
+        real s[3];
+        shade_hit(st, fr, (uint32_t)gid, st->r_y + 3 * gid, st->r_ny + 3 * gid, s, &st->r_bslot[gid], &nshadow,
+                  &nocc, &nbounce);
+        const float *m = sc->mats + 6 * sc->tmat[st->r_tri[gid]];
+        for (int k = 0; k < 3; ++k) st->r_sample[3 * gid + k] = (real)m[k] * s[k];
+        st->r_valid[gid] = 1;
     }
     st->stats[ST_SHADOW] += nshadow;
     st->stats[ST_OCCLUDED] += nocc;
     st->stats[ST_BOUNCE] += nbounce;
     /* sequential phase: cell lookup/creation and accumulation in ray order */
-    size_t PR = (size_t)st->P * R;
     for (size_t gid = 0; gid < PR; ++gid) {
         if (!(st->r_cell[gid] & 0x10000u)) continue;
         st->stats[ST_RAYS]++;

@@ -208,6 +208,40 @@ def room_scene(seed: int = SCENE_SEED, light_le: float = 10.0) -> Scene:
     return b.scene("room")
 
 
+def lights_room_scene(seed: int = SCENE_SEED, n_lights: int = 64) -> Scene:
+    """The room of room_scene (same walls and boxes) lit by n_lights small emissive quads
+    instead of one: 0.2x0.2 m, 1 cm off the ceiling (facing down) or the four walls (facing
+    in), random colours, radiance log-uniform over [2, 200] so that a few lights dominate."""
+    base = room_scene(seed)
+    rng = np.random.default_rng(seed + 101)
+    b = _Builder()
+    b.mats = [list(m) for m in base.materials[:-1]]   # without the ceiling light
+    keep = base.tri_mat < len(base.materials) - 1
+    b.v.append(base.verts.astype(np.float32))
+    b.f.append(base.idx[keep])
+    b.m.append(base.tri_mat[keep])
+    b.nv = len(base.verts)
+    s = 0.1
+    for _ in range(n_lights):
+        le = 10.0 ** rng.uniform(np.log10(2.0), np.log10(200.0)) * rng.uniform(0.4, 1.0, size=3)
+        mat = b.material((0.0, 0.0, 0.0), le)
+        face = rng.integers(0, 5)
+        a, c = rng.uniform(0.3, 5.7, size=2)
+        h = rng.uniform(1.0, 2.7)
+        if face == 0:      # ceiling, facing down
+            v, f = _quad((a, 2.99, c), (s, 0.0, 0.0), (0.0, 0.0, s))
+        elif face == 1:    # wall x = 0, facing +x
+            v, f = _quad((0.01, h, c), (0.0, s, 0.0), (0.0, 0.0, s))
+        elif face == 2:    # wall x = 6, facing -x
+            v, f = _quad((5.99, h, c), (0.0, 0.0, s), (0.0, s, 0.0))
+        elif face == 3:    # wall z = 0, facing +z
+            v, f = _quad((a, h, 0.01), (s, 0.0, 0.0), (0.0, s, 0.0))
+        else:              # wall z = 6, facing -z
+            v, f = _quad((a, h, 5.99), (0.0, s, 0.0), (s, 0.0, 0.0))
+        b.add(v, f, mat)
+    return b.scene("lights_room")
+
+
 def _field_light_quad(center):
     v, f = _quad(center, (1.0, 0.0, 0.0), (0.0, 0.0, 1.0))   # normal -y (down)
     return v[f].reshape(-1, 9)
@@ -432,11 +466,11 @@ PRESETS = {
 
 def make_scene(name: str) -> Scene:
     return {"room": room_scene, "field": field_scene, "city": city_scene,
-            "furnace": furnace_scene}[name]()
+            "furnace": furnace_scene, "lights_room": lights_room_scene}[name]()
 
 
 def camera_for(scene_name: str, index: int) -> Frame:
-    if scene_name == "room":
+    if scene_name in ("room", "lights_room"):
         return room_camera(index)
     if scene_name == "field":
         return orbit_camera(index)
