@@ -126,7 +126,20 @@ typedef struct gi_config {
      * (else the coarsest level if it holds any).  Export with gi_tiles_export. */
     uint32_t cache_tiles;
     uint32_t tile_min_samples;
-    uint32_t reserved2[2];
+    /* 1: light sampling by RIS over a light grid (Section 2.3).  After the probe rays, a grid
+     * of cubic cells (longest axis in lgrid_dim cells, 1..32) is laid over the box of the
+     * frame's hit points; each cell keeps the lgrid_k (1..32) emitter triangles of largest
+     * importance (mean over its corners of luminance * area * cos / max(d^2, area)), lights
+     * facing away from the cell or farther than sqrt(luminance * area / lgrid_threshold)
+     * culled.  Each hit draws ris_candidates (1..8) candidates from its cell's list (a
+     * uniform pick, a uniform point) and keeps one by weighted reservoir sampling with target
+     * luminance * cos * cos / d^2; one shadow ray.  At most 2048 emitter triangles. */
+    uint32_t light_grid;
+    uint32_t ris_candidates;
+    uint32_t lgrid_dim;
+    uint32_t lgrid_k;
+    float lgrid_threshold;
+    uint32_t reserved3[3];
 } gi_config;
 
 typedef struct gi_frame {
@@ -272,6 +285,13 @@ gi_status gi_learned_query(gi_context *ctx, const float *d_pos, const float *d_n
  * pointer may be null.  GI_ERR_UNSUPPORTED without tiles. */
 gi_status gi_tiles_export(gi_context *ctx, uint64_t *h_id, uint64_t *h_key, uint32_t *h_life, uint32_t *h_acc,
                           float *h_L, uint32_t *h_nhist, float *h_Lq, uint32_t cap, uint32_t *n_out);
+
+/* Light grid of the last trace (light_grid = 1; host-synchronous): geom = origin x, y, z and
+ * cell side; dims = cells per axis; per cell (x fastest, at most cap_cells) the emitter
+ * indices (into the emitter order: static emitters in triangle order, then dynamic ones;
+ * lgrid_k per cell, the first count[c] valid) and the count.  GI_ERR_UNSUPPORTED without it. */
+gi_status gi_light_grid_export(gi_context *ctx, float *h_geom, uint32_t *h_dims, uint32_t *h_list, uint32_t *h_count,
+                               uint32_t cap_cells);
 
 /* Live cells in slot order: id = bucket << 32 | fingerprint, key (descriptor bits), acc
  * [n][4] (fixed-point r,g,b sums and count of the current frame), L [n][3] cached radiance,

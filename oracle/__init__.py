@@ -35,7 +35,7 @@ class OrcConfig(C.Structure):
                 ("t_sky", C.c_float), ("sky", C.c_float * 4),
                 ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32),
                 ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32), ("light_grid", C.c_uint32),
-                ("lgrid_dim", C.c_uint32), ("lgrid_k", C.c_uint32), ("ris_m", C.c_uint32), ("lgrid_tau", C.c_float),
+                ("lgrid_dim", C.c_uint32), ("lgrid_k", C.c_uint32), ("ris_candidates", C.c_uint32), ("lgrid_threshold", C.c_float),
                 ("pad8", C.c_uint32), ("pad9", C.c_uint32)]
 
 
@@ -50,7 +50,7 @@ def default_config(**kw) -> dict:
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
                temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min_samples=16, light_grid=0,
-               lgrid_dim=16, lgrid_k=8, ris_m=4, lgrid_tau=1e-3)
+               lgrid_dim=16, lgrid_k=8, ris_candidates=4, lgrid_threshold=1e-3)
     cfg.update(kw)
     return cfg
 

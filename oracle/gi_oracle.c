@@ -1709,7 +1709,8 @@ static void ris_light(const state *st, const orc_frame *fr, uint32_t gid, const 
     }
     real W = wsum / ((real)c->ris_m * ph_sel);
     const float *le = sc->mats + 6 * sc->tmat[sc->etri[k_sel]] + 3;
-    for (int q = 0; q < 3; ++q) E[q] = ((real)le[q] * g_sel) * W;
+    real gw = g_sel * W;
+    for (int q = 0; q < 3; ++q) E[q] = (real)le[q] * gw;
 }
 
 static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const real *y,

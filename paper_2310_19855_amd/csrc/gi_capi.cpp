@@ -126,14 +126,17 @@ gi_status upload_emitters(gi_context* c, const float* dyn_tv, const uint32_t* dy
     etri.push_back(t);
     area.push_back(c->h_static_emit_area[k]);
     const float* v = &c->h_static_tv[9 * (size_t)t];
-    for (int i = 0; i < 3; ++i) verts.insert(verts.end(), {v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0f});
+    // w of the first vertex: the triangle's area, rounded once from float64
+    for (int i = 0; i < 3; ++i)
+      verts.insert(verts.end(), {v[3 * i], v[3 * i + 1], v[3 * i + 2], i == 0 ? (float)area.back() : 0.0f});
   }
   for (uint32_t k = 0; k < nd; ++k) {
     if (!emits(c->h_mats, dyn_mat[k])) continue;
     etri.push_back(c->nt + k);
     area.push_back(tri_area(dyn_tv + 9 * (size_t)k));
     const float* v = dyn_tv + 9 * (size_t)k;
-    for (int i = 0; i < 3; ++i) verts.insert(verts.end(), {v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0f});
+    for (int i = 0; i < 3; ++i)
+      verts.insert(verts.end(), {v[3 * i], v[3 * i + 1], v[3 * i + 2], i == 0 ? (float)area.back() : 0.0f});
   }
   const uint32_t n = (uint32_t)etri.size();
   std::vector<uint32_t> thr(n);
@@ -210,6 +213,10 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->d_over_count);
   dfree(c->d_recon);
   dfree(c->d_cdf);
+  dfree(c->d_lg_box);
+  dfree(c->d_lg_part);
+  dfree(c->d_lg_list);
+  dfree(c->d_lg_count);
   dfree(c->d_sh);
   dfree(c->tab.fp);
   dfree(c->tab.key);
@@ -260,6 +267,12 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->cache_tiles > 1) { why = "cache_tiles must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   if (g->cache_tiles && g->cache_mode != GI_CACHE_PLAIN) { why = "cache_tiles needs the plain cache"; return GI_ERR_INVALID_ARG; }
   if (g->cache_tiles && g->table_log2 > 22) { why = "cache_tiles: table_log2 (tiles) out of [6, 22]"; return GI_ERR_INVALID_ARG; }
+  if (g->light_grid > 1) { why = "light_grid must be 0 or 1"; return GI_ERR_INVALID_ARG; }
+  if (g->light_grid && (g->lgrid_dim < 1 || g->lgrid_dim > 32 || g->lgrid_k < 1 || g->lgrid_k > 32 ||
+                        g->ris_candidates < 1 || g->ris_candidates > 8 || !(g->lgrid_threshold > 0.0f))) {
+    why = "light grid: lgrid_dim and lgrid_k in [1, 32], ris_candidates in [1, 8], lgrid_threshold > 0";
+    return GI_ERR_INVALID_ARG;
+  }
   return GI_OK;
 }
 
@@ -347,6 +360,13 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
   if (cfg->ray_guiding) {
     A(dalloc(&c->d_recon, (size_t)c->P * 64));
     A(dalloc(&c->d_cdf, (size_t)c->P * 64));
+  }
+  if (cfg->light_grid) {
+    const size_t cells = (size_t)cfg->lgrid_dim * cfg->lgrid_dim * cfg->lgrid_dim;
+    A(dalloc(&c->d_lg_box, 6));
+    A(dalloc(&c->d_lg_part, 6 * ((PR + 255) / 256)));
+    A(dalloc(&c->d_lg_list, cells * cfg->lgrid_k));
+    A(dalloc(&c->d_lg_count, cells));
   }
   A(dalloc(&c->d_sh, (size_t)c->P * 28));
   A(dalloc(&c->tab.fp, c->N));
@@ -639,6 +659,7 @@ gi_status gi_spawn_probes(gi_context* c, const gi_frame* f, const float* pos, co
 
 gi_status gi_trace_probes(gi_context* c, const gi_frame* f, void* stream) {
   if (!c) return GI_ERR_INVALID_ARG;
+  if (c->cfg.light_grid && c->n_emit > 2048) return fail(c, GI_ERR_UNSUPPORTED, "light grid: more than 2048 emitter triangles");
   if (!f) return fail(c, GI_ERR_INVALID_ARG, "null frame");
   if (c->stage != 1 || f->index != c->fa.index) return fail(c, GI_ERR_STATE, "gi_spawn_probes of this frame first");
   GI_TRY_HIP(c, gi::launch_trace(c, reinterpret_cast<hipStream_t>(stream)));
@@ -752,6 +773,29 @@ gi_status gi_learned_query(gi_context* c, const float* pos, const float* nrm, ui
 }
 
 // ---- exports ------------------------------------------------------------------------------
+
+gi_status gi_light_grid_export(gi_context* c, float* h_geom, uint32_t* h_dims, uint32_t* h_list, uint32_t* h_count,
+                               uint32_t cap_cells) {
+  if (!c || !h_geom || !h_dims) return GI_ERR_INVALID_ARG;
+  if (!c->cfg.light_grid) return fail(c, GI_ERR_UNSUPPORTED, "gi_light_grid_export needs light_grid = 1");
+  try {
+    GI_TRY_HIP(c, hipDeviceSynchronize());
+    uint32_t box[6];
+    GI_TRY_HIP(c, hipMemcpy(box, c->d_lg_box, sizeof(box), hipMemcpyDeviceToHost));
+    gi::LightGridGeom g = gi::light_grid_geom(box, c->cfg.lgrid_dim);
+    for (int k = 0; k < 3; ++k) {
+      h_geom[k] = g.lo[k];
+      h_dims[k] = g.dim[k];
+    }
+    h_geom[3] = g.h;
+    const size_t n = std::min<size_t>((size_t)g.dim[0] * g.dim[1] * g.dim[2], cap_cells);
+    if (h_list) GI_TRY_HIP(c, hipMemcpy(h_list, c->d_lg_list, 4 * n * c->cfg.lgrid_k, hipMemcpyDeviceToHost));
+    if (h_count) GI_TRY_HIP(c, hipMemcpy(h_count, c->d_lg_count, 4 * n, hipMemcpyDeviceToHost));
+    return GI_OK;
+  } catch (const std::exception& ex) {
+    return fail(c, GI_ERR_INTERNAL, ex.what());
+  }
+}
 
 gi_status gi_tiles_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, uint32_t* h_life, uint32_t* h_acc,
                           float* h_L, uint32_t* h_nhist, float* h_Lq, uint32_t cap, uint32_t* n_out) {

@@ -104,6 +104,12 @@ struct gi_context {
   float4* d_recon = nullptr;         // [P*64] rgb, distance (-1: empty cell)
   uint32_t* d_cdf = nullptr;         // [P*64] inclusive weight sums
   bool guided = false;               // this frame's spawn built them
+  // light grid (config light_grid): box of the frame's hits (order-preserving float codes),
+  // per cell the light list and its length
+  uint32_t* d_lg_box = nullptr;      // [6] min x, y, z, max x, y, z
+  uint32_t* d_lg_part = nullptr;     // [blocks of 256 rays][6] partial boxes
+  uint32_t* d_lg_list = nullptr;     // [dim^3][lgrid_k]
+  uint32_t* d_lg_count = nullptr;    // [dim^3]
   bool has_prev = false;             // a previous frame's probes are stored
   bool reprojected = false;          // this frame's spawn reprojected them
   gi_frame prev_frame{};

@@ -15,9 +15,14 @@ struct ShadeTables {
   const float4* mats;    // [2m] albedo, [2m+1] emission
   const uint32_t* etri;
   const uint32_t* ethr;
-  const float4* evert;   // [3 * n_emit] emitter vertices in emitter order
+  const float4* evert;   // [3 * n_emit] emitter vertices in emitter order (first w: area)
   uint32_t n_emit;
   float area_total;
+  // light grid (config light_grid; null list = area-proportional sampling)
+  const uint32_t* lg_box;
+  const uint32_t* lg_list;
+  const uint32_t* lg_count;
+  uint32_t lg_dim, lg_k, ris_m;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -674,6 +679,237 @@ __device__ inline LightSample sample_light(const ShadeTables& st, uint32_t seed,
   return ls;
 }
 
+// Section 2.3: resampled importance sampling over the light-grid cell of the hit point y.
+// Candidates j: a light picked uniformly from the cell's list (hash dimension 16 + 4j), a
+// uniform point on it (17 + 4j, 18 + 4j); weight = target / source pdf = lum * cos_y * cos_l
+// / d^2 * count * area; weighted reservoir sampling keeps candidate j when u (19 + 4j) * sum
+// < weight.  The kept light's g is cos_y cos_l / d^2 * sum / (ris_m * target).
+__device__ inline float lum709(float4 le) { return (0.2126f * le.x + 0.7152f * le.y) + 0.0722f * le.z; }
+
+__device__ inline LightSample sample_light_ris(const ShadeTables& st, uint32_t seed, uint32_t frame, uint32_t gid,
+                                               float yx, float yy, float yz, float px, float py, float pz, float nx,
+                                               float ny, float nz) {
+  LightSample ls;
+  ls.cast = false;
+  ls.tmax = 0.0f;
+  ls.g = 0.0f;
+  ls.mat = 0;
+  const LightGridGeom g = light_grid_geom(st.lg_box, st.lg_dim);
+  const float yv[3] = {yx, yy, yz};
+  uint32_t ci[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float f = floorf((yv[k] - g.lo[k]) / g.h);
+    ci[k] = f < 0.0f ? 0u : (f > (float)(g.dim[k] - 1u) ? g.dim[k] - 1u : (uint32_t)f);
+  }
+  const uint32_t cell = (ci[2] * g.dim[1] + ci[1]) * g.dim[0] + ci[0];
+  const uint32_t m = st.lg_count[cell];
+  if (m == 0u) return ls;
+  const uint32_t* list = st.lg_list + (size_t)cell * st.lg_k;
+  float wsum = 0.0f, ph_sel = 0.0f, g_sel = 0.0f, dist_sel = 0.0f;
+  float ox = 0.f, oy = 0.f, oz = 0.f;
+  uint32_t k_sel = 0xFFFFFFFFu;
+  for (uint32_t j = 0; j < st.ris_m; ++j) {
+    const uint32_t rp = rand_u32(seed, frame, gid, 16u + 4u * j);
+    const uint32_t k = list[(uint32_t)(((uint64_t)rp * m) >> 32)];
+    const float u3 = rand_unit(rand_u32(seed, frame, gid, 17u + 4u * j));
+    const float u4 = rand_unit(rand_u32(seed, frame, gid, 18u + 4u * j));
+    const float us = rand_unit(rand_u32(seed, frame, gid, 19u + 4u * j));
+    const uint32_t e = st.etri[k];
+    const float su = sqrtf(u3);
+    const float b0 = 1.0f - su, b1 = su * (1.0f - u4), b2 = su * u4;
+    const float4 A = st.evert[3 * k], B = st.evert[3 * k + 1], C = st.evert[3 * k + 2];
+    const float wx = ((b0 * A.x + b1 * B.x) + b2 * C.x) - px;
+    const float wy = ((b0 * A.y + b1 * B.y) + b2 * C.y) - py;
+    const float wz = ((b0 * A.z + b1 * B.z) + b2 * C.z) - pz;
+    const float d2 = (wx * wx + wy * wy) + wz * wz;
+    float ph = 0.0f, gg = 0.0f, dist = 0.0f, mx = 0.f, my = 0.f, mz = 0.f;
+    if (d2 > 0.0f) {
+      dist = sqrtf(d2);
+      mx = wx / dist;
+      my = wy / dist;
+      mz = wz / dist;
+      const float4 ne = st.tnrm[e];
+      const float cos_y = (nx * mx + ny * my) + nz * mz;
+      const float cos_l = -((ne.x * mx + ne.y * my) + ne.z * mz);
+      if (cos_y > 0.0f && cos_l > 0.0f) {
+        gg = (cos_y * cos_l) / d2;
+        ph = lum709(st.mats[2 * __float_as_uint(ne.w) + 1]) * gg;
+      }
+    }
+    const float wj = (ph * (float)m) * A.w;
+    wsum = wsum + wj;
+    if (wj > 0.0f && us * wsum < wj) {
+      k_sel = k;
+      ph_sel = ph;
+      g_sel = gg;
+      dist_sel = dist;
+      ox = mx;
+      oy = my;
+      oz = mz;
+    }
+  }
+  if (k_sel == 0xFFFFFFFFu) return ls;
+  const float W = wsum / ((float)st.ris_m * ph_sel);
+  ls.cast = true;
+  ls.ray = make_ray(px, py, pz, ox, oy, oz);
+  ls.tmax = dist_sel * 0.9999f;
+  ls.g = g_sel * W;
+  ls.mat = __float_as_uint(st.tnrm[st.etri[k_sel]].w);
+  return ls;
+}
+
+// ------------------------------------------------------------------------------------------
+// Light grid (Section 2.3.2).  The box of this frame's probe-ray hit points: per block the
+// minimum and maximum codes (lg_encode) of the hit coordinates, y = o + t d exactly as the
+// shading computes it, then one block reduces the partial boxes (integer minima and maxima:
+// the box does not depend on the order).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lg_box_partial(ProbeRayArgs a, const uint4* rec, uint32_t* part) {
+  __shared__ uint32_t red[6][4];
+  const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+  uint32_t v[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+  if (gid < a.P * a.R) {
+    const uint4 r = rec[gid];
+    if (r.w & GI_RAY_HIT) {
+      float ox, oy, oz, dx, dy, dz;
+      uint32_t cell;
+      probe_ray(a, gid, gid / a.R, ox, oy, oz, dx, dy, dz, cell);
+      const float t = __uint_as_float(r.y);
+      const uint32_t cx = lg_encode(ox + t * dx), cy = lg_encode(oy + t * dy), cz = lg_encode(oz + t * dz);
+      v[0] = cx; v[1] = cy; v[2] = cz; v[3] = cx; v[4] = cy; v[5] = cz;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t lo = __shfl_xor(v[k], o, 64), hi = __shfl_xor(v[3 + k], o, 64);
+      v[k] = lo < v[k] ? lo : v[k];
+      v[3 + k] = hi > v[3 + k] ? hi : v[3 + k];
+    }
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0u)
+    for (int k = 0; k < 6; ++k) red[k][w] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 6u) {
+    const uint32_t k = threadIdx.x;
+    uint32_t x = red[k][0];
+    for (int i = 1; i < 4; ++i) x = k < 3u ? (red[k][i] < x ? red[k][i] : x) : (red[k][i] > x ? red[k][i] : x);
+    part[(size_t)blockIdx.x * 6 + k] = x;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_lg_box_final(const uint32_t* part, uint32_t nparts, uint32_t* box) {
+  __shared__ uint32_t red[6][16];
+  uint32_t v[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+  for (uint32_t b = threadIdx.x; b < nparts; b += 1024u)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const uint32_t x = part[(size_t)b * 6 + k];
+      v[k] = k < 3 ? (x < v[k] ? x : v[k]) : (x > v[k] ? x : v[k]);
+    }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t lo = __shfl_xor(v[k], o, 64), hi = __shfl_xor(v[3 + k], o, 64);
+      v[k] = lo < v[k] ? lo : v[k];
+      v[3 + k] = hi > v[3 + k] ? hi : v[3 + k];
+    }
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0u)
+    for (int k = 0; k < 6; ++k) red[k][w] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 6u) {
+    const uint32_t k = threadIdx.x;
+    uint32_t x = red[k][0];
+    for (int i = 1; i < 16; ++i) x = k < 3u ? (red[k][i] < x ? red[k][i] : x) : (red[k][i] > x ? red[k][i] : x);
+    box[k] = x;
+  }
+}
+
+// Light lists, one wave per grid cell: each light's importance (mean over the cell's 8
+// corners of luminance * area * cos / max(d^2, area); culled when the cell's bounding sphere
+// lies behind the light's plane or beyond its range sqrt(luminance * area / threshold) plus
+// the radius) into LDS, then lgrid_k rounds of the largest importance > 0 (ties: lower index).
+constexpr uint32_t kLgMaxLights = 2048;
+
+__global__ __launch_bounds__(64) void k_light_grid(ShadeTables st, uint32_t n_emit, float threshold, uint32_t* list,
+                                                   uint32_t* count) {
+  __shared__ float imp[kLgMaxLights];
+  const LightGridGeom g = light_grid_geom(st.lg_box, st.lg_dim);
+  const uint32_t ncell = g.dim[0] * g.dim[1] * g.dim[2];
+  const uint32_t ci = blockIdx.x, lane = threadIdx.x;
+  if (ci >= ncell) return;
+  const uint32_t cxyz[3] = {ci % g.dim[0], (ci / g.dim[0]) % g.dim[1], ci / (g.dim[0] * g.dim[1])};
+  float cc[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) cc[j] = g.lo[j] + ((float)cxyz[j] + 0.5f) * g.h;
+  const float R = g.h * 0.8660254037844386f;
+  for (uint32_t k = lane; k < n_emit; k += 64u) {
+    const float4 A = st.evert[3 * k], B = st.evert[3 * k + 1], C = st.evert[3 * k + 2];
+    const float cen[3] = {(float)((((double)A.x + (double)B.x) + (double)C.x) / 3.0),
+                          (float)((((double)A.y + (double)B.y) + (double)C.y) / 3.0),
+                          (float)((((double)A.z + (double)B.z) + (double)C.z) / 3.0)};
+    const float4 n = st.tnrm[st.etri[k]];
+    const float phi = lum709(st.mats[2 * __float_as_uint(n.w) + 1]) * A.w;
+    float v = -1.0f;
+    const float sd = ((cc[0] - cen[0]) * n.x + (cc[1] - cen[1]) * n.y) + (cc[2] - cen[2]) * n.z;
+    const float ex = cc[0] - cen[0], ey = cc[1] - cen[1], ez = cc[2] - cen[2];
+    const float dist = sqrtf((ex * ex + ey * ey) + ez * ez);
+    const float range = sqrtf(phi / threshold);
+    if (!(sd < -R) && !(dist > range + R)) {
+      float s = 0.0f;
+      for (uint32_t q = 0; q < 8u; ++q) {
+        float vv3[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) vv3[j] = (g.lo[j] + (float)(cxyz[j] + ((q >> j) & 1u)) * g.h) - cen[j];
+        const float vv = (vv3[0] * vv3[0] + vv3[1] * vv3[1]) + vv3[2] * vv3[2];
+        const float len = sqrtf(vv);
+        const float cs = len > 0.0f ? ((vv3[0] * n.x + vv3[1] * n.y) + vv3[2] * n.z) / len : 0.0f;
+        if (cs > 0.0f) s = s + (phi * cs) / (vv > A.w ? vv : A.w);
+      }
+      v = s * 0.125f;
+    }
+    imp[k] = v;
+  }
+  __syncthreads();
+  const uint32_t K = st.lg_k < n_emit ? st.lg_k : n_emit;
+  uint32_t cnt = 0;
+  for (uint32_t r = 0; r < K; ++r) {
+    float bv = -1.0f;
+    uint32_t bi = 0xFFFFFFFFu;
+    for (uint32_t k = lane; k < n_emit; k += 64u) {
+      const float x = imp[k];
+      if (x > 0.0f && (bi == 0xFFFFFFFFu || x > bv)) {
+        bv = x;
+        bi = k;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const float ov = __shfl_xor(bv, o, 64);
+      const uint32_t oi = __shfl_xor(bi, o, 64);
+      const bool better = oi != 0xFFFFFFFFu && (bi == 0xFFFFFFFFu || ov > bv || (ov == bv && oi < bi));
+      if (better) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (bi == 0xFFFFFFFFu) break;
+    if (lane == 0u) {
+      list[(size_t)ci * st.lg_k + cnt] = bi;
+      imp[bi] = -1.0f;
+    }
+    ++cnt;
+    __syncthreads();
+  }
+  if (lane == 0u) count[ci] = cnt;
+}
+
 template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeTables st, ProbeRayArgs a,
                                                             CacheArgs c, uint4* rec, uint2* rkey, HitList hl,
@@ -721,7 +957,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float eps = origin_offset(a.eps_scale, yx, yy, yz);
   const float px = yx + nx * eps, py = yy + ny * eps, pz = yz + nz * eps;
   float E0 = 0.f, E1 = 0.f, E2 = 0.f;
-  const LightSample ls = sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
+  const LightSample ls = st.lg_list ? sample_light_ris(st, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
+                                    : sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
   const bool cast = ls.cast;
   bool occl = false;
   if (cast) {
@@ -1509,8 +1746,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
         const float yx = ox + t * dx, yy = oy + t * dy, yz = oz + t * dz;
         const float nx = sg * n.x, ny = sg * n.y, nz = sg * n.z;
         const float eps = origin_offset(a.eps_scale, yx, yy, yz);
-        const LightSample ls = sample_light(st, a.seed, a.frame, gid, yx + nx * eps, yy + ny * eps, yz + nz * eps,
-                                            nx, ny, nz);
+        const float px = yx + nx * eps, py = yy + ny * eps, pz = yz + nz * eps;
+        const LightSample ls = st.lg_list
+                                   ? sample_light_ris(st, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
+                                   : sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
         if (ls.cast) {
           shadow = true;
           (void)any_hit<STACK, kTraceBlock, true>(sv, ls.ray, ls.tmax, ts, &sn, &st_);
@@ -1564,6 +1803,12 @@ static ShadeTables shade_tables(const gi_context* c) {
   t.evert = c->d_evert;
   t.n_emit = c->n_emit;
   t.area_total = c->area_total;
+  t.lg_box = c->cfg.light_grid ? c->d_lg_box : nullptr;
+  t.lg_list = c->cfg.light_grid ? c->d_lg_list : nullptr;
+  t.lg_count = c->cfg.light_grid ? c->d_lg_count : nullptr;
+  t.lg_dim = c->cfg.lgrid_dim;
+  t.lg_k = c->cfg.lgrid_k;
+  t.ris_m = c->cfg.ris_candidates;
   return t;
 }
 
@@ -1733,6 +1978,14 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
   const LearnedShadeOut lso = learned_shade_out(c);
   if (lso.trec_count) k_zero_u32<<<1, 64, 0, s>>>(lso.trec_count, 1);
   GI_TIMED(c, "trace_probes", s, (k_trace_probes<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
+  if (c->cfg.light_grid) {
+    // the light grid over this frame's hit points, before the shading that samples it
+    const uint32_t nb = blocks(n, 256);
+    GI_TIMED(c, "lg_box", s, (k_lg_box_partial<<<nb, 256, 0, s>>>(a, c->d_rec, c->d_lg_part)));
+    GI_TIMED(c, "lg_box_final", s, (k_lg_box_final<<<1, 1024, 0, s>>>(c->d_lg_part, nb, c->d_lg_box)));
+    const uint32_t G = c->cfg.lgrid_dim;
+    GI_TIMED(c, "light_grid", s, (k_light_grid<<<G * G * G, 64, 0, s>>>(st, c->n_emit, c->cfg.lgrid_threshold, c->d_lg_list, c->d_lg_count)));
+  }
   GI_TIMED(c, "shade_hits", s, (k_shade_hits<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), learned_shade_out(c), c->d_stats)));
   return hipGetLastError();
 }

@@ -44,7 +44,8 @@ class Config(C.Structure):
                 ("scene_min", C.c_float * 4), ("scene_max", C.c_float * 4),
                 ("lod_scale", C.c_float), ("temporal", C.c_uint32), ("upscale", C.c_uint32),
                 ("ray_guiding", C.c_uint32), ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32),
-                ("reserved2", C.c_uint32 * 2)]
+                ("light_grid", C.c_uint32), ("ris_candidates", C.c_uint32), ("lgrid_dim", C.c_uint32),
+                ("lgrid_k", C.c_uint32), ("lgrid_threshold", C.c_float), ("reserved3", C.c_uint32 * 3)]
 
 
 class Frame(C.Structure):
@@ -57,7 +58,8 @@ DEFAULTS = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces
                 max_life=32, n_cap=256, seed=3, frac_bits=12, cache_mode=CACHE_PLAIN,
                 cell_scale=10.0, r_max=64.0, eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0),
                 mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4,
-                mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_loss_scale=128.0, mlp_judge=0.1, tile_min_samples=16)
+                mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_loss_scale=128.0, mlp_judge=0.1, tile_min_samples=16,
+                ris_candidates=4, lgrid_dim=16, lgrid_k=8, lgrid_threshold=1e-3)
 
 _lib = None
 
@@ -86,6 +88,7 @@ def lib():
     fn("gi_build_bvh", st, vp, vp, u32, vp, u32, vp, vp, u32)
     fn("gi_bvh_build_host", st, vp, u32, vp, u32, vp, u32, P(u32), P(u32), P(u32))
     fn("gi_tiles_export", st, vp, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
+    fn("gi_light_grid_export", st, vp, vp, vp, vp, vp, u32)
     fn("gi_set_dynamic_triangles", st, vp, vp, vp, u32, vp)
     fn("gi_render_gbuffer", st, vp, P(Frame), vp, vp, vp, vp, vp)
     fn("gi_spawn_probes", st, vp, P(Frame), vp, vp, vp, vp)
@@ -356,6 +359,20 @@ class Context:
         o = np.argsort(ident[:k], kind="stable")
         return dict(id=ident[:k][o], key=key[:k][o], life=life[:k][o], acc=acc[:k][o], L=L[:k][o],
                     nhist=nh[:k][o], Lq=Lq[:k][o])
+
+    def light_grid(self):
+        """light grid of the last trace (light_grid = 1): origin, cell side, dims, per-cell
+        lists (emitter indices) and counts"""
+        D = int(self.cfg_dict["lgrid_dim"])
+        K = int(self.cfg_dict["lgrid_k"])
+        geom = np.zeros(4, np.float32)
+        dims = np.zeros(3, np.uint32)
+        lst = np.zeros(D * D * D * K, np.uint32)
+        cnt = np.zeros(D * D * D, np.uint32)
+        self._check(lib().gi_light_grid_export(self.h, geom.ctypes.data, dims.ctypes.data, lst.ctypes.data,
+                                               cnt.ctypes.data, D * D * D), "gi_light_grid_export")
+        n = int(np.prod(dims))
+        return dict(lo=geom[:3].copy(), h=float(geom[3]), dims=dims, list=lst[:n * K].reshape(n, K), count=cnt[:n])
 
     def cache_save(self) -> bytes:
         n = C.c_size_t()

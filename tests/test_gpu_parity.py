@@ -62,6 +62,13 @@ def _run_stage_parity(scene, cfg, frames, check_every=True, camera=None):
         tiled = cfg.get("cache_tiles", 0)
         gt, ot = (pr.ctx.tiles(), pr.ost.tiles()) if tiled else (pr.ctx.table(), pr.ost.table())
         _compare_table(gt, ot)
+        if cfg.get("light_grid", 0):
+            gl, ol = pr.ctx.light_grid(), pr.ost.light_grid()
+            assert np.array_equal(gl["dims"], ol["dims"]), "light grid dims differ"
+            assert np.array_equal(bits(gl["lo"]), bits(ol["lo"].astype(np.float32))) and gl["h"] == ol["h"]
+            assert np.array_equal(gl["count"], ol["count"]), "light list lengths differ"
+            for c in np.nonzero(ol["count"])[0]:
+                assert np.array_equal(gl["list"][c, :ol["count"][c]], ol["list"][c, :ol["count"][c]]), c
         gs, os_ = pr.ctx.stats(), pr.ost.stats()
         for k in ("rays", "hits", "inserts", "overflow", "nonfinite", "wraps", "shadow", "occluded", "bounce"):
             assert gs[k] == os_[k], f"stat {k}: gpu {gs[k]} oracle {os_[k]}"
@@ -304,6 +311,27 @@ def test_two_level_cache_field_levels_of_detail_and_query():
     want = pr.ost.query(pos, nrm)
     assert np.array_equal(got[:, 3], want[:, 3]) and got[:, 3].sum() > 0.5 * len(pos)
     assert_close(got[:, :3], want[:, :3], what="queried prefiltered radiance")
+
+
+def test_light_grid_ris_many_light_room():
+    """light sampling by RIS over the light grid (Section 2.3) on the room lit by 64 small
+    quads, ragged 100x76, two bounces, three frames: the box of the hits, the grid and every
+    cell's light list bit-exact, then every ray's record, the shadow-ray counts and the
+    fixed-point sums (the picks of the reservoirs) bit-exact, atlas, SH and irradiance"""
+    sc = I.lights_room_scene()
+    pr = _run_stage_parity(sc, dict(width=100, height=76, rays_per_probe=32, table_log2=16, bounces=2,
+                                    light_grid=1, lgrid_dim=8, lgrid_k=12, ris_candidates=4, lgrid_threshold=1e-3),
+                           [0, 1, 2], camera=lambda f: I.room_camera(0))
+    g = pr.ctx.light_grid()
+    assert (g["count"] > 0).mean() > 0.5 and pr.ctx.stats()["shadow"] > 0
+
+
+def test_light_grid_field_moving_light():
+    """the grid and RIS on the field, whose moving light changes the emitters every frame;
+    one candidate (a uniform pick from the cell's list) and the default grid"""
+    sc = I.field_scene()
+    _run_stage_parity(sc, dict(width=160, height=96, rays_per_probe=32, table_log2=17, sky=sc.sky, light_grid=1,
+                               ris_candidates=1), [0, 1])
 
 
 def test_room_overflowing_table_invariants():

@@ -33,7 +33,7 @@ def test_ris_is_unbiased_with_full_lists(m):
     qb, tb = _quad(1.5, 2.5, 0.5, 0.25)
     sc = _tri_scene(ta + tb, [[0, 0, 0, 10, 10, 10]] * 2 + [[0, 0, 0, 40, 20, 10]] * 2)
     osc = O.OracleScene(sc, f64=True)
-    st = O.OracleFrameState(osc, O.default_config(light_grid=1, lgrid_dim=4, lgrid_k=8, ris_m=m, lgrid_tau=1e-9))
+    st = O.OracleFrameState(osc, O.default_config(light_grid=1, lgrid_dim=4, lgrid_k=8, ris_candidates=m, lgrid_threshold=1e-9))
     st.light_grid_set([-2.0, -1.0, -2.0], [2.0, 3.0, 2.0])
     g = st.light_grid()
     p = np.array([0.3, 0.0, -0.2])
@@ -67,7 +67,7 @@ def test_culling_and_order():
     qa, ta = _quad(-3.0, 2.0, 0.0, 0.25, down=True)
     qb, tb = _quad(3.0, 2.0, 0.0, 0.25, down=False)
     sc = _tri_scene(ta + tb, [[0, 0, 0, 20, 20, 20]] * 2 + [[0, 0, 0, 20, 20, 20]] * 2)
-    cfg = O.default_config(light_grid=1, lgrid_dim=8, lgrid_k=8, lgrid_tau=1e-6)
+    cfg = O.default_config(light_grid=1, lgrid_dim=8, lgrid_k=8, lgrid_threshold=1e-6)
     st = O.OracleFrameState(O.OracleScene(sc, f64=True), cfg)
     st.light_grid_set([-4.0, -2.5, -4.0], [4.0, 5.5, 4.0])      # cells of 1 m, y from -2.5
     g = st.light_grid()
@@ -91,9 +91,9 @@ def test_culling_and_order():
     # 0.7 m away, B 5.5 m, so A's triangles come first
     both = lights(-2.5, 2.0, 0.5)
     assert set(both) == {0, 1, 2, 3} and set(both[:2]) == {0, 1}
-    # a tiny range (large threshold) culls the far light: tau makes sqrt(phi / tau) 1 m
+    # a tiny range (large threshold) culls the far light: the threshold makes sqrt(phi / tau) 1 m
     phi = 20.0 * 0.5 * 0.5 / 2          # luminance 20, area 0.125 per triangle
-    st2 = O.OracleFrameState(O.OracleScene(sc, f64=True), dict(cfg, lgrid_tau=phi))
+    st2 = O.OracleFrameState(O.OracleScene(sc, f64=True), dict(cfg, lgrid_threshold=phi))
     st2.light_grid_set([-4.0, -2.5, -4.0], [4.0, 5.5, 4.0])
     g2 = st2.light_grid()
     c = cell(-3.0, -1.5, 0.5)
@@ -118,7 +118,7 @@ def test_lists_are_ordered_and_capped():
 def _frames(sc, light_grid, frames=3, W=64, H=48, R=32):
     osc = O.OracleScene(sc, f64=False)
     cfg = O.default_config(width=W, height=H, rays_per_probe=R, table_log2=15, light_grid=light_grid,
-                           lgrid_dim=8, lgrid_k=16, ris_m=4)
+                           lgrid_dim=8, lgrid_k=16, ris_candidates=4)
     st = O.OracleFrameState(osc, cfg)
     fr = I.room_camera(0)
     irr = []
