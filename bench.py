@@ -232,6 +232,7 @@ def main():
         forms["temporal_upscale_2x2"] = temporal_measure(log, upscale=2, with_cpu=False)
         forms["temporal_upscale_2x2_guided"] = temporal_measure(log, upscale=2, ray_guiding=1, with_cpu=False)
         forms["temporal_quality"] = temporal_quality(log)
+        forms["light_sampling"] = light_sampling_measure(log)
 
     line = {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
@@ -606,6 +607,76 @@ def temporal_quality(log, W=512, H=288, R=64, frames=32, ref_R=256, ref_frames=9
         level = (fr.mean(-1)[:, on].mean() / lum[on].mean()).item()
         res["modes"][name] = {"rel_l1": round(err, 4), "level": round(level, 4), "rays_per_frame": int(rays)}
         log(f"[bench] temporal quality {name}: rel L1 {err:.4f}, level {level:.3f}, {int(rays)} rays/frame")
+    return res
+
+
+def light_sampling_measure(log, W=1920, H=1080, R=64, frames=16, timed_from=8, ref_R=128, ref_frames=96):
+    """Light sampling on the room lit by 64 small quads of very different radiance: the plain
+    cache's radiance at visible surface points (every 61st pixel of the frame-0 G-buffer)
+    after 16 frames, against a converged run (area-proportional sampling, 128 rays per probe,
+    96 frames, a long moving average), for area-proportional sampling and for RIS over the
+    light grid with 1, 4 and 8 candidates and cell lists of 16, 64 and all 128 emitter
+    triangles; ms/frame over frames 8..15 and the light grid's kernels."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19855_amd import gi
+    from paper_2310_19855_amd import inputs as I
+    scene = I.lights_room_scene()
+    cam = I.room_camera(0)
+
+    def run(R_, nframes, n_cap, **kw):
+        ctx = gi.Context(width=W, height=H, rays_per_probe=R_, table_log2=20, bounces=1, n_cap=n_cap, **kw)
+        ctx.build_bvh(scene)
+        gb = gi.GBuffer(H, W)
+        out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+        ctx.render_gbuffer(cam, gb.pos, gb.nrm, gb.alb, gb.prim)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for f in range(nframes):
+            cam.index = f
+            if f == timed_from:
+                torch.cuda.synchronize()
+                ctx.profile(True)
+                ctx.profile_read()
+                e0.record()
+            ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
+            ctx.trace_probes(cam)
+            ctx.cache_update(cam)
+            ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, out)
+        e1.record()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ms = e0.elapsed_time(e1) / max(nframes - timed_from, 1)
+        hit = gb.prim.reshape(-1) != 0xFFFFFFFF
+        pos = gb.pos.reshape(-1, 4)[hit][::61].clone()
+        nrm = gb.nrm.reshape(-1, 4)[hit][::61].clone()
+        pos[:, 3] = -1.0
+        q = torch.zeros((pos.shape[0], 4), dtype=torch.float32, device="cuda")
+        ctx.cache_query(pos, nrm, q)
+        torch.cuda.synchronize()
+        ctx.close()
+        n = max(nframes - timed_from, 1)
+        return ms, q.cpu().numpy(), {k: round(v[1] / n, 5) for k, v in prof.items()}
+
+    _, ref, _ = run(ref_R, ref_frames, 1024)
+    modes = {"area": {}, "ris4_k16": dict(light_grid=1, ris_candidates=4, lgrid_k=16),
+             "ris4_k64": dict(light_grid=1, ris_candidates=4, lgrid_k=64),
+             "ris1_k128": dict(light_grid=1, ris_candidates=1, lgrid_k=128),
+             "ris4_k128": dict(light_grid=1, ris_candidates=4, lgrid_k=128),
+             "ris8_k128": dict(light_grid=1, ris_candidates=8, lgrid_k=128)}
+    res = {"workload": f"lights_room (64 emissive quads, radiance 2..200) {W}x{H}, R={R}, one bounce, frames "
+                       f"0..{frames - 1}, ms/frame over {timed_from}..{frames - 1}; relMAE of the cache radiance at "
+                       f"visible points vs area sampling at R={ref_R} over {ref_frames} frames", "modes": {}}
+    for name, kw in modes.items():
+        ms, q, kern = run(R, frames, 256, **kw)
+        both = (q[:, 3] > 0) & (ref[:, 3] > 0)
+        e = float(np.abs(q[both, :3] - ref[both, :3]).sum() / max(np.abs(ref[both, :3]).sum(), 1e-30))
+        lg = {k: v for k, v in kern.items() if k in ("lg_box", "lg_box_final", "light_grid", "shade_hits")}
+        res["modes"][name] = {"ms_per_frame": round(ms, 4), "relMAE": round(e, 5), "points": int(both.sum()),
+                              "kernels_ms": lg}
+        log(f"[bench] light sampling {name}: relMAE {e:.4f} @ {ms:.3f} ms/frame {lg}")
     return res
 
 

@@ -128,7 +128,7 @@ typedef struct gi_config {
     uint32_t tile_min_samples;
     /* 1: light sampling by RIS over a light grid (Section 2.3).  After the probe rays, a grid
      * of cubic cells (longest axis in lgrid_dim cells, 1..32) is laid over the box of the
-     * frame's hit points; each cell keeps the lgrid_k (1..32) emitter triangles of largest
+     * frame's hit points; each cell keeps the lgrid_k (1..256) emitter triangles of largest
      * importance (mean over its corners of luminance * area * cos / max(d^2, area)), lights
      * facing away from the cell or farther than sqrt(luminance * area / lgrid_threshold)
      * culled.  Each hit draws ris_candidates (1..8) candidates from its cell's list (a

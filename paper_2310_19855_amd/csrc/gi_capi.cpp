@@ -268,9 +268,9 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->cache_tiles && g->cache_mode != GI_CACHE_PLAIN) { why = "cache_tiles needs the plain cache"; return GI_ERR_INVALID_ARG; }
   if (g->cache_tiles && g->table_log2 > 22) { why = "cache_tiles: table_log2 (tiles) out of [6, 22]"; return GI_ERR_INVALID_ARG; }
   if (g->light_grid > 1) { why = "light_grid must be 0 or 1"; return GI_ERR_INVALID_ARG; }
-  if (g->light_grid && (g->lgrid_dim < 1 || g->lgrid_dim > 32 || g->lgrid_k < 1 || g->lgrid_k > 32 ||
+  if (g->light_grid && (g->lgrid_dim < 1 || g->lgrid_dim > 32 || g->lgrid_k < 1 || g->lgrid_k > 256 ||
                         g->ris_candidates < 1 || g->ris_candidates > 8 || !(g->lgrid_threshold > 0.0f))) {
-    why = "light grid: lgrid_dim and lgrid_k in [1, 32], ris_candidates in [1, 8], lgrid_threshold > 0";
+    why = "light grid: lgrid_dim in [1, 32], lgrid_k in [1, 256], ris_candidates in [1, 8], lgrid_threshold > 0";
     return GI_ERR_INVALID_ARG;
   }
   return GI_OK;
