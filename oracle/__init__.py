@@ -36,7 +36,7 @@ class OrcConfig(C.Structure):
                 ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32),
                 ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32), ("light_grid", C.c_uint32),
                 ("lgrid_dim", C.c_uint32), ("lgrid_k", C.c_uint32), ("ris_candidates", C.c_uint32), ("lgrid_threshold", C.c_float),
-                ("pad8", C.c_uint32), ("pad9", C.c_uint32)]
+                ("restir", C.c_uint32), ("restir_log2", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -50,7 +50,8 @@ def default_config(**kw) -> dict:
                max_life=32, n_cap=256, seed=3, frac_bits=12, cell_scale=10.0, r_max=64.0,
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
                temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min_samples=16, light_grid=0,
-               lgrid_dim=16, lgrid_k=8, ris_candidates=4, lgrid_threshold=1e-3)
+               lgrid_dim=16, lgrid_k=8, ris_candidates=4, lgrid_threshold=1e-3,
+               restir=0, restir_log2=16)
     cfg.update(kw)
     return cfg
 
@@ -118,6 +119,7 @@ def _lib(f64: bool):
     fn("prefilter", None, R, U32P, C.c_uint32, R)
     fn("light_grid_export", None, vp, R, U32P, U32P, U32P)
     fn("light_grid_set", None, vp, R, R)
+    fn("restir_export", C.c_uint32, vp, U64P, U64P, R, R, R, U32P, U32P, C.c_uint32)
     fn("poke_cell", C.c_int, vp, C.c_uint64, U32P, R, C.c_uint32, C.c_uint32, C.c_uint32)
     fn("cache_update_only", None, vp)
     fn("stats", None, vp, U64P)
@@ -504,6 +506,21 @@ class OracleFrameState:
         o = np.argsort(ident[:n], kind="stable")
         return dict(id=ident[:n][o], key=key[:n][o], life=life[:n][o], acc=acc[:n][o], L=L[:n][o],
                     nhist=nh[:n][o], Lq=Lq[:n][o])
+
+    def reservoirs(self):
+        """the reservoir table written by the last trace (restir): sorted by (bucket,
+        fingerprint): key, light point, contribution weight, normal, light, count"""
+        cap = 1 << int(self.cfg.get("restir_log2", 16))
+        ident = np.zeros(cap, np.uint64)
+        key = np.zeros(cap, np.uint64)
+        y = np.zeros((cap, 3), self.dt)
+        W = np.zeros(cap, self.dt)
+        n = np.zeros((cap, 3), self.dt)
+        k = np.zeros(cap, np.uint32)
+        M = np.zeros(cap, np.uint32)
+        c = _call(self.f64, "restir_export", self.h, ident, key, y, W, n, k, M, cap)
+        o = np.argsort(ident[:c], kind="stable")
+        return dict(id=ident[:c][o], key=key[:c][o], y=y[:c][o], W=W[:c][o], n=n[:c][o], k=k[:c][o], M=M[:c][o])
 
     def light_grid_set(self, lo, hi):
         """build the light grid over the box [lo, hi] (as a trace does over its hit points)"""

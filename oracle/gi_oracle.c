@@ -679,7 +679,7 @@ typedef struct orc_config {
     uint32_t tile_min, light_grid, lgrid_dim, lgrid_k;
     uint32_t ris_m;
     float lgrid_tau;
-    uint32_t pad8, pad9;
+    uint32_t restir, restir_log2;
 } orc_config;
 
 typedef struct orc_frame {
@@ -769,6 +769,15 @@ typedef struct state {
     uint32_t lg_dim[3];
     uint32_t *lg_list;     /* [dim^3 cap][K] emitter indices (into etri) */
     uint32_t *lg_count;    /* [dim^3 cap] */
+    /* world-space reservoirs (Section 2.3.1): two tables, the previous frame's read, this
+     * frame's written; per slot the light point, contribution weight W, light, count M and
+     * the normal of the vertex that stored it */
+    uint32_t rs_N, rs_cur, rs_has_prev;
+    uint32_t *rs_fp[2], *rs_k[2], *rs_M[2], *rs_claim;
+    uint64_t *rs_key[2];
+    real *rs_y[2], *rs_W[2], *rs_n[2];
+    real *r_rsy, *r_rsW;   /* [P*R][3], [P*R]: each hit's final reservoir */
+    uint32_t *r_rsk, *r_rsM; /* M = 0: none */
     /* probes */
     real *atlas;           /* [P][64][4] */
     real *sh;              /* [P][27] */
@@ -1087,6 +1096,23 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->r_tcell = (uint32_t *)calloc(PR, sizeof(uint32_t));
     st->r_y = (real *)calloc(3 * PR, sizeof(real));
     st->r_ny = (real *)calloc(3 * PR, sizeof(real));
+    if (cfg->restir) {
+        st->rs_N = 1u << cfg->restir_log2;
+        for (int t = 0; t < 2; ++t) {
+            st->rs_fp[t] = (uint32_t *)calloc(st->rs_N, sizeof(uint32_t));
+            st->rs_k[t] = (uint32_t *)calloc(st->rs_N, sizeof(uint32_t));
+            st->rs_M[t] = (uint32_t *)calloc(st->rs_N, sizeof(uint32_t));
+            st->rs_key[t] = (uint64_t *)calloc(st->rs_N, sizeof(uint64_t));
+            st->rs_y[t] = (real *)calloc(3 * (size_t)st->rs_N, sizeof(real));
+            st->rs_W[t] = (real *)calloc(st->rs_N, sizeof(real));
+            st->rs_n[t] = (real *)calloc(3 * (size_t)st->rs_N, sizeof(real));
+        }
+        st->rs_claim = (uint32_t *)calloc(st->rs_N, sizeof(uint32_t));
+        st->r_rsy = (real *)calloc(3 * PR, sizeof(real));
+        st->r_rsW = (real *)calloc(PR, sizeof(real));
+        st->r_rsk = (uint32_t *)calloc(PR, sizeof(uint32_t));
+        st->r_rsM = (uint32_t *)calloc(PR, sizeof(uint32_t));
+    }
     if (cfg->light_grid) {
         size_t ncell = (size_t)cfg->lgrid_dim * cfg->lgrid_dim * cfg->lgrid_dim;
         st->lg_list = (uint32_t *)calloc(ncell * (cfg->lgrid_k ? cfg->lgrid_k : 1), sizeof(uint32_t));
@@ -1119,6 +1145,11 @@ void ORC(destroy)(state *st)
     free(st->fp); free(st->key); free(st->acc); free(st->dacc); free(st->L);
     free(st->nhist); free(st->life); free(st->accessed); free(st->atlas); free(st->sh);
     free(st->Lq); free(st->r_tcell); free(st->r_y); free(st->r_ny); free(st->lg_list); free(st->lg_count);
+    for (int t = 0; t < 2; ++t) {
+        free(st->rs_fp[t]); free(st->rs_k[t]); free(st->rs_M[t]); free(st->rs_key[t]); free(st->rs_y[t]);
+        free(st->rs_W[t]); free(st->rs_n[t]);
+    }
+    free(st->rs_claim); free(st->r_rsy); free(st->r_rsW); free(st->r_rsk); free(st->r_rsM);
     free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
     free(st->hist); free(st->traced); free(st->recon); free(st->cdf);
     free(st);
@@ -1651,71 +1682,213 @@ void ORC(light_grid_export)(const state *st, real *geom /* lo[3], h */, uint32_t
     memcpy(count, st->lg_count, sizeof(uint32_t) * n);
 }
 
-/* RIS over the cell's light list: E (irradiance estimate times pi, before albedo) */
-static void ris_light(const state *st, const orc_frame *fr, uint32_t gid, const real *y, const real *yo,
-                      const real *ny, real *E, uint64_t *stat_shadow, uint64_t *stat_occ)
+/* World-space reservoir reuse (Section 2.3.1): the reservoir table is a spatial hash like the
+ * world cache's over the quantised position alone (the descriptor with normal class 0, no
+ * leak bit; levels of detail as the cache's), with the storing vertex's normal beside it.
+ * READING: a hit reuses the previous frame's reservoir of its cell when the normals' cosine
+ * exceeds 0.9 (bilateral test); the stored count is capped at 20 x ris_m; the reused sample
+ * enters with weight target_here(y) * W * M and one more weighted-reservoir step (hash
+ * dimension 48); every hit's final reservoir (before its shadow ray) is offered to its cell
+ * of this frame's table, where the lowest ray id is kept. */
+static uint64_t pos_key(const orc_config *c, const real *cam, const real *y)
+{
+    orc_config cc = *c;
+    cc.cache_tiles = 0;
+    real n[3] = {RC(1.0), RC(0.0), RC(0.0)};
+    return cell_key_cell(&cc, cam, y, n, RC(0.0), 0, NULL);
+}
+
+static int32_t rs_find(const state *st, int t, uint64_t key)
+{
+    uint32_t nb = st->rs_N / BUCKET;
+    uint32_t b = key_bucket(key, nb), f = key_fingerprint(key);
+    for (uint32_t s = 0; s < BUCKET; ++s)
+        if (st->rs_fp[t][b * BUCKET + s] == f) return (int32_t)(b * BUCKET + s);
+    return -1;
+}
+
+static int32_t rs_insert(state *st, int t, uint64_t key)
+{
+    uint32_t nb = st->rs_N / BUCKET;
+    uint32_t b = key_bucket(key, nb), f = key_fingerprint(key);
+    for (uint32_t s = 0; s < BUCKET; ++s)
+        if (st->rs_fp[t][b * BUCKET + s] == f) return (int32_t)(b * BUCKET + s);
+    for (uint32_t s = 0; s < BUCKET; ++s) {
+        uint32_t slot = b * BUCKET + s;
+        if (st->rs_fp[t][slot] == 0u) {
+            st->rs_fp[t][slot] = f;
+            st->rs_key[t][slot] = key;
+            return (int32_t)slot;
+        }
+    }
+    return -1;
+}
+
+/* a light point x on emitter k seen from yo with normal ny: target (luminance * g) and g */
+static void light_target(const scene *sc, uint32_t k, const real *x, const real *yo, const real *ny, real *ph,
+                         real *g, real *om, real *dist)
+{
+    uint32_t t = sc->etri[k];
+    real w[3];
+    for (int q = 0; q < 3; ++q) w[q] = x[q] - yo[q];
+    real d2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+    *ph = RC(0.0);
+    *g = RC(0.0);
+    *dist = RC(0.0);
+    om[0] = om[1] = om[2] = RC(0.0);
+    if (!(d2 > RC(0.0))) return;
+    *dist = RSQRT(d2);
+    for (int q = 0; q < 3; ++q) om[q] = w[q] / *dist;
+    const real *nl = sc->tn + 3 * (size_t)t;
+    real cos_y = (ny[0] * om[0] + ny[1] * om[1]) + ny[2] * om[2];
+    real cos_l = -((nl[0] * om[0] + nl[1] * om[1]) + nl[2] * om[2]);
+    if (cos_y > RC(0.0) && cos_l > RC(0.0)) {
+        *g = (cos_y * cos_l) / d2;
+        *ph = lum709(sc->mats + 6 * sc->tmat[t] + 3) * *g;
+    }
+}
+
+/* RIS over the cell's light list (+ the previous frame's reservoir with restir): E
+ * (irradiance estimate times pi, before albedo); with restir, the final reservoir of the hit
+ * into the per-ray arrays at gid */
+static void ris_light(state *st, const orc_frame *fr, uint32_t gid, const real *y, const real *yo,
+                      const real *ny, real *E, uint64_t *stat_shadow, uint64_t *stat_occ, int store)
 {
     const orc_config *c = &st->cfg;
     const scene *sc = st->sc;
     uint32_t cell = lgrid_cell_of(st, y);
     uint32_t m = st->lg_count[cell];
     const uint32_t *list = st->lg_list + (size_t)cell * c->lgrid_k;
-    if (m == 0) return;
     real wsum = RC(0.0), ph_sel = RC(0.0), g_sel = RC(0.0), dist_sel = RC(0.0);
-    real om_sel[3] = {RC(0.0), RC(0.0), RC(0.0)};
-    uint32_t k_sel = 0xFFFFFFFFu;
-    for (uint32_t j = 0; j < c->ris_m; ++j) {
-        uint32_t rp = rng_u32(c->seed, fr->index, gid, 16u + 4u * j);
-        uint32_t k = list[(uint32_t)(((uint64_t)rp * m) >> 32)];
-        real u3 = rng_unit(rng_u32(c->seed, fr->index, gid, 17u + 4u * j));
-        real u4 = rng_unit(rng_u32(c->seed, fr->index, gid, 18u + 4u * j));
-        real us = rng_unit(rng_u32(c->seed, fr->index, gid, 19u + 4u * j));
-        uint32_t t = sc->etri[k];
-        real su = RSQRT(u3);
-        real b0 = RC(1.0) - su, b1 = su * (RC(1.0) - u4), b2 = su * u4;
-        const float *v = sc->tv + 9 * (size_t)t;
-        real w[3];
-        for (int q = 0; q < 3; ++q) w[q] = ((b0 * (real)v[q] + b1 * (real)v[3 + q]) + b2 * (real)v[6 + q]) - yo[q];
-        real d2 = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
-        real ph = RC(0.0), g = RC(0.0), dist = RC(0.0);
-        real om[3] = {RC(0.0), RC(0.0), RC(0.0)};
-        if (d2 > RC(0.0)) {
-            dist = RSQRT(d2);
-            for (int q = 0; q < 3; ++q) om[q] = w[q] / dist;
-            const real *nl = sc->tn + 3 * (size_t)t;
-            real cos_y = (ny[0] * om[0] + ny[1] * om[1]) + ny[2] * om[2];
-            real cos_l = -((nl[0] * om[0] + nl[1] * om[1]) + nl[2] * om[2]);
-            if (cos_y > RC(0.0) && cos_l > RC(0.0)) {
-                g = (cos_y * cos_l) / d2;
-                ph = lum709(sc->mats + 6 * sc->tmat[t] + 3) * g;
+    real om_sel[3] = {RC(0.0), RC(0.0), RC(0.0)}, x_sel[3] = {RC(0.0), RC(0.0), RC(0.0)};
+    uint32_t k_sel = 0xFFFFFFFFu, M = 0;
+    if (m > 0) {
+        M = c->ris_m;
+        for (uint32_t j = 0; j < c->ris_m; ++j) {
+            uint32_t rp = rng_u32(c->seed, fr->index, gid, 16u + 4u * j);
+            uint32_t k = list[(uint32_t)(((uint64_t)rp * m) >> 32)];
+            real u3 = rng_unit(rng_u32(c->seed, fr->index, gid, 17u + 4u * j));
+            real u4 = rng_unit(rng_u32(c->seed, fr->index, gid, 18u + 4u * j));
+            real us = rng_unit(rng_u32(c->seed, fr->index, gid, 19u + 4u * j));
+            uint32_t t = sc->etri[k];
+            real su = RSQRT(u3);
+            real b0 = RC(1.0) - su, b1 = su * (RC(1.0) - u4), b2 = su * u4;
+            const float *v = sc->tv + 9 * (size_t)t;
+            real x[3];
+            for (int q = 0; q < 3; ++q) x[q] = (b0 * (real)v[q] + b1 * (real)v[3 + q]) + b2 * (real)v[6 + q];
+            real ph, g, dist, om[3];
+            light_target(sc, k, x, yo, ny, &ph, &g, om, &dist);
+            real A = (real)tri_area_f64(v);
+            real wj = (ph * (real)m) * A;
+            wsum = wsum + wj;
+            if (wj > RC(0.0) && us * wsum < wj) {
+                k_sel = k;
+                ph_sel = ph;
+                g_sel = g;
+                dist_sel = dist;
+                for (int q = 0; q < 3; ++q) { om_sel[q] = om[q]; x_sel[q] = x[q]; }
             }
         }
-        real A = (real)tri_area_f64(v);
-        real wj = (ph * (real)m) * A;
-        wsum = wsum + wj;
-        if (wj > RC(0.0) && us * wsum < wj) {
-            k_sel = k;
-            ph_sel = ph;
-            g_sel = g;
-            dist_sel = dist;
-            for (int q = 0; q < 3; ++q) om_sel[q] = om[q];
+    }
+    if (c->restir && st->rs_has_prev) {
+        int pt = (int)st->rs_cur;
+        int32_t s = rs_find(st, pt, pos_key(c, st->cam, y));
+        if (s >= 0) {
+            const real *np = st->rs_n[pt] + 3 * (size_t)s;
+            real cn = (ny[0] * np[0] + ny[1] * np[1]) + ny[2] * np[2];
+            if (cn > RC(0.9)) {
+                uint32_t kp = st->rs_k[pt][s];
+                const real *xp = st->rs_y[pt] + 3 * (size_t)s;
+                uint32_t cap = 20u * c->ris_m;
+                uint32_t Mp = st->rs_M[pt][s] < cap ? st->rs_M[pt][s] : cap;
+                real ph, g, dist, om[3];
+                light_target(sc, kp, xp, yo, ny, &ph, &g, om, &dist);
+                real wp = (ph * st->rs_W[pt][s]) * (real)Mp;
+                wsum = wsum + wp;
+                real us = rng_unit(rng_u32(c->seed, fr->index, gid, 48u));
+                if (wp > RC(0.0) && us * wsum < wp) {
+                    k_sel = kp;
+                    ph_sel = ph;
+                    g_sel = g;
+                    dist_sel = dist;
+                    for (int q = 0; q < 3; ++q) { om_sel[q] = om[q]; x_sel[q] = xp[q]; }
+                }
+                M = M + Mp;
+            }
         }
     }
     if (k_sel == 0xFFFFFFFFu) return;
+    real W = wsum / ((real)M * ph_sel);
+    if (store && c->restir) {
+        st->r_rsM[gid] = M;
+        st->r_rsk[gid] = k_sel;
+        st->r_rsW[gid] = W;
+        for (int q = 0; q < 3; ++q) st->r_rsy[3 * (size_t)gid + q] = x_sel[q];
+    }
     (*stat_shadow)++;
     if (any_hit(sc, yo, om_sel, dist_sel * RC(0.9999))) {
         (*stat_occ)++;
         return;
     }
-    real W = wsum / ((real)c->ris_m * ph_sel);
     const float *le = sc->mats + 6 * sc->tmat[sc->etri[k_sel]] + 3;
     real gw = g_sel * W;
     for (int q = 0; q < 3; ++q) E[q] = (real)le[q] * gw;
 }
 
-static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const real *y,
+/* this frame's reservoirs into the table written this frame (ray order: the lowest ray id of
+ * a cell stays), then that table becomes the one read next frame */
+static void restir_store(state *st)
+{
+    int nt = (int)(st->rs_cur ^ 1u);
+    memset(st->rs_fp[nt], 0, sizeof(uint32_t) * st->rs_N);
+    memset(st->rs_key[nt], 0, sizeof(uint64_t) * st->rs_N);
+    memset(st->rs_claim, 0, sizeof(uint32_t) * st->rs_N);
+    size_t PR = (size_t)st->P * st->R;
+    for (size_t gid = 0; gid < PR; ++gid) {
+        if (!(st->r_cell[gid] & 0x100u) || st->r_rsM[gid] == 0) continue;
+        int32_t s = rs_insert(st, nt, pos_key(&st->cfg, st->cam, st->r_y + 3 * gid));
+        if (s < 0 || st->rs_claim[s]) continue;
+        st->rs_claim[s] = 1;
+        st->rs_k[nt][s] = st->r_rsk[gid];
+        st->rs_M[nt][s] = st->r_rsM[gid];
+        st->rs_W[nt][s] = st->r_rsW[gid];
+        for (int q = 0; q < 3; ++q) {
+            st->rs_y[nt][3 * (size_t)s + q] = st->r_rsy[3 * gid + q];
+            st->rs_n[nt][3 * (size_t)s + q] = st->r_ny[3 * gid + q];
+        }
+    }
+    st->rs_cur = (uint32_t)nt;
+    st->rs_has_prev = 1;
+}
+
+/* the reservoir table written by the last trace, live slots in slot order */
+uint32_t ORC(restir_export)(const state *st, uint64_t *id, uint64_t *key, real *y, real *W, real *n, uint32_t *k,
+                            uint32_t *M, uint32_t cap)
+{
+    if (!st->cfg.restir) return 0;
+    int t = (int)st->rs_cur;
+    uint32_t cnt = 0;
+    for (uint32_t s = 0; s < st->rs_N; ++s) {
+        if (st->rs_fp[t][s] == 0u) continue;
+        if (cnt < cap) {
+            id[cnt] = ((uint64_t)(s / BUCKET) << 32) | st->rs_fp[t][s];
+            key[cnt] = st->rs_key[t][s];
+            for (int q = 0; q < 3; ++q) {
+                y[3 * (size_t)cnt + q] = st->rs_y[t][3 * (size_t)s + q];
+                n[3 * (size_t)cnt + q] = st->rs_n[t][3 * (size_t)s + q];
+            }
+            W[cnt] = st->rs_W[t][s];
+            k[cnt] = st->rs_k[t][s];
+            M[cnt] = st->rs_M[t][s];
+        }
+        ++cnt;
+    }
+    return cnt;
+}
+
+static void shade_hit(state *st, const orc_frame *fr, uint32_t gid, const real *y,
                       const real *ny, real *s_out, int32_t *bslot, uint64_t *stat_shadow,
-                      uint64_t *stat_occ, uint64_t *stat_bounce)
+                      uint64_t *stat_occ, uint64_t *stat_bounce, int store)
 {
     const orc_config *c = &st->cfg;
     const scene *sc = st->sc;
@@ -1724,7 +1897,7 @@ static void shade_hit(const state *st, const orc_frame *fr, uint32_t gid, const 
     real yo[3];
     for (int k = 0; k < 3; ++k) yo[k] = y[k] + ny[k] * eps;
     if (sc->ne > 0 && c->light_grid) {
-        ris_light(st, fr, gid, y, yo, ny, E, stat_shadow, stat_occ);
+        ris_light(st, fr, gid, y, yo, ny, E, stat_shadow, stat_occ, store);
     } else if (sc->ne > 0) {
         uint32_t e = sc->etri[pick_emitter(sc, rng_u32(c->seed, fr->index, gid, 2u))];
         real u3 = rng_unit(rng_u32(c->seed, fr->index, gid, 3u));
@@ -1868,8 +2041,9 @@ void ORC(trace)(state *st, const orc_frame *fr)
         size_t gid = (size_t)g;
         if (!(st->r_cell[gid] & 0x100u)) continue;
         real s[3];
+        if (c->restir) st->r_rsM[gid] = 0;
         shade_hit(st, fr, (uint32_t)gid, st->r_y + 3 * gid, st->r_ny + 3 * gid, s, &st->r_bslot[gid], &nshadow,
-                  &nocc, &nbounce);
+                  &nocc, &nbounce, 1);
         const float *m = sc->mats + 6 * sc->tmat[st->r_tri[gid]];
         for (int k = 0; k < 3; ++k) st->r_sample[3 * gid + k] = (real)m[k] * s[k];
         st->r_valid[gid] = 1;
@@ -1913,6 +2087,7 @@ void ORC(trace)(state *st, const orc_frame *fr)
     for (size_t gid = 0; gid < PR; ++gid)
         if (st->r_bslot[gid] >= 0)
             st->accessed[st->cfg.cache_tiles ? st->r_bslot[gid] / NCELL : st->r_bslot[gid]] = 1u;
+    if (c->restir && c->light_grid) restir_store(st);
 }
 
 /* NEE radiance estimate E/pi (before albedo) for a surface point and normal, one estimate per
@@ -1926,7 +2101,7 @@ void ORC(nee_samples)(state *st, const orc_frame *fr, const real *y, const real 
     for (long i = 0; i < (long)n; ++i) {
         uint64_t a = 0, b = 0, c = 0;
         int32_t bs;
-        shade_hit(st, fr, ids[i], y, ny, out + 3 * i, &bs, &a, &b, &c);
+        shade_hit(st, fr, ids[i], y, ny, out + 3 * i, &bs, &a, &b, &c, 0);
     }
     st->cfg.bounces = saved;
 }

@@ -138,3 +138,51 @@ def test_frames_on_the_many_light_room():
     assert sr["rays"] == sa["rays"] and sr["hits"] == sa["hits"]
     assert 0 < sr["shadow"] <= sr["hits"]
     assert abs(np.mean(irr_r) / np.mean(irr_a) - 1) < 0.15, (irr_r, irr_a)
+
+
+# --- world-space reservoir reuse (Section 2.3.1) -------------------------------------------
+
+def _restir_frames(sc, restir, frames, W=64, H=48, R=16, m=4):
+    osc = O.OracleScene(sc, f64=False)
+    cfg = O.default_config(width=W, height=H, rays_per_probe=R, table_log2=15, light_grid=1, lgrid_dim=8,
+                           lgrid_k=128, ris_candidates=m, restir=restir, restir_log2=15)
+    st = O.OracleFrameState(osc, cfg)
+    fr = I.room_camera(0)
+    out = []
+    for f in range(frames):
+        fr.index = f
+        g = osc.gbuffer(fr, W, H)
+        st.spawn(fr, g[0], g[1], g[3])
+        st.trace(fr)
+        res = st.reservoirs() if restir else None
+        st.update(fr)
+        irr = st.interpolate(fr, g[0], g[1], g[3])
+        out.append(dict(res=res, irr=float(irr[..., :3].mean())))
+    return st, out
+
+
+def test_reservoirs_accumulate_counts_up_to_the_cap():
+    """frame 0 has nothing to reuse: every stored reservoir holds the 4 candidates of its
+    hit; from frame 1 on the stored counts grow by reuse, and never pass 4 + 20 * 4"""
+    sc = I.lights_room_scene()
+    st, out = _restir_frames(sc, 1, 6)
+    r0 = out[0]["res"]
+    assert len(r0["M"]) > 20 and (r0["M"] == 4).all()
+    assert np.allclose(np.linalg.norm(r0["n"], axis=1), 1.0, atol=1e-5)
+    assert (r0["W"] > 0).all() and (r0["k"] < 128).all()
+    grown = [o["res"]["M"].max() for o in out[1:]]
+    assert grown[0] > 4 and max(grown) <= 84 and grown[-1] >= grown[0]
+    # one reservoir per quantised position: keys are distinct and keep no normal class bits
+    k = out[-1]["res"]["key"]
+    assert len(np.unique(k)) == len(k) and ((k >> np.uint64(54)) & np.uint64(0xF) == 0).all()
+
+
+def test_reservoir_reuse_keeps_the_radiance_level():
+    """reuse resamples the same target (unshadowed contribution), so the irradiance level
+    over frames stays that of RIS alone (within the noise of a few frames)"""
+    sc = I.lights_room_scene()
+    _, on = _restir_frames(sc, 1, 6)
+    _, off = _restir_frames(sc, 0, 6)
+    a = np.mean([o["irr"] for o in on[2:]])
+    b = np.mean([o["irr"] for o in off[2:]])
+    assert abs(a / b - 1) < 0.1, (a, b)
