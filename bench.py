@@ -616,7 +616,9 @@ def light_sampling_measure(log, W=1920, H=1080, R=64, frames=16, timed_from=8, r
     after 16 frames, against a converged run (area-proportional sampling, 128 rays per probe,
     96 frames, a long moving average), for area-proportional sampling and for RIS over the
     light grid with 1, 4 and 8 candidates and cell lists of 16, 64 and all 128 emitter
-    triangles; ms/frame over frames 8..15 and the light grid's kernels."""
+    triangles, and with world-space reservoir reuse (with the default cache history of 256
+    samples, and with 8); the mean level against the reference's, ms/frame over frames 8..15
+    and the light grid's kernels."""
     import numpy as np
     import torch
 
@@ -625,7 +627,9 @@ def light_sampling_measure(log, W=1920, H=1080, R=64, frames=16, timed_from=8, r
     scene = I.lights_room_scene()
     cam = I.room_camera(0)
 
-    def run(R_, nframes, n_cap, **kw):
+    def run(R_, nframes, n_cap_default, **kw):
+        kw = dict(kw)
+        n_cap = kw.pop("n_cap", n_cap_default)
         ctx = gi.Context(width=W, height=H, rays_per_probe=R_, table_log2=20, bounces=1, n_cap=n_cap, **kw)
         ctx.build_bvh(scene)
         gb = gi.GBuffer(H, W)
@@ -665,18 +669,29 @@ def light_sampling_measure(log, W=1920, H=1080, R=64, frames=16, timed_from=8, r
              "ris4_k64": dict(light_grid=1, ris_candidates=4, lgrid_k=64),
              "ris1_k128": dict(light_grid=1, ris_candidates=1, lgrid_k=128),
              "ris4_k128": dict(light_grid=1, ris_candidates=4, lgrid_k=128),
-             "ris8_k128": dict(light_grid=1, ris_candidates=8, lgrid_k=128)}
+             "ris8_k128": dict(light_grid=1, ris_candidates=8, lgrid_k=128),
+             "ris4_k128_reuse": dict(light_grid=1, ris_candidates=4, lgrid_k=128, restir=1, restir_log2=20),
+             # a cache that keeps little history (8 samples), as reservoir reuse is meant to allow
+             "ris4_k128_ncap8": dict(light_grid=1, ris_candidates=4, lgrid_k=128, n_cap=8),
+             "ris4_k128_reuse_ncap8": dict(light_grid=1, ris_candidates=4, lgrid_k=128, restir=1, restir_log2=20,
+                                           n_cap=8),
+             "ris4_k128_reuse_cap1": dict(light_grid=1, ris_candidates=4, lgrid_k=128, restir=1, restir_log2=20,
+                                          restir_cap=1),
+             "ris4_k128_reuse_cap1_ncap8": dict(light_grid=1, ris_candidates=4, lgrid_k=128, restir=1,
+                                                restir_log2=20, restir_cap=1, n_cap=8)}
     res = {"workload": f"lights_room (64 emissive quads, radiance 2..200) {W}x{H}, R={R}, one bounce, frames "
                        f"0..{frames - 1}, ms/frame over {timed_from}..{frames - 1}; relMAE of the cache radiance at "
                        f"visible points vs area sampling at R={ref_R} over {ref_frames} frames", "modes": {}}
     for name, kw in modes.items():
-        ms, q, kern = run(R, frames, 256, **kw)
+        ms, q, kern = run(R, frames, 256, **kw)   # n_cap in kw overrides the 256
         both = (q[:, 3] > 0) & (ref[:, 3] > 0)
         e = float(np.abs(q[both, :3] - ref[both, :3]).sum() / max(np.abs(ref[both, :3]).sum(), 1e-30))
-        lg = {k: v for k, v in kern.items() if k in ("lg_box", "lg_box_final", "light_grid", "shade_hits")}
-        res["modes"][name] = {"ms_per_frame": round(ms, 4), "relMAE": round(e, 5), "points": int(both.sum()),
-                              "kernels_ms": lg}
-        log(f"[bench] light sampling {name}: relMAE {e:.4f} @ {ms:.3f} ms/frame {lg}")
+        level = float(q[both, :3].sum() / max(ref[both, :3].sum(), 1e-30))
+        lg = {k: v for k, v in kern.items()
+              if k in ("lg_box", "lg_box_final", "light_grid", "shade_hits", "restir_clear", "restir_store")}
+        res["modes"][name] = {"ms_per_frame": round(ms, 4), "relMAE": round(e, 5), "level": round(level, 4),
+                              "points": int(both.sum()), "kernels_ms": lg}
+        log(f"[bench] light sampling {name}: relMAE {e:.4f}, level {level:.3f} @ {ms:.3f} ms/frame {lg}")
     return res
 
 

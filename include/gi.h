@@ -139,7 +139,15 @@ typedef struct gi_config {
     uint32_t lgrid_dim;
     uint32_t lgrid_k;
     float lgrid_threshold;
-    uint32_t reserved3[3];
+    /* 1: world-space reservoir reuse (Section 2.3.1; needs light_grid).  Each hit's final
+     * reservoir (light point, contribution weight, count, its normal) is kept in a spatial
+     * hash over the quantised position alone (2^restir_log2 slots, 6..24; per cell the
+     * lowest ray id's); the next frame, a hit whose cell holds one with a normal cosine above
+     * 0.9 resamples it into its own reservoir, its count capped at restir_cap (1..64) x
+     * ris_candidates. */
+    uint32_t restir;
+    uint32_t restir_log2;
+    uint32_t restir_cap;
 } gi_config;
 
 typedef struct gi_frame {
@@ -292,6 +300,13 @@ gi_status gi_tiles_export(gi_context *ctx, uint64_t *h_id, uint64_t *h_key, uint
  * lgrid_k per cell, the first count[c] valid) and the count.  GI_ERR_UNSUPPORTED without it. */
 gi_status gi_light_grid_export(gi_context *ctx, float *h_geom, uint32_t *h_dims, uint32_t *h_list, uint32_t *h_count,
                                uint32_t cap_cells);
+
+/* World-space reservoirs written by the last trace (restir = 1; host-synchronous): live slots
+ * in slot order, at most cap: id = bucket << 32 | fingerprint, key (quantised position),
+ * light point and contribution weight [n][4], normal of the storing vertex [n][3], light
+ * (emitter index) and count.  GI_ERR_UNSUPPORTED without reservoirs. */
+gi_status gi_restir_export(gi_context *ctx, uint64_t *h_id, uint64_t *h_key, float *h_yw, float *h_n, uint32_t *h_k,
+                           uint32_t *h_m, uint32_t cap, uint32_t *n_out);
 
 /* Live cells in slot order: id = bucket << 32 | fingerprint, key (descriptor bits), acc
  * [n][4] (fixed-point r,g,b sums and count of the current frame), L [n][3] cached radiance,

@@ -36,7 +36,8 @@ class OrcConfig(C.Structure):
                 ("temporal", C.c_uint32), ("upscale", C.c_uint32), ("ray_guiding", C.c_uint32),
                 ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32), ("light_grid", C.c_uint32),
                 ("lgrid_dim", C.c_uint32), ("lgrid_k", C.c_uint32), ("ris_candidates", C.c_uint32), ("lgrid_threshold", C.c_float),
-                ("restir", C.c_uint32), ("restir_log2", C.c_uint32)]
+                ("restir", C.c_uint32), ("restir_log2", C.c_uint32), ("restir_cap", C.c_uint32),
+                ("pad10", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -51,7 +52,7 @@ def default_config(**kw) -> dict:
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
                temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min_samples=16, light_grid=0,
                lgrid_dim=16, lgrid_k=8, ris_candidates=4, lgrid_threshold=1e-3,
-               restir=0, restir_log2=16)
+               restir=0, restir_log2=16, restir_cap=20)
     cfg.update(kw)
     return cfg
 

@@ -679,7 +679,7 @@ typedef struct orc_config {
     uint32_t tile_min, light_grid, lgrid_dim, lgrid_k;
     uint32_t ris_m;
     float lgrid_tau;
-    uint32_t restir, restir_log2;
+    uint32_t restir, restir_log2, restir_cap, pad10;
 } orc_config;
 
 typedef struct orc_frame {
@@ -1686,7 +1686,7 @@ void ORC(light_grid_export)(const state *st, real *geom /* lo[3], h */, uint32_t
  * world cache's over the quantised position alone (the descriptor with normal class 0, no
  * leak bit; levels of detail as the cache's), with the storing vertex's normal beside it.
  * READING: a hit reuses the previous frame's reservoir of its cell when the normals' cosine
- * exceeds 0.9 (bilateral test); the stored count is capped at 20 x ris_m; the reused sample
+ * exceeds 0.9 (bilateral test); the stored count is capped at restir_cap x ris_m; the reused sample
  * enters with weight target_here(y) * W * M and one more weighted-reservoir step (hash
  * dimension 48); every hit's final reservoir (before its shadow ray) is offered to its cell
  * of this frame's table, where the lowest ray id is kept. */
@@ -1799,7 +1799,7 @@ static void ris_light(state *st, const orc_frame *fr, uint32_t gid, const real *
             if (cn > RC(0.9)) {
                 uint32_t kp = st->rs_k[pt][s];
                 const real *xp = st->rs_y[pt] + 3 * (size_t)s;
-                uint32_t cap = 20u * c->ris_m;
+                uint32_t cap = c->restir_cap * c->ris_m;
                 uint32_t Mp = st->rs_M[pt][s] < cap ? st->rs_M[pt][s] : cap;
                 real ph, g, dist, om[3];
                 light_target(sc, kp, xp, yo, ny, &ph, &g, om, &dist);

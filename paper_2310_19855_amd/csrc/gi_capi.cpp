@@ -217,6 +217,18 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->d_lg_part);
   dfree(c->d_lg_list);
   dfree(c->d_lg_count);
+  for (int t = 0; t < 2; ++t) {
+    dfree(c->d_rs_fp[t]);
+    dfree(c->d_rs_key[t]);
+    dfree(c->d_rs_yw[t]);
+    dfree(c->d_rs_n[t]);
+    dfree(c->d_rs_m[t]);
+  }
+  dfree(c->d_rs_claim);
+  dfree(c->d_r_rs_yw);
+  dfree(c->d_r_rs_n);
+  dfree(c->d_r_rs_m);
+  dfree(c->d_r_rs_slot);
   dfree(c->d_sh);
   dfree(c->tab.fp);
   dfree(c->tab.key);
@@ -273,6 +285,9 @@ gi_status check_config(const gi_config* g, std::string& why) {
     why = "light grid: lgrid_dim in [1, 32], lgrid_k in [1, 256], ris_candidates in [1, 8], lgrid_threshold > 0";
     return GI_ERR_INVALID_ARG;
   }
+  if (g->restir > 1 || (g->restir && !g->light_grid)) { why = "restir must be 0 or 1 and needs light_grid"; return GI_ERR_INVALID_ARG; }
+  if (g->restir && (g->restir_log2 < 6 || g->restir_log2 > 24)) { why = "restir_log2 out of [6, 24]"; return GI_ERR_INVALID_ARG; }
+  if (g->restir && (g->restir_cap < 1 || g->restir_cap > 64)) { why = "restir_cap out of [1, 64]"; return GI_ERR_INVALID_ARG; }
   return GI_OK;
 }
 
@@ -367,6 +382,21 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
     A(dalloc(&c->d_lg_part, 6 * ((PR + 255) / 256)));
     A(dalloc(&c->d_lg_list, cells * cfg->lgrid_k));
     A(dalloc(&c->d_lg_count, cells));
+  }
+  if (cfg->restir) {
+    const size_t NR = (size_t)1 << cfg->restir_log2;
+    for (int t = 0; t < 2; ++t) {
+      A(dalloc(&c->d_rs_fp[t], NR));
+      A(dalloc(&c->d_rs_key[t], NR));
+      A(dalloc(&c->d_rs_yw[t], NR));
+      A(dalloc(&c->d_rs_n[t], NR));
+      A(dalloc(&c->d_rs_m[t], NR));
+    }
+    A(dalloc(&c->d_rs_claim, NR));
+    A(dalloc(&c->d_r_rs_yw, PR));
+    A(dalloc(&c->d_r_rs_n, PR));
+    A(dalloc(&c->d_r_rs_m, PR));
+    A(dalloc(&c->d_r_rs_slot, PR));
   }
   A(dalloc(&c->d_sh, (size_t)c->P * 28));
   A(dalloc(&c->tab.fp, c->N));
@@ -773,6 +803,55 @@ gi_status gi_learned_query(gi_context* c, const float* pos, const float* nrm, ui
 }
 
 // ---- exports ------------------------------------------------------------------------------
+
+gi_status gi_restir_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, float* h_yw, float* h_n, uint32_t* h_k,
+                           uint32_t* h_m, uint32_t cap, uint32_t* n_out) {
+  if (!c || !n_out) return GI_ERR_INVALID_ARG;
+  if (!c->cfg.restir) return fail(c, GI_ERR_UNSUPPORTED, "gi_restir_export needs restir = 1");
+  try {
+    GI_TRY_HIP(c, hipDeviceSynchronize());
+    const size_t N = (size_t)1 << c->cfg.restir_log2;
+    const uint32_t t = c->rs_cur;   // the table the last trace wrote
+    std::vector<uint32_t> fp(N), m(N);
+    std::vector<uint64_t> key(N);
+    std::vector<float4> yw(N), nr(N);
+    GI_TRY_HIP(c, hipMemcpy(fp.data(), c->d_rs_fp[t], 4 * N, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(key.data(), c->d_rs_key[t], 8 * N, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(yw.data(), c->d_rs_yw[t], 16 * N, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(nr.data(), c->d_rs_n[t], 16 * N, hipMemcpyDeviceToHost));
+    GI_TRY_HIP(c, hipMemcpy(m.data(), c->d_rs_m[t], 4 * N, hipMemcpyDeviceToHost));
+    uint32_t n = 0;
+    for (size_t s = 0; s < N; ++s) {
+      if (!fp[s] || !c->rs_has_prev) continue;
+      if (n < cap) {
+        if (h_id) h_id[n] = ((uint64_t)(s / gi::kBucketSlots) << 32) | fp[s];
+        if (h_key) h_key[n] = key[s];
+        if (h_yw) {
+          h_yw[4 * (size_t)n] = yw[s].x;
+          h_yw[4 * (size_t)n + 1] = yw[s].y;
+          h_yw[4 * (size_t)n + 2] = yw[s].z;
+          h_yw[4 * (size_t)n + 3] = yw[s].w;
+        }
+        if (h_n) {
+          h_n[3 * (size_t)n] = nr[s].x;
+          h_n[3 * (size_t)n + 1] = nr[s].y;
+          h_n[3 * (size_t)n + 2] = nr[s].z;
+        }
+        if (h_k) {
+          uint32_t kb;
+          std::memcpy(&kb, &nr[s].w, 4);
+          h_k[n] = kb;
+        }
+        if (h_m) h_m[n] = m[s];
+      }
+      ++n;
+    }
+    *n_out = n;
+    return GI_OK;
+  } catch (const std::exception& ex) {
+    return fail(c, GI_ERR_INTERNAL, ex.what());
+  }
+}
 
 gi_status gi_light_grid_export(gi_context* c, float* h_geom, uint32_t* h_dims, uint32_t* h_list, uint32_t* h_count,
                                uint32_t cap_cells) {

@@ -110,6 +110,19 @@ struct gi_context {
   uint32_t* d_lg_part = nullptr;     // [blocks of 256 rays][6] partial boxes
   uint32_t* d_lg_list = nullptr;     // [dim^3][lgrid_k]
   uint32_t* d_lg_count = nullptr;    // [dim^3]
+  // world-space reservoirs (config restir): two position-keyed tables, read / written in turn
+  uint32_t* d_rs_fp[2] = {nullptr, nullptr};
+  uint64_t* d_rs_key[2] = {nullptr, nullptr};
+  float4* d_rs_yw[2] = {nullptr, nullptr};   // light point, contribution weight
+  float4* d_rs_n[2] = {nullptr, nullptr};    // normal of the storing vertex, w = light bits
+  uint32_t* d_rs_m[2] = {nullptr, nullptr};  // count
+  uint32_t* d_rs_claim = nullptr;            // lowest ray id offering to each slot
+  float4* d_r_rs_yw = nullptr;               // [P*R] each hit's final reservoir
+  float4* d_r_rs_n = nullptr;
+  uint32_t* d_r_rs_m = nullptr;              // 0: none
+  int32_t* d_r_rs_slot = nullptr;
+  uint32_t rs_cur = 0;                       // table read this frame
+  bool rs_has_prev = false;
   bool has_prev = false;             // a previous frame's probes are stored
   bool reprojected = false;          // this frame's spawn reprojected them
   gi_frame prev_frame{};

@@ -683,12 +683,56 @@ __device__ inline LightSample sample_light(const ShadeTables& st, uint32_t seed,
 // Candidates j: a light picked uniformly from the cell's list (hash dimension 16 + 4j), a
 // uniform point on it (17 + 4j, 18 + 4j); weight = target / source pdf = lum * cos_y * cos_l
 // / d^2 * count * area; weighted reservoir sampling keeps candidate j when u (19 + 4j) * sum
-// < weight.  The kept light's g is cos_y cos_l / d^2 * sum / (ris_m * target).
+// < weight.  With world-space reservoir reuse (Section 2.3.1), the previous frame's reservoir
+// of the hit's quantised position (a normal cosine above 0.9) enters with weight
+// target(y_prev) * W_prev * min(M_prev, restir_cap * ris_m) by one more step (dimension 48), and the
+// hit's final reservoir is offered to this frame's table (the lowest ray id per cell stays).
+// The kept light's g is cos_y cos_l / d^2 * sum / (M * target).
 __device__ inline float lum709(float4 le) { return (0.2126f * le.x + 0.7152f * le.y) + 0.0722f * le.z; }
 
-__device__ inline LightSample sample_light_ris(const ShadeTables& st, uint32_t seed, uint32_t frame, uint32_t gid,
-                                               float yx, float yy, float yz, float px, float py, float pz, float nx,
-                                               float ny, float nz) {
+struct RestirArgs {
+  uint32_t on;                  // reservoirs are kept
+  uint32_t cap;                 // largest count a reused reservoir enters with
+  uint32_t has_prev;            // the read table holds the previous frame's
+  CacheArgs prev, next;         // fp / key / bucket_mask of the read and written tables
+  const float4* pyw;            // read table: light point, weight
+  const float4* pn;             // read table: normal, w = light bits
+  const uint32_t* pm;           // read table: count
+  uint32_t* claim;              // written table: lowest ray id per slot
+  float4* r_yw;                 // per ray: final reservoir
+  float4* r_n;
+  uint32_t* r_m;
+  int32_t* r_slot;
+  float cell_scale, lod_scale, cam[3];
+};
+
+__device__ inline void light_target(const ShadeTables& st, uint32_t k, float xx, float xy, float xz, float px,
+                                    float py, float pz, float nx, float ny, float nz, float& ph, float& gg,
+                                    float& dist, float& mx, float& my, float& mz) {
+  const uint32_t e = st.etri[k];
+  const float wx = xx - px, wy = xy - py, wz = xz - pz;
+  const float d2 = (wx * wx + wy * wy) + wz * wz;
+  ph = 0.0f;
+  gg = 0.0f;
+  dist = 0.0f;
+  mx = my = mz = 0.0f;
+  if (!(d2 > 0.0f)) return;
+  dist = sqrtf(d2);
+  mx = wx / dist;
+  my = wy / dist;
+  mz = wz / dist;
+  const float4 ne = st.tnrm[e];
+  const float cos_y = (nx * mx + ny * my) + nz * mz;
+  const float cos_l = -((ne.x * mx + ne.y * my) + ne.z * mz);
+  if (cos_y > 0.0f && cos_l > 0.0f) {
+    gg = (cos_y * cos_l) / d2;
+    ph = lum709(st.mats[2 * __float_as_uint(ne.w) + 1]) * gg;
+  }
+}
+
+__device__ inline LightSample sample_light_ris(const ShadeTables& st, const RestirArgs& ra, uint32_t seed,
+                                               uint32_t frame, uint32_t gid, float yx, float yy, float yz, float px,
+                                               float py, float pz, float nx, float ny, float nz) {
   LightSample ls;
   ls.cast = false;
   ls.tmax = 0.0f;
@@ -704,53 +748,87 @@ __device__ inline LightSample sample_light_ris(const ShadeTables& st, uint32_t s
   }
   const uint32_t cell = (ci[2] * g.dim[1] + ci[1]) * g.dim[0] + ci[0];
   const uint32_t m = st.lg_count[cell];
-  if (m == 0u) return ls;
   const uint32_t* list = st.lg_list + (size_t)cell * st.lg_k;
   float wsum = 0.0f, ph_sel = 0.0f, g_sel = 0.0f, dist_sel = 0.0f;
-  float ox = 0.f, oy = 0.f, oz = 0.f;
-  uint32_t k_sel = 0xFFFFFFFFu;
-  for (uint32_t j = 0; j < st.ris_m; ++j) {
-    const uint32_t rp = rand_u32(seed, frame, gid, 16u + 4u * j);
-    const uint32_t k = list[(uint32_t)(((uint64_t)rp * m) >> 32)];
-    const float u3 = rand_unit(rand_u32(seed, frame, gid, 17u + 4u * j));
-    const float u4 = rand_unit(rand_u32(seed, frame, gid, 18u + 4u * j));
-    const float us = rand_unit(rand_u32(seed, frame, gid, 19u + 4u * j));
-    const uint32_t e = st.etri[k];
-    const float su = sqrtf(u3);
-    const float b0 = 1.0f - su, b1 = su * (1.0f - u4), b2 = su * u4;
-    const float4 A = st.evert[3 * k], B = st.evert[3 * k + 1], C = st.evert[3 * k + 2];
-    const float wx = ((b0 * A.x + b1 * B.x) + b2 * C.x) - px;
-    const float wy = ((b0 * A.y + b1 * B.y) + b2 * C.y) - py;
-    const float wz = ((b0 * A.z + b1 * B.z) + b2 * C.z) - pz;
-    const float d2 = (wx * wx + wy * wy) + wz * wz;
-    float ph = 0.0f, gg = 0.0f, dist = 0.0f, mx = 0.f, my = 0.f, mz = 0.f;
-    if (d2 > 0.0f) {
-      dist = sqrtf(d2);
-      mx = wx / dist;
-      my = wy / dist;
-      mz = wz / dist;
-      const float4 ne = st.tnrm[e];
-      const float cos_y = (nx * mx + ny * my) + nz * mz;
-      const float cos_l = -((ne.x * mx + ne.y * my) + ne.z * mz);
-      if (cos_y > 0.0f && cos_l > 0.0f) {
-        gg = (cos_y * cos_l) / d2;
-        ph = lum709(st.mats[2 * __float_as_uint(ne.w) + 1]) * gg;
+  float ox = 0.f, oy = 0.f, oz = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+  uint32_t k_sel = 0xFFFFFFFFu, M = 0u;
+  if (m > 0u) {
+    M = st.ris_m;
+    for (uint32_t j = 0; j < st.ris_m; ++j) {
+      const uint32_t rp = rand_u32(seed, frame, gid, 16u + 4u * j);
+      const uint32_t k = list[(uint32_t)(((uint64_t)rp * m) >> 32)];
+      const float u3 = rand_unit(rand_u32(seed, frame, gid, 17u + 4u * j));
+      const float u4 = rand_unit(rand_u32(seed, frame, gid, 18u + 4u * j));
+      const float us = rand_unit(rand_u32(seed, frame, gid, 19u + 4u * j));
+      const float su = sqrtf(u3);
+      const float b0 = 1.0f - su, b1 = su * (1.0f - u4), b2 = su * u4;
+      const float4 A = st.evert[3 * k], B = st.evert[3 * k + 1], C = st.evert[3 * k + 2];
+      const float xx = (b0 * A.x + b1 * B.x) + b2 * C.x;
+      const float xy = (b0 * A.y + b1 * B.y) + b2 * C.y;
+      const float xz = (b0 * A.z + b1 * B.z) + b2 * C.z;
+      float ph, gg, dist, mx, my, mz;
+      light_target(st, k, xx, xy, xz, px, py, pz, nx, ny, nz, ph, gg, dist, mx, my, mz);
+      const float wj = (ph * (float)m) * A.w;
+      wsum = wsum + wj;
+      if (wj > 0.0f && us * wsum < wj) {
+        k_sel = k;
+        ph_sel = ph;
+        g_sel = gg;
+        dist_sel = dist;
+        ox = mx; oy = my; oz = mz;
+        sx = xx; sy = xy; sz = xz;
       }
     }
-    const float wj = (ph * (float)m) * A.w;
-    wsum = wsum + wj;
-    if (wj > 0.0f && us * wsum < wj) {
-      k_sel = k;
-      ph_sel = ph;
-      g_sel = gg;
-      dist_sel = dist;
-      ox = mx;
-      oy = my;
-      oz = mz;
+  }
+  uint64_t pkey = 0;
+  if (ra.on) {
+    uint32_t tc;
+    pkey = descriptor(ra.cell_scale, 0u, ra.lod_scale, ra.cam[0], ra.cam[1], ra.cam[2], yx, yy, yz, 1.0f, 0.0f,
+                      0.0f, 0.0f, false, 0u, tc);
+  }
+  if (ra.on && ra.has_prev) {
+    const int32_t s = table_lookup(ra.prev, pkey);
+    if (s >= 0) {
+      const float4 np = ra.pn[s];
+      const float cn = (nx * np.x + ny * np.y) + nz * np.z;
+      if (cn > 0.9f) {
+        const uint32_t kp = __float_as_uint(np.w);
+        const float4 xp = ra.pyw[s];
+        const uint32_t Mp = ra.pm[s] < ra.cap ? ra.pm[s] : ra.cap;
+        float ph, gg, dist, mx, my, mz;
+        light_target(st, kp, xp.x, xp.y, xp.z, px, py, pz, nx, ny, nz, ph, gg, dist, mx, my, mz);
+        const float wp = (ph * xp.w) * (float)Mp;
+        wsum = wsum + wp;
+        const float us = rand_unit(rand_u32(seed, frame, gid, 48u));
+        if (wp > 0.0f && us * wsum < wp) {
+          k_sel = kp;
+          ph_sel = ph;
+          g_sel = gg;
+          dist_sel = dist;
+          ox = mx; oy = my; oz = mz;
+          sx = xp.x; sy = xp.y; sz = xp.z;
+        }
+        M = M + Mp;
+      }
     }
   }
-  if (k_sel == 0xFFFFFFFFu) return ls;
-  const float W = wsum / ((float)st.ris_m * ph_sel);
+  if (k_sel == 0xFFFFFFFFu) {
+    if (ra.on) {
+      ra.r_m[gid] = 0u;
+      ra.r_slot[gid] = -1;
+    }
+    return ls;
+  }
+  const float W = wsum / ((float)M * ph_sel);
+  if (ra.on) {
+    bool ins;
+    const int32_t slot = table_insert(ra.next, pkey, ins);
+    ra.r_yw[gid] = make_float4(sx, sy, sz, W);
+    ra.r_n[gid] = make_float4(nx, ny, nz, __uint_as_float(k_sel));
+    ra.r_m[gid] = M;
+    ra.r_slot[gid] = slot;
+    if (slot >= 0) atomicMin(ra.claim + slot, gid);
+  }
   ls.cast = true;
   ls.ray = make_ray(px, py, pz, ox, oy, oz);
   ls.tmax = dist_sel * 0.9999f;
@@ -910,10 +988,32 @@ __global__ __launch_bounds__(64) void k_light_grid(ShadeTables st, uint32_t n_em
   if (lane == 0u) count[ci] = cnt;
 }
 
+// World-space reservoirs (Section 2.3.1): the table written this frame starts empty; after
+// the shading, each slot takes the reservoir of the lowest ray id that offered to it.
+__global__ __launch_bounds__(256) void k_restir_clear(uint32_t* fp, uint64_t* key, uint32_t* claim, uint32_t n) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  fp[i] = 0u;
+  key[i] = 0u;
+  claim[i] = 0xFFFFFFFFu;
+}
+
+__global__ __launch_bounds__(256) void k_restir_store(const uint4* rec, uint32_t n, RestirArgs ra, float4* yw,
+                                                      float4* nrm, uint32_t* cnt) {
+  const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+  if (gid >= n || !(rec[gid].w & GI_RAY_HIT)) return;
+  if (ra.r_m[gid] == 0u) return;
+  const int32_t s = ra.r_slot[gid];
+  if (s < 0 || ra.claim[s] != gid) return;
+  yw[s] = ra.r_yw[gid];
+  nrm[s] = ra.r_n[gid];
+  cnt[s] = ra.r_m[gid];
+}
+
 template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeTables st, ProbeRayArgs a,
                                                             CacheArgs c, uint4* rec, uint2* rkey, HitList hl,
-                                                            LearnedShadeOut lo,
+                                                            LearnedShadeOut lo, RestirArgs ra,
                                                             unsigned long long* stats) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
   __shared__ uint16_t stkt[STACK * kTraceBlock];
@@ -957,7 +1057,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float eps = origin_offset(a.eps_scale, yx, yy, yz);
   const float px = yx + nx * eps, py = yy + ny * eps, pz = yz + nz * eps;
   float E0 = 0.f, E1 = 0.f, E2 = 0.f;
-  const LightSample ls = st.lg_list ? sample_light_ris(st, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
+  const LightSample ls = st.lg_list ? sample_light_ris(st, ra, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
                                     : sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
   const bool cast = ls.cast;
   bool occl = false;
@@ -1719,7 +1819,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_rays(SceneView sv, const 
 // tested (the algorithmic traffic of the traversal), no other side effect
 template <int STACK>
 __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, ShadeTables st, ProbeRayArgs a,
-                                                                 CacheArgs c, const uint4* rec,
+                                                                 CacheArgs c, const uint4* rec, RestirArgs ra,
                                                                  unsigned long long* out) {
   __shared__ uint32_t stk[STACK * kTraceBlock];
   __shared__ uint16_t stkt[STACK * kTraceBlock];
@@ -1748,7 +1848,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
         const float eps = origin_offset(a.eps_scale, yx, yy, yz);
         const float px = yx + nx * eps, py = yy + ny * eps, pz = yz + nz * eps;
         const LightSample ls = st.lg_list
-                                   ? sample_light_ris(st, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
+                                   ? sample_light_ris(st, ra, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
                                    : sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
         if (ls.cast) {
           shadow = true;
@@ -1858,6 +1958,41 @@ static CacheArgs cache_args(const gi_context* c) {
   a.lod_scale = c->cfg.lod_scale;
   for (int k = 0; k < 3; ++k) a.cam[k] = c->fa.cam[k];
   return a;
+}
+
+static RestirArgs restir_args(const gi_context* c) {
+  RestirArgs r;
+  r.on = c->cfg.restir;
+  r.cap = c->cfg.restir_cap * c->cfg.ris_candidates;
+  r.has_prev = c->cfg.restir && c->rs_has_prev;
+  const uint32_t cur = c->rs_cur, nxt = c->rs_cur ^ 1u;
+  r.prev = cache_args(c);
+  r.next = r.prev;
+  if (c->cfg.restir) {
+    const uint32_t mask = ((1u << c->cfg.restir_log2) / kBucket) - 1u;
+    r.prev.fp = c->d_rs_fp[cur];
+    r.prev.key = c->d_rs_key[cur];
+    r.prev.bucket_mask = mask;
+    r.next.fp = c->d_rs_fp[nxt];
+    r.next.key = c->d_rs_key[nxt];
+    r.next.bucket_mask = mask;
+    r.pyw = c->d_rs_yw[cur];
+    r.pn = c->d_rs_n[cur];
+    r.pm = c->d_rs_m[cur];
+  } else {
+    r.pyw = nullptr;
+    r.pn = nullptr;
+    r.pm = nullptr;
+  }
+  r.claim = c->d_rs_claim;
+  r.r_yw = c->d_r_rs_yw;
+  r.r_n = c->d_r_rs_n;
+  r.r_m = c->d_r_rs_m;
+  r.r_slot = c->d_r_rs_slot;
+  r.cell_scale = c->cfg.cell_scale;
+  r.lod_scale = c->cfg.lod_scale;
+  for (int k = 0; k < 3; ++k) r.cam[k] = c->fa.cam[k];
+  return r;
 }
 
 void timer_begin(gi_context* c, const char* name, hipStream_t s, hipEvent_t* a) {
@@ -1978,6 +2113,11 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
   const LearnedShadeOut lso = learned_shade_out(c);
   if (lso.trec_count) k_zero_u32<<<1, 64, 0, s>>>(lso.trec_count, 1);
   GI_TIMED(c, "trace_probes", s, (k_trace_probes<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
+  const RestirArgs ra = restir_args(c);
+  if (ra.on) {
+    const uint32_t NR = 1u << c->cfg.restir_log2;
+    GI_TIMED(c, "restir_clear", s, (k_restir_clear<<<blocks(NR, 256), 256, 0, s>>>(ra.next.fp, ra.next.key, ra.claim, NR)));
+  }
   if (c->cfg.light_grid) {
     // the light grid over this frame's hit points, before the shading that samples it
     const uint32_t nb = blocks(n, 256);
@@ -1986,7 +2126,14 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
     const uint32_t G = c->cfg.lgrid_dim;
     GI_TIMED(c, "light_grid", s, (k_light_grid<<<G * G * G, 64, 0, s>>>(st, c->n_emit, c->cfg.lgrid_threshold, c->d_lg_list, c->d_lg_count)));
   }
-  GI_TIMED(c, "shade_hits", s, (k_shade_hits<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), learned_shade_out(c), c->d_stats)));
+  GI_TIMED(c, "shade_hits", s, (k_shade_hits<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, ca, c->d_rec, c->d_rkey, hit_list(c), learned_shade_out(c), ra, c->d_stats)));
+  if (ra.on) {
+    // this frame's reservoirs into the written table (the lowest ray id per slot), which the
+    // next frame reads
+    GI_TIMED(c, "restir_store", s, (k_restir_store<<<blocks(n, 256), 256, 0, s>>>(c->d_rec, (uint32_t)n, ra, c->d_rs_yw[c->rs_cur ^ 1u], c->d_rs_n[c->rs_cur ^ 1u], c->d_rs_m[c->rs_cur ^ 1u])));
+    c->rs_cur ^= 1u;
+    c->rs_has_prev = true;
+  }
   return hipGetLastError();
 }
 
@@ -2046,7 +2193,10 @@ hipError_t launch_trace_rays(gi_context* c, const float4* o, const float4* d, ui
 hipError_t launch_count_traversal(gi_context* c, unsigned long long* out, hipStream_t s) {
   const uint64_t n = (uint64_t)c->P * c->R;
   k_zero_u64<<<1, 64, 0, s>>>(out, 8);
-  k_count_traversal<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), probe_args(c), cache_args(c), c->d_rec, out);
+  RestirArgs off = restir_args(c);
+  off.on = 0u;   // counting rays must not write reservoirs
+  off.has_prev = 0u;
+  k_count_traversal<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), shade_tables(c), probe_args(c), cache_args(c), c->d_rec, off, out);
   return hipGetLastError();
 }
 

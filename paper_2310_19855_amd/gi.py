@@ -45,7 +45,8 @@ class Config(C.Structure):
                 ("lod_scale", C.c_float), ("temporal", C.c_uint32), ("upscale", C.c_uint32),
                 ("ray_guiding", C.c_uint32), ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32),
                 ("light_grid", C.c_uint32), ("ris_candidates", C.c_uint32), ("lgrid_dim", C.c_uint32),
-                ("lgrid_k", C.c_uint32), ("lgrid_threshold", C.c_float), ("reserved3", C.c_uint32 * 3)]
+                ("lgrid_k", C.c_uint32), ("lgrid_threshold", C.c_float), ("restir", C.c_uint32),
+                ("restir_log2", C.c_uint32), ("restir_cap", C.c_uint32)]
 
 
 class Frame(C.Structure):
@@ -59,7 +60,8 @@ DEFAULTS = dict(width=128, height=128, rays_per_probe=16, table_log2=16, bounces
                 cell_scale=10.0, r_max=64.0, eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0),
                 mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4,
                 mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_loss_scale=128.0, mlp_judge=0.1, tile_min_samples=16,
-                ris_candidates=4, lgrid_dim=16, lgrid_k=8, lgrid_threshold=1e-3)
+                ris_candidates=4, lgrid_dim=16, lgrid_k=8, lgrid_threshold=1e-3, restir_log2=16,
+                restir_cap=20)
 
 _lib = None
 
@@ -89,6 +91,7 @@ def lib():
     fn("gi_bvh_build_host", st, vp, u32, vp, u32, vp, u32, P(u32), P(u32), P(u32))
     fn("gi_tiles_export", st, vp, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
     fn("gi_light_grid_export", st, vp, vp, vp, vp, vp, u32)
+    fn("gi_restir_export", st, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
     fn("gi_set_dynamic_triangles", st, vp, vp, vp, u32, vp)
     fn("gi_render_gbuffer", st, vp, P(Frame), vp, vp, vp, vp, vp)
     fn("gi_spawn_probes", st, vp, P(Frame), vp, vp, vp, vp)
@@ -359,6 +362,24 @@ class Context:
         o = np.argsort(ident[:k], kind="stable")
         return dict(id=ident[:k][o], key=key[:k][o], life=life[:k][o], acc=acc[:k][o], L=L[:k][o],
                     nhist=nh[:k][o], Lq=Lq[:k][o])
+
+    def reservoirs(self):
+        """world-space reservoirs written by the last trace (restir = 1), sorted by (bucket,
+        fingerprint): key, light point, contribution weight, normal, light, count"""
+        N = 1 << int(self.cfg_dict["restir_log2"])
+        ident = np.zeros(N, np.uint64)
+        key = np.zeros(N, np.uint64)
+        yw = np.zeros((N, 4), np.float32)
+        nr = np.zeros((N, 3), np.float32)
+        k = np.zeros(N, np.uint32)
+        m = np.zeros(N, np.uint32)
+        n = C.c_uint32()
+        self._check(lib().gi_restir_export(self.h, ident.ctypes.data, key.ctypes.data, yw.ctypes.data, nr.ctypes.data,
+                                           k.ctypes.data, m.ctypes.data, N, C.byref(n)), "gi_restir_export")
+        c = n.value
+        o = np.argsort(ident[:c], kind="stable")
+        return dict(id=ident[:c][o], key=key[:c][o], y=yw[:c, :3][o], W=yw[:c, 3][o], n=nr[:c][o], k=k[:c][o],
+                    M=m[:c][o])
 
     def light_grid(self):
         """light grid of the last trace (light_grid = 1): origin, cell side, dims, per-cell

@@ -69,6 +69,13 @@ def _run_stage_parity(scene, cfg, frames, check_every=True, camera=None):
             assert np.array_equal(gl["count"], ol["count"]), "light list lengths differ"
             for c in np.nonzero(ol["count"])[0]:
                 assert np.array_equal(gl["list"][c, :ol["count"][c]], ol["list"][c, :ol["count"][c]]), c
+        if cfg.get("restir", 0):
+            gv, ov = pr.ctx.reservoirs(), pr.ost.reservoirs()
+            assert np.array_equal(gv["id"], ov["id"]) and np.array_equal(gv["key"], ov["key"]), "reservoir cells"
+            for k in ("k", "M"):
+                assert np.array_equal(gv[k], ov[k]), f"reservoir {k} differs"
+            for k in ("y", "W", "n"):
+                assert np.array_equal(bits(gv[k]), bits(ov[k].astype(np.float32))), f"reservoir {k} differs"
         gs, os_ = pr.ctx.stats(), pr.ost.stats()
         for k in ("rays", "hits", "inserts", "overflow", "nonfinite", "wraps", "shadow", "occluded", "bounce"):
             assert gs[k] == os_[k], f"stat {k}: gpu {gs[k]} oracle {os_[k]}"
@@ -326,6 +333,18 @@ def test_light_grid_ris_many_light_room():
     assert (g["count"] > 0).mean() > 0.5 and pr.ctx.stats()["shadow"] > 0
 
 
+def test_restir_reservoir_reuse_many_light_room():
+    """world-space reservoir reuse (Section 2.3.1) on the many-light room over four frames:
+    the reservoir table of every frame (cells, light, point, weight, count, normal) and all
+    that follows from the resampled picks bit-exact, then atlas, SH and irradiance"""
+    sc = I.lights_room_scene()
+    pr = _run_stage_parity(sc, dict(width=100, height=76, rays_per_probe=32, table_log2=16, bounces=2, light_grid=1,
+                                    lgrid_dim=8, lgrid_k=128, ris_candidates=4, restir=1, restir_log2=16),
+                           [0, 1, 2, 3], camera=lambda f: I.room_camera(0))
+    r = pr.ctx.reservoirs()
+    assert len(r["M"]) > 100 and r["M"].max() > 4
+
+
 def test_light_grid_field_moving_light():
     """the grid and RIS on the field, whose moving light changes the emitters every frame;
     one candidate (a uniform pick from the cell's list) and the default grid"""
@@ -578,6 +597,8 @@ def test_invalid_arguments_and_frame_order():
         gi.Context(width=64, height=64, ray_guiding=1)      # guiding needs temporal reuse
     with pytest.raises(gi.GIError, match="INVALID"):
         gi.Context(width=64, height=64, cache_tiles=1, cache_mode=gi.CACHE_MLP_BF16)   # tiles: plain cache only
+    with pytest.raises(gi.GIError, match="INVALID"):
+        gi.Context(width=64, height=64, restir=1)            # reservoirs need the light grid
     ctx = gi.Context(width=64, height=64, cache_tiles=1, table_log2=8)
     with pytest.raises(gi.GIError, match="UNSUPPORTED"):
         ctx.table()                                          # per-cell export of the single-level cache
