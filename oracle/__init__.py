@@ -37,7 +37,8 @@ class OrcConfig(C.Structure):
                 ("cache_tiles", C.c_uint32), ("tile_min_samples", C.c_uint32), ("light_grid", C.c_uint32),
                 ("lgrid_dim", C.c_uint32), ("lgrid_k", C.c_uint32), ("ris_candidates", C.c_uint32), ("lgrid_threshold", C.c_float),
                 ("restir", C.c_uint32), ("restir_log2", C.c_uint32), ("restir_cap", C.c_uint32),
-                ("pad10", C.c_uint32)]
+                ("denoise", C.c_uint32), ("dn_hist_max", C.c_uint32), ("dn_radius", C.c_uint32),
+                ("pad11", C.c_uint32), ("pad12", C.c_uint32)]
 
 
 class OrcFrame(C.Structure):
@@ -52,7 +53,7 @@ def default_config(**kw) -> dict:
                eps_scale=1e-4, t_sky=1e4, sky=(0.0, 0.0, 0.0), probe_filter=0, lod_scale=0.0,
                temporal=0, upscale=0, ray_guiding=0, cache_tiles=0, tile_min_samples=16, light_grid=0,
                lgrid_dim=16, lgrid_k=8, ris_candidates=4, lgrid_threshold=1e-3,
-               restir=0, restir_log2=16, restir_cap=20)
+               restir=0, restir_log2=16, restir_cap=20, denoise=0, dn_hist_max=16, dn_radius=4)
     cfg.update(kw)
     return cfg
 
@@ -121,6 +122,8 @@ def _lib(f64: bool):
     fn("light_grid_export", None, vp, R, U32P, U32P, U32P)
     fn("light_grid_set", None, vp, R, R)
     fn("restir_export", C.c_uint32, vp, U64P, U64P, R, R, R, U32P, U32P, C.c_uint32)
+    fn("denoise", None, vp, C.POINTER(OrcFrame), R, R, U32P, R, R)
+    fn("denoise_export", None, vp, R, U32P)
     fn("poke_cell", C.c_int, vp, C.c_uint64, U32P, R, C.c_uint32, C.c_uint32, C.c_uint32)
     fn("cache_update_only", None, vp)
     fn("stats", None, vp, U64P)
@@ -507,6 +510,24 @@ class OracleFrameState:
         o = np.argsort(ident[:n], kind="stable")
         return dict(id=ident[:n][o], key=key[:n][o], life=life[:n][o], acc=acc[:n][o], L=L[:n][o],
                     nhist=nh[:n][o], Lq=Lq[:n][o])
+
+    def denoise(self, frame, gpos, gnrm, gprim, irr):
+        """the denoiser over this frame's interpolated irradiance irr [H, W, 4] (rgb, flag)"""
+        H, W = gprim.shape
+        out = np.zeros((H, W, 4), self.dt)
+        f = make_frame(frame)
+        _call(self.f64, "denoise", self.h, C.byref(f), np.ascontiguousarray(gpos, self.dt),
+              np.ascontiguousarray(gnrm, self.dt), np.ascontiguousarray(gprim, np.uint32),
+              np.ascontiguousarray(irr, self.dt), out)
+        return out
+
+    def denoise_state(self):
+        """the accumulated irradiance and history length [H, W, 4], and the radius per pixel"""
+        H, W = int(self.cfg["height"]), int(self.cfg["width"])
+        hist = np.zeros((H, W, 4), self.dt)
+        rad = np.zeros((H, W), np.uint32)
+        _call(self.f64, "denoise_export", self.h, hist, rad)
+        return hist, rad
 
     def reservoirs(self):
         """the reservoir table written by the last trace (restir): sorted by (bucket,

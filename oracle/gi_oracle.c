@@ -679,7 +679,8 @@ typedef struct orc_config {
     uint32_t tile_min, light_grid, lgrid_dim, lgrid_k;
     uint32_t ris_m;
     float lgrid_tau;
-    uint32_t restir, restir_log2, restir_cap, pad10;
+    uint32_t restir, restir_log2, restir_cap, denoise;
+    uint32_t dn_hist_max, dn_radius, pad11, pad12;
 } orc_config;
 
 typedef struct orc_frame {
@@ -777,6 +778,13 @@ typedef struct state {
     uint64_t *rs_key[2];
     real *rs_y[2], *rs_W[2], *rs_n[2];
     real *r_rsy, *r_rsW;   /* [P*R][3], [P*R]: each hit's final reservoir */
+    /* screen-space denoiser (Section 2.4.3): accumulated irradiance and history length of the
+     * previous frame, its G-buffer and camera */
+    real *dn_hist, *dn_acc;  /* [H*W][4] rgb, history length */
+    real *dn_ppos, *dn_pnrm; /* [H*W][4] */
+    uint32_t *dn_pprim, *dn_rad;
+    uint32_t dn_has_prev;
+    orc_frame dn_pfr;
     uint32_t *r_rsk, *r_rsM; /* M = 0: none */
     /* probes */
     real *atlas;           /* [P][64][4] */
@@ -1096,6 +1104,15 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->r_tcell = (uint32_t *)calloc(PR, sizeof(uint32_t));
     st->r_y = (real *)calloc(3 * PR, sizeof(real));
     st->r_ny = (real *)calloc(3 * PR, sizeof(real));
+    if (cfg->denoise) {
+        size_t HW = (size_t)cfg->width * cfg->height;
+        st->dn_hist = (real *)calloc(4 * HW, sizeof(real));
+        st->dn_acc = (real *)calloc(4 * HW, sizeof(real));
+        st->dn_ppos = (real *)calloc(4 * HW, sizeof(real));
+        st->dn_pnrm = (real *)calloc(4 * HW, sizeof(real));
+        st->dn_pprim = (uint32_t *)calloc(HW, sizeof(uint32_t));
+        st->dn_rad = (uint32_t *)calloc(HW, sizeof(uint32_t));
+    }
     if (cfg->restir) {
         st->rs_N = 1u << cfg->restir_log2;
         for (int t = 0; t < 2; ++t) {
@@ -1150,6 +1167,7 @@ void ORC(destroy)(state *st)
         free(st->rs_W[t]); free(st->rs_n[t]);
     }
     free(st->rs_claim); free(st->r_rsy); free(st->r_rsW); free(st->r_rsk); free(st->r_rsM);
+    free(st->dn_hist); free(st->dn_acc); free(st->dn_ppos); free(st->dn_pnrm); free(st->dn_pprim); free(st->dn_rad);
     free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
     free(st->hist); free(st->traced); free(st->recon); free(st->cdf);
     free(st);
@@ -2675,6 +2693,144 @@ void ORC(interpolate)(state *st, const orc_frame *fr, const real *gpos, const re
     }
     st->stats[ST_RELAXED] = relaxed;
     st->stats[ST_NOPROBE] = noprobe;
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Screen-space denoiser (Section 2.4.3): temporal accumulation of the interpolated irradiance
+ * and a spatial filter whose radius shrinks as the history grows.
+ * Temporal: a pixel's world position projected with the previous camera lands on a previous
+ * pixel; the history is valid when that pixel was not sky, lies within the pixel's cell size
+ * (Algorithm 6) of its tangent plane and has a normal cosine above 0.9.  With a valid history
+ * the history length becomes n = min(n_prev + 1, dn_hist_max) and the accumulated value
+ * E_hist + (E - E_hist) / n (the running mean over the last n frames, capped); without one,
+ * n = 1 and the value is this frame's.  A pixel without a probe (flag 2) keeps its history as
+ * it is, or stays empty (n = 0).
+ * Spatial: radius r = floor(dn_radius / n) (r = dn_radius at n = 0), dilated to the largest r
+ * of the 3x3 neighbourhood (the dilated blur mask); the output is the mean over the (2R+1)^2
+ * window of the neighbours' accumulated values that hold one, weighted by cs / (cs + |depth
+ * difference|) (cs the pixel's cell size) times max(0, normal cosine)^8.  The history kept is
+ * the accumulated value before the spatial filter.
+ * READING: every constant above (0.9, the radius law, the weights, the exponent 8) fills a
+ * point the paper leaves open; flags pass through in the output's fourth channel.
+ * ------------------------------------------------------------------------------------- */
+static int project_cam(const orc_frame *pf, uint32_t W, uint32_t H, const real *X, int32_t *qx, int32_t *qy)
+{
+    real v[3] = {X[0] - (real)pf->pos[0], X[1] - (real)pf->pos[1], X[2] - (real)pf->pos[2]};
+    real z = (v[0] * (real)pf->fwd[0] + v[1] * (real)pf->fwd[1]) + v[2] * (real)pf->fwd[2];
+    if (!(z > RC(0.0))) return 0;
+    real a = ((v[0] * (real)pf->right[0] + v[1] * (real)pf->right[1]) + v[2] * (real)pf->right[2]) / z;
+    real b = ((v[0] * (real)pf->up[0] + v[1] * (real)pf->up[1]) + v[2] * (real)pf->up[2]) / z;
+    real aspect = (real)W / (real)H;
+    real sx = a / ((real)pf->tan_half * aspect), sy = b / (real)pf->tan_half;
+    real fx = ((sx + RC(1.0)) * (real)W) * RC(0.5), fy = ((RC(1.0) - sy) * (real)H) * RC(0.5);
+    if (!(fx >= RC(0.0) && fx < (real)W && fy >= RC(0.0) && fy < (real)H)) return 0;
+    *qx = (int32_t)fx;
+    *qy = (int32_t)fy;
+    return 1;
+}
+
+void ORC(denoise)(state *st, const orc_frame *fr, const real *gpos, const real *gnrm, const uint32_t *gprim,
+                  const real *in, real *out)
+{
+    const orc_config *c = &st->cfg;
+    const uint32_t W = st->W, H = st->H, NM = c->dn_hist_max, RM = c->dn_radius;
+    real kappa = (real)ORC(distance_scale)(fr->fov_y, W, H);
+    real *acc = st->dn_acc;
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < (long)H; ++y)
+        for (uint32_t x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            real *a = acc + 4 * p;
+            a[0] = a[1] = a[2] = a[3] = RC(0.0);
+            if (gprim[p] == MISS) continue;
+            const real *X = gpos + 4 * p, *n = gnrm + 4 * p, *E = in + 4 * p;
+            int hv = 0;
+            size_t q = 0;
+            int32_t qx, qy;
+            if (st->dn_has_prev && project_cam(&st->dn_pfr, W, H, X, &qx, &qy)) {
+                q = (size_t)qy * W + (size_t)qx;
+                if (st->dn_pprim[q] != MISS && st->dn_hist[4 * q + 3] > RC(0.0)) {
+                    const real *Xq = st->dn_ppos + 4 * q, *nq = st->dn_pnrm + 4 * q;
+                    real ex = X[0] - (real)fr->pos[0], ey = X[1] - (real)fr->pos[1], ez = X[2] - (real)fr->pos[2];
+                    real cs = kappa * RSQRT((ex * ex + ey * ey) + ez * ez);
+                    real pd = RABS(((Xq[0] - X[0]) * n[0] + (Xq[1] - X[1]) * n[1]) + (Xq[2] - X[2]) * n[2]);
+                    real nc = (nq[0] * n[0] + nq[1] * n[1]) + nq[2] * n[2];
+                    hv = pd < cs && nc > RC(0.9);
+                }
+            }
+            const real *Hh = st->dn_hist + 4 * q;
+            if (E[3] == RC(2.0)) {
+                if (hv)
+                    for (int k = 0; k < 4; ++k) a[k] = Hh[k];
+                continue;
+            }
+            if (hv) {
+                real np = Hh[3] + RC(1.0);
+                real nn = np < (real)NM ? np : (real)NM;
+                for (int k = 0; k < 3; ++k) a[k] = Hh[k] + (E[k] - Hh[k]) / nn;
+                a[3] = nn;
+            } else {
+                for (int k = 0; k < 3; ++k) a[k] = E[k];
+                a[3] = RC(1.0);
+            }
+        }
+    /* radius per pixel, then the dilated mask inside the filter */
+    uint32_t *rad = st->dn_rad;
+    for (size_t p = 0; p < (size_t)W * H; ++p) {
+        uint32_t n = (uint32_t)acc[4 * p + 3];
+        rad[p] = gprim[p] == MISS ? 0u : (n == 0 ? RM : RM / n);
+    }
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < (long)H; ++y)
+        for (uint32_t x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            real *o = out + 4 * p;
+            o[3] = in[4 * p + 3];
+            if (gprim[p] == MISS) { o[0] = o[1] = o[2] = RC(0.0); continue; }
+            uint32_t R = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    long yy = y + dy, xx = (long)x + dx;
+                    if (yy < 0 || xx < 0 || yy >= (long)H || xx >= (long)W) continue;
+                    uint32_t r = rad[(size_t)yy * W + (size_t)xx];
+                    R = r > R ? r : R;
+                }
+            const real *a = acc + 4 * p;
+            if (R == 0) { o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; continue; }
+            const real *X = gpos + 4 * p, *n = gnrm + 4 * p;
+            real ex = X[0] - (real)fr->pos[0], ey = X[1] - (real)fr->pos[1], ez = X[2] - (real)fr->pos[2];
+            real cs = kappa * RSQRT((ex * ex + ey * ey) + ez * ez);
+            real s[3] = {RC(0.0), RC(0.0), RC(0.0)}, ws = RC(0.0);
+            for (int dy = -(int)R; dy <= (int)R; ++dy)
+                for (int dx = -(int)R; dx <= (int)R; ++dx) {
+                    long yy = y + dy, xx = (long)x + dx;
+                    if (yy < 0 || xx < 0 || yy >= (long)H || xx >= (long)W) continue;
+                    size_t q = (size_t)yy * W + (size_t)xx;
+                    if (gprim[q] == MISS || acc[4 * q + 3] == RC(0.0)) continue;
+                    const real *nq = gnrm + 4 * q;
+                    real nd = (n[0] * nq[0] + n[1] * nq[1]) + n[2] * nq[2];
+                    nd = rmax(nd, RC(0.0));
+                    real n2 = nd * nd, n4 = n2 * n2, n8 = n4 * n4;
+                    real w = (cs / (cs + RABS(gpos[4 * q + 3] - X[3]))) * n8;
+                    for (int k = 0; k < 3; ++k) s[k] = s[k] + w * acc[4 * q + k];
+                    ws = ws + w;
+                }
+            for (int k = 0; k < 3; ++k) o[k] = ws > RC(0.0) ? s[k] / ws : a[k];
+        }
+    /* the accumulated values become the history */
+    memcpy(st->dn_hist, acc, sizeof(real) * 4 * (size_t)W * H);
+    memcpy(st->dn_ppos, gpos, sizeof(real) * 4 * (size_t)W * H);
+    memcpy(st->dn_pnrm, gnrm, sizeof(real) * 4 * (size_t)W * H);
+    memcpy(st->dn_pprim, gprim, sizeof(uint32_t) * (size_t)W * H);
+    st->dn_pfr = *fr;
+    st->dn_has_prev = 1;
+}
+
+void ORC(denoise_export)(const state *st, real *hist, uint32_t *rad)
+{
+    size_t HW = (size_t)st->W * st->H;
+    memcpy(hist, st->dn_hist, sizeof(real) * 4 * HW);
+    memcpy(rad, st->dn_rad, sizeof(uint32_t) * HW);
 }
 
 /* lookup-only query of the world cache for caller points (pos.w >= 0 is the ray length for
