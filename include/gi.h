@@ -284,6 +284,30 @@ gi_status gi_e4m3_encode(gi_context *ctx, const float *d_in, uint8_t *d_out, uin
 gi_status gi_learned_query(gi_context *ctx, const float *d_pos, const float *d_nrm, uint32_t n,
                            float *d_out, void *stream);
 
+/* ---- screen-space denoiser (Section 2.4.3) ------------------------------------------------
+ * A separate object: it needs the G-buffer, the interpolated irradiance and the camera only.
+ * Temporal accumulation over the reprojected history (valid when the previous pixel held one,
+ * was not sky, lies within the pixel's cell size of its tangent plane and has a normal cosine
+ * above 0.9): history length n = min(n + 1, hist_max) (1..1024), value = history + (E -
+ * history) / n; otherwise n = 1.  Pixels without a probe (flag 2) keep their history.  Then a
+ * spatial filter of radius floor(radius_max / n) (0..16; radius_max at n = 0) dilated over the
+ * 3x3 neighbourhood, weights cs / (cs + |depth difference|) * max(0, normal cosine)^8.  The
+ * accumulated values before the filter are the next frame's history. */
+typedef struct gi_denoiser gi_denoiser;
+gi_status gi_denoiser_create(uint32_t width, uint32_t height, uint32_t hist_max, uint32_t radius_max,
+                             gi_denoiser **out);
+void gi_denoiser_destroy(gi_denoiser *dn);
+/* forget the history (the next frame starts over) */
+gi_status gi_denoiser_reset(gi_denoiser *dn);
+/* device pointers owned by the caller, 16-byte aligned: the G-buffer of gi_render_gbuffer
+ * (pos [H][W][4] with w = view distance, nrm [H][W][4], prim [H][W]), the irradiance of
+ * gi_interpolate_probes [H][W][4] (rgb, flag) -> out [H][W][4] (rgb, the same flag); async on
+ * stream; calls on one denoiser are serialised by the caller */
+gi_status gi_denoise(gi_denoiser *dn, const gi_frame *frame, const float *d_pos, const float *d_nrm,
+                     const uint32_t *d_prim, const float *d_irradiance, float *d_out, void *stream);
+/* host-synchronous: the history (rgb, n) [H][W][4] and the radius per pixel [H][W] */
+gi_status gi_denoiser_export(gi_denoiser *dn, float *h_hist, uint32_t *h_radius);
+
 /* ---- parity, resume and observability (host-synchronous, host pointers) --------------- */
 
 /* Two-level cache export (cache_tiles = 1; host-synchronous): the live tiles in slot order,

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgi.so")
 
-SOURCES = ["gi_capi.cpp", "gi_bvh.cpp", "gi_kernels.hip", "gi_learned.hip"]
+SOURCES = ["gi_capi.cpp", "gi_bvh.cpp", "gi_kernels.hip", "gi_learned.hip", "gi_denoise.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -92,6 +92,11 @@ def lib():
     fn("gi_tiles_export", st, vp, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
     fn("gi_light_grid_export", st, vp, vp, vp, vp, vp, u32)
     fn("gi_restir_export", st, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
+    fn("gi_denoiser_create", st, u32, u32, u32, u32, P(vp))
+    fn("gi_denoiser_destroy", None, vp)
+    fn("gi_denoiser_reset", st, vp)
+    fn("gi_denoise", st, vp, P(Frame), vp, vp, vp, vp, vp, vp)
+    fn("gi_denoiser_export", st, vp, vp, vp)
     fn("gi_set_dynamic_triangles", st, vp, vp, vp, u32, vp)
     fn("gi_render_gbuffer", st, vp, P(Frame), vp, vp, vp, vp, vp)
     fn("gi_spawn_probes", st, vp, P(Frame), vp, vp, vp, vp)
@@ -449,3 +454,45 @@ class GBuffer:
     def host(self):
         return (self.pos.cpu().numpy(), self.nrm.cpu().numpy(), self.alb.cpu().numpy(),
                 self.prim.cpu().numpy().view(np.uint32))
+
+
+class Denoiser:
+    """The screen-space denoiser (gi_denoiser_*): temporal accumulation with a capped history
+    and a spatial filter whose radius follows the history length."""
+
+    def __init__(self, width, height, hist_max=16, radius_max=4):
+        L = lib()
+        h = C.c_void_p()
+        st = L.gi_denoiser_create(width, height, hist_max, radius_max, C.byref(h))
+        if st != GI_OK:
+            raise GIError(f"gi_denoiser_create failed: {ERRORS.get(st, st)}")
+        self.h, self.W, self.H = h, width, height
+
+    def _check(self, st, what):
+        if st != GI_OK:
+            raise GIError(f"{what} failed: {ERRORS.get(st, st)}")
+
+    def __call__(self, frame, pos, nrm, prim, irradiance, out, stream=None):
+        f = make_frame(frame)
+        self._check(lib().gi_denoise(self.h, C.byref(f), _ptr(pos), _ptr(nrm), _ptr(prim), _ptr(irradiance),
+                                     _ptr(out), _stream(stream)), "gi_denoise")
+
+    def reset(self):
+        self._check(lib().gi_denoiser_reset(self.h), "gi_denoiser_reset")
+
+    def state(self):
+        hist = np.zeros((self.H, self.W, 4), np.float32)
+        rad = np.zeros((self.H, self.W), np.uint32)
+        self._check(lib().gi_denoiser_export(self.h, hist.ctypes.data, rad.ctypes.data), "gi_denoiser_export")
+        return hist, rad
+
+    def close(self):
+        if self.h:
+            lib().gi_denoiser_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
