@@ -523,6 +523,21 @@ def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, t
     torch.cuda.synchronize()
     prof = ctx.profile_read()
     ctx.profile(False)
+    dn_ms = None
+    if upscale == 1 and not ray_guiding:
+        # the screen-space denoiser on this workload's last frame, 8 calls (history growing)
+        dn = gi.Denoiser(W, H)
+        den = torch.zeros_like(out)
+        dn(cam, gb.pos, gb.nrm, gb.prim, out, den)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(8):
+            dn(cam, gb.pos, gb.nrm, gb.prim, out, den)
+        e1.record()
+        torch.cuda.synchronize()
+        dn_ms = e0.elapsed_time(e1) / 8
+        dn.close()
     n = frames - timed_from
     P = ((W + 7) // 8) * ((H + 7) // 8)
     rays = (ctx.stats()["rays"] - rays0) / n
@@ -531,6 +546,8 @@ def temporal_measure(log, scene_name="field", W=1920, H=1080, R=64, frames=24, t
                        + (", ray guiding" if ray_guiding else ""),
            "probe_rays_per_frame": int(rays), "ray_fraction": round(rays / (P * R), 4),
            "kernels_ms_per_frame": {k: round(v[1] / n, 5) for k, v in sorted(prof.items()) if k != "gbuffer"}}
+    if dn_ms is not None:
+        res["denoiser_ms_per_frame"] = round(dn_ms, 5)
     if "reconstruct" in prof:
         ms = prof["reconstruct"][1] / max(prof["reconstruct"][0], 1)
         b = P * (1024 + 32 + 1024 + 256)
@@ -562,8 +579,9 @@ def temporal_quality(log, W=512, H=288, R=64, frames=32, ref_R=256, ref_frames=9
     probe): the per-pixel irradiance of frames 24..31 against a converged reference (the mean
     of 88 frames of 256 rays per probe without temporal reuse), as the relative L1 error over
     the image and the ratio of mean levels, for: no reuse; reuse (Algorithms 1, 3); reuse with
-    ray guiding; 2x2 upscaling with adaptive sampling; upscaling with guiding.  The rays per
-    frame are measured by the context's counters."""
+    ray guiding; 2x2 upscaling with adaptive sampling; upscaling with guiding; and the last
+    two modes' ends followed by the screen-space denoiser (Section 2.4.3).  The rays per frame
+    are measured by the context's counters."""
     import torch
 
     from paper_2310_19855_amd import gi
@@ -571,11 +589,13 @@ def temporal_quality(log, W=512, H=288, R=64, frames=32, ref_R=256, ref_frames=9
     scene = I.room_scene()
     cam = I.room_camera(0)
 
-    def run(R_, nframes, keep_from, **kw):
+    def run(R_, nframes, keep_from, denoise=False, **kw):
         ctx = gi.Context(width=W, height=H, rays_per_probe=R_, table_log2=18, bounces=2, **kw)
         ctx.build_bvh(scene)
         gb = gi.GBuffer(H, W)
         out = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+        dn = gi.Denoiser(W, H) if denoise else None
+        den = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
         acc, kept, rays0 = [], 0, 0
         for f in range(nframes):
             cam.index = f
@@ -586,11 +606,15 @@ def temporal_quality(log, W=512, H=288, R=64, frames=32, ref_R=256, ref_frames=9
             ctx.trace_probes(cam)
             ctx.cache_update(cam)
             ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, out)
+            if dn is not None:
+                dn(cam, gb.pos, gb.nrm, gb.prim, out, den)
             if f >= keep_from:
-                acc.append(out[..., :3].clone())
+                acc.append((den if dn is not None else out)[..., :3].clone())
                 kept += 1
         rays = (ctx.stats()["rays"] - rays0) / max(kept, 1)
         ctx.close()
+        if dn is not None:
+            dn.close()
         return torch.stack(acc), rays
 
     ref_frames_t, _ = run(ref_R, ref_frames, 8)
@@ -598,7 +622,9 @@ def temporal_quality(log, W=512, H=288, R=64, frames=32, ref_R=256, ref_frames=9
     lum = ref.mean(-1)
     on = lum > 1e-3 * lum.max()
     modes = {"no_reuse": {}, "reuse": dict(temporal=1), "reuse_guided": dict(temporal=1, ray_guiding=1),
-             "upscale_2x2": dict(temporal=1, upscale=2), "upscale_2x2_guided": dict(temporal=1, upscale=2, ray_guiding=1)}
+             "upscale_2x2": dict(temporal=1, upscale=2), "upscale_2x2_guided": dict(temporal=1, upscale=2, ray_guiding=1),
+             "no_reuse_denoised": dict(denoise=True),
+             "upscale_2x2_guided_denoised": dict(temporal=1, upscale=2, ray_guiding=1, denoise=True)}
     res = {"workload": f"room {W}x{H}, fixed camera, R={R}, two bounces, frames 24..{frames - 1}; reference "
                        f"R={ref_R} without reuse, mean of {ref_frames} frames", "modes": {}}
     for name, kw in modes.items():
