@@ -15,11 +15,15 @@
  *     references.
  *
  * Section references are to the GI-1.0 paper (Boisse et al., 2022):
- *   Section 2.1.1 temporal upscale / spawning, 2.1.3 ray tracing of probes, 2.1.4 radiance
- *   blending and backup, 2.1.5 probe masking (Algorithm 4), 2.1.7 adaptive cell size
- *   (Algorithm 6), 2.2.1 spatial-hash world cache, 2.2.2 light-leak bit, 2.2.3 temporal
- *   accumulation into cells, 2.2.4 radiance feedback, 2.3.1 light sampling with one shadow
- *   ray, 2.4.1 per-pixel interpolation, 2.4.2 spherical harmonics.
+ *   Section 2.1.1 spawning, probe reprojection (Algorithm 1) and temporal upscaling, 2.1.2
+ *   adaptive sampling (Algorithm 2) and ray guiding with the parallax-corrected
+ *   reconstruction, 2.1.3 ray tracing of probes, 2.1.4 radiance blending (Algorithm 3) and
+ *   backup, 2.1.5 probe masking (Algorithm 4), 2.1.6 probe-space filter (Algorithm 5), 2.1.7
+ *   adaptive cell size (Algorithm 6), 2.2.1 spatial-hash world cache and its levels of
+ *   detail, 2.2.2 light-leak bit, 2.2.3 temporal accumulation into cells and the two-level
+ *   tiled cache with MIP prefiltering, 2.2.4 radiance feedback, 2.3 light sampling (one
+ *   shadow ray; RIS over the light grid; world-space reservoir reuse), 2.4.1 per-pixel
+ *   interpolation, 2.4.2 spherical harmonics, 2.4.3 screen-space denoising.
  * Definitions that the paper leaves open are marked READING and listed in the design notes.
  *
  * parity unpinned: none of the functions below lacks a pin; see tests/test_oracle_*.py.
