@@ -310,6 +310,8 @@ struct SceneView {
 // below the distance); spilled entries carry 0.
 template <int K, int BLOCK>
 struct TStack {
+  // the LDS part is a ring indexed with & (K - 1)
+  static_assert(K > 0 && (K & (K - 1)) == 0, "the LDS stack holds a power-of-two number of entries");
   uint32_t* lds;      // &lds_array[lane]
   uint16_t* tlds;     // &lds_distance_array[lane]
   uint32_t* spill;    // &spill_array[lane id]; entry i at spill[i * stride]
