@@ -345,6 +345,27 @@ def test_restir_reservoir_reuse_many_light_room():
     assert len(r["M"]) > 100 and r["M"].max() > 4
 
 
+def test_every_option_together():
+    """every part beyond the hot path at once on the many-light room with a turning camera:
+    2x2 temporal upscaling with adaptive sampling and ray guiding, the probe filter, the
+    two-level cache with levels of detail, the light grid with RIS and reservoir reuse, two
+    bounces; four frames, every stage against the oracle"""
+    import math
+    sc = I.lights_room_scene()
+
+    def cam(f):
+        fr = I.room_camera(0)
+        yaw = math.radians(1.5 * f)
+        c, s = math.cos(yaw), math.sin(yaw)
+        rot = lambda v: np.array([c * v[0] + s * v[2], v[1], -s * v[0] + c * v[2]], np.float32)
+        fr.fwd, fr.right, fr.up = rot(fr.fwd), rot(fr.right), rot(fr.up)
+        return fr
+    _run_stage_parity(sc, dict(width=100, height=76, rays_per_probe=32, table_log2=12, bounces=2, temporal=1,
+                               upscale=2, ray_guiding=1, probe_filter=1, cache_tiles=1, tile_min_samples=8,
+                               lod_scale=0.06, light_grid=1, lgrid_dim=8, lgrid_k=32, ris_candidates=4, restir=1,
+                               restir_log2=16), [0, 1, 2, 3], camera=cam)
+
+
 def test_light_grid_field_moving_light():
     """the grid and RIS on the field, whose moving light changes the emitters every frame;
     one candidate (a uniform pick from the cell's list) and the default grid"""
