@@ -23,7 +23,7 @@
  *   detail, 2.2.2 light-leak bit, 2.2.3 temporal accumulation into cells and the two-level
  *   tiled cache with MIP prefiltering, 2.2.4 radiance feedback, 2.3 light sampling (one
  *   shadow ray; RIS over the light grid; world-space reservoir reuse), 2.4.1 per-pixel
- *   interpolation, 2.4.2 spherical harmonics, 2.4.3 screen-space denoising.
+ *   interpolation, 2.4.2 spherical harmonics (with SH reprojection), 2.4.3 screen-space denoising.
  * Definitions that the paper leaves open are marked READING and listed in the design notes.
  *
  * parity unpinned: none of the functions below lacks a pin; see tests/test_oracle_*.py.
@@ -802,6 +802,7 @@ typedef struct state {
     orc_frame prev_fr;     /* camera of the previous frame */
     uint32_t *prev_mask;   /* [P] level 0 of the previous frame's probe mask */
     real *prev_pos, *prev_nrm, *prev_atlas;
+    real *prev_sh;         /* [P][27] the previous frame's SH (reprojected with the probes) */
     uint32_t *win;         /* [P] pixel (mask encoding) the previous probe moved to, or SENTINEL */
     uint32_t *hist;        /* [P] previous tile of that probe, or SENTINEL */
     uint32_t *traced;      /* [P] the tile's probe traces rays this frame */
@@ -1147,6 +1148,7 @@ state *ORC(create)(const orc_config *cfg, scene *sc)
     st->prev_pos = (real *)calloc(4 * P, sizeof(real));
     st->prev_nrm = (real *)calloc(4 * P, sizeof(real));
     st->prev_atlas = (real *)calloc(P * NCELL * 4, sizeof(real));
+    st->prev_sh = (real *)calloc(P * 27, sizeof(real));
     st->win = (uint32_t *)calloc(P, sizeof(uint32_t));
     st->hist = (uint32_t *)calloc(P, sizeof(uint32_t));
     st->traced = (uint32_t *)calloc(P, sizeof(uint32_t));
@@ -1172,7 +1174,7 @@ void ORC(destroy)(state *st)
     }
     free(st->rs_claim); free(st->r_rsy); free(st->r_rsW); free(st->r_rsk); free(st->r_rsM);
     free(st->dn_hist); free(st->dn_acc); free(st->dn_ppos); free(st->dn_pnrm); free(st->dn_pprim); free(st->dn_rad);
-    free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->win);
+    free(st->prev_mask); free(st->prev_pos); free(st->prev_nrm); free(st->prev_atlas); free(st->prev_sh); free(st->win);
     free(st->hist); free(st->traced); free(st->recon); free(st->cdf);
     free(st);
 }
@@ -2341,6 +2343,17 @@ static void gather(state *st)
 #define SH_C20 0.31539156525252005  /* sqrt(5/pi)/4 */
 #define SH_C22 0.54627421529603959  /* sqrt(15/pi)/4 */
 
+/* SH reprojection (Section 2.4.2): a kept probe that traces nothing this frame and keeps the
+ * reprojected probe's atlas as it is (no ray guiding, no probe filter) keeps that probe's SH
+ * too, so only the other probes are projected.
+ * READING: the SH is world-space radiance, so the moved probe keeps it as it was rather than
+ * re-projecting the copied cells in its own (slightly turned) frame. */
+static int keeps_previous_sh(const state *st, long p)
+{
+    return st->cfg.temporal && !st->guided && !st->cfg.probe_filter && !st->traced[p] &&
+           st->hist[p] != SENTINEL && st->mask[p] != SENTINEL;
+}
+
 static void sh_project(state *st)
 {
 #pragma omp parallel for schedule(static)
@@ -2348,6 +2361,10 @@ static void sh_project(state *st)
         real *out = st->sh + (size_t)p * 27;
         for (int i = 0; i < 27; ++i) out[i] = RC(0.0);
         if (st->mask[p] == SENTINEL) continue;
+        if (keeps_previous_sh(st, p)) {
+            memcpy(out, st->prev_sh + (size_t)st->hist[p] * 27, sizeof(real) * 27);
+            continue;
+        }
         const real *n = st->pnrm + 4 * p;
         real t[3], b[3];
         onb(n, t, b);
@@ -2559,6 +2576,7 @@ static void save_history(state *st, const orc_frame *fr)
     memcpy(st->prev_pos, st->ppos, sizeof(real) * 4 * st->P);
     memcpy(st->prev_nrm, st->pnrm, sizeof(real) * 4 * st->P);
     memcpy(st->prev_atlas, st->atlas, sizeof(real) * 4 * NCELL * st->P);
+    memcpy(st->prev_sh, st->sh, sizeof(real) * 27 * st->P);
     st->prev_fr = *fr;
     st->has_prev = 1;
 }

@@ -203,6 +203,7 @@ void free_frame_buffers(gi_context* c) {
   dfree(c->d_prev_pos);
   dfree(c->d_prev_nrm);
   dfree(c->d_prev_atlas);
+  dfree(c->d_prev_sh);
   dfree(c->d_win);
   dfree(c->d_hist);
   dfree(c->d_place);
@@ -365,6 +366,7 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
     A(dalloc(&c->d_hist, (size_t)c->P));
   }
   if (cfg->upscale > 1) {
+    A(dalloc(&c->d_prev_sh, (size_t)c->P * 28));
     A(dalloc(&c->d_place, (size_t)c->P));
     A(dalloc(&c->d_traced, (size_t)c->P));
     A(dalloc(&c->d_cls, (size_t)c->P));
@@ -718,6 +720,8 @@ gi_status gi_cache_update(gi_context* c, const gi_frame* f, void* stream) {
     GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_pos, c->d_ppos, 16 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
     GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_nrm, c->d_pnrm, 16 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
     GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_atlas, c->d_atlas, 16 * 64 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
+    if (c->d_prev_sh)
+      GI_TRY_HIP(c, hipMemcpyAsync(c->d_prev_sh, c->d_sh, 4 * 28 * (size_t)c->P, hipMemcpyDeviceToDevice, s));
     c->prev_frame = *f;
     c->has_prev = true;
   }

@@ -91,6 +91,7 @@ struct gi_context {
   float4* d_prev_pos = nullptr;      // [P]
   float4* d_prev_nrm = nullptr;      // [P]
   float4* d_prev_atlas = nullptr;    // [P*64]
+  float* d_prev_sh = nullptr;        // [P*28] with upscale > 1: SH kept by probes that trace nothing
   uint32_t* d_win = nullptr;         // [P] pixel the previous probe moved to, or sentinel
   uint32_t* d_hist = nullptr;        // [P] previous tile of that probe, or sentinel
   // temporal upscaling (config upscale > 1, Algorithm 2): placement, traced flags, override list

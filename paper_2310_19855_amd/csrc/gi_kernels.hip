@@ -1297,7 +1297,8 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
                                                   const float* moments, uint32_t R, float s0, float s1, float s2,
                                                   LearnedGatherIn lg, uint32_t do_sh, const uint32_t* hist,
                                                   const uint32_t* traced, const float4* recon,
-                                                  const float4* prev_atlas, float4* atlas, float* sh) {
+                                                  const float4* prev_atlas, const float* prev_sh, float4* atlas,
+                                                  float* sh) {
   __shared__ float rv[kGatherMaxR][4];
   __shared__ uint32_t rc[kGatherMaxR];
   __shared__ float cv[64][4];
@@ -1333,7 +1334,13 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
       }
     } else {
       const uint32_t hp = hist ? hist[p] : kSentinel;
-      if (hp != kSentinel) q = prev_atlas[(size_t)hp * 64 + lane];
+      if (hp != kSentinel) {
+        atlas[(size_t)p * 64 + lane] = prev_atlas[(size_t)hp * 64 + lane];
+        // SH reprojection (Section 2.4.2): the copied atlas keeps its SH as well, as the
+        // world-space radiance it was, without a new projection
+        if (do_sh && lane < 28) sh[(size_t)p * 28 + lane] = prev_sh[(size_t)hp * 28 + lane];
+        return;
+      }
     }
     atlas[(size_t)p * 64 + lane] = q;
     if (do_sh) probe_sh(p, lane, pnrm[p], moments, q.x, q.y, q.z, sh);
@@ -2149,7 +2156,7 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const uint32_t filt = c->cfg.probe_filter;
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->cfg.cache_tiles ? c->tab.Lq : c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_atlas, c->d_sh)));
+  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->cfg.cache_tiles ? c->tab.Lq : c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_prev_sh, c->d_atlas, c->d_sh)));
   if (filt) {
     // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
     const MipInfo mi = mip_info(c);

@@ -13,6 +13,7 @@ What the method fixes, checked here without re-running the oracle's code path:
 - with a fixed camera a probe, once placed, stays on its pixel; a kept probe that does not
   trace keeps its previous radiance exactly; after the four quadrants of the spawn tile have
   each been jittered into (frames 0, 1, 3, 4 of the Halton sequence) every tile holds a probe;
+  such a kept probe keeps its SH as well (SH reprojection);
 - Algorithm 2 under this implementation's reading (override tiles in tile order, pick by the
   counter hash of dimension 7, the lowest-numbered picker wins) on a frame where override and
   empty tiles exist (frame 2 of the fixed camera)."""
@@ -51,7 +52,7 @@ def _run(cfg, frames, cam=None):
         pr = st.probes()
         win, hist, traced = st.temporal(with_traced=True)
         rays = int(st.stats()["rays"])
-        out.append(dict(mask=pr["mask"][:P].copy(), atlas=pr["atlas"].copy(), win=win, hist=hist,
+        out.append(dict(mask=pr["mask"][:P].copy(), atlas=pr["atlas"].copy(), sh=pr["sh"].copy(), win=win, hist=hist,
                         traced=traced.astype(bool), rays=rays - prev_rays, prim=g[3].reshape(-1)))
         prev_rays = rays
     return st, out
@@ -106,10 +107,12 @@ def test_fixed_camera_sequence():
         assert np.array_equal(o["mask"][prev_placed], p["mask"][prev_placed]), f
         assert np.array_equal(o["hist"][prev_placed], np.nonzero(prev_placed)[0].astype(np.uint32))
         assert (placed >= prev_placed).all()
-        # kept probes that did not trace keep their radiance exactly
+        # kept probes that did not trace keep their radiance exactly, and their SH with it
+        # (SH reprojection: no projection for them)
         kept = prev_placed & ~o["traced"]
         assert kept.any()
         assert np.array_equal(o["atlas"][kept], p["atlas"][kept]), f
+        assert np.array_equal(o["sh"][kept], p["sh"][kept]), f
         # kept probes that traced blend new rays into it
         fresh = prev_placed & o["traced"]
         if fresh.any():
