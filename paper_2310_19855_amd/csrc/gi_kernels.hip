@@ -1221,6 +1221,8 @@ __global__ void k_cache_update(uint32_t N, uint32_t* fp, uint64_t* key, uint4* a
 // one wave per probe, lane = atlas cell
 // ------------------------------------------------------------------------------------------
 
+// the configuration caps the rays per probe at 256; up to 64 rays the kernel is built with a
+// 64-entry ray stage, which cuts its LDS from 7.25 to 3.25 KiB and lets more waves share a CU
 constexpr int kGatherMaxR = 256;
 
 // one butterfly step of a transpose-reduce over the first 2H entries of v: lanes whose bit
@@ -1292,6 +1294,7 @@ __device__ inline void probe_sh(uint32_t p, uint32_t lane, float4 nn, const floa
   const float out = v[0] + __shfl_xor(v[0], 1, 64);
   if ((lane & 1u) == 0u && coef < 28u) sh[(size_t)p * 28 + coef] = coef < 27u ? out : 0.0f;}
 
+template <int MAXR>
 __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const float4* pnrm, const uint4* rec,
                                                   const float4* L, const float4* tnrm, const float4* mats,
                                                   const float* moments, uint32_t R, float s0, float s1, float s2,
@@ -1299,8 +1302,8 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
                                                   const uint32_t* traced, const float4* recon,
                                                   const float4* prev_atlas, const float* prev_sh, float4* atlas,
                                                   float* sh) {
-  __shared__ float rv[kGatherMaxR][4];
-  __shared__ uint32_t rc[kGatherMaxR];
+  __shared__ float rv[MAXR][4];
+  __shared__ uint32_t rc[MAXR];
   __shared__ float cv[64][4];
   __shared__ float cs[64][4];
   __shared__ uint32_t cn[64];
@@ -2156,7 +2159,12 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const uint32_t filt = c->cfg.probe_filter;
-  GI_TIMED(c, "gather_sh", s, (k_gather_sh<<<c->P, 64, 0, s>>>(c->d_mask, c->d_pnrm, c->d_rec, c->cfg.cache_tiles ? c->tab.Lq : c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_prev_sh, c->d_atlas, c->d_sh)));
+#define GI_GATHER_ARGS c->d_mask, c->d_pnrm, c->d_rec, c->cfg.cache_tiles ? c->tab.Lq : c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_prev_sh, c->d_atlas, c->d_sh
+  if (c->R <= 64u)
+    GI_TIMED(c, "gather_sh", s, (k_gather_sh<64><<<c->P, 64, 0, s>>>(GI_GATHER_ARGS)));
+  else
+    GI_TIMED(c, "gather_sh", s, (k_gather_sh<kGatherMaxR><<<c->P, 64, 0, s>>>(GI_GATHER_ARGS)));
+#undef GI_GATHER_ARGS
   if (filt) {
     // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
     const MipInfo mi = mip_info(c);
