@@ -175,10 +175,11 @@ def test_field_levels_of_detail_frames_and_query():
     assert_close(g[:, :3], o[:, :3], what="query")
 
 
-@pytest.mark.parametrize("R", [1, 256])
+@pytest.mark.parametrize("R", [1, 64, 65, 256])
 def test_extreme_rays_per_probe(R):
     """the smallest and the largest number of rays per probe (256 rays: four waves per probe
-    in the trace, four chunks in the gather's per-cell sums)"""
+    in the trace, four chunks in the gather's per-cell sums), and both sides of the gather's
+    64-entry ray stage (64 rays fill it; 65 take the full stage with a ragged second chunk)"""
     _run_stage_parity(I.room_scene(), dict(width=72, height=40, rays_per_probe=R, table_log2=16, bounces=2), [0, 1])
 
 
