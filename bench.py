@@ -51,6 +51,30 @@ def _traffic(kernel, workload, form):
     return k.get("bytes_per_launch")
 
 
+# Table 1 of the paper splits a frame into three columns; each kernel of the pass falls in one
+# (the paper's passes to columns, Section 5): probe rays are "raytracing"; spawn, the world
+# cache's insert / light sample / shadow ray / update and the probe gather are "caching &
+# sampling"; SH projection (fused into the gather here), interpolation and filtering are
+# "interpolate & denoise".  The learned surrogate is not in the paper: its own column.
+TABLE1 = {"trace_probes": "raytracing",
+          "spawn": "caching_sampling", "mask_mip": "caching_sampling", "shade_hits": "caching_sampling",
+          "cache_update": "caching_sampling", "cache_update_tiles": "caching_sampling",
+          "gather_sh": "caching_sampling", "reproject": "caching_sampling", "reconstruct": "caching_sampling",
+          "lg_box": "caching_sampling", "lg_box_final": "caching_sampling", "light_grid": "caching_sampling",
+          "restir_clear": "caching_sampling", "restir_store": "caching_sampling",
+          "interpolate": "interpolate_denoise", "filter_x": "interpolate_denoise", "filter_y": "interpolate_denoise"}
+
+
+def table1_buckets(kern, frames):
+    """ms per frame per Table-1 column from per-kernel totals"""
+    out = {"raytracing": 0.0, "caching_sampling": 0.0, "interpolate_denoise": 0.0, "learned": 0.0, "other": 0.0}
+    for name, v in kern.items():
+        b = TABLE1.get(name, "learned" if name.startswith(("learned_", "mlp_", "train", "infer", "adam", "judge",
+                                                             "select", "sort")) else "other")
+        out[b] += v["avg_ms"] * v["launches"] / max(frames, 1)
+    return {k: round(v, 5) for k, v in out.items() if v or k != "other"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,9 +83,12 @@ def main():
     ap.add_argument("--workload", default="field1080")
     ap.add_argument("--profile-frames", type=int, default=5)
     ap.add_argument("--cpu-frames", type=int, default=40,
-                    help="oracle frames timed for cpu_baseline (about 0.25 s each on 16 host threads)")
+                    help="oracle frames timed for cpu_baseline (about 0.2 s each on 16 host threads)")
+    ap.add_argument("--cpu-single-frames", type=int, default=2, help="oracle frames timed on one host thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the plain / MLP-BF16 / MLP-FP8 comparison")
+    ap.add_argument("--forms", metavar="PATH", default=None,
+                    help="after the headline line, run the optional sweeps (cache forms, 4K, furnace, probe "
+                         "filter, temporal reuse, light sampling) and write them as JSON to PATH")
     ap.add_argument("--form", default="plain", choices=("plain", "mlp_bf16", "mlp_fp8"),
                     help="cache form of the timed frames (learned forms train and infer every frame)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -75,14 +102,39 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    line = headline(args, log)
+    print(json.dumps(line), flush=True)
+    if args.forms:
+        forms = optional_sweeps(log)
+        with open(args.forms, "w") as fh:
+            json.dump(forms, fh, indent=1)
+        log(f"[bench] optional sweeps written to {args.forms}")
 
-    import numpy as np
+
+def optional_sweeps(log):
+    import torch
+    torch.cuda.empty_cache()
+    forms = forms_comparison(log)
+    forms.update(field4k_and_furnace(log))
+    forms["probe_filter"] = probe_filter_measure(log)
+    forms["temporal_reuse"] = temporal_measure(log)
+    forms["temporal_upscale_2x2"] = temporal_measure(log, upscale=2, with_cpu=False)
+    forms["temporal_upscale_2x2_guided"] = temporal_measure(log, upscale=2, ray_guiding=1, with_cpu=False)
+    forms["temporal_quality"] = temporal_quality(log)
+    forms["light_sampling"] = light_sampling_measure(log)
+    return forms
+
+
+def headline(args, log):
+    """The timed frames of the workload, per-kernel times, the roofline of the dominant kernel
+    and the CPU oracle on a bounded sample of the same workload: the benchmark's one line."""
+    import numpy as np  # noqa: F401
     import torch
 
     from paper_2310_19855_amd import gi
     from paper_2310_19855_amd import inputs as I
 
-    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
     preset = dict(I.PRESETS[args.workload])
     W, H, R = preset["width"], preset["height"], preset["rays_per_probe"]
     scene = I.make_scene(preset["scene"])
@@ -149,8 +201,11 @@ def main():
     stats = ctx.stats()
     ms_per_frame = wall * 1e3 / args.steps
     log(f"[bench] {args.steps} frames: {ms_per_frame:.3f} ms/frame wall, {gpu_ms / args.steps:.3f} ms/frame events")
+    if stats["wraps"]:
+        raise RuntimeError(f"{stats['wraps']} fixed-point cell sums wrapped: the cached averages are corrupt")
 
-    # per-kernel device times (HIP events on the launch stream), separate pass
+    # per-kernel device times (HIP events on the launch stream), separate pass over frames
+    # already seen (the cache is warm, as in the timed frames)
     ctx.profile(True)
     ctx.profile_read()
     for k in range(args.profile_frames):
@@ -159,14 +214,14 @@ def main():
     prof = ctx.profile_read()
     ctx.profile(False)
     trav = ctx.measure_traversal()
-    pf = ctx.stats()
     kern = {name: dict(launches=c, avg_ms=ms / max(c, 1)) for name, (c, ms) in prof.items()}
 
-    probes_valid = stats["rays"] / args.steps / R
     rays_per_frame = stats["rays"] / args.steps
     hits_per_frame = stats["hits"] / args.steps
     trace_ms = kern.get("trace_probes", {}).get("avg_ms", float("nan"))
     mrays = rays_per_frame / (trace_ms * 1e-3) / 1e6 if trace_ms == trace_ms else None
+    total_rays = (stats["rays"] + stats["shadow"] + stats["bounce"]) / args.steps
+    frame_ms_events = gpu_ms / args.steps
 
     # algorithmic bytes per launch (the traffic the method must move), per kernel
     P = int(dims[0])
@@ -189,8 +244,9 @@ def main():
             v["gbs"] = alg[name] / (v["avg_ms"] * 1e-3) / 1e9
             v["frac_hbm"] = v["gbs"] / HBM_PEAK_GBS
         v["share"] = v["avg_ms"] * v["launches"] / max(args.profile_frames, 1) / total_ms if total_ms else None
-    # the traversal kernels are bound by VALU issue (their node and triangle bytes come from L2
-    # and the Infinity Cache): their roofline is fp32 ALU operations against the VALU peak
+    # the traversal's arithmetic view beside its HBM view: the fp32 operations of the tests
+    # the walk runs against the VALU issue peak (its node and triangle bytes come mostly from
+    # L2 and the Infinity Cache, so the byte roofline is an upper bound on what it could take)
     alg_ops = {"trace_probes": trav["probe_nodes"] * NODE_OPS + trav["probe_tris"] * TRI_OPS,
                "shade_hits": trav["shadow_nodes"] * NODE_OPS + trav["shadow_tris"] * TRI_OPS}
     for name, v in kern.items():
@@ -199,42 +255,33 @@ def main():
             v["tops"] = alg_ops[name] / (v["avg_ms"] * 1e-3) / 1e12
             v["frac_alu"] = v["tops"] / VALU_PEAK_TOPS
     dk = kern[dom]
-    view_hbm = {"alg_bytes_per_launch": dk.get("alg_bytes"), "achieved_gbs": round(dk.get("gbs", 0.0), 2),
-                "peak_gbs": HBM_PEAK_GBS, "frac": round(dk.get("frac_hbm", 0.0), 5)}
-    if dom in ALU_BOUND:
-        roofline = {"kernel": dom, "bound": "alu", "achieved": round(dk["tops"], 3), "peak": round(VALU_PEAK_TOPS, 2),
-                    "unit": "TFLOP/s", "frac": round(dk["frac_alu"], 5),
-                    "traffic": _traffic(dom, args.workload, args.form),
-                    "alg_ops_per_launch": dk["alg_ops"], "hbm_view": view_hbm}
-    else:
-        roofline = {"kernel": dom, "bound": "hbm", "achieved": view_hbm["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": view_hbm["frac"], "traffic": _traffic(dom, args.workload, args.form),
-                    "alg_bytes_per_launch": dk.get("alg_bytes")}
-    roofline.update({"avg_launch_ms": dk["avg_ms"],
-                     "bytes_per_probe_ray": (trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES) / pr_rays,
-                     "nodes_per_probe_ray": trav["probe_nodes"] / pr_rays,
-                     "tris_per_probe_ray": trav["probe_tris"] / pr_rays})
+    traffic = _traffic(dom, args.workload, args.form)
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(dk.get("gbs", 0.0), 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dk.get("frac_hbm", 0.0), 5), "traffic": traffic,
+                "alg_bytes_per_launch": dk.get("alg_bytes"), "avg_launch_ms": round(dk["avg_ms"], 5)}
+    if traffic:
+        roofline["dram_frac_of_alg_bytes"] = round(traffic / max(dk.get("alg_bytes", 1), 1), 4)
+    if dom in alg_ops:
+        roofline["alu_view"] = {"alg_ops_per_launch": dk["alg_ops"], "achieved": round(dk["tops"], 3),
+                                "peak": round(VALU_PEAK_TOPS, 2), "unit": "T fp32 op/s",
+                                "frac": round(dk["frac_alu"], 5)}
+    if dom in ("trace_probes", "shade_hits"):
+        roofline.update({"bytes_per_probe_ray": round((trav["probe_nodes"] * NODE_BYTES
+                                                       + trav["probe_tris"] * TRI_BYTES) / pr_rays, 1),
+                         "nodes_per_probe_ray": round(trav["probe_nodes"] / pr_rays, 3),
+                         "tris_per_probe_ray": round(trav["probe_tris"] / pr_rays, 3)})
     log(f"[bench] kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms x{v['launches'] // max(args.profile_frames, 1)}"
                                          for k, v in sorted(kern.items(), key=lambda kv: -kv[1]['avg_ms'] * kv[1]['launches'])))
+    buckets = table1_buckets(kern, args.profile_frames)
+    log(f"[bench] Table-1 columns (ms/frame): {buckets}")
 
     cpu = None
     if not args.no_cpu_baseline and args.form == "plain":
-        cpu = cpu_baseline(scene, cfg, cams, args.cpu_frames, log)
-    forms = None
-    if not args.no_forms:
         del gbs
-        del ctx
         torch.cuda.empty_cache()
-        forms = forms_comparison(log)
-        forms.update(field4k_and_furnace(log))
-        forms["probe_filter"] = probe_filter_measure(log)
-        forms["temporal_reuse"] = temporal_measure(log)
-        forms["temporal_upscale_2x2"] = temporal_measure(log, upscale=2, with_cpu=False)
-        forms["temporal_upscale_2x2_guided"] = temporal_measure(log, upscale=2, ray_guiding=1, with_cpu=False)
-        forms["temporal_quality"] = temporal_quality(log)
-        forms["light_sampling"] = light_sampling_measure(log)
+        cpu = cpu_baseline(scene, cfg, args.cpu_frames, log, single_frames=args.cpu_single_frames)
 
-    line = {
+    return {
         "metric": "GI ms/frame & probe Mrays/s at 1080p; plain vs MLP cache at fixed rel. error",
         "value": round(ms_per_frame, 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_frame, 4), "higher_is_better": False,
@@ -245,16 +292,18 @@ def main():
                                f"{preset['bounces']} bounce(s), frames {args.warmup}..{n_frames - 1}",
                    "cache": args.form},
         "probe_mrays_per_s": round(mrays, 1) if mrays else None,
+        "total_mrays_per_s": round(total_rays / (frame_ms_events * 1e-3) / 1e6, 1),
         "probe_rays_per_frame": int(rays_per_frame), "hits_per_frame": int(hits_per_frame),
-        "gpu_event_ms_per_frame": round(gpu_ms / args.steps, 4),
+        "shadow_rays_per_frame": int(stats["shadow"] / args.steps),
+        "gpu_event_ms_per_frame": round(frame_ms_events, 4),
+        "table1_ms_per_frame": buckets,
+        "fixed_point_wraps": int(stats["wraps"]), "overflow_drops": int(stats["overflow"]),
         "bvh_build_s": round(t_bvh, 2),
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "cache_forms": forms,
     }
-    print(json.dumps(line), flush=True)
 
 
 FORMS = {"plain": 0, "plain_lod": 0, "plain_tiles": 0, "plain_lod_tiles": 0, "mlp_bf16": 1, "mlp_fp8": 2}
@@ -785,44 +834,59 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_read_bytes": n * 4, "copy_write_bytes": n * 4, "launches": 5}), flush=True)
 
 
-def cpu_baseline(scene, cfg, cams, frames, log, single_frames=2):
-    """The oracle (plain C, all host threads) on the same scene, config and frames at full
-    resolution: spawn -> trace -> update -> interpolate, G-buffer excluded, averaged."""
+def cpu_baseline(scene, cfg, frames, log, single_frames=2):
+    """The oracle (plain C, float32 parity mode, all host threads) on the same scene, config and
+    frames at full resolution: spawn -> trace -> cache update -> gather + SH -> interpolate per
+    frame, each stage timed; G-buffer rendering and the oracle's BVH build excluded.  Then the
+    same on one thread over the first single_frames frames with a fresh cache."""
     import oracle as O
+    from paper_2310_19855_amd import inputs as I
     cores = O.set_threads(1)        # the threads the parallel loops use (OMP_NUM_THREADS or all)
     O.set_threads(cores)
     t0 = time.time()
     osc = O.OracleScene(scene)
-    st = O.OracleFrameState(osc, dict(O.default_config(), **cfg))
     t_build = time.time() - t0
-    tot = 0.0
-    for f in range(frames):
-        osc.set_frame_dynamic(f)
-        g = osc.gbuffer(cams[f], cfg["width"], cfg["height"])
-        t1 = time.time()
-        st.frame(cams[f], g)
-        tot += time.time() - t1
-        log(f"[bench] cpu oracle frame {f}: {time.time() - t1:.2f}s")
-    ms = tot * 1e3 / frames
-    # the same oracle on one thread: a fresh frame state over the first few frames
+    stage_names = ("spawn", "trace", "update", "gather_sh", "interpolate")
+
+    def run(nframes):
+        st = O.OracleFrameState(osc, dict(O.default_config(), **cfg))
+        tot = dict.fromkeys(stage_names, 0.0)
+        for f in range(nframes):
+            cam = I.camera_for(scene.name, f)
+            cam.index = f
+            osc.set_frame_dynamic(f)
+            pos, nrm, _alb, prim = osc.gbuffer(cam, cfg["width"], cfg["height"])
+            t = [time.perf_counter()]
+            st.spawn(cam, pos, nrm, prim)
+            t.append(time.perf_counter())
+            st.trace(cam)
+            t.append(time.perf_counter())
+            st.cache_update_only()
+            t.append(time.perf_counter())
+            st.probe_pass(cam)
+            t.append(time.perf_counter())
+            st.interpolate(cam, pos, nrm, prim)
+            t.append(time.perf_counter())
+            for i, k in enumerate(stage_names):
+                tot[k] += t[i + 1] - t[i]
+            log(f"[bench] cpu oracle frame {f}: {t[-1] - t[0]:.2f}s")
+        return {k: v * 1e3 / max(nframes, 1) for k, v in tot.items()}
+
+    stages = run(frames)
+    ms = sum(stages.values())
     one = None
     if single_frames:
         prev = O.set_threads(1)
-        st1 = O.OracleFrameState(osc, dict(O.default_config(), **cfg))
-        tot1 = 0.0
-        for f in range(single_frames):
-            osc.set_frame_dynamic(f)
-            g = osc.gbuffer(cams[f], cfg["width"], cfg["height"])
-            t1 = time.time()
-            st1.frame(cams[f], g)
-            tot1 += time.time() - t1
+        s1 = run(single_frames)
         O.set_threads(prev)
-        one = {"value": round(tot1 * 1e3 / single_frames, 1), "unit": "ms/frame", "cores": 1,
+        one = {"value": round(sum(s1.values()), 1), "unit": "ms/frame", "cores": 1,
+               "stages_ms": {k: round(v, 2) for k, v in s1.items()},
                "sample": f"frames 0..{single_frames - 1}, fresh cache"}
         log(f"[bench] cpu oracle, one thread: {one['value']:.0f} ms/frame")
     return {"value": round(ms, 1), "unit": "ms/frame", "cores": cores, "kind": "oracle",
-            "sample": f"{frames} full frames (frames 0..{frames - 1}) of the same workload, "
-                      f"spawn..interpolate, G-buffer and BVH build ({t_build:.1f}s) excluded",
+            "stages_ms": {k: round(v, 2) for k, v in stages.items()},
+            "sample": f"{frames} full frames (frames 0..{frames - 1}) of the same workload, fresh cache, "
+                      f"spawn..interpolate, G-buffer and the oracle's BVH build ({t_build:.1f}s) excluded",
             "host": _host_cpu(), "single_thread": one}
 
 

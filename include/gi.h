@@ -78,7 +78,9 @@ typedef struct gi_config {
     uint32_t cache_mode;         /* GI_CACHE_*                                            */
     uint32_t probe_filter;       /* 1: separable 7x7 probe-space filter (Algorithm 5) before SH */
     float cell_scale;            /* S = 1 / cell size of the position quantiser (2.2.1)    */
-    float r_max;                 /* clamp of a cache sample before quantisation           */
+    float r_max;                 /* clamp of a cache sample before quantisation; with
+                                    frac_bits: r_max * 2^F * 64 < 2^32 (a wave's group sum
+                                    of one cell fits a u32), else GI_ERR_INVALID_ARG      */
     float eps_scale;             /* ray origin offset = eps_scale * (1 + max|p_i|)        */
     float t_sky;                 /* travelled distance recorded for a ray that misses     */
     float sky[4];                /* environment radiance returned by a miss (rgb, pad)    */

@@ -110,6 +110,7 @@ def _lib(f64: bool):
     fn("spawn", None, vp, C.POINTER(OrcFrame), R, R, U32P)
     fn("trace", None, vp, C.POINTER(OrcFrame))
     fn("update", None, vp, C.POINTER(OrcFrame))
+    fn("probe_pass", None, vp, C.POINTER(OrcFrame))
     fn("interpolate", None, vp, C.POINTER(OrcFrame), R, R, U32P, R)
     fn("query", None, vp, R, R, C.c_uint32, R)
     fn("dims", None, vp, U32P)
@@ -567,6 +568,12 @@ class OracleFrameState:
 
     def cache_update_only(self):
         _call(self.f64, "cache_update_only", self.h)
+
+    def probe_pass(self, frame):
+        """the per-probe half of update(): gather, backup, blend / filter if configured, SH;
+        cache_update_only() followed by probe_pass() is update()"""
+        f = make_frame(frame)
+        _call(self.f64, "probe_pass", self.h, C.byref(f))
 
     def stats(self):
         out = np.zeros(16, np.uint64)

@@ -2609,9 +2609,20 @@ void ORC(temporal_export)(const state *st, uint32_t *win, uint32_t *hist, uint32
     memcpy(traced, st->traced, sizeof(uint32_t) * st->P);
 }
 
+/* The per-probe half of the update (Sections 2.1.4, 2.1.6, 2.4.2): gather with backup,
+ * the temporal blend and probe filter when configured, SH projection.  ORC(update) is the
+ * cache update (Sections 2.2.1, 2.2.3) followed by this; the split exists so that the two
+ * halves can be timed separately. */
+void ORC(probe_pass)(state *st, const orc_frame *fr);
+
 void ORC(update)(state *st, const orc_frame *fr)
 {
     cache_update(st);
+    ORC(probe_pass)(st, fr);
+}
+
+void ORC(probe_pass)(state *st, const orc_frame *fr)
+{
     gather(st);
     if (st->cfg.temporal) temporal_blend(st);
     if (st->cfg.probe_filter) {

@@ -269,6 +269,12 @@ gi_status check_config(const gi_config* g, std::string& why) {
   if (g->frac_bits < 1 || g->frac_bits > 16) { why = "frac_bits out of [1, 16]"; return GI_ERR_INVALID_ARG; }
   if (g->max_life < 1) { why = "max_life must be >= 1"; return GI_ERR_INVALID_ARG; }
   if (!(g->cell_scale > 0.0f) || !(g->r_max > 0.0f) || !(g->eps_scale >= 0.0f)) { why = "cell_scale, r_max must be > 0"; return GI_ERR_INVALID_ARG; }
+  // a wave adds up to 64 quantised samples of one cell before its atomic: that group sum must
+  // fit a u32, or it would wrap without the carry being seen
+  if (!(g->r_max < 1e30f) || (double)g->r_max * std::ldexp(1.0, (int)g->frac_bits) * 64.0 >= 4294967296.0 - 64.0) {
+    why = "r_max * 2^frac_bits * 64 must stay below 2^32";
+    return GI_ERR_INVALID_ARG;
+  }
   if (g->cache_mode > GI_CACHE_MLP_FP8) { why = "unknown cache_mode"; return GI_ERR_INVALID_ARG; }
   if (g->probe_filter > 1) { why = "probe_filter must be 0 or 1"; return GI_ERR_INVALID_ARG; }
   if (!(g->lod_scale >= 0.0f) || !(g->lod_scale < 1e30f)) { why = "lod_scale must be finite and >= 0"; return GI_ERR_INVALID_ARG; }

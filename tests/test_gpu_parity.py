@@ -621,6 +621,9 @@ def test_invalid_arguments_and_frame_order():
         gi.Context(width=64, height=64, cache_tiles=1, cache_mode=gi.CACHE_MLP_BF16)   # tiles: plain cache only
     with pytest.raises(gi.GIError, match="INVALID"):
         gi.Context(width=64, height=64, restir=1)            # reservoirs need the light grid
+    with pytest.raises(gi.GIError, match="INVALID"):
+        gi.Context(width=64, height=64, frac_bits=16, r_max=1024.0)   # a wave's group sum would wrap
+    gi.Context(width=64, height=64, frac_bits=16, r_max=1000.0).close()
     ctx = gi.Context(width=64, height=64, cache_tiles=1, table_log2=8)
     with pytest.raises(gi.GIError, match="UNSUPPORTED"):
         ctx.table()                                          # per-cell export of the single-level cache
