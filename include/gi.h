@@ -256,6 +256,20 @@ gi_status gi_cache_query(gi_context *ctx, const float *d_pos, const float *d_nrm
 gi_status gi_trace_rays(gi_context *ctx, const float *d_o, const float *d_d, uint32_t n,
                         uint32_t any_hit, uint32_t *d_tri, float *d_t, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gi_trace_rays with the same arguments and
+ * results (bit-identical), whose traversal-stack spill rows live in a fixed 16 MiB device
+ * array, one per GPU, held from library load until the process ends, instead of the
+ * context's spill buffer.  It calls no allocator.  The context must have been created on the
+ * current device (its gi_create looked up the array's address there; else
+ * GI_ERR_INVALID_ARG).  Rays go in chunks of (4 Mi / spill rows) lane ids, rounded down to
+ * 64; a BVH too deep for one chunk of 64 (more than 65,536 spill rows, which gi_build_bvh
+ * never produces) is GI_ERR_UNSUPPORTED.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other threads, other contexts) race
+ * and give undefined results; serialise them. */
+gi_status gi_trace_rays_noalloc(gi_context *ctx, const float *d_o, const float *d_d, uint32_t n,
+                                uint32_t any_hit, uint32_t *d_tri, float *d_t, void *stream);
+
 /* Measurement: re-walk the last traced frame's probe rays and their shadow rays with an
  * instrumented copy of the traversal (no other side effect).  h_out8: [0] probe rays,
  * [1] nodes visited, [2] triangles tested, [3] shadow rays, [4] nodes, [5] triangles.

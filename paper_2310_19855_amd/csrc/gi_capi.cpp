@@ -333,6 +333,11 @@ gi_status gi_create(const gi_config* cfg, gi_context** out) {
     delete c;
     return GI_ERR_UNSUPPORTED;
   }
+  // the device address of gi_trace_rays_noalloc's static scratch array on this device
+  if (gi::scratch_init(dev) != hipSuccess) {
+    delete c;
+    return GI_ERR_HIP;
+  }
   c->W = cfg->width;
   c->H = cfg->height;
   c->TW = (c->W + 7) / 8;
@@ -770,6 +775,22 @@ gi_status gi_trace_rays(gi_context* c, const float* o, const float* d, uint32_t 
   if (!c->has_scene) return fail(c, GI_ERR_STATE, "gi_build_bvh first");
   GI_TRY_HIP(c, gi::launch_trace_rays(c, reinterpret_cast<const float4*>(o), reinterpret_cast<const float4*>(d), n,
                                       any_hit, tri, t, reinterpret_cast<hipStream_t>(stream)));
+  return GI_OK;
+}
+
+gi_status gi_trace_rays_noalloc(gi_context* c, const float* o, const float* d, uint32_t n, uint32_t any_hit,
+                                uint32_t* tri, float* t, void* stream) {
+  if (!c) return GI_ERR_INVALID_ARG;
+  if (n && (!o || !d || !tri || !t)) return fail(c, GI_ERR_INVALID_ARG, "null argument");
+  if (n && (!aligned16(o) || !aligned16(d))) return fail(c, GI_ERR_INVALID_ARG, "not 16-byte aligned");
+  if (!c->has_scene) return fail(c, GI_ERR_STATE, "gi_build_bvh first");
+  if (gi::noalloc_chunk_rays(c->spill_rows) == 0)
+    return fail(c, GI_ERR_UNSUPPORTED, "BVH too deep: its traversal-stack spill rows do not fit the 16 MiB static scratch");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != c->device)
+    return fail(c, GI_ERR_INVALID_ARG, "the context's device is not the current device");
+  GI_TRY_HIP(c, gi::launch_trace_rays_noalloc(c, reinterpret_cast<const float4*>(o), reinterpret_cast<const float4*>(d),
+                                              n, any_hit, tri, t, reinterpret_cast<hipStream_t>(stream)));
   return GI_OK;
 }
 

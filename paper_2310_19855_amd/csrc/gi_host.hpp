@@ -173,6 +173,16 @@ hipError_t launch_trace_rays(gi_context* c, const float4* o, const float4* d, ui
                              uint32_t* tri, float* t, hipStream_t s);
 hipError_t launch_zero_stats(gi_context* c, hipStream_t s);
 hipError_t launch_count_traversal(gi_context* c, unsigned long long* out, hipStream_t s);
+// gi_trace_rays_noalloc: a static device array of kNoAllocScratchWords u32 (16 MiB) per GPU
+// holds the traversal-stack spill rows; scratch_init looks up its address on the current
+// device (once per device, at gi_create); rays are traced in chunks of
+// noalloc_chunk_rays(spill_rows) lane ids (0: the BVH is too deep for the array)
+constexpr size_t kNoAllocScratchWords = (size_t)4 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_init(int device);
+uint32_t noalloc_chunk_rays(uint32_t spill_rows);
+hipError_t launch_trace_rays_noalloc(gi_context* c, const float4* o, const float4* d, uint32_t n, uint32_t any,
+                                     uint32_t* tri, float* t, hipStream_t s);
 
 // learned surrogate (gi_learned.hip)
 struct LearnedShadeOut {       // written by the shading pass in learned mode (else all null)

@@ -2,6 +2,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "gi_device.hpp"
 #include "gi_host.hpp"
 
@@ -2201,6 +2203,56 @@ hipError_t launch_trace_rays(gi_context* c, const float4* o, const float4* d, ui
   for (uint32_t off = 0; off < n; off += cap) {
     const uint32_t m = n - off < cap ? n - off : cap;
     GI_TIMED(c, "trace_rays", s, (k_trace_rays<kLdsStack><<<blocks(m, kTraceBlock), kTraceBlock, 0, s>>>(scene_view(c), o + off, d + off, m, any, tri + off, t + off)));
+  }
+  return hipGetLastError();
+}
+
+// Traversal-stack spill rows of gi_trace_rays_noalloc: one fixed array per GPU (the loaded
+// code object holds it until the process ends), so that the call allocates nothing.  Host
+// code never uses the symbol itself: its device address is looked up once per device, with
+// that device current, and kept in scratch_ptr.
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchWords];
+
+static std::mutex scratch_mu;
+static uint32_t* scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  scratch_ptr[device] = static_cast<uint32_t*>(p);
+  return hipSuccess;
+}
+
+uint32_t noalloc_chunk_rays(uint32_t spill_rows) {
+  if (spill_rows == 0) return 0xFFFFFFFFu;
+  const size_t per = kNoAllocScratchWords / spill_rows;   // lane ids one row can hold
+  return (uint32_t)(per / kTraceBlock * kTraceBlock);
+}
+
+hipError_t launch_trace_rays_noalloc(gi_context* c, const float4* o, const float4* d, uint32_t n, uint32_t any,
+                                     uint32_t* tri, float* t, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint32_t* sp = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (c->device >= 0 && c->device < kMaxDevices) sp = scratch_ptr[c->device];
+  }
+  if (!sp) return hipErrorNotInitialized;
+  const uint32_t cap = noalloc_chunk_rays(c->spill_rows);
+  if (cap == 0) return hipErrorInvalidValue;
+  SceneView v = scene_view(c);
+  v.spill = sp;                  // rows of cap lane ids each, in the static array
+  v.spill_stride = c->spill_rows ? cap : 0u;
+  for (uint32_t off = 0; off < n; off += cap) {
+    const uint32_t m = n - off < cap ? n - off : cap;
+    // no per-kernel timer here: its events may be created on first use
+    k_trace_rays<kLdsStack><<<blocks(m, kTraceBlock), kTraceBlock, 0, s>>>(v, o + off, d + off, m, any, tri + off, t + off);
+    if (cap == 0xFFFFFFFFu) break;
   }
   return hipGetLastError();
 }

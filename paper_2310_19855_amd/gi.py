@@ -105,6 +105,7 @@ def lib():
     fn("gi_interpolate_probes", st, vp, P(Frame), vp, vp, vp, vp, vp)
     fn("gi_cache_query", st, vp, vp, vp, u32, vp, vp)
     fn("gi_trace_rays", st, vp, vp, vp, u32, u32, vp, vp, vp)
+    fn("gi_trace_rays_noalloc", st, vp, vp, vp, u32, u32, vp, vp, vp)
     fn("gi_measure_traversal", st, vp, vp, vp)
     fn("gi_learned_train", st, vp, P(Frame), vp)
     fn("gi_learned_query", st, vp, vp, vp, u32, vp, vp)
@@ -285,6 +286,10 @@ class Context:
     def trace_rays(self, o, d, tri, t, any_hit=False, stream=None):
         self._check(lib().gi_trace_rays(self.h, _ptr(o), _ptr(d), o.shape[0], int(any_hit), _ptr(tri),
                                         _ptr(t), _stream(stream)), "gi_trace_rays")
+
+    def trace_rays_noalloc(self, o, d, tri, t, any_hit=False, stream=None):
+        self._check(lib().gi_trace_rays_noalloc(self.h, _ptr(o), _ptr(d), o.shape[0], int(any_hit), _ptr(tri),
+                                                _ptr(t), _stream(stream)), "gi_trace_rays_noalloc")
 
     def measure_traversal(self, stream=None):
         out = np.zeros(8, np.uint64)
