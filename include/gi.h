@@ -388,6 +388,20 @@ gi_status gi_profile_read(gi_context *ctx, char *h_names, size_t names_cap, uint
 /* Learned-cache parameters as a blob (resume); layout private to the library. */
 gi_status gi_learned_save(gi_context *ctx, void *h_blob, size_t cap, size_t *size_out);
 gi_status gi_learned_load(gi_context *ctx, const void *h_blob, size_t size);
+/* The last gi_learned_train's batch (host-synchronous; learned mode).  The frame's training
+ * rays are the probe rays whose hit found or created a world-cache cell with a finite sample,
+ * in ray order (ray id = probe * R + ray); the batch's rows = mlp_steps * 2^mlp_batch_log2
+ * (at most 2^20) picks, pick k = training ray floor((k + u) * n / rows) with n the number of
+ * training rays and u the frame's uniform number of the seeded stream (frame, id 2^31 - 1,
+ * dimension 9).  h_raw [rows][12] floats in pick order: hit point and distance, face-forwarded
+ * normal with the ray id's bits in the 4th float, training target rgb and 1; h_grouped the
+ * same rows stably sorted by the 15-bit Morton code of the position normalised to the
+ * encoding domain (32 cells per axis): optimiser step k trains on grouped rows k, k + s,
+ * k + 2s, ... with s = rows / 2^mlp_batch_log2.  *rows_out and *n_train_out are always set;
+ * the arrays (either may be NULL) are filled when cap_rows >= rows, else GI_ERR_INVALID_ARG. */
+gi_status gi_learned_batch_export(gi_context *ctx, float *h_raw, float *h_grouped, uint32_t cap_rows,
+                                  uint32_t *rows_out, uint32_t *n_train_out);
+
 /* Loss of the last training step and the fallback decision of the last update:
  * [0] loss, [1] judged relative error, [2] fallback (0/1), [3] steps taken, [4] steps skipped */
 gi_status gi_learned_stats(gi_context *ctx, float *h_out8);

@@ -116,6 +116,7 @@ def _lib(f64: bool):
     fn("dims", None, vp, U32P)
     fn("export_probes", None, vp, U32P, R, R, R, R)
     fn("export_rays", None, vp, I32P, R, U32P, U32P, U64P, R)
+    fn("export_hits", None, vp, R, R)
     fn("export_table", C.c_uint32, vp, U64P, U64P, U32P, R, U32P, U32P, C.c_uint32)
     fn("export_tiles", C.c_uint32, vp, U64P, U64P, U32P, U32P, R, U32P, R, C.c_uint32)
     fn("tile_keys", None, C.POINTER(OrcConfig), R, R, R, R, C.c_uint32, U64P, U32P)
@@ -482,6 +483,15 @@ class OracleFrameState:
         sample = np.zeros((n, 3), self.dt)
         _call(self.f64, "export_rays", self.h, slot, t, tri, cell, key, sample)
         return dict(slot=slot, t=t, tri=tri, cell=cell, key=key, sample=sample)
+
+    def hits(self):
+        """hit point y and face-forwarded normal ny [P*R, 3] of the last trace (rows of rays
+        that missed hold stale values)"""
+        n = self.P * self.R
+        y = np.zeros((n, 3), self.dt)
+        ny = np.zeros((n, 3), self.dt)
+        _call(self.f64, "export_hits", self.h, y, ny)
+        return y, ny
 
     def table(self):
         cap = self.N

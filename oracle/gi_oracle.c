@@ -2912,6 +2912,15 @@ void ORC(export_rays)(const state *st, int32_t *slot, real *t, uint32_t *tri, ui
     if (sample) memcpy(sample, st->r_sample, sizeof(real) * 3 * PR);
 }
 
+/* hit point and face-forwarded normal of every probe ray's hit, [P*R][3] each (meaningful
+ * where the ray's flags hold the hit bit) */
+void ORC(export_hits)(const state *st, real *y, real *ny)
+{
+    size_t PR = (size_t)st->P * st->R;
+    if (y) memcpy(y, st->r_y, sizeof(real) * 3 * PR);
+    if (ny) memcpy(ny, st->r_ny, sizeof(real) * 3 * PR);
+}
+
 /* live cells in slot order: bucket*2^32|fp, key, acc[4], L[3], nhist, life; returns count */
 uint32_t ORC(export_table)(const state *st, uint64_t *id, uint64_t *key, uint32_t *acc, real *L,
                            uint32_t *nhist, uint32_t *life, uint32_t cap)

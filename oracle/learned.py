@@ -210,6 +210,68 @@ class Adam:
         return True
 
 
+# ---- the frame's training batch (not in the paper; the surrogate's own data path) --------
+#
+#   * training rays: the frame's probe rays whose hit found or created a world-cache cell
+#     (slot >= 0) and whose cache sample is finite, in ray order (ray id = probe * R + ray);
+#     their samples (before quantisation) are the targets.
+#   * rows = steps * B picks (at most 2^20, a whole number of B), pick k = training ray
+#     floor((k + u) n / rows), n training rays, u the frame's uniform number.
+#   * grouping: the rows stably sorted by the 15-bit Morton code of the normalised position
+#     (32 cells per axis); optimiser step k trains on grouped rows k, k + s, k + 2s, ...,
+#     s = rows / B.
+
+def training_rays(slot, flags, sample):
+    """ids (ascending) of the rays whose hit (flag bit 8) has a cell (slot >= 0) and a finite
+    sample"""
+    hit = (np.asarray(flags) & 0x100) != 0
+    ok = hit & (np.asarray(slot) >= 0) & np.isfinite(np.asarray(sample, np.float64)).all(1)
+    return np.nonzero(ok)[0]
+
+
+def frame_u(seed, frame):
+    """the selection's uniform number of a frame: the top 24 bits of the nested PCG hash
+    rng(seed, frame, 2^31 - 1, 9), times 2^-24 (float32)"""
+    h = int(rng_u32(seed, frame, 0x7FFFFFFF, 9))
+    return np.float32(h >> 8) * np.float32(5.9604644775390625e-08)
+
+
+def batch_rows(B, steps):
+    """rows of a frame's batch: one sub-batch of B per step, at most 2^20 rows"""
+    return B * max(1, min(steps, (1 << 20) // B))
+
+
+def select_picks(n, rows, u):
+    """indices into the training-ray list: floor((k + u) n / rows) for k < rows, in float64 (each
+    product is rounded once, as written), at most n - 1"""
+    k = np.arange(rows, dtype=np.float64)
+    r = np.floor((k + np.float64(u)) * np.float64(n) / np.float64(rows)).astype(np.int64)
+    return np.minimum(r, n - 1)
+
+
+def morton15(x32):
+    """15-bit Morton code of positions in [0, 1]^3 (float32): cell q_a = min(trunc(32 x_a), 31)
+    per axis; bit 3i + a of the code is bit i of q_a"""
+    x32 = np.asarray(x32, np.float32)
+    q = np.minimum((x32 * np.float32(32.0)).astype(np.int64), 31)
+    code = np.zeros(len(x32), np.int64)
+    for i in range(5):
+        for a in range(3):
+            code |= ((q[:, a] >> i) & 1) << (3 * i + a)
+    return code
+
+
+def group_order(x32):
+    """row order of the grouped batch: by Morton code, ties in pick order"""
+    return np.argsort(morton15(x32), kind="stable")
+
+
+def step_rows(rows, B, k):
+    """grouped rows of optimiser step k"""
+    sub = rows // B
+    return np.arange(k % sub, rows, sub)[:B]
+
+
 # ---- FP8 (OCP e4m3: 1 sign, 4 exponent bits with bias 7, 3 mantissa bits, max 448, no
 #      infinities, S.1111.111 = NaN) ----
 

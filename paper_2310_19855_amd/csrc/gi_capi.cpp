@@ -1186,6 +1186,19 @@ gi_status gi_learned_load(gi_context* c, const void* blob, size_t size) {
   return GI_OK;
 }
 
+gi_status gi_learned_batch_export(gi_context* c, float* h_raw, float* h_grouped, uint32_t cap_rows, uint32_t* rows_out,
+                                  uint32_t* n_train_out) {
+  if (!c || !rows_out || !n_train_out) return GI_ERR_INVALID_ARG;
+  if (!c->learned) return fail(c, GI_ERR_STATE, "learned cache disabled");
+  GI_TRY_HIP(c, hipDeviceSynchronize());
+  uint32_t rows = 0, n = 0;
+  GI_TRY_HIP(c, gi::learned_batch_export(c, h_raw, h_grouped, cap_rows, rows, n));
+  *rows_out = rows;
+  *n_train_out = n;
+  if ((h_raw || h_grouped) && cap_rows < rows) return fail(c, GI_ERR_INVALID_ARG, "cap_rows below the batch rows");
+  return GI_OK;
+}
+
 gi_status gi_learned_stats(gi_context* c, float* out8) {
   if (!c || !out8) return GI_ERR_INVALID_ARG;
   if (!c->learned) return fail(c, GI_ERR_STATE, "learned cache disabled");

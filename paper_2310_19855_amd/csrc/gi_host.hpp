@@ -188,9 +188,9 @@ hipError_t launch_trace_rays_noalloc(gi_context* c, const float4* o, const float
 struct LearnedShadeOut {       // written by the shading pass in learned mode (else all null)
   float4* hitpos = nullptr;    // [P*R] hit point
   float4* hitnrm = nullptr;    // [P*R] face-forwarded normal
-  float4* trec = nullptr;      // training records: target rgb, w = ray id bits
-  uint32_t* trec_count = nullptr;
-  uint32_t trec_cap = 0;
+  float4* trec = nullptr;      // [P*R] training target of the ray's hit (rgb, w = 1)
+  uint8_t* tflag = nullptr;    // [P*R, padded] 1 where trec holds this frame's sample
+  uint32_t tflag_words = 0;    // u32 words of tflag cleared per frame
 };
 struct LearnedGatherIn {       // read by the probe gather in learned mode (else all null)
   const float4* lmlp = nullptr;   // [P*R] surrogate radiance at each hit
@@ -212,6 +212,10 @@ size_t learned_blob_size(gi_context* c);
 hipError_t learned_save(gi_context* c, void* blob);
 hipError_t learned_load(gi_context* c, const void* blob);
 void learned_stats(gi_context* c, float* out8);
+// the frame's training batch as selected and as grouped (rows x 3 float4 each), the number of
+// rows and of the frame's training rays; copies only when cap_rows >= rows
+hipError_t learned_batch_export(gi_context* c, float* h_raw, float* h_grouped, uint32_t cap_rows, uint32_t& rows,
+                                uint32_t& n_train);
 hipError_t e4m3_encode_array(const float* in, uint8_t* out, uint32_t n, hipStream_t st);
 
 }  // namespace gi

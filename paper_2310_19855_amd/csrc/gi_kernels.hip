@@ -1113,17 +1113,11 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float s2 = alb.z * (E2 * 0.31830988618379067f + Lb2);
   const bool finite = isfinite(s0) && isfinite(s1) && isfinite(s2);
   stat_add(stats, GI_STAT_NONFINITE, !finite);
-  if (lo.trec) {
-    // learned mode: the sample (before quantisation) becomes a training record
-    const uint64_t m = __ballot(finite);
-    if (m) {
-      const uint32_t leader = (uint32_t)__ffsll((long long)__ballot(1)) - 1u;
-      uint32_t base = 0;
-      if ((threadIdx.x & 63u) == leader) base = atomicAdd(lo.trec_count, (uint32_t)__popcll(m));
-      base = __shfl(base, (int)leader, 64);
-      const uint32_t at = base + (uint32_t)__popcll(m & lanes_below());
-      if (finite && at < lo.trec_cap) lo.trec[at] = make_float4(s0, s1, s2, __uint_as_float(gid));
-    }
+  if (lo.trec && finite) {
+    // learned mode: the sample (before quantisation) is the ray's training record; the flag
+    // puts the ray in the frame's training list, which is compacted in ray order
+    lo.trec[gid] = make_float4(s0, s1, s2, 1.0f);
+    lo.tflag[gid] = 1u;
   }
   if (!finite) return;
   const float scale = (float)(1u << c.frac_bits);
@@ -2123,7 +2117,7 @@ hipError_t launch_trace(gi_context* c, hipStream_t s) {
   const ProbeRayArgs a = probe_args(c);
   const CacheArgs ca = cache_args(c);
   const LearnedShadeOut lso = learned_shade_out(c);
-  if (lso.trec_count) k_zero_u32<<<1, 64, 0, s>>>(lso.trec_count, 1);
+  if (lso.tflag) k_zero_u32<<<blocks(lso.tflag_words, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(lso.tflag), lso.tflag_words);
   GI_TIMED(c, "trace_probes", s, (k_trace_probes<kLdsStack><<<blocks(n, kTraceBlock), kTraceBlock, 0, s>>>(sv, st, a, c->d_rec, c->d_rkey, hit_list(c), c->d_stats)));
   const RestirArgs ra = restir_args(c);
   if (ra.on) {

@@ -53,13 +53,27 @@ struct LearnedState {
   __bf16* wb = nullptr;          // W1 [64][64] | W1t [64][64] | W2 | W2t | W3 [16][64] | W3t [64][32]
   uint8_t* w8 = nullptr;         // e4m3 W1 | W2 | W3 (row-major [out][in])
   float* scales = nullptr;       // [0..2] weight scales, [3..5] activation amax (X, H1, H2), [6..8] act scales
-  float4* hitpos = nullptr;      // [P*R] hit point (learned mode)
+  float4* hitpos = nullptr;      // [P*R] hit point (learned mode), w = hit distance
   float4* hitnrm = nullptr;      // [P*R] face-forwarded normal
-  float4* trec = nullptr;        // [P*R] training record: target rgb, w = ray id bits
-  uint32_t* trec_count = nullptr;
-  float4* batch_raw = nullptr;   // [B][3]: pos, nrm, target as selected
-  float4* batch = nullptr;       // the same rows grouped by spatial (Morton) bucket
-  uint32_t* sort_cnt = nullptr;  // [kSortBuckets] bucket counters / offsets
+  float4* trec = nullptr;        // [P*R] training target of the ray's hit (rgb, w = 1)
+  uint8_t* tflag = nullptr;      // [tflag_blocks * kTile] 1 where trec holds this frame's sample
+  uint32_t tflag_blocks = 0;
+  uint32_t* clist = nullptr;     // [P*R] the frame's training rays in ray order
+  uint32_t* ccount = nullptr;    // [tflag_blocks + 1] per-block counts -> offsets, [last] = total
+  float4* batch_raw = nullptr;   // [rows][3]: pos, nrm (w = ray id bits), target as selected
+  float4* batch = nullptr;       // the same rows grouped by spatial (Morton) bucket, stable
+  // radix sort buffers: batch keys and row indices (rows), gradient pairs (B * L * 8)
+  uint32_t* bkeys[2] = {nullptr, nullptr};
+  uint32_t* bvals[2] = {nullptr, nullptr};
+  uint32_t* pkeys[2] = {nullptr, nullptr};
+  float2* pvals[2] = {nullptr, nullptr};
+  uint32_t* rs_hist = nullptr;   // [256][blocks] digit counts -> offsets
+  uint32_t* tail_key = nullptr;  // per reduction tile: key, sum and origin of its last segment
+  float2* tail_sum = nullptr;
+  uint32_t* tail_in = nullptr;
+  size_t n_pairs = 0;
+  uint32_t key_bits = 0;         // bits of a gradient pair key (level * T + entry)
+  float* lpart = nullptr;        // [train_waves] loss partials
   float2* judge_part = nullptr;  // per-wave (error, norm) partials of the judge
   uint32_t B = 0;
   uint32_t sub = 1;              // sub-batches held by the frame's batch (rows = sub * B)
@@ -215,48 +229,183 @@ __global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* w
   mlp_copies(mlp, wb, w8, scales);
 }
 
-// ---- training batch selection: k-th sample = record floor((k + u) n / B) ----------------
+// ---- the frame's training rays, compacted in ray order ---------------------------------
+// A ray is a training sample when its probe ray hit, its hit found or created a world-cache
+// cell and its sample is finite (flag set by the shading pass).  Blocks of kTile flags:
+// count, one-block exclusive scan of the counts, then each block writes its rays' ids at
+// their ranks.  The list is a function of the flags alone.
+constexpr uint32_t kTile = 4096;      // items per block of 256 threads (16 each)
 
-__global__ void k_select_batch(const float4* trec, const uint32_t* count, uint32_t cap, const float4* hitpos,
-                               const float4* hitnrm, float u, uint32_t B, float4* batch, float* acc) {
+__device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t* lds, uint32_t& total) {
+  // exclusive prefix over the 256 threads of a block, in thread order
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)x, d, 64);
+    if (lane >= (uint32_t)d) x += o;
+  }
+  if (lane == 63u) lds[w] = x;
+  __syncthreads();
+  uint32_t base = 0;
+  for (uint32_t k = 0; k < w; ++k) base += lds[k];
+  total = lds[0] + lds[1] + lds[2] + lds[3];
+  __syncthreads();
+  return base + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_tflag_count(const uint8_t* flag, uint32_t* cnt) {
+  __shared__ uint32_t lds[4];
+  const uint4 f = reinterpret_cast<const uint4*>(flag + (size_t)blockIdx.x * kTile)[threadIdx.x];
+  // every byte is 0 or 1: the popcount of a word is its number of set flags
+  const uint32_t c = __popc(f.x) + __popc(f.y) + __popc(f.z) + __popc(f.w);
+  uint32_t total;
+  block_excl_scan256(c, lds, total);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+// exclusive scan of n counts in place; cnt[n] = total (one block of 1024 threads)
+__global__ __launch_bounds__(1024) void k_scan_counts(uint32_t* cnt, uint32_t n) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (n + 1023u) / 1024u;
+  const uint32_t b0 = t * per, b1 = min(b0 + per, n);
+  uint32_t sum = 0u;
+  for (uint32_t i = b0; i < b1; ++i) sum += cnt[i];
+  part[t] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024u; d <<= 1) {
+    const uint32_t o = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += o;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+  for (uint32_t i = b0; i < b1; ++i) {
+    const uint32_t v = cnt[i];
+    cnt[i] = run;
+    run += v;
+  }
+  if (t == 1023u) cnt[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_tflag_compact(const uint8_t* flag, const uint32_t* off, uint32_t* list) {
+  __shared__ uint32_t lds[4];
+  const uint32_t base_id = blockIdx.x * kTile + 16u * threadIdx.x;
+  const uint4 f = reinterpret_cast<const uint4*>(flag + (size_t)blockIdx.x * kTile)[threadIdx.x];
+  const uint32_t c = __popc(f.x) + __popc(f.y) + __popc(f.z) + __popc(f.w);
+  uint32_t total;
+  uint32_t at = off[blockIdx.x] + block_excl_scan256(c, lds, total);
+  const uint32_t w[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if ((w[q] >> (8 * b)) & 1u) list[at++] = base_id + 4u * q + b;
+}
+
+// ---- training batch selection: k-th of `rows` samples = list entry floor((k + u) n / rows) --
+
+__global__ void k_select_batch(const uint32_t* list, const uint32_t* count, const float4* trec, const float4* hitpos,
+                               const float4* hitnrm, float u, uint32_t rows, float4* batch, float* acc) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t n = *count;
-  if (n > cap) n = cap;
+  const uint32_t n = *count;
   if (k == 0) acc[7] = (float)n;
-  if (k >= B) return;
+  if (k >= rows) return;
   if (n == 0) {
     batch[3 * k] = batch[3 * k + 1] = batch[3 * k + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
     return;
   }
-  uint32_t r = (uint32_t)(((double)k + (double)u) * (double)n / (double)B);
+  uint32_t r = (uint32_t)(((double)k + (double)u) * (double)n / (double)rows);
   if (r >= n) r = n - 1u;
-  const float4 t = trec[r];
-  const uint32_t gid = __float_as_uint(t.w);
+  const uint32_t gid = list[r];
+  const float4 nv = hitnrm[gid];
   batch[3 * k] = hitpos[gid];
-  batch[3 * k + 1] = hitnrm[gid];
-  batch[3 * k + 2] = make_float4(t.x, t.y, t.z, 1.0f);
+  batch[3 * k + 1] = make_float4(nv.x, nv.y, nv.z, __uint_as_float(gid));
+  batch[3 * k + 2] = trec[gid];
 }
 
-// ---- spatial order of a batch: rows grouped by a 15-bit Morton code of the normalised
-// position (32 cells per axis; counting sort: histogram, scan, scatter), so that neighbouring
-// lanes of a training wave share grid corners and their gradient atomics can be merged.  The
-// order inside a bucket is that of the scatter's atomics. -----------------------------------
+// ---- stable LSD radix sort of (u32 key, payload) pairs, 8-bit digits ---------------------
+// Per pass: per-block digit counts (blocks of kTile items), one-block scan in digit-major
+// order, and a scatter in which every item goes to its digit's offset plus the number of
+// items of its block with the same digit and a lower index (wave ballots, then waves and
+// rounds in order), so equal keys keep their input order.
 constexpr uint32_t kSortBuckets = 1u << 15;
 
+__global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* key, uint32_t n, uint32_t shift, uint32_t nb,
+                                                 uint32_t* hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t b0 = blockIdx.x * kTile;
+  for (uint32_t j = 0; j < kTile / 256u; ++j) {
+    const uint32_t i = b0 + j * 256u + threadIdx.x;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* kin, const V* vin, uint32_t* kout, V* vout,
+                                                    uint32_t n, uint32_t shift, uint32_t nb, const uint32_t* off) {
+  __shared__ uint32_t run[256];        // next rank of each digit in this block
+  __shared__ uint32_t wcnt[4][256];    // this round's count of each digit per wave
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  run[t] = off[t * nb + blockIdx.x];
+  const uint32_t b0 = blockIdx.x * kTile;
+  for (uint32_t j = 0; j < kTile / 256u; ++j) {
+    wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0u;
+    __syncthreads();
+    const uint32_t i = b0 + j * 256u + t;
+    const bool on = i < n;
+    const uint32_t k = on ? kin[i] : 0u;
+    const uint32_t d = (k >> shift) & 255u;
+    uint64_t same = __ballot(on);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1u);
+      same &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    if (on && rank == 0u) wcnt[w][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    uint32_t before = run[d];
+    for (uint32_t q = 0; q < w; ++q) before += wcnt[q][d];
+    if (on) {
+      kout[before + rank] = k;
+      vout[before + rank] = vin[i];
+    }
+    __syncthreads();
+    run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+  }
+}
+
+// sorts (keys[0], vals[0]) by the low `bits` bits of the keys, stable; returns the index of
+// the buffer pair holding the result
+template <typename V>
+static hipError_t radix_sort(uint32_t* keys[2], V* vals[2], uint32_t n, uint32_t bits, uint32_t* hist,
+                             hipStream_t st, int& which) {
+  which = 0;
+  if (n == 0) return hipSuccess;
+  const uint32_t nb = (n + kTile - 1u) / kTile;
+  for (uint32_t shift = 0; shift < bits; shift += 8u) {
+    k_rs_hist<<<nb, 256, 0, st>>>(keys[which], n, shift, nb, hist);
+    k_scan_counts<<<1, 1024, 0, st>>>(hist, 256u * nb);
+    k_rs_scatter<V><<<nb, 256, 0, st>>>(keys[which], vals[which], keys[which ^ 1], vals[which ^ 1], n, shift, nb, hist);
+    which ^= 1;
+  }
+  return hipGetLastError();
+}
+
+// ---- spatial grouping of the frame's batch: rows stably sorted by a 15-bit Morton code of
+// the normalised position (32 cells per axis), so that the 32 samples of a training group
+// are neighbours and share coarse grid entries ------------------------------------------------
 __device__ inline uint32_t spread5(uint32_t v) {
   v &= 0x1Fu;
   v = (v | (v << 8)) & 0x0000F00Fu;
   v = (v | (v << 4)) & 0x000C30C3u;
   v = (v | (v << 2)) & 0x00249249u;
-  return v;
-}
-
-__device__ inline uint32_t spread9(uint32_t v) {
-  v &= 0x1FFu;
-  v = (v | (v << 16)) & 0x030000FFu;
-  v = (v | (v << 8)) & 0x0300F00Fu;
-  v = (v | (v << 4)) & 0x030C30C3u;
-  v = (v | (v << 2)) & 0x09249249u;
   return v;
 }
 
@@ -269,48 +418,20 @@ __device__ inline uint32_t sort_bucket(const LearnedParams& lp, const float4& p)
   return spread5(q0) | (spread5(q1) << 1) | (spread5(q2) << 2);
 }
 
-__global__ void k_sort_count(LearnedParams lp, const float4* in, uint32_t B, uint32_t* cnt) {
+__global__ void k_batch_keys(LearnedParams lp, const float4* in, uint32_t rows, uint32_t* key, uint32_t* idx) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B) return;
-  atomicAdd(&cnt[sort_bucket(lp, in[3 * (size_t)i])], 1u);
+  if (i >= rows) return;
+  key[i] = sort_bucket(lp, in[3 * (size_t)i]);
+  idx[i] = i;
 }
 
-// exclusive prefix sum of the kSortBuckets counters in place (one block of 1024 threads)
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* cnt) {
-  __shared__ uint32_t part[1024];
-  constexpr uint32_t per = kSortBuckets / 1024u;
-  const uint32_t t = threadIdx.x;
-  uint32_t v[per];
-  uint32_t sum = 0u;
-#pragma unroll
-  for (uint32_t j = 0; j < per; ++j) {
-    v[j] = cnt[t * per + j];
-    sum += v[j];
-  }
-  part[t] = sum;
-  __syncthreads();
-  for (uint32_t d = 1; d < 1024u; d <<= 1) {
-    const uint32_t o = t >= d ? part[t - d] : 0u;
-    __syncthreads();
-    part[t] += o;
-    __syncthreads();
-  }
-  uint32_t run = part[t] - sum;
-#pragma unroll
-  for (uint32_t j = 0; j < per; ++j) {
-    cnt[t * per + j] = run;
-    run += v[j];
-  }
-}
-
-__global__ void k_sort_scatter(LearnedParams lp, const float4* in, float4* out, uint32_t B, uint32_t* off) {
+__global__ void k_batch_gather(const float4* in, const uint32_t* idx, uint32_t rows, float4* out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B) return;
-  const float4 p = in[3 * (size_t)i];
-  const uint32_t d = atomicAdd(&off[sort_bucket(lp, p)], 1u);
-  out[3 * (size_t)d] = p;
-  out[3 * (size_t)d + 1] = in[3 * (size_t)i + 1];
-  out[3 * (size_t)d + 2] = in[3 * (size_t)i + 2];
+  if (i >= rows) return;
+  const size_t r = idx[i];
+  out[3 * (size_t)i] = in[3 * r];
+  out[3 * (size_t)i + 1] = in[3 * r + 1];
+  out[3 * (size_t)i + 2] = in[3 * r + 2];
 }
 
 __global__ void k_zero_f32(float* p, uint64_t n);
@@ -320,11 +441,12 @@ static hipError_t sort_batch(gi_context* c, hipStream_t st, uint32_t rows) {
   LearnedState* s = c->learned;
   hipEvent_t ev;
   timer_begin(c, "learned_sort", st, &ev);
-  k_zero_f32<<<nblk(kSortBuckets, 256), 256, 0, st>>>(reinterpret_cast<float*>(s->sort_cnt), kSortBuckets);
-  k_sort_count<<<nblk(rows, 256), 256, 0, st>>>(s->lp, s->batch_raw, rows, s->sort_cnt);
-  k_sort_scan<<<1, 1024, 0, st>>>(s->sort_cnt);
-  k_sort_scatter<<<nblk(rows, 256), 256, 0, st>>>(s->lp, s->batch_raw, s->batch, rows, s->sort_cnt);
+  k_batch_keys<<<nblk(rows, 256), 256, 0, st>>>(s->lp, s->batch_raw, rows, s->bkeys[0], s->bvals[0]);
+  int which = 0;
+  hipError_t e = radix_sort<uint32_t>(s->bkeys, s->bvals, rows, 15u, s->rs_hist, st, which);
+  k_batch_gather<<<nblk(rows, 256), 256, 0, st>>>(s->batch_raw, s->bvals[which], rows, s->batch);
   timer_end(c, "learned_sort", st, ev);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -357,11 +479,13 @@ __device__ inline void atomic_max_abs(float* p, float v) {
   atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
 }
 
-// sample i of the step is row off + stride * i of the batch array
+// sample i of the step is row off + stride * i of the batch array.  The encoding gradient is
+// written as (entry key, contribution) pairs at fixed positions (group, level, corner,
+// sample), to be sorted and summed per entry: no float atomics, so the step is deterministic.
 __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
-                                              uint32_t stride, const __half* grid_h, float* grid_g,
-                                              const __bf16* wb, float loss_scale, float* part, float* acc,
-                                              float* amax) {
+                                              uint32_t stride, const __half* grid_h, uint32_t* pkey, float2* pval,
+                                              uint32_t log2T, const __bf16* wb, float loss_scale, float* part,
+                                              float* lpart, float* acc, float* amax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TrainSmem& S = *reinterpret_cast<TrainSmem*>(smem_raw);
   const int lane = threadIdx.x;
@@ -386,27 +510,7 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
   float ax = 0.f, ah1 = 0.f, ah2 = 0.f;
   const int s = lane & 31, half_ = lane >> 5;
   for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
-    // -- the group's 32 samples in Morton order (27-bit code, bitonic network over the lanes
-    // of each half), so that equal grid corners sit in neighbouring lanes
-    uint32_t row;
-    {
-      const float4 p0 = batch[3 * (off + stride * (32 * g + s))];
-      float y0, y1, y2;
-      norm_pos(lp, p0.x, p0.y, p0.z, y0, y1, y2);
-      const uint32_t code = spread9(min((uint32_t)(y0 * 512.0f), 511u)) |
-                            (spread9(min((uint32_t)(y1 * 512.0f), 511u)) << 1) |
-                            (spread9(min((uint32_t)(y2 * 512.0f), 511u)) << 2);
-      uint32_t key = (code << 5) | (uint32_t)s;
-#pragma unroll
-      for (int k = 2; k <= 32; k <<= 1)
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-          const uint32_t other = (uint32_t)__shfl_xor((int)key, j, 64);
-          const bool keep_min = ((s & j) == 0) == ((s & k) == 0);
-          key = keep_min ? min(key, other) : max(key, other);
-        }
-      row = off + stride * (32 * g + (key & 31u));
-    }
+    const uint32_t row = off + stride * (32 * g + s);
     // -- encoding: lane = (sample s, levels 8*half_ .. 8*half_+7)
     const float4 pos = batch[3 * row];
     const float4 nrm = batch[3 * row + 1];
@@ -565,37 +669,19 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
         }
       }
     __syncthreads();
-    // -- encoding backward: scatter w * dX into the level tables.  Lanes hold spatially
-    // sorted samples, so runs of neighbouring lanes often name the same table entry: each run
-    // is summed across lanes (segmented suffix sum) and only its first lane issues the atomics.
+    // -- encoding backward: pair (level * T + entry, w * dX) of every sample, level and corner,
+    // at position ((g * L + l) * 8 + c) * 32 + s (lanes of a half write 32 consecutive pairs)
     for (int k = 0; k < 8; ++k) {
       const int l = 8 * half_ + k;
-      const bool on = l < (int)lp.L;
+      if (l >= (int)lp.L) break;
       Corners cn;
-      if (on) level_corners(lp, l, x0, x1, x2, cn);
-      const float d0 = on ? S.dX[s * 33 + 2 * l] : 0.0f, d1 = on ? S.dX[s * 33 + 2 * l + 1] : 0.0f;
-      float* gl = grid_g + (size_t)(on ? l : 0) * lp.T * 2u;
+      level_corners(lp, l, x0, x1, x2, cn);
+      const float d0 = S.dX[s * 33 + 2 * l], d1 = S.dX[s * 33 + 2 * l + 1];
+      const size_t base = ((size_t)g * lp.L + (uint32_t)l) * 8u * 32u + (uint32_t)s;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const uint32_t a = on ? (uint32_t)l * lp.T + cn.idx[c] : 0xFFFFFFFFu;
-        float v0 = on ? cn.w[c] * d0 : 0.0f, v1 = on ? cn.w[c] * d1 : 0.0f;
-        const uint32_t prev = (uint32_t)__shfl_up((int)a, 1, 64);
-        const bool head = lane == 0 || prev != a;
-        const uint64_t heads = __ballot(head);
-        const uint32_t rid = (uint32_t)__popcll(heads & (~0ull >> (63 - lane)));
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const float o0 = __shfl_down(v0, d, 64), o1 = __shfl_down(v1, d, 64);
-          const uint32_t orid = (uint32_t)__shfl_down((int)rid, d, 64);
-          if (lane + d < 64 && orid == rid) {
-            v0 = v0 + o0;
-            v1 = v1 + o1;
-          }
-        }
-        if (on && head) {
-          if (v0 != 0.0f) atomicAdd(&gl[2u * cn.idx[c]], v0);
-          if (v1 != 0.0f) atomicAdd(&gl[2u * cn.idx[c] + 1u], v1);
-        }
+        pkey[base + 32u * c] = ((uint32_t)l << log2T) | cn.idx[c];
+        pval[base + 32u * c] = make_float2(cn.w[c] * d0, cn.w[c] * d1);
       }
     }
     __syncthreads();
@@ -625,7 +711,7 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
   }
   const bool any_bad = __ballot(bad) != 0;
   if (lane == 0) {
-    atomicAdd(&acc[0], loss * inv3b);
+    lpart[blockIdx.x] = loss * inv3b;
     if (any_bad) acc[1] = 1.0f;
     atomic_max_abs(&amax[0], ax);
     atomic_max_abs(&amax[1], ah1);
@@ -635,8 +721,15 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
 
 // deterministic sum of the per-wave partials (fixed order) -> gradient; flags non-finite
 // (64 parameters per block; 16 slices of the waves per parameter, summed in a fixed order)
-__global__ __launch_bounds__(1024) void k_reduce_mlp(const float* part, uint32_t waves, float* g, float* acc) {
+__global__ __launch_bounds__(1024) void k_reduce_mlp(const float* part, const float* lpart, uint32_t waves, float* g,
+                                                     float* acc) {
   __shared__ float red[16][64];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the step's loss: per-wave partials summed in wave order
+    float l = 0.0f;
+    for (uint32_t w = 0; w < waves; ++w) l += lpart[w];
+    acc[0] = l;
+  }
   const int l = threadIdx.x & 63, slice = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + l;
   float s = 0.0f;
@@ -669,43 +762,112 @@ __device__ inline void adam_lazy(float graw, float& p, float& m, float& v, const
   p = p - a.lr * mh / (sqrtf(vh) + a.eps);
 }
 
-// four parameters per thread: a group whose four gradients are zero is left untouched
-__global__ void k_adam_grid(float* p, __half* ph, float* g, float* m, float* v, uint64_t n, AdamArgs a,
-                            const float* acc) {
-  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t i0 = 4 * q;
-  if (i0 >= n) return;
-  if (i0 + 4 <= n) {
-    const float4 g4 = reinterpret_cast<const float4*>(g)[q];
-    if (g4.x == 0.0f && g4.y == 0.0f && g4.z == 0.0f && g4.w == 0.0f) return;
-    reinterpret_cast<float4*>(g)[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (acc[1] != 0.0f) return;
-    float4 p4 = reinterpret_cast<const float4*>(p)[q];
-    float4 m4 = reinterpret_cast<const float4*>(m)[q];
-    float4 v4 = reinterpret_cast<const float4*>(v)[q];
-    adam_lazy(g4.x, p4.x, m4.x, v4.x, a);
-    adam_lazy(g4.y, p4.y, m4.y, v4.y, a);
-    adam_lazy(g4.z, p4.z, m4.z, v4.z, a);
-    adam_lazy(g4.w, p4.w, m4.w, v4.w, a);
-    reinterpret_cast<float4*>(p)[q] = p4;
-    reinterpret_cast<float4*>(m)[q] = m4;
-    reinterpret_cast<float4*>(v)[q] = v4;
-    __half2* h2 = reinterpret_cast<__half2*>(ph) + 2 * q;
-    h2[0] = __halves2half2(__float2half(p4.x), __float2half(p4.y));
-    h2[1] = __halves2half2(__float2half(p4.z), __float2half(p4.w));
-    return;
+// ---- per-entry sums of the sorted gradient pairs, then the grid step --------------------
+// Tiles of kTile sorted pairs, thread t of a tile holding pairs 16t..16t+15.  Each thread sums
+// its pairs in order, restarting where the key changes; a segmented scan over the threads
+// (fixed association) extends every pair's sum back to the tile start or to its entry's first
+// pair.  An entry whose pairs began in an earlier tile adds the tail sums of the earlier
+// tiles, nearest first, which the first pass (MODE 0) records.  Every order is fixed, so the
+// sums, and the step, are deterministic.  MODE 1: lazy Adam on the entry's two parameters
+// (skipped when the step's gradients are non-finite); MODE 2: the dense gradient (a
+// gradient-only step).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2* val, uint32_t n, uint32_t* tail_key,
+                                              float2* tail_sum, uint32_t* tail_in, float* p, __half* ph, float* m,
+                                              float* v, float* gdense, AdamArgs a, const float* acc) {
+  __shared__ uint32_t sk[kTile + 1];
+  __shared__ float2 sv[kTile];
+  __shared__ float2 cs[2][256];
+  __shared__ uint32_t cf[2][256];
+  const uint32_t t = threadIdx.x;
+  const uint32_t b0 = blockIdx.x * kTile;
+  for (uint32_t j = 0; j < kTile / 256u; ++j) {
+    const uint32_t i = b0 + j * 256u + t;
+    sk[j * 256u + t] = i < n ? key[i] : 0xFFFFFFFFu;
+    sv[j * 256u + t] = i < n ? val[i] : make_float2(0.0f, 0.0f);
   }
-  for (uint64_t i = i0; i < n; ++i) {
-    const float graw = g[i];
-    if (graw == 0.0f) continue;
-    g[i] = 0.0f;
-    if (acc[1] != 0.0f) continue;
-    float pi = p[i], mi = m[i], vi = v[i];
-    adam_lazy(graw, pi, mi, vi, a);
-    p[i] = pi;
-    m[i] = mi;
-    v[i] = vi;
-    ph[i] = __float2half(pi);
+  if (t == 0) sk[kTile] = b0 + kTile < n ? key[b0 + kTile] : 0xFFFFFFFFu;   // first key of the next tile
+  const uint32_t kbefore = b0 > 0 ? key[b0 - 1] : 0xFFFFFFFFu;              // keys are < 2^28: never equal
+  __syncthreads();
+  float2 loc[16];
+  uint32_t headbits = 0;     // bit j: a key change at or before pair j inside this thread's chunk
+                             // (loc[j] then sums from the last of them, with no carry)
+  float sx = 0.0f, sy = 0.0f;
+  uint32_t kp = t == 0 ? kbefore : sk[16u * t - 1u];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t k = sk[16u * t + j];
+    if (k != kp) {
+      sx = 0.0f;
+      sy = 0.0f;
+      headbits |= 0xFFFFu << j;
+    }
+    const float2 w = sv[16u * t + j];
+    sx = sx + w.x;
+    sy = sy + w.y;
+    loc[j] = make_float2(sx, sy);
+    kp = k;
+  }
+  // inclusive segmented scan over threads of (holds a key change, sum after its last change)
+  int cur = 0;
+  cs[0][t] = make_float2(sx, sy);
+  cf[0][t] = headbits ? 1u : 0u;
+  __syncthreads();
+  for (uint32_t d = 1; d < 256u; d <<= 1) {
+    float2 sv2 = cs[cur][t];
+    uint32_t f = cf[cur][t];
+    if (t >= d && !f) {
+      const float2 o = cs[cur][t - d];
+      sv2 = make_float2(o.x + sv2.x, o.y + sv2.y);
+      f = cf[cur][t - d];
+    }
+    cs[cur ^ 1][t] = sv2;
+    cf[cur ^ 1][t] = f;
+    cur ^= 1;
+    __syncthreads();
+  }
+  const float2 carry = t > 0 ? cs[cur][t - 1] : make_float2(0.0f, 0.0f);
+  const bool carry_in_tile = t > 0 && cf[cur][t - 1] != 0u;
+  const bool skip = MODE == 1 && acc[1] != 0.0f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t idx = 16u * t + j;
+    const bool own = (headbits >> j) & 1u;
+    const float2 sum = own ? loc[j] : make_float2(carry.x + loc[j].x, carry.y + loc[j].y);
+    const bool inside = own || carry_in_tile;
+    if (MODE == 0) {
+      if (idx == kTile - 1u) {
+        tail_key[blockIdx.x] = sk[idx];
+        tail_sum[blockIdx.x] = sum;
+        tail_in[blockIdx.x] = inside ? 1u : 0u;
+      }
+      continue;
+    }
+    const uint32_t k = sk[idx];
+    if (b0 + idx >= n || sk[idx + 1] == k) continue;    // not the last pair of its entry
+    float gx = sum.x, gy = sum.y;
+    if (!inside)
+      for (uint32_t bb = blockIdx.x; bb-- > 0;) {
+        const float2 ts = tail_sum[bb];
+        gx = gx + ts.x;
+        gy = gy + ts.y;
+        if (tail_in[bb]) break;
+      }
+    const size_t q = 2u * (size_t)k;
+    if (MODE == 2) {
+      gdense[q] = gx;
+      gdense[q + 1] = gy;
+    } else if (!skip) {
+      float2 pp = *reinterpret_cast<float2*>(p + q);
+      float2 mm = *reinterpret_cast<float2*>(m + q);
+      float2 vv = *reinterpret_cast<float2*>(v + q);
+      adam_lazy(gx, pp.x, mm.x, vv.x, a);
+      adam_lazy(gy, pp.y, mm.y, vv.y, a);
+      *reinterpret_cast<float2*>(p + q) = pp;
+      *reinterpret_cast<float2*>(m + q) = mm;
+      *reinterpret_cast<float2*>(v + q) = vv;
+      *reinterpret_cast<__half2*>(ph + q) = __halves2half2(__float2half(pp.x), __float2half(pp.y));
+    }
   }
 }
 
@@ -1033,13 +1195,36 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->hitpos, PR));
   A(lalloc(&s->hitnrm, PR));
   A(lalloc(&s->trec, PR));
-  A(lalloc(&s->trec_count, 1));
+  s->tflag_blocks = (uint32_t)((PR + kTile - 1) / kTile);
+  A(lalloc(&s->tflag, (size_t)s->tflag_blocks * kTile));
+  A(lalloc(&s->clist, PR));
+  A(lalloc(&s->ccount, (size_t)s->tflag_blocks + 1));
   // the frame's batch holds one sub-batch per optimiser step (at most 2^20 rows)
   const uint32_t steps = g.mlp_steps ? g.mlp_steps : 1u;
   s->sub = std::max<uint32_t>(1u, std::min<uint32_t>(steps, (1u << 20) / s->B));
-  A(lalloc(&s->batch, 3 * (size_t)s->B * s->sub));
-  A(lalloc(&s->batch_raw, 3 * (size_t)s->B * s->sub));
-  A(lalloc(&s->sort_cnt, kSortBuckets));
+  const size_t rows = (size_t)s->B * s->sub;
+  A(lalloc(&s->batch, 3 * rows));
+  A(lalloc(&s->batch_raw, 3 * rows));
+  // gradient pairs of a step: every sample, level and corner; keys of level * T + entry
+  s->n_pairs = (size_t)s->B * lp.L * 8u;
+  uint32_t lbits = 0;
+  while ((1u << lbits) < lp.L) ++lbits;
+  uint32_t tbits = 0;
+  while ((1u << tbits) < lp.T) ++tbits;
+  s->key_bits = lbits + tbits;
+  for (int k = 0; k < 2; ++k) {
+    A(lalloc(&s->bkeys[k], rows));
+    A(lalloc(&s->bvals[k], rows));
+    A(lalloc(&s->pkeys[k], s->n_pairs));
+    A(lalloc(&s->pvals[k], s->n_pairs));
+  }
+  const size_t nb_max = (std::max(rows, s->n_pairs) + kTile - 1) / kTile;
+  A(lalloc(&s->rs_hist, 256 * nb_max + 1));
+  const size_t ntiles = (s->n_pairs + kTile - 1) / kTile;
+  A(lalloc(&s->tail_key, ntiles));
+  A(lalloc(&s->tail_sum, ntiles));
+  A(lalloc(&s->tail_in, ntiles));
+  A(lalloc(&s->lpart, s->train_waves));
   A(lalloc(&s->judge_part, (size_t)c->hit_blocks_per_stripe * kStatStripes));
   A(lalloc(&s->lmlp, PR));
   A(lalloc(&s->acc, 16));
@@ -1054,7 +1239,7 @@ hipError_t learned_create(gi_context* c) {
   A(hipMemset(s->mlp_g, 0, 4 * kMlpParams));
   A(hipMemset(s->scales, 0, 64));
   A(hipMemset(s->acc, 0, 64));
-  A(hipMemset(s->trec_count, 0, 4));
+  A(hipMemset(s->tflag, 0, (size_t)s->tflag_blocks * kTile));
   A(hipMemset(s->lmlp, 0, 16 * PR));
   if (e != hipSuccess) return e;
   const uint64_t n = std::max<uint64_t>(s->grid_n, kMlpParams);
@@ -1074,8 +1259,10 @@ void learned_destroy(gi_context* c) {
   LearnedState* s = c->learned;
   if (!s) return;
   void* ptrs[] = {s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->mlp, s->mlp_g, s->mlp_m, s->mlp_v,
-                  s->mlp_part, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->trec_count, s->batch,
-                  s->batch_raw, s->sort_cnt, s->judge_part, s->lmlp, s->acc};
+                  s->mlp_part, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->tflag, s->clist,
+                  s->ccount, s->batch, s->batch_raw, s->bkeys[0], s->bkeys[1], s->bvals[0], s->bvals[1],
+                  s->pkeys[0], s->pkeys[1], s->pvals[0], s->pvals[1], s->rs_hist, s->tail_key, s->tail_sum,
+                  s->tail_in, s->lpart, s->judge_part, s->lmlp, s->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -1101,33 +1288,55 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   LearnedState* s = c->learned;
   const float S = c->cfg.mlp_loss_scale > 0.0f ? c->cfg.mlp_loss_scale : 1.0f;
   k_train_begin<<<1, 64, 0, st>>>(s->acc, s->scales);
-  // the applied step's grid Adam leaves the gradient zeroed; a gradient-only step does not
+  // a gradient-only step leaves its dense gradient in grid_g; clear it before the next
   if (s->grad_dirty) k_zero_f32<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid_g, s->grid_n);
   s->grad_dirty = false;
   const uint32_t groups = s->B / 32u;
   const uint32_t waves = std::min<uint32_t>(s->train_waves, std::max<uint32_t>(groups, 1u));
+  uint32_t log2T = 0;
+  while ((1u << log2T) < s->lp.T) ++log2T;
   hipEvent_t ev;
   timer_begin(c, "learned_train", st, &ev);
   // every launched wave writes its whole partial, so the partials need no clearing
-  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->grid_g, s->wb, S,
-                                                s->mlp_part, s->acc, s->scales + 3);
+  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->pkeys[0],
+                                                s->pvals[0], log2T, s->wb, S, s->mlp_part, s->lpart, s->acc,
+                                                s->scales + 3);
   timer_end(c, "learned_train", st, ev);
-  k_reduce_mlp<<<nblk(kMlpParams, 64), 1024, 0, st>>>(s->mlp_part, waves, s->mlp_g, s->acc);
+  k_reduce_mlp<<<nblk(kMlpParams, 64), 1024, 0, st>>>(s->mlp_part, s->lpart, waves, s->mlp_g, s->acc);
+  // the encoding gradient: pairs sorted by entry, summed per entry in a fixed order
+  timer_begin(c, "learned_grad_sort", st, &ev);
+  int which = 0;
+  const uint32_t n = (uint32_t)s->n_pairs;
+  hipError_t e = radix_sort<float2>(s->pkeys, s->pvals, n, s->key_bits, s->rs_hist, st, which);
+  timer_end(c, "learned_grad_sort", st, ev);
+  if (e != hipSuccess) return e;
+  const uint32_t nt = nblk(n, kTile);
+  AdamArgs ag{};
   if (apply) {
     s->step += 1;
-    AdamArgs ag, am;
-    ag.b1 = am.b1 = 0.9f;
-    ag.b2 = am.b2 = 0.99f;
-    ag.c1 = am.c1 = (float)(1.0 - std::pow(0.9, (double)s->step));
-    ag.c2 = am.c2 = (float)(1.0 - std::pow(0.99, (double)s->step));
-    ag.inv_scale = am.inv_scale = 1.0f / S;
+    ag.b1 = 0.9f;
+    ag.b2 = 0.99f;
+    ag.c1 = (float)(1.0 - std::pow(0.9, (double)s->step));
+    ag.c2 = (float)(1.0 - std::pow(0.99, (double)s->step));
+    ag.inv_scale = 1.0f / S;
     ag.lr = c->cfg.mlp_lr_grid;
     ag.eps = 1e-15f;
+  }
+  timer_begin(c, "learned_grad_apply", st, &ev);
+  k_gred<0><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_key, s->tail_sum, s->tail_in, s->grid,
+                                s->grid_h, s->grid_m, s->grid_v, s->grid_g, ag, s->acc);
+  if (apply)
+    k_gred<1><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_key, s->tail_sum, s->tail_in, s->grid,
+                                  s->grid_h, s->grid_m, s->grid_v, s->grid_g, ag, s->acc);
+  else
+    k_gred<2><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_key, s->tail_sum, s->tail_in, s->grid,
+                                  s->grid_h, s->grid_m, s->grid_v, s->grid_g, ag, s->acc);
+  timer_end(c, "learned_grad_apply", st, ev);
+  if (apply) {
+    AdamArgs am = ag;
     am.lr = c->cfg.mlp_lr_mlp;
     am.eps = 1e-8f;
     timer_begin(c, "learned_adam", st, &ev);
-    k_adam_grid<<<nblk((s->grid_n + 3) / 4, 256), 256, 0, st>>>(s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v,
-                                                                s->grid_n, ag, s->acc);
     k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc, s->wb, s->w8, s->scales,
                                    c->d_stats);
     timer_end(c, "learned_adam", st, ev);
@@ -1141,15 +1350,20 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
 hipError_t learned_train(gi_context* c, hipStream_t st) {
   LearnedState* s = c->learned;
   learned_set_domain(c);
-  // the frame's batch: sub * B stratified picks over this frame's training records, grouped
+  // the frame's training rays in ray order, then sub * B stratified picks over them, grouped
   // by Morton bucket once; step k trains on rows k, k + sub, k + 2 sub, ... (each step spans
   // the whole scene and its rows stay in spatial order)
-  const size_t PR = (size_t)c->P * c->R;
   const uint32_t steps = c->cfg.mlp_steps ? c->cfg.mlp_steps : 1u;
   const uint32_t rows = s->B * s->sub;
   const float u = rand_unit_host(hash_pcg(hash_pcg(hash_pcg(hash_pcg(c->cfg.seed) + c->fa.index) + 0x7FFFFFFFu) + 9u));
-  k_select_batch<<<nblk(rows, 256), 256, 0, st>>>(s->trec, s->trec_count, (uint32_t)PR, s->hitpos, s->hitnrm, u,
-                                                  rows, s->batch_raw, s->acc);
+  hipEvent_t ev;
+  timer_begin(c, "learned_select", st, &ev);
+  k_tflag_count<<<s->tflag_blocks, 256, 0, st>>>(s->tflag, s->ccount);
+  k_scan_counts<<<1, 1024, 0, st>>>(s->ccount, s->tflag_blocks);
+  k_tflag_compact<<<s->tflag_blocks, 256, 0, st>>>(s->tflag, s->ccount, s->clist);
+  k_select_batch<<<nblk(rows, 256), 256, 0, st>>>(s->clist, s->ccount + s->tflag_blocks, s->trec, s->hitpos,
+                                                  s->hitnrm, u, rows, s->batch_raw, s->acc);
+  timer_end(c, "learned_select", st, ev);
   hipError_t e = sort_batch(c, st, rows);
   for (uint32_t k = 0; k < steps && e == hipSuccess; ++k) e = train_step(c, st, true, k % s->sub, s->sub);
   if (e != hipSuccess) return e;
@@ -1262,6 +1476,17 @@ hipError_t learned_load(gi_context* c, const void* blob) {
   return e;
 }
 
+hipError_t learned_batch_export(gi_context* c, float* h_raw, float* h_grouped, uint32_t cap_rows, uint32_t& rows,
+                                uint32_t& n_train) {
+  LearnedState* s = c->learned;
+  rows = s->B * s->sub;
+  hipError_t e = hipMemcpy(&n_train, s->ccount + s->tflag_blocks, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess || cap_rows < rows) return e;
+  if (h_raw) e = hipMemcpy(h_raw, s->batch_raw, 48 * (size_t)rows, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && h_grouped) e = hipMemcpy(h_grouped, s->batch, 48 * (size_t)rows, hipMemcpyDeviceToHost);
+  return e;
+}
+
 void learned_stats(gi_context* c, float* out8) {
   LearnedState* s = c->learned;
   float acc[16];
@@ -1287,8 +1512,8 @@ LearnedShadeOut learned_shade_out(gi_context* c) {
   o.hitpos = s->hitpos;
   o.hitnrm = s->hitnrm;
   o.trec = s->trec;
-  o.trec_count = s->trec_count;
-  o.trec_cap = c->P * c->R;
+  o.tflag = s->tflag;
+  o.tflag_words = s->tflag_blocks * (kTile / 4u);
   return o;
 }
 

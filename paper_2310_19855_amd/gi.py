@@ -124,6 +124,7 @@ def lib():
     fn("gi_learned_save", st, vp, vp, sz, P(sz))
     fn("gi_learned_load", st, vp, vp, sz)
     fn("gi_learned_stats", st, vp, vp)
+    fn("gi_learned_batch_export", st, vp, vp, vp, u32, P(u32), P(u32))
     _lib = L
     return L
 
@@ -430,6 +431,18 @@ class Context:
         self._check(lib().gi_learned_stats(self.h, out.ctypes.data), "gi_learned_stats")
         return dict(loss=float(out[0]), judged_err=float(out[1]), fallback=bool(out[2]),
                     steps=int(out[3]), skipped=int(out[4]))
+
+    def learned_batch(self):
+        """the last gi_learned_train's batch: dict(raw, grouped [rows, 3, 4] float32 (pos+t,
+        normal + ray-id bits, target + 1), gid [rows] (raw order), n_train)"""
+        rows, n = C.c_uint32(0), C.c_uint32(0)
+        self._check(lib().gi_learned_batch_export(self.h, None, None, 0, C.byref(rows), C.byref(n)),
+                    "gi_learned_batch_export")
+        raw = np.zeros((rows.value, 3, 4), np.float32)
+        grouped = np.zeros((rows.value, 3, 4), np.float32)
+        self._check(lib().gi_learned_batch_export(self.h, raw.ctypes.data, grouped.ctypes.data, rows.value,
+                                                  C.byref(rows), C.byref(n)), "gi_learned_batch_export")
+        return dict(raw=raw, grouped=grouped, gid=raw[:, 1, 3].view(np.uint32).copy(), n_train=int(n.value))
 
     def profile(self, on: bool):
         self._check(lib().gi_profile_enable(self.h, int(on)), "gi_profile_enable")

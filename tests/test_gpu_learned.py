@@ -97,9 +97,9 @@ def test_gradients_and_adam_step_match_the_oracle():
     gW1, gW2, gW3 = gm[:4096].reshape(64, 64), gm[4096:8192].reshape(64, 64), gm[8192:].reshape(16, 64)
     # BF16 operands with FP32 accumulation: direction and scale of every gradient block
     for got, ref in ((gW1, g["W1"]), (gW2, g["W2"]), (gW3, g["W3"]), (gg, g["grid"])):
-        assert _cos(got, ref) > 0.995, _cos(got, ref)
-        assert abs(np.linalg.norm(got) / np.linalg.norm(ref) - 1) < 0.03
-    assert abs(ctx.learned_stats()["loss"] - loss) / loss < 0.02
+        assert _cos(got, ref) > 0.999, _cos(got, ref)
+        assert abs(np.linalg.norm(got) / np.linalg.norm(ref) - 1) < 0.01
+    assert abs(ctx.learned_stats()["loss"] - loss) / loss < 0.01
     # the Adam step (gradients recomputed on the same batch): first step is -lr * sign(g)
     ctx.learned_step(tp, tn, tt, apply=True)
     torch.cuda.synchronize()
@@ -115,7 +115,8 @@ def test_gradients_and_adam_step_match_the_oracle():
     assert (np.sign(d_mlp[big]) == -np.sign(gref[big])).mean() > 0.99
 
 
-@pytest.mark.parametrize("mode,tol", [(gi.CACHE_MLP_BF16, 0.03), (gi.CACHE_MLP_FP8, 0.15)])
+# measured: BF16 0.0055, FP8 e4m3 0.049 relative L2
+@pytest.mark.parametrize("mode,tol", [(gi.CACHE_MLP_BF16, 0.01), (gi.CACHE_MLP_FP8, 0.08)])
 def test_inference_matches_oracle_after_training_steps(mode, tol):
     ctx, sc, lo, hi = _ctx(mode)
     spec = OL.Spec(levels=LEVELS, table_log2=TLOG2)
@@ -135,6 +136,7 @@ def test_inference_matches_oracle_after_training_steps(mode, tol):
     ref, _ = OL.forward(spec, params, OL.normalize_pos(qp[:, :3], lo, hi), qn[:, :3])
     ref = np.maximum(ref, 0)
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"mode {mode}: inference relative L2 {rel:.5f}")
     assert rel < tol, rel
 
 
@@ -300,3 +302,204 @@ def test_surrogate_gain_over_plain_cache_on_the_field_scene():
     e_mlp = np.abs(m[found, :3] - Lr[found]).sum() / np.abs(Lr[found]).sum()
     print(f"field, 8 frames at 64 rays, {found.sum()} points: relMAE plain {e_plain:.4f}, surrogate {e_mlp:.4f}")
     assert e_mlp < 0.85 * e_plain
+
+
+# ---- full-size learned path: batch selection, gradients, steps, determinism -------------
+
+def _field_learned_cfg(sc, **kw):
+    cfg = dict(width=1920, height=1080, rays_per_probe=64, table_log2=20, bounces=1, sky=sc.sky,
+               cache_mode=gi.CACHE_MLP_BF16, mlp_batch_log2=14, mlp_levels=16, mlp_table_log2=19, mlp_steps=4,
+               mlp_lr_grid=1e-2, mlp_lr_mlp=1e-2, mlp_judge=10.0, seed=SEED, mlp_loss_scale=128.0,
+               scene_min=tuple(sc.verts.min(0)) + (0.0,), scene_max=tuple(sc.verts.max(0)) + (0.0,))
+    cfg.update(kw)
+    return cfg
+
+
+def _oracle_batch(pr, rows, f, lo, hi):
+    """the oracle's batch of frame f (after its trace): raw rows [rows, 3, 4] and the grouped order"""
+    r = pr.ost.rays()
+    y, ny = pr.ost.hits()
+    gids = OL.training_rays(r["slot"], r["cell"], r["sample"])
+    picks = gids[OL.select_picks(len(gids), rows, OL.frame_u(SEED, f))]
+    raw = np.zeros((rows, 3, 4), np.float32)
+    raw[:, 0, :3] = y[picks]
+    raw[:, 0, 3] = r["t"][picks]
+    raw[:, 1, :3] = ny[picks]
+    raw[:, 1, 3] = picks.astype(np.uint32).view(np.float32)
+    raw[:, 2, :3] = r["sample"][picks]
+    raw[:, 2, 3] = 1.0
+    order = OL.group_order(OL.normalize_pos(raw[:, 0, :3], lo, hi))
+    return len(gids), raw, order
+
+
+def test_training_batch_matches_oracle_field1080():
+    """The learned path's batch selection on two frames of the 1920x1080 field (64 rays per
+    probe, 2^14-sample steps, 4 steps): the frame's training rays (compacted in ray order),
+    every pick (ray id), its hit point, distance, normal and target, and the stable Morton
+    grouping bit-exact with the oracle."""
+    from gpu_common import Pair
+    sc = I.field_scene()
+    cfg = _field_learned_cfg(sc)
+    pr = Pair(sc, cfg)
+    lo, hi = sc.verts.min(0), sc.verts.max(0)
+    rows = OL.batch_rows(1 << 14, 4)
+    for f in (0, 1):
+        fr = I.camera_for("field", f)
+        fr.index = f
+        pr.set_frame_dynamic(f)
+        (gp, gn, ga, gprim), (op, on, oa, oprim) = pr.gbuffer(fr)
+        pr.ctx.spawn_probes(fr, pr.gb.pos, pr.gb.nrm, pr.gb.prim)
+        pr.ost.spawn(fr, op, on, oprim)
+        pr.ctx.trace_probes(fr)
+        pr.ost.trace(fr)
+        pr.ctx.learned_train(fr)
+        b = pr.ctx.learned_batch()
+        n, raw, order = _oracle_batch(pr, rows, f, lo, hi)
+        assert b["n_train"] == n and n > 400_000
+        assert np.array_equal(b["gid"], raw[:, 1, 3].view(np.uint32)), "picked rays differ"
+        assert np.array_equal(b["raw"].view(np.uint32), raw.view(np.uint32)), "batch rows differ"
+        assert np.array_equal(b["grouped"].view(np.uint32), raw[order].view(np.uint32)), "grouping differs"
+        pr.ctx.cache_update(fr)
+        pr.ost.update(fr)
+    pr.ctx.close()
+
+
+@pytest.mark.parametrize("levels,tlog2", [(8, 14), (16, 19)])
+def test_full_size_step_matches_the_oracle(levels, tlog2):
+    """One 2^14-sample step at the benchmark's sizes, where the low levels take the dense
+    corner index ((N_l + 1)^3 <= T: level 0 at 8 x 2^14, levels 0-4 at 16 x 2^19) and the
+    gradient pairs are sorted and summed per entry: MLP and grid gradients against the float64
+    oracle (cosine and norm ratio per block), then the Adam step (the first step moves every
+    parameter with a clear gradient by -lr * sign(g))."""
+    spec = OL.Spec(levels=levels, table_log2=tlog2)
+    assert any((N + 1) ** 3 <= spec.T for N in spec.resolutions())
+    sc = I.field_scene()
+    lo, hi = sc.verts.min(0), sc.verts.max(0)
+    ctx = gi.Context(width=64, height=64, cache_mode=gi.CACHE_MLP_BF16, mlp_levels=levels, mlp_table_log2=tlog2,
+                     mlp_batch_log2=14, seed=SEED, mlp_loss_scale=128.0, mlp_lr_grid=OL.Spec.lr_grid,
+                     mlp_lr_mlp=OL.Spec.lr_mlp, scene_min=tuple(lo) + (0.0,), scene_max=tuple(hi) + (0.0,))
+    ctx.build_bvh(sc)
+    B = 1 << 14
+    # clustered samples (shared coarse entries, long per-entry runs in the sort) and spread ones
+    rng = np.random.default_rng(2)
+    pos, nrm, tgt = _samples(B, lo, hi, seed=5)
+    pos[: B // 2, :3] = rng.normal(loc=(lo + hi) / 2, scale=1.5, size=(B // 2, 3)).clip(lo, hi)
+    tp, tn, tt = (torch.from_numpy(a).cuda() for a in (pos, nrm, tgt))
+    ctx.learned_step(tp, tn, tt, apply=False)
+    torch.cuda.synchronize()
+    st = _unpack(ctx, spec)
+    params = OL.init_params(spec, SEED)
+    x32 = OL.normalize_pos(pos[:, :3], lo, hi)
+    loss, g = OL.loss_and_grads(spec, params, x32, nrm[:, :3], tgt[:, :3])
+    S = 128.0
+    gg = st["grid_g"].reshape(spec.levels, spec.T, 2) / S
+    gm = st["mlp_g"] / S
+    got = {"W1": gm[:4096].reshape(64, 64), "W2": gm[4096:8192].reshape(64, 64), "W3": gm[8192:].reshape(16, 64),
+           "grid": gg}
+    for k in ("W1", "W2", "W3", "grid"):
+        c = _cos(got[k], g[k])
+        r = np.linalg.norm(got[k]) / np.linalg.norm(g[k])
+        print(f"{levels}x2^{tlog2} {k}: cosine {c:.6f}, norm ratio {r:.5f}")
+        assert c > 0.999, (k, c)
+        assert abs(r - 1) < 0.01, (k, r)
+    # dense levels: every entry the oracle touches is touched on the GPU, and no other
+    for l, N in enumerate(spec.resolutions()):
+        if (N + 1) ** 3 <= spec.T:
+            assert np.array_equal(gg[l] != 0, g["grid"][l] != 0), l
+    assert abs(ctx.learned_stats()["loss"] - loss) / loss < 0.01
+    ctx.learned_step(tp, tn, tt, apply=True)
+    torch.cuda.synchronize()
+    st2 = _unpack(ctx, spec)
+    assert st2["step"] == 1
+    d_grid = st2["grid"] - st["grid"]
+    gref = g["grid"].ravel()
+    big = np.abs(gref) > 1e-3 * np.abs(gref).max()
+    assert (np.sign(d_grid[big]) == -np.sign(gref[big])).mean() > 0.999
+    assert np.allclose(np.abs(d_grid[big]), OL.Spec.lr_grid, rtol=1e-3)
+    # lazy step: entries without a gradient keep their value
+    assert np.array_equal(d_grid[gref == 0] != 0, np.zeros(int((gref == 0).sum()), bool))
+    ctx.close()
+
+
+def test_learned_frames_are_deterministic():
+    """Two contexts running the same learned frames produce bit-identical parameters, Adam
+    moments and losses (no float atomics on the training path)"""
+    sc = I.room_scene()
+    blobs, losses = [], []
+    for _ in range(2):
+        ctx, _, _, _ = _ctx(gi.CACHE_MLP_BF16, width=256, height=192, rays_per_probe=32, table_log2=16,
+                            mlp_batch_log2=12, mlp_levels=16, mlp_table_log2=16, mlp_steps=3, mlp_judge=10.0)
+        gb = gi.GBuffer(192, 256)
+        out = torch.zeros((192, 256, 4), dtype=torch.float32, device="cuda")
+        ls = []
+        for f in range(4):
+            fr = I.room_camera(f % 2)
+            fr.index = f
+            ctx.render_gbuffer(fr, gb.pos, gb.nrm, gb.alb, gb.prim)
+            ctx.spawn_probes(fr, gb.pos, gb.nrm, gb.prim)
+            ctx.trace_probes(fr)
+            ctx.learned_train(fr)
+            ctx.cache_update(fr)
+            ctx.interpolate_probes(fr, gb.pos, gb.nrm, gb.prim, out)
+            ls.append(ctx.learned_stats()["loss"])
+        torch.cuda.synchronize()
+        blobs.append(np.frombuffer(ctx.learned_save(), np.uint8).copy())
+        losses.append(ls)
+        ctx.close()
+    assert losses[0] == losses[1]
+    assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_learned_frame_matches_the_oracle_field1080():
+    """One whole learned frame of the benchmark workload (1920x1080 field, 64 rays per probe,
+    4 steps of 2^14 samples on 16 x 2^19 entries): the oracle takes its own bit-identical
+    batch and groups through the same 4 Adam steps in float64; the steps' losses, the
+    parameters' update directions and the trained surrogate's radiance at the batch's points
+    are compared."""
+    from gpu_common import Pair
+    sc = I.field_scene()
+    cfg = _field_learned_cfg(sc)
+    pr = Pair(sc, cfg)
+    lo, hi = sc.verts.min(0), sc.verts.max(0)
+    B, steps = 1 << 14, 4
+    rows = OL.batch_rows(B, steps)
+    fr = I.camera_for("field", 0)
+    fr.index = 0
+    pr.set_frame_dynamic(0)
+    (gp, gn, ga, gprim), (op, on, oa, oprim) = pr.gbuffer(fr)
+    pr.ctx.spawn_probes(fr, pr.gb.pos, pr.gb.nrm, pr.gb.prim)
+    pr.ost.spawn(fr, op, on, oprim)
+    pr.ctx.trace_probes(fr)
+    pr.ost.trace(fr)
+    spec = OL.Spec(levels=16, table_log2=19, lr_grid=1e-2, lr_mlp=1e-2)
+    st0 = _unpack(pr.ctx, spec)
+    pr.ctx.learned_train(fr)
+    torch.cuda.synchronize()
+    st = _unpack(pr.ctx, spec)
+    assert st["step"] == steps
+    n, raw, order = _oracle_batch(pr, rows, 0, lo, hi)
+    grouped = raw[order]
+    params = OL.init_params(spec, SEED)
+    opt = OL.Adam(spec, params)
+    for k in range(steps):
+        r = grouped[OL.step_rows(rows, B, k)]
+        loss, g = OL.loss_and_grads(spec, params, OL.normalize_pos(r[:, 0, :3], lo, hi), r[:, 1, :3], r[:, 2, :3])
+        assert opt.step(params, g)
+    assert abs(pr.ctx.learned_stats()["loss"] - loss) / loss < 0.02, (pr.ctx.learned_stats()["loss"], loss)
+    got = _params_from(st["grid"], st["mlp"], spec)
+    ini = _params_from(st0["grid"], st0["mlp"], spec)
+    for k in ("W1", "W2", "W3", "grid"):
+        c = _cos(got[k] - ini[k], params[k] - ini[k])
+        print(f"update direction {k}: cosine {c:.5f}")
+        assert c > 0.98, (k, c)
+    pts = grouped[::16]
+    q = torch.zeros((len(pts), 4), dtype=torch.float32, device="cuda")
+    pr.ctx.learned_query(torch.from_numpy(np.ascontiguousarray(pts[:, 0])).cuda(),
+                         torch.from_numpy(np.ascontiguousarray(pts[:, 1])).cuda(), q)
+    torch.cuda.synchronize()
+    ref, _ = OL.forward(spec, params, OL.normalize_pos(pts[:, 0, :3], lo, hi), pts[:, 1, :3])
+    ref = np.maximum(ref, 0)
+    rel = np.linalg.norm(q.cpu().numpy()[:, :3] - ref) / np.linalg.norm(ref)
+    print(f"surrogate radiance at {len(pts)} batch points: relative L2 {rel:.5f}")
+    assert rel < 0.05, rel
+    pr.ctx.close()

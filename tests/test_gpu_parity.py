@@ -513,12 +513,23 @@ def test_furnace_parity_and_closed_form():
         L = rho * (le + L)
         p = pr.ctx.probes()
         valid = p["mask"][:len(p["pos"])] != SENT
-        assert abs(p["atlas"][valid][..., :3].mean() / (le + L) - 1) < 8e-3, f
-    assert abs((le + L) / (le / (1 - rho)) - 1) < 2e-4
+        atlas = p["atlas"][valid][..., :3].astype(np.float64)
+        # every probe ray returns Le + L_f of the cell it hits: the mean over the GPU atlas
+        # follows the recurrence (cells created late lag a frame early on; single cells spread
+        # up to a few % from the facets and the 2^-12 steps)
+        assert abs(atlas.mean() / (le + L) - 1) < (1.5e-3 if f < 20 else 3e-4), f
+        assert np.abs(atlas / (le + L) - 1).max() < 0.1, f
+    # and converges to the closed-form limit Le / (1 - rho) = 5 (rho^41 = 1.1e-4 away)
+    assert abs(atlas.mean() / (le / (1 - rho)) - 1) < 7e-4
+    # the cells the last frame's rays touched hold L_39 = rho Le (1 - rho^40) / (1 - rho)
+    t = pr.ctx.table()
+    live = t["life"] == cfg.get("max_life", 32)
+    assert live.sum() > 100
+    assert abs(t["L"][live].astype(np.float64).mean() / L - 1) < 5e-4
     pr.ctx.interpolate_probes(fr, pr.gb.pos, pr.gb.nrm, pr.gb.prim, pr.out)
     o = pr.out.cpu().numpy()
     assert (o[..., 3] == 0).all()
-    assert abs(o[..., :3].mean() / (math.pi * (le + L)) - 1) < 8e-3
+    assert abs(o[..., :3].mean() / (math.pi * (le + L)) - 1) < 2e-3
 
 
 def test_cache_query_matches_oracle():

@@ -185,3 +185,75 @@ def test_init_values_are_seeded_uniform():
     assert abs(v.mean()) < 0.01 and abs(v.var() - 1 / 3) < 0.01
     assert np.array_equal(v, L.init_values(3, 1, 100000, 1.0))
     assert not np.array_equal(v, L.init_values(4, 1, 100000, 1.0))
+
+
+# ---- the frame's training batch --------------------------------------------------------
+
+def test_training_rays_hand_flags():
+    # rays: 0 hit with a cell, 1 miss, 2 hit that overflowed (no cell), 3 hit with a non-finite
+    # sample, 4 hit with a cell
+    flags = np.array([0x100 | 5, 3, 0x100, 0x100 | 0x10000, 0x100 | 0x200], np.uint32)
+    slot = np.array([7, -1, -1, 3, 0], np.int32)
+    sample = np.array([[1, 1, 1], [0, 0, 0], [1, 1, 1], [np.inf, 0, 0], [0, 0, 0]], np.float32)
+    assert L.training_rays(slot, flags, sample).tolist() == [0, 4]
+
+
+def test_select_picks_hand_values_and_strata():
+    # floor((k + 1/2) * 10 / 4) = floor(1.25), floor(3.75), floor(6.25), floor(8.75)
+    assert L.select_picks(10, 4, 0.5).tolist() == [1, 3, 6, 8]
+    # fewer training rays than rows: floor(3k / 8) repeats rays in order
+    assert L.select_picks(3, 8, 0.0).tolist() == [0, 0, 0, 1, 1, 1, 2, 2]
+    # u just below 1 never reaches n
+    u = np.float32(1.0) - np.float32(2.0 ** -24)
+    assert L.select_picks(5, 5, u).tolist() == [0, 1, 2, 3, 4]
+    # with n >= rows, pick k lies in stratum [k n / rows, (k + 1) n / rows): exact rationals
+    from fractions import Fraction
+    n, rows = 1000003, 4096
+    u = L.frame_u(3, 7)
+    picks = L.select_picks(n, rows, u)
+    for k in range(0, rows, 97):
+        exact = (Fraction(k) + Fraction(float(u))) * n / rows
+        assert picks[k] == math.floor(exact)
+        assert Fraction(k * n, rows) <= picks[k] < Fraction((k + 1) * n, rows)
+
+
+def test_frame_u_is_the_top_24_bits_of_the_seeded_hash():
+    for seed, f in ((3, 0), (3, 1), (17, 59)):
+        u = L.frame_u(seed, f)
+        assert u.dtype == np.float32 and 0.0 <= u < 1.0
+        assert float(u) * 2 ** 24 == int(L.rng_u32(seed, f, 0x7FFFFFFF, 9)) >> 8
+    assert L.frame_u(3, 0) != L.frame_u(3, 1)
+
+
+def test_morton15_hand_codes():
+    c = lambda q: L.morton15(np.array([q], np.float32) / np.float32(32))[0]  # noqa: E731
+    assert c([1, 0, 0]) == 1 and c([0, 1, 0]) == 2 and c([0, 0, 1]) == 4
+    assert c([2, 0, 0]) == 8 and c([0, 0, 16]) == 1 << 14
+    assert c([31, 31, 31]) == (1 << 15) - 1 and c([5, 9, 3]) == c([5, 9, 3])
+    # the top of the domain clamps into the last cell
+    assert L.morton15(np.array([[1.0, 1.0, 1.0]], np.float32))[0] == (1 << 15) - 1
+    # interleaving by brute force over random cells
+    rng = np.random.default_rng(0)
+    q = rng.integers(0, 32, size=(200, 3))
+    got = L.morton15((q.astype(np.float32) + np.float32(0.5)) / np.float32(32))
+    for (a, b, cc), g in zip(q, got):
+        bits = "".join(f"{z:05b}"[4 - i] + f"{y:05b}"[4 - i] + f"{x:05b}"[4 - i]
+                       for i in reversed(range(5)) for x, y, z in [(a, b, cc)])
+        assert g == int(bits, 2)
+
+
+def test_group_order_is_a_stable_sort_by_code():
+    rng = np.random.default_rng(1)
+    x = rng.integers(0, 4, size=(500, 3)).astype(np.float32) / np.float32(4)   # many equal codes
+    order = L.group_order(x)
+    codes = L.morton15(x)
+    assert sorted(range(500), key=lambda i: (int(codes[i]), i)) == order.tolist()
+
+
+def test_step_rows_partition_the_batch():
+    B, steps = 16, 4
+    rows = L.batch_rows(B, steps)
+    assert rows == 64 and L.batch_rows(1 << 19, 4) == 1 << 20 and L.batch_rows(1 << 20, 4) == 1 << 20
+    got = np.concatenate([L.step_rows(rows, B, k) for k in range(steps)])
+    assert sorted(got.tolist()) == list(range(rows))
+    assert L.step_rows(rows, B, 1).tolist() == list(range(1, 64, 4))
