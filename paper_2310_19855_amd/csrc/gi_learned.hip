@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "gi_device.hpp"
 #include "gi_host.hpp"
@@ -40,11 +41,11 @@ struct LearnedParams {
 struct LearnedState {
   LearnedParams lp;
   uint32_t grid_n = 0;           // L * T * 2
-  float* grid = nullptr;         // FP32 master [L][T][2]
-  __half* grid_h = nullptr;      // FP16 working copy
-  float* grid_g = nullptr;       // gradient (scaled by the loss scale)
-  float* grid_m = nullptr;
-  float* grid_v = nullptr;
+  // FP32 master values and Adam moments of the grid, interleaved per table entry (its two
+  // features) in one 32-byte line: p0 p1 m0 m1 v0 v1 0 0 (entry e at gstate[8e])
+  float* gstate = nullptr;
+  __half* grid_h = nullptr;      // FP16 working copy [L][T][2]
+  float* grid_g = nullptr;       // gradient of a gradient-only step (scaled by the loss scale)
   float* mlp = nullptr;          // FP32 master: W1 [64][64], W2 [64][64], W3 [16][64]
   float* mlp_g = nullptr;
   float* mlp_m = nullptr;
@@ -68,12 +69,14 @@ struct LearnedState {
   uint32_t* pkeys[2] = {nullptr, nullptr};
   float2* pvals[2] = {nullptr, nullptr};
   uint32_t* rs_hist = nullptr;   // [256][blocks] digit counts -> offsets
-  uint32_t* tail_key = nullptr;  // per reduction tile: key, sum and origin of its last segment
-  float2* tail_sum = nullptr;
-  uint32_t* tail_in = nullptr;
+  float2* tail_sum = nullptr;    // per reduction tile: partial sum of its last entry, whether
+  uint32_t* tail_in = nullptr;   // that entry began inside the tile, and the tile's carry-in
+  float2* tail_carry = nullptr;
   size_t n_pairs = 0;
   uint32_t key_bits = 0;         // bits of a gradient pair key (level * T + entry)
   float* lpart = nullptr;        // [train_waves] loss partials
+  float2* enc = nullptr;         // [B][16] the step's encoding (level features)
+  float* dX = nullptr;           // [B][32] gradient of the loss at the encoding
   float2* judge_part = nullptr;  // per-wave (error, norm) partials of the judge
   uint32_t B = 0;
   uint32_t sub = 1;              // sub-batches held by the frame's batch (rows = sub * B)
@@ -159,14 +162,14 @@ __device__ inline float init_value(uint32_t seed, uint32_t stream, uint32_t i, f
   return (u * 2.0f - 1.0f) * scale;
 }
 
-__global__ void k_learned_init(float* grid, __half* grid_h, uint32_t L, uint32_t T, float* mlp, uint32_t seed) {
+__global__ void k_learned_init(float* gstate, __half* grid_h, uint32_t L, uint32_t T, float* mlp, uint32_t seed) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t n = (uint64_t)L * T * 2u;
   if (i < n) {
     const uint32_t l = (uint32_t)(i / ((uint64_t)T * 2u));
     const uint32_t k = (uint32_t)(i % ((uint64_t)T * 2u));
     const float v = init_value(seed, 100u + l, k, 1e-4f);
-    grid[i] = v;
+    gstate[8u * (i >> 1) + (i & 1u)] = v;   // moments are zeroed by the caller
     grid_h[i] = __float2half(v);
   }
   if (i < (uint64_t)kMlpParams) {
@@ -236,8 +239,10 @@ __global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* w
 // their ranks.  The list is a function of the flags alone.
 constexpr uint32_t kTile = 4096;      // items per block of 256 threads (16 each)
 
-__device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t* lds, uint32_t& total) {
-  // exclusive prefix over the 256 threads of a block, in thread order
+// exclusive prefix over the NT threads of a block, in thread order; every thread of the block
+// must call it (it holds two barriers); lds holds NT / 64 words
+template <uint32_t NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t& total) {
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
   uint32_t x = v;
 #pragma unroll
@@ -248,10 +253,18 @@ __device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t* lds, uint32_
   if (lane == 63u) lds[w] = x;
   __syncthreads();
   uint32_t base = 0;
-  for (uint32_t k = 0; k < w; ++k) base += lds[k];
-  total = lds[0] + lds[1] + lds[2] + lds[3];
+  total = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < NT / 64u; ++k) {
+    if (k < w) base += lds[k];
+    total += lds[k];
+  }
   __syncthreads();
   return base + x - v;
+}
+
+__device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t* lds, uint32_t& total) {
+  return block_excl_scan<256>(v, lds, total);
 }
 
 __global__ __launch_bounds__(256) void k_tflag_count(const uint8_t* flag, uint32_t* cnt) {
@@ -330,54 +343,132 @@ __global__ void k_select_batch(const uint32_t* list, const uint32_t* count, cons
 // order, and a scatter in which every item goes to its digit's offset plus the number of
 // items of its block with the same digit and a lower index (wave ballots, then waves and
 // rounds in order), so equal keys keep their input order.
-constexpr uint32_t kSortBuckets = 1u << 15;
+constexpr uint32_t kRsThreads = 512, kRsRounds = 4, kRsTile = kRsThreads * kRsRounds;
 
-__global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* key, uint32_t n, uint32_t shift, uint32_t nb,
-                                                 uint32_t* hist) {
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* key, uint32_t n, uint32_t shift, uint32_t nb,
+                                                        uint32_t* hist) {
   __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0u;
+  if (threadIdx.x < 256u) h[threadIdx.x] = 0u;
   __syncthreads();
-  const uint32_t b0 = blockIdx.x * kTile;
-  for (uint32_t j = 0; j < kTile / 256u; ++j) {
-    const uint32_t i = b0 + j * 256u + threadIdx.x;
-    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+  // thread t counts keys 4t..4t+3 of the tile (one 16-byte load when all are in range)
+  const uint32_t i0 = blockIdx.x * kRsTile + kRsRounds * threadIdx.x;
+  if (i0 + kRsRounds <= n) {
+    const uint4 k4 = *reinterpret_cast<const uint4*>(key + i0);
+    atomicAdd(&h[(k4.x >> shift) & 255u], 1u);
+    atomicAdd(&h[(k4.y >> shift) & 255u], 1u);
+    atomicAdd(&h[(k4.z >> shift) & 255u], 1u);
+    atomicAdd(&h[(k4.w >> shift) & 255u], 1u);
+  } else {
+    for (uint32_t i = i0; i < n; ++i) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < 256u) hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// block d: exclusive prefix of digit d's block counts (in place) and the digit's total
+__global__ __launch_bounds__(256) void k_rs_digit_scan(uint32_t* hist, uint32_t nb, uint32_t* dtot) {
+  __shared__ uint32_t lds[4];
+  uint32_t* h = hist + (size_t)blockIdx.x * nb;
+  uint32_t carry = 0u;
+  for (uint32_t c = 0; c < nb; c += 256u) {
+    const uint32_t i = c + threadIdx.x;
+    const uint32_t v = i < nb ? h[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan256(v, lds, total);
+    if (i < nb) h[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
+// The tile is first ordered by digit in LDS (stable ranks from wave ballots, waves and rounds
+// in order), then written out so that consecutive threads write consecutive addresses of
+// each digit's run.
 template <typename V>
-__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* kin, const V* vin, uint32_t* kout, V* vout,
-                                                    uint32_t n, uint32_t shift, uint32_t nb, const uint32_t* off) {
-  __shared__ uint32_t run[256];        // next rank of each digit in this block
-  __shared__ uint32_t wcnt[4][256];    // this round's count of each digit per wave
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* kin, const V* vin, uint32_t* kout, V* vout,
+                                                           uint32_t n, uint32_t shift, uint32_t nb, const uint32_t* off,
+                                                           const uint32_t* dtot) {
+  constexpr uint32_t W = kRsThreads / 64u;
+  __shared__ uint32_t sk[kRsTile];
+  __shared__ V sv[kRsTile];
+  __shared__ uint32_t gbase[256];      // global position of each digit's first item of this tile
+  __shared__ uint32_t lbase[256];      // local position of each digit's first item
+  __shared__ uint32_t run[256];        // items of each digit placed so far
+  __shared__ uint32_t wcnt[W][256];    // this round's count of each digit per wave
+  __shared__ uint32_t lds[W];
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
-  run[t] = off[t * nb + blockIdx.x];
-  const uint32_t b0 = blockIdx.x * kTile;
-  for (uint32_t j = 0; j < kTile / 256u; ++j) {
-    wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0u;
+  const uint32_t b0 = blockIdx.x * kRsTile;
+  const uint32_t m = n - b0 < kRsTile ? n - b0 : kRsTile;     // items of this tile
+  uint32_t key[kRsRounds];
+  V val[kRsRounds];
+  if (t < 256u) run[t] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kRsRounds; ++j) {
+    const uint32_t i = j * kRsThreads + t;
+    key[j] = i < m ? kin[b0 + i] : 0u;
+    if (i < m) {
+      val[j] = vin[b0 + i];
+      atomicAdd(&run[(key[j] >> shift) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  // digit scans over the whole block (threads from 256 on carry zeros): local starts of the
+  // digits in the tile, global starts
+  {
+    uint32_t total;
+    const uint32_t cnt = t < 256u ? run[t] : 0u;
+    const uint32_t lb = block_excl_scan<kRsThreads>(cnt, lds, total);
+    const uint32_t gb = block_excl_scan<kRsThreads>(t < 256u ? dtot[t] : 0u, lds, total);
+    if (t < 256u) {
+      lbase[t] = lb;
+      gbase[t] = gb + off[t * nb + blockIdx.x];
+      run[t] = 0u;
+    }
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < kRsRounds; ++j) {
+    if (t < 256u)
+#pragma unroll
+      for (uint32_t q = 0; q < W; ++q) wcnt[q][t] = 0u;
     __syncthreads();
-    const uint32_t i = b0 + j * 256u + t;
-    const bool on = i < n;
-    const uint32_t k = on ? kin[i] : 0u;
-    const uint32_t d = (k >> shift) & 255u;
+    const uint32_t i = j * kRsThreads + t;
+    const bool on = i < m;
+    const uint32_t d = (key[j] >> shift) & 255u;
     uint64_t same = __ballot(on);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const uint64_t m = __ballot((d >> b) & 1u);
-      same &= ((d >> b) & 1u) ? m : ~m;
+      const uint64_t mb = __ballot((d >> b) & 1u);
+      same &= ((d >> b) & 1u) ? mb : ~mb;
     }
     const uint32_t rank = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
     if (on && rank == 0u) wcnt[w][d] = (uint32_t)__popcll(same);
     __syncthreads();
-    uint32_t before = run[d];
-    for (uint32_t q = 0; q < w; ++q) before += wcnt[q][d];
     if (on) {
-      kout[before + rank] = k;
-      vout[before + rank] = vin[i];
+      uint32_t at = lbase[d] + run[d] + rank;
+      for (uint32_t q = 0; q < w; ++q) at += wcnt[q][d];
+      sk[at] = key[j];
+      sv[at] = val[j];
     }
     __syncthreads();
-    run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    if (t < 256u) {
+      uint32_t add = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < W; ++q) add += wcnt[q][t];
+      run[t] += add;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kRsRounds; ++j) {
+    const uint32_t i = j * kRsThreads + t;
+    if (i < m) {
+      const uint32_t k = sk[i];
+      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t g = gbase[d] + (i - lbase[d]);
+      kout[g] = k;
+      vout[g] = sv[i];
+    }
   }
 }
 
@@ -388,11 +479,13 @@ static hipError_t radix_sort(uint32_t* keys[2], V* vals[2], uint32_t n, uint32_t
                              hipStream_t st, int& which) {
   which = 0;
   if (n == 0) return hipSuccess;
-  const uint32_t nb = (n + kTile - 1u) / kTile;
+  const uint32_t nb = (n + kRsTile - 1u) / kRsTile;
+  uint32_t* dtot = hist + 256u * nb;
   for (uint32_t shift = 0; shift < bits; shift += 8u) {
-    k_rs_hist<<<nb, 256, 0, st>>>(keys[which], n, shift, nb, hist);
-    k_scan_counts<<<1, 1024, 0, st>>>(hist, 256u * nb);
-    k_rs_scatter<V><<<nb, 256, 0, st>>>(keys[which], vals[which], keys[which ^ 1], vals[which ^ 1], n, shift, nb, hist);
+    k_rs_hist<<<nb, kRsThreads, 0, st>>>(keys[which], n, shift, nb, hist);
+    k_rs_digit_scan<<<256, 256, 0, st>>>(hist, nb, dtot);
+    k_rs_scatter<V><<<nb, kRsThreads, 0, st>>>(keys[which], vals[which], keys[which ^ 1], vals[which ^ 1], n, shift, nb,
+                                               hist, dtot);
     which ^= 1;
   }
   return hipGetLastError();
@@ -479,13 +572,60 @@ __device__ inline void atomic_max_abs(float* p, float v) {
   atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
 }
 
+// ---- the step's encoding, forward and backward: one thread per (level, sample), lanes of a
+// wave on 64 consecutive samples of one level (neighbouring samples share coarse entries) ----
+// sample i of the step is row off + stride * i of the batch array
+__global__ __launch_bounds__(256) void k_encode_fwd(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
+                                                    uint32_t stride, const __half* grid_h, float2* enc) {
+  const uint32_t q = blockIdx.x * 256u + threadIdx.x;
+  if (q >= lp.L * B) return;
+  const uint32_t l = q / B, i = q % B;
+  const float4 pos = batch[3 * (size_t)(off + stride * i)];
+  float x0, x1, x2;
+  norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
+  Corners cn;
+  level_corners(lp, (int)l, x0, x1, x2, cn);
+  const __half2* tab = reinterpret_cast<const __half2*>(grid_h) + (size_t)l * lp.T;
+  float2 v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = __half22float2(tab[cn.idx[c]]);
+  float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    f0 = f0 + cn.w[c] * v[c].x;
+    f1 = f1 + cn.w[c] * v[c].y;
+  }
+  enc[(size_t)i * kMaxLevels + l] = make_float2(f0, f1);
+}
+
+// the encoding gradient as (level * T + entry, w * dX) pairs at position (l * 8 + c) * B + i:
+// no float atomics; the pairs are sorted and summed per entry in a fixed order
+__global__ __launch_bounds__(256) void k_encode_bwd(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
+                                                    uint32_t stride, const float* dX, uint32_t log2T, uint32_t* pkey,
+                                                    float2* pval) {
+  const uint32_t q = blockIdx.x * 256u + threadIdx.x;
+  if (q >= lp.L * B) return;
+  const uint32_t l = q / B, i = q % B;
+  const float4 pos = batch[3 * (size_t)(off + stride * i)];
+  float x0, x1, x2;
+  norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
+  Corners cn;
+  level_corners(lp, (int)l, x0, x1, x2, cn);
+  const float2 d = *reinterpret_cast<const float2*>(dX + (size_t)i * 32u + 2u * l);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const size_t at = ((size_t)l * 8u + (uint32_t)c) * B + i;
+    pkey[at] = (l << log2T) | cn.idx[c];
+    pval[at] = make_float2(cn.w[c] * d.x, cn.w[c] * d.y);
+  }
+}
+
 // sample i of the step is row off + stride * i of the batch array.  The encoding gradient is
 // written as (entry key, contribution) pairs at fixed positions (group, level, corner,
 // sample), to be sorted and summed per entry: no float atomics, so the step is deterministic.
 __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
-                                              uint32_t stride, const __half* grid_h, uint32_t* pkey, float2* pval,
-                                              uint32_t log2T, const __bf16* wb, float loss_scale, float* part,
-                                              float* lpart, float* acc, float* amax) {
+                                              uint32_t stride, const float2* enc, float* dXg, const __bf16* wb,
+                                              float loss_scale, float* part, float* lpart, float* acc, float* amax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TrainSmem& S = *reinterpret_cast<TrainSmem*>(smem_raw);
   const int lane = threadIdx.x;
@@ -510,26 +650,18 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
   float ax = 0.f, ah1 = 0.f, ah2 = 0.f;
   const int s = lane & 31, half_ = lane >> 5;
   for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
-    const uint32_t row = off + stride * (32 * g + s);
-    // -- encoding: lane = (sample s, levels 8*half_ .. 8*half_+7)
-    const float4 pos = batch[3 * row];
+    const uint32_t si = 32 * g + s;          // sample of the step
+    const uint32_t row = off + stride * si;
+    // -- encoding (k_encode_fwd): lane = (sample s, levels 8*half_ .. 8*half_+7)
     const float4 nrm = batch[3 * row + 1];
     if (lane < 32) S.tgt[s] = batch[3 * row + 2];
-    float x0, x1, x2;
-    norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
     for (int k = 0; k < 8; ++k) {
       const int l = 8 * half_ + k;
       float f0 = 0.f, f1 = 0.f;
       if (l < (int)lp.L) {
-        Corners cn;
-        level_corners(lp, l, x0, x1, x2, cn);
-        const __half2* tab = reinterpret_cast<const __half2*>(grid_h) + (size_t)l * lp.T;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const float2 v = __half22float2(tab[cn.idx[c]]);
-          f0 = f0 + cn.w[c] * v.x;
-          f1 = f1 + cn.w[c] * v.y;
-        }
+        const float2 e = enc[(size_t)si * kMaxLevels + l];
+        f0 = e.x;
+        f1 = e.y;
       }
       const __bf16 b0 = to_bf16(f0), b1 = to_bf16(f1);
       S.X[s * kLd64 + 2 * l] = b0;
@@ -669,20 +801,12 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
         }
       }
     __syncthreads();
-    // -- encoding backward: pair (level * T + entry, w * dX) of every sample, level and corner,
-    // at position ((g * L + l) * 8 + c) * 32 + s (lanes of a half write 32 consecutive pairs)
-    for (int k = 0; k < 8; ++k) {
-      const int l = 8 * half_ + k;
-      if (l >= (int)lp.L) break;
-      Corners cn;
-      level_corners(lp, l, x0, x1, x2, cn);
-      const float d0 = S.dX[s * 33 + 2 * l], d1 = S.dX[s * 33 + 2 * l + 1];
-      const size_t base = ((size_t)g * lp.L + (uint32_t)l) * 8u * 32u + (uint32_t)s;
+    // -- the encoding columns of dX go to k_encode_bwd
+    if (lane < 32) {
+      const float* src = S.dX + s * 33;
+      float4* dst = reinterpret_cast<float4*>(dXg + (size_t)si * 32u);
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        pkey[base + 32u * c] = ((uint32_t)l << log2T) | cn.idx[c];
-        pval[base + 32u * c] = make_float2(cn.w[c] * d0, cn.w[c] * d1);
-      }
+      for (int c = 0; c < 8; ++c) dst[c] = make_float4(src[4 * c], src[4 * c + 1], src[4 * c + 2], src[4 * c + 3]);
     }
     __syncthreads();
   }
@@ -724,11 +848,12 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
 __global__ __launch_bounds__(1024) void k_reduce_mlp(const float* part, const float* lpart, uint32_t waves, float* g,
                                                      float* acc) {
   __shared__ float red[16][64];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    // the step's loss: per-wave partials summed in wave order
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    // the step's loss: lane j sums partials j, j + 64, ... in order, then a fixed butterfly
     float l = 0.0f;
-    for (uint32_t w = 0; w < waves; ++w) l += lpart[w];
-    acc[0] = l;
+    for (uint32_t w = threadIdx.x; w < waves; w += 64u) l += lpart[w];
+    for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
+    if (threadIdx.x == 0) acc[0] = l;
   }
   const int l = threadIdx.x & 63, slice = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + l;
@@ -763,131 +888,189 @@ __device__ inline void adam_lazy(float graw, float& p, float& m, float& v, const
 }
 
 // ---- per-entry sums of the sorted gradient pairs, then the grid step --------------------
-// Tiles of kTile sorted pairs, thread t of a tile holding pairs 16t..16t+15.  Each thread sums
-// its pairs in order, restarting where the key changes; a segmented scan over the threads
-// (fixed association) extends every pair's sum back to the tile start or to its entry's first
-// pair.  An entry whose pairs began in an earlier tile adds the tail sums of the earlier
-// tiles, nearest first, which the first pass (MODE 0) records.  Every order is fixed, so the
-// sums, and the step, are deterministic.  MODE 1: lazy Adam on the entry's two parameters
-// (skipped when the step's gradients are non-finite); MODE 2: the dense gradient (a
-// gradient-only step).
+// Tiles of kGredTile sorted pairs, thread t of a tile holding pairs 4t..4t+3.  Each thread
+// sums its pairs in order, restarting where the key changes; a segmented scan over the
+// threads (fixed association) extends every pair's sum back to the tile start or to its
+// entry's first pair.  MODE 0 records each tile's last partial sum and whether its entry began
+// inside the tile; k_gred_carry turns those into each tile's carry-in (a segmented scan over
+// the tiles); MODE 1 adds the carry to entries that began in an earlier tile and, at each
+// entry's last pair, takes the lazy Adam step of its two parameters (none when the step's
+// gradients are non-finite); MODE 2 writes the dense gradient instead (a gradient-only step).
+// Every order is fixed, so the sums, and the step, are deterministic.
+constexpr uint32_t kGredItems = 4, kGredTile = 256 * kGredItems;
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2* val, uint32_t n, uint32_t* tail_key,
-                                              float2* tail_sum, uint32_t* tail_in, float* p, __half* ph, float* m,
-                                              float* v, float* gdense, AdamArgs a, const float* acc) {
-  __shared__ uint32_t sk[kTile + 1];
-  __shared__ float2 sv[kTile];
+__global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2* val, uint32_t n, float2* tail_sum,
+                                              uint32_t* tail_in, const float2* carry_in, float* gstate, __half* ph,
+                                              float* gdense, AdamArgs a, const float* acc) {
   __shared__ float2 cs[2][256];
   __shared__ uint32_t cf[2][256];
   const uint32_t t = threadIdx.x;
-  const uint32_t b0 = blockIdx.x * kTile;
-  for (uint32_t j = 0; j < kTile / 256u; ++j) {
-    const uint32_t i = b0 + j * 256u + t;
-    sk[j * 256u + t] = i < n ? key[i] : 0xFFFFFFFFu;
-    sv[j * 256u + t] = i < n ? val[i] : make_float2(0.0f, 0.0f);
-  }
-  if (t == 0) sk[kTile] = b0 + kTile < n ? key[b0 + kTile] : 0xFFFFFFFFu;   // first key of the next tile
-  const uint32_t kbefore = b0 > 0 ? key[b0 - 1] : 0xFFFFFFFFu;              // keys are < 2^28: never equal
-  __syncthreads();
-  float2 loc[16];
-  uint32_t headbits = 0;     // bit j: a key change at or before pair j inside this thread's chunk
-                             // (loc[j] then sums from the last of them, with no carry)
-  float sx = 0.0f, sy = 0.0f;
-  uint32_t kp = t == 0 ? kbefore : sk[16u * t - 1u];
+  const uint32_t i0 = blockIdx.x * kGredTile + kGredItems * t;
+  uint32_t k[kGredItems];
+  float2 w[kGredItems];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const uint32_t k = sk[16u * t + j];
-    if (k != kp) {
+  for (uint32_t j = 0; j < kGredItems; ++j) {
+    const bool on = i0 + j < n;
+    k[j] = on ? key[i0 + j] : 0xFFFFFFFFu;          // keys are < 2^28: never equal to padding
+    w[j] = on ? val[i0 + j] : make_float2(0.0f, 0.0f);
+  }
+  const uint32_t kprev = i0 > 0 && i0 - 1 < n ? key[i0 - 1] : 0xFFFFFFFFu;
+  const uint32_t knext = i0 + kGredItems < n ? key[i0 + kGredItems] : 0xFFFFFFFFu;
+  // an entry's last pair is known from the keys alone: its Adam state is loaded now, so that
+  // the loads overlap the scan below
+  bool last[kGredItems];
+  float4 pm[kGredItems], vz[kGredItems];
+  float4* gs = reinterpret_cast<float4*>(gstate);
+#pragma unroll
+  for (uint32_t j = 0; j < kGredItems; ++j) {
+    const uint32_t kn = j + 1 < kGredItems ? k[j + 1] : knext;
+    last[j] = i0 + j < n && kn != k[j];
+    if (MODE == 1 && last[j]) {
+      pm[j] = gs[2u * (size_t)k[j]];
+      vz[j] = gs[2u * (size_t)k[j] + 1u];
+    }
+  }
+  // bit j: the pair's key differs from the one before it (a key change at or before pair j
+  // inside this thread's chunk once OR-ed forward)
+  uint32_t heads = 0;
+  float2 loc[kGredItems];
+  float sx = 0.0f, sy = 0.0f;
+  uint32_t kp = kprev;
+#pragma unroll
+  for (uint32_t j = 0; j < kGredItems; ++j) {
+    if (k[j] != kp) {
       sx = 0.0f;
       sy = 0.0f;
-      headbits |= 0xFFFFu << j;
+      heads |= 0xFu << j;
     }
-    const float2 w = sv[16u * t + j];
-    sx = sx + w.x;
-    sy = sy + w.y;
+    sx = sx + w[j].x;
+    sy = sy + w[j].y;
     loc[j] = make_float2(sx, sy);
-    kp = k;
+    kp = k[j];
   }
-  // inclusive segmented scan over threads of (holds a key change, sum after its last change)
   int cur = 0;
   cs[0][t] = make_float2(sx, sy);
-  cf[0][t] = headbits ? 1u : 0u;
+  cf[0][t] = heads ? 1u : 0u;
   __syncthreads();
   for (uint32_t d = 1; d < 256u; d <<= 1) {
-    float2 sv2 = cs[cur][t];
+    float2 s2 = cs[cur][t];
     uint32_t f = cf[cur][t];
     if (t >= d && !f) {
       const float2 o = cs[cur][t - d];
-      sv2 = make_float2(o.x + sv2.x, o.y + sv2.y);
+      s2 = make_float2(o.x + s2.x, o.y + s2.y);
       f = cf[cur][t - d];
     }
-    cs[cur ^ 1][t] = sv2;
+    cs[cur ^ 1][t] = s2;
     cf[cur ^ 1][t] = f;
     cur ^= 1;
     __syncthreads();
   }
   const float2 carry = t > 0 ? cs[cur][t - 1] : make_float2(0.0f, 0.0f);
   const bool carry_in_tile = t > 0 && cf[cur][t - 1] != 0u;
+  if (MODE == 0) {
+    if (t == 255u) {
+      const uint32_t j = kGredItems - 1;
+      const bool own = (heads >> j) & 1u;
+      tail_sum[blockIdx.x] = own ? loc[j] : make_float2(carry.x + loc[j].x, carry.y + loc[j].y);
+      tail_in[blockIdx.x] = (own || carry_in_tile) ? 1u : 0u;
+    }
+    return;
+  }
+  const float2 cin = carry_in[blockIdx.x];
   const bool skip = MODE == 1 && acc[1] != 0.0f;
+  float gx[kGredItems], gy[kGredItems];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const uint32_t idx = 16u * t + j;
-    const bool own = (headbits >> j) & 1u;
-    const float2 sum = own ? loc[j] : make_float2(carry.x + loc[j].x, carry.y + loc[j].y);
-    const bool inside = own || carry_in_tile;
-    if (MODE == 0) {
-      if (idx == kTile - 1u) {
-        tail_key[blockIdx.x] = sk[idx];
-        tail_sum[blockIdx.x] = sum;
-        tail_in[blockIdx.x] = inside ? 1u : 0u;
-      }
-      continue;
+  for (uint32_t j = 0; j < kGredItems; ++j) {
+    const bool own = (heads >> j) & 1u;
+    float2 sum = own ? loc[j] : make_float2(carry.x + loc[j].x, carry.y + loc[j].y);
+    if (!(own || carry_in_tile)) sum = make_float2(sum.x + cin.x, sum.y + cin.y);
+    gx[j] = sum.x;
+    gy[j] = sum.y;
+  }
+  if (MODE == 2) {
+#pragma unroll
+    for (uint32_t j = 0; j < kGredItems; ++j)
+      if (last[j]) *reinterpret_cast<float2*>(gdense + 2u * (size_t)k[j]) = make_float2(gx[j], gy[j]);
+    return;
+  }
+  if (skip) return;
+#pragma unroll
+  for (uint32_t j = 0; j < kGredItems; ++j)
+    if (last[j]) {
+      adam_lazy(gx[j], pm[j].x, pm[j].z, vz[j].x, a);
+      adam_lazy(gy[j], pm[j].y, pm[j].w, vz[j].y, a);
+      gs[2u * (size_t)k[j]] = pm[j];
+      gs[2u * (size_t)k[j] + 1u] = vz[j];
+      *reinterpret_cast<__half2*>(ph + 2u * (size_t)k[j]) = __halves2half2(__float2half(pm[j].x), __float2half(pm[j].y));
     }
-    const uint32_t k = sk[idx];
-    if (b0 + idx >= n || sk[idx + 1] == k) continue;    // not the last pair of its entry
-    float gx = sum.x, gy = sum.y;
-    if (!inside)
-      for (uint32_t bb = blockIdx.x; bb-- > 0;) {
-        const float2 ts = tail_sum[bb];
-        gx = gx + ts.x;
-        gy = gy + ts.y;
-        if (tail_in[bb]) break;
+}
+
+// carry-in of every tile: the sum of the pairs, in earlier tiles, of the entry that is open at
+// the tile's start (segmented inclusive scan of the tile tails, restarting at tiles whose last
+// entry began inside them); one block, fixed association
+__global__ __launch_bounds__(1024) void k_gred_carry(const float2* tail_sum, const uint32_t* tail_in, uint32_t nt,
+                                                     float2* carry_in) {
+  __shared__ float2 cs[2][1024];
+  __shared__ uint32_t cf[2][1024];
+  const uint32_t t = threadIdx.x;
+  float2 run = make_float2(0.0f, 0.0f);   // inclusive value of the previous chunk's last tile
+  for (uint32_t c = 0; c < nt; c += 1024u) {
+    const uint32_t b = c + t;
+    float2 s2 = b < nt ? tail_sum[b] : make_float2(0.0f, 0.0f);
+    uint32_t f = b < nt ? tail_in[b] : 1u;
+    int cur = 0;
+    cs[0][t] = s2;
+    cf[0][t] = f;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024u; d <<= 1) {
+      float2 x = cs[cur][t];
+      uint32_t g = cf[cur][t];
+      if (t >= d && !g) {
+        const float2 o = cs[cur][t - d];
+        x = make_float2(o.x + x.x, o.y + x.y);
+        g = cf[cur][t - d];
       }
-    const size_t q = 2u * (size_t)k;
-    if (MODE == 2) {
-      gdense[q] = gx;
-      gdense[q + 1] = gy;
-    } else if (!skip) {
-      float2 pp = *reinterpret_cast<float2*>(p + q);
-      float2 mm = *reinterpret_cast<float2*>(m + q);
-      float2 vv = *reinterpret_cast<float2*>(v + q);
-      adam_lazy(gx, pp.x, mm.x, vv.x, a);
-      adam_lazy(gy, pp.y, mm.y, vv.y, a);
-      *reinterpret_cast<float2*>(p + q) = pp;
-      *reinterpret_cast<float2*>(m + q) = mm;
-      *reinterpret_cast<float2*>(v + q) = vv;
-      *reinterpret_cast<__half2*>(ph + q) = __halves2half2(__float2half(pp.x), __float2half(pp.y));
+      cs[cur ^ 1][t] = x;
+      cf[cur ^ 1][t] = g;
+      cur ^= 1;
+      __syncthreads();
     }
+    // tile b's carry-in = inclusive value of tile b - 1 (chained to the previous chunk)
+    float2 prev;
+    if (t == 0) {
+      prev = run;
+    } else {
+      prev = cs[cur][t - 1];
+      if (!cf[cur][t - 1]) prev = make_float2(run.x + prev.x, run.y + prev.y);
+    }
+    if (b < nt) carry_in[b] = prev;
+    float2 endv = cs[cur][1023];
+    const uint32_t endf = cf[cur][1023];
+    __syncthreads();
+    if (!endf) endv = make_float2(run.x + endv.x, run.y + endv.y);
+    run = endv;
   }
 }
 
 // end of an applied step (one block of 1024 threads): Adam on the MLP weights, their bf16 and
 // e4m3 working copies, the e4m3 activation scales of the step's batch, the step's statistics
-__global__ __launch_bounds__(1024) void k_mlp_step(float* p, const float* g, float* m, float* v, AdamArgs a,
-                                                   float* acc, __bf16* wb, uint8_t* w8, float* scales,
+// Adam on the MLP weights (dense), one parameter per thread
+__global__ __launch_bounds__(256) void k_mlp_adam(float* p, const float* g, float* m, float* v, AdamArgs a,
+                                                  const float* acc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= kMlpParams || acc[1] != 0.0f) return;
+  const float gi = g[i] * a.inv_scale;
+  const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+  const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] = p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+}
+
+__global__ __launch_bounds__(1024) void k_mlp_step(float* p, float* acc, __bf16* wb, uint8_t* w8, float* scales,
                                                    unsigned long long* stats) {
   const bool skip = acc[1] != 0.0f;
-  if (!skip) {
-    for (int i = threadIdx.x; i < kMlpParams; i += 1024) {
-      const float gi = g[i] * a.inv_scale;
-      const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
-      const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
-      m[i] = mi;
-      v[i] = vi;
-      p[i] = p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
-    }
-  }
-  __syncthreads();
   mlp_copies(p, wb, w8, scales);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
@@ -899,9 +1082,9 @@ __global__ __launch_bounds__(1024) void k_mlp_step(float* p, const float* g, flo
   }
 }
 
-__global__ void k_learned_copy_half(const float* p, __half* h, uint64_t n) {
+__global__ void k_learned_copy_half(const float* gstate, __half* h, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) h[i] = __float2half(p[i]);
+  if (i < n) h[i] = __float2half(gstate[8u * (i >> 1) + (i & 1u)]);
 }
 
 __global__ void k_zero_f32(float* p, uint64_t n) {
@@ -950,21 +1133,34 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
   float feat[64];
 #pragma unroll
   for (int c = 0; c < 64; ++c) feat[c] = 0.0f;
+  // levels in groups of 4: the group's 32 corner loads are issued together (levels past L
+  // load level L - 1's entries and are dropped), then summed per level in corner order
 #pragma unroll
-  for (int l = 0; l < kMaxLevels; ++l) {
-    if (l < (int)lp.L) {
-      Corners cn;
-      level_corners(lp, l, x0, x1, x2, cn);
+  for (int gl = 0; gl < kMaxLevels; gl += 4) {
+    if (gl >= (int)lp.L) break;
+    Corners cn[4];
+    __half2 hv[4][8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int l = min(gl + q, (int)lp.L - 1);
+      level_corners(lp, l, x0, x1, x2, cn[q]);
       const __half2* tab = reinterpret_cast<const __half2*>(grid_h) + (size_t)l * lp.T;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) hv[q][c] = tab[cn[q].idx[c]];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
       float f0 = 0.f, f1 = 0.f;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const float2 v = __half22float2(tab[cn.idx[c]]);
-        f0 = f0 + cn.w[c] * v.x;
-        f1 = f1 + cn.w[c] * v.y;
+        const float2 v = __half22float2(hv[q][c]);
+        f0 = f0 + cn[q].w[c] * v.x;
+        f1 = f1 + cn[q].w[c] * v.y;
       }
-      feat[2 * l] = f0;
-      feat[2 * l + 1] = f1;
+      if (gl + q < (int)lp.L) {
+        feat[2 * (gl + q)] = f0;
+        feat[2 * (gl + q) + 1] = f1;
+      }
     }
   }
   feat[32] = (n4.x + 1.0f) * 0.5f;
@@ -1179,11 +1375,9 @@ hipError_t learned_create(gi_context* c) {
   const size_t PR = (size_t)c->P * c->R;
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-  A(lalloc(&s->grid, s->grid_n));
+  A(lalloc(&s->gstate, 4 * (size_t)s->grid_n));
   A(lalloc(&s->grid_h, s->grid_n));
   A(lalloc(&s->grid_g, s->grid_n));
-  A(lalloc(&s->grid_m, s->grid_n));
-  A(lalloc(&s->grid_v, s->grid_n));
   A(lalloc(&s->mlp, kMlpParams));
   A(lalloc(&s->mlp_g, kMlpParams));
   A(lalloc(&s->mlp_m, kMlpParams));
@@ -1218,13 +1412,15 @@ hipError_t learned_create(gi_context* c) {
     A(lalloc(&s->pkeys[k], s->n_pairs));
     A(lalloc(&s->pvals[k], s->n_pairs));
   }
-  const size_t nb_max = (std::max(rows, s->n_pairs) + kTile - 1) / kTile;
-  A(lalloc(&s->rs_hist, 256 * nb_max + 1));
-  const size_t ntiles = (s->n_pairs + kTile - 1) / kTile;
-  A(lalloc(&s->tail_key, ntiles));
+  const size_t nb_max = (std::max(rows, s->n_pairs) + kRsTile - 1) / kRsTile;
+  A(lalloc(&s->rs_hist, 256 * nb_max + 256));
+  const size_t ntiles = (s->n_pairs + kGredTile - 1) / kGredTile;
   A(lalloc(&s->tail_sum, ntiles));
   A(lalloc(&s->tail_in, ntiles));
+  A(lalloc(&s->tail_carry, ntiles));
   A(lalloc(&s->lpart, s->train_waves));
+  A(lalloc(&s->enc, (size_t)s->B * kMaxLevels));
+  A(lalloc(&s->dX, (size_t)s->B * 32u));
   A(lalloc(&s->judge_part, (size_t)c->hit_blocks_per_stripe * kStatStripes));
   A(lalloc(&s->lmlp, PR));
   A(lalloc(&s->acc, 16));
@@ -1232,8 +1428,7 @@ hipError_t learned_create(gi_context* c) {
   A(hipFuncSetAttribute(reinterpret_cast<const void*>(k_train), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)sizeof(TrainSmem)));
   A(hipMemset(s->grid_g, 0, 4 * (size_t)s->grid_n));
-  A(hipMemset(s->grid_m, 0, 4 * (size_t)s->grid_n));
-  A(hipMemset(s->grid_v, 0, 4 * (size_t)s->grid_n));
+  A(hipMemset(s->gstate, 0, 16 * (size_t)s->grid_n));
   A(hipMemset(s->mlp_m, 0, 4 * kMlpParams));
   A(hipMemset(s->mlp_v, 0, 4 * kMlpParams));
   A(hipMemset(s->mlp_g, 0, 4 * kMlpParams));
@@ -1243,7 +1438,7 @@ hipError_t learned_create(gi_context* c) {
   A(hipMemset(s->lmlp, 0, 16 * PR));
   if (e != hipSuccess) return e;
   const uint64_t n = std::max<uint64_t>(s->grid_n, kMlpParams);
-  k_learned_init<<<nblk(n, 256), 256>>>(s->grid, s->grid_h, lp.L, lp.T, s->mlp, g.seed);
+  k_learned_init<<<nblk(n, 256), 256>>>(s->gstate, s->grid_h, lp.L, lp.T, s->mlp, g.seed);
   k_mlp_copies<<<1, 1024>>>(s->mlp, s->wb, s->w8, s->scales);
   {
     // unit activation scales until the first training step measures them
@@ -1258,11 +1453,11 @@ hipError_t learned_create(gi_context* c) {
 void learned_destroy(gi_context* c) {
   LearnedState* s = c->learned;
   if (!s) return;
-  void* ptrs[] = {s->grid, s->grid_h, s->grid_g, s->grid_m, s->grid_v, s->mlp, s->mlp_g, s->mlp_m, s->mlp_v,
+  void* ptrs[] = {s->gstate, s->grid_h, s->grid_g, s->mlp, s->mlp_g, s->mlp_m, s->mlp_v,
                   s->mlp_part, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->tflag, s->clist,
                   s->ccount, s->batch, s->batch_raw, s->bkeys[0], s->bkeys[1], s->bvals[0], s->bvals[1],
-                  s->pkeys[0], s->pkeys[1], s->pvals[0], s->pvals[1], s->rs_hist, s->tail_key, s->tail_sum,
-                  s->tail_in, s->lpart, s->judge_part, s->lmlp, s->acc};
+                  s->pkeys[0], s->pkeys[1], s->pvals[0], s->pvals[1], s->rs_hist, s->tail_sum, s->tail_in,
+                  s->tail_carry, s->lpart, s->enc, s->dX, s->judge_part, s->lmlp, s->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -1297,10 +1492,13 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   while ((1u << log2T) < s->lp.T) ++log2T;
   hipEvent_t ev;
   timer_begin(c, "learned_train", st, &ev);
+  const uint32_t nq = s->lp.L * s->B;
+  k_encode_fwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->enc);
   // every launched wave writes its whole partial, so the partials need no clearing
-  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->pkeys[0],
-                                                s->pvals[0], log2T, s->wb, S, s->mlp_part, s->lpart, s->acc,
-                                                s->scales + 3);
+  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->enc, s->dX, s->wb, S,
+                                                s->mlp_part, s->lpart, s->acc, s->scales + 3);
+  k_encode_bwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->dX, log2T, s->pkeys[0],
+                                              s->pvals[0]);
   timer_end(c, "learned_train", st, ev);
   k_reduce_mlp<<<nblk(kMlpParams, 64), 1024, 0, st>>>(s->mlp_part, s->lpart, waves, s->mlp_g, s->acc);
   // the encoding gradient: pairs sorted by entry, summed per entry in a fixed order
@@ -1310,7 +1508,7 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   hipError_t e = radix_sort<float2>(s->pkeys, s->pvals, n, s->key_bits, s->rs_hist, st, which);
   timer_end(c, "learned_grad_sort", st, ev);
   if (e != hipSuccess) return e;
-  const uint32_t nt = nblk(n, kTile);
+  const uint32_t nt = nblk(n, kGredTile);
   AdamArgs ag{};
   if (apply) {
     s->step += 1;
@@ -1323,22 +1521,23 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
     ag.eps = 1e-15f;
   }
   timer_begin(c, "learned_grad_apply", st, &ev);
-  k_gred<0><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_key, s->tail_sum, s->tail_in, s->grid,
-                                s->grid_h, s->grid_m, s->grid_v, s->grid_g, ag, s->acc);
+  k_gred<0><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->tail_carry,
+                                s->gstate, s->grid_h, s->grid_g, ag, s->acc);
+  k_gred_carry<<<1, 1024, 0, st>>>(s->tail_sum, s->tail_in, nt, s->tail_carry);
   if (apply)
-    k_gred<1><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_key, s->tail_sum, s->tail_in, s->grid,
-                                  s->grid_h, s->grid_m, s->grid_v, s->grid_g, ag, s->acc);
+    k_gred<1><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->tail_carry,
+                                  s->gstate, s->grid_h, s->grid_g, ag, s->acc);
   else
-    k_gred<2><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_key, s->tail_sum, s->tail_in, s->grid,
-                                  s->grid_h, s->grid_m, s->grid_v, s->grid_g, ag, s->acc);
+    k_gred<2><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->tail_carry,
+                                  s->gstate, s->grid_h, s->grid_g, ag, s->acc);
   timer_end(c, "learned_grad_apply", st, ev);
   if (apply) {
     AdamArgs am = ag;
     am.lr = c->cfg.mlp_lr_mlp;
     am.eps = 1e-8f;
     timer_begin(c, "learned_adam", st, &ev);
-    k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc, s->wb, s->w8, s->scales,
-                                   c->d_stats);
+    k_mlp_adam<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc);
+    k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->acc, s->wb, s->w8, s->scales, c->d_stats);
     timer_end(c, "learned_adam", st, ev);
   } else {
     s->grad_dirty = true;
@@ -1440,10 +1639,23 @@ hipError_t learned_save(gi_context* c, void* blob) {
   std::memcpy(p, hdr, 64);
   p += 64;
   const size_t G = 4 * (size_t)s->grid_n, M = 4 * (size_t)kMlpParams;
-  const void* src[8] = {s->grid, s->mlp, s->grid_g, s->mlp_g, s->grid_m, s->grid_v, s->mlp_m, s->mlp_v};
+  // the interleaved grid state goes out as three arrays (values, first and second moments)
+  std::vector<float> gs(4 * (size_t)s->grid_n);
+  e = hipMemcpy(gs.data(), s->gstate, 16 * (size_t)s->grid_n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  std::vector<float> gp(s->grid_n), gm(s->grid_n), gv(s->grid_n);
+  for (size_t i = 0; i < s->grid_n; ++i) {
+    const size_t b = 8 * (i >> 1) + (i & 1);
+    gp[i] = gs[b];
+    gm[i] = gs[b + 2];
+    gv[i] = gs[b + 4];
+  }
+  const void* src[8] = {gp.data(), s->mlp, s->grid_g, s->mlp_g, gm.data(), gv.data(), s->mlp_m, s->mlp_v};
+  const bool dev[8] = {false, true, true, true, false, false, true, true};
   const size_t sz[8] = {G, M, G, M, G, G, M, M};
   for (int k = 0; k < 8 && e == hipSuccess; ++k) {
-    e = hipMemcpy(p, src[k], sz[k], hipMemcpyDeviceToHost);
+    if (dev[k]) e = hipMemcpy(p, src[k], sz[k], hipMemcpyDeviceToHost);
+    else std::memcpy(p, src[k], sz[k]);
     p += sz[k];
   }
   return e;
@@ -1460,16 +1672,28 @@ hipError_t learned_load(gi_context* c, const void* blob) {
   s->step = (int)hdr[4];
   p += 64;
   const size_t G = 4 * (size_t)s->grid_n, M = 4 * (size_t)kMlpParams;
-  void* dst[8] = {s->grid, s->mlp, s->grid_g, s->mlp_g, s->grid_m, s->grid_v, s->mlp_m, s->mlp_v};
+  std::vector<float> gp(s->grid_n), gm(s->grid_n), gv(s->grid_n);
+  void* dst[8] = {gp.data(), s->mlp, s->grid_g, s->mlp_g, gm.data(), gv.data(), s->mlp_m, s->mlp_v};
+  const bool dev[8] = {false, true, true, true, false, false, true, true};
   const size_t sz[8] = {G, M, G, M, G, G, M, M};
   for (int k = 0; k < 8 && e == hipSuccess; ++k) {
-    e = hipMemcpy(dst[k], p, sz[k], hipMemcpyHostToDevice);
+    if (dev[k]) e = hipMemcpy(dst[k], p, sz[k], hipMemcpyHostToDevice);
+    else std::memcpy(dst[k], p, sz[k]);
     p += sz[k];
   }
   if (e != hipSuccess) return e;
+  std::vector<float> gs(4 * (size_t)s->grid_n, 0.0f);
+  for (size_t i = 0; i < s->grid_n; ++i) {
+    const size_t b = 8 * (i >> 1) + (i & 1);
+    gs[b] = gp[i];
+    gs[b + 2] = gm[i];
+    gs[b + 4] = gv[i];
+  }
+  e = hipMemcpy(s->gstate, gs.data(), 16 * (size_t)s->grid_n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
   s->grad_dirty = true;   // the restored gradient is the saved state's, not a clean buffer
   // rebuild the working copies
-  k_learned_copy_half<<<nblk(s->grid_n, 256), 256>>>(s->grid, s->grid_h, s->grid_n);
+  k_learned_copy_half<<<nblk(s->grid_n, 256), 256>>>(s->gstate, s->grid_h, s->grid_n);
   k_mlp_copies<<<1, 1024>>>(s->mlp, s->wb, s->w8, s->scales);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipDeviceSynchronize();
