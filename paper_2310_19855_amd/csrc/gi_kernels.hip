@@ -1159,50 +1159,79 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
 // ------------------------------------------------------------------------------------------
 // Cache update (Section 2.2.1 decay, Section 2.2.3 moving average): one thread per slot
 // ------------------------------------------------------------------------------------------
-__global__ void k_cache_update(uint32_t N, uint32_t* fp, uint64_t* key, uint4* acc, float4* L, uint2* meta,
-                               uint32_t* accessed, uint32_t n_cap, uint32_t max_life, uint32_t frac_bits,
-                               unsigned long long* stats) {
+// thread t of the grid updates slots t, t + T, t + 2T, t + 3T (T = threads of the grid): all
+// fingerprints, then the live slots' state, are loaded before any is used
+constexpr uint32_t kUpdateSlots = 4;
+
+__global__ __launch_bounds__(256) void k_cache_update(uint32_t N, uint32_t* fp, uint64_t* key, uint4* acc, float4* L,
+                                                      uint2* meta, uint32_t* accessed, uint32_t n_cap,
+                                                      uint32_t max_life, uint32_t frac_bits,
+                                                      unsigned long long* stats) {
   __shared__ uint32_t bcount[2];   // the block's live and evicted slots: one atomic each per block
   if (threadIdx.x < 2u) bcount[threadIdx.x] = 0u;
   __syncthreads();
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  bool live = false, evicted = false;
-  if (s < N && fp[s] != 0u) {
-    const uint4 a = acc[s];
-    float4 l = L[s];
-    uint2 m = meta[s];
-    if (a.w > 0u) {
-      const uint32_t h = m.x < n_cap ? m.x : n_cap;
-      const float w = (float)a.w / (float)((double)h + (double)a.w);
-      const double den = (double)a.w * (double)(1u << frac_bits);
-      const float m0 = (float)((double)a.x / den);
-      const float m1 = (float)((double)a.y / den);
-      const float m2 = (float)((double)a.z / den);
-      l.x = l.x + w * (m0 - l.x);
-      l.y = l.y + w * (m1 - l.y);
-      l.z = l.z + w * (m2 - l.z);
-      const uint64_t nh = (uint64_t)m.x + a.w;
-      m.x = nh < n_cap ? (uint32_t)nh : n_cap;
+  const uint32_t T = gridDim.x * blockDim.x;
+  const uint32_t s0 = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t f[kUpdateSlots];
+#pragma unroll
+  for (uint32_t k = 0; k < kUpdateSlots; ++k) {
+    const uint32_t s = s0 + k * T;
+    f[k] = s < N ? fp[s] : 0u;
+  }
+  uint4 a[kUpdateSlots];
+  float4 l[kUpdateSlots];
+  uint2 m[kUpdateSlots];
+  uint32_t acc_bit[kUpdateSlots];
+#pragma unroll
+  for (uint32_t k = 0; k < kUpdateSlots; ++k)
+    if (f[k] != 0u) {
+      const uint32_t s = s0 + k * T;
+      a[k] = acc[s];
+      l[k] = L[s];
+      m[k] = meta[s];
+      acc_bit[k] = accessed[s];
     }
-    m.y = accessed[s] ? max_life : m.y - 1u;
-    if (m.y == 0u) {
+  uint32_t nlive = 0, nevict = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kUpdateSlots; ++k) {
+    if (f[k] == 0u) continue;
+    const uint32_t s = s0 + k * T;
+    if (a[k].w > 0u) {
+      const uint32_t h = m[k].x < n_cap ? m[k].x : n_cap;
+      const float w = (float)a[k].w / (float)((double)h + (double)a[k].w);
+      const double den = (double)a[k].w * (double)(1u << frac_bits);
+      const float m0 = (float)((double)a[k].x / den);
+      const float m1 = (float)((double)a[k].y / den);
+      const float m2 = (float)((double)a[k].z / den);
+      l[k].x = l[k].x + w * (m0 - l[k].x);
+      l[k].y = l[k].y + w * (m1 - l[k].y);
+      l[k].z = l[k].z + w * (m2 - l[k].z);
+      const uint64_t nh = (uint64_t)m[k].x + a[k].w;
+      m[k].x = nh < n_cap ? (uint32_t)nh : n_cap;
+    }
+    m[k].y = acc_bit[k] ? max_life : m[k].y - 1u;
+    if (m[k].y == 0u) {
       fp[s] = 0u;
       key[s] = 0u;
-      m.x = 0u;
-      l = make_float4(0.f, 0.f, 0.f, 0.f);
-      evicted = true;
+      m[k].x = 0u;
+      l[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      ++nevict;
     } else {
-      live = true;
+      ++nlive;
     }
-    L[s] = l;
-    meta[s] = m;
-    acc[s] = make_uint4(0u, 0u, 0u, 0u);
-    accessed[s] = 0u;
+    L[s] = l[k];
+    meta[s] = m[k];
+    if (a[k].w | a[k].x | a[k].y | a[k].z) acc[s] = make_uint4(0u, 0u, 0u, 0u);
+    if (acc_bit[k]) accessed[s] = 0u;
   }
-  const uint64_t ml = __ballot(live), me = __ballot(evicted);
+  // the block's counts: a wave sum, then one LDS atomic per wave and one global one per block
+  for (int o = 32; o >= 1; o >>= 1) {
+    nlive += (uint32_t)__shfl_xor((int)nlive, o, 64);
+    nevict += (uint32_t)__shfl_xor((int)nevict, o, 64);
+  }
   if ((threadIdx.x & 63u) == 0u) {
-    if (ml) atomicAdd(&bcount[0], (uint32_t)__popcll(ml));
-    if (me) atomicAdd(&bcount[1], (uint32_t)__popcll(me));
+    if (nlive) atomicAdd(&bcount[0], nlive);
+    if (nevict) atomicAdd(&bcount[1], nevict);
   }
   __syncthreads();
   if (threadIdx.x == 0u) {
@@ -1220,17 +1249,45 @@ __global__ void k_cache_update(uint32_t N, uint32_t* fp, uint64_t* key, uint4* a
 // the configuration caps the rays per probe at 256; up to 64 rays the kernel is built with a
 // 64-entry ray stage, which cuts its LDS from 7.25 to 3.25 KiB and lets more waves share a CU
 constexpr int kGatherMaxR = 256;
+constexpr uint32_t kGatherWaves = 4;
+
+// orders the LDS accesses of one wave (a block barrier is not needed when no other wave of the
+// block reads them)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // one butterfly step of a transpose-reduce over the first 2H entries of v: lanes whose bit
 // log2(2H) is set keep the upper half, the others the lower half, each adding its partner's copy
 template <int H>
+__device__ inline float lane_xor(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if (H == 4) return __uint_as_float(__builtin_amdgcn_update_dpp(0u, u, 0x128, 0xF, 0xF, false));   // row_ror:8 = xor 8
+  if (H == 2) return __uint_as_float(__builtin_amdgcn_ds_swizzle(u, 0x101F));                       // xor 4
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, u, 0x4E, 0xF, 0xF, false));                 // quad_perm 2301 = xor 2
+}
+
+template <int H>
 __device__ inline void transpose_reduce_step(float (&v)[32], uint32_t lane, uint32_t& coef) {
   const bool up = (lane & (uint32_t)(2 * H)) != 0u;
+  if (H >= 8) {
+    // lane halves (H = 16) or rows of 16 (H = 8) exchange whole registers: the swap hands each
+    // lane its own and its partner's copy of the half it keeps
 #pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const float keep = up ? v[H + i] : v[i];
-    const float send = up ? v[i] : v[H + i];
-    v[i] = keep + __shfl_xor(send, 2 * H, 64);
+    for (int i = 0; i < H; ++i) {
+      const auto r = H == 16 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[H + i]), false, false)
+                             : __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[H + i]), false, false);
+      v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const float keep = up ? v[H + i] : v[i];
+      const float send = up ? v[i] : v[H + i];
+      v[i] = keep + lane_xor<H>(send);
+    }
   }
   coef += up ? (uint32_t)H : 0u;
 }
@@ -1238,13 +1295,25 @@ __device__ inline void transpose_reduce_step(float (&v)[32], uint32_t lane, uint
 // SH projection of one probe's atlas (Section 2.4.2), one wave per probe, lane = cell:
 // exact integrals of the 9 real basis functions over the cell from its direction moments
 // rotated into the probe frame (columns t, b, n); c0..c2 = the cell's radiance
-__device__ inline void probe_sh(uint32_t p, uint32_t lane, float4 nn, const float* moments, float c0, float c1,
+struct CellMoments {
+  float v[10];   // solid angle, first moments (3), second moments xx yy zz xy xz yz
+};
+
+__device__ inline CellMoments load_moments(const float* moments, uint32_t lane) {
+  CellMoments m;
+  const float* mo = moments + lane * 10;
+#pragma unroll
+  for (int i = 0; i < 10; ++i) m.v[i] = mo[i];
+  return m;
+}
+
+__device__ inline void probe_sh(uint32_t p, uint32_t lane, float4 nn, const CellMoments& cm, float c0, float c1,
                                 float c2, float* sh) {
   const Basis B = make_basis(nn.x, nn.y, nn.z);
   const float R00 = B.tx, R10 = B.ty, R20 = B.tz;
   const float R01 = B.bx, R11 = B.by, R21 = B.bz;
   const float R02 = nn.x, R12 = nn.y, R22 = nn.z;
-  const float* mo = moments + lane * 10;
+  const float* mo = cm.v;
   const float om = mo[0];
   const float mlx = mo[1], mly = mo[2], mlz = mo[3];
   const float Mxx = mo[4], Myy = mo[5], Mzz = mo[6], Mxy = mo[7], Mxz = mo[8], Myz = mo[9];
@@ -1287,24 +1356,43 @@ __device__ inline void probe_sh(uint32_t p, uint32_t lane, float4 nn, const floa
   transpose_reduce_step<4>(v, lane, coef);
   transpose_reduce_step<2>(v, lane, coef);
   transpose_reduce_step<1>(v, lane, coef);
-  const float out = v[0] + __shfl_xor(v[0], 1, 64);
+  const float out = v[0] + __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v[0]), 0xB1, 0xF, 0xF, false));
   if ((lane & 1u) == 0u && coef < 28u) sh[(size_t)p * 28 + coef] = coef < 27u ? out : 0.0f;}
 
+// kGatherWaves independent waves per block, wave w of block b gathering probe b * kGatherWaves + w
+// with its own LDS: the waves share no data, so they order their LDS accesses with wave-level
+// barriers and a block holds several probes (a single-wave block per probe is launched at a
+// third of the rate)
 template <int MAXR>
-__global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const float4* pnrm, const uint4* rec,
-                                                  const float4* L, const float4* tnrm, const float4* mats,
-                                                  const float* moments, uint32_t R, float s0, float s1, float s2,
-                                                  LearnedGatherIn lg, uint32_t do_sh, const uint32_t* hist,
-                                                  const uint32_t* traced, const float4* recon,
-                                                  const float4* prev_atlas, const float* prev_sh, float4* atlas,
-                                                  float* sh) {
-  __shared__ float rv[MAXR][4];
-  __shared__ uint32_t rc[MAXR];
-  __shared__ float cv[64][4];
-  __shared__ float cs[64][4];
-  __shared__ uint32_t cn[64];
-  const uint32_t p = blockIdx.x;
-  const uint32_t lane = threadIdx.x;
+__global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t* mask, const float4* pnrm,
+                                                                 const uint4* rec, const float4* L,
+                                                                 const float4* tnrm, const float4* mats,
+                                                                 const float* moments, uint32_t P, uint32_t R,
+                                                                 float s0, float s1, float s2, LearnedGatherIn lg,
+                                                                 uint32_t do_sh, const uint32_t* hist,
+                                                                 const uint32_t* traced, const float4* recon,
+                                                                 const float4* prev_atlas, const float* prev_sh,
+                                                                 float4* atlas, float* sh) {
+  __shared__ float rv_s[kGatherWaves][MAXR][4];
+  __shared__ uint32_t rc_s[kGatherWaves][MAXR];
+  __shared__ float cv_s[kGatherWaves][64][4];
+  __shared__ float cs_s[kGatherWaves][64][4];
+  __shared__ uint32_t cn_s[kGatherWaves][64];
+  const uint32_t wv = threadIdx.x >> 6;
+  float (*rv)[4] = rv_s[wv];
+  uint32_t* rc = rc_s[wv];
+  float (*cv)[4] = cv_s[wv];
+  float (*cs)[4] = cs_s[wv];
+  uint32_t* cn = cn_s[wv];
+  const uint32_t p = blockIdx.x * kGatherWaves + wv;
+  const uint32_t lane = threadIdx.x & 63u;
+  if (p >= P) return;
+  // every load that does not depend on another is issued first (the probe's records, its
+  // normal and the cell moments of the SH projection), so that their latencies overlap
+  uint4 rr0 = make_uint4(0u, 0u, 0u, 0u);
+  if (lane < R) rr0 = rec[(size_t)p * R + lane];
+  const float4 pn = pnrm[p];
+  const CellMoments cmo = load_moments(moments, lane);
   if (mask[p] == kSentinel) {
     atlas[(size_t)p * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (do_sh && lane < 28) sh[(size_t)p * 28 + lane] = 0.0f;
@@ -1319,7 +1407,7 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
       const float4 r = recon[(size_t)p * 64 + lane];
       cv[lane][0] = r.x; cv[lane][1] = r.y; cv[lane][2] = r.z; cv[lane][3] = r.w;
       const uint64_t pop = __ballot(r.w >= 0.0f);
-      __syncthreads();
+      wave_sync();
       if (r.w >= 0.0f) {
         q = r;
       } else if (pop) {
@@ -1342,11 +1430,11 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
       }
     }
     atlas[(size_t)p * 64 + lane] = q;
-    if (do_sh) probe_sh(p, lane, pnrm[p], moments, q.x, q.y, q.z, sh);
+    if (do_sh) probe_sh(p, lane, pnrm[p], load_moments(moments, lane), q.x, q.y, q.z, sh);
     return;
   }
   for (uint32_t j = lane; j < R; j += 64) {
-    const uint4 r = rec[(size_t)p * R + j];
+    const uint4 r = j == lane ? rr0 : rec[(size_t)p * R + j];
     float v0, v1, v2;
     if (!(r.w & GI_RAY_HIT)) {
       v0 = s0; v1 = s1; v2 = s2;
@@ -1375,7 +1463,7 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
   }
   cs[lane][0] = cs[lane][1] = cs[lane][2] = cs[lane][3] = 0.0f;
   cn[lane] = 0u;
-  __syncthreads();
+  wave_sync();
   // per-cell sums in ray order (the same float32 order as a sequential loop over the rays):
   // in each chunk of 64 rays, the lanes whose rays share a cell are found with one ballot per
   // bit of the cell id, and the first of them folds their rays, in ascending order, into the
@@ -1403,7 +1491,7 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
       cs[c][0] = x0; cs[c][1] = x1; cs[c][2] = x2; cs[c][3] = x3;
       cn[c] = k;
     }
-    __syncthreads();
+    wave_sync();
   }
   const float a0 = cs[lane][0], a1 = cs[lane][1], a2 = cs[lane][2], a3 = cs[lane][3];
   const uint32_t cnt = cn[lane];
@@ -1414,18 +1502,22 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
   }
   cv[lane][0] = c0; cv[lane][1] = c1; cv[lane][2] = c2; cv[lane][3] = c3;
   const uint64_t populated = __ballot(cnt != 0u);
-  __syncthreads();
-  if (!cnt) {
-    // radiance backup: mean of the populated cells, summed in ascending cell order
-    float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+  wave_sync();
+  if (populated != ~0ull) {
+    // radiance backup: mean of the populated cells, summed in ascending cell order (the probe
+    // filter's decisions depend on these bits); lane k < 4 sums channel k (one LDS read and one
+    // add per cell) and the empty cells read the four means
+    float mk = 0.f;
+    if (lane < 4u)
+      for (uint64_t m = populated; m; m &= m - 1u) mk = mk + cv[__ffsll((long long)m) - 1][lane];
     const uint32_t np = (uint32_t)__popcll(populated);
-    for (uint64_t m = populated; m; m &= m - 1u) {
-      const int i = __ffsll((long long)m) - 1;
-      m0 = m0 + cv[i][0]; m1 = m1 + cv[i][1]; m2 = m2 + cv[i][2]; m3 = m3 + cv[i][3];
-    }
-    if (np) {
-      const float fn = (float)np;
-      c0 = m0 / fn; c1 = m1 / fn; c2 = m2 / fn; c3 = m3 / fn;
+    if (np) mk = mk / (float)np;
+    const float b0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 0));
+    const float b1 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 1));
+    const float b2 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 2));
+    const float b3 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 3));
+    if (!cnt && np) {
+      c0 = b0; c1 = b1; c2 = b2; c3 = b3;
     }
   }
   if (recon || hist) {
@@ -1448,7 +1540,7 @@ __global__ __launch_bounds__(64) void k_gather_sh(const uint32_t* mask, const fl
     }
   }
   atlas[(size_t)p * 64 + lane] = make_float4(c0, c1, c2, c3);
-  if (do_sh) probe_sh(p, lane, pnrm[p], moments, c0, c1, c2, sh);
+  if (do_sh) probe_sh(p, lane, pn, cmo, c0, c1, c2, sh);
 }
 
 // Algorithm 4: first valid probe of the probe-mask MIP chain at a tile offset from a pixel's tile
@@ -1547,7 +1639,7 @@ __global__ __launch_bounds__(64) void k_filter_probes(const uint32_t* mask, MipI
   }
   const float o0 = r0 / wsum, o1 = r1 / wsum, o2 = r2 / wsum, o3 = r3 / wsum;
   out[(size_t)p * 64 + lane] = make_float4(o0, o1, o2, o3);
-  if (VERTICAL) probe_sh(p, lane, np, moments, o0, o1, o2, sh);
+  if (VERTICAL) probe_sh(p, lane, np, load_moments(moments, lane), o0, o1, o2, sh);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2147,7 +2239,7 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
   if (c->cfg.cache_tiles) {
     GI_TIMED(c, "cache_update_tiles", s, (k_cache_update_tiles<<<c->N / 8u, 512, 0, s>>>(c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.cn, c->tab.Lq, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->cfg.tile_min_samples, c->d_stats)));
   } else {
-    GI_TIMED(c, "cache_update", s, (k_cache_update<<<blocks(c->N, 256), 256, 0, s>>>(c->N, c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->d_stats)));
+    GI_TIMED(c, "cache_update", s, (k_cache_update<<<blocks(c->N, 256 * kUpdateSlots), 256, 0, s>>>(c->N, c->tab.fp, c->tab.key, c->tab.acc, c->tab.L, c->tab.meta, c->tab.accessed, c->cfg.n_cap, c->cfg.max_life, c->cfg.frac_bits, c->d_stats)));
   }
   if (c->learned && c->cfg.cache_mode != GI_CACHE_PLAIN) {
     // the surrogate's radiance at every hit, then the judge against confident plain cells
@@ -2155,11 +2247,12 @@ hipError_t launch_update(gi_context* c, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const uint32_t filt = c->cfg.probe_filter;
-#define GI_GATHER_ARGS c->d_mask, c->d_pnrm, c->d_rec, c->cfg.cache_tiles ? c->tab.Lq : c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_prev_sh, c->d_atlas, c->d_sh
+#define GI_GATHER_ARGS c->d_mask, c->d_pnrm, c->d_rec, c->cfg.cache_tiles ? c->tab.Lq : c->tab.L, c->d_tnrm, c->d_mats, c->d_moments, c->P, c->R, c->cfg.sky[0], c->cfg.sky[1], c->cfg.sky[2], learned_gather_in(c), filt ? 0u : 1u, c->reprojected ? c->d_hist : nullptr, c->cfg.upscale > 1 ? c->d_traced : nullptr, c->guided ? c->d_recon : nullptr, c->d_prev_atlas, c->d_prev_sh, c->d_atlas, c->d_sh
+  const uint32_t gb = blocks(c->P, kGatherWaves);
   if (c->R <= 64u)
-    GI_TIMED(c, "gather_sh", s, (k_gather_sh<64><<<c->P, 64, 0, s>>>(GI_GATHER_ARGS)));
+    GI_TIMED(c, "gather_sh", s, (k_gather_sh<64><<<gb, 64 * kGatherWaves, 0, s>>>(GI_GATHER_ARGS)));
   else
-    GI_TIMED(c, "gather_sh", s, (k_gather_sh<kGatherMaxR><<<c->P, 64, 0, s>>>(GI_GATHER_ARGS)));
+    GI_TIMED(c, "gather_sh", s, (k_gather_sh<kGatherMaxR><<<gb, 64 * kGatherWaves, 0, s>>>(GI_GATHER_ARGS)));
 #undef GI_GATHER_ARGS
   if (filt) {
     // Algorithm 5: x pass into the scratch atlas, y pass back (and the SH of the result)
