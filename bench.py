@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--forms", metavar="PATH", default=None,
                     help="after the headline line, run the optional sweeps (cache forms, 4K, furnace, probe "
                          "filter, temporal reuse, light sampling) and write them as JSON to PATH")
+    ap.add_argument("--equal-error", metavar="PATH", default=None,
+                    help="after the headline line, run the equal-error protocol (field sequence of 60 frames, "
+                         "evaluation frames 0, 29, 59, R in 8..128, plain / MLP-BF16 / MLP-FP8) and write it to PATH")
     ap.add_argument("--form", default="plain", choices=("plain", "mlp_bf16", "mlp_fp8"),
                     help="cache form of the timed frames (learned forms train and infer every frame)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -105,6 +108,11 @@ def main():
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
     line = headline(args, log)
     print(json.dumps(line), flush=True)
+    if args.equal_error:
+        res = equal_error_protocol(log)
+        with open(args.equal_error, "w") as fh:
+            json.dump(res, fh, indent=1)
+        log(f"[bench] equal-error protocol written to {args.equal_error}")
     if args.forms:
         forms = optional_sweeps(log)
         with open(args.forms, "w") as fh:
@@ -385,6 +393,129 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
         torch.cuda.synchronize()
     ctx.close()
     return res
+
+
+EE_FORMS = ("plain", "mlp_bf16", "mlp_fp8")
+EE_FRAMES, EE_EVAL = 60, (0, 29, 59)
+
+
+def _point_reference(frame):
+    """the float64 point reference of a frame of the field sequence (its camera and lights
+    frozen): seeded visible surface points of its 480x270 view and the converged radiance there"""
+    import numpy as np
+    g = os.path.join(ROOT, "tests", "golden")
+    path = os.path.join(g, f"field480x270_f{frame}_points.npz")
+    if frame == 0 and not os.path.exists(path):
+        path = os.path.join(g, "field480x270_reference.npz")
+    if not os.path.exists(path):
+        return None
+    return np.load(path)
+
+
+def equal_error_protocol(log, W=1920, H=1080, frames=EE_FRAMES, eval_frames=EE_EVAL, sweep_R=SWEEP_R,
+                         timed_from=5):
+    """The equal-error comparison on the benchmark workload's own sequence: the 1920x1080 field
+    with its orbiting camera and moving light, 60 frames, for each cache form (plain, MLP with
+    BF16 inference, MLP with FP8 e4m3 inference) and each rays-per-probe R.  At the evaluation
+    frames 0, 29 and 59 the cache's radiance (the plain cell, or the surrogate) is compared with
+    the float64 oracle's converged radiance at that frame's reference points (relMAE over the
+    points whose cell the plain cache holds); ms/frame is the GPU time of the pass (spawn to
+    interpolation, learned training and inference included) over frames 5..59, from HIP events
+    around each frame.  Beside it, the per-pixel reading: the irradiance image of a 480x270 run
+    with the frame-0 camera and lights frozen (16 frames) against the oracle's converged
+    irradiance image of that view (relMAE over pixels with a probe on both sides)."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19855_amd import gi
+    from paper_2310_19855_amd import inputs as I
+    refs = {f: _point_reference(f) for f in eval_frames}
+    missing = [f for f, r in refs.items() if r is None]
+    if missing:
+        return {"error": f"no point reference for frames {missing} (python -m oracle.make_reference --scene field "
+                         f"--frame F --points-only)"}
+    scene = I.make_scene("field")
+    pts = {f: (torch.from_numpy(r["point_pos"]).cuda(), torch.from_numpy(r["point_nrm"]).cuda(),
+               r["point_L"].astype(np.float64)) for f, r in refs.items()}
+    out = {"protocol": f"field {W}x{H}, frames 0..{frames - 1} (orbit camera, moving light), evaluation frames "
+                       f"{list(eval_frames)}; relMAE of the cache radiance at each evaluation frame's seeded surface "
+                       f"points vs the float64 oracle's converged radiance there (light and camera of that frame), "
+                       f"over the points whose cell the plain cache holds; ms/frame over frames {timed_from}.."
+                       f"{frames - 1}", "mlp": dict(MLP_CFG), "sweep": {}}
+    for form in EE_FORMS:
+        out["sweep"][form] = {}
+        for R in sweep_R:
+            cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, cache_mode=FORMS[form])
+            if form != "plain":
+                cfg.update(MLP_CFG)
+            ctx = gi.Context(**cfg)
+            ctx.build_bvh(scene)
+            gb = gi.GBuffer(H, W)
+            o = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            ms, errs = [], {}
+            for f in range(frames):
+                cam = I.camera_for("field", f)
+                cam.index = f
+                ctx.set_dynamic(*scene.dynamic(f))
+                ctx.render_gbuffer(cam, gb.pos, gb.nrm, gb.alb, gb.prim)
+                e0.record()
+                ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
+                ctx.trace_probes(cam)
+                if form != "plain":
+                    ctx.learned_train(cam)
+                ctx.cache_update(cam)
+                ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, o)
+                e1.record()
+                torch.cuda.synchronize()
+                if f >= timed_from:
+                    ms.append(e0.elapsed_time(e1))
+                if f in pts:
+                    pp, pn, Lr = pts[f]
+                    q = torch.zeros((pp.shape[0], 4), dtype=torch.float32, device="cuda")
+                    ctx.cache_query(pp, pn, q)
+                    plain_q = q.cpu().numpy()
+                    if form != "plain":
+                        ctx.learned_query(pp, pn, q)
+                    val = q.cpu().numpy()
+                    found = plain_q[:, 3] > 0
+                    L = val[found, :3].astype(np.float64)
+                    errs[f] = {"relMAE": round(float(np.abs(L - Lr[found]).sum() / max(np.abs(Lr[found]).sum(), 1e-30)), 5),
+                               "points": int(found.sum())}
+            ctx.close()
+            row = {"ms_per_frame": round(float(np.mean(ms)), 4), "eval": errs,
+                   "max_relMAE": max(v["relMAE"] for v in errs.values())}
+            out["sweep"][form][R] = row
+            log(f"[bench] equal error {form} R={R}: {row['ms_per_frame']:.3f} ms/frame, relMAE "
+                + ", ".join(f"f{f} {v['relMAE']:.3f}" for f, v in errs.items()))
+
+    def cheapest(form, level):
+        ok = [(v["ms_per_frame"], R) for R, v in out["sweep"][form].items() if v["max_relMAE"] <= level]
+        if not ok:
+            return None
+        m, R = min(ok)
+        return {"rays_per_probe": R, "ms_per_frame": m, "max_relMAE": out["sweep"][form][R]["max_relMAE"]}
+    out["equal_error_5pct"] = {f: cheapest(f, 0.05) for f in EE_FORMS}
+    common = max(min(v["max_relMAE"] for v in out["sweep"][f].values()) for f in EE_FORMS)
+    out["equal_error_common"] = {"level": round(common, 5), **{f: cheapest(f, common) for f in EE_FORMS}}
+    out["nominal_R64"] = {f: out["sweep"][f].get(64) for f in EE_FORMS}
+    # per-pixel reading at frame 0 (480x270, the converged irradiance image of the frozen view)
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "field480x270_reference.npz"))
+    w, h = int(ref["width"]), int(ref["height"])
+    pix = {}
+    for form in EE_FORMS:
+        r = run_form("field", scene, w, h, 64, form, SWEEP_FRAMES, SWEEP_TIMED_FROM, want_out=True)
+        img = r["out"]
+        ok = (img[..., 3] == 0) & (ref["flag"] == 0)
+        E = img[ok][:, :3].astype(np.float64)
+        Er = ref["irradiance"][ok].astype(np.float64)
+        pix[form] = {"relMAE": round(float(np.abs(E - Er).sum() / max(np.abs(Er).sum(), 1e-30)), 5),
+                     "pixels": int(ok.sum())}
+    out["per_pixel_frame0_480x270_R64"] = pix
+    log(f"[bench] equal error at 5%: {out['equal_error_5pct']}; common level {out['equal_error_common']}; "
+        f"per-pixel {pix}")
+    return out
 
 
 def forms_comparison(log, W=1920, H=1080):

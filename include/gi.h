@@ -28,7 +28,7 @@
  *   - Results are deterministic: every integer result (probe mask, hit index, hit distance
  *     bits, cell key, per-cell fixed-point sums and counts) is bit-reproducible and equal to
  *     the float32 definition of the method; the slot a cell occupies inside its bucket is not
- *     part of the result (exports are in slot order; compare by cell id).
+ *     part of the result, so exports list cells in ascending key order.
  */
 #ifndef GI_H
 #define GI_H
@@ -326,7 +326,7 @@ gi_status gi_denoiser_export(gi_denoiser *dn, float *h_hist, uint32_t *h_radius)
 
 /* ---- parity, resume and observability (host-synchronous, host pointers) --------------- */
 
-/* Two-level cache export (cache_tiles = 1; host-synchronous): the live tiles in slot order,
+/* Two-level cache export (cache_tiles = 1; host-synchronous): the live tiles in ascending key order,
  * at most cap of them; id = bucket << 32 | fingerprint, key = tile descriptor, life, and per
  * cell (64 per tile, [n][64][...]) the fixed-point sums and count of this frame, the moving
  * average, its sample count and the prefiltered radiance that readers see.  Any output
@@ -342,13 +342,13 @@ gi_status gi_light_grid_export(gi_context *ctx, float *h_geom, uint32_t *h_dims,
                                uint32_t cap_cells);
 
 /* World-space reservoirs written by the last trace (restir = 1; host-synchronous): live slots
- * in slot order, at most cap: id = bucket << 32 | fingerprint, key (quantised position),
+ * in ascending key order, at most cap: id = bucket << 32 | fingerprint, key (quantised position),
  * light point and contribution weight [n][4], normal of the storing vertex [n][3], light
  * (emitter index) and count.  GI_ERR_UNSUPPORTED without reservoirs. */
 gi_status gi_restir_export(gi_context *ctx, uint64_t *h_id, uint64_t *h_key, float *h_yw, float *h_n, uint32_t *h_k,
                            uint32_t *h_m, uint32_t cap, uint32_t *n_out);
 
-/* Live cells in slot order: id = bucket << 32 | fingerprint, key (descriptor bits), acc
+/* Live cells in ascending key order: id = bucket << 32 | fingerprint, key (descriptor bits), acc
  * [n][4] (fixed-point r,g,b sums and count of the current frame), L [n][3] cached radiance,
  * nhist, life.  Writes at most cap cells; *n_out = number of live cells.
  * GI_ERR_UNSUPPORTED with cache_tiles (see gi_tiles_export); so are save and load. */
@@ -360,6 +360,8 @@ gi_status gi_cache_export(gi_context *ctx, uint64_t *h_id, uint64_t *h_key, uint
  * the size only.  gi_cache_import restores a blob from a context of the same config. */
 gi_status gi_cache_save(gi_context *ctx, void *h_blob, size_t cap, size_t *size_out);
 gi_status gi_cache_load(gi_context *ctx, const void *h_blob, size_t size);
+/* The same as gi_cache_load: restore a world cache saved from a context of the same config. */
+gi_status gi_cache_import(gi_context *ctx, const void *h_blob, size_t size);
 
 /* Ray records of the last gi_trace_probes, [P*R] each: slot (or -1), t, tri, flags; and the
  * descriptor key of the hit (0 for a miss). */
@@ -388,6 +390,10 @@ gi_status gi_profile_read(gi_context *ctx, char *h_names, size_t names_cap, uint
 /* Learned-cache parameters as a blob (resume); layout private to the library. */
 gi_status gi_learned_save(gi_context *ctx, void *h_blob, size_t cap, size_t *size_out);
 gi_status gi_learned_load(gi_context *ctx, const void *h_blob, size_t size);
+/* The same as gi_learned_save / gi_learned_load (the surrogate's parameters, gradients and
+ * Adam state as one blob; import requires a context of the same levels and table size). */
+gi_status gi_learned_export(gi_context *ctx, void *h_blob, size_t cap, size_t *size_out);
+gi_status gi_learned_import(gi_context *ctx, const void *h_blob, size_t size);
 /* The last gi_learned_train's batch (host-synchronous; learned mode).  The frame's training
  * rays are the probe rays whose hit found or created a world-cache cell with a finite sample,
  * in ray order (ray id = probe * R + ray); the batch's rows = mlp_steps * 2^mlp_batch_log2

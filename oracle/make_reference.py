@@ -7,6 +7,9 @@ placement) and the world-cache cells whose history reached min_hist samples (key
 sample count).
 
     python -m oracle.make_reference [--scene room --width 480 --height 270 --frames 24 --rays 1024]
+
+With --frame F --points-only: only the point reference of frame F of the scene's sequence
+(its camera and its lights frozen at F), written to <scene><W>x<H>_f<F>_points.npz.
 """
 import argparse
 import os
@@ -40,7 +43,7 @@ def reference(scene, width, height, frames, rays, seed=3):
     return out, st.table(), g, st
 
 
-def point_reference(st, g, n_points, n_samples, seed=17):
+def point_reference(st, g, n_points, n_samples, seed=17, scene="room"):
     """Converged reflected radiance at seeded visible surface points: for one bounce a cell's
     sample is albedo * E / pi with E the one-light-sample NEE estimate (Sections 2.2.4, 2.3.1),
     so its expectation at a point is albedo times the mean of n_samples such estimates there.
@@ -52,7 +55,7 @@ def point_reference(st, g, n_points, n_samples, seed=17):
     P = pos.reshape(-1, 4)[pick].astype(np.float64)
     Nn = nrm.reshape(-1, 4)[pick].astype(np.float64)
     A = alb.reshape(-1, 4)[pick, :3].astype(np.float64)
-    fr = I.camera_for("room", 0)  # only the frame index enters NEE: it picks the RNG stream
+    fr = I.camera_for(scene, 0)   # only the frame index enters NEE: it picks the RNG stream
     fr.index = 1 << 20            # a stream of its own, apart from the frames' streams
     ids = np.arange(n_samples, dtype=np.uint32)
     L = np.zeros((len(pick), 3))
@@ -79,9 +82,27 @@ def main():
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--points", type=int, default=8192)
     ap.add_argument("--point-samples", type=int, default=16384)
+    ap.add_argument("--frame", type=int, default=0, help="frame of the sequence whose camera and lights are frozen")
+    ap.add_argument("--points-only", action="store_true", help="only the point reference of --frame")
     args = ap.parse_args()
+    if args.points_only:
+        sc = I.make_scene(args.scene)
+        osc = O.OracleScene(sc, f64=True)
+        osc.set_frame_dynamic(args.frame)
+        st = O.OracleFrameState(osc, O.default_config(width=args.width, height=args.height, rays_per_probe=1,
+                                                       table_log2=10, sky=sc.sky))
+        g = osc.gbuffer(I.camera_for(args.scene, args.frame), args.width, args.height)
+        pix, ppos, pnrm, pL, pse = point_reference(st, g, args.points, args.point_samples, scene=args.scene)
+        path = os.path.join(ROOT, "tests", "golden", f"{args.scene}{args.width}x{args.height}_f{args.frame}_points.npz")
+        np.savez_compressed(path, frame=args.frame, width=args.width, height=args.height, scene=args.scene,
+                            point_pixel=pix.astype(np.uint32), point_pos=ppos, point_nrm=pnrm,
+                            point_L=pL.astype(np.float32), point_se=pse.astype(np.float32),
+                            point_samples=args.point_samples)
+        print(f"point reference of frame {args.frame}: relative standard error {pse.sum() / pL.sum():.4f}")
+        print("wrote", path)
+        return
     E, tab, g, st = reference(args.scene, args.width, args.height, args.frames, args.rays)
-    pix, ppos, pnrm, pL, pse = point_reference(st, g, args.points, args.point_samples)
+    pix, ppos, pnrm, pL, pse = point_reference(st, g, args.points, args.point_samples, scene=args.scene)
     # converged world-cache cells: those with at least min_hist samples of history
     min_hist = args.min_hist
     keep = tab["nhist"] >= min_hist

@@ -852,8 +852,12 @@ gi_status gi_restir_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, float
     GI_TRY_HIP(c, hipMemcpy(nr.data(), c->d_rs_n[t], 16 * N, hipMemcpyDeviceToHost));
     GI_TRY_HIP(c, hipMemcpy(m.data(), c->d_rs_m[t], 4 * N, hipMemcpyDeviceToHost));
     uint32_t n = 0;
-    for (size_t s = 0; s < N; ++s) {
-      if (!fp[s] || !c->rs_has_prev) continue;
+    // live slots in ascending key order (slot positions are not part of the result)
+    std::vector<uint32_t> live;
+    for (size_t s = 0; s < N; ++s)
+      if (fp[s] && c->rs_has_prev) live.push_back((uint32_t)s);
+    std::sort(live.begin(), live.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
+    for (const uint32_t s : live) {
       if (n < cap) {
         if (h_id) h_id[n] = ((uint64_t)(s / gi::kBucketSlots) << 32) | fp[s];
         if (h_key) h_key[n] = key[s];
@@ -926,9 +930,13 @@ gi_status gi_tiles_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, uint32
     GI_TRY_HIP(c, hipMemcpy(L.data(), c->tab.L, 16 * NC, hipMemcpyDeviceToHost));
     GI_TRY_HIP(c, hipMemcpy(cn.data(), c->tab.cn, 4 * NC, hipMemcpyDeviceToHost));
     GI_TRY_HIP(c, hipMemcpy(Lq.data(), c->tab.Lq, 16 * NC, hipMemcpyDeviceToHost));
+    // live cells in ascending key order (slot positions are not part of the result)
+    std::vector<uint32_t> live;
+    for (size_t s = 0; s < N; ++s)
+      if (fp[s]) live.push_back((uint32_t)s);
+    std::sort(live.begin(), live.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
     uint32_t n = 0;
-    for (size_t s = 0; s < N; ++s) {
-      if (!fp[s]) continue;
+    for (const uint32_t s : live) {
       if (n < cap) {
         if (h_id) h_id[n] = ((uint64_t)(s / gi::kBucketSlots) << 32) | fp[s];
         if (h_key) h_key[n] = key[s];
@@ -980,9 +988,13 @@ gi_status gi_cache_export(gi_context* c, uint64_t* h_id, uint64_t* h_key, uint32
     GI_TRY_HIP(c, hipMemcpy(acc.data(), c->tab.acc, 16 * N, hipMemcpyDeviceToHost));
     GI_TRY_HIP(c, hipMemcpy(L.data(), c->tab.L, 16 * N, hipMemcpyDeviceToHost));
     GI_TRY_HIP(c, hipMemcpy(meta.data(), c->tab.meta, 8 * N, hipMemcpyDeviceToHost));
+    // live cells in ascending key order (slot positions are not part of the result)
+    std::vector<uint32_t> live;
+    for (size_t s = 0; s < N; ++s)
+      if (fp[s]) live.push_back((uint32_t)s);
+    std::sort(live.begin(), live.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
     uint32_t n = 0;
-    for (size_t s = 0; s < N; ++s) {
-      if (!fp[s]) continue;
+    for (const uint32_t s : live) {
       if (n < cap) {
         if (h_id) h_id[n] = ((uint64_t)(s / gi::kBucketSlots) << 32) | fp[s];
         if (h_key) h_key[n] = key[s];
@@ -1198,6 +1210,14 @@ gi_status gi_learned_batch_export(gi_context* c, float* h_raw, float* h_grouped,
   if ((h_raw || h_grouped) && cap_rows < rows) return fail(c, GI_ERR_INVALID_ARG, "cap_rows below the batch rows");
   return GI_OK;
 }
+
+gi_status gi_cache_import(gi_context* c, const void* h_blob, size_t size) { return gi_cache_load(c, h_blob, size); }
+
+gi_status gi_learned_export(gi_context* c, void* h_blob, size_t cap, size_t* size_out) {
+  return gi_learned_save(c, h_blob, cap, size_out);
+}
+
+gi_status gi_learned_import(gi_context* c, const void* h_blob, size_t size) { return gi_learned_load(c, h_blob, size); }
 
 gi_status gi_learned_stats(gi_context* c, float* out8) {
   if (!c || !out8) return GI_ERR_INVALID_ARG;

@@ -114,6 +114,7 @@ def lib():
     fn("gi_cache_export", st, vp, vp, vp, vp, vp, vp, vp, u32, P(u32))
     fn("gi_cache_save", st, vp, vp, sz, P(sz))
     fn("gi_cache_load", st, vp, vp, sz)
+    fn("gi_cache_import", st, vp, vp, sz)
     fn("gi_rays_export", st, vp, vp, vp, vp, vp, vp)
     fn("gi_probes_export", st, vp, vp, vp, vp, vp, vp)
     fn("gi_get_dims", st, vp, vp)
@@ -123,6 +124,8 @@ def lib():
     fn("gi_profile_read", st, vp, vp, sz, vp, vp, u32, P(u32))
     fn("gi_learned_save", st, vp, vp, sz, P(sz))
     fn("gi_learned_load", st, vp, vp, sz)
+    fn("gi_learned_export", st, vp, vp, sz, P(sz))
+    fn("gi_learned_import", st, vp, vp, sz)
     fn("gi_learned_stats", st, vp, vp)
     fn("gi_learned_batch_export", st, vp, vp, vp, u32, P(u32), P(u32))
     _lib = L
@@ -414,17 +417,17 @@ class Context:
         return buf.raw
 
     def cache_load(self, blob: bytes):
-        self._check(lib().gi_cache_load(self.h, blob, len(blob)), "gi_cache_load")
+        self._check(lib().gi_cache_import(self.h, blob, len(blob)), "gi_cache_import")
 
     def learned_save(self) -> bytes:
         n = C.c_size_t()
-        self._check(lib().gi_learned_save(self.h, None, 0, C.byref(n)), "gi_learned_save")
+        self._check(lib().gi_learned_export(self.h, None, 0, C.byref(n)), "gi_learned_export")
         buf = C.create_string_buffer(n.value)
-        self._check(lib().gi_learned_save(self.h, buf, n.value, C.byref(n)), "gi_learned_save")
+        self._check(lib().gi_learned_export(self.h, buf, n.value, C.byref(n)), "gi_learned_export")
         return buf.raw
 
     def learned_load(self, blob: bytes):
-        self._check(lib().gi_learned_load(self.h, blob, len(blob)), "gi_learned_load")
+        self._check(lib().gi_learned_import(self.h, blob, len(blob)), "gi_learned_import")
 
     def learned_stats(self):
         out = np.zeros(8, np.float32)

@@ -299,3 +299,39 @@ def test_furnace_feedback_recurrence(furnace):
         assert abs(pr["atlas"][valid][..., :3].mean() / (le + L) - 1) < 8e-3, f
     # converging to Le / (1 - rho) = 5 with relative error rho^(f+1)
     assert abs((le + L) - le / (1 - rho) * (1 - rho ** 9)) < 1e-9
+
+
+def test_point_reference_files_of_the_field_sequence():
+    """The stored point references of frames 29 and 59 of the field sequence (written by
+    oracle/make_reference.py from the oracle alone) are visible surface points of that frame's
+    view, and their radiance is the mean of the oracle's one-light-sample estimates there: an
+    independent re-estimate with other random numbers agrees within 5 standard errors."""
+    import os
+
+    import numpy as np
+
+    import oracle as O
+    from paper_2310_19855_amd import inputs as I
+    g = os.path.join(os.path.dirname(__file__), "golden")
+    sc = I.make_scene("field")
+    for f in (29, 59):
+        ref = np.load(os.path.join(g, f"field480x270_f{f}_points.npz"))
+        assert int(ref["frame"]) == f and len(ref["point_L"]) == 8192
+        osc = O.OracleScene(sc, f64=True)
+        osc.set_frame_dynamic(f)
+        pos, nrm, alb, prim = osc.gbuffer(I.camera_for("field", f), 480, 270)
+        pix = ref["point_pixel"].astype(np.int64)
+        assert (prim.reshape(-1)[pix] != 0xFFFFFFFF).all()
+        assert np.array_equal(pos.reshape(-1, 4)[pix, :3].astype(np.float32), ref["point_pos"][:, :3])
+        st = O.OracleFrameState(osc, O.default_config(width=480, height=270, rays_per_probe=1, table_log2=10,
+                                                       sky=sc.sky))
+        fr = I.camera_for("field", 0)
+        fr.index = (1 << 20) + 7            # a stream the reference did not use
+        ids = np.arange(4096, dtype=np.uint32)
+        for i in (0, 1000, 4000, 8000):
+            e = st.nee(fr, ref["point_pos"][i, :3].astype(np.float64), ref["point_nrm"][i, :3].astype(np.float64), ids)
+            a = alb.reshape(-1, 4)[pix[i], :3].astype(np.float64)
+            est = a * e.mean(0)
+            se = a * e.std(0) / np.sqrt(len(ids))
+            tol = 5 * np.sqrt(se ** 2 + ref["point_se"][i].astype(np.float64) ** 2) + 1e-9
+            assert (np.abs(est - ref["point_L"][i]) <= tol).all(), (f, i, est, ref["point_L"][i])
