@@ -397,6 +397,7 @@ def run_form(scene_name, scene, W, H, R, form, frames, timed_from, points=None, 
 
 EE_FORMS = ("plain", "mlp_bf16", "mlp_fp8")
 EE_FRAMES, EE_EVAL = 60, (0, 29, 59)
+EE_CAPS = (4, 16, 64)
 
 
 def _point_reference(frame):
@@ -442,53 +443,59 @@ def equal_error_protocol(log, W=1920, H=1080, frames=EE_FRAMES, eval_frames=EE_E
                        f"points vs the float64 oracle's converged radiance there (light and camera of that frame), "
                        f"over the points whose cell the plain cache holds; ms/frame over frames {timed_from}.."
                        f"{frames - 1}", "mlp": dict(MLP_CFG), "sweep": {}}
-    for form in EE_FORMS:
-        out["sweep"][form] = {}
-        for R in sweep_R:
-            cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, cache_mode=FORMS[form])
+    def run(form, R, extra=None):
+        cfg = dict(width=W, height=H, rays_per_probe=R, table_log2=20, sky=scene.sky, cache_mode=FORMS[form])
+        if form != "plain":
+            cfg.update(MLP_CFG)
+        cfg.update(extra or {})
+        ctx = gi.Context(**cfg)
+        ctx.build_bvh(scene)
+        gb = gi.GBuffer(H, W)
+        o = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ms, errs = [], {}
+        for f in range(frames):
+            cam = I.camera_for("field", f)
+            cam.index = f
+            ctx.set_dynamic(*scene.dynamic(f))
+            ctx.render_gbuffer(cam, gb.pos, gb.nrm, gb.alb, gb.prim)
+            e0.record()
+            ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
+            ctx.trace_probes(cam)
             if form != "plain":
-                cfg.update(MLP_CFG)
-            ctx = gi.Context(**cfg)
-            ctx.build_bvh(scene)
-            gb = gi.GBuffer(H, W)
-            o = torch.zeros((H, W, 4), dtype=torch.float32, device="cuda")
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            ms, errs = [], {}
-            for f in range(frames):
-                cam = I.camera_for("field", f)
-                cam.index = f
-                ctx.set_dynamic(*scene.dynamic(f))
-                ctx.render_gbuffer(cam, gb.pos, gb.nrm, gb.alb, gb.prim)
-                e0.record()
-                ctx.spawn_probes(cam, gb.pos, gb.nrm, gb.prim)
-                ctx.trace_probes(cam)
+                ctx.learned_train(cam)
+            ctx.cache_update(cam)
+            ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, o)
+            e1.record()
+            torch.cuda.synchronize()
+            if f >= timed_from:
+                ms.append(e0.elapsed_time(e1))
+            if f in pts:
+                pp, pn, Lr = pts[f]
+                q = torch.zeros((pp.shape[0], 4), dtype=torch.float32, device="cuda")
+                ctx.cache_query(pp, pn, q)
+                plain_q = q.cpu().numpy()
                 if form != "plain":
-                    ctx.learned_train(cam)
-                ctx.cache_update(cam)
-                ctx.interpolate_probes(cam, gb.pos, gb.nrm, gb.prim, o)
-                e1.record()
-                torch.cuda.synchronize()
-                if f >= timed_from:
-                    ms.append(e0.elapsed_time(e1))
-                if f in pts:
-                    pp, pn, Lr = pts[f]
-                    q = torch.zeros((pp.shape[0], 4), dtype=torch.float32, device="cuda")
-                    ctx.cache_query(pp, pn, q)
-                    plain_q = q.cpu().numpy()
-                    if form != "plain":
-                        ctx.learned_query(pp, pn, q)
-                    val = q.cpu().numpy()
-                    found = plain_q[:, 3] > 0
-                    L = val[found, :3].astype(np.float64)
-                    errs[f] = {"relMAE": round(float(np.abs(L - Lr[found]).sum() / max(np.abs(Lr[found]).sum(), 1e-30)), 5),
-                               "points": int(found.sum())}
-            ctx.close()
-            row = {"ms_per_frame": round(float(np.mean(ms)), 4), "eval": errs,
-                   "max_relMAE": max(v["relMAE"] for v in errs.values())}
-            out["sweep"][form][R] = row
-            log(f"[bench] equal error {form} R={R}: {row['ms_per_frame']:.3f} ms/frame, relMAE "
-                + ", ".join(f"f{f} {v['relMAE']:.3f}" for f, v in errs.items()))
+                    ctx.learned_query(pp, pn, q)
+                val = q.cpu().numpy()
+                found = plain_q[:, 3] > 0
+                L = val[found, :3].astype(np.float64)
+                errs[f] = {"relMAE": round(float(np.abs(L - Lr[found]).sum() / max(np.abs(Lr[found]).sum(), 1e-30)), 5),
+                           "points": int(found.sum())}
+        ctx.close()
+        row = {"ms_per_frame": round(float(np.mean(ms)), 4), "eval": errs,
+               "max_relMAE": max(v["relMAE"] for v in errs.values())}
+        log(f"[bench] equal error {form} R={R} {extra or ''}: {row['ms_per_frame']:.3f} ms/frame, relMAE "
+            + ", ".join(f"f{f} {v['relMAE']:.3f}" for f, v in errs.items()))
+        return row
+
+    for form in EE_FORMS:
+        out["sweep"][form] = {R: run(form, R) for R in sweep_R}
+    # the plain cache's history cap (samples in its moving average): with a moving light a long
+    # history averages the radiance of the light's earlier positions
+    out["plain_history_cap"] = {f"R{R}_cap{cap}": run("plain", R, {"n_cap": cap})
+                                for R in (64, 128) for cap in EE_CAPS}
 
     def cheapest(form, level):
         ok = [(v["ms_per_frame"], R) for R, v in out["sweep"][form].items() if v["max_relMAE"] <= level]

@@ -2256,6 +2256,19 @@ static void cache_update(state *st)
  * atlas cell in ray order; cells that received no ray get the mean of the populated cells
  * (radiance backup); alpha holds the mean travelled distance.
  * ------------------------------------------------------------------------------------- */
+/* The radiance backup's mean (Section 2.1.4 fills the cells without rays with the average of
+ * the populated ones; the order of that sum is not given): a balanced pairwise sum over the
+ * 64 cells in index order, cells without a value counting as zero -- pairs (0,1), (2,3), ...,
+ * then pairs of those sums, and so on. */
+static real pair_sum64(const real *v, int stride)
+{
+    real t[NCELL];
+    for (int i = 0; i < NCELL; ++i) t[i] = v[(size_t)i * stride];
+    for (int w = 1; w < NCELL; w *= 2)
+        for (int i = 0; i < NCELL; i += 2 * w) t[i] = t[i] + t[i + w];
+    return t[0];
+}
+
 static void gather(state *st)
 {
     const orc_config *c = &st->cfg;
@@ -2273,15 +2286,15 @@ static void gather(state *st)
              * others */
             if (st->guided) {
                 const real *rc = st->recon + (size_t)p * NCELL * 4;
-                real mean[4] = {RC(0.0), RC(0.0), RC(0.0), RC(0.0)};
+                real val[NCELL * 4], mean[4];
                 uint32_t npop = 0;
                 for (int i = 0; i < NCELL; ++i) {
-                    if (rc[4 * i + 3] < RC(0.0)) continue;
-                    for (int k = 0; k < 4; ++k) mean[k] = mean[k] + rc[4 * i + k];
-                    ++npop;
+                    const int has = !(rc[4 * i + 3] < RC(0.0));
+                    for (int k = 0; k < 4; ++k) val[4 * i + k] = has ? rc[4 * i + k] : RC(0.0);
+                    npop += (uint32_t)has;
                 }
                 if (npop == 0) continue;
-                for (int k = 0; k < 4; ++k) mean[k] = mean[k] / (real)npop;
+                for (int k = 0; k < 4; ++k) mean[k] = pair_sum64(val + k, 4) / (real)npop;
                 for (int i = 0; i < NCELL; ++i)
                     for (int k = 0; k < 4; ++k) at[4 * i + k] = rc[4 * i + 3] < RC(0.0) ? mean[k] : rc[4 * i + k];
             } else if (st->hist[p] != SENTINEL) {
@@ -2313,18 +2326,15 @@ static void gather(state *st)
             sum[cell][3] = sum[cell][3] + st->r_t[gid];
             cnt[cell]++;
         }
-        real mean[4] = {RC(0.0), RC(0.0), RC(0.0), RC(0.0)};
+        real mean[4];
         uint32_t npop = 0;
         for (int i = 0; i < NCELL; ++i) {
             if (!cnt[i]) continue;
-            for (int k = 0; k < 4; ++k) {
-                at[4 * i + k] = sum[i][k] / (real)cnt[i];
-                mean[k] = mean[k] + at[4 * i + k];
-            }
+            for (int k = 0; k < 4; ++k) at[4 * i + k] = sum[i][k] / (real)cnt[i];
             ++npop;
         }
         if (npop == 0) continue;
-        for (int k = 0; k < 4; ++k) mean[k] = mean[k] / (real)npop;
+        for (int k = 0; k < 4; ++k) mean[k] = pair_sum64(at + k, 4) / (real)npop;
         for (int i = 0; i < NCELL; ++i)
             if (!cnt[i])
                 for (int k = 0; k < 4; ++k) at[4 * i + k] = mean[k];

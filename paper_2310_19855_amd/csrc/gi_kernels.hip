@@ -1269,6 +1269,21 @@ __device__ inline float lane_xor(float x) {
   return __uint_as_float(__builtin_amdgcn_update_dpp(0u, u, 0x4E, 0xF, 0xF, false));                 // quad_perm 2301 = xor 2
 }
 
+// balanced pairwise sum over the 64 lanes (lanes 2i and 2i + 1 first, then pairs of those
+// sums, and so on up to the two halves): the radiance backup's sum in a fixed order.
+// Each step adds the partner's value (lane ^ 1, 2, 4, 8, 16, 32); float addition commutes, so
+// both partners hold the same sum and every lane ends with the total.
+__device__ inline float wave_pair_sum(float x) {
+  x = x + __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0xB1, 0xF, 0xF, false));   // xor 1
+  x = x + __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0x4E, 0xF, 0xF, false));   // xor 2
+  x = x + __uint_as_float(__builtin_amdgcn_ds_swizzle(__float_as_uint(x), 0x101F));                       // xor 4
+  x = x + __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0x128, 0xF, 0xF, false));  // xor 8
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);                                                 // xor 16
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);                                              // xor 32
+}
+
 template <int H>
 __device__ inline void transpose_reduce_step(float (&v)[32], uint32_t lane, uint32_t& coef) {
   const bool up = (lane & (uint32_t)(2 * H)) != 0u;
@@ -1375,13 +1390,11 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
                                                                  float4* atlas, float* sh) {
   __shared__ float rv_s[kGatherWaves][MAXR][4];
   __shared__ uint32_t rc_s[kGatherWaves][MAXR];
-  __shared__ float cv_s[kGatherWaves][64][4];
   __shared__ float cs_s[kGatherWaves][64][4];
   __shared__ uint32_t cn_s[kGatherWaves][64];
   const uint32_t wv = threadIdx.x >> 6;
   float (*rv)[4] = rv_s[wv];
   uint32_t* rc = rc_s[wv];
-  float (*cv)[4] = cv_s[wv];
   float (*cs)[4] = cs_s[wv];
   uint32_t* cn = cn_s[wv];
   const uint32_t p = blockIdx.x * kGatherWaves + wv;
@@ -1405,17 +1418,13 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     if (recon) {
       const float4 r = recon[(size_t)p * 64 + lane];
-      cv[lane][0] = r.x; cv[lane][1] = r.y; cv[lane][2] = r.z; cv[lane][3] = r.w;
-      const uint64_t pop = __ballot(r.w >= 0.0f);
-      wave_sync();
-      if (r.w >= 0.0f) {
+      const bool has = r.w >= 0.0f;
+      const uint64_t pop = __ballot(has);
+      const float m0 = wave_pair_sum(has ? r.x : 0.0f), m1 = wave_pair_sum(has ? r.y : 0.0f);
+      const float m2 = wave_pair_sum(has ? r.z : 0.0f), m3 = wave_pair_sum(has ? r.w : 0.0f);
+      if (has) {
         q = r;
       } else if (pop) {
-        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
-        for (uint64_t m = pop; m; m &= m - 1u) {
-          const int i = __ffsll((long long)m) - 1;
-          m0 = m0 + cv[i][0]; m1 = m1 + cv[i][1]; m2 = m2 + cv[i][2]; m3 = m3 + cv[i][3];
-        }
         const float fn = (float)__popcll(pop);
         q = make_float4(m0 / fn, m1 / fn, m2 / fn, m3 / fn);
       }
@@ -1500,23 +1509,14 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
     const float fc = (float)cnt;
     c0 = a0 / fc; c1 = a1 / fc; c2 = a2 / fc; c3 = a3 / fc;
   }
-  cv[lane][0] = c0; cv[lane][1] = c1; cv[lane][2] = c2; cv[lane][3] = c3;
   const uint64_t populated = __ballot(cnt != 0u);
-  wave_sync();
-  if (populated != ~0ull) {
-    // radiance backup: mean of the populated cells, summed in ascending cell order (the probe
-    // filter's decisions depend on these bits); lane k < 4 sums channel k (one LDS read and one
-    // add per cell) and the empty cells read the four means
-    float mk = 0.f;
-    if (lane < 4u)
-      for (uint64_t m = populated; m; m &= m - 1u) mk = mk + cv[__ffsll((long long)m) - 1][lane];
-    const uint32_t np = (uint32_t)__popcll(populated);
-    if (np) mk = mk / (float)np;
-    const float b0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 0));
-    const float b1 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 1));
-    const float b2 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 2));
-    const float b3 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(mk), 3));
-    if (!cnt && np) {
+  if (populated != ~0ull && populated != 0ull) {
+    // radiance backup: the mean of the populated cells (a balanced pairwise sum over the 64
+    // cells, empty ones counting as zero: the probe filter's decisions depend on these bits)
+    const float fn = (float)__popcll(populated);
+    const float b0 = wave_pair_sum(c0) / fn, b1 = wave_pair_sum(c1) / fn;
+    const float b2 = wave_pair_sum(c2) / fn, b3 = wave_pair_sum(c3) / fn;
+    if (!cnt) {
       c0 = b0; c1 = b1; c2 = b2; c3 = b3;
     }
   }
