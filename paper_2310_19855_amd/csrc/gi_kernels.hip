@@ -1392,20 +1392,22 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
   __shared__ uint32_t rc_s[kGatherWaves][MAXR];
   __shared__ float cs_s[kGatherWaves][64][4];
   __shared__ uint32_t cn_s[kGatherWaves][64];
+  __shared__ unsigned long long cm_s[kGatherWaves][64];
   const uint32_t wv = threadIdx.x >> 6;
   float (*rv)[4] = rv_s[wv];
   uint32_t* rc = rc_s[wv];
   float (*cs)[4] = cs_s[wv];
   uint32_t* cn = cn_s[wv];
+  unsigned long long* cm = cm_s[wv];
   const uint32_t p = blockIdx.x * kGatherWaves + wv;
   const uint32_t lane = threadIdx.x & 63u;
   if (p >= P) return;
-  // every load that does not depend on another is issued first (the probe's records, its
-  // normal and the cell moments of the SH projection), so that their latencies overlap
+  // the probe's records and normal are loaded first, so that their latencies overlap (the
+  // cell moments of the SH projection are loaded where they are used: held from here they
+  // cost 11 registers and a wave of occupancy)
   uint4 rr0 = make_uint4(0u, 0u, 0u, 0u);
   if (lane < R) rr0 = rec[(size_t)p * R + lane];
   const float4 pn = pnrm[p];
-  const CellMoments cmo = load_moments(moments, lane);
   if (mask[p] == kSentinel) {
     atlas[(size_t)p * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (do_sh && lane < 28) sh[(size_t)p * 28 + lane] = 0.0f;
@@ -1442,68 +1444,113 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
     if (do_sh) probe_sh(p, lane, pnrm[p], load_moments(moments, lane), q.x, q.y, q.z, sh);
     return;
   }
-  for (uint32_t j = lane; j < R; j += 64) {
-    const uint4 r = j == lane ? rr0 : rec[(size_t)p * R + j];
-    float v0, v1, v2;
-    if (!(r.w & GI_RAY_HIT)) {
-      v0 = s0; v1 = s1; v2 = s2;
-    } else {
-      float le0 = 0.f, le1 = 0.f, le2 = 0.f;
-      if (r.w & GI_RAY_EMIT) {
-        const float4 e = mats[2 * __float_as_uint(tnrm[r.z].w) + 1];
-        le0 = e.x; le1 = e.y; le2 = e.z;
-      }
-      float l0 = 0.f, l1 = 0.f, l2 = 0.f;
-      const bool confident = (int32_t)r.x >= 0 && lg.meta && lg.meta[r.x].x >= 64u;
-      if (lg.lmlp && (lg.flags[4] == 0.0f || !confident)) {
-        // learned mode: the surrogate's radiance at this hit, unless the judge fell back to
-        // the plain cache and this hit's cell is confident
-        const float4 lv = lg.lmlp[(size_t)p * R + j];
-        l0 = lv.x; l1 = lv.y; l2 = lv.z;
-      } else if ((int32_t)r.x >= 0) {
-        const float4 lv = L[r.x];
-        l0 = lv.x; l1 = lv.y; l2 = lv.z;
-      }
-      v0 = le0 + l0; v1 = le1 + l1; v2 = le2 + l2;
+  // a ray's value: the sky on a miss, else the hit's front-face emission plus the cached
+  // radiance of its cell (or the surrogate's); .w = the travelled distance
+  auto ray_value = [&](const uint4 r, uint32_t j) -> float4 {
+    if (!(r.w & GI_RAY_HIT)) return make_float4(s0, s1, s2, __uint_as_float(r.y));
+    float le0 = 0.f, le1 = 0.f, le2 = 0.f;
+    if (r.w & GI_RAY_EMIT) {
+      const float4 e = mats[2 * __float_as_uint(tnrm[r.z].w) + 1];
+      le0 = e.x; le1 = e.y; le2 = e.z;
     }
-    rv[j][0] = v0; rv[j][1] = v1; rv[j][2] = v2;
-    rv[j][3] = __uint_as_float(r.y);
-    rc[j] = r.w & 63u;
-  }
-  cs[lane][0] = cs[lane][1] = cs[lane][2] = cs[lane][3] = 0.0f;
-  cn[lane] = 0u;
-  wave_sync();
-  // per-cell sums in ray order (the same float32 order as a sequential loop over the rays):
-  // in each chunk of 64 rays, the lanes whose rays share a cell are found with one ballot per
-  // bit of the cell id, and the first of them folds their rays, in ascending order, into the
-  // cell's running sums
-  for (uint32_t base = 0; base < R; base += 64u) {
-    const uint32_t j = base + lane;
-    const bool on = j < R;
-    const uint32_t c = on ? rc[j] : 0u;
-    uint64_t same = __ballot(on);
-#pragma unroll
-    for (int b = 0; b < 6; ++b) {
-      const uint64_t mb = __ballot(on && ((c >> b) & 1u));
-      same &= ((c >> b) & 1u) ? mb : ~mb;
+    float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+    const bool confident = (int32_t)r.x >= 0 && lg.meta && lg.meta[r.x].x >= 64u;
+    if (lg.lmlp && (lg.flags[4] == 0.0f || !confident)) {
+      // learned mode: the surrogate's radiance at this hit, unless the judge fell back to the
+      // plain cache and this hit's cell is confident
+      const float4 lv = lg.lmlp[(size_t)p * R + j];
+      l0 = lv.x; l1 = lv.y; l2 = lv.z;
+    } else if ((int32_t)r.x >= 0) {
+      const float4 lv = L[r.x];
+      l0 = lv.x; l1 = lv.y; l2 = lv.z;
     }
+    return make_float4(le0 + l0, le1 + l1, le2 + l2, __uint_as_float(r.y));
+  };
+  // per-cell sums in ray order (the same float32 order as a sequential loop over the rays from
+  // zero); lane k then holds cell k's sums a0..a3 and ray count
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  uint32_t cnt = 0;
+  if (MAXR <= 64) {
+    // lane j holds ray j.  The rays of each cell are marked in a per-cell lane mask (an LDS OR,
+    // whose result does not depend on order); the cell's first ray folds the others into its
+    // value, reading up to three of them at a time and adding them in ascending order
+    const bool on = lane < R;
+    const uint32_t c = rr0.w & 63u;
+    const float4 v = on ? ray_value(rr0, lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+    rv[lane][0] = v.x; rv[lane][1] = v.y; rv[lane][2] = v.z; rv[lane][3] = v.w;
+    cm[lane] = 0ull;
+    wave_sync();
+    if (on) atomicOr(&cm[c], 1ull << lane);
+    wave_sync();
+    const uint64_t mine = cm[lane];
+    const uint64_t same = on ? cm[c] : 0ull;
+    cnt = (uint32_t)__popcll(mine);
     if (on && (uint32_t)__ffsll((long long)same) - 1u == lane) {
-      float x0 = cs[c][0], x1 = cs[c][1], x2 = cs[c][2], x3 = cs[c][3];
-      uint32_t k = cn[c];
-      uint64_t m = same;
+      float x0 = 0.0f + v.x, x1 = 0.0f + v.y, x2 = 0.0f + v.z, x3 = 0.0f + v.w;
+      uint64_t m = same & (same - 1u);
       while (m) {
-        const uint32_t i = base + (uint32_t)__ffsll((long long)m) - 1u;
+        const uint32_t i1 = (uint32_t)__ffsll((long long)m) - 1u;
         m &= m - 1u;
-        x0 = x0 + rv[i][0]; x1 = x1 + rv[i][1]; x2 = x2 + rv[i][2]; x3 = x3 + rv[i][3];
-        ++k;
+        const bool h2 = m != 0u;
+        const uint32_t i2 = h2 ? (uint32_t)__ffsll((long long)m) - 1u : i1;
+        m &= m - 1u;
+        const bool h3 = m != 0u;
+        const uint32_t i3 = h3 ? (uint32_t)__ffsll((long long)m) - 1u : i1;
+        m &= m - 1u;
+        const float y10 = rv[i1][0], y11 = rv[i1][1], y12 = rv[i1][2], y13 = rv[i1][3];
+        const float y20 = rv[i2][0], y21 = rv[i2][1], y22 = rv[i2][2], y23 = rv[i2][3];
+        const float y30 = rv[i3][0], y31 = rv[i3][1], y32 = rv[i3][2], y33 = rv[i3][3];
+        x0 = x0 + y10; x1 = x1 + y11; x2 = x2 + y12; x3 = x3 + y13;
+        if (h2) { x0 = x0 + y20; x1 = x1 + y21; x2 = x2 + y22; x3 = x3 + y23; }
+        if (h3) { x0 = x0 + y30; x1 = x1 + y31; x2 = x2 + y32; x3 = x3 + y33; }
       }
       cs[c][0] = x0; cs[c][1] = x1; cs[c][2] = x2; cs[c][3] = x3;
-      cn[c] = k;
     }
     wave_sync();
+    if (cnt) {
+      a0 = cs[lane][0]; a1 = cs[lane][1]; a2 = cs[lane][2]; a3 = cs[lane][3];
+    }
+  } else {
+    for (uint32_t j = lane; j < R; j += 64) {
+      const uint4 r = j == lane ? rr0 : rec[(size_t)p * R + j];
+      const float4 v = ray_value(r, j);
+      rv[j][0] = v.x; rv[j][1] = v.y; rv[j][2] = v.z; rv[j][3] = v.w;
+      rc[j] = r.w & 63u;
+    }
+    cs[lane][0] = cs[lane][1] = cs[lane][2] = cs[lane][3] = 0.0f;
+    cn[lane] = 0u;
+    wave_sync();
+    // in each chunk of 64 rays, the lanes whose rays share a cell are found with one ballot per
+    // bit of the cell id, and the first of them folds their rays, in ascending order, into the
+    // cell's running sums
+    for (uint32_t base = 0; base < R; base += 64u) {
+      const uint32_t j = base + lane;
+      const bool on = j < R;
+      const uint32_t c = on ? rc[j] : 0u;
+      uint64_t same = __ballot(on);
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        const uint64_t mb = __ballot(on && ((c >> b) & 1u));
+        same &= ((c >> b) & 1u) ? mb : ~mb;
+      }
+      if (on && (uint32_t)__ffsll((long long)same) - 1u == lane) {
+        float x0 = cs[c][0], x1 = cs[c][1], x2 = cs[c][2], x3 = cs[c][3];
+        uint32_t k = cn[c];
+        uint64_t m = same;
+        while (m) {
+          const uint32_t i = base + (uint32_t)__ffsll((long long)m) - 1u;
+          m &= m - 1u;
+          x0 = x0 + rv[i][0]; x1 = x1 + rv[i][1]; x2 = x2 + rv[i][2]; x3 = x3 + rv[i][3];
+          ++k;
+        }
+        cs[c][0] = x0; cs[c][1] = x1; cs[c][2] = x2; cs[c][3] = x3;
+        cn[c] = k;
+      }
+      wave_sync();
+    }
+    a0 = cs[lane][0]; a1 = cs[lane][1]; a2 = cs[lane][2]; a3 = cs[lane][3];
+    cnt = cn[lane];
   }
-  const float a0 = cs[lane][0], a1 = cs[lane][1], a2 = cs[lane][2], a3 = cs[lane][3];
-  const uint32_t cnt = cn[lane];
   float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
   if (cnt) {
     const float fc = (float)cnt;
@@ -1540,7 +1587,7 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
     }
   }
   atlas[(size_t)p * 64 + lane] = make_float4(c0, c1, c2, c3);
-  if (do_sh) probe_sh(p, lane, pn, cmo, c0, c1, c2, sh);
+  if (do_sh) probe_sh(p, lane, pn, load_moments(moments, lane), c0, c1, c2, sh);
 }
 
 // Algorithm 4: first valid probe of the probe-mask MIP chain at a tile offset from a pixel's tile
