@@ -2254,7 +2254,8 @@ static void cache_update(state *st)
  * Probe gather (Section 2.1.4): per probe, every ray's radiance (sky on a miss, else the
  * hit's front-face emission plus the updated cached outgoing radiance) is averaged per
  * atlas cell in ray order; cells that received no ray get the mean of the populated cells
- * (radiance backup); alpha holds the mean travelled distance.
+ * (radiance backup); alpha holds the mean travelled distance.  Every mean here is its sum
+ * times the rounded reciprocal of its count (the paper fixes no rounding).
  * ------------------------------------------------------------------------------------- */
 /* The radiance backup's mean (Section 2.1.4 fills the cells without rays with the average of
  * the populated ones; the order of that sum is not given): a balanced pairwise sum over the
@@ -2294,7 +2295,8 @@ static void gather(state *st)
                     npop += (uint32_t)has;
                 }
                 if (npop == 0) continue;
-                for (int k = 0; k < 4; ++k) mean[k] = pair_sum64(val + k, 4) / (real)npop;
+                const real inv = RC(1.0) / (real)npop;
+                for (int k = 0; k < 4; ++k) mean[k] = pair_sum64(val + k, 4) * inv;
                 for (int i = 0; i < NCELL; ++i)
                     for (int k = 0; k < 4; ++k) at[4 * i + k] = rc[4 * i + 3] < RC(0.0) ? mean[k] : rc[4 * i + k];
             } else if (st->hist[p] != SENTINEL) {
@@ -2330,11 +2332,13 @@ static void gather(state *st)
         uint32_t npop = 0;
         for (int i = 0; i < NCELL; ++i) {
             if (!cnt[i]) continue;
-            for (int k = 0; k < 4; ++k) at[4 * i + k] = sum[i][k] / (real)cnt[i];
+            const real inv = RC(1.0) / (real)cnt[i];
+            for (int k = 0; k < 4; ++k) at[4 * i + k] = sum[i][k] * inv;
             ++npop;
         }
         if (npop == 0) continue;
-        for (int k = 0; k < 4; ++k) mean[k] = pair_sum64(at + k, 4) / (real)npop;
+        const real inv = RC(1.0) / (real)npop;
+        for (int k = 0; k < 4; ++k) mean[k] = pair_sum64(at + k, 4) * inv;
         for (int i = 0; i < NCELL; ++i)
             if (!cnt[i])
                 for (int k = 0; k < 4; ++k) at[4 * i + k] = mean[k];

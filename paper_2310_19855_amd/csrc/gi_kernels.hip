@@ -1402,11 +1402,9 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
   const uint32_t p = blockIdx.x * kGatherWaves + wv;
   const uint32_t lane = threadIdx.x & 63u;
   if (p >= P) return;
-  // the probe's records and normal are loaded first, so that their latencies overlap (the
-  // cell moments of the SH projection are loaded where they are used: held from here they
-  // cost 11 registers and a wave of occupancy)
-  uint4 rr0 = make_uint4(0u, 0u, 0u, 0u);
-  if (lane < R) rr0 = rec[(size_t)p * R + lane];
+  // the ray records are read once the probe is known to be traced (a third of the probes of
+  // an outdoor view are sky, whose records hold nothing); the cell moments of the SH projection
+  // are loaded where they are used (held from the start they cost a wave of occupancy)
   const float4 pn = pnrm[p];
   if (mask[p] == kSentinel) {
     atlas[(size_t)p * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1427,8 +1425,8 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
       if (has) {
         q = r;
       } else if (pop) {
-        const float fn = (float)__popcll(pop);
-        q = make_float4(m0 / fn, m1 / fn, m2 / fn, m3 / fn);
+        const float inv = 1.0f / (float)__popcll(pop);
+        q = make_float4(m0 * inv, m1 * inv, m2 * inv, m3 * inv);
       }
     } else {
       const uint32_t hp = hist ? hist[p] : kSentinel;
@@ -1444,6 +1442,8 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
     if (do_sh) probe_sh(p, lane, pnrm[p], load_moments(moments, lane), q.x, q.y, q.z, sh);
     return;
   }
+  uint4 rr0 = make_uint4(0u, 0u, 0u, 0u);
+  if (lane < R) rr0 = rec[(size_t)p * R + lane];
   // a ray's value: the sky on a miss, else the hit's front-face emission plus the cached
   // radiance of its cell (or the surrogate's); .w = the travelled distance
   auto ray_value = [&](const uint4 r, uint32_t j) -> float4 {
@@ -1553,16 +1553,17 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_sh(const uint32_t*
   }
   float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
   if (cnt) {
-    const float fc = (float)cnt;
-    c0 = a0 / fc; c1 = a1 / fc; c2 = a2 / fc; c3 = a3 / fc;
+    // every mean is its sum times the rounded reciprocal of its count
+    const float inv = 1.0f / (float)cnt;
+    c0 = a0 * inv; c1 = a1 * inv; c2 = a2 * inv; c3 = a3 * inv;
   }
   const uint64_t populated = __ballot(cnt != 0u);
   if (populated != ~0ull && populated != 0ull) {
     // radiance backup: the mean of the populated cells (a balanced pairwise sum over the 64
     // cells, empty ones counting as zero: the probe filter's decisions depend on these bits)
-    const float fn = (float)__popcll(populated);
-    const float b0 = wave_pair_sum(c0) / fn, b1 = wave_pair_sum(c1) / fn;
-    const float b2 = wave_pair_sum(c2) / fn, b3 = wave_pair_sum(c3) / fn;
+    const float inv = 1.0f / (float)__popcll(populated);
+    const float b0 = wave_pair_sum(c0) * inv, b1 = wave_pair_sum(c1) * inv;
+    const float b2 = wave_pair_sum(c2) * inv, b3 = wave_pair_sum(c3) * inv;
     if (!cnt) {
       c0 = b0; c1 = b1; c2 = b2; c3 = b3;
     }
