@@ -1332,22 +1332,27 @@ __device__ inline void probe_sh(uint32_t p, uint32_t lane, float4 nn, const Cell
   const float om = mo[0];
   const float mlx = mo[1], mly = mo[2], mlz = mo[3];
   const float Mxx = mo[4], Myy = mo[5], Mzz = mo[6], Mxy = mo[7], Mxz = mo[8], Myz = mo[9];
-  const float mwx = R00 * mlx + R01 * mly + R02 * mlz;
-  const float mwy = R10 * mlx + R11 * mly + R12 * mlz;
-  const float mwz = R20 * mlx + R21 * mly + R22 * mlz;
+  // the projection is compared within a tolerance (no integer decision depends on its bits),
+  // so its dot products are fused multiply-adds
+  auto dot3 = [](float a0, float b0, float a1, float b1, float a2, float b2) {
+    return fmaf(a0, b0, fmaf(a1, b1, a2 * b2));
+  };
+  const float mwx = dot3(R00, mlx, R01, mly, R02, mlz);
+  const float mwy = dot3(R10, mlx, R11, mly, R12, mlz);
+  const float mwz = dot3(R20, mlx, R21, mly, R22, mlz);
   // T = R M (rows i), W = T R^T
-  const float T00 = R00 * Mxx + R01 * Mxy + R02 * Mxz, T01 = R00 * Mxy + R01 * Myy + R02 * Myz,
-              T02 = R00 * Mxz + R01 * Myz + R02 * Mzz;
-  const float T10 = R10 * Mxx + R11 * Mxy + R12 * Mxz, T11 = R10 * Mxy + R11 * Myy + R12 * Myz,
-              T12 = R10 * Mxz + R11 * Myz + R12 * Mzz;
-  const float T20 = R20 * Mxx + R21 * Mxy + R22 * Mxz, T21 = R20 * Mxy + R21 * Myy + R22 * Myz,
-              T22 = R20 * Mxz + R21 * Myz + R22 * Mzz;
-  const float Wxx = T00 * R00 + T01 * R01 + T02 * R02;
-  const float Wyy = T10 * R10 + T11 * R11 + T12 * R12;
-  const float Wzz = T20 * R20 + T21 * R21 + T22 * R22;
-  const float Wxy = T00 * R10 + T01 * R11 + T02 * R12;
-  const float Wxz = T00 * R20 + T01 * R21 + T02 * R22;
-  const float Wyz = T10 * R20 + T11 * R21 + T12 * R22;
+  const float T00 = dot3(R00, Mxx, R01, Mxy, R02, Mxz), T01 = dot3(R00, Mxy, R01, Myy, R02, Myz),
+              T02 = dot3(R00, Mxz, R01, Myz, R02, Mzz);
+  const float T10 = dot3(R10, Mxx, R11, Mxy, R12, Mxz), T11 = dot3(R10, Mxy, R11, Myy, R12, Myz),
+              T12 = dot3(R10, Mxz, R11, Myz, R12, Mzz);
+  const float T20 = dot3(R20, Mxx, R21, Mxy, R22, Mxz), T21 = dot3(R20, Mxy, R21, Myy, R22, Myz),
+              T22 = dot3(R20, Mxz, R21, Myz, R22, Mzz);
+  const float Wxx = dot3(T00, R00, T01, R01, T02, R02);
+  const float Wyy = dot3(T10, R10, T11, R11, T12, R12);
+  const float Wzz = dot3(T20, R20, T21, R21, T22, R22);
+  const float Wxy = dot3(T00, R10, T01, R11, T02, R12);
+  const float Wxz = dot3(T00, R20, T01, R21, T02, R22);
+  const float Wyz = dot3(T10, R20, T11, R21, T12, R22);
   const float k0 = 0.28209479177387814f, k1 = 0.48860251190291992f, k2 = 1.09254843059207907f,
               k20 = 0.31539156525252005f, k22 = 0.54627421529603959f;
   const float I[9] = {k0 * om, k1 * mwy, k1 * mwz, k1 * mwx, k2 * Wxy, k2 * Wyz, k20 * (3.0f * Wzz - om),
