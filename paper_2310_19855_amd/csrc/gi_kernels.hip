@@ -12,6 +12,14 @@ namespace gi {
 constexpr int kTraceBlock = 64;   // one wave per block: the LDS part of the stack is [K][64]
 constexpr int kLdsStack = kLdsStackEntries;   // traversal-stack entries per lane in LDS (the rest spill)
 
+// orders the LDS accesses of one wave (a block barrier is not needed when no other wave of the
+// block reads them)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct ShadeTables {
   const float4* tnrm;    // unit normal, w = material index bits
   const float4* mats;    // [2m] albedo, [2m+1] emission
@@ -1017,8 +1025,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
                                                             CacheArgs c, uint4* rec, uint2* rkey, HitList hl,
                                                             LearnedShadeOut lo, RestirArgs ra,
                                                             unsigned long long* stats) {
-  __shared__ uint32_t stk[STACK * kTraceBlock];
+  // the traversal stacks; after the walks their LDS holds the wave's entry grouping
+  __shared__ __align__(8) uint32_t stk[STACK * kTraceBlock];
   __shared__ uint16_t stkt[STACK * kTraceBlock];
+  static_assert(STACK * kTraceBlock >= 576, "the entry grouping needs 576 words of the stack's LDS");
   // block b shades items [w * 64, w * 64 + 64) of list stripe b / blocks_per_stripe
   const uint32_t stripe = blockIdx.x / hl.blocks_per_stripe;
   const uint32_t item = (blockIdx.x % hl.blocks_per_stripe) * kTraceBlock + threadIdx.x;
@@ -1126,24 +1136,41 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const uint32_t q2 = (uint32_t)rintf(fminf(fmaxf(s2, 0.0f), c.r_max) * scale);
   // the lanes of this wave that add to one entry are summed first, by the first of them, which
   // issues the entry's atomics once (integer sums: the grouping does not change the result,
-  // nor the number of carries, as every partial sum stays below 2^32)
+  // nor the number of carries, as every partial sum stays below 2^32).  The lanes of an entry
+  // are found through a wave-private hash of the entries in the stacks' LDS (insert by
+  // compare-and-swap with linear probing, then an OR of the lane's bit; 128 places for at most
+  // 64 entries, so every insert ends)
   const uint32_t ent = (uint32_t)slot;
+  const uint32_t lane = threadIdx.x & 63u;
   const uint64_t active = __ballot(true);
-  uint64_t same = active;
-#pragma unroll
-  for (int b = 0; b < 32; ++b) {
-    const uint64_t mb = __ballot((ent >> b) & 1u);
-    same &= ((ent >> b) & 1u) ? mb : ~mb;
+  const uint32_t nact = (uint32_t)__popcll(active), rank = (uint32_t)__popcll(active & lanes_below());
+  uint32_t* keys = stk;                                                          // entry + 1, 0 = free
+  unsigned long long* lanes = reinterpret_cast<unsigned long long*>(stk + 128);   // lane mask per place
+  uint32_t* qv = stk + 384;                                                      // [64][3] samples
+  wave_sync();
+  for (uint32_t k = rank; k < 128u; k += nact) {
+    keys[k] = 0u;
+    lanes[k] = 0ull;
   }
+  qv[3 * lane] = q0;
+  qv[3 * lane + 1] = q1;
+  qv[3 * lane + 2] = q2;
+  wave_sync();
+  uint32_t h = (ent * 0x9E3779B1u) >> 25;
+  while (true) {
+    const uint32_t old = atomicCAS(&keys[h], 0u, ent + 1u);
+    if (old == 0u || old == ent + 1u) break;
+    h = (h + 1u) & 127u;
+  }
+  atomicOr(&lanes[h], 1ull << lane);
+  wave_sync();
+  const uint64_t same = lanes[h];
   uint32_t g0 = 0u, g1 = 0u, g2 = 0u;
-  for (uint64_t m = active; m; m &= m - 1u) {
+  for (uint64_t m = (uint32_t)__ffsll((long long)same) - 1u == lane ? same : 0ull; m; m &= m - 1u) {
     const int i = __ffsll((long long)m) - 1;
-    const uint32_t v0 = __shfl(q0, i, 64), v1 = __shfl(q1, i, 64), v2 = __shfl(q2, i, 64);
-    if ((same >> i) & 1u) {
-      g0 += v0;
-      g1 += v1;
-      g2 += v2;
-    }
+    g0 += qv[3 * i];
+    g1 += qv[3 * i + 1];
+    g2 += qv[3 * i + 2];
   }
   if ((uint32_t)__ffsll((long long)same) - 1u == (threadIdx.x & 63u)) {
     uint32_t* accp = reinterpret_cast<uint32_t*>(c.acc + slot);
@@ -1250,14 +1277,6 @@ __global__ __launch_bounds__(256) void k_cache_update(uint32_t N, uint32_t* fp, 
 // 64-entry ray stage, which cuts its LDS from 7.25 to 3.25 KiB and lets more waves share a CU
 constexpr int kGatherMaxR = 256;
 constexpr uint32_t kGatherWaves = 4;
-
-// orders the LDS accesses of one wave (a block barrier is not needed when no other wave of the
-// block reads them)
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // one butterfly step of a transpose-reduce over the first 2H entries of v: lanes whose bit
 // log2(2H) is set keep the upper half, the others the lower half, each adding its partner's copy
