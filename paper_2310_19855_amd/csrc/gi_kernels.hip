@@ -648,14 +648,20 @@ struct LightSample {
   uint32_t mat;
 };
 
-__device__ inline LightSample sample_light(const ShadeTables& st, uint32_t seed, uint32_t frame, uint32_t gid, float px,
-                                           float py, float pz, float nx, float ny, float nz) {
-  LightSample ls;
-  ls.cast = false;
-  ls.tmax = 0.0f;
-  ls.g = 0.0f;
-  ls.mat = 0;
-  if (st.n_emit == 0) return ls;
+// the part of the light sample that does not depend on the hit: the emitter (its index, the
+// point on it and its normal), so that its loads can be issued before the hit's own
+struct LightPick {
+  uint32_t e;
+  float xlx, xly, xlz;
+  float4 ne;
+};
+
+__device__ inline LightPick pick_light(const ShadeTables& st, uint32_t seed, uint32_t frame, uint32_t gid) {
+  LightPick lp;
+  lp.e = 0u;
+  lp.xlx = lp.xly = lp.xlz = 0.0f;
+  lp.ne = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (st.n_emit == 0) return lp;
   const uint32_t rsel = rand_u32(seed, frame, gid, 2u);
   uint32_t lo = 0, hi = st.n_emit - 1u;
   while (lo < hi) {
@@ -663,21 +669,33 @@ __device__ inline LightSample sample_light(const ShadeTables& st, uint32_t seed,
     if (rsel < st.ethr[mid]) hi = mid;
     else lo = mid + 1u;
   }
-  const uint32_t e = st.etri[lo];
+  lp.e = st.etri[lo];
   const float u3 = rand_unit(rand_u32(seed, frame, gid, 3u));
   const float u4 = rand_unit(rand_u32(seed, frame, gid, 4u));
   const float su = sqrtf(u3);
   const float b0 = 1.0f - su, b1 = su * (1.0f - u4), b2 = su * u4;
   const float4 A = st.evert[3 * lo], B = st.evert[3 * lo + 1], C = st.evert[3 * lo + 2];
-  const float xlx = (b0 * A.x + b1 * B.x) + b2 * C.x;
-  const float xly = (b0 * A.y + b1 * B.y) + b2 * C.y;
-  const float xlz = (b0 * A.z + b1 * B.z) + b2 * C.z;
-  const float wx = xlx - px, wy = xly - py, wz = xlz - pz;
+  lp.xlx = (b0 * A.x + b1 * B.x) + b2 * C.x;
+  lp.xly = (b0 * A.y + b1 * B.y) + b2 * C.y;
+  lp.xlz = (b0 * A.z + b1 * B.z) + b2 * C.z;
+  lp.ne = st.tnrm[lp.e];
+  return lp;
+}
+
+__device__ inline LightSample sample_light(const ShadeTables& st, const LightPick& lp, float px, float py, float pz,
+                                           float nx, float ny, float nz) {
+  LightSample ls;
+  ls.cast = false;
+  ls.tmax = 0.0f;
+  ls.g = 0.0f;
+  ls.mat = 0;
+  if (st.n_emit == 0) return ls;
+  const float wx = lp.xlx - px, wy = lp.xly - py, wz = lp.xlz - pz;
   const float d2 = (wx * wx + wy * wy) + wz * wz;
   if (!(d2 > 0.0f)) return ls;
   const float dist = sqrtf(d2);
   const float omx = wx / dist, omy = wy / dist, omz = wz / dist;
-  const float4 ne = st.tnrm[e];
+  const float4 ne = lp.ne;
   const float cos_y = (nx * omx + ny * omy) + nz * omz;
   const float cos_l = -((ne.x * omx + ne.y * omy) + ne.z * omz);
   if (!(cos_y > 0.0f && cos_l > 0.0f)) return ls;
@@ -1036,6 +1054,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const uint32_t gid = hl.ids[stripe * hl.stripe_cap + item];
   TStack<STACK, kTraceBlock> ts(stk + threadIdx.x, stkt + threadIdx.x, sv.spill + gid, sv.spill_stride);
   const uint4 rr = rec[gid];
+  // the emitter of the light sample depends on the ray's random numbers only: its loads go
+  // first, beside the hit's
+  const LightPick lpick = st.lg_list ? LightPick{} : pick_light(st, a.seed, a.frame, gid);
   stat_add(stats, GI_STAT_HITS, true);
   const uint32_t p = gid / a.R;
   float ox, oy, oz, dx, dy, dz;
@@ -1061,8 +1082,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   stat_add(stats, GI_STAT_INSERTS, inserted);
   stat_add(stats, GI_STAT_OVERFLOW, tslot < 0);
   // set once: with tiles thousands of hits share one flag, and a store from each would queue
-  // at its L2 line
-  if (tslot >= 0 && c.accessed[tslot] == 0u) c.accessed[tslot] = 1u;
+  // at its L2 line (the flag is read here and written after the light sample, so that the
+  // read's latency passes meanwhile)
+  const uint32_t was_accessed = tslot >= 0 ? c.accessed[tslot] : 1u;
   const int32_t slot = cache_entry(c, tslot, tcell);
 
   // one light sample: area-proportional emitter, uniform point, one shadow ray
@@ -1070,7 +1092,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   const float px = yx + nx * eps, py = yy + ny * eps, pz = yz + nz * eps;
   float E0 = 0.f, E1 = 0.f, E2 = 0.f;
   const LightSample ls = st.lg_list ? sample_light_ris(st, ra, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
-                                    : sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
+                                    : sample_light(st, lpick, px, py, pz, nx, ny, nz);
   const bool cast = ls.cast;
   bool occl = false;
   if (cast) {
@@ -1084,6 +1106,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_hits(SceneView sv, ShadeT
   }
   stat_add(stats, GI_STAT_SHADOW, cast);
   stat_add(stats, GI_STAT_OCCLUDED, occl);
+  if (was_accessed == 0u) c.accessed[tslot] = 1u;
   // cached bounce (temporal radiance feedback, Section 2.2.4)
   float Lb0 = 0.f, Lb1 = 0.f, Lb2 = 0.f;
   if (c.bounces >= 2) {
@@ -2019,7 +2042,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_count_traversal(SceneView sv, S
         const float px = yx + nx * eps, py = yy + ny * eps, pz = yz + nz * eps;
         const LightSample ls = st.lg_list
                                    ? sample_light_ris(st, ra, a.seed, a.frame, gid, yx, yy, yz, px, py, pz, nx, ny, nz)
-                                   : sample_light(st, a.seed, a.frame, gid, px, py, pz, nx, ny, nz);
+                                   : sample_light(st, pick_light(st, a.seed, a.frame, gid), px, py, pz, nx, ny, nz);
         if (ls.cast) {
           shadow = true;
           (void)any_hit<STACK, kTraceBlock, true>(sv, ls.ray, ls.tmax, ts, &sn, &st_);
