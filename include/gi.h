@@ -380,8 +380,10 @@ gi_status gi_get_dims(gi_context *ctx, uint32_t *h_out16);
 gi_status gi_get_stats(gi_context *ctx, uint64_t *h_out16);
 gi_status gi_reset_stats(gi_context *ctx, void *stream);
 
-/* Per-kernel device timing with HIP events on the launch stream: enable (1) / disable (0);
- * read returns, for up to cap kernels, NUL-separated names, launch counts and total ms since
+/* Per-kernel device timing with HIP events on the launch stream: on = 1 times every kernel,
+ * on = 2 only the probe-ray traversal (two events per frame, so a measured run stays as it
+ * is), 0 none; other values are GI_ERR_INVALID_ARG.  The events skip the system-scope fence.
+ * Read returns, for up to cap kernels, NUL-separated names, launch counts and total ms since
  * the last read, and resets the totals.  Reading synchronises. */
 gi_status gi_profile_enable(gi_context *ctx, uint32_t on);
 gi_status gi_profile_read(gi_context *ctx, char *h_names, size_t names_cap, uint32_t *h_counts,

@@ -1134,8 +1134,8 @@ gi_status gi_reset_stats(gi_context* c, void* stream) {
 }
 
 gi_status gi_profile_enable(gi_context* c, uint32_t on) {
-  if (!c) return GI_ERR_INVALID_ARG;
-  c->prof = on != 0;
+  if (!c || on > 2u) return GI_ERR_INVALID_ARG;
+  c->prof = on;
   return GI_OK;
 }
 

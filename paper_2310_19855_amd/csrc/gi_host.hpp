@@ -146,7 +146,7 @@ struct gi_context {
   std::vector<uint32_t> h_etri, h_ethr;   // current emitter table (host mirror)
   std::vector<float> h_evert;
   // profiling
-  bool prof = false;
+  uint32_t prof = 0;   // kernel timers: 0 off, 1 every kernel, 2 the probe-ray traversal only
   std::vector<gi::KernelTimer> timers;
   std::vector<hipEvent_t> event_pool;
   std::vector<std::string> prof_names;

@@ -2,6 +2,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <mutex>
 
 #include "gi_device.hpp"
@@ -2188,13 +2189,16 @@ static RestirArgs restir_args(const gi_context* c) {
   return r;
 }
 
+// the per-kernel timers only measure: their events skip the system-scope fence (the cache
+// writeback and invalidation it costs would slow the next kernel and lengthen short ones)
+static hipError_t timer_event(hipEvent_t* e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 void timer_begin(gi_context* c, const char* name, hipStream_t s, hipEvent_t* a) {
-  (void)name;
   *a = nullptr;
-  if (!c->prof) return;
+  if (!c->prof || (c->prof == 2u && std::strcmp(name, "trace_probes") != 0)) return;
   if (c->event_pool.empty()) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (timer_event(&e) != hipSuccess) return;
     c->event_pool.push_back(e);
   }
   *a = c->event_pool.back();
@@ -2206,7 +2210,7 @@ void timer_end(gi_context* c, const char* name, hipStream_t s, hipEvent_t a) {
   if (!c->prof || !a) return;
   hipEvent_t b;
   if (c->event_pool.empty()) {
-    if (hipEventCreate(&b) != hipSuccess) return;
+    if (timer_event(&b) != hipSuccess) return;
   } else {
     b = c->event_pool.back();
     c->event_pool.pop_back();

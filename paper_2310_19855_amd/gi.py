@@ -447,7 +447,8 @@ class Context:
                                                   C.byref(rows), C.byref(n)), "gi_learned_batch_export")
         return dict(raw=raw, grouped=grouped, gid=raw[:, 1, 3].view(np.uint32).copy(), n_train=int(n.value))
 
-    def profile(self, on: bool):
+    def profile(self, on):
+        """True / 1: time every kernel; 2: only the probe-ray traversal; False / 0: off"""
         self._check(lib().gi_profile_enable(self.h, int(on)), "gi_profile_enable")
 
     def profile_read(self):
