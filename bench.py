@@ -254,8 +254,18 @@ def headline(args, log):
         "gather_sh": rays_per_frame * 32 + P * (64 * 16 + 112 + 16),
         "interpolate": W * H * (52 + 16) + P * 144,
     }
+    if args.form in ("mlp_bf16", "mlp_fp8"):
+        # one optimiser step's gradient sort: 8 corner pairs per level and sample, each pass of
+        # the 8-bit LSD sort reads the 4-B key for its histogram, then reads and writes the
+        # 12-B pair
+        n_pairs = (1 << MLP_CFG["mlp_batch_log2"]) * MLP_CFG["mlp_levels"] * 8
+        key_bits = (MLP_CFG["mlp_levels"] - 1).bit_length() + MLP_CFG["mlp_table_log2"]
+        alg["learned_grad_sort"] = n_pairs * 28 * ((key_bits + 7) // 8)
     total_ms = sum(v["avg_ms"] * v["launches"] for v in kern.values()) / max(args.profile_frames, 1)
-    dom = max(kern.items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])[0]
+    # the dominant kernel among those with algorithmic bytes (stages such as the learned
+    # training, a mix of gathers and matrix work, have none)
+    dom = max(((k, v) for k, v in kern.items() if k in alg),
+              key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])[0]
     for name, v in kern.items():
         if name in alg:
             v["alg_bytes"] = int(alg[name])

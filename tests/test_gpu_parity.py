@@ -638,6 +638,8 @@ def test_invalid_arguments_and_frame_order():
     ctx = gi.Context(width=64, height=64, cache_tiles=1, table_log2=8)
     with pytest.raises(gi.GIError, match="UNSUPPORTED"):
         ctx.table()                                          # per-cell export of the single-level cache
+    with pytest.raises(gi.GIError, match="INVALID"):
+        ctx.profile(3)                                       # timer levels are 0, 1 and 2
     ctx.close()
 
 
