@@ -47,7 +47,7 @@ enum {
     GI_ERR_OOM = -2,          /* device or host allocation failed */
     GI_ERR_HIP = -3,          /* a HIP runtime call failed */
     GI_ERR_STATE = -4,        /* call out of frame order, or before gi_build_bvh */
-    GI_ERR_UNSUPPORTED = -5,  /* device is not gfx950, or a feature outside this build */
+    GI_ERR_UNSUPPORTED = -5,  /* device is not gfx950, or a feature the library does not provide */
     GI_ERR_INTERNAL = -6      /* unexpected failure (message in gi_last_error) */
 };
 

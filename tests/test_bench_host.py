@@ -1,5 +1,5 @@
 """Host-side legs of bench.py: the CPU oracle baseline and the Table-1 grouping run without a
-GPU, so that the benchmark's line cannot fail in them on the GPU machine."""
+GPU, so that a mistake in them cannot keep the benchmark from printing its line."""
 import json
 import os
 import subprocess
