@@ -1094,15 +1094,19 @@ __global__ void k_zero_f32(float* p, uint64_t n) {
 
 // ---- inference: one wave evaluates 64 points (4 row tiles) ------------------------------
 
-struct InferSmem {
+// one activation tile per wave, BF16 or e4m3 rows: each layer's outputs stay in the MFMA
+// accumulators until every product has read the tile, then overwrite it in place (one tile
+// instead of a ping-pong pair per precision: 9 KiB per wave, so 17 waves share a CU's LDS)
+union InferSmem {
   __bf16 A[64 * kLd64];
-  __bf16 B[64 * kLd64];
   uint8_t A8[64 * 80];
-  uint8_t B8[64 * 80];
+  float y[64 * 4];
 };
 
+// 4 waves per SIMD is what the activation tile's LDS allows; asked for, the compiler keeps the
+// layer accumulators in VGPRs instead of adding AGPRs on top of the gather phase's registers
 template <bool FP8, bool HITLIST>
-__global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* grid_h, const __bf16* wb,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_infer(LearnedParams lp, const __half* grid_h, const __bf16* wb,
                                               const uint8_t* w8, const float* scales, const float4* pos,
                                               const float4* nrm, uint32_t n, const uint32_t* list_ids,
                                               const uint32_t* list_count, uint32_t stripe_cap,
@@ -1129,10 +1133,16 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
   }
   float x0, x1, x2;
   norm_pos(lp, p4.x, p4.y, p4.z, x0, x1, x2);
-  // encoding + inputs of this lane's row
-  float feat[64];
-#pragma unroll
-  for (int c = 0; c < 64; ++c) feat[c] = 0.0f;
+  // the input row of this lane (64 features: 2 per level, the normal mapped to [0, 1], a 1,
+  // zeros) goes straight into the tile, as BF16 or as e4m3 codes of feature x (1 / s_x) (the
+  // activation scales' reciprocals are taken once: this quantisation is the kernel's own
+  // approximation, held to a tolerance against the float64 forward pass)
+  const float sx = FP8 ? scales[6] : 1.0f;
+  const float rsx = FP8 ? 1.0f / sx : 1.0f;
+  auto put = [&](int c, float v) {
+    if (FP8) S.A8[lane * 80 + c] = (uint8_t)e4m3_code(v * rsx);
+    else S.A[lane * kLd64 + c] = to_bf16(v);
+  };
   // levels in groups of 4: the group's 32 corner loads are issued together (levels past L
   // load level L - 1's entries and are dropped), then summed per level in corner order
 #pragma unroll
@@ -1158,116 +1168,90 @@ __global__ __launch_bounds__(64) void k_infer(LearnedParams lp, const __half* gr
         f1 = f1 + cn[q].w[c] * v.y;
       }
       if (gl + q < (int)lp.L) {
-        feat[2 * (gl + q)] = f0;
-        feat[2 * (gl + q) + 1] = f1;
+        put(2 * (gl + q), f0);
+        put(2 * (gl + q) + 1, f1);
       }
     }
   }
-  feat[32] = (n4.x + 1.0f) * 0.5f;
-  feat[33] = (n4.y + 1.0f) * 0.5f;
-  feat[34] = (n4.z + 1.0f) * 0.5f;
-  feat[35] = 1.0f;
+  for (int c = 2 * (int)lp.L; c < 32; ++c) put(c, 0.0f);
+  put(32, (n4.x + 1.0f) * 0.5f);
+  put(33, (n4.y + 1.0f) * 0.5f);
+  put(34, (n4.z + 1.0f) * 0.5f);
+  put(35, 1.0f);
+#pragma unroll
+  for (int c = 36; c < 64; ++c) put(c, 0.0f);
+  __syncthreads();
   const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
-  float y0 = 0.f, y1 = 0.f, y2 = 0.f;
-  if (!FP8) {
-#pragma unroll
-    for (int c = 0; c < 64; ++c) S.A[lane * kLd64 + c] = to_bf16(feat[c]);
-    __syncthreads();
-    const __bf16* W1 = wb;
-    const __bf16* W2 = wb + 8192;
-    const __bf16* W3 = wb + 16384;
-    // layer 1 -> B, layer 2 -> A, layer 3 -> registers
+  // one hidden layer: the 16 output tiles of tile x W^T, then (after every product has read
+  // the tile) relu, rescaled and rounded to the tile's format, in place
+  auto hidden = [&](const void* W, float dq, float rsn) {
+    f32x4_t acc[16];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
         f32x4_t a = z4;
-        a = mma_bf16(S.A + 16 * mt * kLd64, kLd64, W1 + 16 * nt * 64, 64, a);
-        a = mma_bf16(S.A + 16 * mt * kLd64 + 32, kLd64, W1 + 16 * nt * 64 + 32, 64, a);
-        const int col = 16 * nt + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) S.B[(16 * mt + 4 * (lane >> 4) + i) * kLd64 + col] = to_bf16(fmaxf(a[i], 0.0f));
+        if (FP8) {
+          const uint8_t* W8 = static_cast<const uint8_t*>(W);
+          a = mma_fp8(S.A8 + 16 * mt * 80, 80, W8 + 16 * nt * 64, 64, a);
+          a = mma_fp8(S.A8 + 16 * mt * 80 + 32, 80, W8 + 16 * nt * 64 + 32, 64, a);
+        } else {
+          const __bf16* Wb = static_cast<const __bf16*>(W);
+          a = mma_bf16(S.A + 16 * mt * kLd64, kLd64, Wb + 16 * nt * 64, 64, a);
+          a = mma_bf16(S.A + 16 * mt * kLd64 + 32, kLd64, Wb + 16 * nt * 64 + 32, 64, a);
+        }
+        acc[4 * mt + nt] = a;
       }
     __syncthreads();
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t a = z4;
-        a = mma_bf16(S.B + 16 * mt * kLd64, kLd64, W2 + 16 * nt * 64, 64, a);
-        a = mma_bf16(S.B + 16 * mt * kLd64 + 32, kLd64, W2 + 16 * nt * 64 + 32, 64, a);
         const int col = 16 * nt + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) S.A[(16 * mt + 4 * (lane >> 4) + i) * kLd64 + col] = to_bf16(fmaxf(a[i], 0.0f));
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * mt + 4 * (lane >> 4) + i;
+          if (FP8) S.A8[row * 80 + col] = (uint8_t)e4m3_code(fmaxf(acc[4 * mt + nt][i] * dq, 0.0f) * rsn);
+          else S.A[row * kLd64 + col] = to_bf16(fmaxf(acc[4 * mt + nt][i], 0.0f));
+        }
       }
     __syncthreads();
-    float* yo = reinterpret_cast<float*>(S.B);   // [64][4] outputs
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      f32x4_t a = z4;
-      a = mma_bf16(S.A + 16 * mt * kLd64, kLd64, W3, 64, a);
-      a = mma_bf16(S.A + 16 * mt * kLd64 + 32, kLd64, W3 + 32, 64, a);
-      const int col = lane & 15;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (col < 3) yo[(16 * mt + 4 * (lane >> 4) + i) * 4 + col] = a[i];
-    }
-    __syncthreads();
-    y0 = yo[lane * 4];
-    y1 = yo[lane * 4 + 1];
-    y2 = yo[lane * 4 + 2];
+  };
+  // per-tensor scaled e4m3 operands for FP8 (float32 accumulation, dequantised by s_x * s_w)
+  const float s1 = FP8 ? scales[7] : 1.0f, s2 = FP8 ? scales[8] : 1.0f;
+  const float d1 = FP8 ? sx * scales[0] : 1.0f, d2 = FP8 ? s1 * scales[1] : 1.0f, d3 = FP8 ? s2 * scales[2] : 1.0f;
+  if (FP8) {
+    hidden(w8, d1, 1.0f / s1);
+    hidden(w8 + 4096, d2, 1.0f / s2);
   } else {
-    // per-tensor scaled e4m3 operands, float32 accumulation, dequantise by s_x * s_w
-    const float sx = scales[6], s1 = scales[7], s2 = scales[8];
+    hidden(wb, 1.0f, 1.0f);
+    hidden(wb + 8192, 1.0f, 1.0f);
+  }
+  // output layer (3 of 16 columns used) into registers, then through the tile to the rows' lanes
+  f32x4_t o[4];
 #pragma unroll
-    for (int c = 0; c < 64; ++c) S.A8[lane * 80 + c] = (uint8_t)e4m3_code(feat[c] / sx);
-    __syncthreads();
-    const uint8_t* W1 = w8;
-    const uint8_t* W2 = w8 + 4096;
-    const uint8_t* W3 = w8 + 8192;
-    const float d1 = sx * scales[0], d2 = s1 * scales[1], d3 = s2 * scales[2];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t a = z4;
-        a = mma_fp8(S.A8 + 16 * mt * 80, 80, W1 + 16 * nt * 64, 64, a);
-        a = mma_fp8(S.A8 + 16 * mt * 80 + 32, 80, W1 + 16 * nt * 64 + 32, 64, a);
-        const int col = 16 * nt + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          S.B8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_code(fmaxf(a[i] * d1, 0.0f) / s1);
-      }
-    __syncthreads();
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4_t a = z4;
+    if (FP8) {
+      a = mma_fp8(S.A8 + 16 * mt * 80, 80, w8 + 8192, 64, a);
+      a = mma_fp8(S.A8 + 16 * mt * 80 + 32, 80, w8 + 8192 + 32, 64, a);
+    } else {
+      a = mma_bf16(S.A + 16 * mt * kLd64, kLd64, wb + 16384, 64, a);
+      a = mma_bf16(S.A + 16 * mt * kLd64 + 32, kLd64, wb + 16384 + 32, 64, a);
+    }
+    o[mt] = a;
+  }
+  __syncthreads();
+  {
+    const int col = lane & 15;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t a = z4;
-        a = mma_fp8(S.B8 + 16 * mt * 80, 80, W2 + 16 * nt * 64, 64, a);
-        a = mma_fp8(S.B8 + 16 * mt * 80 + 32, 80, W2 + 16 * nt * 64 + 32, 64, a);
-        const int col = 16 * nt + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          S.A8[(16 * mt + 4 * (lane >> 4) + i) * 80 + col] = (uint8_t)e4m3_code(fmaxf(a[i] * d2, 0.0f) / s2);
-      }
-    __syncthreads();
-    float* yo = reinterpret_cast<float*>(S.B);
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      f32x4_t a = z4;
-      a = mma_fp8(S.A8 + 16 * mt * 80, 80, W3, 64, a);
-      a = mma_fp8(S.A8 + 16 * mt * 80 + 32, 80, W3 + 32, 64, a);
-      const int col = lane & 15;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if (col < 3) yo[(16 * mt + 4 * (lane >> 4) + i) * 4 + col] = a[i] * d3;
-    }
-    __syncthreads();
-    y0 = yo[lane * 4];
-    y1 = yo[lane * 4 + 1];
-    y2 = yo[lane * 4 + 2];
+        if (col < 3) S.y[(16 * mt + 4 * (lane >> 4) + i) * 4 + col] = o[mt][i] * d3;
   }
+  __syncthreads();
+  const float y0 = S.y[lane * 4], y1 = S.y[lane * 4 + 1], y2 = S.y[lane * 4 + 2];
   if (valid) out[oidx] = make_float4(fmaxf(y0, 0.0f), fmaxf(y1, 0.0f), fmaxf(y2, 0.0f), 1.0f);
 }
 
