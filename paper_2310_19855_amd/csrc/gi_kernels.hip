@@ -1818,15 +1818,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_interpolate(const float4* gpos, 
         const float nd = (pn.x * qn.x + pn.y * qn.y) + pn.z * qn.z;
         const float w = (pd <= cell_size) ? wb * fmaxf(0.0f, nd) : 0.0f;
         // irradiance from the probe's SH at this pixel's normal: sum over l of (A_l c_l) Y_l(n)
+        // (values compared within a tolerance: fused multiply-adds; the weights, which decide
+        // the pixel's flag, stay as written)
         float E0 = 0.f, E1 = 0.f, E2 = 0.f;
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
-          E0 = E0 + ash[k][3 * l] * Y[l];
-          E1 = E1 + ash[k][3 * l + 1] * Y[l];
-          E2 = E2 + ash[k][3 * l + 2] * Y[l];
+          E0 = fmaf(ash[k][3 * l], Y[l], E0);
+          E1 = fmaf(ash[k][3 * l + 1], Y[l], E1);
+          E2 = fmaf(ash[k][3 * l + 2], Y[l], E2);
         }
         r0 = r0 + E0; r1 = r1 + E1; r2 = r2 + E2;
-        a0 = a0 + w * E0; a1 = a1 + w * E1; a2 = a2 + w * E2;
+        a0 = fmaf(w, E0, a0); a1 = fmaf(w, E1, a1); a2 = fmaf(w, E2, a2);
         ws = ws + w;
         ++nf;
       }
