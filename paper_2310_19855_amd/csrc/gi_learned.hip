@@ -473,16 +473,17 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* kin, 
 }
 
 // sorts (keys[0], vals[0]) by the low `bits` bits of the keys, stable; returns the index of
-// the buffer pair holding the result
+// the buffer pair holding the result.  first_hist: the tile counts of the lowest digit are
+// already in hist (written with the keys)
 template <typename V>
 static hipError_t radix_sort(uint32_t* keys[2], V* vals[2], uint32_t n, uint32_t bits, uint32_t* hist,
-                             hipStream_t st, int& which) {
+                             hipStream_t st, int& which, bool first_hist = false) {
   which = 0;
   if (n == 0) return hipSuccess;
   const uint32_t nb = (n + kRsTile - 1u) / kRsTile;
   uint32_t* dtot = hist + 256u * nb;
   for (uint32_t shift = 0; shift < bits; shift += 8u) {
-    k_rs_hist<<<nb, kRsThreads, 0, st>>>(keys[which], n, shift, nb, hist);
+    if (shift > 0u || !first_hist) k_rs_hist<<<nb, kRsThreads, 0, st>>>(keys[which], n, shift, nb, hist);
     k_rs_digit_scan<<<256, 256, 0, st>>>(hist, nb, dtot);
     k_rs_scatter<V><<<nb, kRsThreads, 0, st>>>(keys[which], vals[which], keys[which ^ 1], vals[which ^ 1], n, shift, nb,
                                                hist, dtot);
@@ -600,29 +601,49 @@ __global__ __launch_bounds__(256) void k_encode_fwd(LearnedParams lp, const floa
 
 // the encoding gradient as (level * T + entry, w * dX) pairs at position (l * 8 + c) * B + i:
 // no float atomics; the pairs are sorted and summed per entry in a fixed order
+// thread q = (level l, sample i) writes its 8 corner pairs at positions 8 q .. 8 q + 7, so
+// block b writes exactly the sort's tile b (2,048 pairs) and counts the tile's low key digits
+// for the sort's first pass (LDS counts: the same whatever the order)
 __global__ __launch_bounds__(256) void k_encode_bwd(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
                                                     uint32_t stride, const float* dX, uint32_t log2T, uint32_t* pkey,
-                                                    float2* pval) {
+                                                    float2* pval, uint32_t nb, uint32_t* hist) {
+  static_assert(kRsTile == 256u * 8u, "one encoding block per sort tile");
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
   const uint32_t q = blockIdx.x * 256u + threadIdx.x;
-  if (q >= lp.L * B) return;
-  const uint32_t l = q / B, i = q % B;
-  const float4 pos = batch[3 * (size_t)(off + stride * i)];
-  float x0, x1, x2;
-  norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
-  Corners cn;
-  level_corners(lp, (int)l, x0, x1, x2, cn);
-  const float2 d = *reinterpret_cast<const float2*>(dX + (size_t)i * 32u + 2u * l);
+  if (q < lp.L * B) {
+    const uint32_t l = q / B, i = q % B;
+    const float4 pos = batch[3 * (size_t)(off + stride * i)];
+    float x0, x1, x2;
+    norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
+    Corners cn;
+    level_corners(lp, (int)l, x0, x1, x2, cn);
+    const float2 d = *reinterpret_cast<const float2*>(dX + (size_t)i * 32u + 2u * l);
+    uint32_t k[8];
+    float v[16];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const size_t at = ((size_t)l * 8u + (uint32_t)c) * B + i;
-    pkey[at] = (l << log2T) | cn.idx[c];
-    pval[at] = make_float2(cn.w[c] * d.x, cn.w[c] * d.y);
+    for (int c = 0; c < 8; ++c) {
+      k[c] = (l << log2T) | cn.idx[c];
+      v[2 * c] = cn.w[c] * d.x;
+      v[2 * c + 1] = cn.w[c] * d.y;
+      atomicAdd(&h[k[c] & 255u], 1u);
+    }
+    // the thread's 8 pairs are contiguous: 16-byte stores
+    uint4* kq = reinterpret_cast<uint4*>(pkey + (size_t)q * 8u);
+    kq[0] = make_uint4(k[0], k[1], k[2], k[3]);
+    kq[1] = make_uint4(k[4], k[5], k[6], k[7]);
+    float4* vq = reinterpret_cast<float4*>(pval + (size_t)q * 8u);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) vq[j] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
   }
+  __syncthreads();
+  hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 // sample i of the step is row off + stride * i of the batch array.  The encoding gradient is
-// written as (entry key, contribution) pairs at fixed positions (group, level, corner,
-// sample), to be sorted and summed per entry: no float atomics, so the step is deterministic.
+// written as (entry key, contribution) pairs at fixed positions (level, sample, corner), to
+// be sorted and summed per entry: no float atomics, so the step is deterministic.
 __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
                                               uint32_t stride, const float2* enc, float* dXg, const __bf16* wb,
                                               float loss_scale, float* part, float* lpart, float* acc, float* amax) {
@@ -1482,14 +1503,14 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->enc, s->dX, s->wb, S,
                                                 s->mlp_part, s->lpart, s->acc, s->scales + 3);
   k_encode_bwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->dX, log2T, s->pkeys[0],
-                                              s->pvals[0]);
+                                              s->pvals[0], nblk(nq, 256), s->rs_hist);
   timer_end(c, "learned_train", st, ev);
   k_reduce_mlp<<<nblk(kMlpParams, 64), 1024, 0, st>>>(s->mlp_part, s->lpart, waves, s->mlp_g, s->acc);
   // the encoding gradient: pairs sorted by entry, summed per entry in a fixed order
   timer_begin(c, "learned_grad_sort", st, &ev);
   int which = 0;
   const uint32_t n = (uint32_t)s->n_pairs;
-  hipError_t e = radix_sort<float2>(s->pkeys, s->pvals, n, s->key_bits, s->rs_hist, st, which);
+  hipError_t e = radix_sort<float2>(s->pkeys, s->pvals, n, s->key_bits, s->rs_hist, st, which, true);
   timer_end(c, "learned_grad_sort", st, ev);
   if (e != hipSuccess) return e;
   const uint32_t nt = nblk(n, kGredTile);
