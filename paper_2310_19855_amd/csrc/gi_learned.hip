@@ -184,7 +184,27 @@ __global__ void k_learned_init(float* gstate, __half* grid_h, uint32_t L, uint32
 
 // bf16 and e4m3 working copies of the MLP weights and their per-tensor scales (one block of
 // 1024 threads)
-__device__ void mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* scales) {
+// BF16 copies of weight i (of the three tensors laid out W1, W2, W3): row-major and transposed
+// (W3t is [64][32], its columns 16..31 zero)
+__device__ inline void mlp_bf16_copy(int i, float w, __bf16* wb) {
+  const __bf16 b = to_bf16(w);
+  if (i < 4096) {
+    wb[i] = b;
+    wb[4096 + (i & 63) * 64 + (i >> 6)] = b;
+  } else if (i < 8192) {
+    const int j = i - 4096;
+    wb[8192 + j] = b;
+    wb[12288 + (j & 63) * 64 + (j >> 6)] = b;
+  } else {
+    const int j = i - 8192, r = j >> 6, c = j & 63;
+    wb[16384 + j] = b;
+    wb[16384 + 1024 + c * 32 + r] = b;
+    wb[16384 + 1024 + c * 32 + 16 + r] = to_bf16(0.0f);
+  }
+}
+
+// per-tensor e4m3 scales (max |w| / 448) and e4m3 copies of the weights; one block of 1024
+__device__ void mlp_e4m3_copies(const float* mlp, uint8_t* w8, float* scales) {
   __shared__ float red[3][32];
   const int t = threadIdx.x;
   float am[3] = {0.f, 0.f, 0.f};
@@ -204,28 +224,16 @@ __device__ void mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* sca
     scales[t] = v > 0.0f ? v / 448.0f : 1.0f;
   }
   __syncthreads();
-  __bf16* W1 = wb;
-  __bf16* W1t = wb + 4096;
-  __bf16* W2 = wb + 8192;
-  __bf16* W2t = wb + 12288;
-  __bf16* W3 = wb + 16384;
-  __bf16* W3t = wb + 16384 + 1024;   // [64][32], columns 16..31 zero
-  for (int i = t; i < 4096; i += 1024) {
-    const int r = i >> 6, c = i & 63;
-    W1[i] = to_bf16(mlp[kOffW1 + i]);
-    W1t[c * 64 + r] = to_bf16(mlp[kOffW1 + i]);
-    W2[i] = to_bf16(mlp[kOffW2 + i]);
-    W2t[c * 64 + r] = to_bf16(mlp[kOffW2 + i]);
-    w8[i] = (uint8_t)e4m3_code(mlp[kOffW1 + i] / scales[0]);
-    w8[4096 + i] = (uint8_t)e4m3_code(mlp[kOffW2 + i] / scales[1]);
+  const float s0 = scales[0], s1 = scales[1], s2 = scales[2];
+  for (int i = t; i < kMlpParams; i += 1024) {
+    const float sc = i < 4096 ? s0 : (i < 8192 ? s1 : s2);
+    w8[i] = (uint8_t)e4m3_code(mlp[i] / sc);
   }
-  for (int i = t; i < 1024; i += 1024) {
-    const int r = i >> 6, c = i & 63;
-    W3[i] = to_bf16(mlp[kOffW3 + i]);
-    w8[8192 + i] = (uint8_t)e4m3_code(mlp[kOffW3 + i] / scales[2]);
-    W3t[c * 32 + r] = to_bf16(mlp[kOffW3 + i]);
-    W3t[c * 32 + 16 + r] = to_bf16(0.0f);
-  }
+}
+
+__device__ void mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* scales) {
+  for (int i = threadIdx.x; i < kMlpParams; i += 1024) mlp_bf16_copy(i, mlp[i], wb);
+  mlp_e4m3_copies(mlp, w8, scales);
 }
 
 __global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* wb, uint8_t* w8, float* scales) {
@@ -1077,22 +1085,30 @@ __global__ __launch_bounds__(1024) void k_gred_carry(const float2* tail_sum, con
 // end of an applied step (one block of 1024 threads): Adam on the MLP weights, their bf16 and
 // e4m3 working copies, the e4m3 activation scales of the step's batch, the step's statistics
 // Adam on the MLP weights (dense), one parameter per thread
+// the MLP's Adam step (skipped when the step's loss was not finite) and the weights' BF16
+// copies; the e4m3 copies, which need every weight's new value for their scales, follow in
+// k_mlp_step
 __global__ __launch_bounds__(256) void k_mlp_adam(float* p, const float* g, float* m, float* v, AdamArgs a,
-                                                  const float* acc) {
+                                                  const float* acc, __bf16* wb) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= kMlpParams || acc[1] != 0.0f) return;
-  const float gi = g[i] * a.inv_scale;
-  const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
-  const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] = p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+  if (i >= kMlpParams) return;
+  float w = p[i];
+  if (acc[1] == 0.0f) {
+    const float gi = g[i] * a.inv_scale;
+    const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w = w - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    p[i] = w;
+  }
+  mlp_bf16_copy(i, w, wb);
 }
 
-__global__ __launch_bounds__(1024) void k_mlp_step(float* p, float* acc, __bf16* wb, uint8_t* w8, float* scales,
+__global__ __launch_bounds__(1024) void k_mlp_step(float* p, float* acc, uint8_t* w8, float* scales,
                                                    unsigned long long* stats) {
   const bool skip = acc[1] != 0.0f;
-  mlp_copies(p, wb, w8, scales);
+  mlp_e4m3_copies(p, w8, scales);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
       const float am = scales[3 + k];
@@ -1541,8 +1557,8 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
     am.lr = c->cfg.mlp_lr_mlp;
     am.eps = 1e-8f;
     timer_begin(c, "learned_adam", st, &ev);
-    k_mlp_adam<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc);
-    k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->acc, s->wb, s->w8, s->scales, c->d_stats);
+    k_mlp_adam<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc, s->wb);
+    k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->acc, s->w8, s->scales, c->d_stats);
     timer_end(c, "learned_adam", st, ev);
   } else {
     s->grad_dirty = true;
