@@ -247,6 +247,13 @@ __global__ __launch_bounds__(1024) void k_mlp_copies(const float* mlp, __bf16* w
 // their ranks.  The list is a function of the flags alone.
 constexpr uint32_t kTile = 4096;      // items per block of 256 threads (16 each)
 
+// orders the LDS accesses of one wave's lanes (no cost beyond keeping the compiler's order)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // exclusive prefix over the NT threads of a block, in thread order; every thread of the block
 // must call it (it holds two barriers); lds holds NT / 64 words
 template <uint32_t NT>
@@ -347,10 +354,11 @@ __global__ void k_select_batch(const uint32_t* list, const uint32_t* count, cons
 }
 
 // ---- stable LSD radix sort of (u32 key, payload) pairs, 8-bit digits ---------------------
-// Per pass: per-block digit counts (blocks of kTile items), one-block scan in digit-major
-// order, and a scatter in which every item goes to its digit's offset plus the number of
-// items of its block with the same digit and a lower index (wave ballots, then waves and
-// rounds in order), so equal keys keep their input order.
+// Per pass: per-block digit counts (blocks of kRsTile items), a scan of each digit's block
+// counts (one block per digit), and a scatter in which every item goes to its digit's offset
+// plus the number of items of its block with the same digit and a lower index (wave ballots
+// within a round, each wave's counts over its rounds, then the waves in order), so equal keys
+// keep their input order.
 constexpr uint32_t kRsThreads = 512, kRsRounds = 4, kRsTile = kRsThreads * kRsRounds;
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* key, uint32_t n, uint32_t shift, uint32_t nb,
@@ -389,59 +397,41 @@ __global__ __launch_bounds__(256) void k_rs_digit_scan(uint32_t* hist, uint32_t 
   if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// The tile is first ordered by digit in LDS (stable ranks from wave ballots, waves and rounds
-// in order), then written out so that consecutive threads write consecutive addresses of
-// each digit's run.
+// The tile is first ordered by digit in LDS, then written out so that consecutive threads
+// write consecutive addresses of each digit's run.  Wave w owns the tile's items
+// w*256 .. w*256+255 (four rounds of 64): an item's rank among its wave's items of the same
+// digit is its rank in its round's ballot plus the wave's count of that digit in earlier
+// rounds (a per-wave LDS row, touched by that wave alone); the waves' rows, scanned in wave
+// order, and the digits' tile offsets place it.  Equal digits keep their input order.
 template <typename V>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* kin, const V* vin, uint32_t* kout, V* vout,
                                                            uint32_t n, uint32_t shift, uint32_t nb, const uint32_t* off,
                                                            const uint32_t* dtot) {
-  constexpr uint32_t W = kRsThreads / 64u;
+  constexpr uint32_t W = kRsThreads / 64u, PW = kRsTile / W;
+  static_assert(PW == 64u * kRsRounds && kRsThreads >= 256u, "a wave holds kRsRounds rounds of 64 items");
   __shared__ uint32_t sk[kRsTile];
   __shared__ V sv[kRsTile];
-  __shared__ uint32_t gbase[256];      // global position of each digit's first item of this tile
+  __shared__ uint32_t wc[W][256];      // per wave: digit counts, then their prefix over earlier waves
   __shared__ uint32_t lbase[256];      // local position of each digit's first item
-  __shared__ uint32_t run[256];        // items of each digit placed so far
-  __shared__ uint32_t wcnt[W][256];    // this round's count of each digit per wave
-  __shared__ uint32_t lds[W];
+  __shared__ uint32_t gbase[256];      // global position of each digit's first item of this tile
+  __shared__ uint32_t lc[W], ld[W];
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
   const uint32_t b0 = blockIdx.x * kRsTile;
   const uint32_t m = n - b0 < kRsTile ? n - b0 : kRsTile;     // items of this tile
-  uint32_t key[kRsRounds];
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t key[kRsRounds], rk[kRsRounds];
   V val[kRsRounds];
-  if (t < 256u) run[t] = 0u;
-  __syncthreads();
 #pragma unroll
   for (uint32_t j = 0; j < kRsRounds; ++j) {
-    const uint32_t i = j * kRsThreads + t;
+    const uint32_t i = w * PW + 64u * j + lane;
     key[j] = i < m ? kin[b0 + i] : 0u;
-    if (i < m) {
-      val[j] = vin[b0 + i];
-      atomicAdd(&run[(key[j] >> shift) & 255u], 1u);
-    }
+    if (i < m) val[j] = vin[b0 + i];
   }
-  __syncthreads();
-  // digit scans over the whole block (threads from 256 on carry zeros): local starts of the
-  // digits in the tile, global starts
-  {
-    uint32_t total;
-    const uint32_t cnt = t < 256u ? run[t] : 0u;
-    const uint32_t lb = block_excl_scan<kRsThreads>(cnt, lds, total);
-    const uint32_t gb = block_excl_scan<kRsThreads>(t < 256u ? dtot[t] : 0u, lds, total);
-    if (t < 256u) {
-      lbase[t] = lb;
-      gbase[t] = gb + off[t * nb + blockIdx.x];
-      run[t] = 0u;
-    }
-  }
+#pragma unroll
+  for (uint32_t k = 0; k < 256u; k += 64u) wc[w][k + lane] = 0u;
 #pragma unroll
   for (uint32_t j = 0; j < kRsRounds; ++j) {
-    if (t < 256u)
-#pragma unroll
-      for (uint32_t q = 0; q < W; ++q) wcnt[q][t] = 0u;
-    __syncthreads();
-    const uint32_t i = j * kRsThreads + t;
-    const bool on = i < m;
+    const bool on = w * PW + 64u * j + lane < m;
     const uint32_t d = (key[j] >> shift) & 255u;
     uint64_t same = __ballot(on);
 #pragma unroll
@@ -449,21 +439,56 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* kin, 
       const uint64_t mb = __ballot((d >> b) & 1u);
       same &= ((d >> b) & 1u) ? mb : ~mb;
     }
-    const uint32_t rank = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
-    if (on && rank == 0u) wcnt[w][d] = (uint32_t)__popcll(same);
-    __syncthreads();
-    if (on) {
-      uint32_t at = lbase[d] + run[d] + rank;
-      for (uint32_t q = 0; q < w; ++q) at += wcnt[q][d];
+    const uint32_t r = (uint32_t)__popcll(same & below);
+    wave_sync();                        // the row as left by the previous round
+    const uint32_t base = on ? wc[w][d] : 0u;
+    rk[j] = base + r;
+    wave_sync();                        // every lane has read before the row changes
+    if (on && r == 0u) wc[w][d] = base + (uint32_t)__popcll(same);
+  }
+  __syncthreads();
+  // digit t: prefix of the waves' counts in wave order, then exclusive scans over the digits
+  // of the tile counts (local starts) and of the digit totals (global starts), together
+  uint32_t c = 0u;
+  if (t < 256u) {
+#pragma unroll
+    for (uint32_t q = 0; q < W; ++q) {
+      const uint32_t x = wc[q][t];
+      wc[q][t] = c;
+      c += x;
+    }
+  }
+  uint32_t x1 = c, x2 = t < 256u ? dtot[t] : 0u;
+#pragma unroll
+  for (int dd = 1; dd < 64; dd <<= 1) {
+    const uint32_t o1 = (uint32_t)__shfl_up((int)x1, dd, 64), o2 = (uint32_t)__shfl_up((int)x2, dd, 64);
+    if (lane >= (uint32_t)dd) {
+      x1 += o1;
+      x2 += o2;
+    }
+  }
+  if (lane == 63u) {
+    lc[w] = x1;
+    ld[w] = x2;
+  }
+  __syncthreads();
+  if (t < 256u) {
+    uint32_t e1 = x1 - c, e2 = x2 - dtot[t];
+    for (uint32_t q = 0; q < w; ++q) {
+      e1 += lc[q];
+      e2 += ld[q];
+    }
+    lbase[t] = e1;
+    gbase[t] = e2 + off[t * nb + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kRsRounds; ++j) {
+    if (w * PW + 64u * j + lane < m) {
+      const uint32_t d = (key[j] >> shift) & 255u;
+      const uint32_t at = lbase[d] + wc[w][d] + rk[j];
       sk[at] = key[j];
       sv[at] = val[j];
-    }
-    __syncthreads();
-    if (t < 256u) {
-      uint32_t add = 0;
-#pragma unroll
-      for (uint32_t q = 0; q < W; ++q) add += wcnt[q][t];
-      run[t] += add;
     }
   }
   __syncthreads();
