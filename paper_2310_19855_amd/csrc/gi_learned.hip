@@ -28,6 +28,8 @@ constexpr int kLd64 = 72;   // padded LDS row of a 64-wide bf16 tile (breaks ban
 constexpr int kLd32 = 40;   // padded LDS row of a 32-wide bf16 tile
 constexpr int kMlpParams = 64 * 64 + 64 * 64 + 16 * 64;
 constexpr int kOffW1 = 0, kOffW2 = 4096, kOffW3 = 8192;
+static_assert(kMlpParams % 256 == 0, "the weight-gradient reduction takes 256 parameters per block");
+constexpr uint32_t kRedGroups = 16;   // runs of waves summed separately, then in order
 constexpr uint32_t kPrimeY = 2654435761u, kPrimeZ = 805459861u;
 constexpr int kMaxLevels = 16;
 
@@ -51,6 +53,7 @@ struct LearnedState {
   float* mlp_m = nullptr;
   float* mlp_v = nullptr;
   float* mlp_part = nullptr;     // [train_waves][kMlpParams]
+  float* mlp_part2 = nullptr;    // [kRedGroups][kMlpParams] sums of consecutive runs of waves
   __bf16* wb = nullptr;          // W1 [64][64] | W1t [64][64] | W2 | W2t | W3 [16][64] | W3t [64][32]
   uint8_t* w8 = nullptr;         // e4m3 W1 | W2 | W3 (row-major [out][in])
   float* scales = nullptr;       // [0..2] weight scales, [3..5] activation amax (X, H1, H2), [6..8] act scales
@@ -71,7 +74,6 @@ struct LearnedState {
   uint32_t* rs_hist = nullptr;   // [256][blocks] digit counts -> offsets
   float2* tail_sum = nullptr;    // per reduction tile: partial sum of its last entry, whether
   uint32_t* tail_in = nullptr;   // that entry began inside the tile, and the tile's carry-in
-  float2* tail_carry = nullptr;
   size_t n_pairs = 0;
   uint32_t key_bits = 0;         // bits of a gradient pair key (level * T + entry)
   float* lpart = nullptr;        // [train_waves] loss partials
@@ -610,8 +612,15 @@ __device__ inline void atomic_max_abs(float* p, float v) {
 // wave on 64 consecutive samples of one level (neighbouring samples share coarse entries) ----
 // sample i of the step is row off + stride * i of the batch array
 __global__ __launch_bounds__(256) void k_encode_fwd(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
-                                                    uint32_t stride, const __half* grid_h, float2* enc) {
+                                                    uint32_t stride, const __half* grid_h, float2* enc, float* acc,
+                                                    float* amax) {
   const uint32_t q = blockIdx.x * 256u + threadIdx.x;
+  if (q == 0u) {
+    // the step's loss, non-finite flag and activation ranges start from zero
+    acc[0] = 0.0f;
+    acc[1] = 0.0f;
+    amax[0] = amax[1] = amax[2] = 0.0f;
+  }
   if (q >= lp.L * B) return;
   const uint32_t l = q / B, i = q % B;
   const float4 pos = batch[3 * (size_t)(off + stride * i)];
@@ -897,29 +906,63 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
   }
 }
 
-// deterministic sum of the per-wave partials (fixed order) -> gradient; flags non-finite
-// (64 parameters per block; 16 slices of the waves per parameter, summed in a fixed order)
-__global__ __launch_bounds__(1024) void k_reduce_mlp(const float* part, const float* lpart, uint32_t waves, float* g,
-                                                     float* acc) {
-  __shared__ float red[16][64];
+// deterministic sum of the per-wave partials (fixed order) -> gradient; flags non-finite.
+// Stage 1: block (x, y) sums the waves of run y (kRedGroups consecutive runs of waves) for
+// 256 parameters, four slices of the run's waves (one float4 column per thread) added in a
+// fixed order; stage 2 (reduce_mlp_finish) adds the runs in order.
+__global__ __launch_bounds__(256) void k_reduce_mlp(const float* part, uint32_t waves, float* part2) {
+  __shared__ float4 red[4][64];
+  const uint32_t l = threadIdx.x & 63u, slice = threadIdx.x >> 6;
+  const uint32_t c4 = blockIdx.x * 64u + l;                    // float4 column
+  const uint32_t per = (waves + kRedGroups - 1u) / kRedGroups;
+  const uint32_t w0 = blockIdx.y * per, w1 = w0 + per < waves ? w0 + per : waves;
+  const float4* p4 = reinterpret_cast<const float4*>(part);
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (c4 < kMlpParams / 4)
+    for (uint32_t w = w0 + slice; w < w1; w += 4u) {
+      const float4 v = p4[(size_t)w * (kMlpParams / 4) + c4];
+      s.x += v.x;
+      s.y += v.y;
+      s.z += v.z;
+      s.w += v.w;
+    }
+  red[slice][l] = s;
+  __syncthreads();
+  if (slice == 0u && c4 < kMlpParams / 4) {
+    float4 t = red[0][l];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      const float4 v = red[k][l];
+      t.x += v.x;
+      t.y += v.y;
+      t.z += v.z;
+      t.w += v.w;
+    }
+    reinterpret_cast<float4*>(part2 + (size_t)blockIdx.y * kMlpParams)[c4] = t;
+  }
+}
+
+// stage 2, run by the blocks of the first pass over the sorted grid pairs (which comes after
+// stage 1 and before any reader of the gradient or of the flags)
+struct MlpFinish {
+  const float* part2;
+  const float* lpart;
+  uint32_t waves;
+  float* g;
+};
+
+__device__ inline void reduce_mlp_finish(const MlpFinish& mf, float* acc) {
   if (blockIdx.x == 0 && threadIdx.x < 64) {
     // the step's loss: lane j sums partials j, j + 64, ... in order, then a fixed butterfly
     float l = 0.0f;
-    for (uint32_t w = threadIdx.x; w < waves; w += 64u) l += lpart[w];
+    for (uint32_t w = threadIdx.x; w < mf.waves; w += 64u) l += mf.lpart[w];
     for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
     if (threadIdx.x == 0) acc[0] = l;
   }
-  const int l = threadIdx.x & 63, slice = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + l;
-  float s = 0.0f;
-  if (i < kMlpParams)
-    for (uint32_t w = slice; w < waves; w += 16u) s += part[(size_t)w * kMlpParams + i];
-  red[slice][l] = s;
-  __syncthreads();
-  if (slice == 0 && i < kMlpParams) {
-    float t = 0.0f;
-    for (int k = 0; k < 16; ++k) t += red[k][l];
-    g[i] = t;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (uint32_t)kMlpParams; i += gridDim.x * blockDim.x) {
+    float t = mf.part2[i];
+    for (uint32_t k = 1; k < kRedGroups; ++k) t += mf.part2[(size_t)k * kMlpParams + i];
+    mf.g[i] = t;
     if (!isfinite(t)) acc[1] = 1.0f;
   }
 }
@@ -946,8 +989,9 @@ __device__ inline void adam_lazy(float graw, float& p, float& m, float& v, const
 // sums its pairs in order, restarting where the key changes; a segmented scan over the
 // threads (fixed association) extends every pair's sum back to the tile start or to its
 // entry's first pair.  MODE 0 records each tile's last partial sum and whether its entry began
-// inside the tile; k_gred_carry turns those into each tile's carry-in (a segmented scan over
-// the tiles); MODE 1 adds the carry to entries that began in an earlier tile and, at each
+// inside the tile.  In MODE 1 and 2 a tile's carry-in (the sums, in earlier tiles, of the entry
+// open at its start) is the run of those tail sums from the tile where that entry began,
+// added oldest first; MODE 1 adds the carry to entries that began in an earlier tile and, at each
 // entry's last pair, takes the lazy Adam step of its two parameters (none when the step's
 // gradients are non-finite); MODE 2 writes the dense gradient instead (a gradient-only step).
 // Every order is fixed, so the sums, and the step, are deterministic.
@@ -955,11 +999,39 @@ constexpr uint32_t kGredItems = 4, kGredTile = 256 * kGredItems;
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2* val, uint32_t n, float2* tail_sum,
-                                              uint32_t* tail_in, const float2* carry_in, float* gstate, __half* ph,
-                                              float* gdense, AdamArgs a, const float* acc) {
+                                              uint32_t* tail_in, float* gstate, __half* ph, float* gdense, AdamArgs a,
+                                              float* acc, MlpFinish mf) {
   __shared__ float2 cs[2][256];
   __shared__ uint32_t cf[2][256];
+  __shared__ float2 cin_s;
   const uint32_t t = threadIdx.x;
+  if (MODE != 0 && t < 64u) {
+    // wave 0: the carry-in.  Walk back over the earlier tiles' flags, 64 at a time, to the
+    // nearest tile whose last entry began inside it (tile 0's always did), then add the tail
+    // sums from that tile up to this one's predecessor in tile order.
+    const uint32_t b = blockIdx.x;
+    uint32_t first = 0u, top = b;
+    while (top > 0u) {
+      const bool f = t < top && tail_in[top - 1u - t] != 0u;
+      const uint64_t m = __ballot(f);
+      if (m) {
+        first = top - (uint32_t)__ffsll((long long)m);
+        break;
+      }
+      top = top > 64u ? top - 64u : 0u;
+    }
+    float2 cs0 = make_float2(0.0f, 0.0f);
+    for (uint32_t c0 = first; c0 < b; c0 += 64u) {
+      const float2 v = c0 + t < b ? tail_sum[c0 + t] : make_float2(0.0f, 0.0f);
+      const uint32_t cnt = b - c0 < 64u ? b - c0 : 64u;
+      for (uint32_t q = 0; q < cnt; ++q) {
+        const float ox = __shfl(v.x, (int)q, 64), oy = __shfl(v.y, (int)q, 64);
+        cs0.x = cs0.x + ox;
+        cs0.y = cs0.y + oy;
+      }
+    }
+    if (t == 0u) cin_s = cs0;
+  }
   const uint32_t i0 = blockIdx.x * kGredTile + kGredItems * t;
   uint32_t k[kGredItems];
   float2 w[kGredItems];
@@ -1023,6 +1095,7 @@ __global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2*
   const float2 carry = t > 0 ? cs[cur][t - 1] : make_float2(0.0f, 0.0f);
   const bool carry_in_tile = t > 0 && cf[cur][t - 1] != 0u;
   if (MODE == 0) {
+    reduce_mlp_finish(mf, acc);
     if (t == 255u) {
       const uint32_t j = kGredItems - 1;
       const bool own = (heads >> j) & 1u;
@@ -1031,7 +1104,7 @@ __global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2*
     }
     return;
   }
-  const float2 cin = carry_in[blockIdx.x];
+  const float2 cin = cin_s;
   const bool skip = MODE == 1 && acc[1] != 0.0f;
   float gx[kGredItems], gy[kGredItems];
 #pragma unroll
@@ -1058,53 +1131,6 @@ __global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2*
       gs[2u * (size_t)k[j] + 1u] = vz[j];
       *reinterpret_cast<__half2*>(ph + 2u * (size_t)k[j]) = __halves2half2(__float2half(pm[j].x), __float2half(pm[j].y));
     }
-}
-
-// carry-in of every tile: the sum of the pairs, in earlier tiles, of the entry that is open at
-// the tile's start (segmented inclusive scan of the tile tails, restarting at tiles whose last
-// entry began inside them); one block, fixed association
-__global__ __launch_bounds__(1024) void k_gred_carry(const float2* tail_sum, const uint32_t* tail_in, uint32_t nt,
-                                                     float2* carry_in) {
-  __shared__ float2 cs[2][1024];
-  __shared__ uint32_t cf[2][1024];
-  const uint32_t t = threadIdx.x;
-  float2 run = make_float2(0.0f, 0.0f);   // inclusive value of the previous chunk's last tile
-  for (uint32_t c = 0; c < nt; c += 1024u) {
-    const uint32_t b = c + t;
-    float2 s2 = b < nt ? tail_sum[b] : make_float2(0.0f, 0.0f);
-    uint32_t f = b < nt ? tail_in[b] : 1u;
-    int cur = 0;
-    cs[0][t] = s2;
-    cf[0][t] = f;
-    __syncthreads();
-    for (uint32_t d = 1; d < 1024u; d <<= 1) {
-      float2 x = cs[cur][t];
-      uint32_t g = cf[cur][t];
-      if (t >= d && !g) {
-        const float2 o = cs[cur][t - d];
-        x = make_float2(o.x + x.x, o.y + x.y);
-        g = cf[cur][t - d];
-      }
-      cs[cur ^ 1][t] = x;
-      cf[cur ^ 1][t] = g;
-      cur ^= 1;
-      __syncthreads();
-    }
-    // tile b's carry-in = inclusive value of tile b - 1 (chained to the previous chunk)
-    float2 prev;
-    if (t == 0) {
-      prev = run;
-    } else {
-      prev = cs[cur][t - 1];
-      if (!cf[cur][t - 1]) prev = make_float2(run.x + prev.x, run.y + prev.y);
-    }
-    if (b < nt) carry_in[b] = prev;
-    float2 endv = cs[cur][1023];
-    const uint32_t endf = cf[cur][1023];
-    __syncthreads();
-    if (!endf) endv = make_float2(run.x + endv.x, run.y + endv.y);
-    run = endv;
-  }
 }
 
 // end of an applied step (one block of 1024 threads): Adam on the MLP weights, their bf16 and
@@ -1369,14 +1395,6 @@ __global__ __launch_bounds__(1024) void k_judge_decide(const float2* part, uint3
   }
 }
 
-__global__ void k_train_begin(float* acc, float* scales) {
-  if (threadIdx.x == 0) {
-    acc[0] = 0.0f;
-    acc[1] = 0.0f;
-    scales[3] = scales[4] = scales[5] = 0.0f;
-  }
-}
-
 __global__ void k_train_end(float* acc, unsigned long long* stats) {
   if (threadIdx.x == 0) {
     acc[5] = acc[0];
@@ -1429,6 +1447,7 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->mlp_m, kMlpParams));
   A(lalloc(&s->mlp_v, kMlpParams));
   A(lalloc(&s->mlp_part, (size_t)s->train_waves * kMlpParams));
+  A(lalloc(&s->mlp_part2, (size_t)kRedGroups * kMlpParams));
   A(lalloc(&s->wb, 16384 + 1024 + 2048));
   A(lalloc(&s->w8, kMlpParams));
   A(lalloc(&s->scales, 16));
@@ -1463,7 +1482,6 @@ hipError_t learned_create(gi_context* c) {
   const size_t ntiles = (s->n_pairs + kGredTile - 1) / kGredTile;
   A(lalloc(&s->tail_sum, ntiles));
   A(lalloc(&s->tail_in, ntiles));
-  A(lalloc(&s->tail_carry, ntiles));
   A(lalloc(&s->lpart, s->train_waves));
   A(lalloc(&s->enc, (size_t)s->B * kMaxLevels));
   A(lalloc(&s->dX, (size_t)s->B * 32u));
@@ -1500,10 +1518,10 @@ void learned_destroy(gi_context* c) {
   LearnedState* s = c->learned;
   if (!s) return;
   void* ptrs[] = {s->gstate, s->grid_h, s->grid_g, s->mlp, s->mlp_g, s->mlp_m, s->mlp_v,
-                  s->mlp_part, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->tflag, s->clist,
+                  s->mlp_part, s->mlp_part2, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->tflag, s->clist,
                   s->ccount, s->batch, s->batch_raw, s->bkeys[0], s->bkeys[1], s->bvals[0], s->bvals[1],
                   s->pkeys[0], s->pkeys[1], s->pvals[0], s->pvals[1], s->rs_hist, s->tail_sum, s->tail_in,
-                  s->tail_carry, s->lpart, s->enc, s->dX, s->judge_part, s->lmlp, s->acc};
+                  s->lpart, s->enc, s->dX, s->judge_part, s->lmlp, s->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -1528,7 +1546,6 @@ void learned_set_domain(gi_context* c) {
 static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t off, uint32_t stride) {
   LearnedState* s = c->learned;
   const float S = c->cfg.mlp_loss_scale > 0.0f ? c->cfg.mlp_loss_scale : 1.0f;
-  k_train_begin<<<1, 64, 0, st>>>(s->acc, s->scales);
   // a gradient-only step leaves its dense gradient in grid_g; clear it before the next
   if (s->grad_dirty) k_zero_f32<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid_g, s->grid_n);
   s->grad_dirty = false;
@@ -1539,14 +1556,15 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   hipEvent_t ev;
   timer_begin(c, "learned_train", st, &ev);
   const uint32_t nq = s->lp.L * s->B;
-  k_encode_fwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->enc);
+  k_encode_fwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->enc, s->acc,
+                                              s->scales + 3);
   // every launched wave writes its whole partial, so the partials need no clearing
   k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->enc, s->dX, s->wb, S,
                                                 s->mlp_part, s->lpart, s->acc, s->scales + 3);
   k_encode_bwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->dX, log2T, s->pkeys[0],
                                               s->pvals[0], nblk(nq, 256), s->rs_hist);
   timer_end(c, "learned_train", st, ev);
-  k_reduce_mlp<<<nblk(kMlpParams, 64), 1024, 0, st>>>(s->mlp_part, s->lpart, waves, s->mlp_g, s->acc);
+  k_reduce_mlp<<<dim3(kMlpParams / 256, kRedGroups), 256, 0, st>>>(s->mlp_part, waves, s->mlp_part2);
   // the encoding gradient: pairs sorted by entry, summed per entry in a fixed order
   timer_begin(c, "learned_grad_sort", st, &ev);
   int which = 0;
@@ -1566,16 +1584,16 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
     ag.lr = c->cfg.mlp_lr_grid;
     ag.eps = 1e-15f;
   }
+  const MlpFinish mf{s->mlp_part2, s->lpart, waves, s->mlp_g};
   timer_begin(c, "learned_grad_apply", st, &ev);
-  k_gred<0><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->tail_carry,
-                                s->gstate, s->grid_h, s->grid_g, ag, s->acc);
-  k_gred_carry<<<1, 1024, 0, st>>>(s->tail_sum, s->tail_in, nt, s->tail_carry);
+  k_gred<0><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->gstate, s->grid_h,
+                                s->grid_g, ag, s->acc, mf);
   if (apply)
-    k_gred<1><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->tail_carry,
-                                  s->gstate, s->grid_h, s->grid_g, ag, s->acc);
+    k_gred<1><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->gstate, s->grid_h,
+                                  s->grid_g, ag, s->acc, mf);
   else
-    k_gred<2><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->tail_carry,
-                                  s->gstate, s->grid_h, s->grid_g, ag, s->acc);
+    k_gred<2><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->gstate, s->grid_h,
+                                  s->grid_g, ag, s->acc, mf);
   timer_end(c, "learned_grad_apply", st, ev);
   if (apply) {
     AdamArgs am = ag;
