@@ -101,6 +101,18 @@ __device__ inline f32x4_t mma_bf16(const __bf16* A, int lda, const __bf16* Bt, i
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
 }
 
+// the B fragment of mma_bf16 for this lane, loaded ahead of its product
+__device__ inline bf16x8_t frag_bf16(const __bf16* Bt, int ldb) {
+  const int lane = threadIdx.x & 63;
+  return *reinterpret_cast<const bf16x8_t*>(Bt + (lane & 15) * ldb + (lane >> 4) * 8);
+}
+
+__device__ inline f32x4_t mma_bf16f(const __bf16* A, int lda, const bf16x8_t& b, f32x4_t acc) {
+  const int lane = threadIdx.x & 63;
+  const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(A + (lane & 15) * lda + (lane >> 4) * 8);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
 __device__ inline f32x4_t mma_fp8(const uint8_t* A, int lda, const uint8_t* Bt, int ldb, f32x4_t acc) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, kb = (lane >> 4) * 8;
@@ -686,12 +698,16 @@ __global__ __launch_bounds__(256) void k_encode_bwd(LearnedParams lp, const floa
 // sample i of the step is row off + stride * i of the batch array.  The encoding gradient is
 // written as (entry key, contribution) pairs at fixed positions (level, sample, corner), to
 // be sorted and summed per entry: no float atomics, so the step is deterministic.
-__global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
-                                              uint32_t stride, const float2* enc, float* dXg, const __bf16* wb,
-                                              float loss_scale, float* part, float* lpart, float* acc, float* amax) {
+constexpr uint32_t kTrainWaves = 8;   // waves of a training block: one 16x16 tile of each layer's output each
+
+__global__ __launch_bounds__(64 * kTrainWaves) void k_train(LearnedParams lp, const float4* batch, uint32_t B,
+                                                            uint32_t off, uint32_t stride, const float2* enc,
+                                                            float* dXg, const __bf16* wb, float loss_scale,
+                                                            float* part, float* lpart, float* acc, float* amax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TrainSmem& S = *reinterpret_cast<TrainSmem*>(smem_raw);
-  const int lane = threadIdx.x;
+  __shared__ float red[kTrainWaves][4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const __bf16* W1 = wb;
   const __bf16* W1t = wb + 4096;
   const __bf16* W2 = wb + 8192;
@@ -699,27 +715,31 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
   const __bf16* W3 = wb + 16384;
   const __bf16* W3t = wb + 16384 + 1024;
   const f32x4_t z4 = {0.f, 0.f, 0.f, 0.f};
-  f32x4_t g1[4][4], g2[4][4], g3[4];
+  // wave w: forward and backward tile (sample rows 16*fm, unit columns 16*fn); of the weight
+  // gradients, dW1 and dW2 tiles (row tile gm, column tiles 2*gh, 2*gh+1) and, for w < 4,
+  // column tile w of dW3
+  const int fm = w >> 2, fn = w & 3, gm = w & 3, gh = w >> 2;
+  f32x4_t g1[2], g2[2], g3 = z4;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    g3[a] = z4;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) g1[a][b] = g2[a][b] = z4;
-  }
+  for (int a = 0; a < 2; ++a) g1[a] = g2[a] = z4;
   const uint32_t groups = B / 32u;
   const float inv3b = 1.0f / (3.0f * (float)B);
   float loss = 0.0f;
   bool bad = false;
   float ax = 0.f, ah1 = 0.f, ah2 = 0.f;
-  const int s = lane & 31, half_ = lane >> 5;
+  // encoding fill: thread = (sample s, level lg, two of the 32 other columns)
+  const int s = t & 31, lg = t >> 5;
   for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const uint32_t si = 32 * g + s;          // sample of the step
     const uint32_t row = off + stride * si;
-    // -- encoding (k_encode_fwd): lane = (sample s, levels 8*half_ .. 8*half_+7)
     const float4 nrm = batch[3 * row + 1];
-    if (lane < 32) S.tgt[s] = batch[3 * row + 2];
-    for (int k = 0; k < 8; ++k) {
-      const int l = 8 * half_ + k;
+    if (t < 32) S.tgt[s] = batch[3 * row + 2];
+    // each phase's weight fragments are requested one phase ahead, so that their latency
+    // passes during the phase before
+    const bf16x8_t f1a = frag_bf16(W1 + 16 * fn * 64, 64), f1b = frag_bf16(W1 + 16 * fn * 64 + 32, 64);
+    const bf16x8_t f2a = frag_bf16(W2 + 16 * fn * 64, 64), f2b = frag_bf16(W2 + 16 * fn * 64 + 32, 64);
+    {
+      const int l = lg;
       float f0 = 0.f, f1 = 0.f;
       if (l < (int)lp.L) {
         const float2 e = enc[(size_t)si * kMaxLevels + l];
@@ -733,8 +753,10 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
       S.Xt[(2 * l + 1) * kLd32 + s] = b1;
       ax = fmaxf(ax, fmaxf(fabsf(f0), fabsf(f1)));
     }
-    // normal features, constant input, zero padding: columns 32..63 split over the 2 halves
-    for (int c = 32 + 16 * half_; c < 48 + 16 * half_; ++c) {
+    // normal features, constant input, zero padding: columns 32..63, two per thread
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int c = 32 + 2 * lg + k;
       float v = 0.0f;
       if (c == 32) v = (nrm.x + 1.0f) * 0.5f;
       else if (c == 33) v = (nrm.y + 1.0f) * 0.5f;
@@ -745,45 +767,41 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
       ax = fmaxf(ax, fabsf(v));
     }
     __syncthreads();
-    // -- layer 1: Z1 = X W1^T
+    // -- layer 1: Z1 = X W1^T, tile (fm, fn)
+    {
+      f32x4_t a = z4;
+      a = mma_bf16f(S.X + 16 * fm * kLd64, kLd64, f1a, a);
+      a = mma_bf16f(S.X + 16 * fm * kLd64 + 32, kLd64, f1b, a);
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t a = z4;
-        a = mma_bf16(S.X + 16 * mt * kLd64, kLd64, W1 + 16 * nt * 64, 64, a);
-        a = mma_bf16(S.X + 16 * mt * kLd64 + 32, kLd64, W1 + 16 * nt * 64 + 32, 64, a);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { a[i] = fmaxf(a[i], 0.0f); ah1 = fmaxf(ah1, a[i]); }
-        store_tile(a, S.H1, kLd64, S.H1t, kLd32, 16 * mt, 16 * nt);
-      }
+      for (int i = 0; i < 4; ++i) { a[i] = fmaxf(a[i], 0.0f); ah1 = fmaxf(ah1, a[i]); }
+      store_tile(a, S.H1, kLd64, S.H1t, kLd32, 16 * fm, 16 * fn);
+    }
+    const bf16x8_t f3a = frag_bf16(W3, 64), f3b = frag_bf16(W3 + 32, 64);
+    const bf16x8_t f3t = frag_bf16(W3t + 16 * fn * 32, 32);
     __syncthreads();
     // -- layer 2
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t a = z4;
-        a = mma_bf16(S.H1 + 16 * mt * kLd64, kLd64, W2 + 16 * nt * 64, 64, a);
-        a = mma_bf16(S.H1 + 16 * mt * kLd64 + 32, kLd64, W2 + 16 * nt * 64 + 32, 64, a);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { a[i] = fmaxf(a[i], 0.0f); ah2 = fmaxf(ah2, a[i]); }
-        store_tile(a, S.H2, kLd64, S.H2t, kLd32, 16 * mt, 16 * nt);
-      }
-    __syncthreads();
-    // -- layer 3 and the loss gradient (scaled by the loss scale)
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+    {
       f32x4_t a = z4;
-      a = mma_bf16(S.H2 + 16 * mt * kLd64, kLd64, W3, 64, a);
-      a = mma_bf16(S.H2 + 16 * mt * kLd64 + 32, kLd64, W3 + 32, 64, a);
+      a = mma_bf16f(S.H1 + 16 * fm * kLd64, kLd64, f2a, a);
+      a = mma_bf16f(S.H1 + 16 * fm * kLd64 + 32, kLd64, f2b, a);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { a[i] = fmaxf(a[i], 0.0f); ah2 = fmaxf(ah2, a[i]); }
+      store_tile(a, S.H2, kLd64, S.H2t, kLd32, 16 * fm, 16 * fn);
+    }
+    __syncthreads();
+    // -- layer 3 and the loss gradient (scaled by the loss scale): waves 0 and 1, one row tile each
+    if (w < 2) {
+      const int mt = w;
+      f32x4_t a = z4;
+      a = mma_bf16f(S.H2 + 16 * mt * kLd64, kLd64, f3a, a);
+      a = mma_bf16f(S.H2 + 16 * mt * kLd64 + 32, kLd64, f3b, a);
       const int col = lane & 15;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = 16 * mt + 4 * (lane >> 4) + i;
+        const int r = 16 * mt + 4 * (lane >> 4) + i;
         float d = 0.0f;
         if (col < 3) {
-          const float4 t4 = S.tgt[row];
+          const float4 t4 = S.tgt[r];
           const float tv = col == 0 ? t4.x : (col == 1 ? t4.y : t4.z);
           const float y = a[i];
           const float den = y * y + 0.01f;
@@ -793,116 +811,115 @@ __global__ __launch_bounds__(64) void k_train(LearnedParams lp, const float4* ba
           if (!isfinite(d)) bad = true;
         }
         const __bf16 b = to_bf16(d);
-        S.dY[row * kLd32 + col] = b;
-        S.dY[row * kLd32 + 16 + col] = to_bf16(0.0f);
-        S.dYt[col * kLd32 + row] = b;
+        S.dY[r * kLd32 + col] = b;
+        S.dY[r * kLd32 + 16 + col] = to_bf16(0.0f);
+        S.dYt[col * kLd32 + r] = b;
+      }
+    }
+    const bf16x8_t f2ta = frag_bf16(W2t + 16 * fn * 64, 64), f2tb = frag_bf16(W2t + 16 * fn * 64 + 32, 64);
+    __syncthreads();
+    // -- dW3 += dY^T H2 (column tile w, waves 0..3)
+    if (w < 4) g3 = mma_bf16(S.dYt, kLd32, S.H2t + 16 * w * kLd32, kLd32, g3);
+    // -- dH2 = dY W3 (K = 16 padded to 32), dZ2 = dH2 * [H2 > 0]; tile (fm, fn)
+    {
+      f32x4_t a = z4;
+      a = mma_bf16f(S.dY + 16 * fm * kLd32, kLd32, f3t, a);
+      const int col = 16 * fn + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * fm + 4 * (lane >> 4) + i;
+        if (!(from_bf16(S.H2[r * kLd64 + col]) > 0.0f)) a[i] = 0.0f;
+      }
+      store_tile(a, S.dZ2, kLd64, S.dZ2t, kLd32, 16 * fm, 16 * fn);
+    }
+    const bf16x8_t f1ta = frag_bf16(W1t + 16 * (w & 1) * 64, 64), f1tb = frag_bf16(W1t + 16 * (w & 1) * 64 + 32, 64);
+    __syncthreads();
+    // -- dW2 += dZ2^T H1 (row tile gm, column tiles 2gh, 2gh+1)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      g2[j] = mma_bf16(S.dZ2t + 16 * gm * kLd32, kLd32, S.H1t + 16 * (2 * gh + j) * kLd32, kLd32, g2[j]);
+    // -- dH1 = dZ2 W2, dZ1 = dH1 * [H1 > 0]; tile (fm, fn)
+    {
+      f32x4_t a = z4;
+      a = mma_bf16f(S.dZ2 + 16 * fm * kLd64, kLd64, f2ta, a);
+      a = mma_bf16f(S.dZ2 + 16 * fm * kLd64 + 32, kLd64, f2tb, a);
+      const int col = 16 * fn + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * fm + 4 * (lane >> 4) + i;
+        if (!(from_bf16(S.H1[r * kLd64 + col]) > 0.0f)) a[i] = 0.0f;
+      }
+      store_tile(a, S.dZ1, kLd64, S.dZ1t, kLd32, 16 * fm, 16 * fn);
+    }
+    __syncthreads();
+    // -- dW1 += dZ1^T X (row tile gm, column tiles 2gh, 2gh+1)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      g1[j] = mma_bf16(S.dZ1t + 16 * gm * kLd32, kLd32, S.Xt + 16 * (2 * gh + j) * kLd32, kLd32, g1[j]);
+    // -- dX[:, 0:32] = dZ1 W1 (encoding columns only), kept in float32: waves 0..3, a tile each
+    if (w < 4) {
+      const int mt = w >> 1, nt = w & 1;
+      f32x4_t a = z4;
+      a = mma_bf16f(S.dZ1 + 16 * mt * kLd64, kLd64, f1ta, a);
+      a = mma_bf16f(S.dZ1 + 16 * mt * kLd64 + 32, kLd64, f1tb, a);
+      const int col = 16 * nt + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * mt + 4 * (lane >> 4) + i;
+        S.dX[r * 33 + col] = a[i];
+        if (!isfinite(a[i])) bad = true;
       }
     }
     __syncthreads();
-    // -- dW3 += dY^T H2
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) g3[nt] = mma_bf16(S.dYt, kLd32, S.H2t + 16 * nt * kLd32, kLd32, g3[nt]);
-    // -- dH2 = dY W3 (K = 16 padded to 32), dZ2 = dH2 * [H2 > 0]
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t a = z4;
-        a = mma_bf16(S.dY + 16 * mt * kLd32, kLd32, W3t + 16 * nt * 32, 32, a);
-        const int col = 16 * nt + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 16 * mt + 4 * (lane >> 4) + i;
-          if (!(from_bf16(S.H2[row * kLd64 + col]) > 0.0f)) a[i] = 0.0f;
-        }
-        store_tile(a, S.dZ2, kLd64, S.dZ2t, kLd32, 16 * mt, 16 * nt);
-      }
-    __syncthreads();
-    // -- dW2 += dZ2^T H1
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        g2[mt][nt] = mma_bf16(S.dZ2t + 16 * mt * kLd32, kLd32, S.H1t + 16 * nt * kLd32, kLd32, g2[mt][nt]);
-    // -- dH1 = dZ2 W2, dZ1 = dH1 * [H1 > 0]
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        f32x4_t a = z4;
-        a = mma_bf16(S.dZ2 + 16 * mt * kLd64, kLd64, W2t + 16 * nt * 64, 64, a);
-        a = mma_bf16(S.dZ2 + 16 * mt * kLd64 + 32, kLd64, W2t + 16 * nt * 64 + 32, 64, a);
-        const int col = 16 * nt + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 16 * mt + 4 * (lane >> 4) + i;
-          if (!(from_bf16(S.H1[row * kLd64 + col]) > 0.0f)) a[i] = 0.0f;
-        }
-        store_tile(a, S.dZ1, kLd64, S.dZ1t, kLd32, 16 * mt, 16 * nt);
-      }
-    __syncthreads();
-    // -- dW1 += dZ1^T X
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        g1[mt][nt] = mma_bf16(S.dZ1t + 16 * mt * kLd32, kLd32, S.Xt + 16 * nt * kLd32, kLd32, g1[mt][nt]);
-    // -- dX[:, 0:32] = dZ1 W1 (encoding columns only), kept in float32
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt) {
-        f32x4_t a = z4;
-        a = mma_bf16(S.dZ1 + 16 * mt * kLd64, kLd64, W1t + 16 * nt * 64, 64, a);
-        a = mma_bf16(S.dZ1 + 16 * mt * kLd64 + 32, kLd64, W1t + 16 * nt * 64 + 32, 64, a);
-        const int col = 16 * nt + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 16 * mt + 4 * (lane >> 4) + i;
-          S.dX[row * 33 + col] = a[i];
-          if (!isfinite(a[i])) bad = true;
-        }
-      }
-    __syncthreads();
-    // -- the encoding columns of dX go to k_encode_bwd
-    if (lane < 32) {
-      const float* src = S.dX + s * 33;
-      float4* dst = reinterpret_cast<float4*>(dXg + (size_t)si * 32u);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) dst[c] = make_float4(src[4 * c], src[4 * c + 1], src[4 * c + 2], src[4 * c + 3]);
+    // -- the encoding columns of dX go to k_encode_bwd: thread = (sample, 4 columns)
+    if (t < 256) {
+      const int ss = t >> 3, c4 = t & 7;
+      const float* src = S.dX + ss * 33 + 4 * c4;
+      reinterpret_cast<float4*>(dXg + (size_t)(32 * g + ss) * 32u)[c4] = make_float4(src[0], src[1], src[2], src[3]);
     }
     __syncthreads();
   }
-  // per-wave weight-gradient partials (C layout: row 4*(lane/16)+i, column lane%16 of a tile)
+  // per-block weight-gradient partials (C layout: row 4*(lane/16)+i, column lane%16 of a tile)
   float* pw = part + (size_t)blockIdx.x * kMlpParams;
   const int col = lane & 15, rb = 4 * (lane >> 4);
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int i = 0; i < 4; ++i) {
+      pw[kOffW1 + (16 * gm + rb + i) * 64 + 16 * (2 * gh + j) + col] = g1[j][i];
+      pw[kOffW2 + (16 * gm + rb + i) * 64 + 16 * (2 * gh + j) + col] = g2[j][i];
+    }
+  if (w < 4)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        pw[kOffW1 + (16 * mt + rb + i) * 64 + 16 * nt + col] = g1[mt][nt][i];
-        pw[kOffW2 + (16 * mt + rb + i) * 64 + 16 * nt + col] = g2[mt][nt][i];
-      }
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) pw[kOffW3 + (rb + i) * 64 + 16 * nt + col] = g3[nt][i];
-  // loss, non-finite flag and activation ranges
+    for (int i = 0; i < 4; ++i) pw[kOffW3 + (rb + i) * 64 + 16 * w + col] = g3[i];
+  // loss, non-finite flag and activation ranges: per wave, then the block's waves in order
   for (int o = 32; o >= 1; o >>= 1) {
     loss += __shfl_xor(loss, o, 64);
     ax = fmaxf(ax, __shfl_xor(ax, o, 64));
     ah1 = fmaxf(ah1, __shfl_xor(ah1, o, 64));
     ah2 = fmaxf(ah2, __shfl_xor(ah2, o, 64));
   }
-  const bool any_bad = __ballot(bad) != 0;
+  if (__ballot(bad) != 0 && lane == 0) acc[1] = 1.0f;
   if (lane == 0) {
-    lpart[blockIdx.x] = loss * inv3b;
-    if (any_bad) acc[1] = 1.0f;
-    atomic_max_abs(&amax[0], ax);
-    atomic_max_abs(&amax[1], ah1);
-    atomic_max_abs(&amax[2], ah2);
+    red[w][0] = loss;
+    red[w][1] = ax;
+    red[w][2] = ah1;
+    red[w][3] = ah2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    float l = red[0][0], bx = red[0][1], b1 = red[0][2], b2 = red[0][3];
+#pragma unroll
+    for (uint32_t q = 1; q < kTrainWaves; ++q) {
+      l += red[q][0];
+      bx = fmaxf(bx, red[q][1]);
+      b1 = fmaxf(b1, red[q][2]);
+      b2 = fmaxf(b2, red[q][3]);
+    }
+    lpart[blockIdx.x] = l * inv3b;
+    atomic_max_abs(&amax[0], bx);
+    atomic_max_abs(&amax[1], b1);
+    atomic_max_abs(&amax[2], b2);
   }
 }
 
@@ -1558,8 +1575,8 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   const uint32_t nq = s->lp.L * s->B;
   k_encode_fwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->enc, s->acc,
                                               s->scales + 3);
-  // every launched wave writes its whole partial, so the partials need no clearing
-  k_train<<<waves, 64, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->enc, s->dX, s->wb, S,
+  // every launched block writes its whole partial, so the partials need no clearing
+  k_train<<<waves, 64 * kTrainWaves, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->enc, s->dX, s->wb, S,
                                                 s->mlp_part, s->lpart, s->acc, s->scales + 3);
   k_encode_bwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->dX, log2T, s->pkeys[0],
                                               s->pvals[0], nblk(nq, 256), s->rs_hist);
