@@ -77,7 +77,6 @@ struct LearnedState {
   size_t n_pairs = 0;
   uint32_t key_bits = 0;         // bits of a gradient pair key (level * T + entry)
   float* lpart = nullptr;        // [train_waves] loss partials
-  float2* enc = nullptr;         // [B][16] the step's encoding (level features)
   float* dX = nullptr;           // [B][32] gradient of the loss at the encoding
   float2* judge_part = nullptr;  // per-wave (error, norm) partials of the judge
   uint32_t B = 0;
@@ -620,39 +619,8 @@ __device__ inline void atomic_max_abs(float* p, float v) {
   atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
 }
 
-// ---- the step's encoding, forward and backward: one thread per (level, sample), lanes of a
-// wave on 64 consecutive samples of one level (neighbouring samples share coarse entries) ----
-// sample i of the step is row off + stride * i of the batch array
-__global__ __launch_bounds__(256) void k_encode_fwd(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
-                                                    uint32_t stride, const __half* grid_h, float2* enc, float* acc,
-                                                    float* amax) {
-  const uint32_t q = blockIdx.x * 256u + threadIdx.x;
-  if (q == 0u) {
-    // the step's loss, non-finite flag and activation ranges start from zero
-    acc[0] = 0.0f;
-    acc[1] = 0.0f;
-    amax[0] = amax[1] = amax[2] = 0.0f;
-  }
-  if (q >= lp.L * B) return;
-  const uint32_t l = q / B, i = q % B;
-  const float4 pos = batch[3 * (size_t)(off + stride * i)];
-  float x0, x1, x2;
-  norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
-  Corners cn;
-  level_corners(lp, (int)l, x0, x1, x2, cn);
-  const __half2* tab = reinterpret_cast<const __half2*>(grid_h) + (size_t)l * lp.T;
-  float2 v[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) v[c] = __half22float2(tab[cn.idx[c]]);
-  float f0 = 0.f, f1 = 0.f;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    f0 = f0 + cn.w[c] * v[c].x;
-    f1 = f1 + cn.w[c] * v[c].y;
-  }
-  enc[(size_t)i * kMaxLevels + l] = make_float2(f0, f1);
-}
-
+// ---- the step's encoding gradient: one thread per (level, sample), lanes of a wave on 64
+// consecutive samples of one level (neighbouring samples share coarse entries) ----
 // the encoding gradient as (level * T + entry, w * dX) pairs at position (l * 8 + c) * B + i:
 // no float atomics; the pairs are sorted and summed per entry in a fixed order
 // thread q = (level l, sample i) writes its 8 corner pairs at positions 8 q .. 8 q + 7, so
@@ -700,8 +668,8 @@ __global__ __launch_bounds__(256) void k_encode_bwd(LearnedParams lp, const floa
 // be sorted and summed per entry: no float atomics, so the step is deterministic.
 constexpr uint32_t kTrainWaves = 8;   // waves of a training block: one 16x16 tile of each layer's output each
 
-__global__ __launch_bounds__(64 * kTrainWaves) void k_train(LearnedParams lp, const float4* batch, uint32_t B,
-                                                            uint32_t off, uint32_t stride, const float2* enc,
+__global__ __launch_bounds__(64 * kTrainWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_train(LearnedParams lp, const float4* batch, uint32_t B,
+                                                            uint32_t off, uint32_t stride, const __half* grid_h,
                                                             float* dXg, const __bf16* wb, float loss_scale,
                                                             float* part, float* lpart, float* acc, float* amax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -727,24 +695,35 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_train(LearnedParams lp, co
   float loss = 0.0f;
   bool bad = false;
   float ax = 0.f, ah1 = 0.f, ah2 = 0.f;
-  // encoding fill: thread = (sample s, level lg, two of the 32 other columns)
+  // input fill: thread = (sample s, level lg: its encoding, two of the 32 other columns)
   const int s = t & 31, lg = t >> 5;
   for (uint32_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const uint32_t si = 32 * g + s;          // sample of the step
     const uint32_t row = off + stride * si;
+    const float4 pos = batch[3 * row];
     const float4 nrm = batch[3 * row + 1];
     if (t < 32) S.tgt[s] = batch[3 * row + 2];
     // each phase's weight fragments are requested one phase ahead, so that their latency
     // passes during the phase before
     const bf16x8_t f1a = frag_bf16(W1 + 16 * fn * 64, 64), f1b = frag_bf16(W1 + 16 * fn * 64 + 32, 64);
-    const bf16x8_t f2a = frag_bf16(W2 + 16 * fn * 64, 64), f2b = frag_bf16(W2 + 16 * fn * 64 + 32, 64);
     {
+      // the sample's encoding at level l: trilinear blend of the FP16 corner features
       const int l = lg;
       float f0 = 0.f, f1 = 0.f;
       if (l < (int)lp.L) {
-        const float2 e = enc[(size_t)si * kMaxLevels + l];
-        f0 = e.x;
-        f1 = e.y;
+        float x0, x1, x2;
+        norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
+        Corners cn;
+        level_corners(lp, l, x0, x1, x2, cn);
+        const __half2* tab = reinterpret_cast<const __half2*>(grid_h) + (size_t)l * lp.T;
+        float2 v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = __half22float2(tab[cn.idx[c]]);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          f0 = f0 + cn.w[c] * v[c].x;
+          f1 = f1 + cn.w[c] * v[c].y;
+        }
       }
       const __bf16 b0 = to_bf16(f0), b1 = to_bf16(f1);
       S.X[s * kLd64 + 2 * l] = b0;
@@ -766,6 +745,7 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_train(LearnedParams lp, co
       S.Xt[c * kLd32 + s] = to_bf16(v);
       ax = fmaxf(ax, fabsf(v));
     }
+    const bf16x8_t f2a = frag_bf16(W2 + 16 * fn * 64, 64), f2b = frag_bf16(W2 + 16 * fn * 64 + 32, 64);
     __syncthreads();
     // -- layer 1: Z1 = X W1^T, tile (fm, fn)
     {
@@ -1177,13 +1157,16 @@ __global__ __launch_bounds__(1024) void k_mlp_step(float* p, float* acc, uint8_t
                                                    unsigned long long* stats) {
   const bool skip = acc[1] != 0.0f;
   mlp_e4m3_copies(p, w8, scales);
+  __syncthreads();                      // every thread has read the flag
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
       const float am = scales[3 + k];
       scales[6 + k] = am > 0.0f ? am / 448.0f : 1.0f;
+      scales[3 + k] = 0.0f;             // the next step's activation ranges start from zero
     }
     acc[5] = acc[0];
     if (skip) stats[GI_STAT_MLP_SKIPPED] += 1ull;
+    acc[1] = 0.0f;                      // and its non-finite flag
   }
 }
 
@@ -1412,10 +1395,14 @@ __global__ __launch_bounds__(1024) void k_judge_decide(const float2* part, uint3
   }
 }
 
-__global__ void k_train_end(float* acc, unsigned long long* stats) {
+// closes a gradient-only step (the applied step's k_mlp_step does the same): the loss is
+// published, and the flag and activation ranges are cleared for the next step
+__global__ void k_train_end(float* acc, float* amax, unsigned long long* stats) {
   if (threadIdx.x == 0) {
     acc[5] = acc[0];
     if (acc[1] != 0.0f) stats[GI_STAT_MLP_SKIPPED] += 1ull;
+    acc[1] = 0.0f;
+    amax[0] = amax[1] = amax[2] = 0.0f;
   }
 }
 
@@ -1500,7 +1487,6 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->tail_sum, ntiles));
   A(lalloc(&s->tail_in, ntiles));
   A(lalloc(&s->lpart, s->train_waves));
-  A(lalloc(&s->enc, (size_t)s->B * kMaxLevels));
   A(lalloc(&s->dX, (size_t)s->B * 32u));
   A(lalloc(&s->judge_part, (size_t)c->hit_blocks_per_stripe * kStatStripes));
   A(lalloc(&s->lmlp, PR));
@@ -1538,7 +1524,7 @@ void learned_destroy(gi_context* c) {
                   s->mlp_part, s->mlp_part2, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->tflag, s->clist,
                   s->ccount, s->batch, s->batch_raw, s->bkeys[0], s->bkeys[1], s->bvals[0], s->bvals[1],
                   s->pkeys[0], s->pkeys[1], s->pvals[0], s->pvals[1], s->rs_hist, s->tail_sum, s->tail_in,
-                  s->lpart, s->enc, s->dX, s->judge_part, s->lmlp, s->acc};
+                  s->lpart, s->dX, s->judge_part, s->lmlp, s->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -1573,10 +1559,8 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   hipEvent_t ev;
   timer_begin(c, "learned_train", st, &ev);
   const uint32_t nq = s->lp.L * s->B;
-  k_encode_fwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->enc, s->acc,
-                                              s->scales + 3);
   // every launched block writes its whole partial, so the partials need no clearing
-  k_train<<<waves, 64 * kTrainWaves, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->enc, s->dX, s->wb, S,
+  k_train<<<waves, 64 * kTrainWaves, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->dX, s->wb, S,
                                                 s->mlp_part, s->lpart, s->acc, s->scales + 3);
   k_encode_bwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->dX, log2T, s->pkeys[0],
                                               s->pvals[0], nblk(nq, 256), s->rs_hist);
@@ -1622,7 +1606,7 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
     timer_end(c, "learned_adam", st, ev);
   } else {
     s->grad_dirty = true;
-    k_train_end<<<1, 64, 0, st>>>(s->acc, c->d_stats);
+    k_train_end<<<1, 64, 0, st>>>(s->acc, s->scales + 3, c->d_stats);
   }
   return hipGetLastError();
 }
