@@ -77,7 +77,6 @@ struct LearnedState {
   size_t n_pairs = 0;
   uint32_t key_bits = 0;         // bits of a gradient pair key (level * T + entry)
   float* lpart = nullptr;        // [train_waves] loss partials
-  float* dX = nullptr;           // [B][32] gradient of the loss at the encoding
   float2* judge_part = nullptr;  // per-wave (error, norm) partials of the judge
   uint32_t B = 0;
   uint32_t sub = 1;              // sub-batches held by the frame's batch (rows = sub * B)
@@ -601,6 +600,7 @@ struct TrainSmem {
   __bf16 dZ1[32 * kLd64], dZ1t[64 * kLd32];
   float dX[32 * 33];
   float4 tgt[32];
+  float4 pos[32];        // sample positions, for the gradient pairs at the end of the group
 };
 
 // store a 16x16 accumulator tile (rows r0.., cols c0..) as bf16 into M[row][ld] and Mt[col][ldt]
@@ -619,62 +619,27 @@ __device__ inline void atomic_max_abs(float* p, float v) {
   atomicMax(reinterpret_cast<unsigned int*>(p), __float_as_uint(fabsf(v)));
 }
 
-// ---- the step's encoding gradient: one thread per (level, sample), lanes of a wave on 64
-// consecutive samples of one level (neighbouring samples share coarse entries) ----
-// the encoding gradient as (level * T + entry, w * dX) pairs at position (l * 8 + c) * B + i:
-// no float atomics; the pairs are sorted and summed per entry in a fixed order
-// thread q = (level l, sample i) writes its 8 corner pairs at positions 8 q .. 8 q + 7, so
-// block b writes exactly the sort's tile b (2,048 pairs) and counts the tile's low key digits
-// for the sort's first pass (LDS counts: the same whatever the order)
-__global__ __launch_bounds__(256) void k_encode_bwd(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off,
-                                                    uint32_t stride, const float* dX, uint32_t log2T, uint32_t* pkey,
-                                                    float2* pval, uint32_t nb, uint32_t* hist) {
-  static_assert(kRsTile == 256u * 8u, "one encoding block per sort tile");
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0u;
-  __syncthreads();
-  const uint32_t q = blockIdx.x * 256u + threadIdx.x;
-  if (q < lp.L * B) {
-    const uint32_t l = q / B, i = q % B;
-    const float4 pos = batch[3 * (size_t)(off + stride * i)];
-    float x0, x1, x2;
-    norm_pos(lp, pos.x, pos.y, pos.z, x0, x1, x2);
-    Corners cn;
-    level_corners(lp, (int)l, x0, x1, x2, cn);
-    const float2 d = *reinterpret_cast<const float2*>(dX + (size_t)i * 32u + 2u * l);
-    uint32_t k[8];
-    float v[16];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      k[c] = (l << log2T) | cn.idx[c];
-      v[2 * c] = cn.w[c] * d.x;
-      v[2 * c + 1] = cn.w[c] * d.y;
-      atomicAdd(&h[k[c] & 255u], 1u);
-    }
-    // the thread's 8 pairs are contiguous: 16-byte stores
-    uint4* kq = reinterpret_cast<uint4*>(pkey + (size_t)q * 8u);
-    kq[0] = make_uint4(k[0], k[1], k[2], k[3]);
-    kq[1] = make_uint4(k[4], k[5], k[6], k[7]);
-    float4* vq = reinterpret_cast<float4*>(pval + (size_t)q * 8u);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) vq[j] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
-  }
-  __syncthreads();
-  hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
-}
-
 // sample i of the step is row off + stride * i of the batch array.  The encoding gradient is
-// written as (entry key, contribution) pairs at fixed positions (level, sample, corner), to
-// be sorted and summed per entry: no float atomics, so the step is deterministic.
+// written as (level * T + entry, corner weight * dX) pairs, to be sorted and summed per entry:
+// no float atomics, so the step is deterministic.  Group g (samples 32 g .. 32 g + 31) fills
+// pairs [256 L g, 256 L (g + 1)) in (level, sample, corner) order, so the pairs of one level,
+// which hold every copy of its keys, come in sample order across the groups.  When 256 L is a
+// whole number of sort tiles (L a multiple of 8) the block also counts the low key digits of
+// its tiles for the sort's first pass.
 constexpr uint32_t kTrainWaves = 8;   // waves of a training block: one 16x16 tile of each layer's output each
 
 __global__ __launch_bounds__(64 * kTrainWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_train(LearnedParams lp, const float4* batch, uint32_t B,
                                                             uint32_t off, uint32_t stride, const __half* grid_h,
-                                                            float* dXg, const __bf16* wb, float loss_scale,
-                                                            float* part, float* lpart, float* acc, float* amax) {
+                                                            const __bf16* wb, float loss_scale, float* part,
+                                                            float* lpart, float* acc, float* amax, uint32_t log2T,
+                                                            uint32_t* pkey, float2* pval, uint32_t nb,
+                                                            uint32_t* hist) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TrainSmem& S = *reinterpret_cast<TrainSmem*>(smem_raw);
   __shared__ float red[kTrainWaves][4];
+  __shared__ uint32_t hs[2][256];       // low-digit counts of the group's sort tiles
+  static_assert(kRsTile == 2048u && kMaxLevels <= 16, "a group's pairs are at most two sort tiles");
+  const bool tiles = (lp.L & 7u) == 0u;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const __bf16* W1 = wb;
   const __bf16* W1t = wb + 4096;
@@ -702,7 +667,14 @@ __global__ __launch_bounds__(64 * kTrainWaves) __attribute__((amdgpu_waves_per_e
     const uint32_t row = off + stride * si;
     const float4 pos = batch[3 * row];
     const float4 nrm = batch[3 * row + 1];
-    if (t < 32) S.tgt[s] = batch[3 * row + 2];
+    if (t < 32) {
+      S.tgt[s] = batch[3 * row + 2];
+      S.pos[s] = pos;
+    }
+    if (t < 256) {
+      hs[0][t] = 0u;
+      hs[1][t] = 0u;
+    }
     // each phase's weight fragments are requested one phase ahead, so that their latency
     // passes during the phase before
     const bf16x8_t f1a = frag_bf16(W1 + 16 * fn * 64, 64), f1b = frag_bf16(W1 + 16 * fn * 64 + 32, 64);
@@ -851,11 +823,36 @@ __global__ __launch_bounds__(64 * kTrainWaves) __attribute__((amdgpu_waves_per_e
       }
     }
     __syncthreads();
-    // -- the encoding columns of dX go to k_encode_bwd: thread = (sample, 4 columns)
-    if (t < 256) {
-      const int ss = t >> 3, c4 = t & 7;
-      const float* src = S.dX + ss * 33 + 4 * c4;
-      reinterpret_cast<float4*>(dXg + (size_t)(32 * g + ss) * 32u)[c4] = make_float4(src[0], src[1], src[2], src[3]);
+    // -- the encoding gradient: thread (s, l) writes its 8 corner pairs, contiguous
+    if (lg < (int)lp.L) {
+      const int l = lg;
+      const float4 ps = S.pos[s];
+      float x0, x1, x2;
+      norm_pos(lp, ps.x, ps.y, ps.z, x0, x1, x2);
+      Corners cn;
+      level_corners(lp, l, x0, x1, x2, cn);
+      const float d0 = S.dX[s * 33 + 2 * l], d1 = S.dX[s * 33 + 2 * l + 1];
+      uint32_t k[8];
+      float v[16];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        k[c] = ((uint32_t)l << log2T) | cn.idx[c];
+        v[2 * c] = cn.w[c] * d0;
+        v[2 * c + 1] = cn.w[c] * d1;
+        if (tiles) atomicAdd(&hs[l >> 3][k[c] & 255u], 1u);
+      }
+      const size_t q = ((size_t)g * lp.L + (size_t)l) * 32u + (size_t)s;
+      uint4* kq = reinterpret_cast<uint4*>(pkey + q * 8u);
+      kq[0] = make_uint4(k[0], k[1], k[2], k[3]);
+      kq[1] = make_uint4(k[4], k[5], k[6], k[7]);
+      float4* vq = reinterpret_cast<float4*>(pval + q * 8u);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) vq[j] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    }
+    __syncthreads();
+    if (tiles && t < 256) {
+      const uint32_t t0 = g * (lp.L >> 3);
+      for (uint32_t j = 0; j < (lp.L >> 3); ++j) hist[(size_t)t * nb + t0 + j] = hs[j][t];
     }
     __syncthreads();
   }
@@ -1487,7 +1484,6 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->tail_sum, ntiles));
   A(lalloc(&s->tail_in, ntiles));
   A(lalloc(&s->lpart, s->train_waves));
-  A(lalloc(&s->dX, (size_t)s->B * 32u));
   A(lalloc(&s->judge_part, (size_t)c->hit_blocks_per_stripe * kStatStripes));
   A(lalloc(&s->lmlp, PR));
   A(lalloc(&s->acc, 16));
@@ -1524,7 +1520,7 @@ void learned_destroy(gi_context* c) {
                   s->mlp_part, s->mlp_part2, s->wb, s->w8, s->scales, s->hitpos, s->hitnrm, s->trec, s->tflag, s->clist,
                   s->ccount, s->batch, s->batch_raw, s->bkeys[0], s->bkeys[1], s->bvals[0], s->bvals[1],
                   s->pkeys[0], s->pkeys[1], s->pvals[0], s->pvals[1], s->rs_hist, s->tail_sum, s->tail_in,
-                  s->lpart, s->dX, s->judge_part, s->lmlp, s->acc};
+                  s->lpart, s->judge_part, s->lmlp, s->acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete s;
@@ -1558,19 +1554,20 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   while ((1u << log2T) < s->lp.T) ++log2T;
   hipEvent_t ev;
   timer_begin(c, "learned_train", st, &ev);
-  const uint32_t nq = s->lp.L * s->B;
-  // every launched block writes its whole partial, so the partials need no clearing
-  k_train<<<waves, 64 * kTrainWaves, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->dX, s->wb, S,
-                                                s->mlp_part, s->lpart, s->acc, s->scales + 3);
-  k_encode_bwd<<<nblk(nq, 256), 256, 0, st>>>(s->lp, s->batch, s->B, off, stride, s->dX, log2T, s->pkeys[0],
-                                              s->pvals[0], nblk(nq, 256), s->rs_hist);
+  // every launched block writes its whole partial, so the partials need no clearing; the
+  // gradient pairs fill [0, n_pairs) (L * B * 8)
+  const uint32_t n = (uint32_t)s->n_pairs;
+  const uint32_t nbt = nblk(n, kRsTile);
+  const bool tiles = (s->lp.L & 7u) == 0u;
+  k_train<<<waves, 64 * kTrainWaves, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->wb, S,
+                                                              s->mlp_part, s->lpart, s->acc, s->scales + 3, log2T,
+                                                              s->pkeys[0], s->pvals[0], nbt, s->rs_hist);
   timer_end(c, "learned_train", st, ev);
   k_reduce_mlp<<<dim3(kMlpParams / 256, kRedGroups), 256, 0, st>>>(s->mlp_part, waves, s->mlp_part2);
   // the encoding gradient: pairs sorted by entry, summed per entry in a fixed order
   timer_begin(c, "learned_grad_sort", st, &ev);
   int which = 0;
-  const uint32_t n = (uint32_t)s->n_pairs;
-  hipError_t e = radix_sort<float2>(s->pkeys, s->pvals, n, s->key_bits, s->rs_hist, st, which, true);
+  hipError_t e = radix_sort<float2>(s->pkeys, s->pvals, n, s->key_bits, s->rs_hist, st, which, tiles);
   timer_end(c, "learned_grad_sort", st, ev);
   if (e != hipSuccess) return e;
   const uint32_t nt = nblk(n, kGredTile);
