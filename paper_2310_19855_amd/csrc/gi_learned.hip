@@ -1150,10 +1150,11 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* p, const float* g, floa
   mlp_bf16_copy(i, w, wb);
 }
 
+// fp8: the e4m3 copies and scales are formed only for FP8 inference (no other reader)
 __global__ __launch_bounds__(1024) void k_mlp_step(float* p, float* acc, uint8_t* w8, float* scales,
-                                                   unsigned long long* stats) {
+                                                   unsigned long long* stats, bool fp8) {
   const bool skip = acc[1] != 0.0f;
-  mlp_e4m3_copies(p, w8, scales);
+  if (fp8) mlp_e4m3_copies(p, w8, scales);
   __syncthreads();                      // every thread has read the flag
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
@@ -1599,7 +1600,8 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
     am.eps = 1e-8f;
     timer_begin(c, "learned_adam", st, &ev);
     k_mlp_adam<<<nblk(kMlpParams, 256), 256, 0, st>>>(s->mlp, s->mlp_g, s->mlp_m, s->mlp_v, am, s->acc, s->wb);
-    k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->acc, s->w8, s->scales, c->d_stats);
+    k_mlp_step<<<1, 1024, 0, st>>>(s->mlp, s->acc, s->w8, s->scales, c->d_stats,
+                                   c->cfg.cache_mode == GI_CACHE_MLP_FP8);
     timer_end(c, "learned_adam", st, ev);
   } else {
     s->grad_dirty = true;
