@@ -2,12 +2,16 @@
 // multiresolution hash encoding (16 levels x 2^19 entries x 2 FP16 features) feeding a
 // 64-64 ReLU MLP, trained online on the radiance samples the pass produces each frame.
 //
-// Kernels: training forward + backward fused per wave of 32 samples (encoding gathers, BF16
-// MFMA layers with FP32 accumulation, relative-L2 loss with static loss scaling, backward
-// through the MLP on MFMA, weight gradients as per-wave MFMA partials, encoding gradients
-// scattered with FP32 atomics), a deterministic reduction of the weight gradients, dense Adam
-// with a skip on non-finite gradients, BF16 or FP8 (OCP e4m3) inference at every probe-ray
-// hit, and the judge that falls back to confident plain cells when the surrogate is off.
+// Kernels: the frame's training rays compacted in ray order and picked stratified; per
+// optimiser step, training forward + backward fused per block of 8 waves and 32 samples
+// (encoding gathers, BF16 MFMA layers with FP32 accumulation, relative-L2 loss with static
+// loss scaling, backward through the MLP on MFMA, weight gradients as per-block MFMA partials,
+// the encoding gradient as (entry, contribution) pairs), a fixed-order reduction of the weight
+// gradients, a stable radix sort of the pairs and per-entry sums in a fixed order with a lazy
+// Adam step of the touched grid entries, Adam on the MLP, a skip of the whole step on
+// non-finite gradients; BF16 or FP8 (OCP e4m3) inference at every probe-ray hit, and the judge
+// that falls back to confident plain cells when the surrogate is off.  Every sum has a fixed
+// order, so training is reproducible run to run.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -29,7 +33,7 @@ constexpr int kLd32 = 40;   // padded LDS row of a 32-wide bf16 tile
 constexpr int kMlpParams = 64 * 64 + 64 * 64 + 16 * 64;
 constexpr int kOffW1 = 0, kOffW2 = 4096, kOffW3 = 8192;
 static_assert(kMlpParams % 256 == 0, "the weight-gradient reduction takes 256 parameters per block");
-constexpr uint32_t kRedGroups = 16;   // runs of waves summed separately, then in order
+constexpr uint32_t kRedGroups = 16;   // runs of training blocks summed separately, then in order
 constexpr uint32_t kPrimeY = 2654435761u, kPrimeZ = 805459861u;
 constexpr int kMaxLevels = 16;
 
@@ -52,8 +56,8 @@ struct LearnedState {
   float* mlp_g = nullptr;
   float* mlp_m = nullptr;
   float* mlp_v = nullptr;
-  float* mlp_part = nullptr;     // [train_waves][kMlpParams]
-  float* mlp_part2 = nullptr;    // [kRedGroups][kMlpParams] sums of consecutive runs of waves
+  float* mlp_part = nullptr;     // [train_blocks][kMlpParams] per-block weight-gradient partials
+  float* mlp_part2 = nullptr;    // [kRedGroups][kMlpParams] sums of consecutive runs of blocks
   __bf16* wb = nullptr;          // W1 [64][64] | W1t [64][64] | W2 | W2t | W3 [16][64] | W3t [64][32]
   uint8_t* w8 = nullptr;         // e4m3 W1 | W2 | W3 (row-major [out][in])
   float* scales = nullptr;       // [0..2] weight scales, [3..5] activation amax (X, H1, H2), [6..8] act scales
@@ -72,18 +76,18 @@ struct LearnedState {
   uint32_t* pkeys[2] = {nullptr, nullptr};
   float2* pvals[2] = {nullptr, nullptr};
   uint32_t* rs_hist = nullptr;   // [256][blocks] digit counts -> offsets
-  float2* tail_sum = nullptr;    // per reduction tile: partial sum of its last entry, whether
-  uint32_t* tail_in = nullptr;   // that entry began inside the tile, and the tile's carry-in
+  float2* tail_sum = nullptr;    // per reduction tile: partial sum of its last entry and
+  uint32_t* tail_in = nullptr;   // whether that entry began inside the tile
   size_t n_pairs = 0;
   uint32_t key_bits = 0;         // bits of a gradient pair key (level * T + entry)
-  float* lpart = nullptr;        // [train_waves] loss partials
+  float* lpart = nullptr;        // [train_blocks] loss partials
   float2* judge_part = nullptr;  // per-wave (error, norm) partials of the judge
   uint32_t B = 0;
   uint32_t sub = 1;              // sub-batches held by the frame's batch (rows = sub * B)
   float4* lmlp = nullptr;        // [P*R] surrogate radiance at each hit
   float* acc = nullptr;          // [0] loss sum, [1] non-finite flag, [2] judge |diff|, [3] judge |plain|,
                                  // [4] fallback flag, [5] last loss, [6] last judged error, [7] batch n
-  uint32_t train_waves = 0;
+  uint32_t train_blocks = 0;
   bool grad_dirty = false;       // grid_g holds a gradient-only step's result
   int step = 0, skipped = 0;
   float host_stats[8] = {0};
@@ -589,7 +593,7 @@ static hipError_t sort_batch(gi_context* c, hipStream_t st, uint32_t rows) {
   return hipGetLastError();
 }
 
-// ---- fused training forward + backward, one wave per 32-sample group -------------------
+// ---- fused training forward + backward, one block of 8 waves per 32-sample group -------
 
 struct TrainSmem {
   __bf16 X[32 * kLd64], Xt[64 * kLd32];
@@ -900,16 +904,16 @@ __global__ __launch_bounds__(64 * kTrainWaves) __attribute__((amdgpu_waves_per_e
   }
 }
 
-// deterministic sum of the per-wave partials (fixed order) -> gradient; flags non-finite.
-// Stage 1: block (x, y) sums the waves of run y (kRedGroups consecutive runs of waves) for
-// 256 parameters, four slices of the run's waves (one float4 column per thread) added in a
-// fixed order; stage 2 (reduce_mlp_finish) adds the runs in order.
-__global__ __launch_bounds__(256) void k_reduce_mlp(const float* part, uint32_t waves, float* part2) {
+// deterministic sum of the per-block partials (fixed order) -> gradient; flags non-finite.
+// Stage 1: block (x, y) sums the partials of run y (kRedGroups consecutive runs of training
+// blocks) for 256 parameters, four slices of the run (one float4 column per thread) added in
+// a fixed order; stage 2 (reduce_mlp_finish) adds the runs in order.
+__global__ __launch_bounds__(256) void k_reduce_mlp(const float* part, uint32_t parts, float* part2) {
   __shared__ float4 red[4][64];
   const uint32_t l = threadIdx.x & 63u, slice = threadIdx.x >> 6;
   const uint32_t c4 = blockIdx.x * 64u + l;                    // float4 column
-  const uint32_t per = (waves + kRedGroups - 1u) / kRedGroups;
-  const uint32_t w0 = blockIdx.y * per, w1 = w0 + per < waves ? w0 + per : waves;
+  const uint32_t per = (parts + kRedGroups - 1u) / kRedGroups;
+  const uint32_t w0 = blockIdx.y * per, w1 = w0 + per < parts ? w0 + per : parts;
   const float4* p4 = reinterpret_cast<const float4*>(part);
   float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
   if (c4 < kMlpParams / 4)
@@ -941,7 +945,7 @@ __global__ __launch_bounds__(256) void k_reduce_mlp(const float* part, uint32_t 
 struct MlpFinish {
   const float* part2;
   const float* lpart;
-  uint32_t waves;
+  uint32_t parts;
   float* g;
 };
 
@@ -949,7 +953,7 @@ __device__ inline void reduce_mlp_finish(const MlpFinish& mf, float* acc) {
   if (blockIdx.x == 0 && threadIdx.x < 64) {
     // the step's loss: lane j sums partials j, j + 64, ... in order, then a fixed butterfly
     float l = 0.0f;
-    for (uint32_t w = threadIdx.x; w < mf.waves; w += 64u) l += mf.lpart[w];
+    for (uint32_t w = threadIdx.x; w < mf.parts; w += 64u) l += mf.lpart[w];
     for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
     if (threadIdx.x == 0) acc[0] = l;
   }
@@ -1437,7 +1441,7 @@ hipError_t learned_create(gi_context* c) {
   s->grid_n = lp.L * lp.T * 2u;
   s->B = 1u << (g.mlp_batch_log2 ? (g.mlp_batch_log2 > 20 ? 20 : g.mlp_batch_log2) : 16u);
   if (s->B < 32) s->B = 32;
-  s->train_waves = 512;
+  s->train_blocks = 512;
   const size_t PR = (size_t)c->P * c->R;
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t r) { if (e == hipSuccess) e = r; };
@@ -1448,7 +1452,7 @@ hipError_t learned_create(gi_context* c) {
   A(lalloc(&s->mlp_g, kMlpParams));
   A(lalloc(&s->mlp_m, kMlpParams));
   A(lalloc(&s->mlp_v, kMlpParams));
-  A(lalloc(&s->mlp_part, (size_t)s->train_waves * kMlpParams));
+  A(lalloc(&s->mlp_part, (size_t)s->train_blocks * kMlpParams));
   A(lalloc(&s->mlp_part2, (size_t)kRedGroups * kMlpParams));
   A(lalloc(&s->wb, 16384 + 1024 + 2048));
   A(lalloc(&s->w8, kMlpParams));
@@ -1484,7 +1488,7 @@ hipError_t learned_create(gi_context* c) {
   const size_t ntiles = (s->n_pairs + kGredTile - 1) / kGredTile;
   A(lalloc(&s->tail_sum, ntiles));
   A(lalloc(&s->tail_in, ntiles));
-  A(lalloc(&s->lpart, s->train_waves));
+  A(lalloc(&s->lpart, s->train_blocks));
   A(lalloc(&s->judge_part, (size_t)c->hit_blocks_per_stripe * kStatStripes));
   A(lalloc(&s->lmlp, PR));
   A(lalloc(&s->acc, 16));
@@ -1550,7 +1554,7 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   if (s->grad_dirty) k_zero_f32<<<nblk(s->grid_n, 256), 256, 0, st>>>(s->grid_g, s->grid_n);
   s->grad_dirty = false;
   const uint32_t groups = s->B / 32u;
-  const uint32_t waves = std::min<uint32_t>(s->train_waves, std::max<uint32_t>(groups, 1u));
+  const uint32_t tblocks = std::min<uint32_t>(s->train_blocks, std::max<uint32_t>(groups, 1u));
   uint32_t log2T = 0;
   while ((1u << log2T) < s->lp.T) ++log2T;
   hipEvent_t ev;
@@ -1560,11 +1564,11 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
   const uint32_t n = (uint32_t)s->n_pairs;
   const uint32_t nbt = nblk(n, kRsTile);
   const bool tiles = (s->lp.L & 7u) == 0u;
-  k_train<<<waves, 64 * kTrainWaves, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->wb, S,
+  k_train<<<tblocks, 64 * kTrainWaves, sizeof(TrainSmem), st>>>(s->lp, s->batch, s->B, off, stride, s->grid_h, s->wb, S,
                                                               s->mlp_part, s->lpart, s->acc, s->scales + 3, log2T,
                                                               s->pkeys[0], s->pvals[0], nbt, s->rs_hist);
   timer_end(c, "learned_train", st, ev);
-  k_reduce_mlp<<<dim3(kMlpParams / 256, kRedGroups), 256, 0, st>>>(s->mlp_part, waves, s->mlp_part2);
+  k_reduce_mlp<<<dim3(kMlpParams / 256, kRedGroups), 256, 0, st>>>(s->mlp_part, tblocks, s->mlp_part2);
   // the encoding gradient: pairs sorted by entry, summed per entry in a fixed order
   timer_begin(c, "learned_grad_sort", st, &ev);
   int which = 0;
@@ -1583,7 +1587,7 @@ static hipError_t train_step(gi_context* c, hipStream_t st, bool apply, uint32_t
     ag.lr = c->cfg.mlp_lr_grid;
     ag.eps = 1e-15f;
   }
-  const MlpFinish mf{s->mlp_part2, s->lpart, waves, s->mlp_g};
+  const MlpFinish mf{s->mlp_part2, s->lpart, tblocks, s->mlp_g};
   timer_begin(c, "learned_grad_apply", st, &ev);
   k_gred<0><<<nt, 256, 0, st>>>(s->pkeys[which], s->pvals[which], n, s->tail_sum, s->tail_in, s->gstate, s->grid_h,
                                 s->grid_g, ag, s->acc, mf);
