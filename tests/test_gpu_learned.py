@@ -364,22 +364,23 @@ def test_training_batch_matches_oracle_field1080():
     pr.ctx.close()
 
 
-@pytest.mark.parametrize("levels,tlog2", [(8, 14), (16, 19)])
-def test_full_size_step_matches_the_oracle(levels, tlog2):
+@pytest.mark.parametrize("levels,tlog2,blog2", [(8, 14, 14), (16, 19, 14), (16, 19, 15)])
+def test_full_size_step_matches_the_oracle(levels, tlog2, blog2):
     """One 2^14-sample step at the benchmark's sizes, where the low levels take the dense
     corner index ((N_l + 1)^3 <= T: level 0 at 8 x 2^14, levels 0-4 at 16 x 2^19) and the
     gradient pairs are sorted and summed per entry: MLP and grid gradients against the float64
     oracle (cosine and norm ratio per block), then the Adam step (the first step moves every
-    parameter with a clear gradient by -lr * sign(g))."""
+    parameter with a clear gradient by -lr * sign(g)).  At 2^15 samples the training kernel's
+    512 blocks each take two 32-sample groups in turn."""
     spec = OL.Spec(levels=levels, table_log2=tlog2)
     assert any((N + 1) ** 3 <= spec.T for N in spec.resolutions())
     sc = I.field_scene()
     lo, hi = sc.verts.min(0), sc.verts.max(0)
     ctx = gi.Context(width=64, height=64, cache_mode=gi.CACHE_MLP_BF16, mlp_levels=levels, mlp_table_log2=tlog2,
-                     mlp_batch_log2=14, seed=SEED, mlp_loss_scale=128.0, mlp_lr_grid=OL.Spec.lr_grid,
+                     mlp_batch_log2=blog2, seed=SEED, mlp_loss_scale=128.0, mlp_lr_grid=OL.Spec.lr_grid,
                      mlp_lr_mlp=OL.Spec.lr_mlp, scene_min=tuple(lo) + (0.0,), scene_max=tuple(hi) + (0.0,))
     ctx.build_bvh(sc)
-    B = 1 << 14
+    B = 1 << blog2
     # clustered samples (shared coarse entries, long per-entry runs in the sort) and spread ones
     rng = np.random.default_rng(2)
     pos, nrm, tgt = _samples(B, lo, hi, seed=5)
@@ -399,7 +400,7 @@ def test_full_size_step_matches_the_oracle(levels, tlog2):
     for k in ("W1", "W2", "W3", "grid"):
         c = _cos(got[k], g[k])
         r = np.linalg.norm(got[k]) / np.linalg.norm(g[k])
-        print(f"{levels}x2^{tlog2} {k}: cosine {c:.6f}, norm ratio {r:.5f}")
+        print(f"{levels}x2^{tlog2}, 2^{blog2} samples {k}: cosine {c:.6f}, norm ratio {r:.5f}")
         assert c > 0.999, (k, c)
         assert abs(r - 1) < 0.01, (k, r)
     # dense levels: every entry the oracle touches is touched on the GPU, and no other
