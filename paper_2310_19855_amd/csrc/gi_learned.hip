@@ -631,13 +631,13 @@ __device__ inline void atomic_max_abs(float* p, float v) {
 // whole number of sort tiles (L a multiple of 8) the block also counts the low key digits of
 // its tiles for the sort's first pass.
 constexpr uint32_t kTrainWaves = 8;   // waves of a training block: one 16x16 tile of each layer's output each
+static_assert(64 * kTrainWaves == 32 * kMaxLevels, "one thread of a training block per (sample, level) of its group");
 
-__global__ __launch_bounds__(64 * kTrainWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_train(LearnedParams lp, const float4* batch, uint32_t B,
-                                                            uint32_t off, uint32_t stride, const __half* grid_h,
-                                                            const __bf16* wb, float loss_scale, float* part,
-                                                            float* lpart, float* acc, float* amax, uint32_t log2T,
-                                                            uint32_t* pkey, float2* pval, uint32_t nb,
-                                                            uint32_t* hist) {
+// 4 waves per SIMD (two blocks per CU, as the LDS tiles allow) caps the registers at 128
+__global__ __launch_bounds__(64 * kTrainWaves) __attribute__((amdgpu_waves_per_eu(4)))
+void k_train(LearnedParams lp, const float4* batch, uint32_t B, uint32_t off, uint32_t stride, const __half* grid_h,
+             const __bf16* wb, float loss_scale, float* part, float* lpart, float* acc, float* amax, uint32_t log2T,
+             uint32_t* pkey, float2* pval, uint32_t nb, uint32_t* hist) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TrainSmem& S = *reinterpret_cast<TrainSmem*>(smem_raw);
   __shared__ float red[kTrainWaves][4];
