@@ -79,10 +79,14 @@ def test_initial_parameters_match_the_oracle_bit_for_bit():
     assert np.array_equal(st["mlp"], mlp_ref)
 
 
-def test_gradients_and_adam_step_match_the_oracle():
-    ctx, sc, lo, hi = _ctx()
+@pytest.mark.parametrize("blog2", [BLOG2, 5])
+def test_gradients_and_adam_step_match_the_oracle(blog2):
+    """Gradients and the first Adam step against the float64 oracle.  At 2^5 samples the step's
+    1,024 gradient pairs fill half of one sort tile (the ragged-tile path of the sort), one
+    training block takes the only 32-sample group, and most runs of the reduction are empty."""
+    ctx, sc, lo, hi = _ctx(mlp_batch_log2=blog2)
     spec = OL.Spec(levels=LEVELS, table_log2=TLOG2)
-    B = 1 << BLOG2
+    B = 1 << blog2
     pos, nrm, tgt = _samples(B, lo, hi)
     tp, tn, tt = (torch.from_numpy(a).cuda() for a in (pos, nrm, tgt))
     ctx.learned_step(tp, tn, tt, apply=False)
