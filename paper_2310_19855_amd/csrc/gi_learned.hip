@@ -983,8 +983,9 @@ __device__ inline void adam_lazy(float graw, float& p, float& m, float& v, const
 }
 
 // ---- per-entry sums of the sorted gradient pairs, then the grid step --------------------
-// Tiles of kGredTile sorted pairs, thread t of a tile holding pairs 4t..4t+3.  Each thread
-// sums its pairs in order, restarting where the key changes; a segmented scan over the
+// Tiles of kGredTile sorted pairs, thread t of a tile holding pairs kGredItems t ..
+// kGredItems (t + 1) - 1 (one pair per thread: 256-pair tiles, whose many blocks overlap one
+// another's loads).  Each thread sums its pairs in order, restarting where the key changes; a segmented scan over the
 // threads (fixed association) extends every pair's sum back to the tile start or to its
 // entry's first pair.  MODE 0 records each tile's last partial sum and whether its entry began
 // inside the tile.  In MODE 1 and 2 a tile's carry-in (the sums, in earlier tiles, of the entry
@@ -993,7 +994,8 @@ __device__ inline void adam_lazy(float graw, float& p, float& m, float& v, const
 // entry's last pair, takes the lazy Adam step of its two parameters (none when the step's
 // gradients are non-finite); MODE 2 writes the dense gradient instead (a gradient-only step).
 // Every order is fixed, so the sums, and the step, are deterministic.
-constexpr uint32_t kGredItems = 4, kGredTile = 256 * kGredItems;
+constexpr uint32_t kGredItems = 1, kGredTile = 256 * kGredItems;
+static_assert(kGredItems <= 32, "a thread's key changes fit one word");
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2* val, uint32_t n, float2* tail_sum,
@@ -1066,7 +1068,7 @@ __global__ __launch_bounds__(256) void k_gred(const uint32_t* key, const float2*
     if (k[j] != kp) {
       sx = 0.0f;
       sy = 0.0f;
-      heads |= 0xFu << j;
+      heads |= ((0xFFFFFFFFu >> (32u - kGredItems)) << j) & (0xFFFFFFFFu >> (32u - kGredItems));
     }
     sx = sx + w[j].x;
     sy = sy + w[j].y;
